@@ -1,0 +1,222 @@
+/*
+ * panorama.h - C ABI of the MI355X pruned k-NN scan (progressive distance
+ * refinement with Cauchy-Schwarz pruning over a PCA basis).
+ *
+ * The method: vectors are rotated by an orthogonal, energy-compacting
+ * transform T (the PCA basis of Section 4.1) and stored level-major (Section
+ * 6.1).  A candidate's squared distance to the query is built up one level of
+ * dimensions at a time (Eq. 1-2); after each level a lower bound from the
+ * tail energies of query and candidate (Eq. 3; Eq. 4 for eps < 1) is compared
+ * with the running k-th best distance and the candidate is dropped as soon as
+ * the bound exceeds it (Algorithm 1).  At eps = 1 the result equals exact
+ * k-NN over the candidate set (Problem 1), the candidate set being the
+ * vectors of the probed IVF lists (Problem 2 with IVF, Section 6.1).
+ *
+ * Conventions shared by every entry point:
+ *  - Status: every call returns pano_status.  PANO_OK is 0; any other value
+ *    leaves outputs unspecified and sets a thread-local message readable with
+ *    pano_last_error().  Nothing aborts and no C++ exception crosses the ABI.
+ *  - Ownership: opaque handles (pano_ctx, pano_transform, pano_index) are
+ *    created and freed only by the library.  Array arguments are borrowed for
+ *    the duration of the call; output arrays are allocated by the caller.
+ *  - Memory spaces: arguments named *_host are host memory; arguments named
+ *    *_dev are device memory on the context's GPU.  Row-major float32 rows of
+ *    length d unless stated otherwise.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream).  Calls enqueue their GPU work on it and return when the results
+ *    are in the output arrays (they synchronise the stream before returning).
+ *  - Distances are squared Euclidean distances.  The reported distance of a
+ *    result is the canonical D(q, x): sum over j = 0..d-1, in that order, of
+ *    ((double)q_j - (double)x_j)^2 with every product and sum rounded to
+ *    FP64, then rounded to float32.  Results are ordered by ascending
+ *    (D, id); missing results are id -1 and distance +inf.
+ */
+#ifndef PANORAMA_H
+#define PANORAMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PANO_OK = 0,
+    PANO_EINVAL = 1,       /* invalid argument (shape, range, non-finite input) */
+    PANO_ENOMEM = 2,       /* device or host allocation failed */
+    PANO_EDEVICE = 3,      /* a HIP runtime call failed */
+    PANO_EUNSUPPORTED = 4, /* valid request the library does not implement */
+    PANO_EBUSY = 5         /* resource temporarily exhausted */
+} pano_status;
+
+typedef enum { PANO_F32 = 0, PANO_BF16 = 1 } pano_dtype;
+
+typedef struct pano_ctx pano_ctx;
+typedef struct pano_transform pano_transform;
+typedef struct pano_index pano_index;
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *pano_last_error(void);
+
+/* Library version string. */
+const char *pano_version(void);
+
+/* Create a context bound to HIP device `device`.  The context owns scratch
+ * memory reused across searches.  A context may be used by one thread at a
+ * time. */
+pano_status pano_ctx_create(int device, pano_ctx **out);
+void pano_ctx_destroy(pano_ctx *ctx);
+
+/*
+ * build_transform: the PCA basis of Section 4.1, fitted on the host in FP64.
+ * x_host [n][d] float32 rows.  The mean mu and covariance are accumulated in
+ * FP64 over a seeded sample of `fit_sample` rows (fit_sample <= 0 or >= n:
+ * every row); T's rows are the eigenvectors of the covariance sorted by
+ * descending eigenvalue, each signed so that its largest-magnitude entry is
+ * positive.  Vectors are mapped to T (v - mu).  Also records lambda and the
+ * energy-compaction constant alpha (Section 4.1, E(m) ~ exp(-alpha m / d)).
+ * Errors: EINVAL if n < 2, d < 1 or x has a non-finite value.
+ */
+pano_status pano_build_transform(const float *x_host, int64_t n, int32_t d, int64_t fit_sample,
+                                 uint64_t seed, pano_transform **out);
+
+/* Identity transform (mu = 0, T = I): raw-vector pruning. */
+pano_status pano_transform_identity(int32_t d, pano_transform **out);
+
+/* A caller-supplied transform: mu_host [d], T_host [d][d] row-major FP64.
+ * EINVAL if T is not orthonormal to 1e-9 (max |T T^t - I|). */
+pano_status pano_transform_from(int32_t d, const double *mu_host, const double *T_host,
+                                pano_transform **out);
+
+/* Copy out the transform.  Any output pointer may be NULL.  mu_host [d],
+ * T_host [d][d], lambda_host [d] (0 for caller-supplied transforms). */
+pano_status pano_transform_get(const pano_transform *tf, int32_t *d, double *mu_host,
+                               double *T_host, double *lambda_host, double *alpha);
+void pano_transform_free(pano_transform *tf);
+
+/*
+ * ivf_assign: the coarse quantiser of IVF (Section 6.1): Lloyd's k-means in
+ * raw space.  x_dev [n][d]; centroids_dev [nlist][d] and assign_dev [n]
+ * (int32) are outputs.  Initial centroids are nlist distinct rows drawn with
+ * `seed`; each of `iters` iterations assigns every row to its nearest centroid
+ * on the GPU and recomputes the means (an empty cluster keeps its centroid).
+ * The final assignment pass uses the same nearest-centroid rule.  nlist = 1
+ * gives the flat index (centroid = mean, every row in list 0).
+ * Errors: EINVAL if nlist < 1 or nlist > n.
+ */
+pano_status pano_ivf_assign(pano_ctx *ctx, const float *x_dev, int64_t n, int32_t d,
+                            int32_t nlist, int32_t iters, uint64_t seed, float *centroids_dev,
+                            int32_t *assign_dev, void *stream);
+
+/*
+ * build_levels: pack the index (Section 6.1 level-major batches, Section 6.5
+ * tail energies).  x_dev [n][d] raw rows; centroids_dev [nlist][d];
+ * assign_dev [n] in [0, nlist).  m_host [L+1] level cuts with m[0] = 0 <
+ * m[1] < ... < m[L] = d (Eq. 2).  `block` is the batch size B (a multiple of
+ * 64, 64..1024; 0 = 256).  Each list is cut into blocks of B vectors; within a
+ * block all B level-l slices are contiguous, then level l+1 (each slice padded
+ * to a multiple of 4 floats with zeros).  Per vector the tail norms
+ * sqrt(R_x^(l,d)) for l = 0..L-1 are stored (4L bytes).  The index keeps a
+ * device copy of the raw rows (used for the canonical rescoring) and of the
+ * centroids; it lives in device memory and is owned by the handle.
+ * store = PANO_BF16 additionally stores the level slices in bfloat16.
+ * Errors: EINVAL on inconsistent shapes or cuts; ENOMEM.
+ */
+pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const float *x_dev,
+                              int64_t n, int32_t d, const float *centroids_dev,
+                              const int32_t *assign_dev, int32_t nlist, const int32_t *m_host,
+                              int32_t L, int32_t block, pano_dtype store, pano_index **out,
+                              void *stream);
+
+/* Tuning knobs of a search (0 = library default for every field). */
+typedef struct {
+    int32_t group;        /* max queries sharing one scan work item (1..16) */
+    int32_t blocks_per_item; /* blocks of a list scanned by one work item */
+    int32_t seed_pool;    /* candidates of the nearest list ranked to seed d_k */
+    int32_t seed_count;   /* of those, how many get their exact distance */
+    int32_t grid;         /* persistent scan workgroups (0 = 4 per CU) */
+    int32_t use_bf16;     /* 1: scan BF16 level slices (index built with BF16) */
+    int32_t reserved[6];
+} pano_search_params;
+
+/* Search flags. */
+#define PANO_SEARCH_STATS 1u  /* collect counters, readable with pano_stats_get */
+
+/*
+ * search: k nearest neighbours of each query among the vectors of its probed
+ * lists (exact at probe for eps = 1; Algorithm 1 with Eq. 4 for eps < 1).
+ * q_dev [nq][d] float32.  nprobe_dev [nq] int32 per-query probe counts, or
+ * NULL to use nprobe_all for every query; probe counts are clamped to
+ * [1, nlist].  The probe set of a query is its nprobe nearest lists by
+ * (D(q, centroid), list id).  eps in [0, 1] (Eq. 4; 1 = exact).  Outputs
+ * ids_dev [nq][k] int64 (row index of the vector in build_levels' x) and
+ * dists_dev [nq][k] float32 (canonical D), ascending by (D, id).  `params`
+ * may be NULL.  Errors: EINVAL if k < 1, nq < 0, eps outside [0, 1] or a
+ * query is non-finite; ENOMEM if scratch cannot be allocated.
+ */
+pano_status pano_search(pano_index *idx, const float *q_dev, int64_t nq, int32_t k,
+                        const int32_t *nprobe_dev, int32_t nprobe_all, float eps,
+                        int64_t *ids_dev, float *dists_dev, const pano_search_params *params,
+                        uint32_t flags, void *stream);
+
+/*
+ * search_bruteforce: the same contract as pano_search with pruning disabled:
+ * every probed candidate's full distance is computed from the same level-major
+ * tiles with the same work decomposition (the same-GPU brute-force baseline).
+ * eps is ignored.
+ */
+pano_status pano_search_bruteforce(pano_index *idx, const float *q_dev, int64_t nq, int32_t k,
+                                   const int32_t *nprobe_dev, int32_t nprobe_all, int64_t *ids_dev,
+                                   float *dists_dev, const pano_search_params *params,
+                                   uint32_t flags, void *stream);
+
+typedef struct {
+    int64_t n;
+    int32_t d;
+    int32_t d_pad;          /* sum of the level widths padded to 4 */
+    int32_t nlist;
+    int32_t L;
+    int32_t block;
+    int32_t has_bf16;
+    int64_t nblocks;
+    int64_t max_list_len;
+    int64_t bytes_levels;   /* FP32 level tiles */
+    int64_t bytes_levels_bf16;
+    int64_t bytes_tails;    /* 4 L bytes per stored slot */
+    int64_t bytes_ids;
+    int64_t bytes_raw;      /* raw rows kept for the canonical rescoring */
+    double transform_err_max; /* certified bound on ||stored - exact rotated|| */
+    double sigma_ratio;     /* sigma_max / sigma_min of the FP32 transform */
+} pano_index_info_t;
+
+pano_status pano_index_info(const pano_index *idx, pano_index_info_t *out);
+
+/* Copy the level cuts (m[0..L]) and the per-list lengths (nlist) to host. */
+pano_status pano_index_layout(const pano_index *idx, int32_t *m_host, int64_t *list_len_host);
+
+/* Counters of the last search on this index with PANO_SEARCH_STATS. */
+typedef struct {
+    int64_t nq;
+    int64_t candidates;      /* (query, candidate) pairs in the probe sets */
+    int64_t dims_read;       /* coordinates read by the scan, sum over pairs */
+    int64_t level_reads[64]; /* pairs that read level l (l < 64) */
+    int64_t items;           /* scan work items */
+    int64_t committed;       /* entries written to the per-query result buffers */
+    int64_t band;            /* entries rescored with the canonical recipe */
+    int64_t fallback_queries;/* queries answered by the exact fallback path */
+    double ms_total;         /* device time of the whole search */
+    double ms_scan;          /* device time of the scan kernel */
+    double ms_merge;         /* device time of merge + rescoring */
+    double ms_prep;          /* device time of transform, probe, work list, seed */
+    int64_t scan_bytes;      /* bytes of level slices, tails and ids touched */
+} pano_stats_t;
+
+pano_status pano_stats_get(const pano_index *idx, pano_stats_t *out);
+
+void pano_index_free(pano_index *idx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PANORAMA_H */

@@ -1,0 +1,471 @@
+// C ABI of the pruned k-NN scan: argument checking, handle management, the
+// index build (transform, tails, level-major packing) and the search
+// orchestration.  Every exported function catches all exceptions and maps
+// them to a pano_status with a thread-local message.
+#include "internal.h"
+#include "search_common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+namespace pano {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+template <class F> static pano_status guarded(F &&f)
+{
+    try {
+        g_last_error.clear();
+        f();
+        return PANO_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return PANO_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return PANO_EDEVICE;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return PANO_EDEVICE;
+    }
+}
+
+static double gamma_n(double nn)
+{
+    const double u = std::ldexp(1.0, -24);
+    return nn * u / (1.0 - nn * u);
+}
+
+// Certified error constants of the FP32 path (see the design notes):
+//  * transform outputs carry |err| <= kappa ||fl(v - mu)||, kappa from the
+//    chunked accumulation bound and the row/column sums of |T32|;
+//  * the FP32 matrix has singular values in [sqrt(1 - delta), sqrt(1 + delta)]
+//    with delta = ||T32 T32^t - I||_F;
+//  * a head distance over m coordinates has relative error <= gamma(m + L + 24).
+static void compute_margins(pano_index *ix, const std::vector<float> &T32)
+{
+    const int d = ix->d;
+    const double u = std::ldexp(1.0, -24);
+    std::vector<double> rs(d, 0.0), cs(d, 0.0);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double a = std::fabs((double)T32[(size_t)i * d + j]);
+            rs[i] += a;
+            cs[j] += a;
+        }
+    const double nabs = std::sqrt(*std::max_element(rs.begin(), rs.end()) * *std::max_element(cs.begin(), cs.end()));
+    std::vector<double> part(d, 0.0);
+    parallel_for(d, 8, [&](int64_t ib, int64_t ie) {
+        for (int64_t i = ib; i < ie; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < d; ++j) {
+                double s = 0.0;
+                for (int t = 0; t < d; ++t) s += (double)T32[(size_t)i * d + t] * (double)T32[(size_t)j * d + t];
+                double e = s - (i == j ? 1.0 : 0.0);
+                acc += e * e;
+            }
+            part[i] = acc;
+        }
+    });
+    double fro2 = 0.0;
+    for (double v : part) fro2 += v;
+    const double delta = std::sqrt(fro2) * (1.0 + 1e-6) + 1e-15 * d * d;
+    if (delta >= 0.5) throw Error{PANO_EINVAL, "transform is not orthonormal in FP32"};
+    const double smax = std::sqrt(1.0 + delta), smin = std::sqrt(1.0 - delta);
+    const int tk = 32;
+    const double gT = gamma_n((double)tk + (d + tk - 1) / tk + 2);
+    const double kappa = (gT * nabs * (1.0 + u) + smax * u * (1.0 + u)) * (1.0 + 1e-6);
+    const double up = u * (1.0 + 1e-5);
+    const double rho = (smax / smin) * std::sqrt((1.0 + up) / (1.0 - up)) * (1.0 + 1e-7);
+    Margins &mg = ix->mg;
+    std::memset(&mg, 0, sizeof(mg));
+    for (int l = 1; l <= ix->L; ++l) mg.c_level[l] = (float)(gamma_n((double)ix->mp[l] + ix->L + 24) * 1.01);
+    mg.c_final = mg.c_level[ix->L];
+    mg.c_tail = (float)(12.0 * u);
+    mg.kappa = (float)kappa;
+    mg.rho = (float)rho;
+    ix->sigma_ratio = smax / smin;
+}
+
+static LevelGeom geom_of(const pano_index *ix)
+{
+    LevelGeom g{};
+    g.L = ix->L;
+    g.d = ix->d;
+    g.d_pad = ix->d_pad;
+    g.B = ix->B;
+    for (int l = 0; l <= ix->L; ++l) g.mp[l] = ix->mp[l];
+    for (int l = 0; l < ix->L; ++l) g.wp[l] = ix->wp[l];
+    return g;
+}
+
+static bool all_finite(const float *x, int64_t count)
+{
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+}  // namespace pano
+
+using namespace pano;
+
+extern "C" {
+
+const char *pano_last_error(void) { return g_last_error.c_str(); }
+const char *pano_version(void) { return "panorama-mi355x 0.1"; }
+
+pano_status pano_ctx_create(int device, pano_ctx **out)
+{
+    return guarded([&] {
+        PANO_REQUIRE(out != nullptr, "out is NULL");
+        int count = 0;
+        PANO_HIP(hipGetDeviceCount(&count));
+        PANO_REQUIRE(device >= 0 && device < count, "device index out of range");
+        PANO_HIP(hipSetDevice(device));
+        auto *c = new pano_ctx();
+        c->device = device;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+        *out = c;
+    });
+}
+
+void pano_ctx_destroy(pano_ctx *ctx) { delete ctx; }
+
+pano_status pano_build_transform(const float *x_host, int64_t n, int32_t d, int64_t fit_sample, uint64_t seed,
+                                 pano_transform **out)
+{
+    return guarded([&] {
+        PANO_REQUIRE(out != nullptr && x_host != nullptr, "null argument");
+        PANO_REQUIRE(n >= 2 && d >= 1, "need n >= 2 rows and d >= 1");
+        std::vector<int64_t> rows = seeded_sample(n, fit_sample, seed);
+        for (int64_t r : rows)
+            PANO_REQUIRE(all_finite(x_host + r * (int64_t)d, d), "x has a non-finite value");
+        auto tf = std::make_unique<pano_transform>();
+        tf->d = d;
+        std::vector<double> cov;
+        mean_cov_fp64(x_host, n, d, rows, tf->mu, cov);
+        if (!symmetric_eigen(cov, d, tf->lambda, tf->T))
+            throw Error{PANO_EDEVICE, "eigensolver did not converge"};
+        // alpha: least-squares fit of log E(m) ~ -alpha m / d where E(m) >= 1e-3
+        std::vector<double> tail(d + 1, 0.0);
+        for (int j = d - 1; j >= 0; --j) tail[j] = tail[j + 1] + std::max(tf->lambda[j], 0.0);
+        double sxx = 0.0, sxy = 0.0;
+        for (int m = 0; m < d; ++m) {
+            double e = tail[0] > 0 ? tail[m] / tail[0] : 0.0;
+            if (e < 1e-3) continue;
+            double xm = (double)m / d;
+            sxx += xm * xm;
+            sxy += xm * std::log(e);
+        }
+        tf->alpha = sxx > 0 ? -sxy / sxx : 0.0;
+        *out = tf.release();
+    });
+}
+
+pano_status pano_transform_identity(int32_t d, pano_transform **out)
+{
+    return guarded([&] {
+        PANO_REQUIRE(out != nullptr && d >= 1, "bad arguments");
+        auto tf = std::make_unique<pano_transform>();
+        tf->d = d;
+        tf->mu.assign(d, 0.0);
+        tf->T.assign((size_t)d * d, 0.0);
+        for (int i = 0; i < d; ++i) tf->T[(size_t)i * d + i] = 1.0;
+        tf->lambda.assign(d, 0.0);
+        *out = tf.release();
+    });
+}
+
+pano_status pano_transform_from(int32_t d, const double *mu_host, const double *T_host, pano_transform **out)
+{
+    return guarded([&] {
+        PANO_REQUIRE(out != nullptr && mu_host != nullptr && T_host != nullptr && d >= 1, "bad arguments");
+        double worst = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                double s = 0.0;
+                for (int t = 0; t < d; ++t) s += T_host[(size_t)i * d + t] * T_host[(size_t)j * d + t];
+                worst = std::max(worst, std::fabs(s - (i == j ? 1.0 : 0.0)));
+            }
+        PANO_REQUIRE(worst <= 1e-9, "T is not orthonormal to 1e-9");
+        auto tf = std::make_unique<pano_transform>();
+        tf->d = d;
+        tf->mu.assign(mu_host, mu_host + d);
+        tf->T.assign(T_host, T_host + (size_t)d * d);
+        tf->lambda.assign(d, 0.0);
+        *out = tf.release();
+    });
+}
+
+pano_status pano_transform_get(const pano_transform *tf, int32_t *d, double *mu_host, double *T_host,
+                               double *lambda_host, double *alpha)
+{
+    return guarded([&] {
+        PANO_REQUIRE(tf != nullptr, "transform is NULL");
+        if (d) *d = tf->d;
+        if (mu_host) std::copy(tf->mu.begin(), tf->mu.end(), mu_host);
+        if (T_host) std::copy(tf->T.begin(), tf->T.end(), T_host);
+        if (lambda_host) std::copy(tf->lambda.begin(), tf->lambda.end(), lambda_host);
+        if (alpha) *alpha = tf->alpha;
+    });
+}
+
+void pano_transform_free(pano_transform *tf) { delete tf; }
+
+pano_status pano_ivf_assign(pano_ctx *ctx, const float *x_dev, int64_t n, int32_t d, int32_t nlist, int32_t iters,
+                            uint64_t seed, float *centroids_dev, int32_t *assign_dev, void *stream)
+{
+    return guarded([&] {
+        PANO_REQUIRE(ctx && x_dev && centroids_dev && assign_dev, "null argument");
+        PANO_REQUIRE(n >= 1 && d >= 1 && nlist >= 1 && nlist <= n, "need 1 <= nlist <= n");
+        PANO_REQUIRE(iters >= 0, "iters must be >= 0");
+        PANO_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        // initial centroids: nlist distinct rows chosen with the seed
+        std::vector<int64_t> init = seeded_sample(n, nlist, seed);
+        for (int c = 0; c < nlist; ++c)
+            PANO_HIP(hipMemcpyAsync(centroids_dev + (int64_t)c * d, x_dev + init[c] * d, sizeof(float) * d,
+                                    hipMemcpyDeviceToDevice, s));
+        DevMem S, cn, perm_d, off_d;
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(1ll << 28) / std::max(1, nlist)));
+        S.alloc(sizeof(float) * chunk * nlist);
+        cn.alloc(sizeof(float) * nlist);
+        perm_d.alloc(sizeof(int64_t) * n);
+        off_d.alloc(sizeof(int64_t) * (nlist + 1));
+        std::vector<int32_t> asg(n);
+        std::vector<int64_t> perm(n), off(nlist + 1);
+        auto assign_pass = [&]() {
+            launch_sqnorms(centroids_dev, nlist, d, cn.as<float>(), s);
+            for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+                int64_t rn = std::min(chunk, n - r0);
+                launch_gemm_nt(x_dev + r0 * d, rn, d, centroids_dev, nlist, S.as<float>(), s);
+                launch_argmin_rows(S.as<float>(), rn, nlist, cn.as<float>(), assign_dev + r0, s);
+            }
+        };
+        for (int it = 0; it < iters; ++it) {
+            assign_pass();
+            PANO_HIP(hipMemcpyAsync(asg.data(), assign_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+            PANO_HIP(hipStreamSynchronize(s));
+            std::fill(off.begin(), off.end(), 0);
+            for (int64_t i = 0; i < n; ++i) off[asg[i] + 1]++;
+            for (int c = 0; c < nlist; ++c) off[c + 1] += off[c];
+            std::vector<int64_t> fill(off.begin(), off.end() - 1);
+            for (int64_t i = 0; i < n; ++i) perm[fill[asg[i]]++] = i;
+            PANO_HIP(hipMemcpyAsync(perm_d.p, perm.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+            PANO_HIP(hipMemcpyAsync(off_d.p, off.data(), sizeof(int64_t) * (nlist + 1), hipMemcpyHostToDevice, s));
+            launch_centroid_update(x_dev, d, perm_d.as<int64_t>(), off_d.as<int64_t>(), nlist, centroids_dev, s);
+            PANO_HIP(hipStreamSynchronize(s));
+        }
+        assign_pass();
+        PANO_HIP(hipStreamSynchronize(s));
+    });
+}
+
+pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const float *x_dev, int64_t n, int32_t d,
+                              const float *centroids_dev, const int32_t *assign_dev, int32_t nlist,
+                              const int32_t *m_host, int32_t L, int32_t block, pano_dtype store, pano_index **out,
+                              void *stream)
+{
+    return guarded([&] {
+        PANO_REQUIRE(ctx && tf && x_dev && centroids_dev && assign_dev && m_host && out, "null argument");
+        PANO_REQUIRE(tf->d == d, "transform dimension does not match d");
+        PANO_REQUIRE(n >= 1 && d >= 1 && nlist >= 1, "bad sizes");
+        PANO_REQUIRE(L >= 1 && L <= 64, "L must be in [1, 64]");
+        PANO_REQUIRE(m_host[0] == 0 && m_host[L] == d, "level cuts must start at 0 and end at d");
+        for (int l = 0; l < L; ++l) PANO_REQUIRE(m_host[l] < m_host[l + 1], "level cuts must increase");
+        if (block == 0) block = 256;
+        PANO_REQUIRE(block == 64 || block == 128 || block == 256, "block must be 64, 128 or 256");
+        PANO_REQUIRE(store == PANO_F32 || store == PANO_BF16, "unknown storage dtype");
+        PANO_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        auto ix = std::make_unique<pano_index>();
+        ix->ctx = ctx;
+        ix->n = n;
+        ix->d = d;
+        ix->nlist = nlist;
+        ix->L = L;
+        ix->B = block;
+        ix->m.assign(m_host, m_host + L + 1);
+        ix->mp.assign(L + 1, 0);
+        ix->wp.assign(L, 0);
+        for (int l = 0; l < L; ++l) {
+            ix->wp[l] = ((m_host[l + 1] - m_host[l]) + 3) / 4 * 4;
+            ix->mp[l + 1] = ix->mp[l] + ix->wp[l];
+        }
+        ix->d_pad = ix->mp[L];
+        PANO_REQUIRE(ix->wp[0] <= 64, "the first level may hold at most 64 dimensions");
+        PANO_REQUIRE(ix->d_pad <= 4096, "d up to 4096 is supported");
+        ix->has_bf16 = store == PANO_BF16;
+        // transform in FP32
+        std::vector<float> T32((size_t)d * d), mu32(d);
+        for (size_t i = 0; i < T32.size(); ++i) T32[i] = (float)tf->T[i];
+        for (int j = 0; j < d; ++j) mu32[j] = (float)tf->mu[j];
+        compute_margins(ix.get(), T32);
+        ix->T32.alloc(sizeof(float) * T32.size());
+        ix->mu32.alloc(sizeof(float) * d);
+        PANO_HIP(hipMemcpyAsync(ix->T32.p, T32.data(), sizeof(float) * T32.size(), hipMemcpyHostToDevice, s));
+        PANO_HIP(hipMemcpyAsync(ix->mu32.p, mu32.data(), sizeof(float) * d, hipMemcpyHostToDevice, s));
+        std::vector<int32_t> padcol(d);
+        for (int l = 0; l < L; ++l)
+            for (int j = m_host[l]; j < m_host[l + 1]; ++j) padcol[j] = ix->mp[l] + (j - m_host[l]);
+        DevMem padcol_d, Y, tails_row, vnorm;
+        padcol_d.alloc(sizeof(int32_t) * d);
+        PANO_HIP(hipMemcpyAsync(padcol_d.p, padcol.data(), sizeof(int32_t) * d, hipMemcpyHostToDevice, s));
+        ix->meta.alloc(sizeof(int32_t) * d);
+        PANO_HIP(hipMemcpyAsync(ix->meta.p, padcol.data(), sizeof(int32_t) * d, hipMemcpyHostToDevice, s));
+        Y.alloc(sizeof(float) * (size_t)n * ix->d_pad);
+        PANO_HIP(hipMemsetAsync(Y.p, 0, Y.bytes, s));
+        launch_transform(x_dev, n, d, ix->T32.as<float>(), ix->mu32.as<float>(), padcol_d.as<int32_t>(), Y.as<float>(),
+                         ix->d_pad, s);
+        tails_row.alloc(sizeof(float) * (size_t)n * L);
+        vnorm.alloc(sizeof(double) * n);
+        LevelGeom g = geom_of(ix.get());
+        launch_row_norms(Y.as<float>(), n, g, x_dev, ix->mu32.as<float>(), tails_row.as<float>(), vnorm.as<double>(), s);
+        std::vector<double> vn(n);
+        PANO_HIP(hipMemcpyAsync(vn.data(), vnorm.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        std::vector<int32_t> asg(n);
+        PANO_HIP(hipMemcpyAsync(asg.data(), assign_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        PANO_HIP(hipStreamSynchronize(s));
+        double vmax = 0.0;
+        for (double v : vn) vmax = std::max(vmax, v);
+        ix->transform_err_max = (double)ix->mg.kappa * vmax * (1.0 + 1e-6);
+        ix->mg.e_max = (float)(ix->transform_err_max * (1.0 + 1e-6));
+        // lists: stable counting sort by assignment
+        ix->list_len.assign(nlist, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            PANO_REQUIRE(asg[i] >= 0 && asg[i] < nlist, "assignment out of range");
+            ix->list_len[asg[i]]++;
+        }
+        std::vector<int64_t> start(nlist + 1, 0);
+        for (int l = 0; l < nlist; ++l) start[l + 1] = start[l] + ix->list_len[l];
+        std::vector<int64_t> perm(n);
+        {
+            std::vector<int64_t> fill(start.begin(), start.end() - 1);
+            for (int64_t i = 0; i < n; ++i) perm[fill[asg[i]]++] = i;
+        }
+        ix->list_blk.assign(nlist + 1, 0);
+        for (int l = 0; l < nlist; ++l) {
+            int64_t nb = (ix->list_len[l] + block - 1) / block;
+            ix->list_blk[l + 1] = ix->list_blk[l] + nb;
+            ix->max_list_len = std::max(ix->max_list_len, ix->list_len[l]);
+            ix->max_list_blocks = std::max(ix->max_list_blocks, nb);
+        }
+        ix->nblocks = ix->list_blk[nlist];
+        std::vector<int32_t> block_list(std::max<int64_t>(1, ix->nblocks));
+        for (int l = 0; l < nlist; ++l)
+            for (int64_t b = ix->list_blk[l]; b < ix->list_blk[l + 1]; ++b) block_list[b] = l;
+        DevMem perm_d, start_d, block_list_d;
+        perm_d.alloc(sizeof(int64_t) * n);
+        start_d.alloc(sizeof(int64_t) * (nlist + 1));
+        block_list_d.alloc(sizeof(int32_t) * block_list.size());
+        ix->list_blk_d.alloc(sizeof(int64_t) * (nlist + 1));
+        ix->list_len_d.alloc(sizeof(int64_t) * nlist);
+        PANO_HIP(hipMemcpyAsync(perm_d.p, perm.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+        PANO_HIP(hipMemcpyAsync(start_d.p, start.data(), sizeof(int64_t) * (nlist + 1), hipMemcpyHostToDevice, s));
+        PANO_HIP(hipMemcpyAsync(block_list_d.p, block_list.data(), sizeof(int32_t) * block_list.size(),
+                                hipMemcpyHostToDevice, s));
+        PANO_HIP(hipMemcpyAsync(ix->list_blk_d.p, ix->list_blk.data(), sizeof(int64_t) * (nlist + 1),
+                                hipMemcpyHostToDevice, s));
+        PANO_HIP(hipMemcpyAsync(ix->list_len_d.p, ix->list_len.data(), sizeof(int64_t) * nlist, hipMemcpyHostToDevice, s));
+        const size_t slots = (size_t)ix->nblocks * block;
+        ix->levels.alloc(sizeof(float) * slots * ix->d_pad);
+        if (ix->has_bf16) ix->levels_bf16.alloc(sizeof(uint16_t) * slots * ix->d_pad);
+        ix->tails.alloc(sizeof(float) * slots * L);
+        ix->ids.alloc(sizeof(int32_t) * slots);
+        ix->blk_cnt.alloc(sizeof(int32_t) * std::max<int64_t>(1, ix->nblocks));
+        launch_pack(Y.as<float>(), tails_row.as<float>(), perm_d.as<int64_t>(), start_d.as<int64_t>(),
+                    ix->list_blk_d.as<int64_t>(), block_list_d.as<int32_t>(), ix->nblocks, g, ix->levels.as<float>(),
+                    ix->has_bf16 ? ix->levels_bf16.as<uint16_t>() : nullptr, ix->tails.as<float>(),
+                    ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(), s);
+        ix->raw.alloc(sizeof(float) * (size_t)n * d);
+        PANO_HIP(hipMemcpyAsync(ix->raw.p, x_dev, sizeof(float) * (size_t)n * d, hipMemcpyDeviceToDevice, s));
+        ix->cent.alloc(sizeof(float) * ((size_t)nlist * d + nlist));
+        PANO_HIP(hipMemcpyAsync(ix->cent.p, centroids_dev, sizeof(float) * (size_t)nlist * d, hipMemcpyDeviceToDevice, s));
+        launch_sqnorms(ix->cent.as<float>(), nlist, d, ix->cent.as<float>() + (size_t)nlist * d, s);
+        PANO_HIP(hipStreamSynchronize(s));
+        *out = ix.release();
+    });
+}
+
+pano_status pano_search(pano_index *idx, const float *q_dev, int64_t nq, int32_t k, const int32_t *nprobe_dev,
+                        int32_t nprobe_all, float eps, int64_t *ids_dev, float *dists_dev,
+                        const pano_search_params *params, uint32_t flags, void *stream)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx && (nq == 0 || (q_dev && ids_dev && dists_dev)), "null argument");
+        PANO_REQUIRE(k >= 1 && nq >= 0, "need k >= 1 and nq >= 0");
+        PANO_REQUIRE(eps >= 0.f && eps <= 1.f, "eps must be in [0, 1]");
+        PANO_REQUIRE(nprobe_dev != nullptr || nprobe_all >= 1, "nprobe_all must be >= 1");
+        if (nq == 0) return;
+        run_search(idx, q_dev, nq, k, nprobe_dev, nprobe_all, eps, ids_dev, dists_dev, params, flags, false,
+                   (hipStream_t)stream);
+    });
+}
+
+pano_status pano_search_bruteforce(pano_index *idx, const float *q_dev, int64_t nq, int32_t k,
+                                   const int32_t *nprobe_dev, int32_t nprobe_all, int64_t *ids_dev, float *dists_dev,
+                                   const pano_search_params *params, uint32_t flags, void *stream)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx && (nq == 0 || (q_dev && ids_dev && dists_dev)), "null argument");
+        PANO_REQUIRE(k >= 1 && nq >= 0, "need k >= 1 and nq >= 0");
+        PANO_REQUIRE(nprobe_dev != nullptr || nprobe_all >= 1, "nprobe_all must be >= 1");
+        if (nq == 0) return;
+        run_search(idx, q_dev, nq, k, nprobe_dev, nprobe_all, 1.f, ids_dev, dists_dev, params, flags, true,
+                   (hipStream_t)stream);
+    });
+}
+
+pano_status pano_index_info(const pano_index *idx, pano_index_info_t *out)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx && out, "null argument");
+        std::memset(out, 0, sizeof(*out));
+        out->n = idx->n;
+        out->d = idx->d;
+        out->d_pad = idx->d_pad;
+        out->nlist = idx->nlist;
+        out->L = idx->L;
+        out->block = idx->B;
+        out->has_bf16 = idx->has_bf16;
+        out->nblocks = idx->nblocks;
+        out->max_list_len = idx->max_list_len;
+        const int64_t slots = idx->nblocks * idx->B;
+        out->bytes_levels = slots * idx->d_pad * 4;
+        out->bytes_levels_bf16 = idx->has_bf16 ? slots * idx->d_pad * 2 : 0;
+        out->bytes_tails = slots * idx->L * 4;
+        out->bytes_ids = slots * 4;
+        out->bytes_raw = idx->n * idx->d * 4;
+        out->transform_err_max = idx->transform_err_max;
+        out->sigma_ratio = idx->sigma_ratio;
+    });
+}
+
+pano_status pano_index_layout(const pano_index *idx, int32_t *m_host, int64_t *list_len_host)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx, "null index");
+        if (m_host) std::copy(idx->m.begin(), idx->m.end(), m_host);
+        if (list_len_host) std::copy(idx->list_len.begin(), idx->list_len.end(), list_len_host);
+    });
+}
+
+pano_status pano_stats_get(const pano_index *idx, pano_stats_t *out)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx && out, "null argument");
+        *out = idx->stats;
+    });
+}
+
+void pano_index_free(pano_index *idx) { delete idx; }
+
+}  // extern "C"

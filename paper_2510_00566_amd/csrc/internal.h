@@ -1,0 +1,154 @@
+// Internal declarations of the pruned-scan library: handle layouts, error
+// helpers and the host-side launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/panorama.h"
+
+namespace pano {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+struct Error {
+    pano_status st;
+    std::string msg;
+};
+#define PANO_HIP(call)                                                                          \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            throw ::pano::Error{PANO_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+#define PANO_REQUIRE(cond, msg)                                  \
+    do {                                                         \
+        if (!(cond)) throw ::pano::Error{PANO_EINVAL, (msg)};    \
+    } while (0)
+
+// ---------------------------------------------------------------- host linalg
+void parallel_for(int64_t n, int64_t min_chunk, const std::function<void(int64_t, int64_t)> &fn);
+std::vector<int64_t> seeded_sample(int64_t n, int64_t count, uint64_t seed);
+void mean_cov_fp64(const float *x, int64_t n, int d, const std::vector<int64_t> &rows,
+                   std::vector<double> &mu, std::vector<double> &cov);
+bool symmetric_eigen(const std::vector<double> &sym, int n, std::vector<double> &evals,
+                     std::vector<double> &evecs_rows);
+
+// ---------------------------------------------------------------- device memory
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b)
+    {
+        release();
+        if (b == 0) b = 256;
+        if (hipMalloc(&p, b) != hipSuccess) {
+            p = nullptr;
+            throw Error{PANO_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+        }
+        bytes = b;
+    }
+    void ensure(size_t b)
+    {
+        if (b > bytes) alloc(b + b / 4);
+    }
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------- error model
+// Constants of the certified floating-point margins.  u = 2^-24 (FP32 unit
+// roundoff); gamma(n) = n u / (1 - n u).
+struct Margins {
+    float c_level[65];  // coefficient on the head distance after level l (l = 1..L)
+    float c_tail;       // coefficient on (a + b)^2 for the tail term
+    float e_max;        // max over stored rows of the transform error bound
+    float kappa;        // per-unit-norm transform error bound (queries use kappa*||v||)
+    float rho;          // sigma_max/sigma_min of the FP32 transform times (1+u')/(1-u') root
+    float c_final;      // coefficient on D~ for the error of the full distance
+};
+
+}  // namespace pano
+
+// ---------------------------------------------------------------- handles
+struct pano_ctx {
+    int device = 0;
+    int num_cu = 256;
+    pano::DevMem scratch[12];
+};
+
+struct pano_transform {
+    int d = 0;
+    std::vector<double> mu, T, lambda;
+    double alpha = 0.0;
+};
+
+struct pano_index {
+    pano_ctx *ctx = nullptr;
+    int64_t n = 0;
+    int d = 0, d_pad = 0, nlist = 0, L = 0, B = 256;
+    bool has_bf16 = false;
+    std::vector<int32_t> m, mp, wp;          // cuts, padded cuts, padded widths
+    std::vector<int64_t> list_len, list_blk; // list lengths, block offsets (nlist+1)
+    int64_t nblocks = 0, max_list_len = 0, max_list_blocks = 0;
+    pano::DevMem mu32, T32, cent, raw, levels, levels_bf16, tails, ids, blk_cnt, list_blk_d,
+        list_len_d, meta;
+    pano::Margins mg{};
+    double transform_err_max = 0.0, sigma_ratio = 1.0;
+    pano_stats_t stats{};
+};
+
+namespace pano {
+
+// ---------------------------------------------------------------- device launchers
+// Level geometry passed to kernels by value.
+struct LevelGeom {
+    int L;
+    int d;
+    int d_pad;
+    int B;
+    int mp[65];  // padded cuts
+    int wp[64];  // padded widths
+};
+
+// Y[r][padcol[j]] = sum_j T[i][j] * (X[r][j] - mu[j]) with chunked FP32
+// accumulation; Y has ld_y columns (padding columns are left untouched).
+void launch_transform(const float *X, int64_t n, int d, const float *T, const float *mu,
+                      const int32_t *padcol, float *Y, int ld_y, hipStream_t s);
+// Dense product S[r][c] = sum_j A[r][j] * Bm[c][j] (FP32), for k-means and the
+// coarse step.
+void launch_gemm_nt(const float *A, int64_t n, int d, const float *Bm, int nb, float *S,
+                    hipStream_t s);
+// Per row: tail norms sqrt(sum_{j >= mp_l} y_j^2) for l = 0..L-1 (FP64 sums),
+// and ||fl(x - mu)|| in FP64 (vnorm).
+void launch_row_norms(const float *Y, int64_t n, const LevelGeom &g, const float *X, const float *mu,
+                      float *tails_rowmajor, double *vnorm, hipStream_t s);
+void launch_argmin_rows(const float *S, int64_t n, int nb, const float *cnorm, int32_t *assign,
+                        hipStream_t s);
+void launch_centroid_update(const float *X, int d, const int64_t *perm, const int64_t *off, int nlist,
+                            float *cent, hipStream_t s);
+void launch_sqnorms(const float *X, int64_t n, int d, float *out, hipStream_t s);
+void launch_pack(const float *Y, const float *tails_row, const int64_t *perm, const int64_t *list_start,
+                 const int64_t *list_blk, const int32_t *block_list, int64_t nblocks, const LevelGeom &g,
+                 float *levels, uint16_t *levels_bf16, float *tails, int32_t *ids, int32_t *blk_cnt,
+                 hipStream_t s);
+
+struct SearchArgs;
+void run_search(pano_index *idx, const float *q, int64_t nq, int k, const int32_t *nprobe_dev,
+                int nprobe_all, float eps, int64_t *ids, float *dists, const pano_search_params *prm,
+                uint32_t flags, bool brute, hipStream_t s);
+
+}  // namespace pano

@@ -1,0 +1,314 @@
+// Build-side kernels for gfx950: the FP32 transform of rows into the
+// rotated frame (Section 4.1, applied as T (v - mu)), k-means assignment and
+// update (the IVF coarse quantiser of Section 6.1), per-row tail norms
+// (Section 6.5) and the level-major packing of Section 6.1.
+#include "internal.h"
+
+namespace pano {
+
+// ---------------------------------------------------------------- tiled product
+// One workgroup computes a 64 x 64 output tile; each thread a 4 x 4 sub-tile.
+// The reduction dimension is consumed in chunks of 32: every chunk is summed
+// in a fresh register and then added to the running total, so the rounding
+// error of an output is at most gamma(32 + ceil(K/32) + 1) times the sum of
+// the absolute products (the bound the pruning margins are built on).
+constexpr int TM = 64, TN = 64, TK = 32;
+
+template <bool SUB_MU>
+__global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, int64_t n, int K,
+                                                 const float *__restrict__ Bm, int nb,
+                                                 const float *__restrict__ mu,
+                                                 const int32_t *__restrict__ outcol,
+                                                 float *__restrict__ Out, int ld_out)
+{
+    __shared__ float As[TK][TM + 4];
+    __shared__ float Bs[TK][TN + 4];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * TM;
+    const int c0 = blockIdx.y * TN;
+    float tot[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) tot[i][j] = 0.f;
+
+    for (int k0 = 0; k0 < K; k0 += TK) {
+        // load A tile (TM rows x TK cols) and B tile (TN rows x TK cols)
+#pragma unroll
+        for (int t = 0; t < (TM * TK) / 256; ++t) {
+            int e = tid + t * 256;
+            int rr = e / TK, kk = e % TK;
+            int64_t r = r0 + rr;
+            int kx = k0 + kk;
+            float v = 0.f;
+            if (r < n && kx < K) {
+                v = A[r * K + kx];
+                if (SUB_MU) v = v - mu[kx];
+            }
+            As[kk][rr] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < (TN * TK) / 256; ++t) {
+            int e = tid + t * 256;
+            int cc = e / TK, kk = e % TK;
+            int c = c0 + cc;
+            int kx = k0 + kk;
+            Bs[kk][cc] = (c < nb && kx < K) ? Bm[(int64_t)c * K + kx] : 0.f;
+        }
+        __syncthreads();
+        float acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+#pragma unroll 8
+        for (int kk = 0; kk < TK; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fmaf(a[i], b[j], acc[i][j]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tot[i][j] += acc[i][j];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int64_t r = r0 + ty * 4 + i;
+        if (r >= n) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int c = c0 + tx * 4 + j;
+            if (c >= nb) continue;
+            int oc = outcol ? outcol[c] : c;
+            Out[r * ld_out + oc] = tot[i][j];
+        }
+    }
+}
+
+void launch_transform(const float *X, int64_t n, int d, const float *T, const float *mu,
+                      const int32_t *padcol, float *Y, int ld_y, hipStream_t s)
+{
+    if (n == 0) return;
+    dim3 grid((unsigned)((n + TM - 1) / TM), (unsigned)((d + TN - 1) / TN));
+    hipLaunchKernelGGL(k_tile_nt<true>, grid, dim3(256), 0, s, X, n, d, T, d, mu, padcol, Y, ld_y);
+    PANO_HIP(hipGetLastError());
+}
+
+void launch_gemm_nt(const float *A, int64_t n, int d, const float *Bm, int nb, float *S, hipStream_t s)
+{
+    if (n == 0) return;
+    dim3 grid((unsigned)((n + TM - 1) / TM), (unsigned)((nb + TN - 1) / TN));
+    hipLaunchKernelGGL(k_tile_nt<false>, grid, dim3(256), 0, s, A, n, d, Bm, nb, nullptr, nullptr, S, nb);
+    PANO_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- row norms
+// One wavefront per row.  Level energies are summed in FP64, the tail norm
+// after level l is the square root of the suffix sum, rounded to FP32.
+__device__ inline double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, int64_t n, LevelGeom g,
+                                                   const float *__restrict__ X,
+                                                   const float *__restrict__ mu,
+                                                   float *__restrict__ tails, double *__restrict__ vnorm)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    const float *y = Y + r * g.d_pad;
+    double suffix = 0.0;
+    for (int l = g.L - 1; l >= 0; --l) {
+        double e = 0.0;
+        for (int c = g.mp[l] + lane; c < g.mp[l + 1]; c += 64) {
+            double v = (double)y[c];
+            e += v * v;
+        }
+        e = wave_sum_f64(e);
+        suffix += e;
+        if (lane == 0) tails[r * g.L + l] = (float)sqrt(suffix);
+    }
+    if (vnorm) {
+        const float *x = X + r * g.d;
+        double e = 0.0;
+        for (int c = lane; c < g.d; c += 64) {
+            double v = (double)(x[c] - mu[c]);
+            e += v * v;
+        }
+        e = wave_sum_f64(e);
+        if (lane == 0) vnorm[r] = sqrt(e);
+    }
+}
+
+void launch_row_norms(const float *Y, int64_t n, const LevelGeom &g, const float *X, const float *mu,
+                      float *tails_rowmajor, double *vnorm, hipStream_t s)
+{
+    if (n == 0) return;
+    dim3 grid((unsigned)((n + 3) / 4));
+    hipLaunchKernelGGL(k_row_norms, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm);
+    PANO_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- k-means
+__global__ __launch_bounds__(256) void k_sqnorms(const float *__restrict__ X, int64_t n, int d,
+                                                 float *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    float e = 0.f;
+    for (int c = lane; c < d; c += 64) e = __builtin_fmaf(X[r * d + c], X[r * d + c], e);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+    if (lane == 0) out[r] = e;
+}
+
+void launch_sqnorms(const float *X, int64_t n, int d, float *out, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_sqnorms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d, out);
+    PANO_HIP(hipGetLastError());
+}
+
+// assign[r] = argmin_c (||c||^2 - 2 <x_r, c>), ties to the smaller c.
+__global__ __launch_bounds__(256) void k_argmin_rows(const float *__restrict__ S, int64_t n, int nb,
+                                                     const float *__restrict__ cnorm,
+                                                     int32_t *__restrict__ assign)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    float best = INFINITY;
+    int bi = 0x7fffffff;
+    for (int c = lane; c < nb; c += 64) {
+        float v = cnorm[c] - 2.f * S[r * nb + c];
+        if (v < best || (v == best && c < bi)) {
+            best = v;
+            bi = c;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        float ov = __shfl_xor(best, o, 64);
+        int oi = __shfl_xor(bi, o, 64);
+        if (ov < best || (ov == best && oi < bi)) {
+            best = ov;
+            bi = oi;
+        }
+    }
+    if (lane == 0) assign[r] = bi;
+}
+
+void launch_argmin_rows(const float *S, int64_t n, int nb, const float *cnorm, int32_t *assign,
+                        hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_argmin_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, S, n, nb, cnorm, assign);
+    PANO_HIP(hipGetLastError());
+}
+
+// One workgroup per cluster: mean of its members (FP64 sums over members in
+// ascending row order).  Empty clusters keep their centroid.
+__global__ __launch_bounds__(256) void k_centroid_update(const float *__restrict__ X, int d,
+                                                         const int64_t *__restrict__ perm,
+                                                         const int64_t *__restrict__ off,
+                                                         float *__restrict__ cent)
+{
+    const int c = blockIdx.x;
+    const int64_t b = off[c], e = off[c + 1];
+    if (e <= b) return;
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+        double s = 0.0;
+        for (int64_t t = b; t < e; ++t) s += (double)X[perm[t] * d + j];
+        cent[(int64_t)c * d + j] = (float)(s / (double)(e - b));
+    }
+}
+
+void launch_centroid_update(const float *X, int d, const int64_t *perm, const int64_t *off, int nlist,
+                            float *cent, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_centroid_update, dim3(nlist), dim3(256), 0, s, X, d, perm, off, cent);
+    PANO_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- packing
+__device__ inline uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+// One workgroup per block of B slots.  Level-major within the block: all B
+// slices of level 0, then all B slices of level 1, ...
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ Y, const float *__restrict__ tails_row,
+                                              const int64_t *__restrict__ perm,
+                                              const int64_t *__restrict__ list_start,
+                                              const int64_t *__restrict__ list_blk,
+                                              const int32_t *__restrict__ block_list, LevelGeom g,
+                                              float *__restrict__ levels, uint16_t *__restrict__ levels_bf16,
+                                              float *__restrict__ tails, int32_t *__restrict__ ids,
+                                              int32_t *__restrict__ blk_cnt)
+{
+    __shared__ int lvl_of[4096];
+    __shared__ int64_t rows[1024];
+    const int64_t gb = blockIdx.x;
+    const int l = block_list[gb];
+    const int64_t first = (gb - list_blk[l]) * g.B;
+    const int64_t len = list_start[l + 1] - list_start[l];
+    const int cnt = (int)min<int64_t>(g.B, len - first);
+    for (int c = threadIdx.x; c < g.d_pad; c += blockDim.x) {
+        int lv = 0;
+        while (c >= g.mp[lv + 1]) ++lv;
+        lvl_of[c] = lv;
+    }
+    for (int s = threadIdx.x; s < g.B; s += blockDim.x)
+        rows[s] = s < cnt ? perm[list_start[l] + first + s] : -1;
+    __syncthreads();
+    if (threadIdx.x == 0) blk_cnt[gb] = cnt;
+    float *dst = levels + gb * (int64_t)g.B * g.d_pad;
+    uint16_t *dstb = levels_bf16 ? levels_bf16 + gb * (int64_t)g.B * g.d_pad : nullptr;
+    const int64_t tot = (int64_t)g.B * g.d_pad;
+    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+        int s = (int)(e / g.d_pad), c = (int)(e % g.d_pad);
+        int lv = lvl_of[c];
+        int64_t r = rows[s];
+        float v = r >= 0 ? Y[r * g.d_pad + c] : 0.f;
+        int64_t o = (int64_t)g.B * g.mp[lv] + (int64_t)s * g.wp[lv] + (c - g.mp[lv]);
+        dst[o] = v;
+        if (dstb) dstb[o] = f32_to_bf16_rne(v);
+    }
+    for (int e = threadIdx.x; e < g.B * g.L; e += blockDim.x) {
+        int lv = e / g.B, s = e % g.B;
+        int64_t r = rows[s];
+        tails[gb * (int64_t)g.B * g.L + e] = r >= 0 ? tails_row[r * g.L + lv] : 0.f;
+    }
+    for (int s = threadIdx.x; s < g.B; s += blockDim.x) ids[gb * g.B + s] = (int32_t)rows[s];
+}
+
+void launch_pack(const float *Y, const float *tails_row, const int64_t *perm, const int64_t *list_start,
+                 const int64_t *list_blk, const int32_t *block_list, int64_t nblocks, const LevelGeom &g,
+                 float *levels, uint16_t *levels_bf16, float *tails, int32_t *ids, int32_t *blk_cnt,
+                 hipStream_t s)
+{
+    if (nblocks == 0) return;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)nblocks), dim3(256), 0, s, Y, tails_row, perm, list_start,
+                       list_blk, block_list, g, levels, levels_bf16, tails, ids, blk_cnt);
+    PANO_HIP(hipGetLastError());
+}
+
+}  // namespace pano

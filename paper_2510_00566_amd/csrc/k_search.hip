@@ -1,0 +1,987 @@
+// Search kernels for gfx950: coarse probing, work decomposition, threshold
+// seeding, the persistent pruned scan (Algorithm 1 with the Compute / Update /
+// Consolidate phases of Section 6.1 fused per level), the per-query merge with
+// canonical rescoring of the boundary band, and the exact fallback.
+#include "search_common.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace pano {
+
+// ================================================================ query prep
+__global__ void k_query_consts(const double *__restrict__ vnorm, int64_t nq, float kappa, float e_max,
+                               float *__restrict__ qE)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    // Rounded up by a relative 1e-6 to cover the FP32 rounding of this bound.
+    qE[i] = (float)((double)kappa * vnorm[i] * (1.0 + 1e-6)) + e_max;
+}
+
+// ================================================================ coarse probing
+// One workgroup per query.  Approximate distances to every centroid come from
+// the dense product S = q . c (chunked FP32), with a certified absolute error
+// bound c_co (||q||^2 + ||c||^2).  A list is certainly in the probe set if its
+// upper bound is below the (p+1)-th smallest lower bound; the uncertain lists
+// of the band are rescored with the canonical recipe and ordered by (D, l).
+__global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, const float *__restrict__ qn2,
+                                               const float *__restrict__ cn2, const float *__restrict__ q,
+                                               const float *__restrict__ cent, int d, int nlist,
+                                               const int32_t *__restrict__ nprobe_dev, int nprobe_all,
+                                               float c_co, int np_max, int32_t *__restrict__ probes,
+                                               int32_t *__restrict__ np_out)
+{
+    extern __shared__ uint64_t sm[];
+    uint64_t *K = sm;                               // [P]
+    float *LO = reinterpret_cast<float *>(K + next_pow2(nlist));  // [nlist]
+    float *UP = LO + nlist;                         // [nlist]
+    __shared__ int wave_tmp[NT / 64];
+    __shared__ float Up_s, Lp1_s;
+    __shared__ int ncert_s, nunc_s;
+    const int64_t qi = blockIdx.x;
+    const int P = next_pow2(nlist);
+    int p = nprobe_dev ? nprobe_dev[qi] : nprobe_all;
+    p = p < 1 ? 1 : (p > nlist ? nlist : p);
+    if (p > np_max) p = np_max;
+    const float u2 = 1.0f + 1.2e-7f;  // (1 + u') for the FP32 rounding of D
+    const float qq = qn2[qi];
+    for (int l = threadIdx.x; l < P; l += NT) {
+        if (l < nlist) {
+            float a = qq + cn2[l] - 2.f * S[qi * nlist + l];
+            float del = c_co * (qq + cn2[l]);
+            float lo = fmaxf(a - del, 0.f) * (1.0f - 1.2e-7f);
+            float up = (a + del) * u2;
+            LO[l] = lo;
+            UP[l] = up;
+            K[l] = make_key(up, l);
+        } else {
+            K[l] = KEY_MAX;
+        }
+    }
+    __syncthreads();
+    block_bitonic_sort(K, P);
+    if (threadIdx.x == 0) Up_s = key_dist(K[p - 1]);
+    __syncthreads();
+    for (int l = threadIdx.x; l < P; l += NT) K[l] = l < nlist ? make_key(LO[l], l) : KEY_MAX;
+    __syncthreads();
+    block_bitonic_sort(K, P);
+    if (threadIdx.x == 0) Lp1_s = p < nlist ? key_dist(K[p]) : INFINITY;
+    __syncthreads();
+    const float Up = Up_s, Lp1 = Lp1_s;
+    // Walk the lists in ascending lower-bound order: certain ones go straight to
+    // the output, uncertain band members to a rescoring list (kept in LO's
+    // storage, which is no longer needed once copied).
+    int ncert = 0, nunc = 0;
+    int32_t *ulist = reinterpret_cast<int32_t *>(UP + nlist);  // [nlist]
+    for (int base = 0; base < nlist; base += NT) {
+        int r = base + threadIdx.x;
+        int l = r < nlist ? key_id(K[r]) : 0;
+        bool inb = r < nlist && LO[l] <= Up;
+        bool cert = inb && UP[l] < Lp1;
+        bool unc = inb && !cert;
+        int tc, tu;
+        int oc = block_exclusive_scan(cert ? 1 : 0, wave_tmp, &tc);
+        int ou = block_exclusive_scan(unc ? 1 : 0, wave_tmp, &tu);
+        if (cert && ncert + oc < p) probes[qi * np_max + ncert + oc] = l;
+        if (unc) ulist[nunc + ou] = l;
+        ncert += tc;
+        nunc += tu;
+        __syncthreads();
+    }
+    if (ncert > p) ncert = p;  // cannot happen: certain lists number at most p
+    const int need = p - ncert;
+    if (need > 0) {
+        const int PU = next_pow2(nunc);
+        for (int i = threadIdx.x; i < PU; i += NT) {
+            if (i < nunc) {
+                int l = ulist[i];
+                K[i] = make_key(canon_dist(q + qi * d, cent + (int64_t)l * d, d), l);
+            } else {
+                K[i] = KEY_MAX;
+            }
+        }
+        __syncthreads();
+        block_bitonic_sort(K, PU);
+        for (int i = threadIdx.x; i < need; i += NT) probes[qi * np_max + ncert + i] = key_id(K[i]);
+    }
+    for (int i = p + threadIdx.x; i < np_max; i += NT) probes[qi * np_max + i] = -1;
+    if (threadIdx.x == 0) np_out[qi] = p;
+}
+
+__global__ void k_single_list(int64_t nq, int np_max, int32_t *__restrict__ probes, int32_t *__restrict__ np_out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    probes[i * np_max] = 0;
+    for (int r = 1; r < np_max; ++r) probes[i * np_max + r] = -1;
+    np_out[i] = 1;
+}
+
+// ================================================================ work list
+__global__ void k_wl_count(int64_t nq, int np_max, const int32_t *__restrict__ probes,
+                           const int32_t *__restrict__ np, int32_t *__restrict__ list_cnt)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    for (int r = 0; r < np[i]; ++r) atomicAdd(&list_cnt[probes[i * np_max + r]], 1);
+}
+
+// One workgroup: per-list query offsets and the item offsets of the eight
+// XCD queues (lists are ordered by (l mod 8, l div 8)).
+__global__ __launch_bounds__(NT) void k_wl_offsets(int nlist, int ceil8, int G, int bpi,
+                                                   const int32_t *__restrict__ list_cnt,
+                                                   const int64_t *__restrict__ list_blk,
+                                                   int64_t *__restrict__ list_qoff,
+                                                   int64_t *__restrict__ item_off)
+{
+    __shared__ int wave_tmp[NT / 64];
+    int64_t run = 0;
+    for (int base = 0; base < nlist; base += NT) {
+        int l = base + threadIdx.x;
+        int c = l < nlist ? list_cnt[l] : 0;
+        int tot;
+        int o = block_exclusive_scan(c, wave_tmp, &tot);
+        if (l < nlist) list_qoff[l] = run + o;
+        run += tot;
+    }
+    if (threadIdx.x == 0) list_qoff[nlist] = run;
+    __syncthreads();
+    const int npos = 8 * ceil8;
+    int64_t irun = 0;
+    for (int base = 0; base < npos; base += NT) {
+        int pos = base + threadIdx.x;
+        int items = 0;
+        if (pos < npos) {
+            int l = (pos % ceil8) * 8 + pos / ceil8;
+            if (l < nlist) {
+                int c = list_cnt[l];
+                int64_t nb = list_blk[l + 1] - list_blk[l];
+                if (c > 0 && nb > 0) items = ((c + G - 1) / G) * (int)((nb + bpi - 1) / bpi);
+            }
+        }
+        int tot;
+        int o = block_exclusive_scan(items, wave_tmp, &tot);
+        if (pos < npos) item_off[pos] = irun + o;
+        irun += tot;
+    }
+    if (threadIdx.x == 0) item_off[npos] = irun;
+}
+
+__global__ void k_wl_fill(int64_t nq, int np_max, const int32_t *__restrict__ probes,
+                          const int32_t *__restrict__ np, const int64_t *__restrict__ list_qoff,
+                          int32_t *__restrict__ list_fill, int32_t *__restrict__ list_q)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    for (int r = 0; r < np[i]; ++r) {
+        int l = probes[i * np_max + r];
+        int pos = atomicAdd(&list_fill[l], 1);
+        list_q[list_qoff[l] + pos] = (int32_t)i;
+    }
+}
+
+// ================================================================ index views
+struct IndexView {
+    const float *levels;
+    const float *tails;   // [block][level][B]
+    const int32_t *ids;   // [block][B]
+    const int32_t *blk_cnt;
+    const int64_t *list_blk;
+    const float *raw;     // [n][d]
+};
+
+struct QueryView {
+    const float *qy;      // [nq][d_pad]
+    const float *qtail;   // [nq][L]
+    const float *qE;      // [nq]
+    const float *qraw;    // [nq][d]
+};
+
+// ================================================================ seeding
+// One workgroup per query: rank the first `pool` candidates of the query's
+// nearest list by their level-1 lower bound, compute the full distance of the
+// `cnt` most promising ones and start d_k from their k-th best (Algorithm 1
+// seeds its heap with exact distances before the first batch).
+__global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, QueryView qv,
+                                             const int32_t *__restrict__ probes, int np_max,
+                                             const int64_t *__restrict__ list_len, int pool, int cnt,
+                                             float *__restrict__ thr)
+{
+    __shared__ uint64_t K[1024];
+    const int64_t q = blockIdx.x;
+    const int l0 = probes[q * np_max];
+    const int64_t len = list_len[l0];
+    const int P = (int)min<int64_t>(pool, len);
+    const int S = min(cnt, P);
+    if (S < c.k) return;
+    const LevelGeom &g = c.g;
+    const int64_t b0 = ix.list_blk[l0];
+    const float *qy = qv.qy + q * g.d_pad;
+    const float a1 = g.L > 1 ? qv.qtail[q * g.L + 1] : 0.f;
+    const int PP = next_pow2(P);
+    for (int p = threadIdx.x; p < PP; p += NT) {
+        if (p < P) {
+            int64_t gb = b0 + p / g.B;
+            int s = p % g.B;
+            const float *x = ix.levels + gb * (int64_t)g.B * g.d_pad + (int64_t)s * g.wp[0];
+            float sh = 0.f;
+            for (int j = 0; j < g.wp[0]; ++j) {
+                float t = qy[j] - x[j];
+                sh = __builtin_fmaf(t, t, sh);
+            }
+            float b1 = g.L > 1 ? ix.tails[gb * (int64_t)g.B * g.L + g.B + s] : 0.f;
+            float tt = a1 - b1;
+            K[p] = make_key(sh + tt * tt, p);
+        } else {
+            K[p] = KEY_MAX;
+        }
+    }
+    __syncthreads();
+    block_bitonic_sort(K, PP);
+    // Full distance of the S most promising candidates.
+    uint64_t mine = KEY_MAX;
+    if (threadIdx.x < S) {
+        int p = key_id(K[threadIdx.x]);
+        int64_t gb = b0 + p / g.B;
+        int s = p % g.B;
+        const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
+        float sh = 0.f;
+        for (int lv = 0; lv < g.L; ++lv) {
+            const float *x = blk + (int64_t)g.B * g.mp[lv] + (int64_t)s * g.wp[lv];
+            const float *qq = qy + g.mp[lv];
+            for (int j = 0; j < g.wp[lv]; ++j) {
+                float t = qq[j] - x[j];
+                sh = __builtin_fmaf(t, t, sh);
+            }
+        }
+        mine = make_key(sh, threadIdx.x);
+    }
+    __syncthreads();
+    const int PS = next_pow2(S);
+    for (int i = threadIdx.x; i < PS; i += NT) K[i] = KEY_MAX;
+    __syncthreads();
+    if (threadIdx.x < S) K[threadIdx.x] = mine;
+    __syncthreads();
+    block_bitonic_sort(K, PS);
+    if (threadIdx.x == 0) {
+        float t = prune_threshold(key_dist(K[c.k - 1]), qv.qE[q], c.mg);
+        atomic_min_nonneg(&thr[q], t);
+    }
+}
+
+// ================================================================ scan
+struct WorkView {
+    const int32_t *list_cnt;
+    const int64_t *list_qoff;
+    const int32_t *list_q;
+    const int64_t *item_off;
+    int32_t *heads;        // [8] queue heads
+    float *thr;            // [nq]
+    uint64_t *buf;         // [nq][capq]
+    int32_t *buf_cnt;      // [nq]
+    int32_t *flags;        // [nq]
+    unsigned long long *stats;  // optional counters
+};
+
+// Counters layout (unsigned long long): [0] items, [1] committed, [2] bytes,
+// [8 + l] pairs reading level l.
+constexpr int ST_ITEMS = 0, ST_COMMIT = 1, ST_BYTES = 2, ST_LEVEL = 8;
+
+template <bool PRUNE>
+__global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    __shared__ uint32_t pr[GMAX * 256];
+    __shared__ float pS[GMAX * 256];
+    __shared__ uint8_t keep[GMAX * 256];
+    __shared__ uint64_t sbuf[NT / 64][SB_MAX];
+    __shared__ uint64_t topk[1024];
+    __shared__ int wave_tmp[NT / 64];
+    __shared__ int qid_s[GMAX], tcnt[GMAX], ncand[GMAX];
+    __shared__ float thr_s[GMAX], E_s[GMAX];
+    __shared__ int item_s, npairs_s;
+
+    const LevelGeom &g = c.g;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    float *Stmp = reinterpret_cast<float *>(&sbuf[0][0]);  // [GMAX][256], aliases sbuf
+    __shared__ unsigned long long my_lv[64];
+    int queue = blockIdx.x & 7;
+    int tried = 0;
+    unsigned long long my_items = 0, my_bytes = 0;
+    const int Lc = g.L < 64 ? g.L : 64;
+    for (int i = tid; i < 64; i += NT) my_lv[i] = 0;
+
+    while (true) {
+        // ---- pull the next item from this workgroup's XCD queue, then steal
+        if (tid == 0) {
+            int it = -1;
+            while (tried < 8) {
+                const int64_t qb = wk.item_off[queue * c.ceil8], qe = wk.item_off[(queue + 1) * c.ceil8];
+                if (qe > qb) {
+                    int v = atomicAdd(&wk.heads[queue], 1);
+                    if (qb + v < qe) {
+                        it = (int)(qb + v);
+                        break;
+                    }
+                }
+                queue = (queue + 1) & 7;
+                ++tried;
+            }
+            item_s = it;
+        }
+        __syncthreads();
+        const int item = item_s;
+        if (item < 0) break;
+        // ---- decode: binary search the queue-ordered item offsets
+        int lo = 0, hi = 8 * c.ceil8;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (wk.item_off[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const int pos = lo;
+        const int l = (pos % c.ceil8) * 8 + pos / c.ceil8;
+        const int local = (int)(item - wk.item_off[pos]);
+        const int qcnt = wk.list_cnt[l];
+        const int groups = (qcnt + c.G - 1) / c.G;
+        const int gi = local % groups, ri = local / groups;
+        const int ng = min(c.G, qcnt - gi * c.G);
+        const int64_t lb0 = ix.list_blk[l], nblk = ix.list_blk[l + 1] - lb0;
+        const int bstart = ri * c.bpi;
+        const int bend = (int)min<int64_t>(nblk, (int64_t)(ri + 1) * c.bpi);
+        if (tid < ng) {
+            int qq = wk.list_q[wk.list_qoff[l] + gi * c.G + tid];
+            qid_s[tid] = qq;
+            tcnt[tid] = 0;
+            thr_s[tid] = INFINITY;
+            E_s[tid] = qv.qE[qq];
+        }
+        ++my_items;
+        __syncthreads();
+
+        for (int bb = bstart; bb < bend; ++bb) {
+            const int64_t gb = lb0 + bb;
+            const int cnt = ix.blk_cnt[gb];
+            const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
+            const float *tl = ix.tails + gb * (int64_t)g.B * g.L;
+            if (tid < ng) {
+                float t = __hip_atomic_load(&wk.thr[qid_s[tid]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                thr_s[tid] = fminf(thr_s[tid], t);
+                ncand[tid] = 0;
+            }
+            __syncthreads();
+            const int s = tid;
+            const bool valid = s < cnt;
+            uint32_t mask = 0;
+            if (PRUNE) {
+                // ---- level 1, dense over the block: every candidate against
+                // every query of the group (the query slice is wave-uniform).
+                const int w0 = g.wp[0];
+                float4 xr[16];
+#pragma unroll
+                for (int c4 = 0; c4 < 16; ++c4) {
+                    if (c4 * 4 < w0 && valid) xr[c4] = *reinterpret_cast<const float4 *>(blk + (int64_t)s * w0 + c4 * 4);
+                    else xr[c4] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                const float b1 = (g.L > 1 && valid) ? tl[g.B + s] : 0.f;
+                for (int gq = 0; gq < ng; ++gq) {
+                    const int qq = __builtin_amdgcn_readfirstlane(qid_s[gq]);
+                    const float *qy = qv.qy + (int64_t)qq * g.d_pad;
+                    float sh = 0.f;
+#pragma unroll
+                    for (int c4 = 0; c4 < 16; ++c4) {
+                        if (c4 * 4 < w0) {
+                            float4 q4 = *reinterpret_cast<const float4 *>(qy + c4 * 4);
+                            float t0 = q4.x - xr[c4].x, t1 = q4.y - xr[c4].y;
+                            float t2 = q4.z - xr[c4].z, t3 = q4.w - xr[c4].w;
+                            sh = __builtin_fmaf(t0, t0, sh);
+                            sh = __builtin_fmaf(t1, t1, sh);
+                            sh = __builtin_fmaf(t2, t2, sh);
+                            sh = __builtin_fmaf(t3, t3, sh);
+                        }
+                    }
+                    const float a1 = g.L > 1 ? qv.qtail[(int64_t)qq * g.L + 1] : 0.f;
+                    const float dt = a1 - b1;
+                    const float lb = sh + dt * dt + c.one_m_eps2 * a1 * b1;
+                    const float eta = c.mg.c_level[1] * sh + c.mg.c_tail * (a1 + b1) * (a1 + b1);
+                    const bool sv = valid && (lb - eta <= thr_s[gq]);
+                    mask |= (uint32_t)sv << gq;
+                    Stmp[gq * 256 + s] = sh;
+                }
+                if (tid == 0) {
+                    my_bytes += (unsigned long long)cnt * (w0 * 4 + (g.L > 1 ? 4 : 0) + 4);
+                    if (Lc > 0) my_lv[0] += (unsigned long long)cnt * ng;
+                }
+            } else {
+                // ---- brute force: every level dense, distances accumulated per
+                // (query, candidate) in LDS.
+                for (int gq = 0; gq < ng; ++gq) Stmp[gq * 256 + s] = 0.f;
+                for (int lv = 0; lv < g.L; ++lv) {
+                    const int w = g.wp[lv];
+                    const float *xs = blk + (int64_t)g.B * g.mp[lv] + (int64_t)s * w;
+                    for (int c0 = 0; c0 < w; c0 += 64) {
+                        float4 xr[16];
+#pragma unroll
+                        for (int c4 = 0; c4 < 16; ++c4) {
+                            if (c0 + c4 * 4 < w && valid) xr[c4] = *reinterpret_cast<const float4 *>(xs + c0 + c4 * 4);
+                            else xr[c4] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        }
+                        for (int gq = 0; gq < ng; ++gq) {
+                            const int qq = __builtin_amdgcn_readfirstlane(qid_s[gq]);
+                            const float *qy = qv.qy + (int64_t)qq * g.d_pad + g.mp[lv] + c0;
+                            float sh = 0.f;
+#pragma unroll
+                            for (int c4 = 0; c4 < 16; ++c4) {
+                                if (c0 + c4 * 4 < w) {
+                                    float4 q4 = *reinterpret_cast<const float4 *>(qy + c4 * 4);
+                                    float t0 = q4.x - xr[c4].x, t1 = q4.y - xr[c4].y;
+                                    float t2 = q4.z - xr[c4].z, t3 = q4.w - xr[c4].w;
+                                    sh = __builtin_fmaf(t0, t0, sh);
+                                    sh = __builtin_fmaf(t1, t1, sh);
+                                    sh = __builtin_fmaf(t2, t2, sh);
+                                    sh = __builtin_fmaf(t3, t3, sh);
+                                }
+                            }
+                            Stmp[gq * 256 + s] += sh;
+                        }
+                    }
+                }
+                for (int gq = 0; gq < ng; ++gq) {
+                    const float dd = Stmp[gq * 256 + s];
+                    const bool sv = valid && (dd * (1.f - c.mg.c_final) <= thr_s[gq]);
+                    mask |= (uint32_t)sv << gq;
+                }
+                if (tid == 0) {
+                    my_bytes += (unsigned long long)cnt * (g.d_pad * 4 + 4);
+                    for (int lv = 0; lv < Lc; ++lv) my_lv[lv] += (unsigned long long)cnt * ng;
+                }
+            }
+            // ---- consolidate the (query, candidate) survivors of level 1
+            {
+                int tot;
+                int off = block_exclusive_scan(__popc(mask), wave_tmp, &tot);
+                uint32_t mm = mask;
+                while (mm) {
+                    int gq = __ffs(mm) - 1;
+                    mm &= mm - 1;
+                    pr[off] = ((uint32_t)gq << 8) | (uint32_t)s;
+                    pS[off] = Stmp[gq * 256 + s];
+                    ++off;
+                }
+                if (tid == 0) npairs_s = tot;
+                __syncthreads();
+            }
+            // ---- later levels: only the surviving pairs, gathered by teams of
+            // lanes (one contiguous level slice per pair)
+            if (PRUNE) {
+                for (int lv = 1; lv < g.L; ++lv) {
+                    const int np_ = npairs_s;
+                    if (np_ == 0) break;
+                    const int w = g.wp[lv];
+                    const int w4 = w >> 2;
+                    int TL = 1;
+                    while (TL < w4 && TL < 16) TL <<= 1;
+                    const int nteams = NT / TL;
+                    const int tm = tid / TL, tlane = tid % TL;
+                    const bool last = (lv + 1 == g.L);
+                    const float ce = c.mg.c_level[lv + 1];
+                    for (int p0 = 0; p0 < np_; p0 += nteams) {
+                        const int p = p0 + tm;
+                        const bool act = p < np_;
+                        const uint32_t pv = act ? pr[p] : 0u;
+                        const int gq = (int)(pv >> 8), ss = (int)(pv & 255u);
+                        const int qq = qid_s[gq];
+                        float part = 0.f;
+                        if (act) {
+                            const float *x = blk + (int64_t)g.B * g.mp[lv] + (int64_t)ss * w;
+                            const float *qy = qv.qy + (int64_t)qq * g.d_pad + g.mp[lv];
+                            for (int c4 = tlane; c4 < w4; c4 += TL) {
+                                float4 x4 = *reinterpret_cast<const float4 *>(x + c4 * 4);
+                                float4 q4 = *reinterpret_cast<const float4 *>(qy + c4 * 4);
+                                float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                                part = __builtin_fmaf(t0, t0, part);
+                                part = __builtin_fmaf(t1, t1, part);
+                                part = __builtin_fmaf(t2, t2, part);
+                                part = __builtin_fmaf(t3, t3, part);
+                            }
+                        }
+                        for (int o = TL >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+                        if (act && tlane == 0) {
+                            const float sh = pS[p] + part;
+                            float a = 0.f, b = 0.f;
+                            if (!last) {
+                                a = qv.qtail[(int64_t)qq * g.L + lv + 1];
+                                b = tl[(int64_t)(lv + 1) * g.B + ss];
+                            }
+                            const float dt = a - b;
+                            const float lb = sh + dt * dt + c.one_m_eps2 * a * b;
+                            const float eta = ce * sh + c.mg.c_tail * (a + b) * (a + b);
+                            keep[p] = (lb - eta <= thr_s[gq]) ? 1 : 0;
+                            pS[p] = sh;
+                        }
+                    }
+                    if (tid == 0) {
+                        my_bytes += (unsigned long long)np_ * (w * 4 + (last ? 0 : 4));
+                        if (lv < 64) my_lv[lv] += (unsigned long long)np_;
+                    }
+                    __syncthreads();
+                    // in-place stable compaction of the kept pairs
+                    int kept = 0;
+                    for (int base = 0; base < np_; base += NT) {
+                        const int i = base + tid;
+                        const bool f = i < np_ && keep[i];
+                        const uint32_t pv = f ? pr[i] : 0u;
+                        const float sv = f ? pS[i] : 0.f;
+                        int tot;
+                        int off = block_exclusive_scan(f ? 1 : 0, wave_tmp, &tot);
+                        if (f) {
+                            pr[kept + off] = pv;
+                            pS[kept + off] = sv;
+                        }
+                        kept += tot;
+                        __syncthreads();
+                    }
+                    if (tid == 0) npairs_s = kept;
+                    __syncthreads();
+                }
+            }
+            // ---- commit: merge each query's survivors into its local top-kc
+            const int np_ = npairs_s;
+            if (np_ > 0) {
+                for (int i = tid; i < np_; i += NT) atomicAdd(&ncand[pr[i] >> 8], 1);
+                __syncthreads();
+                volatile uint64_t *SB = &sbuf[wv][0];
+                for (int gq = wv; gq < ng; gq += NT / 64) {
+                    if (ncand[gq] == 0) continue;
+                    const int cntk = tcnt[gq];
+                    uint64_t *tk = &topk[gq * c.kc];
+                    for (int i = lane; i < cntk; i += 64) SB[i] = tk[i];
+                    int napp = 0;
+                    for (int base = 0; base < np_; base += 64) {
+                        const int i = base + lane;
+                        bool f = false;
+                        uint64_t key = 0;
+                        if (i < np_) {
+                            const uint32_t pv = pr[i];
+                            if ((int)(pv >> 8) == gq) {
+                                f = true;
+                                key = make_key(pS[i], ix.ids[gb * g.B + (pv & 255u)]);
+                            }
+                        }
+                        const uint64_t bal = __ballot(f);
+                        const int rk = __popcll(bal & ((1ull << lane) - 1ull));
+                        if (f) SB[cntk + napp + rk] = key;
+                        napp += __popcll(bal);
+                    }
+                    const int tot = cntk + napp;
+                    const int n2 = next_pow2(tot);
+                    for (int i = tot + lane; i < n2; i += 64) SB[i] = KEY_MAX;
+                    __builtin_amdgcn_wave_barrier();
+                    wave_bitonic_sort(SB, n2, lane);
+                    const int keepn = min(c.kc, tot);
+                    for (int i = lane; i < keepn; i += 64) tk[i] = SB[i];
+                    float tnew = thr_s[gq];
+                    if (keepn >= c.k) tnew = fminf(tnew, prune_threshold(key_dist(SB[c.k - 1]), E_s[gq], c.mg));
+                    bool ovf = false;
+                    for (int i = c.kc + lane; i < tot; i += 64)
+                        if (key_dist(SB[i]) * (1.f - c.mg.c_final) <= tnew) ovf = true;
+                    const bool anyovf = __ballot(ovf) != 0ull;
+                    if (lane == 0) {
+                        tcnt[gq] = keepn;
+                        thr_s[gq] = tnew;
+                        if (tnew < INFINITY) atomic_min_nonneg(&wk.thr[qid_s[gq]], tnew);
+                        if (anyovf) atomicOr(&wk.flags[qid_s[gq]], FLAG_OVERFLOW);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            __syncthreads();
+        }
+        // ---- item end: publish each query's local top-kc entries that can
+        // still reach its final band
+        for (int gq = wv; gq < ng; gq += NT / 64) {
+            const int qq = qid_s[gq];
+            const float t = fminf(thr_s[gq], __hip_atomic_load(&wk.thr[qq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            const int cntk = tcnt[gq];
+            int nout = 0;
+            for (int base = 0; base < cntk; base += 64) {
+                const int i = base + lane;
+                const bool f = i < cntk && key_dist(topk[gq * c.kc + i]) * (1.f - c.mg.c_final) <= t;
+                nout += __popcll(__ballot(f));
+            }
+            int basepos = 0;
+            if (lane == 0 && nout > 0) basepos = atomicAdd(&wk.buf_cnt[qq], nout);
+            basepos = __shfl(basepos, 0, 64);
+            int w = 0;
+            for (int base = 0; base < cntk; base += 64) {
+                const int i = base + lane;
+                const uint64_t key = i < cntk ? topk[gq * c.kc + i] : KEY_MAX;
+                const bool f = i < cntk && key_dist(key) * (1.f - c.mg.c_final) <= t;
+                const uint64_t bal = __ballot(f);
+                const int rk = __popcll(bal & ((1ull << lane) - 1ull));
+                if (f) {
+                    const int dst = basepos + w + rk;
+                    if (dst < c.capq) wk.buf[(int64_t)qq * c.capq + dst] = key;
+                    else atomicOr(&wk.flags[qq], FLAG_OVERFLOW);
+                }
+                w += __popcll(bal);
+            }
+        }
+        __syncthreads();
+    }
+    if (wk.stats && tid == 0) {
+        atomicAdd(&wk.stats[ST_ITEMS], my_items);
+        atomicAdd(&wk.stats[ST_BYTES], my_bytes);
+        for (int lv = 0; lv < Lc; ++lv)
+            if (my_lv[lv]) atomicAdd(&wk.stats[ST_LEVEL + lv], my_lv[lv]);
+    }
+}
+
+// ================================================================ merge
+// One workgroup per query: sort the committed entries, find the k-th best
+// computed distance, rescore every entry of the boundary band with the
+// canonical recipe and emit the first k by (D, id).
+__global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__restrict__ buf,
+                                              const int32_t *__restrict__ buf_cnt,
+                                              int32_t *__restrict__ flags, const float *__restrict__ qE,
+                                              const float *__restrict__ qraw, const float *__restrict__ raw,
+                                              int d, int64_t *__restrict__ out_ids, float *__restrict__ out_d,
+                                              unsigned long long *stats)
+{
+    extern __shared__ uint64_t K[];
+    __shared__ int nb_s;
+    const int64_t q = blockIdx.x;
+    const int n_all = buf_cnt[q];
+    if ((flags[q] & FLAG_OVERFLOW) || n_all > c.capq) {
+        if (threadIdx.x == 0) atomicOr(&flags[q], FLAG_OVERFLOW);
+        return;
+    }
+    const int n = n_all;
+    const int P = next_pow2(n > 0 ? n : 1);
+    for (int i = threadIdx.x; i < P; i += NT) K[i] = i < n ? buf[q * c.capq + i] : KEY_MAX;
+    __syncthreads();
+    block_bitonic_sort(K, P);
+    const float thr = n >= c.k ? prune_threshold(key_dist(K[c.k - 1]), qE[q], c.mg) : INFINITY;
+    if (threadIdx.x == 0) nb_s = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NT)
+        if (key_dist(K[i]) * (1.f - c.mg.c_final) <= thr) atomicMax(&nb_s, i + 1);
+    __syncthreads();
+    const int nb = nb_s;
+    if (nb > 4096) {
+        if (threadIdx.x == 0) atomicOr(&flags[q], FLAG_OVERFLOW);
+        return;
+    }
+    // canonical rescoring of the band (the band is a prefix of the sort)
+    for (int i = threadIdx.x; i < nb; i += NT) {
+        const int32_t id = key_id(K[i]);
+        K[i] = make_key(canon_dist(qraw + q * d, raw + (int64_t)id * d, d), id);
+    }
+    const int PB = next_pow2(nb > 0 ? nb : 1);
+    for (int i = nb + threadIdx.x; i < PB; i += NT) K[i] = KEY_MAX;
+    __syncthreads();
+    block_bitonic_sort(K, PB);
+    for (int r = threadIdx.x; r < c.k; r += NT) {
+        if (r < nb) {
+            out_ids[q * c.k + r] = key_id(K[r]);
+            out_d[q * c.k + r] = key_dist(K[r]);
+        } else {
+            out_ids[q * c.k + r] = -1;
+            out_d[q * c.k + r] = INFINITY;
+        }
+    }
+    if (stats && threadIdx.x == 0) {
+        atomicAdd(&stats[ST_COMMIT], (unsigned long long)n);
+        atomicAdd(&stats[3], (unsigned long long)nb);
+    }
+}
+
+// ================================================================ fallback
+// Exact answer for one query by brute force with the canonical recipe:
+// keys of every candidate of the probed lists, then k rounds of a
+// workgroup-wide minimum above the previous key.
+__global__ __launch_bounds__(NT) void k_fallback_keys(const float *__restrict__ q, int d,
+                                                      const int32_t *__restrict__ lists, int nl,
+                                                      const int64_t *__restrict__ list_blk, int B,
+                                                      const int32_t *__restrict__ ids,
+                                                      const int32_t *__restrict__ blk_cnt,
+                                                      const float *__restrict__ raw, int64_t total,
+                                                      uint64_t *__restrict__ keys)
+{
+    // grid-stride over the probed lists' blocks' slots
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = idx; t < total; t += stride) {
+        // locate (list, slot): lists are visited in order; total counts slots
+        int64_t rem = t;
+        int li = 0;
+        int64_t nslots = 0;
+        for (; li < nl; ++li) {
+            nslots = (list_blk[lists[li] + 1] - list_blk[lists[li]]) * B;
+            if (rem < nslots) break;
+            rem -= nslots;
+        }
+        const int64_t gb = list_blk[lists[li]] + rem / B;
+        const int s = (int)(rem % B);
+        if (s < blk_cnt[gb]) {
+            const int32_t id = ids[gb * B + s];
+            keys[t] = make_key(canon_dist(q, raw + (int64_t)id * d, d), id);
+        } else {
+            keys[t] = KEY_MAX;
+        }
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_fallback_select(const uint64_t *__restrict__ keys, int64_t total, int k,
+                                                        int64_t *__restrict__ out_ids, float *__restrict__ out_d)
+{
+    __shared__ unsigned long long best_s;
+    uint64_t prev = 0;
+    bool first = true;
+    for (int r = 0; r < k; ++r) {
+        if (threadIdx.x == 0) best_s = KEY_MAX;
+        __syncthreads();
+        uint64_t mine = KEY_MAX;
+        for (int64_t i = threadIdx.x; i < total; i += NT) {
+            uint64_t v = keys[i];
+            if ((first || v > prev) && v < mine) mine = v;
+        }
+        atomicMin(&best_s, (unsigned long long)mine);
+        __syncthreads();
+        const uint64_t b = best_s;
+        if (threadIdx.x == 0) {
+            if (b == KEY_MAX) {
+                out_ids[r] = -1;
+                out_d[r] = INFINITY;
+            } else {
+                out_ids[r] = key_id(b);
+                out_d[r] = key_dist(b);
+            }
+        }
+        prev = b;
+        first = false;
+        __syncthreads();
+    }
+}
+
+}  // namespace pano
+
+// ================================================================ host side
+namespace pano {
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Carves consecutive sub-buffers out of one device allocation.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <class T> T *take(size_t count)
+    {
+        T *p = reinterpret_cast<T *>(base + off);
+        off += align_up(sizeof(T) * std::max<size_t>(count, 1));
+        return p;
+    }
+};
+
+void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t *nprobe_dev, int nprobe_all,
+                float eps, int64_t *ids, float *dists, const pano_search_params *prm, uint32_t flags, bool brute,
+                hipStream_t s)
+{
+    pano_ctx *ctx = ix->ctx;
+    PANO_HIP(hipSetDevice(ctx->device));
+    PANO_REQUIRE(k <= 128, "k up to 128 is supported");
+    const int d = ix->d, L = ix->L, nlist = ix->nlist;
+    SearchConsts c{};
+    c.k = k;
+    c.kc = next_pow2(std::max(2 * k, 16));
+    int G = 16;
+    while (G > 1 && G * c.kc > 1024) G >>= 1;
+    if (prm && prm->group > 0) G = std::min(prm->group, G);
+    c.G = G;
+    c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 16;
+    c.capq = std::min(4096, std::max(2048, 16 * c.kc));
+    c.nlist = nlist;
+    c.ceil8 = (nlist + 7) / 8;
+    c.prune = brute ? 0 : 1;
+    c.eps = eps;
+    c.one_m_eps2 = 2.f * (1.f - eps);
+    c.mg = ix->mg;
+    c.g = LevelGeom{};
+    c.g.L = L;
+    c.g.d = d;
+    c.g.d_pad = ix->d_pad;
+    c.g.B = ix->B;
+    for (int l = 0; l <= L; ++l) c.g.mp[l] = ix->mp[l];
+    for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
+    const int seed_pool = std::min(1024, (prm && prm->seed_pool > 0) ? prm->seed_pool : 512);
+    const int seed_cnt = std::min(256, std::max(k, (prm && prm->seed_count > 0) ? prm->seed_count : std::max(2 * k, 32)));
+    const int grid = (prm && prm->grid > 0) ? prm->grid : ctx->num_cu * 2;
+    const int np_max = nprobe_dev ? nlist : std::min(nprobe_all, nlist);
+    const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
+
+    // ---- scratch
+    size_t need0 = align_up(sizeof(float) * nq * ix->d_pad) + align_up(sizeof(float) * nq * L) +
+                   3 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
+    size_t need1 = nlist > 1 ? align_up(sizeof(float) * nq * nlist) : 256;
+    size_t need2 = align_up(sizeof(int32_t) * nq * np_max) * 2 + align_up(sizeof(int32_t) * nq) +
+                   2 * align_up(sizeof(int32_t) * nlist) + align_up(sizeof(int32_t) * 8) +
+                   align_up(sizeof(int64_t) * (nlist + 1)) + align_up(sizeof(int64_t) * (8 * c.ceil8 + 1));
+    size_t need3 = 3 * align_up(sizeof(float) * nq) + align_up(sizeof(uint64_t) * nq * c.capq) +
+                   align_up(sizeof(unsigned long long) * 128);
+    ctx->scratch[0].ensure(need0);
+    ctx->scratch[1].ensure(need1);
+    ctx->scratch[2].ensure(need2);
+    ctx->scratch[3].ensure(need3);
+    Carver c0(ctx->scratch[0].p), c2(ctx->scratch[2].p), c3(ctx->scratch[3].p);
+    float *qy = c0.take<float>(nq * ix->d_pad);
+    float *qtail = c0.take<float>(nq * L);
+    float *qE = c0.take<float>(nq);
+    float *qn2 = c0.take<float>(nq);
+    float *spare = c0.take<float>(nq);
+    (void)spare;
+    double *vnorm = c0.take<double>(nq);
+    float *Sco = ctx->scratch[1].as<float>();
+    int32_t *probes = c2.take<int32_t>(nq * np_max);
+    int32_t *list_q = c2.take<int32_t>(nq * np_max);
+    int32_t *npq = c2.take<int32_t>(nq);
+    int32_t *list_cnt = c2.take<int32_t>(nlist);
+    int32_t *list_fill = c2.take<int32_t>(nlist);
+    int32_t *heads = c2.take<int32_t>(8);
+    int64_t *list_qoff = c2.take<int64_t>(nlist + 1);
+    int64_t *item_off = c2.take<int64_t>(8 * c.ceil8 + 1);
+    float *thr = c3.take<float>(nq);
+    int32_t *buf_cnt = c3.take<int32_t>(nq);
+    int32_t *qflags = c3.take<int32_t>(nq);
+    uint64_t *buf = c3.take<uint64_t>(nq * c.capq);
+    unsigned long long *stats = c3.take<unsigned long long>(128);
+
+    hipEvent_t ev[5];
+    if (want_stats) {
+        for (auto &e : ev) PANO_HIP(hipEventCreate(&e));
+        PANO_HIP(hipEventRecord(ev[0], s));
+        PANO_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 128, s));
+    }
+    // ---- query transform, tails and error bound
+    PANO_HIP(hipMemsetAsync(qy, 0, sizeof(float) * nq * ix->d_pad, s));
+    launch_transform(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy, ix->d_pad, s);
+    launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, s);
+    hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, vnorm, nq, ix->mg.kappa,
+                       ix->mg.e_max, qE);
+    // ---- coarse probing
+    if (nlist > 1) {
+        launch_gemm_nt(q, nq, d, ix->cent.as<float>(), nlist, Sco, s);
+        launch_sqnorms(q, nq, d, qn2, s);
+        const double u = std::ldexp(1.0, -24);
+        auto gam = [&](double nn) { return nn * u / (1.0 - nn * u); };
+        const float c_co = (float)((gam(d / 64.0 + 8) + gam(32.0 + (d + 31) / 32 + 2) + 4 * u) * 1.1);
+        const int P = next_pow2(nlist);
+        size_t shm = sizeof(uint64_t) * P + 3 * sizeof(float) * nlist;
+        PANO_HIP(hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        hipLaunchKernelGGL(k_coarse, dim3((unsigned)nq), dim3(NT), shm, s, Sco, qn2, ix->cent.as<float>() + (size_t)nlist * d,
+                           q, ix->cent.as<float>(), d, nlist, nprobe_dev, nprobe_all, c_co, np_max, probes, npq);
+    } else {
+        hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, np_max, probes, npq);
+    }
+    PANO_HIP(hipGetLastError());
+    // ---- work decomposition
+    PANO_HIP(hipMemsetAsync(list_cnt, 0, sizeof(int32_t) * nlist, s));
+    PANO_HIP(hipMemsetAsync(list_fill, 0, sizeof(int32_t) * nlist, s));
+    PANO_HIP(hipMemsetAsync(heads, 0, sizeof(int32_t) * 8, s));
+    hipLaunchKernelGGL(k_wl_count, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, np_max, probes, npq, list_cnt);
+    hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, s, nlist, c.ceil8, c.G, c.bpi, list_cnt,
+                       ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
+    hipLaunchKernelGGL(k_wl_fill, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, np_max, probes, npq, list_qoff,
+                       list_fill, list_q);
+    PANO_HIP(hipMemsetD32Async((hipDeviceptr_t)thr, 0x7f800000, nq, s));
+    PANO_HIP(hipMemsetAsync(buf_cnt, 0, sizeof(int32_t) * nq, s));
+    PANO_HIP(hipMemsetAsync(qflags, 0, sizeof(int32_t) * nq, s));
+    PANO_HIP(hipGetLastError());
+
+    IndexView iv{ix->levels.as<float>(), ix->tails.as<float>(), ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
+                 ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
+    QueryView qv{qy, qtail, qE, q};
+    if (!brute) {
+        hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, s, c, iv, qv, probes, np_max,
+                           ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
+        PANO_HIP(hipGetLastError());
+    }
+    if (want_stats) PANO_HIP(hipEventRecord(ev[1], s));
+    WorkView wk{list_cnt, list_qoff, list_q, item_off, heads, thr, buf, buf_cnt, qflags, want_stats ? stats : nullptr};
+    if (brute)
+        hipLaunchKernelGGL(k_scan<false>, dim3(grid), dim3(NT), 0, s, c, iv, qv, wk);
+    else
+        hipLaunchKernelGGL(k_scan<true>, dim3(grid), dim3(NT), 0, s, c, iv, qv, wk);
+    PANO_HIP(hipGetLastError());
+    if (want_stats) PANO_HIP(hipEventRecord(ev[2], s));
+    {
+        const int P = next_pow2(c.capq);
+        size_t shm = sizeof(uint64_t) * P;
+        PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        hipLaunchKernelGGL(k_merge, dim3((unsigned)nq), dim3(NT), shm, s, c, buf, buf_cnt, qflags, qE, q,
+                           ix->raw.as<float>(), d, ids, dists, want_stats ? stats : nullptr);
+        PANO_HIP(hipGetLastError());
+    }
+    if (want_stats) PANO_HIP(hipEventRecord(ev[3], s));
+    // ---- exact fallback for queries whose bounded buffers overflowed
+    std::vector<int32_t> hflags(nq);
+    PANO_HIP(hipMemcpyAsync(hflags.data(), qflags, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, s));
+    PANO_HIP(hipStreamSynchronize(s));
+    int64_t nfall = 0;
+    for (int64_t qi = 0; qi < nq; ++qi) {
+        if (!(hflags[qi] & FLAG_OVERFLOW)) continue;
+        ++nfall;
+        std::vector<int32_t> pr(np_max);
+        int32_t npv = 0;
+        PANO_HIP(hipMemcpyAsync(pr.data(), probes + qi * np_max, sizeof(int32_t) * np_max, hipMemcpyDeviceToHost, s));
+        PANO_HIP(hipMemcpyAsync(&npv, npq + qi, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PANO_HIP(hipStreamSynchronize(s));
+        int64_t total = 0;
+        for (int r = 0; r < npv; ++r) total += (ix->list_blk[pr[r] + 1] - ix->list_blk[pr[r]]) * ix->B;
+        ctx->scratch[4].ensure(align_up(sizeof(int32_t) * std::max(1, npv)) + align_up(sizeof(uint64_t) * std::max<int64_t>(1, total)));
+        Carver c4(ctx->scratch[4].p);
+        int32_t *lists_d = c4.take<int32_t>(std::max(1, npv));
+        uint64_t *keys = c4.take<uint64_t>(std::max<int64_t>(1, total));
+        PANO_HIP(hipMemcpyAsync(lists_d, pr.data(), sizeof(int32_t) * npv, hipMemcpyHostToDevice, s));
+        unsigned gr = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (total + NT - 1) / NT));
+        hipLaunchKernelGGL(k_fallback_keys, dim3(gr), dim3(NT), 0, s, q + qi * d, d, lists_d, npv,
+                           ix->list_blk_d.as<int64_t>(), ix->B, ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
+                           ix->raw.as<float>(), total, keys);
+        hipLaunchKernelGGL(k_fallback_select, dim3(1), dim3(NT), 0, s, keys, total, k, ids + qi * k, dists + qi * k);
+        PANO_HIP(hipGetLastError());
+        PANO_HIP(hipStreamSynchronize(s));
+    }
+    if (want_stats) {
+        PANO_HIP(hipEventRecord(ev[4], s));
+        PANO_HIP(hipEventSynchronize(ev[4]));
+        std::vector<unsigned long long> hs(128);
+        PANO_HIP(hipMemcpy(hs.data(), stats, sizeof(unsigned long long) * 128, hipMemcpyDeviceToHost));
+        pano_stats_t &st = ix->stats;
+        std::memset(&st, 0, sizeof(st));
+        st.nq = nq;
+        st.items = (int64_t)hs[ST_ITEMS];
+        st.committed = (int64_t)hs[ST_COMMIT];
+        st.band = (int64_t)hs[3];
+        st.scan_bytes = (int64_t)hs[ST_BYTES];
+        st.fallback_queries = nfall;
+        int64_t dims = 0;
+        for (int l = 0; l < L && l < 64; ++l) {
+            st.level_reads[l] = (int64_t)hs[ST_LEVEL + l];
+            dims += st.level_reads[l] * (int64_t)(ix->m[l + 1] - ix->m[l]);
+        }
+        st.candidates = st.level_reads[0];
+        st.dims_read = dims;
+        float t;
+        PANO_HIP(hipEventElapsedTime(&t, ev[0], ev[4]));
+        st.ms_total = t;
+        PANO_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+        st.ms_prep = t;
+        PANO_HIP(hipEventElapsedTime(&t, ev[1], ev[2]));
+        st.ms_scan = t;
+        PANO_HIP(hipEventElapsedTime(&t, ev[2], ev[3]));
+        st.ms_merge = t;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+}
+
+}  // namespace pano

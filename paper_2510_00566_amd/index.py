@@ -1,0 +1,204 @@
+"""Python front end over the C ABI.  PyTorch only supplies device memory and
+the current HIP stream; all computation happens in libpanorama.so."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        L.check(L.lib().pano_ctx_create(device, C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            L.lib().pano_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Transform:
+    def __init__(self, h, d):
+        self.h = h
+        self.d = d
+
+    @classmethod
+    def fit(cls, x: np.ndarray, fit_sample: int = 0, seed: int = 0) -> "Transform":
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        h = C.c_void_p()
+        L.check(L.lib().pano_build_transform(_np_ptr(x), x.shape[0], x.shape[1], int(fit_sample), int(seed),
+                                             C.byref(h)))
+        return cls(h, x.shape[1])
+
+    @classmethod
+    def identity(cls, d: int) -> "Transform":
+        h = C.c_void_p()
+        L.check(L.lib().pano_transform_identity(d, C.byref(h)))
+        return cls(h, d)
+
+    @classmethod
+    def from_matrix(cls, mu: np.ndarray, t: np.ndarray) -> "Transform":
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        h = C.c_void_p()
+        L.check(L.lib().pano_transform_from(mu.shape[0], _np_ptr(mu), _np_ptr(t), C.byref(h)))
+        return cls(h, mu.shape[0])
+
+    def get(self):
+        d = self.d
+        mu = np.empty(d)
+        t = np.empty((d, d))
+        lam = np.empty(d)
+        alpha = C.c_double()
+        dd = C.c_int32()
+        L.check(L.lib().pano_transform_get(self.h, C.byref(dd), _np_ptr(mu), _np_ptr(t), _np_ptr(lam),
+                                           C.byref(alpha)))
+        return mu, t, lam, alpha.value
+
+    def __del__(self):
+        try:
+            if self.h:
+                L.lib().pano_transform_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def ivf_assign(ctx: Context, x_dev, nlist: int, iters: int = 10, seed: int = 0, stream=None):
+    import torch
+    n, d = x_dev.shape
+    cent = torch.empty((nlist, d), dtype=torch.float32, device=x_dev.device)
+    assign = torch.empty((n,), dtype=torch.int32, device=x_dev.device)
+    L.check(L.lib().pano_ivf_assign(ctx.h, _ptr(x_dev), n, d, nlist, iters, seed, _ptr(cent), _ptr(assign),
+                                    _stream_handle(stream)))
+    return cent, assign
+
+
+@dataclass
+class Params:
+    group: int = 0
+    blocks_per_item: int = 0
+    seed_pool: int = 0
+    seed_count: int = 0
+    grid: int = 0
+    use_bf16: int = 0
+
+    def c(self):
+        p = L.SearchParams()
+        p.group, p.blocks_per_item, p.seed_pool = self.group, self.blocks_per_item, self.seed_pool
+        p.seed_count, p.grid, p.use_bf16 = self.seed_count, self.grid, self.use_bf16
+        return p
+
+
+class Index:
+    def __init__(self, h, ctx: Context, d: int):
+        self.h = h
+        self.ctx = ctx
+        self.d = d
+
+    @classmethod
+    def build(cls, ctx: Context, tf: Transform, x_dev, centroids_dev, assign_dev, m, block: int = 256,
+              store: str = "f32", stream=None) -> "Index":
+        m = np.ascontiguousarray(m, dtype=np.int32)
+        n, d = x_dev.shape
+        h = C.c_void_p()
+        L.check(L.lib().pano_build_levels(ctx.h, tf.h, _ptr(x_dev), n, d, _ptr(centroids_dev), _ptr(assign_dev),
+                                          centroids_dev.shape[0], _np_ptr(m), m.size - 1, block,
+                                          L.PANO_BF16 if store == "bf16" else L.PANO_F32, C.byref(h),
+                                          _stream_handle(stream)))
+        return cls(h, ctx, d)
+
+    def _outs(self, q_dev, k):
+        import torch
+        nq = q_dev.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int64, device=q_dev.device)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=q_dev.device)
+        return ids, dists
+
+    def search(self, q_dev, k: int, nprobe=1, eps: float = 1.0, params: Params | None = None,
+               stats: bool = False, stream=None, out=None):
+        import torch
+        ids, dists = out if out is not None else self._outs(q_dev, k)
+        np_dev = None
+        np_all = 0
+        if isinstance(nprobe, torch.Tensor):
+            np_dev = nprobe
+        else:
+            np_all = int(nprobe)
+        prm = params.c() if params is not None else None
+        L.check(L.lib().pano_search(self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all, float(eps),
+                                    _ptr(ids), _ptr(dists), C.byref(prm) if prm is not None else None,
+                                    L.PANO_SEARCH_STATS if stats else 0, _stream_handle(stream)))
+        return ids, dists
+
+    def search_bruteforce(self, q_dev, k: int, nprobe=1, params: Params | None = None, stats: bool = False,
+                          stream=None, out=None):
+        import torch
+        ids, dists = out if out is not None else self._outs(q_dev, k)
+        np_dev = None
+        np_all = 0
+        if isinstance(nprobe, torch.Tensor):
+            np_dev = nprobe
+        else:
+            np_all = int(nprobe)
+        prm = params.c() if params is not None else None
+        L.check(L.lib().pano_search_bruteforce(self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all,
+                                               _ptr(ids), _ptr(dists), C.byref(prm) if prm is not None else None,
+                                               L.PANO_SEARCH_STATS if stats else 0, _stream_handle(stream)))
+        return ids, dists
+
+    def info(self) -> dict:
+        inf = L.IndexInfo()
+        L.check(L.lib().pano_index_info(self.h, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def layout(self):
+        inf = self.info()
+        m = np.empty(inf["L"] + 1, dtype=np.int32)
+        ll = np.empty(inf["nlist"], dtype=np.int64)
+        L.check(L.lib().pano_index_layout(self.h, _np_ptr(m), _np_ptr(ll)))
+        return m, ll
+
+    def stats(self) -> dict:
+        st = L.Stats()
+        L.check(L.lib().pano_stats_get(self.h, C.byref(st)))
+        out = {f: getattr(st, f) for f, _ in st._fields_ if f != "level_reads"}
+        out["level_reads"] = list(st.level_reads)
+        return out
+
+    def free(self):
+        if self.h:
+            L.lib().pano_index_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
