@@ -209,6 +209,9 @@ typedef struct {
     double ms_merge;         /* device time of merge + rescoring */
     double ms_prep;          /* device time of transform, probe, work list, seed */
     int64_t scan_bytes;      /* bytes of level slices, tails and ids touched */
+    int64_t scan_cycles[6];  /* scan phases summed over workgroups (shader clock
+                                cycles of one lane): pull, level 1, later levels,
+                                commit, publish, spare */
 } pano_stats_t;
 
 pano_status pano_stats_get(const pano_index *idx, pano_stats_t *out);

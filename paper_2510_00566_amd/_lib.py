@@ -35,7 +35,7 @@ class Stats(C.Structure):
                 ("level_reads", C.c_int64 * 64), ("items", C.c_int64), ("committed", C.c_int64),
                 ("band", C.c_int64), ("fallback_queries", C.c_int64), ("ms_total", C.c_double),
                 ("ms_scan", C.c_double), ("ms_merge", C.c_double), ("ms_prep", C.c_double),
-                ("scan_bytes", C.c_int64)]
+                ("scan_bytes", C.c_int64), ("scan_cycles", C.c_int64 * 6)]
 
 
 class PanoError(RuntimeError):

@@ -229,11 +229,71 @@ pano_status pano_ivf_assign(pano_ctx *ctx, const float *x_dev, int64_t n, int32_
         PANO_REQUIRE(iters >= 0, "iters must be >= 0");
         PANO_HIP(hipSetDevice(ctx->device));
         hipStream_t s = (hipStream_t)stream;
-        // initial centroids: nlist distinct rows chosen with the seed
-        std::vector<int64_t> init = seeded_sample(n, nlist, seed);
-        for (int c = 0; c < nlist; ++c)
-            PANO_HIP(hipMemcpyAsync(centroids_dev + (int64_t)c * d, x_dev + init[c] * d, sizeof(float) * d,
-                                    hipMemcpyDeviceToDevice, s));
+        // initial centroids: k-means++ (D^2 sampling, Arthur & Vassilvitskii 2007)
+        // over a seeded sample of rows
+        {
+            const int64_t ns = std::min<int64_t>(n, std::max<int64_t>(65536, std::min<int64_t>(262144, 64LL * nlist)));
+            std::vector<int64_t> samp = seeded_sample(n, ns, seed ^ 0x5bd1e995ull);
+            DevMem rows_d, xs, mind;
+            rows_d.alloc(sizeof(int64_t) * ns);
+            xs.alloc(sizeof(float) * (size_t)ns * d);
+            mind.alloc(sizeof(float) * ns);
+            PANO_HIP(hipMemcpyAsync(rows_d.p, samp.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s));
+            launch_gather_rows(x_dev, rows_d.as<int64_t>(), ns, d, xs.as<float>(), s);
+            PANO_HIP(hipMemsetD32Async((hipDeviceptr_t)mind.p, 0x7f800000, ns, s));
+            uint64_t st = seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+            auto next_u01 = [&st]() {
+                uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+                z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+                z ^= z >> 31;
+                return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+            };
+            // greedy variant: each step draws several candidates by D^2 and keeps
+            // the one that lowers the potential most
+            const int ncand = std::min(16, 2 + (int)std::log((double)nlist));
+            DevMem cand_d, pot_d;
+            cand_d.alloc(sizeof(float) * (size_t)ncand * d);
+            pot_d.alloc(sizeof(double) * ncand);
+            std::vector<float> hm(ns);
+            std::vector<double> pot(ncand);
+            std::vector<int64_t> picks(ncand);
+            int64_t pick = (int64_t)(next_u01() * ns) % ns;
+            for (int c = 0; c < nlist; ++c) {
+                PANO_HIP(hipMemcpyAsync(centroids_dev + (int64_t)c * d, xs.as<float>() + pick * d, sizeof(float) * d,
+                                        hipMemcpyDeviceToDevice, s));
+                if (c + 1 == nlist) break;
+                launch_update_mind(xs.as<float>(), ns, d, centroids_dev + (int64_t)c * d, mind.as<float>(), s);
+                PANO_HIP(hipMemcpyAsync(hm.data(), mind.p, sizeof(float) * ns, hipMemcpyDeviceToHost, s));
+                PANO_HIP(hipStreamSynchronize(s));
+                std::vector<double> cum(ns);
+                double tot = 0.0;
+                for (int64_t i = 0; i < ns; ++i) {
+                    tot += (double)hm[i];
+                    cum[i] = tot;
+                }
+                if (!(tot > 0.0)) {
+                    pick = (int64_t)(next_u01() * ns) % ns;
+                    continue;
+                }
+                for (int t = 0; t < ncand; ++t) {
+                    double r = next_u01() * tot;
+                    int64_t i = std::upper_bound(cum.begin(), cum.end(), r) - cum.begin();
+                    picks[t] = std::min<int64_t>(i, ns - 1);
+                    PANO_HIP(hipMemcpyAsync(cand_d.as<float>() + (size_t)t * d, xs.as<float>() + picks[t] * d,
+                                            sizeof(float) * d, hipMemcpyDeviceToDevice, s));
+                }
+                PANO_HIP(hipMemsetAsync(pot_d.p, 0, sizeof(double) * ncand, s));
+                launch_cand_potential(xs.as<float>(), ns, d, cand_d.as<float>(), ncand, mind.as<float>(),
+                                      pot_d.as<double>(), s);
+                PANO_HIP(hipMemcpyAsync(pot.data(), pot_d.p, sizeof(double) * ncand, hipMemcpyDeviceToHost, s));
+                PANO_HIP(hipStreamSynchronize(s));
+                int best = 0;
+                for (int t = 1; t < ncand; ++t)
+                    if (pot[t] < pot[best]) best = t;
+                pick = picks[best];
+            }
+        }
         DevMem S, cn, perm_d, off_d;
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(1ll << 28) / std::max(1, nlist)));
         S.alloc(sizeof(float) * chunk * nlist);

@@ -141,6 +141,10 @@ void launch_argmin_rows(const float *S, int64_t n, int nb, const float *cnorm, i
 void launch_centroid_update(const float *X, int d, const int64_t *perm, const int64_t *off, int nlist,
                             float *cent, hipStream_t s);
 void launch_sqnorms(const float *X, int64_t n, int d, float *out, hipStream_t s);
+void launch_update_mind(const float *X, int64_t n, int d, const float *c, float *mind, hipStream_t s);
+void launch_cand_potential(const float *X, int64_t n, int d, const float *cand, int nc, const float *mind,
+                           double *pot, hipStream_t s);
+void launch_gather_rows(const float *X, const int64_t *rows, int64_t n, int d, float *out, hipStream_t s);
 void launch_pack(const float *Y, const float *tails_row, const int64_t *perm, const int64_t *list_start,
                  const int64_t *list_blk, const int32_t *block_list, int64_t nblocks, const LevelGeom &g,
                  float *levels, uint16_t *levels_bf16, float *tails, int32_t *ids, int32_t *blk_cnt,

@@ -4,15 +4,20 @@
 // (Section 6.5) and the level-major packing of Section 6.1.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace pano {
 
 // ---------------------------------------------------------------- tiled product
-// One workgroup computes a 64 x 64 output tile; each thread a 4 x 4 sub-tile.
-// The reduction dimension is consumed in chunks of 32: every chunk is summed
-// in a fresh register and then added to the running total, so the rounding
-// error of an output is at most gamma(32 + ceil(K/32) + 1) times the sum of
-// the absolute products (the bound the pruning margins are built on).
-constexpr int TM = 64, TN = 64, TK = 32;
+// Dense products Out = (A - mu) B^t on the matrix cores: one workgroup per
+// 64 x 64 output tile, each wavefront a 32 x 32 sub-tile made of four
+// v_mfma_f32_16x16x4f32 accumulators.  The reduction dimension is consumed in
+// chunks of 32: each chunk is summed in fresh accumulators and then added to
+// the running total, so every output carries a rounding error of at most
+// gamma(32 + ceil(K/32) + 1) times the sum of the absolute products (the
+// bound the pruning margins are built on).
+constexpr int TM = 32, TN = 64, TK = 32, TLD = 36;
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 template <bool SUB_MU>
 __global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, int64_t n, int K,
@@ -21,77 +26,92 @@ __global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, in
                                                  const int32_t *__restrict__ outcol,
                                                  float *__restrict__ Out, int ld_out)
 {
-    __shared__ float As[TK][TM + 4];
-    __shared__ float Bs[TK][TN + 4];
+    // two LDS stages: the next chunk is fetched into registers while the
+    // current one feeds the matrix cores
+    __shared__ float As[2][TM][TLD];
+    __shared__ float Bs[2][TN][TLD];
     const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
+    const int lane = tid & 63, w = tid >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int wr = (w >> 1) * 16, wc = (w & 1) * 32;
     const int64_t r0 = (int64_t)blockIdx.x * TM;
     const int c0 = blockIdx.y * TN;
-    float tot[4][4];
+    constexpr int NA = (TM * TK) / 256, NB = (TN * TK) / 256;
+    float ra[NA], rb[NB];
+    auto fetch = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) tot[i][j] = 0.f;
-
-    for (int k0 = 0; k0 < K; k0 += TK) {
-        // load A tile (TM rows x TK cols) and B tile (TN rows x TK cols)
-#pragma unroll
-        for (int t = 0; t < (TM * TK) / 256; ++t) {
-            int e = tid + t * 256;
-            int rr = e / TK, kk = e % TK;
-            int64_t r = r0 + rr;
-            int kx = k0 + kk;
+        for (int t = 0; t < NA; ++t) {
+            const int e = tid + t * 256;
+            const int rr = e / TK, kk = e % TK;
+            const int64_t r = r0 + rr;
+            const int kx = k0 + kk;
             float v = 0.f;
             if (r < n && kx < K) {
                 v = A[r * K + kx];
                 if (SUB_MU) v = v - mu[kx];
             }
-            As[kk][rr] = v;
+            ra[t] = v;
         }
 #pragma unroll
-        for (int t = 0; t < (TN * TK) / 256; ++t) {
-            int e = tid + t * 256;
-            int cc = e / TK, kk = e % TK;
-            int c = c0 + cc;
-            int kx = k0 + kk;
-            Bs[kk][cc] = (c < nb && kx < K) ? Bm[(int64_t)c * K + kx] : 0.f;
+        for (int t = 0; t < NB; ++t) {
+            const int e = tid + t * 256;
+            const int cc = e / TK, kk = e % TK;
+            const int c = c0 + cc;
+            const int kx = k0 + kk;
+            rb[t] = (c < nb && kx < K) ? Bm[(int64_t)c * K + kx] : 0.f;
         }
-        __syncthreads();
-        float acc[4][4];
+    };
+    auto stash = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
-#pragma unroll 8
-        for (int kk = 0; kk < TK; ++kk) {
-            float a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fmaf(a[i], b[j], acc[i][j]);
+        for (int t = 0; t < NA; ++t) {
+            const int e = tid + t * 256;
+            As[buf][e / TK][e % TK] = ra[t];
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int t = 0; t < NB; ++t) {
+            const int e = tid + t * 256;
+            Bs[buf][e / TK][e % TK] = rb[t];
+        }
+    };
+    floatx4_t tot[2];
+    tot[0] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    tot[1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    const int nchunks = (K + TK - 1) / TK;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunks) fetch((ch + 1) * TK);
+        floatx4_t acc[2];
+        acc[0] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        acc[1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) tot[i][j] += acc[i][j];
+        for (int ks = 0; ks < TK / 4; ++ks) {
+            const float a = As[buf][wr + r16][ks * 4 + kq];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const float b = Bs[buf][wc + j * 16 + r16][ks * 4 + kq];
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+            }
+        }
+        tot[0] += acc[0];
+        tot[1] += acc[1];
+        if (ch + 1 < nchunks) stash(buf ^ 1);
         __syncthreads();
     }
+    // lane holds rows 4*(lane/16) + v of column lane%16 of each 16 x 16 tile
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int64_t r = r0 + ty * 4 + i;
-        if (r >= n) continue;
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int c = c0 + tx * 4 + j;
-            if (c >= nb) continue;
-            int oc = outcol ? outcol[c] : c;
-            Out[r * ld_out + oc] = tot[i][j];
+        for (int v = 0; v < 4; ++v) {
+            const int64_t r = r0 + wr + 4 * kq + v;
+            const int c = c0 + wc + j * 16 + r16;
+            if (r < n && c < nb) {
+                const int oc = outcol ? outcol[c] : c;
+                Out[r * ld_out + oc] = tot[j][v];
+            }
         }
-    }
 }
 
 void launch_transform(const float *X, int64_t n, int d, const float *T, const float *mu,
@@ -241,6 +261,90 @@ void launch_centroid_update(const float *X, int d, const int64_t *perm, const in
                             float *cent, hipStream_t s)
 {
     hipLaunchKernelGGL(k_centroid_update, dim3(nlist), dim3(256), 0, s, X, d, perm, off, cent);
+    PANO_HIP(hipGetLastError());
+}
+
+// k-means++ seeding (D^2 sampling): keep, for every sampled row, the squared
+// distance to its nearest chosen centroid.
+__global__ __launch_bounds__(256) void k_update_mind(const float *__restrict__ X, int64_t n, int d,
+                                                     const float *__restrict__ c, float *__restrict__ mind)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    float e = 0.f;
+    for (int j = lane; j < d; j += 64) {
+        float t = X[r * d + j] - c[j];
+        e = __builtin_fmaf(t, t, e);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+    if (lane == 0) mind[r] = fminf(mind[r], e);
+}
+
+// Greedy k-means++: for each of nc candidate centres, the potential
+// sum_i min(mind_i, ||x_i - cand||^2) over the sampled rows.
+__global__ __launch_bounds__(256) void k_cand_potential(const float *__restrict__ X, int64_t n, int d,
+                                                        const float *__restrict__ cand, int nc,
+                                                        const float *__restrict__ mind, double *__restrict__ pot)
+{
+    constexpr int NCMAX = 16;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    double acc[NCMAX];
+#pragma unroll
+    for (int c = 0; c < NCMAX; ++c) acc[c] = 0.0;
+    for (int64_t r = wave; r < n; r += nwaves) {
+        const float m = mind[r];
+#pragma unroll
+        for (int c = 0; c < NCMAX; ++c) {
+            if (c >= nc) break;
+            float e = 0.f;
+            for (int j = lane; j < d; j += 64) {
+                float t = X[r * d + j] - cand[(int64_t)c * d + j];
+                e = __builtin_fmaf(t, t, e);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+            acc[c] += (double)fminf(m, e);
+        }
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < NCMAX; ++c)
+            if (c < nc) atomicAdd(&pot[c], acc[c]);
+}
+
+void launch_cand_potential(const float *X, int64_t n, int d, const float *cand, int nc, const float *mind,
+                           double *pot, hipStream_t s)
+{
+    if (n == 0) return;
+    unsigned grid = (unsigned)std::min<int64_t>(1024, (n + 3) / 4);
+    hipLaunchKernelGGL(k_cand_potential, dim3(grid), dim3(256), 0, s, X, n, d, cand, std::min(nc, 16), mind, pot);
+    PANO_HIP(hipGetLastError());
+}
+
+void launch_update_mind(const float *X, int64_t n, int d, const float *c, float *mind, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_update_mind, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d, c, mind);
+    PANO_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void k_gather_rows(const float *__restrict__ X, const int64_t *__restrict__ rows,
+                                                     int64_t n, int d, float *__restrict__ out)
+{
+    const int64_t r = blockIdx.x;
+    if (r >= n) return;
+    const int64_t src = rows[r];
+    for (int j = threadIdx.x; j < d; j += blockDim.x) out[r * d + j] = X[src * d + j];
+}
+
+void launch_gather_rows(const float *X, const int64_t *rows, int64_t n, int d, float *out, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)n), dim3(256), 0, s, X, rows, n, d, out);
     PANO_HIP(hipGetLastError());
 }
 

@@ -20,93 +20,120 @@ __global__ void k_query_consts(const double *__restrict__ vnorm, int64_t nq, flo
 }
 
 // ================================================================ coarse probing
-// One workgroup per query.  Approximate distances to every centroid come from
-// the dense product S = q . c (chunked FP32), with a certified absolute error
-// bound c_co (||q||^2 + ||c||^2).  A list is certainly in the probe set if its
-// upper bound is below the (p+1)-th smallest lower bound; the uncertain lists
-// of the band are rescored with the canonical recipe and ordered by (D, l).
+// One wavefront per query.  Approximate distances to every centroid come from
+// the dense product S = q . c (chunked FP32 on the matrix cores), with a
+// certified absolute error bound c_co (||q||^2 + ||c||^2).  A list is
+// certainly in the probe set if its upper bound is below the (p+1)-th smallest
+// lower bound; the uncertain lists of the band are rescored with the canonical
+// recipe and ordered by (D, l).
+__host__ __device__ inline size_t coarse_lds_per_wave(int nlist, int d)
+{
+    return (((size_t)nlist * 20 + (size_t)d * 4 + 1024 + 64) + 15) & ~(size_t)15;
+}
+
 __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, const float *__restrict__ qn2,
                                                const float *__restrict__ cn2, const float *__restrict__ q,
-                                               const float *__restrict__ cent, int d, int nlist,
+                                               const float *__restrict__ cent, int d, int nlist, int64_t nq,
                                                const int32_t *__restrict__ nprobe_dev, int nprobe_all,
                                                float c_co, int np_max, int32_t *__restrict__ probes,
                                                int32_t *__restrict__ np_out)
 {
-    extern __shared__ uint64_t sm[];
-    uint64_t *K = sm;                               // [P]
-    float *LO = reinterpret_cast<float *>(K + next_pow2(nlist));  // [nlist]
-    float *UP = LO + nlist;                         // [nlist]
-    __shared__ int wave_tmp[NT / 64];
-    __shared__ float Up_s, Lp1_s;
-    __shared__ int ncert_s, nunc_s;
-    const int64_t qi = blockIdx.x;
-    const int P = next_pow2(nlist);
+    extern __shared__ char smc[];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int64_t qi = (int64_t)blockIdx.x * wpb + w;
+    if (qi >= nq) return;
+    const size_t pw = coarse_lds_per_wave(nlist, d);
+    char *base = smc + pw * w;
+    uint64_t *keys = reinterpret_cast<uint64_t *>(base);            // [nlist]
+    float *LO = reinterpret_cast<float *>(keys + nlist);             // [nlist]
+    float *UP = LO + nlist;                                          // [nlist]
+    int32_t *lst = reinterpret_cast<int32_t *>(UP + nlist);          // [nlist]
+    float *qrow = reinterpret_cast<float *>(lst + nlist);            // [d]
+    int *hist = reinterpret_cast<int *>(qrow + d);                   // [256]
     int p = nprobe_dev ? nprobe_dev[qi] : nprobe_all;
     p = p < 1 ? 1 : (p > nlist ? nlist : p);
     if (p > np_max) p = np_max;
-    const float u2 = 1.0f + 1.2e-7f;  // (1 + u') for the FP32 rounding of D
     const float qq = qn2[qi];
-    for (int l = threadIdx.x; l < P; l += NT) {
-        if (l < nlist) {
-            float a = qq + cn2[l] - 2.f * S[qi * nlist + l];
-            float del = c_co * (qq + cn2[l]);
-            float lo = fmaxf(a - del, 0.f) * (1.0f - 1.2e-7f);
-            float up = (a + del) * u2;
-            LO[l] = lo;
-            UP[l] = up;
-            K[l] = make_key(up, l);
-        } else {
-            K[l] = KEY_MAX;
-        }
+    for (int j = lane; j < d; j += 64) qrow[j] = q[qi * d + j];
+    for (int l = lane; l < nlist; l += 64) {
+        const float a = qq + cn2[l] - 2.f * S[qi * nlist + l];
+        const float del = c_co * (qq + cn2[l]);
+        LO[l] = fmaxf(a - del, 0.f) * (1.0f - 1.2e-7f);
+        UP[l] = fmaxf(a + del, 0.f) * (1.0f + 1.2e-7f);
     }
-    __syncthreads();
-    block_bitonic_sort(K, P);
-    if (threadIdx.x == 0) Up_s = key_dist(K[p - 1]);
-    __syncthreads();
-    for (int l = threadIdx.x; l < P; l += NT) K[l] = l < nlist ? make_key(LO[l], l) : KEY_MAX;
-    __syncthreads();
-    block_bitonic_sort(K, P);
-    if (threadIdx.x == 0) Lp1_s = p < nlist ? key_dist(K[p]) : INFINITY;
-    __syncthreads();
-    const float Up = Up_s, Lp1 = Lp1_s;
-    // Walk the lists in ascending lower-bound order: certain ones go straight to
-    // the output, uncertain band members to a rescoring list (kept in LO's
-    // storage, which is no longer needed once copied).
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const float Up = wave_select_nonneg(UP, nlist, p, hist, lane);
+    const float Lp1 = p < nlist ? wave_select_nonneg(LO, nlist, p + 1, hist, lane) : INFINITY;
+    // certain lists go to the output; uncertain band members are collected
     int ncert = 0, nunc = 0;
-    int32_t *ulist = reinterpret_cast<int32_t *>(UP + nlist);  // [nlist]
-    for (int base = 0; base < nlist; base += NT) {
-        int r = base + threadIdx.x;
-        int l = r < nlist ? key_id(K[r]) : 0;
-        bool inb = r < nlist && LO[l] <= Up;
-        bool cert = inb && UP[l] < Lp1;
-        bool unc = inb && !cert;
-        int tc, tu;
-        int oc = block_exclusive_scan(cert ? 1 : 0, wave_tmp, &tc);
-        int ou = block_exclusive_scan(unc ? 1 : 0, wave_tmp, &tu);
-        if (cert && ncert + oc < p) probes[qi * np_max + ncert + oc] = l;
-        if (unc) ulist[nunc + ou] = l;
-        ncert += tc;
-        nunc += tu;
-        __syncthreads();
+    for (int b0 = 0; b0 < nlist; b0 += 64) {
+        const int l = b0 + lane;
+        const bool inb = l < nlist && LO[l] <= Up;
+        const bool cert = inb && UP[l] < Lp1;
+        const bool unc = inb && !cert;
+        const uint64_t bc = __ballot(cert), bu = __ballot(unc);
+        const uint64_t below = (1ull << lane) - 1ull;
+        if (cert) {
+            const int pos = ncert + __popcll(bc & below);
+            if (pos < p) probes[qi * np_max + pos] = l;
+        }
+        if (unc) lst[nunc + __popcll(bu & below)] = l;
+        ncert += __popcll(bc);
+        nunc += __popcll(bu);
     }
-    if (ncert > p) ncert = p;  // cannot happen: certain lists number at most p
+    if (ncert > p) ncert = p;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const int need = p - ncert;
     if (need > 0) {
         const int PU = next_pow2(nunc);
-        for (int i = threadIdx.x; i < PU; i += NT) {
+        for (int i = lane; i < PU; i += 64) {
             if (i < nunc) {
-                int l = ulist[i];
-                K[i] = make_key(canon_dist(q + qi * d, cent + (int64_t)l * d, d), l);
+                const int l = lst[i];
+                keys[i] = make_key(canon_dist_stream(qrow, cent + (int64_t)l * d, d), l);
             } else {
-                K[i] = KEY_MAX;
+                keys[i] = KEY_MAX;
             }
         }
-        __syncthreads();
-        block_bitonic_sort(K, PU);
-        for (int i = threadIdx.x; i < need; i += NT) probes[qi * np_max + ncert + i] = key_id(K[i]);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        wave_bitonic_sort(keys, PU, lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int i = lane; i < need; i += 64) probes[qi * np_max + ncert + i] = key_id(keys[i]);
     }
-    for (int i = p + threadIdx.x; i < np_max; i += NT) probes[qi * np_max + i] = -1;
-    if (threadIdx.x == 0) np_out[qi] = p;
+    // rank 0 = the probed list with the smallest approximate distance (the
+    // seeding step draws its first candidates from it)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    float bestv = INFINITY;
+    int bestpos = 0x7fffffff, bestl = 0x7fffffff;
+    for (int i = lane; i < p; i += 64) {
+        const int l = probes[qi * np_max + i];
+        const float v = 0.5f * (LO[l] + UP[l]);
+        if (v < bestv || (v == bestv && l < bestl)) {
+            bestv = v;
+            bestl = l;
+            bestpos = i;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float ov = __shfl_xor(bestv, o, 64);
+        const int ol = __shfl_xor(bestl, o, 64), op = __shfl_xor(bestpos, o, 64);
+        if (ov < bestv || (ov == bestv && ol < bestl)) {
+            bestv = ov;
+            bestl = ol;
+            bestpos = op;
+        }
+    }
+    if (lane == 0 && bestpos != 0 && bestpos < p) {
+        const int first = probes[qi * np_max];
+        probes[qi * np_max] = bestl;
+        probes[qi * np_max + bestpos] = first;
+    }
+    for (int i = p + lane; i < np_max; i += 64) probes[qi * np_max + i] = -1;
+    if (lane == 0) np_out[qi] = p;
 }
 
 __global__ void k_single_list(int64_t nq, int np_max, int32_t *__restrict__ probes, int32_t *__restrict__ np_out)
@@ -122,9 +149,11 @@ __global__ void k_single_list(int64_t nq, int np_max, int32_t *__restrict__ prob
 __global__ void k_wl_count(int64_t nq, int np_max, const int32_t *__restrict__ probes,
                            const int32_t *__restrict__ np, int32_t *__restrict__ list_cnt)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nq) return;
-    for (int r = 0; r < np[i]; ++r) atomicAdd(&list_cnt[probes[i * np_max + r]], 1);
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nq * np_max) return;
+    const int64_t i = t / np_max;
+    const int r = (int)(t % np_max);
+    if (r < np[i]) atomicAdd(&list_cnt[probes[t]], 1);
 }
 
 // One workgroup: per-list query offsets and the item offsets of the eight
@@ -172,11 +201,13 @@ __global__ void k_wl_fill(int64_t nq, int np_max, const int32_t *__restrict__ pr
                           const int32_t *__restrict__ np, const int64_t *__restrict__ list_qoff,
                           int32_t *__restrict__ list_fill, int32_t *__restrict__ list_q)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nq) return;
-    for (int r = 0; r < np[i]; ++r) {
-        int l = probes[i * np_max + r];
-        int pos = atomicAdd(&list_fill[l], 1);
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nq * np_max) return;
+    const int64_t i = t / np_max;
+    const int r = (int)(t % np_max);
+    if (r < np[i]) {
+        const int l = probes[t];
+        const int pos = atomicAdd(&list_fill[l], 1);
         list_q[list_qoff[l] + pos] = (int32_t)i;
     }
 }
@@ -209,6 +240,9 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
                                              float *__restrict__ thr)
 {
     __shared__ uint64_t K[1024];
+    __shared__ float Ds[256];
+    __shared__ float4 q1[16];
+    __shared__ int chunk_off[1024], chunk_w[1024];
     const int64_t q = blockIdx.x;
     const int l0 = probes[q * np_max];
     const int64_t len = list_len[l0];
@@ -219,19 +253,35 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
     const int64_t b0 = ix.list_blk[l0];
     const float *qy = qv.qy + q * g.d_pad;
     const float a1 = g.L > 1 ? qv.qtail[q * g.L + 1] : 0.f;
+    const int w0 = g.wp[0], w04 = w0 >> 2;
+    const int nch = g.d_pad >> 2;
+    if (threadIdx.x < w04) q1[threadIdx.x] = *reinterpret_cast<const float4 *>(qy + threadIdx.x * 4);
+    for (int ch = threadIdx.x; ch < nch; ch += NT) {
+        int lv = 0;
+        while (4 * ch >= g.mp[lv + 1]) ++lv;
+        chunk_off[ch] = g.B * g.mp[lv] + (4 * ch - g.mp[lv]);
+        chunk_w[ch] = g.wp[lv];
+    }
+    __syncthreads();
+    // level-1 lower bound of every pool candidate
     const int PP = next_pow2(P);
     for (int p = threadIdx.x; p < PP; p += NT) {
         if (p < P) {
-            int64_t gb = b0 + p / g.B;
-            int s = p % g.B;
-            const float *x = ix.levels + gb * (int64_t)g.B * g.d_pad + (int64_t)s * g.wp[0];
+            const int64_t gb = b0 + p / g.B;
+            const int s = p % g.B;
+            const float *x = ix.levels + gb * (int64_t)g.B * g.d_pad + (int64_t)s * w0;
             float sh = 0.f;
-            for (int j = 0; j < g.wp[0]; ++j) {
-                float t = qy[j] - x[j];
-                sh = __builtin_fmaf(t, t, sh);
+            for (int c4 = 0; c4 < w04; ++c4) {
+                const float4 x4 = *reinterpret_cast<const float4 *>(x + c4 * 4);
+                const float4 q4 = q1[c4];
+                float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                sh = __builtin_fmaf(t0, t0, sh);
+                sh = __builtin_fmaf(t1, t1, sh);
+                sh = __builtin_fmaf(t2, t2, sh);
+                sh = __builtin_fmaf(t3, t3, sh);
             }
-            float b1 = g.L > 1 ? ix.tails[gb * (int64_t)g.B * g.L + g.B + s] : 0.f;
-            float tt = a1 - b1;
+            const float b1 = g.L > 1 ? ix.tails[gb * (int64_t)g.B * g.L + g.B + s] : 0.f;
+            const float tt = a1 - b1;
             K[p] = make_key(sh + tt * tt, p);
         } else {
             K[p] = KEY_MAX;
@@ -239,29 +289,34 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
     }
     __syncthreads();
     block_bitonic_sort(K, PP);
-    // Full distance of the S most promising candidates.
-    uint64_t mine = KEY_MAX;
-    if (threadIdx.x < S) {
-        int p = key_id(K[threadIdx.x]);
-        int64_t gb = b0 + p / g.B;
-        int s = p % g.B;
-        const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
-        float sh = 0.f;
-        for (int lv = 0; lv < g.L; ++lv) {
-            const float *x = blk + (int64_t)g.B * g.mp[lv] + (int64_t)s * g.wp[lv];
-            const float *qq = qy + g.mp[lv];
-            for (int j = 0; j < g.wp[lv]; ++j) {
-                float t = qq[j] - x[j];
-                sh = __builtin_fmaf(t, t, sh);
+    // full distance of the S most promising candidates: 16 lanes per candidate
+    const int team = threadIdx.x >> 4, tl = threadIdx.x & 15;
+    for (int base = 0; base < S; base += NT / 16) {
+        const int si = base + team;
+        float part = 0.f;
+        if (si < S) {
+            const int p = key_id(K[si]);
+            const int64_t gb = b0 + p / g.B;
+            const int s = p % g.B;
+            const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
+#pragma unroll 4
+            for (int ch = tl; ch < nch; ch += 16) {
+                const float4 x4 = *reinterpret_cast<const float4 *>(blk + chunk_off[ch] + (int64_t)s * chunk_w[ch]);
+                const float4 q4 = *reinterpret_cast<const float4 *>(qy + 4 * ch);
+                float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                part = __builtin_fmaf(t0, t0, part);
+                part = __builtin_fmaf(t1, t1, part);
+                part = __builtin_fmaf(t2, t2, part);
+                part = __builtin_fmaf(t3, t3, part);
             }
         }
-        mine = make_key(sh, threadIdx.x);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        if (si < S && tl == 0) Ds[si] = part;
     }
     __syncthreads();
     const int PS = next_pow2(S);
-    for (int i = threadIdx.x; i < PS; i += NT) K[i] = KEY_MAX;
-    __syncthreads();
-    if (threadIdx.x < S) K[threadIdx.x] = mine;
+    for (int i = threadIdx.x; i < PS; i += NT) K[i] = i < S ? make_key(Ds[i], i) : KEY_MAX;
     __syncthreads();
     block_bitonic_sort(K, PS);
     if (threadIdx.x == 0) {
@@ -286,7 +341,7 @@ struct WorkView {
 
 // Counters layout (unsigned long long): [0] items, [1] committed, [2] bytes,
 // [8 + l] pairs reading level l.
-constexpr int ST_ITEMS = 0, ST_COMMIT = 1, ST_BYTES = 2, ST_LEVEL = 8;
+constexpr int ST_ITEMS = 0, ST_COMMIT = 1, ST_BYTES = 2, ST_LEVEL = 8, ST_CYCLES = 80;
 
 template <bool PRUNE>
 __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
@@ -300,17 +355,31 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
     __shared__ int qid_s[GMAX], tcnt[GMAX], ncand[GMAX];
     __shared__ float thr_s[GMAX], E_s[GMAX];
     __shared__ int item_s, npairs_s;
+    __shared__ float4 q1s[GMAX][16];
+    __shared__ float qtl_s[GMAX][64];
 
     const LevelGeom &g = c.g;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     float *Stmp = reinterpret_cast<float *>(&sbuf[0][0]);  // [GMAX][256], aliases sbuf
     __shared__ unsigned long long my_lv[64];
+    __shared__ unsigned long long sparse_bytes_s;
     int queue = blockIdx.x & 7;
     int tried = 0;
     unsigned long long my_items = 0, my_bytes = 0;
     const int Lc = g.L < 64 ? g.L : 64;
     for (int i = tid; i < 64; i += NT) my_lv[i] = 0;
+    if (tid == 0) sparse_bytes_s = 0;
 
+    unsigned long long cyc[6] = {0, 0, 0, 0, 0, 0};
+    unsigned long long tmark = __builtin_readcyclecounter();
+#define PANO_PHASE(i)                                                  \
+    do {                                                               \
+        if (wk.stats && tid == 0) {                                    \
+            unsigned long long now_ = __builtin_readcyclecounter();    \
+            cyc[i] += now_ - tmark;                                    \
+            tmark = now_;                                              \
+        }                                                              \
+    } while (0)
     while (true) {
         // ---- pull the next item from this workgroup's XCD queue, then steal
         if (tid == 0) {
@@ -331,6 +400,7 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
         }
         __syncthreads();
         const int item = item_s;
+        PANO_PHASE(0);
         if (item < 0) break;
         // ---- decode: binary search the queue-ordered item offsets
         int lo = 0, hi = 8 * c.ceil8;
@@ -358,6 +428,19 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
         }
         ++my_items;
         __syncthreads();
+        for (int e = tid; e < ng * 64; e += NT) {
+            const int gq = e >> 6, lv = e & 63;
+            qtl_s[gq][lv] = lv < g.L ? qv.qtail[(int64_t)qid_s[gq] * g.L + lv] : 0.f;
+        }
+        if (PRUNE) {
+            const int w04 = g.wp[0] >> 2;
+            for (int e = tid; e < ng * 16; e += NT) {
+                const int gq = e >> 4, c4 = e & 15;
+                q1s[gq][c4] = c4 < w04 ? *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_s[gq] * g.d_pad + c4 * 4)
+                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            __syncthreads();
+        }
 
         for (int bb = bstart; bb < bend; ++bb) {
             const int64_t gb = lb0 + bb;
@@ -385,13 +468,11 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                 }
                 const float b1 = (g.L > 1 && valid) ? tl[g.B + s] : 0.f;
                 for (int gq = 0; gq < ng; ++gq) {
-                    const int qq = __builtin_amdgcn_readfirstlane(qid_s[gq]);
-                    const float *qy = qv.qy + (int64_t)qq * g.d_pad;
                     float sh = 0.f;
 #pragma unroll
                     for (int c4 = 0; c4 < 16; ++c4) {
                         if (c4 * 4 < w0) {
-                            float4 q4 = *reinterpret_cast<const float4 *>(qy + c4 * 4);
+                            float4 q4 = q1s[gq][c4];
                             float t0 = q4.x - xr[c4].x, t1 = q4.y - xr[c4].y;
                             float t2 = q4.z - xr[c4].z, t3 = q4.w - xr[c4].w;
                             sh = __builtin_fmaf(t0, t0, sh);
@@ -400,7 +481,7 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                             sh = __builtin_fmaf(t3, t3, sh);
                         }
                     }
-                    const float a1 = g.L > 1 ? qv.qtail[(int64_t)qq * g.L + 1] : 0.f;
+                    const float a1 = g.L > 1 ? qtl_s[gq][1] : 0.f;
                     const float dt = a1 - b1;
                     const float lb = sh + dt * dt + c.one_m_eps2 * a1 * b1;
                     const float eta = c.mg.c_level[1] * sh + c.mg.c_tail * (a1 + b1) * (a1 + b1);
@@ -428,12 +509,12 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                         }
                         for (int gq = 0; gq < ng; ++gq) {
                             const int qq = __builtin_amdgcn_readfirstlane(qid_s[gq]);
-                            const float *qy = qv.qy + (int64_t)qq * g.d_pad + g.mp[lv] + c0;
+                            const UniformF4 qy4 = uniform_f4(qv.qy + (int64_t)qq * g.d_pad + g.mp[lv] + c0);
                             float sh = 0.f;
 #pragma unroll
                             for (int c4 = 0; c4 < 16; ++c4) {
                                 if (c0 + c4 * 4 < w) {
-                                    float4 q4 = *reinterpret_cast<const float4 *>(qy + c4 * 4);
+                                    float4 q4 = qy4[c4];
                                     float t0 = q4.x - xr[c4].x, t1 = q4.y - xr[c4].y;
                                     float t2 = q4.z - xr[c4].z, t3 = q4.w - xr[c4].w;
                                     sh = __builtin_fmaf(t0, t0, sh);
@@ -456,6 +537,7 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                     for (int lv = 0; lv < Lc; ++lv) my_lv[lv] += (unsigned long long)cnt * ng;
                 }
             }
+            PANO_PHASE(1);
             // ---- consolidate the (query, candidate) survivors of level 1
             {
                 int tot;
@@ -471,80 +553,80 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                 if (tid == 0) npairs_s = tot;
                 __syncthreads();
             }
-            // ---- later levels: only the surviving pairs, gathered by teams of
-            // lanes (one contiguous level slice per pair)
-            if (PRUNE) {
-                for (int lv = 1; lv < g.L; ++lv) {
-                    const int np_ = npairs_s;
-                    if (np_ == 0) break;
-                    const int w = g.wp[lv];
-                    const int w4 = w >> 2;
-                    int TL = 1;
-                    while (TL < w4 && TL < 16) TL <<= 1;
-                    const int nteams = NT / TL;
-                    const int tm = tid / TL, tlane = tid % TL;
-                    const bool last = (lv + 1 == g.L);
-                    const float ce = c.mg.c_level[lv + 1];
-                    for (int p0 = 0; p0 < np_; p0 += nteams) {
-                        const int p = p0 + tm;
-                        const bool act = p < np_;
-                        const uint32_t pv = act ? pr[p] : 0u;
-                        const int gq = (int)(pv >> 8), ss = (int)(pv & 255u);
-                        const int qq = qid_s[gq];
+            // ---- later levels: each surviving pair is refined by one lane, level
+            // after level, until its bound exceeds the threshold or the last
+            // level is read (no barrier between levels; Update and Consolidate
+            // of Section 6.1 happen once, after the walk)
+            if (PRUNE && g.L > 1) {
+                const int np_ = npairs_s;
+                unsigned long long my_dims = 0;
+                for (int p = tid; p < np_; p += NT) {
+                    const uint32_t pv = pr[p];
+                    const int gq = (int)(pv >> 8), ss = (int)(pv & 255u);
+                    const int qq = qid_s[gq];
+                    const float th = thr_s[gq];
+                    const float *qrow = qv.qy + (int64_t)qq * g.d_pad;
+                    const float *qt = &qtl_s[gq][0];
+                    float sh = pS[p];
+                    bool alive = true;
+                    int lv = 1;
+                    for (; lv < g.L; ++lv) {
+                        const int w4 = g.wp[lv] >> 2;
+                        const float *x = blk + (int64_t)g.B * g.mp[lv] + (int64_t)ss * g.wp[lv];
+                        const float *qq4 = qrow + g.mp[lv];
                         float part = 0.f;
-                        if (act) {
-                            const float *x = blk + (int64_t)g.B * g.mp[lv] + (int64_t)ss * w;
-                            const float *qy = qv.qy + (int64_t)qq * g.d_pad + g.mp[lv];
-                            for (int c4 = tlane; c4 < w4; c4 += TL) {
-                                float4 x4 = *reinterpret_cast<const float4 *>(x + c4 * 4);
-                                float4 q4 = *reinterpret_cast<const float4 *>(qy + c4 * 4);
-                                float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
-                                part = __builtin_fmaf(t0, t0, part);
-                                part = __builtin_fmaf(t1, t1, part);
-                                part = __builtin_fmaf(t2, t2, part);
-                                part = __builtin_fmaf(t3, t3, part);
-                            }
+#pragma unroll 4
+                        for (int c4 = 0; c4 < w4; ++c4) {
+                            const float4 x4 = *reinterpret_cast<const float4 *>(x + c4 * 4);
+                            const float4 q4 = *reinterpret_cast<const float4 *>(qq4 + c4 * 4);
+                            float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                            part = __builtin_fmaf(t0, t0, part);
+                            part = __builtin_fmaf(t1, t1, part);
+                            part = __builtin_fmaf(t2, t2, part);
+                            part = __builtin_fmaf(t3, t3, part);
                         }
-                        for (int o = TL >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-                        if (act && tlane == 0) {
-                            const float sh = pS[p] + part;
-                            float a = 0.f, b = 0.f;
-                            if (!last) {
-                                a = qv.qtail[(int64_t)qq * g.L + lv + 1];
-                                b = tl[(int64_t)(lv + 1) * g.B + ss];
-                            }
-                            const float dt = a - b;
-                            const float lb = sh + dt * dt + c.one_m_eps2 * a * b;
-                            const float eta = ce * sh + c.mg.c_tail * (a + b) * (a + b);
-                            keep[p] = (lb - eta <= thr_s[gq]) ? 1 : 0;
-                            pS[p] = sh;
+                        sh += part;
+                        const bool last = (lv + 1 == g.L);
+                        const float a = last ? 0.f : qt[lv + 1];
+                        const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
+                        const float dt = a - b;
+                        const float lb = sh + dt * dt + c.one_m_eps2 * a * b;
+                        const float eta = c.mg.c_level[lv + 1] * sh + c.mg.c_tail * (a + b) * (a + b);
+                        if (lb - eta > th) {
+                            alive = false;
+                            ++lv;
+                            break;
                         }
                     }
-                    if (tid == 0) {
-                        my_bytes += (unsigned long long)np_ * (w * 4 + (last ? 0 : 4));
-                        if (lv < 64) my_lv[lv] += (unsigned long long)np_;
+                    keep[p] = alive ? 1 : 0;
+                    pS[p] = sh;
+                    if (wk.stats) {
+                        for (int v = 1; v < lv && v < 64; ++v) atomicAdd(&my_lv[v], 1ull);
+                        my_dims += (unsigned long long)(g.mp[lv < g.L ? lv : g.L] - g.mp[1]);
                     }
-                    __syncthreads();
-                    // in-place stable compaction of the kept pairs
-                    int kept = 0;
-                    for (int base = 0; base < np_; base += NT) {
-                        const int i = base + tid;
-                        const bool f = i < np_ && keep[i];
-                        const uint32_t pv = f ? pr[i] : 0u;
-                        const float sv = f ? pS[i] : 0.f;
-                        int tot;
-                        int off = block_exclusive_scan(f ? 1 : 0, wave_tmp, &tot);
-                        if (f) {
-                            pr[kept + off] = pv;
-                            pS[kept + off] = sv;
-                        }
-                        kept += tot;
-                        __syncthreads();
+                }
+                if (wk.stats && my_dims) atomicAdd(&sparse_bytes_s, my_dims * 4ull);
+                __syncthreads();
+                // one stable compaction of the pairs that survived every level
+                int kept = 0;
+                for (int base = 0; base < np_; base += NT) {
+                    const int i = base + tid;
+                    const bool f = i < np_ && keep[i];
+                    const uint32_t pv = f ? pr[i] : 0u;
+                    const float sv = f ? pS[i] : 0.f;
+                    int tot;
+                    int off = block_exclusive_scan(f ? 1 : 0, wave_tmp, &tot);
+                    if (f) {
+                        pr[kept + off] = pv;
+                        pS[kept + off] = sv;
                     }
-                    if (tid == 0) npairs_s = kept;
+                    kept += tot;
                     __syncthreads();
                 }
+                if (tid == 0) npairs_s = kept;
+                __syncthreads();
             }
+            PANO_PHASE(2);
             // ---- commit: merge each query's survivors into its local top-kc
             const int np_ = npairs_s;
             if (np_ > 0) {
@@ -596,6 +678,7 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                 }
             }
             __syncthreads();
+            PANO_PHASE(3);
         }
         // ---- item end: publish each query's local top-kc entries that can
         // still reach its final band
@@ -628,10 +711,13 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
             }
         }
         __syncthreads();
+        PANO_PHASE(4);
     }
+#undef PANO_PHASE
     if (wk.stats && tid == 0) {
+        for (int i = 0; i < 6; ++i) atomicAdd(&wk.stats[ST_CYCLES + i], cyc[i]);
         atomicAdd(&wk.stats[ST_ITEMS], my_items);
-        atomicAdd(&wk.stats[ST_BYTES], my_bytes);
+        atomicAdd(&wk.stats[ST_BYTES], my_bytes + sparse_bytes_s);
         for (int lv = 0; lv < Lc; ++lv)
             if (my_lv[lv]) atomicAdd(&wk.stats[ST_LEVEL + lv], my_lv[lv]);
     }
@@ -650,7 +736,9 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
 {
     extern __shared__ uint64_t K[];
     __shared__ int nb_s;
+    __shared__ float qrow[4096];
     const int64_t q = blockIdx.x;
+    for (int j = threadIdx.x; j < d; j += NT) qrow[j] = qraw[q * d + j];
     const int n_all = buf_cnt[q];
     if ((flags[q] & FLAG_OVERFLOW) || n_all > c.capq) {
         if (threadIdx.x == 0) atomicOr(&flags[q], FLAG_OVERFLOW);
@@ -675,7 +763,7 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
     // canonical rescoring of the band (the band is a prefix of the sort)
     for (int i = threadIdx.x; i < nb; i += NT) {
         const int32_t id = key_id(K[i]);
-        K[i] = make_key(canon_dist(qraw + q * d, raw + (int64_t)id * d, d), id);
+        K[i] = make_key(canon_dist_stream(qrow, raw + (int64_t)id * d, d), id);
     }
     const int PB = next_pow2(nb > 0 ? nb : 1);
     for (int i = nb + threadIdx.x; i < PB; i += NT) K[i] = KEY_MAX;
@@ -799,7 +887,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     while (G > 1 && G * c.kc > 1024) G >>= 1;
     if (prm && prm->group > 0) G = std::min(prm->group, G);
     c.G = G;
-    c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 16;
+    c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1;
     c.capq = std::min(4096, std::max(2048, 16 * c.kc));
     c.nlist = nlist;
     c.ceil8 = (nlist + 7) / 8;
@@ -875,11 +963,14 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         const double u = std::ldexp(1.0, -24);
         auto gam = [&](double nn) { return nn * u / (1.0 - nn * u); };
         const float c_co = (float)((gam(d / 64.0 + 8) + gam(32.0 + (d + 31) / 32 + 2) + 4 * u) * 1.1);
-        const int P = next_pow2(nlist);
-        size_t shm = sizeof(uint64_t) * P + 3 * sizeof(float) * nlist;
+        const size_t per_wave = coarse_lds_per_wave(nlist, d);
+        int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
+        const size_t shm = per_wave * wpb;
+        PANO_REQUIRE(shm <= 160 * 1024, "nlist too large for the coarse step");
         PANO_HIP(hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        hipLaunchKernelGGL(k_coarse, dim3((unsigned)nq), dim3(NT), shm, s, Sco, qn2, ix->cent.as<float>() + (size_t)nlist * d,
-                           q, ix->cent.as<float>(), d, nlist, nprobe_dev, nprobe_all, c_co, np_max, probes, npq);
+        hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), shm, s, Sco, qn2,
+                           ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq, nprobe_dev,
+                           nprobe_all, c_co, np_max, probes, npq);
     } else {
         hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, np_max, probes, npq);
     }
@@ -888,10 +979,11 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     PANO_HIP(hipMemsetAsync(list_cnt, 0, sizeof(int32_t) * nlist, s));
     PANO_HIP(hipMemsetAsync(list_fill, 0, sizeof(int32_t) * nlist, s));
     PANO_HIP(hipMemsetAsync(heads, 0, sizeof(int32_t) * 8, s));
-    hipLaunchKernelGGL(k_wl_count, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, np_max, probes, npq, list_cnt);
+    const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
+    hipLaunchKernelGGL(k_wl_count, dim3(wl_grid), dim3(256), 0, s, nq, np_max, probes, npq, list_cnt);
     hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, s, nlist, c.ceil8, c.G, c.bpi, list_cnt,
                        ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
-    hipLaunchKernelGGL(k_wl_fill, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, np_max, probes, npq, list_qoff,
+    hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, s, nq, np_max, probes, npq, list_qoff,
                        list_fill, list_q);
     PANO_HIP(hipMemsetD32Async((hipDeviceptr_t)thr, 0x7f800000, nq, s));
     PANO_HIP(hipMemsetAsync(buf_cnt, 0, sizeof(int32_t) * nq, s));
@@ -980,6 +1072,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         st.ms_scan = t;
         PANO_HIP(hipEventElapsedTime(&t, ev[2], ev[3]));
         st.ms_merge = t;
+        for (int i = 0; i < 6; ++i) st.scan_cycles[i] = (int64_t)hs[ST_CYCLES + i];
         for (auto &e : ev) (void)hipEventDestroy(e);
     }
 }

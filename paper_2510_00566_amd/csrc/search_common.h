@@ -12,6 +12,23 @@ constexpr int SB_MAX = 512;     // per-wave sort buffer (entries)
 constexpr uint64_t KEY_MAX = ~0ull;
 constexpr int FLAG_OVERFLOW = 1;
 
+// Wave-uniform reads of query slices go through the constant address space so
+// that they become scalar loads into SGPRs (a free broadcast to all lanes).
+struct UniformF4 {
+    const float *p;
+    __device__ inline float4 operator[](int i) const
+    {
+#if defined(__HIP_DEVICE_COMPILE__)
+        typedef __attribute__((address_space(4))) const float cfloat;
+        cfloat *q = (cfloat *)p;
+        return make_float4(q[4 * i], q[4 * i + 1], q[4 * i + 2], q[4 * i + 3]);
+#else
+        return make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
+#endif
+    }
+};
+__device__ inline UniformF4 uniform_f4(const float *p) { return UniformF4{p}; }
+
 // Scalars of one search, passed by value.
 struct SearchConsts {
     int k;
@@ -36,6 +53,48 @@ __device__ inline float canon_dist(const float *__restrict__ q, const float *__r
     double s = 0.0;
     for (int j = 0; j < d; ++j) {
         double t = (double)q[j] - (double)x[j];
+        double t2 = t * t;
+        s = s + t2;
+    }
+    return (float)s;
+}
+
+// The same recipe with the query held in LDS and the row streamed in
+// 16-float chunks (the next chunk is in flight while the current one is
+// summed).  Identical arithmetic, identical order.
+__device__ inline float canon_dist_stream(const float *q_lds, const float *__restrict__ x, int d)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    int j = 0;
+    if ((d & 3) == 0 && d >= 16) {
+        const float4 *x4 = reinterpret_cast<const float4 *>(x);
+        float4 cur[4], nxt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cur[u] = x4[u];
+        const int n16 = d >> 4;
+        for (int c = 0; c < n16; ++c) {
+            if (c + 1 < n16) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) nxt[u] = x4[(c + 1) * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float xv[4] = {cur[u].x, cur[u].y, cur[u].z, cur[u].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    double t = (double)q_lds[c * 16 + u * 4 + e] - (double)xv[e];
+                    double t2 = t * t;
+                    s = s + t2;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+        }
+        j = n16 << 4;
+    }
+    for (; j < d; ++j) {
+        double t = (double)q_lds[j] - (double)x[j];
         double t2 = t * t;
         s = s + t2;
     }
@@ -114,6 +173,64 @@ __host__ __device__ inline int next_pow2(int v)
     int p = 1;
     while (p < v) p <<= 1;
     return p;
+}
+
+// p-th smallest (1-based) of n non-negative floats V[0..n) by one wavefront:
+// an MSB-first radix select over the IEEE bit patterns (monotone for
+// non-negative values), 8 bits per round, with a 256-bin LDS histogram.
+__device__ inline float wave_select_nonneg(const float *V, int n, int p, int *hist, int lane)
+{
+    uint32_t prefix = 0, mask = 0;
+    int need = p;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int i = lane; i < 256; i += 64) hist[i] = 0;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int i = lane; i < n; i += 64) {
+            const uint32_t u = __float_as_uint(V[i]);
+            if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // lane owns bins 4*lane .. 4*lane+3
+        int h[4], sum = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            h[t] = hist[lane * 4 + t];
+            sum += h[t];
+        }
+        int incl = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        const int excl = incl - sum;
+        // the lane whose range holds the need-th element
+        const bool mine = excl < need && need <= incl;
+        const uint64_t bal = __ballot(mine);
+        const int owner = (int)__ffsll((unsigned long long)bal) - 1;
+        int digit = 0, before = 0;
+        if (lane == owner) {
+            int run = excl;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (run + h[t] >= need) {
+                    digit = lane * 4 + t;
+                    before = run;
+                    break;
+                }
+                run += h[t];
+            }
+        }
+        digit = __shfl(digit, owner, 64);
+        before = __shfl(before, owner, 64);
+        prefix |= (uint32_t)digit << shift;
+        mask |= 255u << shift;
+        need -= before;
+        __builtin_amdgcn_wave_barrier();
+    }
+    return __uint_as_float(prefix);
 }
 
 // Exclusive prefix sum of one int per thread over the workgroup; returns the

@@ -188,8 +188,9 @@ class Index:
     def stats(self) -> dict:
         st = L.Stats()
         L.check(L.lib().pano_stats_get(self.h, C.byref(st)))
-        out = {f: getattr(st, f) for f, _ in st._fields_ if f != "level_reads"}
+        out = {f: getattr(st, f) for f, _ in st._fields_ if f not in ("level_reads", "scan_cycles")}
         out["level_reads"] = list(st.level_reads)
+        out["scan_cycles"] = list(st.scan_cycles)
         return out
 
     def free(self):
