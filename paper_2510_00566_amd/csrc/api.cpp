@@ -398,6 +398,15 @@ pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const flo
         for (double v : vn) vmax = std::max(vmax, v);
         ix->transform_err_max = (double)ix->mg.kappa * vmax * (1.0 + 1e-6);
         ix->mg.e_max = (float)(ix->transform_err_max * (1.0 + 1e-6));
+        {
+            // ||y|| <= sigma_max ||v|| + kappa ||v|| for every stored row
+            const double smax = std::sqrt(1.0 + (ix->sigma_ratio * ix->sigma_ratio - 1.0));
+            const double b0 = (smax + (double)ix->mg.kappa) * vmax * (1.0 + 1e-6);
+            ix->mg.b0max2 = (float)(b0 * b0 * (1.0 + 1e-6));
+            int wmax = 0;
+            for (int l = 0; l < L; ++l) wmax = std::max(wmax, ix->wp[l]);
+            ix->mg.c_abs = (float)((gamma_n((double)wmax + L + 8) + 6.0 * std::ldexp(1.0, -24)) * 1.01);
+        }
         // lists: stable counting sort by assignment
         ix->list_len.assign(nlist, 0);
         for (int64_t i = 0; i < n; ++i) {

@@ -79,6 +79,9 @@ struct Margins {
     float kappa;        // per-unit-norm transform error bound (queries use kappa*||v||)
     float rho;          // sigma_max/sigma_min of the FP32 transform times (1+u')/(1-u') root
     float c_final;      // coefficient on D~ for the error of the full distance
+    float c_abs;        // per-query absolute margin A_q = c_abs (a_0^2 + b0max2) for the
+                        // dot-product form (matrix-core level 1 and brute force)
+    float b0max2;       // bound on the largest stored squared norm
 };
 
 }  // namespace pano

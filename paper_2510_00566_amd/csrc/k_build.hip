@@ -358,7 +358,10 @@ __device__ inline uint16_t f32_to_bf16_rne(float f)
 }
 
 // One workgroup per block of B slots.  Level-major within the block: all B
-// slices of level 0, then all B slices of level 1, ...
+// slices of level 0, then all B slices of level 1, ...  Inside a level the
+// level-1 slices are interleaved by groups of four dimensions
+// ([group][slot][4]) so that one 16-byte load per lane reads consecutive slots;
+// the slices of later levels are stored slot after slot.
 __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ Y, const float *__restrict__ tails_row,
                                               const int64_t *__restrict__ perm,
                                               const int64_t *__restrict__ list_start,
@@ -392,7 +395,13 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ Y, const
         int lv = lvl_of[c];
         int64_t r = rows[s];
         float v = r >= 0 ? Y[r * g.d_pad + c] : 0.f;
-        int64_t o = (int64_t)g.B * g.mp[lv] + (int64_t)s * g.wp[lv] + (c - g.mp[lv]);
+        // level 1 (read densely by every query of a group): groups of 4
+        // consecutive dimensions, each group stored for all B slots (float4 per
+        // slot); later levels (read per surviving candidate): each slot's slice
+        // contiguous
+        const int j = c - g.mp[lv];
+        int64_t o = lv == 0 ? (int64_t)(j >> 2) * 4 * g.B + (int64_t)s * 4 + (j & 3)
+                            : (int64_t)g.B * g.mp[lv] + (int64_t)s * g.wp[lv] + j;
         dst[o] = v;
         if (dstb) dstb[o] = f32_to_bf16_rne(v);
     }

@@ -10,13 +10,16 @@
 namespace pano {
 
 // ================================================================ query prep
-__global__ void k_query_consts(const double *__restrict__ vnorm, int64_t nq, float kappa, float e_max,
-                               float *__restrict__ qE)
+__global__ void k_query_consts(const double *__restrict__ vnorm, const float *__restrict__ qtail, int L, int64_t nq,
+                               Margins mg, float *__restrict__ qE, float *__restrict__ qA, int *__restrict__ bad)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nq) return;
-    // Rounded up by a relative 1e-6 to cover the FP32 rounding of this bound.
-    qE[i] = (float)((double)kappa * vnorm[i] * (1.0 + 1e-6)) + e_max;
+    if (!isfinite(vnorm[i])) atomicOr(bad, 1);
+    // Rounded up by a relative 1e-6 to cover the FP32 rounding of these bounds.
+    qE[i] = (float)((double)mg.kappa * vnorm[i] * (1.0 + 1e-6)) + mg.e_max;
+    const double a0 = (double)qtail[i * L];
+    qA[i] = (float)((double)mg.c_abs * (a0 * a0 * (1.0 + 1e-6) + (double)mg.b0max2) * (1.0 + 1e-6));
 }
 
 // ================================================================ coarse probing
@@ -226,6 +229,7 @@ struct QueryView {
     const float *qy;      // [nq][d_pad]
     const float *qtail;   // [nq][L]
     const float *qE;      // [nq]
+    const float *qA;      // [nq]
     const float *qraw;    // [nq][d]
 };
 
@@ -259,8 +263,13 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
     for (int ch = threadIdx.x; ch < nch; ch += NT) {
         int lv = 0;
         while (4 * ch >= g.mp[lv + 1]) ++lv;
-        chunk_off[ch] = g.B * g.mp[lv] + (4 * ch - g.mp[lv]);
-        chunk_w[ch] = g.wp[lv];
+        if (lv == 0) {
+            chunk_off[ch] = 4 * ch * g.B;
+            chunk_w[ch] = 4;
+        } else {
+            chunk_off[ch] = g.B * g.mp[lv] + (4 * ch - g.mp[lv]);
+            chunk_w[ch] = g.wp[lv];
+        }
     }
     __syncthreads();
     // level-1 lower bound of every pool candidate
@@ -269,10 +278,10 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
         if (p < P) {
             const int64_t gb = b0 + p / g.B;
             const int s = p % g.B;
-            const float *x = ix.levels + gb * (int64_t)g.B * g.d_pad + (int64_t)s * w0;
+            const float *x = ix.levels + gb * (int64_t)g.B * g.d_pad + (int64_t)s * 4;
             float sh = 0.f;
             for (int c4 = 0; c4 < w04; ++c4) {
-                const float4 x4 = *reinterpret_cast<const float4 *>(x + c4 * 4);
+                const float4 x4 = *reinterpret_cast<const float4 *>(x + (int64_t)c4 * 4 * g.B);
                 const float4 q4 = q1[c4];
                 float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
                 sh = __builtin_fmaf(t0, t0, sh);
@@ -320,7 +329,7 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
     __syncthreads();
     block_bitonic_sort(K, PS);
     if (threadIdx.x == 0) {
-        float t = prune_threshold(key_dist(K[c.k - 1]), qv.qE[q], c.mg);
+        float t = prune_threshold(key_dist(K[c.k - 1]), qv.qE[q], qv.qA[q], c.mg);
         atomic_min_nonneg(&thr[q], t);
     }
 }
@@ -343,6 +352,46 @@ struct WorkView {
 // [8 + l] pairs reading level l.
 constexpr int ST_ITEMS = 0, ST_COMMIT = 1, ST_BYTES = 2, ST_LEVEL = 8, ST_CYCLES = 80;
 
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// Dot products of the (up to 16) queries of the group with 64 slots of the
+// block (this wavefront's share) over one level, on the matrix cores:
+// v_mfma_f32_16x16x4f32 with queries as rows and slots as columns.  The
+// reduction index is permuted so that each lane feeds four consecutive
+// dimensions from one 16-byte load: in the group of four steps t, lane
+// (r, q) supplies dimensions 16t + 4q .. 16t + 4q + 3 of query r (from LDS)
+// and of slot r (from the level tile: [group][slot][4] for level 1, slot-major
+// rows of row_w floats for later levels).  Each level is
+// summed in fresh accumulators before being added to acc (chunked sums).
+__device__ inline void level_dots(const float *__restrict__ tile, int B, int kg_count, const float4 *qrows,
+                                  int qstride, int wave_slot0, int lane, floatx4_t acc[4], int row_w = 0)
+{
+    const int r16 = lane & 15, kq = lane >> 4;
+    floatx4_t part[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) part[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; 4 * t < kg_count; ++t) {
+        const int kg = 4 * t + kq;
+        const bool ok = kg < kg_count;
+        const float4 qa = ok ? qrows[r16 * qstride + kg] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 xa[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            xa[nt] = !ok ? make_float4(0.f, 0.f, 0.f, 0.f)
+                 : row_w ? *reinterpret_cast<const float4 *>(tile + (int64_t)(wave_slot0 + nt * 16 + r16) * row_w + kg * 4)
+                         : *reinterpret_cast<const float4 *>(tile + ((int64_t)kg * B + wave_slot0 + nt * 16 + r16) * 4);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            part[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.x, xa[nt].x, part[nt], 0, 0, 0);
+            part[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.y, xa[nt].y, part[nt], 0, 0, 0);
+            part[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.z, xa[nt].z, part[nt], 0, 0, 0);
+            part[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.w, xa[nt].w, part[nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] += part[nt];
+}
+
 template <bool PRUNE>
 __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
 {
@@ -353,23 +402,24 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
     __shared__ uint64_t topk[1024];
     __shared__ int wave_tmp[NT / 64];
     __shared__ int qid_s[GMAX], tcnt[GMAX], ncand[GMAX];
-    __shared__ float thr_s[GMAX], E_s[GMAX];
+    __shared__ float thr_s[GMAX], E_s[GMAX], A_s[GMAX], rqh_s[GMAX];
     __shared__ int item_s, npairs_s;
-    __shared__ float4 q1s[GMAX][16];
     __shared__ float qtl_s[GMAX][64];
+    __shared__ unsigned long long my_lv[64];
+    __shared__ unsigned long long sparse_bytes_s;
+    // query rows for the matrix-core dot products: level-1 slices (pruned
+    // scan) or one level at a time (brute force), [query][group of 4]
+    __shared__ float4 qrow_s[GMAX][16];
 
     const LevelGeom &g = c.g;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    float *Stmp = reinterpret_cast<float *>(&sbuf[0][0]);  // [GMAX][256], aliases sbuf
-    __shared__ unsigned long long my_lv[64];
-    __shared__ unsigned long long sparse_bytes_s;
+    const int r16 = lane & 15, kq = lane >> 4;
     int queue = blockIdx.x & 7;
     int tried = 0;
     unsigned long long my_items = 0, my_bytes = 0;
     const int Lc = g.L < 64 ? g.L : 64;
     for (int i = tid; i < 64; i += NT) my_lv[i] = 0;
     if (tid == 0) sparse_bytes_s = 0;
-
     unsigned long long cyc[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long tmark = __builtin_readcyclecounter();
 #define PANO_PHASE(i)                                                  \
@@ -380,6 +430,7 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
             tmark = now_;                                              \
         }                                                              \
     } while (0)
+
     while (true) {
         // ---- pull the next item from this workgroup's XCD queue, then steal
         if (tid == 0) {
@@ -420,11 +471,12 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
         const int bstart = ri * c.bpi;
         const int bend = (int)min<int64_t>(nblk, (int64_t)(ri + 1) * c.bpi);
         if (tid < ng) {
-            int qq = wk.list_q[wk.list_qoff[l] + gi * c.G + tid];
+            const int qq = wk.list_q[wk.list_qoff[l] + gi * c.G + tid];
             qid_s[tid] = qq;
             tcnt[tid] = 0;
             thr_s[tid] = INFINITY;
             E_s[tid] = qv.qE[qq];
+            A_s[tid] = qv.qA[qq];
         }
         ++my_items;
         __syncthreads();
@@ -433,14 +485,21 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
             qtl_s[gq][lv] = lv < g.L ? qv.qtail[(int64_t)qid_s[gq] * g.L + lv] : 0.f;
         }
         if (PRUNE) {
-            const int w04 = g.wp[0] >> 2;
-            for (int e = tid; e < ng * 16; e += NT) {
+            const int kg0 = g.wp[0] >> 2;
+            for (int e = tid; e < GMAX * 16; e += NT) {
                 const int gq = e >> 4, c4 = e & 15;
-                q1s[gq][c4] = c4 < w04 ? *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_s[gq] * g.d_pad + c4 * 4)
-                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+                qrow_s[gq][c4] = (gq < ng && c4 < kg0)
+                                     ? *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_s[gq] * g.d_pad + c4 * 4)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            __syncthreads();
         }
+        __syncthreads();
+        if (tid < ng) {
+            // head energy of level 1: ||q_h||^2 = a_0^2 - a_1^2
+            const float a0 = qtl_s[tid][0], a1 = g.L > 1 ? qtl_s[tid][1] : 0.f;
+            rqh_s[tid] = a0 * a0 - a1 * a1;
+        }
+        __syncthreads();
 
         for (int bb = bstart; bb < bend; ++bb) {
             const int64_t gb = lb0 + bb;
@@ -453,110 +512,109 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                 ncand[tid] = 0;
             }
             __syncthreads();
-            const int s = tid;
-            const bool valid = s < cnt;
-            uint32_t mask = 0;
+            // ---- dense phase on the matrix cores.  Lane (r16, kq) of wave wv
+            // ends with the dot products of queries 4 kq + v (v = 0..3) with
+            // slots wv*64 + nt*16 + r16 (nt = 0..3).
+            floatx4_t acc[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+            const int slot0 = wv * 64;
+            const bool wave_live = slot0 < cnt;
+            uint32_t mask = 0;  // bit nt*4 + v: pair (query 4kq+v, slot slot0+nt*16+r16) kept
+            float sval[16];
             if (PRUNE) {
-                // ---- level 1, dense over the block: every candidate against
-                // every query of the group (the query slice is wave-uniform).
-                const int w0 = g.wp[0];
-                float4 xr[16];
+                if (wave_live) level_dots(blk, g.B, g.wp[0] >> 2, &qrow_s[0][0], 16, slot0, lane, acc);
 #pragma unroll
-                for (int c4 = 0; c4 < 16; ++c4) {
-                    if (c4 * 4 < w0 && valid) xr[c4] = *reinterpret_cast<const float4 *>(blk + (int64_t)s * w0 + c4 * 4);
-                    else xr[c4] = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-                const float b1 = (g.L > 1 && valid) ? tl[g.B + s] : 0.f;
-                for (int gq = 0; gq < ng; ++gq) {
-                    float sh = 0.f;
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int s = slot0 + nt * 16 + r16;
+                    const bool valid = s < cnt;
+                    const float b0 = valid ? tl[s] : 0.f;
+                    const float b1 = (valid && g.L > 1) ? tl[g.B + s] : 0.f;
+                    const float rxh = b0 * b0 - b1 * b1;
 #pragma unroll
-                    for (int c4 = 0; c4 < 16; ++c4) {
-                        if (c4 * 4 < w0) {
-                            float4 q4 = q1s[gq][c4];
-                            float t0 = q4.x - xr[c4].x, t1 = q4.y - xr[c4].y;
-                            float t2 = q4.z - xr[c4].z, t3 = q4.w - xr[c4].w;
-                            sh = __builtin_fmaf(t0, t0, sh);
-                            sh = __builtin_fmaf(t1, t1, sh);
-                            sh = __builtin_fmaf(t2, t2, sh);
-                            sh = __builtin_fmaf(t3, t3, sh);
-                        }
+                    for (int v = 0; v < 4; ++v) {
+                        const int gq = 4 * kq + v;
+                        const bool on = valid && gq < ng;
+                        const float a1 = on && g.L > 1 ? qtl_s[gq][1] : 0.f;
+                        const float sh = (on ? rqh_s[gq] : 0.f) + rxh - 2.f * acc[nt][v];
+                        const float dt = a1 - b1;
+                        const float lb = sh + dt * dt + c.one_m_eps2 * a1 * b1;
+                        const float eta = (on ? A_s[gq] : 0.f) + c.mg.c_tail * (a1 + b1) * (a1 + b1);
+                        const bool sv = on && (lb - eta <= thr_s[on ? gq : 0]);
+                        mask |= (uint32_t)sv << (nt * 4 + v);
+                        sval[nt * 4 + v] = sh;
                     }
-                    const float a1 = g.L > 1 ? qtl_s[gq][1] : 0.f;
-                    const float dt = a1 - b1;
-                    const float lb = sh + dt * dt + c.one_m_eps2 * a1 * b1;
-                    const float eta = c.mg.c_level[1] * sh + c.mg.c_tail * (a1 + b1) * (a1 + b1);
-                    const bool sv = valid && (lb - eta <= thr_s[gq]);
-                    mask |= (uint32_t)sv << gq;
-                    Stmp[gq * 256 + s] = sh;
                 }
                 if (tid == 0) {
-                    my_bytes += (unsigned long long)cnt * (w0 * 4 + (g.L > 1 ? 4 : 0) + 4);
+                    my_bytes += (unsigned long long)cnt * (g.wp[0] * 4 + (g.L > 1 ? 8 : 4) + 4);
                     if (Lc > 0) my_lv[0] += (unsigned long long)cnt * ng;
                 }
             } else {
-                // ---- brute force: every level dense, distances accumulated per
-                // (query, candidate) in LDS.
-                for (int gq = 0; gq < ng; ++gq) Stmp[gq * 256 + s] = 0.f;
+                // brute force: every level, query rows staged per level
                 for (int lv = 0; lv < g.L; ++lv) {
-                    const int w = g.wp[lv];
-                    const float *xs = blk + (int64_t)g.B * g.mp[lv] + (int64_t)s * w;
-                    for (int c0 = 0; c0 < w; c0 += 64) {
-                        float4 xr[16];
-#pragma unroll
-                        for (int c4 = 0; c4 < 16; ++c4) {
-                            if (c0 + c4 * 4 < w && valid) xr[c4] = *reinterpret_cast<const float4 *>(xs + c0 + c4 * 4);
-                            else xr[c4] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    const int kgc = g.wp[lv] >> 2;
+                    for (int base = 0; base < kgc; base += 16) {
+                        const int kgn = min(16, kgc - base);
+                        __syncthreads();
+                        for (int e = tid; e < GMAX * 16; e += NT) {
+                            const int gq = e >> 4, c4 = e & 15;
+                            qrow_s[gq][c4] = (gq < ng && c4 < kgn)
+                                                 ? *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_s[gq] * g.d_pad +
+                                                                                     g.mp[lv] + (base + c4) * 4)
+                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
                         }
-                        for (int gq = 0; gq < ng; ++gq) {
-                            const int qq = __builtin_amdgcn_readfirstlane(qid_s[gq]);
-                            const UniformF4 qy4 = uniform_f4(qv.qy + (int64_t)qq * g.d_pad + g.mp[lv] + c0);
-                            float sh = 0.f;
-#pragma unroll
-                            for (int c4 = 0; c4 < 16; ++c4) {
-                                if (c0 + c4 * 4 < w) {
-                                    float4 q4 = qy4[c4];
-                                    float t0 = q4.x - xr[c4].x, t1 = q4.y - xr[c4].y;
-                                    float t2 = q4.z - xr[c4].z, t3 = q4.w - xr[c4].w;
-                                    sh = __builtin_fmaf(t0, t0, sh);
-                                    sh = __builtin_fmaf(t1, t1, sh);
-                                    sh = __builtin_fmaf(t2, t2, sh);
-                                    sh = __builtin_fmaf(t3, t3, sh);
-                                }
-                            }
-                            Stmp[gq * 256 + s] += sh;
+                        __syncthreads();
+                        if (wave_live) {
+                            if (lv == 0)
+                                level_dots(blk + (int64_t)base * 4 * g.B, g.B, kgn, &qrow_s[0][0], 16, slot0, lane, acc);
+                            else
+                                level_dots(blk + (int64_t)g.B * g.mp[lv] + base * 4, g.B, kgn, &qrow_s[0][0], 16, slot0,
+                                           lane, acc, g.wp[lv]);
                         }
                     }
                 }
-                for (int gq = 0; gq < ng; ++gq) {
-                    const float dd = Stmp[gq * 256 + s];
-                    const bool sv = valid && (dd * (1.f - c.mg.c_final) <= thr_s[gq]);
-                    mask |= (uint32_t)sv << gq;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int s = slot0 + nt * 16 + r16;
+                    const bool valid = s < cnt;
+                    const float b0 = valid ? tl[s] : 0.f;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int gq = 4 * kq + v;
+                        const bool on = valid && gq < ng;
+                        const float a0 = on ? qtl_s[gq][0] : 0.f;
+                        const float dd = a0 * a0 + b0 * b0 - 2.f * acc[nt][v];
+                        const bool sv = on && dist_lower(dd, A_s[gq], c.mg) <= thr_s[gq];
+                        mask |= (uint32_t)sv << (nt * 4 + v);
+                        sval[nt * 4 + v] = dd;
+                    }
                 }
                 if (tid == 0) {
-                    my_bytes += (unsigned long long)cnt * (g.d_pad * 4 + 4);
+                    my_bytes += (unsigned long long)cnt * (g.d_pad * 4 + 4 + 4);
                     for (int lv = 0; lv < Lc; ++lv) my_lv[lv] += (unsigned long long)cnt * ng;
                 }
             }
             PANO_PHASE(1);
-            // ---- consolidate the (query, candidate) survivors of level 1
+            // ---- consolidate: survivors into the (query, slot) pair list
             {
                 int tot;
                 int off = block_exclusive_scan(__popc(mask), wave_tmp, &tot);
-                uint32_t mm = mask;
-                while (mm) {
-                    int gq = __ffs(mm) - 1;
-                    mm &= mm - 1;
-                    pr[off] = ((uint32_t)gq << 8) | (uint32_t)s;
-                    pS[off] = Stmp[gq * 256 + s];
-                    ++off;
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    if (mask & (1u << b)) {
+                        const int nt = b >> 2, v = b & 3;
+                        pr[off] = ((uint32_t)(4 * kq + v) << 8) | (uint32_t)(slot0 + nt * 16 + r16);
+                        pS[off] = sval[b];
+                        ++off;
+                    }
                 }
                 if (tid == 0) npairs_s = tot;
                 __syncthreads();
             }
             // ---- later levels: each surviving pair is refined by one lane, level
             // after level, until its bound exceeds the threshold or the last
-            // level is read (no barrier between levels; Update and Consolidate
-            // of Section 6.1 happen once, after the walk)
+            // level is read (no barrier between levels; the Update and
+            // Consolidate phases of Section 6.1 run once, after the walk)
             if (PRUNE && g.L > 1) {
                 const int np_ = npairs_s;
                 unsigned long long my_dims = 0;
@@ -564,7 +622,7 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                     const uint32_t pv = pr[p];
                     const int gq = (int)(pv >> 8), ss = (int)(pv & 255u);
                     const int qq = qid_s[gq];
-                    const float th = thr_s[gq];
+                    const float th = thr_s[gq], Aq = A_s[gq];
                     const float *qrow = qv.qy + (int64_t)qq * g.d_pad;
                     const float *qt = &qtl_s[gq][0];
                     float sh = pS[p];
@@ -574,6 +632,8 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                         const int w4 = g.wp[lv] >> 2;
                         const float *x = blk + (int64_t)g.B * g.mp[lv] + (int64_t)ss * g.wp[lv];
                         const float *qq4 = qrow + g.mp[lv];
+                        const bool last = (lv + 1 == g.L);
+                        const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
                         float part = 0.f;
 #pragma unroll 4
                         for (int c4 = 0; c4 < w4; ++c4) {
@@ -586,12 +646,10 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                             part = __builtin_fmaf(t3, t3, part);
                         }
                         sh += part;
-                        const bool last = (lv + 1 == g.L);
                         const float a = last ? 0.f : qt[lv + 1];
-                        const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
                         const float dt = a - b;
                         const float lb = sh + dt * dt + c.one_m_eps2 * a * b;
-                        const float eta = c.mg.c_level[lv + 1] * sh + c.mg.c_tail * (a + b) * (a + b);
+                        const float eta = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq + c.mg.c_tail * (a + b) * (a + b);
                         if (lb - eta > th) {
                             alive = false;
                             ++lv;
@@ -647,7 +705,7 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                             const uint32_t pv = pr[i];
                             if ((int)(pv >> 8) == gq) {
                                 f = true;
-                                key = make_key(pS[i], ix.ids[gb * g.B + (pv & 255u)]);
+                                key = make_key(fmaxf(pS[i], 0.f), ix.ids[gb * g.B + (pv & 255u)]);
                             }
                         }
                         const uint64_t bal = __ballot(f);
@@ -663,10 +721,11 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                     const int keepn = min(c.kc, tot);
                     for (int i = lane; i < keepn; i += 64) tk[i] = SB[i];
                     float tnew = thr_s[gq];
-                    if (keepn >= c.k) tnew = fminf(tnew, prune_threshold(key_dist(SB[c.k - 1]), E_s[gq], c.mg));
+                    if (keepn >= c.k)
+                        tnew = fminf(tnew, prune_threshold(key_dist(SB[c.k - 1]), E_s[gq], A_s[gq], c.mg));
                     bool ovf = false;
                     for (int i = c.kc + lane; i < tot; i += 64)
-                        if (key_dist(SB[i]) * (1.f - c.mg.c_final) <= tnew) ovf = true;
+                        if (dist_lower(key_dist(SB[i]), A_s[gq], c.mg) <= tnew) ovf = true;
                     const bool anyovf = __ballot(ovf) != 0ull;
                     if (lane == 0) {
                         tcnt[gq] = keepn;
@@ -685,11 +744,12 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
         for (int gq = wv; gq < ng; gq += NT / 64) {
             const int qq = qid_s[gq];
             const float t = fminf(thr_s[gq], __hip_atomic_load(&wk.thr[qq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            const float Aq = A_s[gq];
             const int cntk = tcnt[gq];
             int nout = 0;
             for (int base = 0; base < cntk; base += 64) {
                 const int i = base + lane;
-                const bool f = i < cntk && key_dist(topk[gq * c.kc + i]) * (1.f - c.mg.c_final) <= t;
+                const bool f = i < cntk && dist_lower(key_dist(topk[gq * c.kc + i]), Aq, c.mg) <= t;
                 nout += __popcll(__ballot(f));
             }
             int basepos = 0;
@@ -699,7 +759,7 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
             for (int base = 0; base < cntk; base += 64) {
                 const int i = base + lane;
                 const uint64_t key = i < cntk ? topk[gq * c.kc + i] : KEY_MAX;
-                const bool f = i < cntk && key_dist(key) * (1.f - c.mg.c_final) <= t;
+                const bool f = i < cntk && dist_lower(key_dist(key), Aq, c.mg) <= t;
                 const uint64_t bal = __ballot(f);
                 const int rk = __popcll(bal & ((1ull << lane) - 1ull));
                 if (f) {
@@ -730,6 +790,7 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
 __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__restrict__ buf,
                                               const int32_t *__restrict__ buf_cnt,
                                               int32_t *__restrict__ flags, const float *__restrict__ qE,
+                                              const float *__restrict__ qA,
                                               const float *__restrict__ qraw, const float *__restrict__ raw,
                                               int d, int64_t *__restrict__ out_ids, float *__restrict__ out_d,
                                               unsigned long long *stats)
@@ -749,11 +810,12 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
     for (int i = threadIdx.x; i < P; i += NT) K[i] = i < n ? buf[q * c.capq + i] : KEY_MAX;
     __syncthreads();
     block_bitonic_sort(K, P);
-    const float thr = n >= c.k ? prune_threshold(key_dist(K[c.k - 1]), qE[q], c.mg) : INFINITY;
+    const float Aq = qA[q];
+    const float thr = n >= c.k ? prune_threshold(key_dist(K[c.k - 1]), qE[q], Aq, c.mg) : INFINITY;
     if (threadIdx.x == 0) nb_s = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += NT)
-        if (key_dist(K[i]) * (1.f - c.mg.c_final) <= thr) atomicMax(&nb_s, i + 1);
+        if (dist_lower(key_dist(K[i]), Aq, c.mg) <= thr) atomicMax(&nb_s, i + 1);
     __syncthreads();
     const int nb = nb_s;
     if (nb > 4096) {
@@ -916,7 +978,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
                    2 * align_up(sizeof(int32_t) * nlist) + align_up(sizeof(int32_t) * 8) +
                    align_up(sizeof(int64_t) * (nlist + 1)) + align_up(sizeof(int64_t) * (8 * c.ceil8 + 1));
     size_t need3 = 3 * align_up(sizeof(float) * nq) + align_up(sizeof(uint64_t) * nq * c.capq) +
-                   align_up(sizeof(unsigned long long) * 128);
+                   align_up(sizeof(unsigned long long) * 128) + align_up(sizeof(int));
     ctx->scratch[0].ensure(need0);
     ctx->scratch[1].ensure(need1);
     ctx->scratch[2].ensure(need2);
@@ -926,8 +988,8 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     float *qtail = c0.take<float>(nq * L);
     float *qE = c0.take<float>(nq);
     float *qn2 = c0.take<float>(nq);
-    float *spare = c0.take<float>(nq);
-    (void)spare;
+    float *qA = c0.take<float>(nq);
+    int *qbad = c3.take<int>(1);
     double *vnorm = c0.take<double>(nq);
     float *Sco = ctx->scratch[1].as<float>();
     int32_t *probes = c2.take<int32_t>(nq * np_max);
@@ -951,11 +1013,12 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         PANO_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 128, s));
     }
     // ---- query transform, tails and error bound
+    PANO_HIP(hipMemsetAsync(qbad, 0, sizeof(int), s));
     PANO_HIP(hipMemsetAsync(qy, 0, sizeof(float) * nq * ix->d_pad, s));
     launch_transform(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy, ix->d_pad, s);
     launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, s);
-    hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, vnorm, nq, ix->mg.kappa,
-                       ix->mg.e_max, qE);
+    hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, vnorm, qtail, L, nq, ix->mg,
+                       qE, qA, qbad);
     // ---- coarse probing
     if (nlist > 1) {
         launch_gemm_nt(q, nq, d, ix->cent.as<float>(), nlist, Sco, s);
@@ -992,7 +1055,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
 
     IndexView iv{ix->levels.as<float>(), ix->tails.as<float>(), ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
                  ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
-    QueryView qv{qy, qtail, qE, q};
+    QueryView qv{qy, qtail, qE, qA, q};
     if (!brute) {
         hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, s, c, iv, qv, probes, np_max,
                            ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
@@ -1010,15 +1073,18 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         const int P = next_pow2(c.capq);
         size_t shm = sizeof(uint64_t) * P;
         PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        hipLaunchKernelGGL(k_merge, dim3((unsigned)nq), dim3(NT), shm, s, c, buf, buf_cnt, qflags, qE, q,
+        hipLaunchKernelGGL(k_merge, dim3((unsigned)nq), dim3(NT), shm, s, c, buf, buf_cnt, qflags, qE, qA, q,
                            ix->raw.as<float>(), d, ids, dists, want_stats ? stats : nullptr);
         PANO_HIP(hipGetLastError());
     }
     if (want_stats) PANO_HIP(hipEventRecord(ev[3], s));
     // ---- exact fallback for queries whose bounded buffers overflowed
     std::vector<int32_t> hflags(nq);
+    int hbad = 0;
     PANO_HIP(hipMemcpyAsync(hflags.data(), qflags, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, s));
+    PANO_HIP(hipMemcpyAsync(&hbad, qbad, sizeof(int), hipMemcpyDeviceToHost, s));
     PANO_HIP(hipStreamSynchronize(s));
+    PANO_REQUIRE(hbad == 0, "a query has a non-finite value");
     int64_t nfall = 0;
     for (int64_t qi = 0; qi < nq; ++qi) {
         if (!(hflags[qi] & FLAG_OVERFLOW)) continue;

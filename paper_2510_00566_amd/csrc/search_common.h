@@ -101,13 +101,27 @@ __device__ inline float canon_dist_stream(const float *q_lds, const float *__res
     return (float)s;
 }
 
-// Pruning threshold tau^2 from the k-th best computed distance Dk (see the
-// error model: tau = E + rho (sqrt(Dk (1 + c_final)) + E)), with slack for
-// the FP32 evaluation of this formula itself.
-__device__ inline float prune_threshold(float Dk, float E, const Margins &mg)
+// Error model of a computed stored-frame distance Dt of a query with absolute
+// margin A (dot-product form): the exact value lies in
+// [(Dt - A)(1 - c_final), (Dt + A)(1 + c_final)].
+__device__ inline float dist_upper(float Dt, float A, const Margins &mg)
+{
+    return (Dt + A) * (1.f + mg.c_final) * (1.f + 1e-6f);
+}
+__device__ inline float dist_lower(float Dt, float A, const Margins &mg)
+{
+    return (Dt - A) * (1.f - mg.c_final);
+}
+
+// Pruning threshold tau^2 from the k-th best computed distance Dk: with
+// E = e_q + e_max (transform error) and rho the conditioning of the FP32
+// transform, tau = E + rho (sqrt(upper(Dk)) + E).  A candidate whose lower
+// bound exceeds tau^2 has a canonical distance above that of k committed
+// candidates.  Slack covers the FP32 evaluation of the formula itself.
+__device__ inline float prune_threshold(float Dk, float E, float A, const Margins &mg)
 {
     if (!(Dk < INFINITY)) return INFINITY;
-    float r = __builtin_sqrtf(Dk * (1.f + mg.c_final));
+    float r = __builtin_sqrtf(dist_upper(Dk, A, mg));
     float tau = E + mg.rho * (r + E);
     return tau * tau * (1.f + 1e-6f);
 }
