@@ -224,7 +224,7 @@ def main():
                    "level_width": w.level_width, "eps": 1.0},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_from_profiles(w.name),
-                     "kernel": "k_scan<true>", "bytes_per_launch": float(np.mean(scan_bytes)),
+                     "kernel": "k_scan_pruned", "bytes_per_launch": float(np.mean(scan_bytes)),
                      "ms_per_launch": float(np.mean(scan_ms))},
         "cpu_baseline": cpu,
         "bruteforce": bf,

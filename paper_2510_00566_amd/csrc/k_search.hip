@@ -393,13 +393,17 @@ __device__ inline void level_dots(const float *__restrict__ tile, int B, int kg_
 }
 
 template <bool PRUNE>
-__global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+__device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView &ix, const QueryView &qv,
+                                          const WorkView &wk)
 {
     __shared__ uint32_t pr[GMAX * 256];
     __shared__ float pS[GMAX * 256];
-    __shared__ uint8_t keep[GMAX * 256];
-    __shared__ uint64_t sbuf[NT / 64][SB_MAX];
-    __shared__ uint64_t topk[1024];
+    // dynamic LDS: [per-wave sort buffers: 4 x sbw][local top-kc: G x kc]; the
+    // walk's keep flags alias the sort buffers (never live at the same time)
+    extern __shared__ uint64_t dyn[];
+    const int sbw = next_pow2(c.kc + 64);
+    uint64_t *topk = dyn + 4 * sbw;
+    uint8_t *keep = reinterpret_cast<uint8_t *>(dyn);
     __shared__ int wave_tmp[NT / 64];
     __shared__ int qid_s[GMAX], tcnt[GMAX], ncand[GMAX];
     __shared__ float thr_s[GMAX], E_s[GMAX], A_s[GMAX], rqh_s[GMAX];
@@ -655,6 +659,33 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                             ++lv;
                             break;
                         }
+                        // Upper bound (the other side of Cauchy-Schwarz): UB =
+                        // ||q_h - x_h||^2 + (||q_t|| + ||x_t||)^2 never grows with
+                        // the level, and every later bound (any eps) stays below
+                        // it.  Once UB is under the threshold the pair cannot be
+                        // pruned any more: read the remaining levels without
+                        // further tests.
+                        if (!last && sh + (a + b) * (a + b) + eta <= th) {
+                            for (int lv2 = lv + 1; lv2 < g.L; ++lv2) {
+                                const int w42 = g.wp[lv2] >> 2;
+                                const float *x2 = blk + (int64_t)g.B * g.mp[lv2] + (int64_t)ss * g.wp[lv2];
+                                const float *q2 = qrow + g.mp[lv2];
+                                float part2 = 0.f;
+#pragma unroll 4
+                                for (int c4 = 0; c4 < w42; ++c4) {
+                                    const float4 x4 = *reinterpret_cast<const float4 *>(x2 + c4 * 4);
+                                    const float4 q4 = *reinterpret_cast<const float4 *>(q2 + c4 * 4);
+                                    float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                                    part2 = __builtin_fmaf(t0, t0, part2);
+                                    part2 = __builtin_fmaf(t1, t1, part2);
+                                    part2 = __builtin_fmaf(t2, t2, part2);
+                                    part2 = __builtin_fmaf(t3, t3, part2);
+                                }
+                                sh += part2;
+                            }
+                            lv = g.L;
+                            break;
+                        }
                     }
                     keep[p] = alive ? 1 : 0;
                     pS[p] = sh;
@@ -690,14 +721,33 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
             if (np_ > 0) {
                 for (int i = tid; i < np_; i += NT) atomicAdd(&ncand[pr[i] >> 8], 1);
                 __syncthreads();
-                volatile uint64_t *SB = &sbuf[wv][0];
+                volatile uint64_t *SB = dyn + wv * sbw;
                 for (int gq = wv; gq < ng; gq += NT / 64) {
                     if (ncand[gq] == 0) continue;
-                    const int cntk = tcnt[gq];
+                    int cntk = tcnt[gq];
                     uint64_t *tk = &topk[gq * c.kc];
                     for (int i = lane; i < cntk; i += 64) SB[i] = tk[i];
                     int napp = 0;
+                    float tnew = thr_s[gq];
+                    bool ovf = false;
+                    // sort what is buffered, keep the best kc, refresh d_k
+                    auto flush = [&]() {
+                        const int tot = cntk + napp;
+                        const int n2 = next_pow2(tot);
+                        for (int i = tot + lane; i < n2; i += 64) SB[i] = KEY_MAX;
+                        __builtin_amdgcn_wave_barrier();
+                        wave_bitonic_sort(SB, n2, lane);
+                        const int keepn = min(c.kc, tot);
+                        if (keepn >= c.k)
+                            tnew = fminf(tnew, prune_threshold(key_dist(SB[c.k - 1]), E_s[gq], A_s[gq], c.mg));
+                        for (int i = c.kc + lane; i < tot; i += 64)
+                            if (dist_lower(key_dist(SB[i]), A_s[gq], c.mg) <= tnew) ovf = true;
+                        cntk = keepn;
+                        napp = 0;
+                        __builtin_amdgcn_wave_barrier();
+                    };
                     for (int base = 0; base < np_; base += 64) {
+                        if (cntk + napp + 64 > sbw) flush();
                         const int i = base + lane;
                         bool f = false;
                         uint64_t key = 0;
@@ -713,22 +763,11 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
                         if (f) SB[cntk + napp + rk] = key;
                         napp += __popcll(bal);
                     }
-                    const int tot = cntk + napp;
-                    const int n2 = next_pow2(tot);
-                    for (int i = tot + lane; i < n2; i += 64) SB[i] = KEY_MAX;
-                    __builtin_amdgcn_wave_barrier();
-                    wave_bitonic_sort(SB, n2, lane);
-                    const int keepn = min(c.kc, tot);
-                    for (int i = lane; i < keepn; i += 64) tk[i] = SB[i];
-                    float tnew = thr_s[gq];
-                    if (keepn >= c.k)
-                        tnew = fminf(tnew, prune_threshold(key_dist(SB[c.k - 1]), E_s[gq], A_s[gq], c.mg));
-                    bool ovf = false;
-                    for (int i = c.kc + lane; i < tot; i += 64)
-                        if (dist_lower(key_dist(SB[i]), A_s[gq], c.mg) <= tnew) ovf = true;
+                    flush();
+                    for (int i = lane; i < cntk; i += 64) tk[i] = SB[i];
                     const bool anyovf = __ballot(ovf) != 0ull;
                     if (lane == 0) {
-                        tcnt[gq] = keepn;
+                        tcnt[gq] = cntk;
                         thr_s[gq] = tnew;
                         if (tnew < INFINITY) atomic_min_nonneg(&wk.thr[qid_s[gq]], tnew);
                         if (anyovf) atomicOr(&wk.flags[qid_s[gq]], FLAG_OVERFLOW);
@@ -781,6 +820,22 @@ __global__ __launch_bounds__(NT, 2) void k_scan(SearchConsts c, IndexView ix, Qu
         for (int lv = 0; lv < Lc; ++lv)
             if (my_lv[lv]) atomicAdd(&wk.stats[ST_LEVEL + lv], my_lv[lv]);
     }
+}
+
+// The pruned scan is tuned for three workgroups per CU (its time goes to the
+// latency of the per-pair level walks); the brute-force scan keeps its
+// registers (its time goes to the dense matrix-core phase).
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_scan_pruned(SearchConsts c,
+                                                                                            IndexView ix,
+                                                                                            QueryView qv,
+                                                                                            WorkView wk)
+{
+    scan_body<true>(c, ix, qv, wk);
+}
+
+__global__ __launch_bounds__(NT) void k_scan_brute(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    scan_body<false>(c, ix, qv, wk);
 }
 
 // ================================================================ merge
@@ -946,7 +1001,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     c.k = k;
     c.kc = next_pow2(std::max(2 * k, 16));
     int G = 16;
-    while (G > 1 && G * c.kc > 1024) G >>= 1;
+    while (G > 1 && G * c.kc > 2048) G >>= 1;
     if (prm && prm->group > 0) G = std::min(prm->group, G);
     c.G = G;
     c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1;
@@ -966,7 +1021,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
     const int seed_pool = std::min(1024, (prm && prm->seed_pool > 0) ? prm->seed_pool : 512);
     const int seed_cnt = std::min(256, std::max(k, (prm && prm->seed_count > 0) ? prm->seed_count : std::max(2 * k, 32)));
-    const int grid = (prm && prm->grid > 0) ? prm->grid : ctx->num_cu * 2;
+    const int grid = (prm && prm->grid > 0) ? prm->grid : ctx->num_cu * (brute ? 2 : 3);
     const int np_max = nprobe_dev ? nlist : std::min(nprobe_all, nlist);
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
 
@@ -1063,10 +1118,11 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     }
     if (want_stats) PANO_HIP(hipEventRecord(ev[1], s));
     WorkView wk{list_cnt, list_qoff, list_q, item_off, heads, thr, buf, buf_cnt, qflags, want_stats ? stats : nullptr};
+    const size_t scan_shm = sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
     if (brute)
-        hipLaunchKernelGGL(k_scan<false>, dim3(grid), dim3(NT), 0, s, c, iv, qv, wk);
+        hipLaunchKernelGGL(k_scan_brute, dim3(grid), dim3(NT), scan_shm, s, c, iv, qv, wk);
     else
-        hipLaunchKernelGGL(k_scan<true>, dim3(grid), dim3(NT), 0, s, c, iv, qv, wk);
+        hipLaunchKernelGGL(k_scan_pruned, dim3(grid), dim3(NT), scan_shm, s, c, iv, qv, wk);
     PANO_HIP(hipGetLastError());
     if (want_stats) PANO_HIP(hipEventRecord(ev[2], s));
     {
