@@ -136,11 +136,13 @@ typedef struct {
     int32_t seed_count;   /* of those, how many get their exact distance */
     int32_t grid;         /* persistent scan workgroups (0 = 4 per CU) */
     int32_t use_bf16;     /* 1: scan BF16 level slices (index built with BF16) */
-    int32_t reserved[6];
+    int32_t reserved[6];  /* [0]: refine a whole level on the matrix cores while at
+                             least this many pairs of a block survive (0 = 64) */
 } pano_search_params;
 
 /* Search flags. */
-#define PANO_SEARCH_STATS 1u  /* collect counters, readable with pano_stats_get */
+#define PANO_SEARCH_STATS 1u  /* collect counters, readable with pano_stats_get (runs eagerly) */
+#define PANO_SEARCH_EAGER 2u  /* do not replay the captured graph of the search */
 
 /*
  * search: k nearest neighbours of each query among the vectors of its probed

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libpanorama.so")
 PANO_OK, PANO_EINVAL, PANO_ENOMEM, PANO_EDEVICE, PANO_EUNSUPPORTED, PANO_EBUSY = range(6)
 PANO_F32, PANO_BF16 = 0, 1
 PANO_SEARCH_STATS = 1
+PANO_SEARCH_EAGER = 2
 
 
 class SearchParams(C.Structure):

@@ -405,7 +405,10 @@ pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const flo
             ix->mg.b0max2 = (float)(b0 * b0 * (1.0 + 1e-6));
             int wmax = 0;
             for (int l = 0; l < L; ++l) wmax = std::max(wmax, ix->wp[l]);
-            ix->mg.c_abs = (float)((gamma_n((double)wmax + L + 8) + 6.0 * std::ldexp(1.0, -24)) * 1.01);
+            // covers the dot-product form of any number of levels: per level
+            // gamma(w + 2)(R_q + R_x) for the product plus 4u (a_l^2 + b_l^2) for
+            // the level energies taken as differences of squared tails
+            ix->mg.c_abs = (float)((gamma_n((double)wmax + 4.0 * L + 16) + 6.0 * std::ldexp(1.0, -24)) * 1.01);
         }
         // lists: stable counting sort by assignment
         ix->list_len.assign(nlist, 0);

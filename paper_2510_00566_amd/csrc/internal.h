@@ -84,6 +84,43 @@ struct Margins {
     float b0max2;       // bound on the largest stored squared norm
 };
 
+// Up to ten buffers cleared (or set to a 32-bit pattern) by one kernel.
+struct FillList {
+    void *p[10];
+    int64_t n[10];  // counts of 32-bit words
+    uint32_t v[10];
+    int m;
+    void add(void *ptr, int64_t count, uint32_t val)
+    {
+        if (m >= 10) throw Error{PANO_EUNSUPPORTED, "too many buffers to clear"};
+        p[m] = ptr;
+        n[m] = count;
+        v[m] = val;
+        ++m;
+    }
+};
+
+// Identity of a captured search graph: every value baked into its nodes.
+struct GraphKey {
+    const void *ix, *q;
+    int64_t nq;
+    int k;
+    const void *npd;
+    int np_all;
+    float eps;
+    bool brute;
+    const void *ids, *dists;
+    int G, bpi, seed_pool, seed_cnt, grid;
+    const void *s0, *s1, *s2, *s3, *pinned;
+    bool operator==(const GraphKey &o) const
+    {
+        return ix == o.ix && q == o.q && nq == o.nq && k == o.k && npd == o.npd && np_all == o.np_all &&
+               eps == o.eps && brute == o.brute && ids == o.ids && dists == o.dists && G == o.G && bpi == o.bpi &&
+               seed_pool == o.seed_pool && seed_cnt == o.seed_cnt && grid == o.grid && s0 == o.s0 && s1 == o.s1 &&
+               s2 == o.s2 && s3 == o.s3 && pinned == o.pinned;
+    }
+};
+
 }  // namespace pano
 
 // ---------------------------------------------------------------- handles
@@ -91,6 +128,61 @@ struct pano_ctx {
     int device = 0;
     int num_cu = 256;
     pano::DevMem scratch[12];
+    // the context's own stream (default priority), events and graph cache
+    hipStream_t stream = nullptr, aux = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_in = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    pano::GraphKey graph_key{};
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+
+    hipStream_t work_stream()
+    {
+        if (!stream) {
+            if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
+                throw pano::Error{PANO_EDEVICE, "hipStreamCreate failed"};
+            for (auto &e : ev)
+                if (hipEventCreate(&e) != hipSuccess) throw pano::Error{PANO_EDEVICE, "hipEventCreate failed"};
+            if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess)
+                throw pano::Error{PANO_EDEVICE, "hipEventCreate failed"};
+            if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess)
+                throw pano::Error{PANO_EDEVICE, "hipStreamCreate failed"};
+        }
+        return stream;
+    }
+    void pinned_ensure(size_t b)
+    {
+        if (b <= pinned_bytes) return;
+        drop_graph();
+        if (pinned) (void)hipHostFree(pinned);
+        pinned = nullptr;
+        pinned_bytes = 0;
+        size_t nb = b + b / 4 + 256;
+        if (hipHostMalloc(&pinned, nb, hipHostMallocDefault) != hipSuccess)
+            throw pano::Error{PANO_ENOMEM, "hipHostMalloc failed"};
+        pinned_bytes = nb;
+    }
+    void drop_graph()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        graph_exec = nullptr;
+    }
+    ~pano_ctx()
+    {
+        drop_graph();
+        if (pinned) (void)hipHostFree(pinned);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (aux) (void)hipStreamDestroy(aux);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
 };
 
 struct pano_transform {

@@ -488,15 +488,6 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             const int gq = e >> 6, lv = e & 63;
             qtl_s[gq][lv] = lv < g.L ? qv.qtail[(int64_t)qid_s[gq] * g.L + lv] : 0.f;
         }
-        if (PRUNE) {
-            const int kg0 = g.wp[0] >> 2;
-            for (int e = tid; e < GMAX * 16; e += NT) {
-                const int gq = e >> 4, c4 = e & 15;
-                qrow_s[gq][c4] = (gq < ng && c4 < kg0)
-                                     ? *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_s[gq] * g.d_pad + c4 * 4)
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-        }
         __syncthreads();
         if (tid < ng) {
             // head energy of level 1: ||q_h||^2 = a_0^2 - a_1^2
@@ -515,6 +506,17 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                 thr_s[tid] = fminf(thr_s[tid], t);
                 ncand[tid] = 0;
             }
+            if (PRUNE) {
+                // level-1 query slices (the dense refinement of the previous
+                // block may have left another level's slices here)
+                const int kg0 = g.wp[0] >> 2;
+                for (int e = tid; e < GMAX * 16; e += NT) {
+                    const int gq = e >> 4, c4 = e & 15;
+                    qrow_s[gq][c4] = (gq < ng && c4 < kg0)
+                                         ? *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_s[gq] * g.d_pad + c4 * 4)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
             __syncthreads();
             // ---- dense phase on the matrix cores.  Lane (r16, kq) of wave wv
             // ends with the dot products of queries 4 kq + v (v = 0..3) with
@@ -526,6 +528,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             const bool wave_live = slot0 < cnt;
             uint32_t mask = 0;  // bit nt*4 + v: pair (query 4kq+v, slot slot0+nt*16+r16) kept
             float sval[16];
+            int lv_start = 1;  // first level left to the per-pair walk
             if (PRUNE) {
                 if (wave_live) level_dots(blk, g.B, g.wp[0] >> 2, &qrow_s[0][0], 16, slot0, lane, acc);
 #pragma unroll
@@ -552,6 +555,60 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                 if (tid == 0) {
                     my_bytes += (unsigned long long)cnt * (g.wp[0] * 4 + (g.L > 1 ? 8 : 4) + 4);
                     if (Lc > 0) my_lv[0] += (unsigned long long)cnt * ng;
+                }
+                // While the survivors stay dense (typically the candidates of a
+                // query's own cluster), keep refining whole levels on the matrix
+                // cores: one coalesced pass over the level tile serves all of
+                // them, instead of one gather per pair.
+                while (lv_start < g.L) {
+                    int alive_tot;
+                    (void)block_exclusive_scan(__popc(mask), wave_tmp, &alive_tot);
+                    if (alive_tot == 0 || alive_tot < c.dense_min || alive_tot * 4 < cnt) break;
+                    const int lv = lv_start;
+                    const int kgc = g.wp[lv] >> 2;
+                    if (kgc > 16) break;
+                    for (int e = tid; e < GMAX * 16; e += NT) {
+                        const int gq = e >> 4, c4 = e & 15;
+                        qrow_s[gq][c4] = (gq < ng && c4 < kgc)
+                                             ? *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_s[gq] * g.d_pad +
+                                                                                 g.mp[lv] + c4 * 4)
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                    __syncthreads();
+                    floatx4_t acc2[4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) acc2[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+                    if (wave_live)
+                        level_dots(blk + (int64_t)g.B * g.mp[lv], g.B, kgc, &qrow_s[0][0], 16, slot0, lane, acc2, g.wp[lv]);
+                    const bool last = lv + 1 == g.L;
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int s = slot0 + nt * 16 + r16;
+                        const bool valid = s < cnt;
+                        const float bl = valid ? tl[(int64_t)lv * g.B + s] : 0.f;
+                        const float bn = (valid && !last) ? tl[(int64_t)(lv + 1) * g.B + s] : 0.f;
+                        const float rxl = bl * bl - bn * bn;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int b = nt * 4 + v;
+                            if (!(mask & (1u << b))) continue;
+                            const int gq = 4 * kq + v;
+                            const float al = qtl_s[gq][lv], an = last ? 0.f : qtl_s[gq][lv + 1];
+                            const float sh = sval[b] + (al * al - an * an) + rxl - 2.f * acc2[nt][v];
+                            sval[b] = sh;
+                            const float dt = an - bn;
+                            const float lb = sh + dt * dt + c.one_m_eps2 * an * bn;
+                            const float eta = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + A_s[gq] +
+                                              c.mg.c_tail * (an + bn) * (an + bn);
+                            if (lb - eta > thr_s[gq]) mask &= ~(1u << b);
+                        }
+                    }
+                    if (tid == 0) {
+                        my_bytes += (unsigned long long)cnt * (g.wp[lv] * 4 + 8);
+                        if (lv < 64) my_lv[lv] += (unsigned long long)alive_tot;
+                    }
+                    ++lv_start;
+                    __syncthreads();
                 }
             } else {
                 // brute force: every level, query rows staged per level
@@ -619,7 +676,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             // after level, until its bound exceeds the threshold or the last
             // level is read (no barrier between levels; the Update and
             // Consolidate phases of Section 6.1 run once, after the walk)
-            if (PRUNE && g.L > 1) {
+            if (PRUNE && lv_start < g.L) {
                 const int np_ = npairs_s;
                 unsigned long long my_dims = 0;
                 for (int p = tid; p < np_; p += NT) {
@@ -631,7 +688,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     const float *qt = &qtl_s[gq][0];
                     float sh = pS[p];
                     bool alive = true;
-                    int lv = 1;
+                    int lv = lv_start;
                     for (; lv < g.L; ++lv) {
                         const int w4 = g.wp[lv] >> 2;
                         const float *x = blk + (int64_t)g.B * g.mp[lv] + (int64_t)ss * g.wp[lv];
@@ -690,8 +747,8 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     keep[p] = alive ? 1 : 0;
                     pS[p] = sh;
                     if (wk.stats) {
-                        for (int v = 1; v < lv && v < 64; ++v) atomicAdd(&my_lv[v], 1ull);
-                        my_dims += (unsigned long long)(g.mp[lv < g.L ? lv : g.L] - g.mp[1]);
+                        for (int v = lv_start; v < lv && v < 64; ++v) atomicAdd(&my_lv[v], 1ull);
+                        my_dims += (unsigned long long)(g.mp[lv < g.L ? lv : g.L] - g.mp[lv_start]);
                     }
                 }
                 if (wk.stats && my_dims) atomicAdd(&sparse_bytes_s, my_dims * 4ull);
@@ -969,6 +1026,17 @@ __global__ __launch_bounds__(NT) void k_fallback_select(const uint64_t *__restri
     }
 }
 
+// ================================================================ buffer clearing
+__global__ void k_fill_multi(FillList f)
+{
+    for (int sgm = 0; sgm < f.m; ++sgm) {
+        uint32_t *p = reinterpret_cast<uint32_t *>(f.p[sgm]);
+        const uint32_t v = f.v[sgm];
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.n[sgm]; i += (int64_t)gridDim.x * blockDim.x)
+            p[i] = v;
+    }
+}
+
 }  // namespace pano
 
 // ================================================================ host side
@@ -1009,6 +1077,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     c.nlist = nlist;
     c.ceil8 = (nlist + 7) / 8;
     c.prune = brute ? 0 : 1;
+    c.dense_min = (prm && prm->reserved[0] > 0) ? prm->reserved[0] : 64;
     c.eps = eps;
     c.one_m_eps2 = 2.f * (1.f - eps);
     c.mg = ix->mg;
@@ -1061,86 +1130,127 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     uint64_t *buf = c3.take<uint64_t>(nq * c.capq);
     unsigned long long *stats = c3.take<unsigned long long>(128);
 
-    hipEvent_t ev[5];
-    if (want_stats) {
-        for (auto &e : ev) PANO_HIP(hipEventCreate(&e));
-        PANO_HIP(hipEventRecord(ev[0], s));
-        PANO_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 128, s));
-    }
-    // ---- query transform, tails and error bound
-    PANO_HIP(hipMemsetAsync(qbad, 0, sizeof(int), s));
-    PANO_HIP(hipMemsetAsync(qy, 0, sizeof(float) * nq * ix->d_pad, s));
-    launch_transform(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy, ix->d_pad, s);
-    launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, s);
-    hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, vnorm, qtail, L, nq, ix->mg,
-                       qE, qA, qbad);
-    // ---- coarse probing
-    if (nlist > 1) {
-        launch_gemm_nt(q, nq, d, ix->cent.as<float>(), nlist, Sco, s);
-        launch_sqnorms(q, nq, d, qn2, s);
-        const double u = std::ldexp(1.0, -24);
-        auto gam = [&](double nn) { return nn * u / (1.0 - nn * u); };
-        const float c_co = (float)((gam(d / 64.0 + 8) + gam(32.0 + (d + 31) / 32 + 2) + 4 * u) * 1.1);
-        const size_t per_wave = coarse_lds_per_wave(nlist, d);
-        int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
-        const size_t shm = per_wave * wpb;
-        PANO_REQUIRE(shm <= 160 * 1024, "nlist too large for the coarse step");
-        PANO_HIP(hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), shm, s, Sco, qn2,
-                           ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq, nprobe_dev,
-                           nprobe_all, c_co, np_max, probes, npq);
-    } else {
-        hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, np_max, probes, npq);
-    }
-    PANO_HIP(hipGetLastError());
-    // ---- work decomposition
-    PANO_HIP(hipMemsetAsync(list_cnt, 0, sizeof(int32_t) * nlist, s));
-    PANO_HIP(hipMemsetAsync(list_fill, 0, sizeof(int32_t) * nlist, s));
-    PANO_HIP(hipMemsetAsync(heads, 0, sizeof(int32_t) * 8, s));
-    const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
-    hipLaunchKernelGGL(k_wl_count, dim3(wl_grid), dim3(256), 0, s, nq, np_max, probes, npq, list_cnt);
-    hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, s, nlist, c.ceil8, c.G, c.bpi, list_cnt,
-                       ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
-    hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, s, nq, np_max, probes, npq, list_qoff,
-                       list_fill, list_q);
-    PANO_HIP(hipMemsetD32Async((hipDeviceptr_t)thr, 0x7f800000, nq, s));
-    PANO_HIP(hipMemsetAsync(buf_cnt, 0, sizeof(int32_t) * nq, s));
-    PANO_HIP(hipMemsetAsync(qflags, 0, sizeof(int32_t) * nq, s));
-    PANO_HIP(hipGetLastError());
-
+    // ---- launch geometry that does not depend on the stream
+    const double u_ = std::ldexp(1.0, -24);
+    auto gam = [&](double nn) { return nn * u_ / (1.0 - nn * u_); };
+    const float c_co = (float)((gam(d / 64.0 + 8) + gam(32.0 + (d + 31) / 32 + 2) + 4 * u_) * 1.1);
+    const size_t per_wave = coarse_lds_per_wave(nlist, d);
+    const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
+    const size_t coarse_shm = per_wave * wpb;
+    PANO_REQUIRE(nlist == 1 || coarse_shm <= 160 * 1024, "nlist too large for the coarse step");
+    const size_t merge_shm = sizeof(uint64_t) * next_pow2(c.capq);
+    const size_t scan_shm = sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
+    if (nlist > 1)
+        PANO_HIP(hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_shm));
+    PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_shm));
+    ctx->pinned_ensure(sizeof(int32_t) * (nq + 1));
+    int32_t *h_flags = reinterpret_cast<int32_t *>(ctx->pinned);
     IndexView iv{ix->levels.as<float>(), ix->tails.as<float>(), ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
                  ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
     QueryView qv{qy, qtail, qE, qA, q};
-    if (!brute) {
-        hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, s, c, iv, qv, probes, np_max,
-                           ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
+    WorkView wk{list_cnt, list_qoff, list_q, item_off, heads, thr, buf, buf_cnt, qflags, nullptr};
+
+    // Every device step of one search, in order, on stream st.  No memset
+    // nodes: buffers are cleared by a fill kernel so the sequence can be
+    // captured into a graph.
+    auto enqueue = [&](hipStream_t st, bool stats_on) {
+        FillList fl{};
+        fl.add(qbad, 1, 0u);
+        fl.add(qy, nq * (int64_t)ix->d_pad, 0u);
+        fl.add(list_cnt, nlist, 0u);
+        fl.add(list_fill, nlist, 0u);
+        fl.add(heads, 8, 0u);
+        fl.add(thr, nq, 0x7f800000u);
+        fl.add(buf_cnt, nq, 0u);
+        fl.add(qflags, nq, 0u);
+        if (stats_on) fl.add(stats, 256, 0u);
+        hipLaunchKernelGGL(k_fill_multi, dim3(256), dim3(256), 0, st, fl);
+        // query transform, tails and error bound
+        launch_transform(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy, ix->d_pad, st);
+        launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, st);
+        hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, vnorm, qtail, L, nq,
+                           ix->mg, qE, qA, qbad);
+        // coarse probing
+        if (nlist > 1) {
+            launch_gemm_nt(q, nq, d, ix->cent.as<float>(), nlist, Sco, st);
+            launch_sqnorms(q, nq, d, qn2, st);
+            hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
+                               qn2, ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq,
+                               nprobe_dev, nprobe_all, c_co, np_max, probes, npq);
+        } else {
+            hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, np_max, probes,
+                               npq);
+        }
+        // threshold seeding (needs only the probes) runs beside the work
+        // decomposition on the context's second stream
+        if (!brute) {
+            PANO_HIP(hipEventRecord(ctx->ev_fork, st));
+            PANO_HIP(hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0));
+            hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, ctx->aux, c, iv, qv, probes, np_max,
+                               ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
+            PANO_HIP(hipEventRecord(ctx->ev_join, ctx->aux));
+        }
+        // work decomposition
+        const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
+        hipLaunchKernelGGL(k_wl_count, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_cnt);
+        hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi, list_cnt,
+                           ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
+        hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_qoff, list_fill,
+                           list_q);
+        if (!brute) PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+        if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[1], st));
+        WorkView w2 = wk;
+        w2.stats = stats_on ? stats : nullptr;
+        if (brute)
+            hipLaunchKernelGGL(k_scan_brute, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+        else
+            hipLaunchKernelGGL(k_scan_pruned, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+        if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[2], st));
+        hipLaunchKernelGGL(k_merge, dim3((unsigned)nq), dim3(NT), merge_shm, st, c, buf, buf_cnt, qflags, qE, qA, q,
+                           ix->raw.as<float>(), d, ids, dists, stats_on ? stats : nullptr);
+        if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[3], st));
+        PANO_HIP(hipMemcpyAsync(h_flags, qflags, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
+        PANO_HIP(hipMemcpyAsync(h_flags + nq, qbad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         PANO_HIP(hipGetLastError());
+    };
+
+    // The search runs on the context's own stream, ordered after the caller's.
+    hipStream_t ws = ctx->work_stream();
+    PANO_HIP(hipEventRecord(ctx->ev_in, s));
+    PANO_HIP(hipStreamWaitEvent(ws, ctx->ev_in, 0));
+    if (want_stats) {
+        PANO_HIP(hipEventRecord(ctx->ev[0], ws));
+        enqueue(ws, true);
+    } else if (!(flags & PANO_SEARCH_EAGER)) {
+        GraphKey key{ix, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
+                     ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p, ctx->pinned};
+        if (!ctx->graph_exec || !(ctx->graph_key == key)) {
+            ctx->drop_graph();
+            hipGraph_t graph;
+            PANO_HIP(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue(ws, false);
+            } catch (...) {
+                hipGraph_t dummy;
+                (void)hipStreamEndCapture(ws, &dummy);
+                throw;
+            }
+            PANO_HIP(hipStreamEndCapture(ws, &graph));
+            hipError_t ie = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            PANO_HIP(ie);
+            ctx->graph_key = key;
+        }
+        PANO_HIP(hipGraphLaunch(ctx->graph_exec, ws));
+    } else {
+        enqueue(ws, false);
     }
-    if (want_stats) PANO_HIP(hipEventRecord(ev[1], s));
-    WorkView wk{list_cnt, list_qoff, list_q, item_off, heads, thr, buf, buf_cnt, qflags, want_stats ? stats : nullptr};
-    const size_t scan_shm = sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
-    if (brute)
-        hipLaunchKernelGGL(k_scan_brute, dim3(grid), dim3(NT), scan_shm, s, c, iv, qv, wk);
-    else
-        hipLaunchKernelGGL(k_scan_pruned, dim3(grid), dim3(NT), scan_shm, s, c, iv, qv, wk);
-    PANO_HIP(hipGetLastError());
-    if (want_stats) PANO_HIP(hipEventRecord(ev[2], s));
-    {
-        const int P = next_pow2(c.capq);
-        size_t shm = sizeof(uint64_t) * P;
-        PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        hipLaunchKernelGGL(k_merge, dim3((unsigned)nq), dim3(NT), shm, s, c, buf, buf_cnt, qflags, qE, qA, q,
-                           ix->raw.as<float>(), d, ids, dists, want_stats ? stats : nullptr);
-        PANO_HIP(hipGetLastError());
-    }
-    if (want_stats) PANO_HIP(hipEventRecord(ev[3], s));
+    PANO_HIP(hipStreamSynchronize(ws));
+    std::vector<int32_t> hflags(h_flags, h_flags + nq);
+    PANO_REQUIRE(h_flags[nq] == 0, "a query has a non-finite value");
+    s = ws;
     // ---- exact fallback for queries whose bounded buffers overflowed
-    std::vector<int32_t> hflags(nq);
-    int hbad = 0;
-    PANO_HIP(hipMemcpyAsync(hflags.data(), qflags, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, s));
-    PANO_HIP(hipMemcpyAsync(&hbad, qbad, sizeof(int), hipMemcpyDeviceToHost, s));
-    PANO_HIP(hipStreamSynchronize(s));
-    PANO_REQUIRE(hbad == 0, "a query has a non-finite value");
+
     int64_t nfall = 0;
     for (int64_t qi = 0; qi < nq; ++qi) {
         if (!(hflags[qi] & FLAG_OVERFLOW)) continue;
@@ -1166,8 +1276,8 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         PANO_HIP(hipStreamSynchronize(s));
     }
     if (want_stats) {
-        PANO_HIP(hipEventRecord(ev[4], s));
-        PANO_HIP(hipEventSynchronize(ev[4]));
+        PANO_HIP(hipEventRecord(ctx->ev[4], s));
+        PANO_HIP(hipEventSynchronize(ctx->ev[4]));
         std::vector<unsigned long long> hs(128);
         PANO_HIP(hipMemcpy(hs.data(), stats, sizeof(unsigned long long) * 128, hipMemcpyDeviceToHost));
         pano_stats_t &st = ix->stats;
@@ -1186,16 +1296,15 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         st.candidates = st.level_reads[0];
         st.dims_read = dims;
         float t;
-        PANO_HIP(hipEventElapsedTime(&t, ev[0], ev[4]));
+        PANO_HIP(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[4]));
         st.ms_total = t;
-        PANO_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+        PANO_HIP(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
         st.ms_prep = t;
-        PANO_HIP(hipEventElapsedTime(&t, ev[1], ev[2]));
+        PANO_HIP(hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[2]));
         st.ms_scan = t;
-        PANO_HIP(hipEventElapsedTime(&t, ev[2], ev[3]));
+        PANO_HIP(hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3]));
         st.ms_merge = t;
         for (int i = 0; i < 6; ++i) st.scan_cycles[i] = (int64_t)hs[ST_CYCLES + i];
-        for (auto &e : ev) (void)hipEventDestroy(e);
     }
 }
 

@@ -39,6 +39,7 @@ struct SearchConsts {
     int nlist;
     int ceil8;         // ceil(nlist / 8)
     int prune;         // 1 = pruned scan, 0 = brute force
+    int dense_min;     // refine a level densely while at least this many pairs survive
     float eps;
     float one_m_eps2;  // 2 (1 - eps)
     Margins mg;

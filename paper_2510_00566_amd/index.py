@@ -108,11 +108,13 @@ class Params:
     seed_count: int = 0
     grid: int = 0
     use_bf16: int = 0
+    dense_min: int = 0
 
     def c(self):
         p = L.SearchParams()
         p.group, p.blocks_per_item, p.seed_pool = self.group, self.blocks_per_item, self.seed_pool
         p.seed_count, p.grid, p.use_bf16 = self.seed_count, self.grid, self.use_bf16
+        p.reserved[0] = self.dense_min
         return p
 
 
@@ -142,7 +144,7 @@ class Index:
         return ids, dists
 
     def search(self, q_dev, k: int, nprobe=1, eps: float = 1.0, params: Params | None = None,
-               stats: bool = False, stream=None, out=None):
+               stats: bool = False, stream=None, out=None, eager: bool = False):
         import torch
         ids, dists = out if out is not None else self._outs(q_dev, k)
         np_dev = None
@@ -152,13 +154,14 @@ class Index:
         else:
             np_all = int(nprobe)
         prm = params.c() if params is not None else None
+        flags = (L.PANO_SEARCH_STATS if stats else 0) | (L.PANO_SEARCH_EAGER if eager else 0)
         L.check(L.lib().pano_search(self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all, float(eps),
                                     _ptr(ids), _ptr(dists), C.byref(prm) if prm is not None else None,
-                                    L.PANO_SEARCH_STATS if stats else 0, _stream_handle(stream)))
+                                    flags, _stream_handle(stream)))
         return ids, dists
 
     def search_bruteforce(self, q_dev, k: int, nprobe=1, params: Params | None = None, stats: bool = False,
-                          stream=None, out=None):
+                          stream=None, out=None, eager: bool = False):
         import torch
         ids, dists = out if out is not None else self._outs(q_dev, k)
         np_dev = None
@@ -170,7 +173,8 @@ class Index:
         prm = params.c() if params is not None else None
         L.check(L.lib().pano_search_bruteforce(self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all,
                                                _ptr(ids), _ptr(dists), C.byref(prm) if prm is not None else None,
-                                               L.PANO_SEARCH_STATS if stats else 0, _stream_handle(stream)))
+                                               (L.PANO_SEARCH_STATS if stats else 0) | (L.PANO_SEARCH_EAGER if eager else 0),
+                                               _stream_handle(stream)))
         return ids, dists
 
     def info(self) -> dict:

@@ -67,3 +67,64 @@ def test_ivf_gist_shape_parity(torch_cuda):
     assert st["dims_read"] < 0.5 * st["candidates"] * w.d
     bi, bd = case["idx"].search_bruteforce(qd, w.k, nprobe=w.nprobe)
     gc.compare(bi.cpu().numpy(), bd.cpu().numpy(), ref_i, ref_d)
+
+
+@gpu
+def test_graph_replay_matches_eager(torch_cuda):
+    """The search is captured into a HIP graph on first use and replayed; every
+    replay (with eager work and synchronisation in between) must equal the
+    eager result bit for bit."""
+    from tests import gpu_cases as gc
+    w = synth.scaled(synth.WORKLOADS["ivf_gist_like"], n=12000, nq=20, nlist=16, nprobe=3, n_clusters=16)
+    w.d = 200
+    w.level_width = 20
+    case = gc.build_case(w)
+    q = torch_cuda.from_numpy(case["data"]["q"]).cuda()
+    ids = torch_cuda.empty((w.nq, w.k), dtype=torch_cuda.int64, device="cuda")
+    dd = torch_cuda.empty((w.nq, w.k), dtype=torch_cuda.float32, device="cuda")
+    ei, ed = case["idx"].search(q, w.k, nprobe=w.nprobe, eager=True)
+    for rep in range(4):
+        case["idx"].search(q, w.k, nprobe=w.nprobe, out=(ids, dd))  # graph replay
+        torch_cuda.cuda.synchronize()
+        assert torch_cuda.equal(ids, ei) and torch_cuda.equal(dd, ed), rep
+        ei2, ed2 = case["idx"].search(q, w.k, nprobe=w.nprobe, eager=True, stats=True)
+        assert torch_cuda.equal(ei2, ei)
+    ref_i, ref_d = gc.oracle_answer(case, case["data"]["q"], w.nprobe, w.k)
+    gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
+
+
+PARAM_GRID = [
+    dict(),
+    dict(blocks_per_item=2),
+    dict(blocks_per_item=4, dense_min=32),
+    dict(blocks_per_item=3, group=8),
+    dict(blocks_per_item=8, group=4, seed_pool=256, seed_count=16),
+    dict(blocks_per_item=4, dense_min=1 << 30),
+    dict(blocks_per_item=2, group=1, grid=7),
+]
+
+
+@gpu
+@pytest.mark.parametrize("kw", PARAM_GRID, ids=[str(sorted(k.items())) for k in PARAM_GRID])
+def test_parity_across_search_knobs(torch_cuda, kw):
+    """Every setting of the search knobs (work-item size, group size, seeding,
+    dense-refinement threshold, grid) returns the oracle's answer."""
+    from tests import gpu_cases as gc
+    from paper_2510_00566_amd.index import Params
+    key = "knob_case"
+    if not hasattr(test_parity_across_search_knobs, key):
+        w = synth.scaled(synth.WORKLOADS["ivf_gist_like"], n=30000, nq=40, nlist=24, nprobe=5, n_clusters=24)
+        w.d = 240
+        w.level_width = 24
+        case = gc.build_case(w)
+        ref = gc.oracle_answer(case, case["data"]["q"], w.nprobe, w.k)
+        setattr(test_parity_across_search_knobs, key, (w, case, ref))
+    w, case, (ref_i, ref_d) = getattr(test_parity_across_search_knobs, key)
+    q = torch_cuda.from_numpy(case["data"]["q"]).cuda()
+    p = Params(**kw)
+    ids, dd = case["idx"].search(q, w.k, nprobe=w.nprobe, params=p)
+    gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
+    ids2, dd2 = case["idx"].search(q, w.k, nprobe=w.nprobe, params=p, eager=True)
+    gc.compare(ids2.cpu().numpy(), dd2.cpu().numpy(), ref_i, ref_d)
+    bi, bd = case["idx"].search_bruteforce(q, w.k, nprobe=w.nprobe, params=p)
+    gc.compare(bi.cpu().numpy(), bd.cpu().numpy(), ref_i, ref_d)
