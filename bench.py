@@ -41,7 +41,7 @@ def scan_source_hash() -> str:
 def traffic_from_profiles(workload: str):
     """HBM bytes per scan launch from the committed rocprofv3 counter summary,
     if it was taken on the current scan kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_scan_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"k_scan_pruned_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--transform", default="residual", choices=["residual", "data"])
     ap.add_argument("--tune", action="store_true", help="run the autotuner and store its choice")
     ap.add_argument("--no-secondary", action="store_true", help="skip the data-fit PCA comparison")
+    ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no graph replay)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the search path here is single-GPU "
@@ -73,6 +76,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        a = torch.ones(256 * 2 ** 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}))
+        return
     from paper_2510_00566_amd import synth
     from paper_2510_00566_amd import autotune
     from paper_2510_00566_amd.index import Context, Index, Params, Transform, ivf_assign
@@ -128,7 +139,7 @@ def main():
     dists = torch.empty((w.nq, w.k), dtype=torch.float32, device="cuda")
 
     def step(stats=False):
-        idx.search(qd, w.k, nprobe=npd, eps=1.0, params=prm, stats=stats, out=(ids, dists))
+        idx.search(qd, w.k, nprobe=npd, eps=1.0, params=prm, stats=stats, out=(ids, dists), eager=args.eager)
 
     for _ in range(args.warmup):
         step()
