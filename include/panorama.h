@@ -97,8 +97,11 @@ void pano_transform_free(pano_transform *tf);
 /*
  * ivf_assign: the coarse quantiser of IVF (Section 6.1): Lloyd's k-means in
  * raw space.  x_dev [n][d]; centroids_dev [nlist][d] and assign_dev [n]
- * (int32) are outputs.  Initial centroids are nlist distinct rows drawn with
- * `seed`; each of `iters` iterations assigns every row to its nearest centroid
+ * (int32) are outputs.  Initial centroids come from greedy k-means++ (D^2
+ * sampling of 2 + ln(nlist) candidates per step, keeping the one that lowers
+ * the potential most) over a seeded sample of max(65536, min(262144,
+ * 64 nlist)) rows (all rows if n is smaller), drawn with `seed`; each of
+ * `iters` iterations assigns every row to its nearest centroid
  * on the GPU and recomputes the means (an empty cluster keeps its centroid).
  * The final assignment pass uses the same nearest-centroid rule.  nlist = 1
  * gives the flat index (centroid = mean, every row in list 0).
@@ -134,8 +137,13 @@ typedef struct {
     int32_t blocks_per_item; /* blocks of a list scanned by one work item */
     int32_t seed_pool;    /* candidates of the nearest list ranked to seed d_k */
     int32_t seed_count;   /* of those, how many get their exact distance */
-    int32_t grid;         /* persistent scan workgroups (0 = 4 per CU) */
-    int32_t use_bf16;     /* 1: scan BF16 level slices (index built with BF16) */
+    int32_t grid;         /* persistent scan workgroups (0 = 3 per CU pruned,
+                             2 per CU brute force) */
+    int32_t use_bf16;     /* 1: the pruned scan reads the bfloat16 level slices
+                             (index built with PANO_BF16, else EINVAL); its
+                             bounds carry a certified bfloat16 margin and every
+                             survivor is rescored from the FP32 slices, so the
+                             result equals the FP32 search's */
     int32_t reserved[6];  /* [0]: refine a whole level on the matrix cores while at
                              least this many pairs of a block survive (0 = 64) */
 } pano_search_params;

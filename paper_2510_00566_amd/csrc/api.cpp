@@ -79,7 +79,8 @@ static void compute_margins(pano_index *ix, const std::vector<float> &T32)
     if (delta >= 0.5) throw Error{PANO_EINVAL, "transform is not orthonormal in FP32"};
     const double smax = std::sqrt(1.0 + delta), smin = std::sqrt(1.0 - delta);
     const int tk = 32;
-    const double gT = gamma_n((double)tk + (d + tk - 1) / tk + 2);
+    // counts doubled: the bound must hold if the matrix cores' adders truncate
+    const double gT = gamma_n(2.0 * ((double)tk + (d + tk - 1) / tk + 2));
     const double kappa = (gT * nabs * (1.0 + u) + smax * u * (1.0 + u)) * (1.0 + 1e-6);
     const double up = u * (1.0 + 1e-5);
     const double rho = (smax / smin) * std::sqrt((1.0 + up) / (1.0 - up)) * (1.0 + 1e-7);
@@ -407,8 +408,17 @@ pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const flo
             for (int l = 0; l < L; ++l) wmax = std::max(wmax, ix->wp[l]);
             // covers the dot-product form of any number of levels: per level
             // gamma(w + 2)(R_q + R_x) for the product plus 4u (a_l^2 + b_l^2) for
-            // the level energies taken as differences of squared tails
-            ix->mg.c_abs = (float)((gamma_n((double)wmax + 4.0 * L + 16) + 6.0 * std::ldexp(1.0, -24)) * 1.01);
+            // the level energies taken as differences of squared tails.  The
+            // counts are doubled so that the bound also holds if the matrix
+            // cores' adders truncate instead of rounding to nearest.
+            ix->mg.c_abs = (float)((gamma_n(2.0 * (wmax + 4.0 * L + 16)) + 6.0 * std::ldexp(1.0, -24)) * 1.01);
+            // bfloat16 scan: 2w products per level (q = q_hi + q_lo), the level
+            // energies of the rounded rows summed in FP32, and the split error
+            // 2 u_b^2 |<q, x~>| <= u_b^2 (R_q + R_x~)
+            const double ub = std::ldexp(1.0, -8);
+            ix->c_abs_bf = (float)((gamma_n(2.0 * (2.0 * wmax + 4.0 * L + 16)) + 6.0 * std::ldexp(1.0, -24) +
+                                    ub * ub * (1.0 + ub)) *
+                                   1.01);
         }
         // lists: stable counting sort by assignment
         ix->list_len.assign(nlist, 0);

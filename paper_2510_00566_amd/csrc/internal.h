@@ -110,13 +110,14 @@ struct GraphKey {
     float eps;
     bool brute;
     const void *ids, *dists;
-    int G, bpi, seed_pool, seed_cnt, grid;
+    int G, bpi, seed_pool, seed_cnt, grid, dense_min, bf16;
     const void *s0, *s1, *s2, *s3, *pinned;
     bool operator==(const GraphKey &o) const
     {
         return ix == o.ix && q == o.q && nq == o.nq && k == o.k && npd == o.npd && np_all == o.np_all &&
                eps == o.eps && brute == o.brute && ids == o.ids && dists == o.dists && G == o.G && bpi == o.bpi &&
-               seed_pool == o.seed_pool && seed_cnt == o.seed_cnt && grid == o.grid && s0 == o.s0 && s1 == o.s1 &&
+               seed_pool == o.seed_pool && seed_cnt == o.seed_cnt && grid == o.grid && dense_min == o.dense_min &&
+               bf16 == o.bf16 && s0 == o.s0 && s1 == o.s1 &&
                s2 == o.s2 && s3 == o.s3 && pinned == o.pinned;
     }
 };
@@ -203,6 +204,7 @@ struct pano_index {
         list_len_d, meta;
     pano::Margins mg{};
     double transform_err_max = 0.0, sigma_ratio = 1.0;
+    float c_abs_bf = 0.f;  // c_abs of the bfloat16 scan (two query terms per product, u_b^2 split error)
     pano_stats_t stats{};
 };
 

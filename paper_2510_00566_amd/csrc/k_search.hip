@@ -218,6 +218,7 @@ __global__ void k_wl_fill(int64_t nq, int np_max, const int32_t *__restrict__ pr
 // ================================================================ index views
 struct IndexView {
     const float *levels;
+    const uint16_t *levels16;  // bfloat16 copy of the level tiles (same layout) or null
     const float *tails;   // [block][level][B]
     const int32_t *ids;   // [block][B]
     const int32_t *blk_cnt;
@@ -392,7 +393,90 @@ __device__ inline void level_dots(const float *__restrict__ tile, int B, int kg_
     for (int nt = 0; nt < 4; ++nt) acc[nt] += part[nt];
 }
 
-template <bool PRUNE>
+// The same dot products from the bfloat16 copy x~ of the tiles on
+// v_mfma_f32_16x16x16bf16_1k.  Lane (r, q) feeds dimensions 16t + 4q .. +3 of
+// query r and of slot r.  The FP32 query is split into q_hi + q_lo, both
+// bfloat16 (|q - q_hi - q_lo| <= u_b^2 |q|), so the products are those with
+// x~ up to a u_b^2 relative term.  Each lane also sums the squares of the x~
+// values it feeds; ex[nt] ends as ||x~_level||^2 of slot nt*16 + r16 (summed
+// over the four lanes that share r16).
+typedef short shortx4_t __attribute__((ext_vector_type(4)));
+__device__ inline void level_dots_bf16(const uint16_t *__restrict__ tile, int B, int kg_count, const float4 *qrows,
+                                       int qstride, int wave_slot0, int lane, floatx4_t acc[4], float ex[4],
+                                       int row_w = 0)
+{
+    const int r16 = lane & 15, kq = lane >> 4;
+    floatx4_t part[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        part[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        ex[nt] = 0.f;
+    }
+    for (int t = 0; 4 * t < kg_count; ++t) {
+        const int kg = 4 * t + kq;
+        const bool ok = kg < kg_count;
+        const float4 qf = ok ? qrows[r16 * qstride + kg] : make_float4(0.f, 0.f, 0.f, 0.f);
+        shortx4_t qh, ql;
+        {
+            const float qv[4] = {qf.x, qf.y, qf.z, qf.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint16_t h = bf16_bits_rne(qv[e]);
+                qh[e] = (short)h;
+                ql[e] = (short)bf16_bits_rne(qv[e] - bf16_to_f32(h));
+            }
+        }
+        uint2 xr[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int slot = wave_slot0 + nt * 16 + r16;
+            xr[nt] = make_uint2(0u, 0u);
+            if (ok)
+                xr[nt] = row_w ? *reinterpret_cast<const uint2 *>(tile + (int64_t)slot * row_w + kg * 4)
+                               : *reinterpret_cast<const uint2 *>(tile + ((int64_t)kg * B + slot) * 4);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            shortx4_t xa;
+            xa[0] = (short)(xr[nt].x & 0xffffu);
+            xa[1] = (short)(xr[nt].x >> 16);
+            xa[2] = (short)(xr[nt].y & 0xffffu);
+            xa[3] = (short)(xr[nt].y >> 16);
+            part[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qh, xa, part[nt], 0, 0, 0);
+            part[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ql, xa, part[nt], 0, 0, 0);
+            const float x0 = __uint_as_float(xr[nt].x << 16), x1 = __uint_as_float(xr[nt].x & 0xffff0000u);
+            const float x2 = __uint_as_float(xr[nt].y << 16), x3 = __uint_as_float(xr[nt].y & 0xffff0000u);
+            ex[nt] = __builtin_fmaf(x0, x0, ex[nt]);
+            ex[nt] = __builtin_fmaf(x1, x1, ex[nt]);
+            ex[nt] = __builtin_fmaf(x2, x2, ex[nt]);
+            ex[nt] = __builtin_fmaf(x3, x3, ex[nt]);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        acc[nt] += part[nt];
+        ex[nt] += __shfl_xor(ex[nt], 16, 64);
+        ex[nt] += __shfl_xor(ex[nt], 32, 64);
+    }
+}
+
+// Bounds for bfloat16 tiles.  With x~ the bfloat16 rounding of the stored
+// FP32 row x, ||x_h - x~_h|| <= delta = u_b ||x|| (plus a subnormal term), so
+// by the triangle inequality a certified bracket [s_lo, s_hi] of
+// ||q_h - x~_h||^2 gives one of ||q_h - x_h||^2.  The factors cover the FP32
+// square root and square.
+__device__ inline float bf_head_lower(float s_lo, float delta)
+{
+    const float r = fmaxf(__builtin_sqrtf(fmaxf(s_lo, 0.f)) * (1.f - 1e-6f) - delta, 0.f);
+    return r * r * (1.f - 1e-6f);
+}
+__device__ inline float bf_head_upper(float s_hi, float delta)
+{
+    const float r = __builtin_sqrtf(fmaxf(s_hi, 0.f)) * (1.f + 1e-6f) + delta;
+    return r * r * (1.f + 1e-6f);
+}
+
+template <bool PRUNE, bool BF>
 __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView &ix, const QueryView &qv,
                                           const WorkView &wk)
 {
@@ -500,6 +584,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             const int64_t gb = lb0 + bb;
             const int cnt = ix.blk_cnt[gb];
             const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
+            const uint16_t *blk16 = BF ? ix.levels16 + gb * (int64_t)g.B * g.d_pad : nullptr;
             const float *tl = ix.tails + gb * (int64_t)g.B * g.L;
             if (tid < ng) {
                 float t = __hip_atomic_load(&wk.thr[qid_s[tid]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -529,7 +614,38 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             uint32_t mask = 0;  // bit nt*4 + v: pair (query 4kq+v, slot slot0+nt*16+r16) kept
             float sval[16];
             int lv_start = 1;  // first level left to the per-pair walk
-            if (PRUNE) {
+            if (PRUNE && BF) {
+                // level 1 from the bfloat16 tile: the dot-product form gives
+                // ||q_h - x~_h||^2 within A; the triangle inequality moves the
+                // bound to x
+                float ex[4] = {0.f, 0.f, 0.f, 0.f};
+                if (wave_live) level_dots_bf16(blk16, g.B, g.wp[0] >> 2, &qrow_s[0][0], 16, slot0, lane, acc, ex);
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int s = slot0 + nt * 16 + r16;
+                    const bool valid = s < cnt;
+                    const float b0 = valid ? tl[s] : 0.f;
+                    const float b1 = (valid && g.L > 1) ? tl[g.B + s] : 0.f;
+                    const float delta = c.ub * b0 + 1e-37f;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int gq = 4 * kq + v;
+                        const bool on = valid && gq < ng;
+                        const float a1 = on && g.L > 1 ? qtl_s[gq][1] : 0.f;
+                        const float sh = (on ? rqh_s[gq] : 0.f) + ex[nt] - 2.f * acc[nt][v];
+                        const float dt = a1 - b1;
+                        const float hl = bf_head_lower(sh - (on ? A_s[gq] : 0.f), delta);
+                        const float lb = hl + dt * dt + c.one_m_eps2 * a1 * b1 - c.mg.c_tail * (a1 + b1) * (a1 + b1);
+                        const bool sv = on && (lb <= thr_s[on ? gq : 0]);
+                        mask |= (uint32_t)sv << (nt * 4 + v);
+                        sval[nt * 4 + v] = sh;
+                    }
+                }
+                if (tid == 0) {
+                    my_bytes += (unsigned long long)cnt * (g.wp[0] * 2 + (g.L > 1 ? 8 : 4) + 4);
+                    if (Lc > 0) my_lv[0] += (unsigned long long)cnt * ng;
+                }
+            } else if (PRUNE) {
                 if (wave_live) level_dots(blk, g.B, g.wp[0] >> 2, &qrow_s[0][0], 16, slot0, lane, acc);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
@@ -556,6 +672,8 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     my_bytes += (unsigned long long)cnt * (g.wp[0] * 4 + (g.L > 1 ? 8 : 4) + 4);
                     if (Lc > 0) my_lv[0] += (unsigned long long)cnt * ng;
                 }
+            }
+            if (PRUNE) {
                 // While the survivors stay dense (typically the candidates of a
                 // query's own cluster), keep refining whole levels on the matrix
                 // cores: one coalesced pass over the level tile serves all of
@@ -578,8 +696,15 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     floatx4_t acc2[4];
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) acc2[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-                    if (wave_live)
-                        level_dots(blk + (int64_t)g.B * g.mp[lv], g.B, kgc, &qrow_s[0][0], 16, slot0, lane, acc2, g.wp[lv]);
+                    float ex2[4] = {0.f, 0.f, 0.f, 0.f};
+                    if (wave_live) {
+                        if (BF)
+                            level_dots_bf16(blk16 + (int64_t)g.B * g.mp[lv], g.B, kgc, &qrow_s[0][0], 16, slot0, lane,
+                                            acc2, ex2, g.wp[lv]);
+                        else
+                            level_dots(blk + (int64_t)g.B * g.mp[lv], g.B, kgc, &qrow_s[0][0], 16, slot0, lane, acc2,
+                                       g.wp[lv]);
+                    }
                     const bool last = lv + 1 == g.L;
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) {
@@ -587,7 +712,8 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         const bool valid = s < cnt;
                         const float bl = valid ? tl[(int64_t)lv * g.B + s] : 0.f;
                         const float bn = (valid && !last) ? tl[(int64_t)(lv + 1) * g.B + s] : 0.f;
-                        const float rxl = bl * bl - bn * bn;
+                        const float rxl = BF ? ex2[nt] : bl * bl - bn * bn;
+                        const float delta = BF ? c.ub * (valid ? tl[s] : 0.f) + 1e-37f : 0.f;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int b = nt * 4 + v;
@@ -597,14 +723,22 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                             const float sh = sval[b] + (al * al - an * an) + rxl - 2.f * acc2[nt][v];
                             sval[b] = sh;
                             const float dt = an - bn;
-                            const float lb = sh + dt * dt + c.one_m_eps2 * an * bn;
-                            const float eta = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + A_s[gq] +
-                                              c.mg.c_tail * (an + bn) * (an + bn);
-                            if (lb - eta > thr_s[gq]) mask &= ~(1u << b);
+                            if (BF) {
+                                const float hl =
+                                    bf_head_lower(sh - c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) - A_s[gq], delta);
+                                const float lb =
+                                    hl + dt * dt + c.one_m_eps2 * an * bn - c.mg.c_tail * (an + bn) * (an + bn);
+                                if (lb > thr_s[gq]) mask &= ~(1u << b);
+                            } else {
+                                const float lb = sh + dt * dt + c.one_m_eps2 * an * bn;
+                                const float eta = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + A_s[gq] +
+                                                  c.mg.c_tail * (an + bn) * (an + bn);
+                                if (lb - eta > thr_s[gq]) mask &= ~(1u << b);
+                            }
                         }
                     }
                     if (tid == 0) {
-                        my_bytes += (unsigned long long)cnt * (g.wp[lv] * 4 + 8);
+                        my_bytes += (unsigned long long)cnt * (g.wp[lv] * (BF ? 2 : 4) + 8);
                         if (lv < 64) my_lv[lv] += (unsigned long long)alive_tot;
                     }
                     ++lv_start;
@@ -676,7 +810,117 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             // after level, until its bound exceeds the threshold or the last
             // level is read (no barrier between levels; the Update and
             // Consolidate phases of Section 6.1 run once, after the walk)
-            if (PRUNE && lv_start < g.L) {
+            if (PRUNE && BF) {
+                // the same walk over the bfloat16 tiles; a pair that survives
+                // every level, or whose upper bound proves it survives, is
+                // rescored from the FP32 tiles before it is committed
+                const int np_ = npairs_s;
+                unsigned long long my_sb = 0;
+                for (int p = tid; p < np_; p += NT) {
+                    const uint32_t pv = pr[p];
+                    const int gq = (int)(pv >> 8), ss = (int)(pv & 255u);
+                    const int qq = qid_s[gq];
+                    const float th = thr_s[gq], Aq = A_s[gq];
+                    const float *qrow = qv.qy + (int64_t)qq * g.d_pad;
+                    const float *qt = &qtl_s[gq][0];
+                    const float delta = c.ub * tl[ss] + 1e-37f;
+                    float sh = pS[p];
+                    bool alive = true;
+                    int lv = lv_start;
+                    for (; lv < g.L; ++lv) {
+                        const int w4 = g.wp[lv] >> 2;
+                        const uint16_t *x = blk16 + (int64_t)g.B * g.mp[lv] + (int64_t)ss * g.wp[lv];
+                        const float *qq4 = qrow + g.mp[lv];
+                        const bool last = (lv + 1 == g.L);
+                        const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
+                        float part = 0.f;
+#pragma unroll 4
+                        for (int c4 = 0; c4 < w4; ++c4) {
+                            const uint2 xr = *reinterpret_cast<const uint2 *>(x + c4 * 4);
+                            const float4 q4 = *reinterpret_cast<const float4 *>(qq4 + c4 * 4);
+                            const float t0 = q4.x - __uint_as_float(xr.x << 16);
+                            const float t1 = q4.y - __uint_as_float(xr.x & 0xffff0000u);
+                            const float t2 = q4.z - __uint_as_float(xr.y << 16);
+                            const float t3 = q4.w - __uint_as_float(xr.y & 0xffff0000u);
+                            part = __builtin_fmaf(t0, t0, part);
+                            part = __builtin_fmaf(t1, t1, part);
+                            part = __builtin_fmaf(t2, t2, part);
+                            part = __builtin_fmaf(t3, t3, part);
+                        }
+                        sh += part;
+                        const float a = last ? 0.f : qt[lv + 1];
+                        const float dt = a - b;
+                        const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
+                        const float ct = c.mg.c_tail * (a + b) * (a + b);
+                        const float lb = bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct;
+                        if (lb > th) {
+                            alive = false;
+                            ++lv;
+                            break;
+                        }
+                        if (!last && bf_head_upper(sh + err, delta) + (a + b) * (a + b) + ct <= th) {
+                            ++lv;
+                            break;
+                        }
+                    }
+                    if (alive) {
+                        // FP32 rescoring: every coordinate, level 1 from its
+                        // interleaved tile, the others slot-major
+                        float full = 0.f;
+                        for (int kg = 0; kg < (g.wp[0] >> 2); ++kg) {
+                            const float4 x4 = *reinterpret_cast<const float4 *>(blk + ((int64_t)kg * g.B + ss) * 4);
+                            const float4 q4 = *reinterpret_cast<const float4 *>(qrow + kg * 4);
+                            float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                            full = __builtin_fmaf(t0, t0, full);
+                            full = __builtin_fmaf(t1, t1, full);
+                            full = __builtin_fmaf(t2, t2, full);
+                            full = __builtin_fmaf(t3, t3, full);
+                        }
+                        for (int l2 = 1; l2 < g.L; ++l2) {
+                            const int w42 = g.wp[l2] >> 2;
+                            const float *x2 = blk + (int64_t)g.B * g.mp[l2] + (int64_t)ss * g.wp[l2];
+                            const float *q2 = qrow + g.mp[l2];
+#pragma unroll 4
+                            for (int c4 = 0; c4 < w42; ++c4) {
+                                const float4 x4 = *reinterpret_cast<const float4 *>(x2 + c4 * 4);
+                                const float4 q4 = *reinterpret_cast<const float4 *>(q2 + c4 * 4);
+                                float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                                full = __builtin_fmaf(t0, t0, full);
+                                full = __builtin_fmaf(t1, t1, full);
+                                full = __builtin_fmaf(t2, t2, full);
+                                full = __builtin_fmaf(t3, t3, full);
+                            }
+                        }
+                        sh = full;
+                    }
+                    keep[p] = alive ? 1 : 0;
+                    pS[p] = sh;
+                    if (wk.stats) {
+                        for (int v = lv_start; v < lv && v < 64; ++v) atomicAdd(&my_lv[v], 1ull);
+                        my_sb += (unsigned long long)(g.mp[lv < g.L ? lv : g.L] - g.mp[lv_start]) * 2ull +
+                                 (alive ? (unsigned long long)g.d_pad * 4ull : 0ull);
+                    }
+                }
+                if (wk.stats && my_sb) atomicAdd(&sparse_bytes_s, my_sb);
+                __syncthreads();
+                int kept = 0;
+                for (int base = 0; base < np_; base += NT) {
+                    const int i = base + tid;
+                    const bool f = i < np_ && keep[i];
+                    const uint32_t pv = f ? pr[i] : 0u;
+                    const float sv = f ? pS[i] : 0.f;
+                    int tot;
+                    int off = block_exclusive_scan(f ? 1 : 0, wave_tmp, &tot);
+                    if (f) {
+                        pr[kept + off] = pv;
+                        pS[kept + off] = sv;
+                    }
+                    kept += tot;
+                    __syncthreads();
+                }
+                if (tid == 0) npairs_s = kept;
+                __syncthreads();
+            } else if (PRUNE && lv_start < g.L) {
                 const int np_ = npairs_s;
                 unsigned long long my_dims = 0;
                 for (int p = tid; p < np_; p += NT) {
@@ -887,12 +1131,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
                                                                                             QueryView qv,
                                                                                             WorkView wk)
 {
-    scan_body<true>(c, ix, qv, wk);
+    scan_body<true, false>(c, ix, qv, wk);
+}
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_scan_pruned_bf16(
+    SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    scan_body<true, true>(c, ix, qv, wk);
 }
 
 __global__ __launch_bounds__(NT) void k_scan_brute(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
 {
-    scan_body<false>(c, ix, qv, wk);
+    scan_body<false, false>(c, ix, qv, wk);
 }
 
 // ================================================================ merge
@@ -1081,6 +1331,19 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     c.eps = eps;
     c.one_m_eps2 = 2.f * (1.f - eps);
     c.mg = ix->mg;
+    const bool use_bf16 = !brute && prm && prm->use_bf16;
+    PANO_REQUIRE(!use_bf16 || ix->has_bf16, "bfloat16 search needs an index built with PANO_BF16");
+    c.bf16 = use_bf16 ? 1 : 0;
+    c.ub = (float)(std::ldexp(1.0, -8) * (1.0 + 1e-6));
+    // Absolute margin of the dot-product form: the bfloat16 scan splits each
+    // query value into two bfloat16 terms and reads rows of norm up to
+    // (1 + u_b) ||x||, which its own constant covers.
+    Margins mq = ix->mg;
+    if (use_bf16) {
+        mq.c_abs = ix->c_abs_bf;
+        mq.b0max2 = (float)((double)ix->mg.b0max2 * (1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -8)) *
+                            (1.0 + 1e-6));
+    }
     c.g = LevelGeom{};
     c.g.L = L;
     c.g.d = d;
@@ -1093,6 +1356,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     const int grid = (prm && prm->grid > 0) ? prm->grid : ctx->num_cu * (brute ? 2 : 3);
     const int np_max = nprobe_dev ? nlist : std::min(nprobe_all, nlist);
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
+    const bool seed_on = !brute && eps >= 1.f;
 
     // ---- scratch
     size_t need0 = align_up(sizeof(float) * nq * ix->d_pad) + align_up(sizeof(float) * nq * L) +
@@ -1133,7 +1397,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     // ---- launch geometry that does not depend on the stream
     const double u_ = std::ldexp(1.0, -24);
     auto gam = [&](double nn) { return nn * u_ / (1.0 - nn * u_); };
-    const float c_co = (float)((gam(d / 64.0 + 8) + gam(32.0 + (d + 31) / 32 + 2) + 4 * u_) * 1.1);
+    const float c_co = (float)((gam(d / 64.0 + 8) + gam(2.0 * (32.0 + (d + 31) / 32 + 2)) + 4 * u_) * 1.1);
     const size_t per_wave = coarse_lds_per_wave(nlist, d);
     const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
     const size_t coarse_shm = per_wave * wpb;
@@ -1145,7 +1409,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_shm));
     ctx->pinned_ensure(sizeof(int32_t) * (nq + 1));
     int32_t *h_flags = reinterpret_cast<int32_t *>(ctx->pinned);
-    IndexView iv{ix->levels.as<float>(), ix->tails.as<float>(), ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
+    IndexView iv{ix->levels.as<float>(), ix->has_bf16 ? ix->levels_bf16.as<uint16_t>() : nullptr, ix->tails.as<float>(), ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
                  ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
     QueryView qv{qy, qtail, qE, qA, q};
     WorkView wk{list_cnt, list_qoff, list_q, item_off, heads, thr, buf, buf_cnt, qflags, nullptr};
@@ -1169,7 +1433,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         launch_transform(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy, ix->d_pad, st);
         launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, st);
         hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, vnorm, qtail, L, nq,
-                           ix->mg, qE, qA, qbad);
+                           mq, qE, qA, qbad);
         // coarse probing
         if (nlist > 1) {
             launch_gemm_nt(q, nq, d, ix->cent.as<float>(), nlist, Sco, st);
@@ -1182,8 +1446,12 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
                                npq);
         }
         // threshold seeding (needs only the probes) runs beside the work
-        // decomposition on the context's second stream
-        if (!brute) {
+        // decomposition on the context's second stream.  Only for the exact
+        // bound: a seed's own relaxed bound (eps < 1) may exceed its distance,
+        // so the scan could prune the very candidates that set d_k and return
+        // fewer than k; without seeding, every d_k comes from committed
+        // candidates.
+        if (seed_on) {
             PANO_HIP(hipEventRecord(ctx->ev_fork, st));
             PANO_HIP(hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0));
             hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, ctx->aux, c, iv, qv, probes, np_max,
@@ -1197,12 +1465,14 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
                            ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
         hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_qoff, list_fill,
                            list_q);
-        if (!brute) PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+        if (seed_on) PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[1], st));
         WorkView w2 = wk;
         w2.stats = stats_on ? stats : nullptr;
         if (brute)
             hipLaunchKernelGGL(k_scan_brute, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+        else if (use_bf16)
+            hipLaunchKernelGGL(k_scan_pruned_bf16, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
         else
             hipLaunchKernelGGL(k_scan_pruned, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
         if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[2], st));
@@ -1223,7 +1493,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         enqueue(ws, true);
     } else if (!(flags & PANO_SEARCH_EAGER)) {
         GraphKey key{ix, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
-                     ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p, ctx->pinned};
+                     c.dense_min, c.bf16, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p, ctx->pinned};
         if (!ctx->graph_exec || !(ctx->graph_key == key)) {
             ctx->drop_graph();
             hipGraph_t graph;

@@ -40,6 +40,8 @@ struct SearchConsts {
     int ceil8;         // ceil(nlist / 8)
     int prune;         // 1 = pruned scan, 0 = brute force
     int dense_min;     // refine a level densely while at least this many pairs survive
+    int bf16;          // 1: read level tiles in bfloat16 (certified margin, FP32 rescoring)
+    float ub;          // bfloat16 unit roundoff 2^-8, rounded up (covers the stored-norm rounding)
     float eps;
     float one_m_eps2;  // 2 (1 - eps)
     Margins mg;
@@ -182,6 +184,14 @@ __device__ inline void block_bitonic_sort(uint64_t *buf, int n)
         }
     }
 }
+
+__device__ inline uint16_t bf16_bits_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __host__ __device__ inline int next_pow2(int v)
 {

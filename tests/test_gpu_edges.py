@@ -1,0 +1,195 @@
+"""GPU parity on the edge cases of the method and the interface: fewer
+candidates than k, a single query with k = 1, exact ties and duplicate rows
+(including a tie band larger than the per-query result buffer, which takes
+the exact fallback), empty input, non-finite queries, per-query probe counts
+on Zipf-sized lists, small ragged blocks, and the relaxed bound (eps < 1)."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from paper_2510_00566_amd import synth
+
+gpu = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _workload(d, k, nlist, nprobe, width, n, nq):
+    base = synth.WORKLOADS["flat_sift_like"]
+    return dataclasses.replace(base, name=f"edge-d{d}", d=d, k=k, nlist=nlist, nprobe=nprobe, level_width=width,
+                               n=n, nq=nq, n_clusters=0)
+
+
+def _run(torch_cuda, case, w, q, nprobe=None, k=None, **kw):
+    from tests import gpu_cases as gc
+    k = k or w.k
+    nprobe = w.nprobe if nprobe is None else nprobe
+    qd = torch_cuda.from_numpy(q).cuda()
+    npd = torch_cuda.from_numpy(np.asarray(nprobe, dtype=np.int32)).cuda() if np.ndim(nprobe) else int(nprobe)
+    ids, dd = case["idx"].search(qd, k, nprobe=npd, stats=True, **kw)
+    st = case["idx"].stats()
+    ref_i, ref_d = gc.oracle_answer(case, q, nprobe, k)
+    gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
+    bi, bd = case["idx"].search_bruteforce(qd, k, nprobe=npd)
+    gc.compare(bi.cpu().numpy(), bd.cpu().numpy(), ref_i, ref_d)
+    return ids.cpu().numpy(), dd.cpu().numpy(), st
+
+
+@gpu
+def test_fewer_candidates_than_k(torch_cuda):
+    """k = 64 over a 40-row flat index: the tail of every answer is (-1, +inf)."""
+    from tests import gpu_cases as gc
+    w = _workload(d=32, k=64, nlist=1, nprobe=1, width=8, n=40, nq=3)
+    x = synth.uniform_cube(40, 32, seed=1)
+    q = synth.uniform_cube(3, 32, seed=2)
+    _log("case fewer-than-k n=40 d=32 k=64")
+    case = gc.build_case(w, data={"x": x, "q": q})
+    ids, dd, _ = _run(torch_cuda, case, w, q)
+    assert (ids[:, 40:] == -1).all() and np.isinf(dd[:, 40:]).all()
+    assert sorted(ids[0, :40].tolist()) == list(range(40))
+
+
+@gpu
+def test_single_query_k1(torch_cuda):
+    from tests import gpu_cases as gc
+    w = _workload(d=96, k=1, nlist=8, nprobe=2, width=16, n=5000, nq=1)
+    x = synth.uniform_cube(5000, 96, seed=3)
+    q = synth.uniform_cube(1, 96, seed=4)
+    _log("case nq=1 k=1 n=5000 d=96 nlist=8")
+    case = gc.build_case(w, data={"x": x, "q": q})
+    _run(torch_cuda, case, w, q)
+
+
+@gpu
+def test_integer_grid_ties(torch_cuda):
+    """Small-integer rows: many exact distance ties and duplicate rows; ties
+    are ordered by id on both sides."""
+    from tests import gpu_cases as gc
+    w = _workload(d=16, k=10, nlist=8, nprobe=3, width=4, n=6000, nq=32)
+    x = synth.integer_grid(6000, 16, seed=5, span=2)
+    q = synth.integer_grid(32, 16, seed=6, span=2)
+    _log("case integer grid n=6000 d=16 nlist=8 nprobe=3")
+    case = gc.build_case(w, data={"x": x, "q": q})
+    _, _, st = _run(torch_cuda, case, w, q)
+    _log("fallback queries", st["fallback_queries"])
+
+
+@gpu
+def test_tie_band_beyond_buffer_takes_fallback(torch_cuda):
+    """5000 identical rows tie for every query: the band of equal distances
+    exceeds the per-query buffer, the exact fallback runs, and the answer is
+    the k smallest ids."""
+    from tests import gpu_cases as gc
+    w = _workload(d=24, k=8, nlist=1, nprobe=1, width=8, n=5008, nq=4)
+    base = synth.uniform_cube(1, 24, seed=7)
+    x = np.repeat(base, 5008, axis=0)
+    x[5000:] = synth.uniform_cube(8, 24, seed=8) + 3.0
+    q = synth.uniform_cube(4, 24, seed=9) * 0.01 + base
+    _log("case identical rows n=5008 d=24 k=8")
+    case = gc.build_case(w, data={"x": x, "q": q}, transform="identity")
+    ids, _, st = _run(torch_cuda, case, w, q)
+    assert (ids == np.arange(8)[None, :]).all()
+    assert st["fallback_queries"] == 4
+
+
+@gpu
+def test_empty_query_batch(torch_cuda):
+    from tests import gpu_cases as gc
+    w = _workload(d=32, k=5, nlist=1, nprobe=1, width=8, n=500, nq=2)
+    x = synth.uniform_cube(500, 32, seed=10)
+    case = gc.build_case(w, data={"x": x, "q": x[:2]})
+    q = torch_cuda.empty((0, 32), dtype=torch_cuda.float32, device="cuda")
+    ids, dd = case["idx"].search(q, 5, nprobe=1)
+    assert ids.shape == (0, 5) and dd.shape == (0, 5)
+
+
+@gpu
+def test_nonfinite_query_rejected(torch_cuda):
+    from tests import gpu_cases as gc
+    from paper_2510_00566_amd._lib import PanoError
+    w = _workload(d=32, k=5, nlist=4, nprobe=2, width=8, n=800, nq=3)
+    x = synth.uniform_cube(800, 32, seed=11)
+    q = synth.uniform_cube(3, 32, seed=12)
+    case = gc.build_case(w, data={"x": x, "q": q})
+    bad = q.copy()
+    bad[1, 7] = np.nan
+    with pytest.raises(PanoError, match="non-finite"):
+        case["idx"].search(torch_cuda.from_numpy(bad).cuda(), 5, nprobe=2)
+    bad[1, 7] = np.inf
+    with pytest.raises(PanoError, match="non-finite"):
+        case["idx"].search(torch_cuda.from_numpy(bad).cuda(), 5, nprobe=2, eager=True)
+    _run(torch_cuda, case, w, q)  # the index is still usable
+
+
+@gpu
+def test_zipf_lists_per_query_nprobe(torch_cuda):
+    """Batched IVF shape: Zipf(1.1) cluster sizes, nprobe drawn per query
+    (clamped to nlist by both sides), 16-wide levels."""
+    from tests import gpu_cases as gc
+    w = synth.scaled(synth.WORKLOADS["ivf_zipf_batched"], n=40000, nq=48, nlist=64, n_clusters=64)
+    data = synth.generate(w)
+    _log("case zipf n=40000 d=128 nlist=64 per-query nprobe")
+    case = gc.build_case(w, data=data)
+    npq = np.minimum(data["nprobe"], 64).astype(np.int32)
+    ids, _, st = _run(torch_cuda, case, w, data["q"], nprobe=npq)
+    _log("zipf stats", {k: st[k] for k in ("candidates", "dims_read", "fallback_queries")})
+    assert st["fallback_queries"] == 0
+
+
+@gpu
+@pytest.mark.parametrize("block", [64, 128])
+def test_small_ragged_blocks(torch_cuda, block):
+    """Blocks of 64 and 128 slots: most lists end in a partly filled block."""
+    from tests import gpu_cases as gc
+    w = synth.scaled(synth.WORKLOADS["ivf_gist_like"], n=15000, nq=20, nlist=20, nprobe=4, n_clusters=20)
+    w.d = 180
+    w.level_width = 20
+    _log(f"case block={block} n=15000 d=180 nlist=20")
+    case = gc.build_case(w, block=block)
+    assert case["idx"].info()["block"] == block
+    _run(torch_cuda, case, w, case["data"]["q"])
+
+
+@gpu
+def test_relaxed_bound_properties(torch_cuda):
+    """eps < 1 (Eq. 4) may drop true neighbours, so its answer is checked by
+    what must still hold: every reported distance is the canonical distance
+    of the reported id, answers are ordered by (D, id), every id comes from a
+    probed list, and no answer beats the exact one; eps = 1 is exact."""
+    from tests import gpu_cases as gc
+    w = synth.scaled(synth.WORKLOADS["ivf_gist_like"], n=15000, nq=24, nlist=16, nprobe=4, n_clusters=16)
+    w.d = 120
+    w.level_width = 12
+    case = gc.build_case(w)
+    q = case["data"]["q"]
+    qd = torch_cuda.from_numpy(q).cuda()
+    ref_i, ref_d = gc.oracle_answer(case, q, w.nprobe, w.k)
+    probes = brute.probe_lists(q, case["cent"], w.nprobe)
+    for eps in (0.0, 0.5, 0.9):
+        ids, dd = case["idx"].search(qd, w.k, nprobe=w.nprobe, eps=eps)
+        ids, dd = ids.cpu().numpy(), dd.cpu().numpy()
+        for i in range(w.nq):
+            assert (ids[i] >= 0).all()
+            assert len(set(ids[i].tolist())) == w.k
+            assert np.isin(case["assign"][ids[i]], probes[i]).all()
+            canon = brute.canonical_dist(q[i], case["x"][ids[i]])
+            assert np.array_equal(canon.astype(np.float32), dd[i])
+            order = np.lexsort((ids[i], dd[i]))
+            assert (order == np.arange(w.k)).all()
+            assert (dd[i] >= ref_d[i]).all()
+    ids, dd = case["idx"].search(qd, w.k, nprobe=w.nprobe, eps=1.0)
+    gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
