@@ -38,10 +38,10 @@ def scan_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload: str):
+def traffic_from_profiles(kernel: str, workload: str):
     """HBM bytes per scan launch from the committed rocprofv3 counter summary,
     if it was taken on the current scan kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_scan_pruned_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner and store its choice")
     ap.add_argument("--no-secondary", action="store_true", help="skip the data-fit PCA comparison")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no graph replay)")
+    ap.add_argument("--store", default="f32", choices=["f32", "bf16"],
+                    help="bf16: keep bfloat16 level slices and scan them (certified margin, FP32 rescoring)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (to calibrate HBM byte counters)")
     args = ap.parse_args()
@@ -120,20 +122,22 @@ def main():
 
     tf = fit_transform(args.transform)
     t0 = time.time()
-    idx = Index.build(ctx, tf, xd, cent, assign, w.level_cuts())
+    idx = Index.build(ctx, tf, xd, cent, assign, w.level_cuts(), store=args.store)
     torch.cuda.synchronize()
     info = idx.info()
     log(f"[bench] index built in {time.time() - t0:.1f}s: {info['nblocks']} blocks, "
         f"levels {info['bytes_levels'] / 1e9:.2f} GB")
 
-    sig = autotune.signature("gfx950", w.d, "f32", w.n, w.nprobe_range[1] if w.nprobe_range else w.nprobe, w.k)
+    use_bf16 = 1 if args.store == "bf16" else 0
+    sig = autotune.signature("gfx950", w.d, args.store, w.n, w.nprobe_range[1] if w.nprobe_range else w.nprobe, w.k)
     prm, _ = autotune.lookup(sig)
     if args.tune or prm is None:
         if args.tune:
-            prm, tbest = autotune.tune_search(idx, qd, w.k, npd, log=log)
+            prm, tbest = autotune.tune_search(idx, qd, w.k, npd, log=log, use_bf16=use_bf16)
             autotune.store(sig, prm, w.level_width, tbest)
         else:
             prm = Params()
+    prm.use_bf16 = use_bf16
     log(f"[bench] search params {prm}")
     ids = torch.empty((w.nq, w.k), dtype=torch.int64, device="cuda")
     dists = torch.empty((w.nq, w.k), dtype=torch.float32, device="cuda")
@@ -144,7 +148,11 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    log("[bench] warmup done")
+    t1 = time.perf_counter()
+    step(stats=True)
+    st0 = idx.stats()
+    log(f"[bench] warmup done; one eager search {1e3 * (time.perf_counter() - t1):.1f} ms, "
+        f"scan {st0['ms_scan']:.2f} ms, fallback queries {st0['fallback_queries']}")
     # ---- timed region: K whole searches (the search sequence is captured
     # once into a HIP graph and replayed)
     torch.cuda.synchronize()
@@ -194,6 +202,29 @@ def main():
             if best is None or rec["qps"] > best["qps"]:
                 best = rec
         bf = best
+
+    # ---- bfloat16 scan against the FP32 scan of the same index
+    precision = None
+    if use_bf16:
+        fi = torch.empty_like(ids)
+        fd = torch.empty_like(dists)
+        p32 = Params(**{k_: v_ for k_, v_ in vars(prm).items()})
+        p32.use_bf16 = 0
+        for _ in range(max(1, args.warmup)):
+            idx.search(qd, w.k, nprobe=npd, params=p32, out=(fi, fd))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            idx.search(qd, w.k, nprobe=npd, params=p32, out=(fi, fd))
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t1
+        idx.search(qd, w.k, nprobe=npd, params=p32, stats=True, out=(fi, fd))
+        st32 = idx.stats()
+        precision = {"f32_qps": w.nq * args.steps / el32, "f32_ms_per_step": el32 * 1000 / args.steps,
+                     "bf16_qps": qps, "same_result_as_f32": bool(torch.equal(fi, ids) and torch.equal(fd, dists)),
+                     "f32_scan_ms": st32["ms_scan"], "f32_scan_bytes": st32["scan_bytes"],
+                     "bf16_scan_ms": float(np.mean(scan_ms)), "bf16_scan_bytes": float(np.mean(scan_bytes))}
+        log(f"[bench] precision {precision}")
 
     # ---- sampled parity against the oracle at full size
     parity = None
@@ -272,8 +303,9 @@ def main():
         idx2.free()
 
     achieved = (np.mean(scan_bytes) / 1e9) / (np.mean(scan_ms) / 1e3)
+    kernel = "k_scan_pruned_bf16" if use_bf16 else "k_scan_pruned"
     out = {
-        "metric": "QPS at exact recall@10 (eps=1) vs same-GPU brute-force scan; HBM GB/s",
+        "metric": f"QPS at exact recall@{w.k} (eps=1) vs same-GPU brute-force scan; HBM GB/s",
         "value": qps,
         "unit": "queries/s",
         "n_gpus": 1,
@@ -283,16 +315,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if use_bf16 else "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nq": w.nq, "k": w.k, "nlist": w.nlist,
                    "nprobe": (list(w.nprobe_range) if w.nprobe_range else w.nprobe), "levels": w.L,
-                   "level_width": w.level_width, "eps": 1.0,
+                   "level_width": w.level_width, "eps": 1.0, "store": args.store,
                    "transform": "pca_fit_on_list_residuals" if (args.transform == "residual" and w.nlist > 1)
                    else "pca_fit_on_data", "search_params": {k_: v_ for k_, v_ in vars(prm).items()}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_from_profiles(w.name),
-                     "kernel": "k_scan_pruned", "bytes_per_launch": float(np.mean(scan_bytes)),
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_from_profiles(kernel, w.name),
+                     "kernel": kernel,
+                     "bytes_per_launch": float(np.mean(scan_bytes)),
                      "ms_per_launch": float(np.mean(scan_ms))},
         "cpu_baseline": cpu,
         "bruteforce": bf,
@@ -304,6 +337,7 @@ def main():
                          "total_device": st["ms_total"]},
         "fallback_queries": st["fallback_queries"],
         "secondary": secondary,
+        "precision": precision,
     }
     print(json.dumps(out))
 

@@ -65,6 +65,7 @@ const char *pano_version(void);
  * memory reused across searches.  A context may be used by one thread at a
  * time. */
 pano_status pano_ctx_create(int device, pano_ctx **out);
+/* Destroy a context; every index built on it must be freed first. */
 void pano_ctx_destroy(pano_ctx *ctx);
 
 /*
@@ -226,6 +227,9 @@ typedef struct {
 
 pano_status pano_stats_get(const pano_index *idx, pano_stats_t *out);
 
+/* Free an index (and the context's cached search graph if it was captured
+ * for this index).  Call before destroying the index's context.  NULL is a
+ * no-op. */
 void pano_index_free(pano_index *idx);
 
 #ifdef __cplusplus

@@ -50,7 +50,8 @@ def _time(fn, reps: int) -> float:
     return (time.perf_counter() - t) / reps
 
 
-def tune_search(idx, q_dev, k: int, nprobe, reps: int = 5, space: dict | None = None, log=None) -> tuple[Params, float]:
+def tune_search(idx, q_dev, k: int, nprobe, reps: int = 5, space: dict | None = None, log=None,
+                use_bf16: int = 0) -> tuple[Params, float]:
     """Coordinate-wise sweep of the search knobs; returns the best Params and
     its time per search (seconds)."""
     space = space or SEARCH_SPACE
@@ -59,7 +60,8 @@ def tune_search(idx, q_dev, k: int, nprobe, reps: int = 5, space: dict | None = 
 
     def mk(cfg):
         return Params(group=cfg["group"], blocks_per_item=cfg["blocks_per_item"],
-                      seed_pool=cfg["seed"][0], seed_count=cfg["seed"][1], dense_min=cfg["dense_min"])
+                      seed_pool=cfg["seed"][0], seed_count=cfg["seed"][1], dense_min=cfg["dense_min"],
+                      use_bf16=use_bf16)
 
     def run(cfg):
         p = mk(cfg)

@@ -6,6 +6,7 @@
 #include "search_common.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -93,6 +94,8 @@ static void compute_margins(pano_index *ix, const std::vector<float> &T32)
     mg.rho = (float)rho;
     ix->sigma_ratio = smax / smin;
 }
+
+static std::atomic<uint64_t> g_index_serial{0};
 
 static LevelGeom geom_of(const pano_index *ix)
 {
@@ -349,6 +352,7 @@ pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const flo
         hipStream_t s = (hipStream_t)stream;
         auto ix = std::make_unique<pano_index>();
         ix->ctx = ctx;
+        ix->serial = ++g_index_serial;
         ix->n = n;
         ix->d = d;
         ix->nlist = nlist;
@@ -548,6 +552,12 @@ pano_status pano_stats_get(const pano_index *idx, pano_stats_t *out)
     });
 }
 
-void pano_index_free(pano_index *idx) { delete idx; }
+void pano_index_free(pano_index *idx)
+{
+    if (!idx) return;
+    // the context's captured search graph may point into this index's memory
+    if (idx->ctx && idx->ctx->graph_exec && idx->ctx->graph_key.ix_serial == idx->serial) idx->ctx->drop_graph();
+    delete idx;
+}
 
 }  // extern "C"

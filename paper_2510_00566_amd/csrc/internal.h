@@ -102,7 +102,8 @@ struct FillList {
 
 // Identity of a captured search graph: every value baked into its nodes.
 struct GraphKey {
-    const void *ix, *q;
+    uint64_t ix_serial;  // unique per index built, so a freed index's address cannot match
+    const void *q;
     int64_t nq;
     int k;
     const void *npd;
@@ -114,7 +115,7 @@ struct GraphKey {
     const void *s0, *s1, *s2, *s3, *pinned;
     bool operator==(const GraphKey &o) const
     {
-        return ix == o.ix && q == o.q && nq == o.nq && k == o.k && npd == o.npd && np_all == o.np_all &&
+        return ix_serial == o.ix_serial && q == o.q && nq == o.nq && k == o.k && npd == o.npd && np_all == o.np_all &&
                eps == o.eps && brute == o.brute && ids == o.ids && dists == o.dists && G == o.G && bpi == o.bpi &&
                seed_pool == o.seed_pool && seed_cnt == o.seed_cnt && grid == o.grid && dense_min == o.dense_min &&
                bf16 == o.bf16 && s0 == o.s0 && s1 == o.s1 &&
@@ -194,6 +195,7 @@ struct pano_transform {
 
 struct pano_index {
     pano_ctx *ctx = nullptr;
+    uint64_t serial = 0;  // process-wide build counter
     int64_t n = 0;
     int d = 0, d_pad = 0, nlist = 0, L = 0, B = 256;
     bool has_bf16 = false;

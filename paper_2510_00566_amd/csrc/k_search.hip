@@ -1146,9 +1146,41 @@ __global__ __launch_bounds__(NT) void k_scan_brute(SearchConsts c, IndexView ix,
 }
 
 // ================================================================ merge
+// Distance bits of the k-th smallest of n keys in global memory: radix
+// select over the 32 bits of the (non-negative) distance, 8 bits per pass,
+// with a 256-bin histogram in LDS.
+__device__ uint32_t block_kth_dist_bits(const uint64_t *__restrict__ keys, int n, int k, int *hist, int *sel)
+{
+    uint32_t prefix = 0, mask = 0;
+    int rank = k;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NT) {
+            const uint32_t b = (uint32_t)(keys[i] >> 32);
+            if ((b & mask) == prefix) atomicAdd(&hist[(b >> shift) & 255u], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0, dg = 0;
+            while (dg < 255 && acc + hist[dg] < rank) acc += hist[dg++];
+            sel[0] = dg;
+            sel[1] = rank - acc;
+        }
+        __syncthreads();
+        prefix |= (uint32_t)sel[0] << shift;
+        mask |= 255u << shift;
+        rank = sel[1];
+        __syncthreads();
+    }
+    return prefix;
+}
+
 // One workgroup per query: sort the committed entries, find the k-th best
 // computed distance, rescore every entry of the boundary band with the
-// canonical recipe and emit the first k by (D, id).
+// canonical recipe and emit the first k by (D, id).  A buffer longer than the
+// LDS sort holds is first cut to the entries that can reach the band: the k-th
+// smallest distance is found by radix select in global memory.
 __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__restrict__ buf,
                                               const int32_t *__restrict__ buf_cnt,
                                               int32_t *__restrict__ flags, const float *__restrict__ qE,
@@ -1159,6 +1191,7 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
 {
     extern __shared__ uint64_t K[];
     __shared__ int nb_s;
+    __shared__ int hist[256], sel[2];
     __shared__ float qrow[4096];
     const int64_t q = blockIdx.x;
     for (int j = threadIdx.x; j < d; j += NT) qrow[j] = qraw[q * d + j];
@@ -1167,10 +1200,36 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
         if (threadIdx.x == 0) atomicOr(&flags[q], FLAG_OVERFLOW);
         return;
     }
-    const int n = n_all;
+    const uint64_t *bq = buf + q * c.capq;
+    int n = n_all;
+    if (n > MERGE_LDS_KEYS) {
+        const float dk = __uint_as_float(block_kth_dist_bits(bq, n, c.k, hist, sel));
+        const float cut = prune_threshold(dk, qE[q], qA[q], c.mg);
+        if (threadIdx.x == 0) nb_s = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NT) {
+            const uint64_t key = bq[i];
+            if (dist_lower(key_dist(key), qA[q], c.mg) <= cut) {
+                const int pos = atomicAdd(&nb_s, 1);
+                if (pos < MERGE_LDS_KEYS) K[pos] = key;
+            }
+        }
+        __syncthreads();
+        n = nb_s;
+        __syncthreads();
+        if (n > MERGE_LDS_KEYS) {
+            if (threadIdx.x == 0) atomicOr(&flags[q], FLAG_OVERFLOW);
+            return;
+        }
+        const int P = next_pow2(n > 0 ? n : 1);
+        for (int i = n + threadIdx.x; i < P; i += NT) K[i] = KEY_MAX;
+        __syncthreads();
+    } else {
+        const int P = next_pow2(n > 0 ? n : 1);
+        for (int i = threadIdx.x; i < P; i += NT) K[i] = i < n ? bq[i] : KEY_MAX;
+        __syncthreads();
+    }
     const int P = next_pow2(n > 0 ? n : 1);
-    for (int i = threadIdx.x; i < P; i += NT) K[i] = i < n ? buf[q * c.capq + i] : KEY_MAX;
-    __syncthreads();
     block_bitonic_sort(K, P);
     const float Aq = qA[q];
     const float thr = n >= c.k ? prune_threshold(key_dist(K[c.k - 1]), qE[q], Aq, c.mg) : INFINITY;
@@ -1203,7 +1262,7 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
         }
     }
     if (stats && threadIdx.x == 0) {
-        atomicAdd(&stats[ST_COMMIT], (unsigned long long)n);
+        atomicAdd(&stats[ST_COMMIT], (unsigned long long)n_all);
         atomicAdd(&stats[3], (unsigned long long)nb);
     }
 }
@@ -1323,7 +1382,21 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     if (prm && prm->group > 0) G = std::min(prm->group, G);
     c.G = G;
     c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1;
-    c.capq = std::min(4096, std::max(2048, 16 * c.kc));
+    // Per-query result buffer: a work item publishes about k entries (its
+    // local best k and their margin band), and a query meets about
+    // nprobe * ceil(mean blocks per list / bpi) work items.  Twice that
+    // estimate, within [2048, 65536] and 4 GiB over the batch; a query that
+    // still overflows takes the exact fallback.
+    {
+        const int np_est = nprobe_dev ? std::min(nlist, 128) : std::min(nprobe_all, nlist);
+        const double mean_blk = (double)ix->list_blk.back() / std::max(1, nlist);
+        const double items = (double)np_est * (std::ceil(mean_blk / c.bpi) + 1.0);
+        const double want = 2.0 * items * (k + 8);
+        int64_t cap = 2048;
+        while (cap < want && cap < 65536) cap <<= 1;
+        while (cap > 2048 && (double)cap * 8.0 * (double)nq > 4.0 * 1073741824.0) cap >>= 1;
+        c.capq = (int)cap;
+    }
     c.nlist = nlist;
     c.ceil8 = (nlist + 7) / 8;
     c.prune = brute ? 0 : 1;
@@ -1402,7 +1475,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
     const size_t coarse_shm = per_wave * wpb;
     PANO_REQUIRE(nlist == 1 || coarse_shm <= 160 * 1024, "nlist too large for the coarse step");
-    const size_t merge_shm = sizeof(uint64_t) * next_pow2(c.capq);
+    const size_t merge_shm = sizeof(uint64_t) * std::min(next_pow2(c.capq), MERGE_LDS_KEYS);
     const size_t scan_shm = sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
     if (nlist > 1)
         PANO_HIP(hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_shm));
@@ -1492,7 +1565,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         PANO_HIP(hipEventRecord(ctx->ev[0], ws));
         enqueue(ws, true);
     } else if (!(flags & PANO_SEARCH_EAGER)) {
-        GraphKey key{ix, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
+        GraphKey key{ix->serial, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
                      c.dense_min, c.bf16, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p, ctx->pinned};
         if (!ctx->graph_exec || !(ctx->graph_key == key)) {
             ctx->drop_graph();

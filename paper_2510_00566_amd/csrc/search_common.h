@@ -7,6 +7,7 @@
 namespace pano {
 
 constexpr int NT = 256;         // threads per workgroup (4 wavefronts)
+constexpr int MERGE_LDS_KEYS = 4096;  // entries the merge sorts in LDS
 constexpr int GMAX = 16;        // max queries per scan work item
 constexpr int SB_MAX = 512;     // per-wave sort buffer (entries)
 constexpr uint64_t KEY_MAX = ~0ull;

@@ -3,6 +3,7 @@ the current HIP stream; all computation happens in libpanorama.so."""
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -30,9 +31,13 @@ class Context:
         L.check(L.lib().pano_ctx_create(device, C.byref(h)))
         self.h = h
         self.device = device
+        self._indexes = weakref.WeakSet()
 
     def close(self):
+        """Destroy the context; indexes built on it are freed first."""
         if self.h:
+            for ix in list(self._indexes):
+                ix.free()
             L.lib().pano_ctx_destroy(self.h)
             self.h = None
 
@@ -123,6 +128,7 @@ class Index:
         self.h = h
         self.ctx = ctx
         self.d = d
+        ctx._indexes.add(self)
 
     @classmethod
     def build(cls, ctx: Context, tf: Transform, x_dev, centroids_dev, assign_dev, m, block: int = 256,

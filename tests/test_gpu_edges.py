@@ -107,6 +107,25 @@ def test_tie_band_beyond_buffer_takes_fallback(torch_cuda):
 
 
 @gpu
+def test_merge_of_long_result_buffers(torch_cuda):
+    """k = 128 over 64-slot blocks of a flat index with weak pruning: each
+    query meets hundreds of work items and its result buffer grows past what
+    the merge sorts in LDS, so the merge first cuts it by radix select."""
+    from tests import gpu_cases as gc
+    w = _workload(d=64, k=128, nlist=1, nprobe=1, width=8, n=30000, nq=8)
+    x = synth.uniform_cube(30000, 64, seed=13)
+    q = synth.uniform_cube(8, 64, seed=14)
+    _log("case long buffers n=30000 d=64 k=128 block=64")
+    case = gc.build_case(w, data={"x": x, "q": q}, block=64)
+    from paper_2510_00566_amd.index import Params
+    # a seed threshold from only k candidates keeps d_k loose for longer
+    _, _, st = _run(torch_cuda, case, w, q, params=Params(seed_pool=128, seed_count=128))
+    _log("published per query", st["committed"] / w.nq, "fallback", st["fallback_queries"])
+    assert st["committed"] > 4096 * w.nq  # so at least one query's buffer exceeds the LDS sort
+    assert st["fallback_queries"] == 0
+
+
+@gpu
 def test_empty_query_batch(torch_cuda):
     from tests import gpu_cases as gc
     w = _workload(d=32, k=5, nlist=1, nprobe=1, width=8, n=500, nq=2)

@@ -128,3 +128,31 @@ def test_parity_across_search_knobs(torch_cuda, kw):
     gc.compare(ids2.cpu().numpy(), dd2.cpu().numpy(), ref_i, ref_d)
     bi, bd = case["idx"].search_bruteforce(q, w.k, nprobe=w.nprobe, params=p)
     gc.compare(bi.cpu().numpy(), bd.cpu().numpy(), ref_i, ref_d)
+
+
+@gpu
+def test_graph_not_reused_across_indexes(torch_cuda):
+    """A search graph captured for one index must never be replayed for
+    another: free an index, build a new one of the same shape (the host
+    allocator may hand out the same handle address) and search with the very
+    same query and output buffers; the answer must be the new index's."""
+    import dataclasses
+    from tests import gpu_cases as gc
+    base = synth.WORKLOADS["flat_sift_like"]
+    w = dataclasses.replace(base, name="graph-reuse", d=48, k=10, nlist=4, nprobe=2, level_width=8, n=4000, nq=16,
+                            n_clusters=0)
+    q = synth.uniform_cube(16, 48, seed=21)
+    qd = torch_cuda.from_numpy(q).cuda()
+    ids = torch_cuda.empty((16, 10), dtype=torch_cuda.int64, device="cuda")
+    dd = torch_cuda.empty((16, 10), dtype=torch_cuda.float32, device="cuda")
+    for rnd, seed in enumerate((22, 23, 24)):
+        x = synth.uniform_cube(4000, 48, seed=seed)
+        case = gc.build_case(w, data={"x": x, "q": q})
+        for brute in (False, True):
+            fn = case["idx"].search_bruteforce if brute else case["idx"].search
+            fn(qd, 10, nprobe=2, out=(ids, dd))
+            torch_cuda.cuda.synchronize()
+            ref_i, ref_d = gc.oracle_answer(case, q, 2, 10)
+            gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
+        case["idx"].free()
+        del case
