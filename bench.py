@@ -157,8 +157,13 @@ def main():
     # once into a HIP graph and replayed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    last = t0
+    for i in range(args.steps):
         step()
+        now = time.perf_counter()
+        if now - last > 30.0:  # progress on very slow configurations only
+            log(f"[bench] step {i + 1}/{args.steps} at {now - t0:.1f}s")
+            last = now
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f}s")

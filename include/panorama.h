@@ -142,11 +142,17 @@ typedef struct {
                              2 per CU brute force) */
     int32_t use_bf16;     /* 1: the pruned scan reads the bfloat16 level slices
                              (index built with PANO_BF16, else EINVAL); its
-                             bounds carry a certified bfloat16 margin and every
-                             survivor is rescored from the FP32 slices, so the
-                             result equals the FP32 search's */
+                             bounds and committed distances carry a certified
+                             bfloat16 margin and the merge rescores the
+                             boundary band from the FP32 rows, so the result
+                             equals the FP32 search's */
     int32_t reserved[6];  /* [0]: refine a whole level on the matrix cores while at
-                             least this many pairs of a block survive (0 = 64) */
+                             least this many pairs of a block survive (0 = 64);
+                             [1]: scan mode, 0 or 1 = one persistent kernel
+                             with a local top-k per work item, 2 = segmented
+                             split scan (level-1 filter, then one pass per
+                             level over each workgroup's surviving pairs;
+                             needs L >= 2, else the persistent scan runs) */
 } pano_search_params;
 
 /* Search flags. */
@@ -169,6 +175,30 @@ pano_status pano_search(pano_index *idx, const float *q_dev, int64_t nq, int32_t
                         const int32_t *nprobe_dev, int32_t nprobe_all, float eps,
                         int64_t *ids_dev, float *dists_dev, const pano_search_params *params,
                         uint32_t flags, void *stream);
+
+/*
+ * search_ctx: pano_search run on context `ctx` (its streams, scratch memory
+ * and graph cache) instead of the context the index was built on.  ctx must
+ * be on the index's device.  Searches on different contexts may run
+ * concurrently from different threads, also on the same index (a serving
+ * loop keeps one context per worker); one context serves one thread at a
+ * time.  PANO_SEARCH_STATS writes the index's counters, so at most one
+ * search of an index should ask for them at a time.
+ */
+pano_status pano_search_ctx(pano_ctx *ctx, pano_index *idx, const float *q_dev, int64_t nq, int32_t k,
+                            const int32_t *nprobe_dev, int32_t nprobe_all, float eps, int64_t *ids_dev,
+                            float *dists_dev, const pano_search_params *params, uint32_t flags,
+                            void *stream);
+
+/*
+ * search_scratch_bytes: device scratch memory (bytes) that a pano_search of
+ * nq queries with this k, probe setting (per_query_nprobe != 0: a per-query
+ * array, else nprobe_all for all) and params needs on its context, beside
+ * the caller's queries and outputs.  Used for memory-based admission.
+ */
+pano_status pano_search_scratch_bytes(const pano_index *idx, int64_t nq, int32_t k,
+                                      int32_t per_query_nprobe, int32_t nprobe_all,
+                                      const pano_search_params *params, int64_t *bytes);
 
 /*
  * search_bruteforce: the same contract as pano_search with pruning disabled:

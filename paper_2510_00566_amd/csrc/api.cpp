@@ -9,6 +9,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 
 namespace pano {
@@ -445,6 +446,13 @@ pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const flo
             ix->max_list_blocks = std::max(ix->max_list_blocks, nb);
         }
         ix->nblocks = ix->list_blk[nlist];
+        {
+            std::vector<int64_t> nb(nlist);
+            for (int l = 0; l < nlist; ++l) nb[l] = ix->list_blk[l + 1] - ix->list_blk[l];
+            std::sort(nb.begin(), nb.end(), std::greater<int64_t>());
+            ix->top_blk_prefix.assign(nlist + 1, 0);
+            for (int l = 0; l < nlist; ++l) ix->top_blk_prefix[l + 1] = ix->top_blk_prefix[l] + nb[l];
+        }
         std::vector<int32_t> block_list(std::max<int64_t>(1, ix->nblocks));
         for (int l = 0; l < nlist; ++l)
             for (int64_t b = ix->list_blk[l]; b < ix->list_blk[l + 1]; ++b) block_list[b] = l;
@@ -481,18 +489,41 @@ pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const flo
     });
 }
 
-pano_status pano_search(pano_index *idx, const float *q_dev, int64_t nq, int32_t k, const int32_t *nprobe_dev,
-                        int32_t nprobe_all, float eps, int64_t *ids_dev, float *dists_dev,
-                        const pano_search_params *params, uint32_t flags, void *stream)
+pano_status pano_search_ctx(pano_ctx *ctx, pano_index *idx, const float *q_dev, int64_t nq, int32_t k,
+                            const int32_t *nprobe_dev, int32_t nprobe_all, float eps, int64_t *ids_dev,
+                            float *dists_dev, const pano_search_params *params, uint32_t flags, void *stream)
 {
     return guarded([&] {
-        PANO_REQUIRE(idx && (nq == 0 || (q_dev && ids_dev && dists_dev)), "null argument");
+        PANO_REQUIRE(ctx && idx && (nq == 0 || (q_dev && ids_dev && dists_dev)), "null argument");
         PANO_REQUIRE(k >= 1 && nq >= 0, "need k >= 1 and nq >= 0");
         PANO_REQUIRE(eps >= 0.f && eps <= 1.f, "eps must be in [0, 1]");
         PANO_REQUIRE(nprobe_dev != nullptr || nprobe_all >= 1, "nprobe_all must be >= 1");
         if (nq == 0) return;
-        run_search(idx, q_dev, nq, k, nprobe_dev, nprobe_all, eps, ids_dev, dists_dev, params, flags, false,
+        run_search(ctx, idx, q_dev, nq, k, nprobe_dev, nprobe_all, eps, ids_dev, dists_dev, params, flags, false,
                    (hipStream_t)stream);
+    });
+}
+
+pano_status pano_search(pano_index *idx, const float *q_dev, int64_t nq, int32_t k, const int32_t *nprobe_dev,
+                        int32_t nprobe_all, float eps, int64_t *ids_dev, float *dists_dev,
+                        const pano_search_params *params, uint32_t flags, void *stream)
+{
+    if (!idx) {
+        set_error("null argument");
+        return PANO_EINVAL;
+    }
+    return pano_search_ctx(idx->ctx, idx, q_dev, nq, k, nprobe_dev, nprobe_all, eps, ids_dev, dists_dev, params,
+                           flags, stream);
+}
+
+pano_status pano_search_scratch_bytes(const pano_index *idx, int64_t nq, int32_t k, int32_t per_query_nprobe,
+                                      int32_t nprobe_all, const pano_search_params *params, int64_t *bytes)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx && bytes, "null argument");
+        PANO_REQUIRE(k >= 1 && nq >= 0, "need k >= 1 and nq >= 0");
+        PANO_REQUIRE(per_query_nprobe || nprobe_all >= 1, "nprobe_all must be >= 1");
+        *bytes = (int64_t)search_scratch_bytes(idx, nq, k, per_query_nprobe != 0, nprobe_all, params, false);
     });
 }
 
@@ -505,8 +536,8 @@ pano_status pano_search_bruteforce(pano_index *idx, const float *q_dev, int64_t 
         PANO_REQUIRE(k >= 1 && nq >= 0, "need k >= 1 and nq >= 0");
         PANO_REQUIRE(nprobe_dev != nullptr || nprobe_all >= 1, "nprobe_all must be >= 1");
         if (nq == 0) return;
-        run_search(idx, q_dev, nq, k, nprobe_dev, nprobe_all, 1.f, ids_dev, dists_dev, params, flags, true,
-                   (hipStream_t)stream);
+        run_search(idx->ctx, idx, q_dev, nq, k, nprobe_dev, nprobe_all, 1.f, ids_dev, dists_dev, params, flags,
+                   true, (hipStream_t)stream);
     });
 }
 

@@ -86,13 +86,14 @@ struct Margins {
 
 // Up to ten buffers cleared (or set to a 32-bit pattern) by one kernel.
 struct FillList {
-    void *p[10];
-    int64_t n[10];  // counts of 32-bit words
-    uint32_t v[10];
+    static constexpr int MAXSEG = 14;
+    void *p[MAXSEG];
+    int64_t n[MAXSEG];  // counts of 32-bit words
+    uint32_t v[MAXSEG];
     int m;
     void add(void *ptr, int64_t count, uint32_t val)
     {
-        if (m >= 10) throw Error{PANO_EUNSUPPORTED, "too many buffers to clear"};
+        if (m >= MAXSEG) throw Error{PANO_EUNSUPPORTED, "too many buffers to clear"};
         p[m] = ptr;
         n[m] = count;
         v[m] = val;
@@ -111,15 +112,15 @@ struct GraphKey {
     float eps;
     bool brute;
     const void *ids, *dists;
-    int G, bpi, seed_pool, seed_cnt, grid, dense_min, bf16;
-    const void *s0, *s1, *s2, *s3, *pinned;
+    int G, bpi, seed_pool, seed_cnt, grid, dense_min, bf16, split;
+    const void *s0, *s1, *s2, *s3, *s5, *s6, *pinned;
     bool operator==(const GraphKey &o) const
     {
         return ix_serial == o.ix_serial && q == o.q && nq == o.nq && k == o.k && npd == o.npd && np_all == o.np_all &&
                eps == o.eps && brute == o.brute && ids == o.ids && dists == o.dists && G == o.G && bpi == o.bpi &&
                seed_pool == o.seed_pool && seed_cnt == o.seed_cnt && grid == o.grid && dense_min == o.dense_min &&
-               bf16 == o.bf16 && s0 == o.s0 && s1 == o.s1 &&
-               s2 == o.s2 && s3 == o.s3 && pinned == o.pinned;
+               bf16 == o.bf16 && split == o.split && s0 == o.s0 && s1 == o.s1 &&
+               s2 == o.s2 && s3 == o.s3 && s5 == o.s5 && s6 == o.s6 && pinned == o.pinned;
     }
 };
 
@@ -201,6 +202,7 @@ struct pano_index {
     bool has_bf16 = false;
     std::vector<int32_t> m, mp, wp;          // cuts, padded cuts, padded widths
     std::vector<int64_t> list_len, list_blk; // list lengths, block offsets (nlist+1)
+    std::vector<int64_t> top_blk_prefix;     // [i]: blocks of the i largest lists together (nlist+1)
     int64_t nblocks = 0, max_list_len = 0, max_list_blocks = 0;
     pano::DevMem mu32, T32, cent, raw, levels, levels_bf16, tails, ids, blk_cnt, list_blk_d,
         list_len_d, meta;
@@ -249,9 +251,10 @@ void launch_pack(const float *Y, const float *tails_row, const int64_t *perm, co
                  float *levels, uint16_t *levels_bf16, float *tails, int32_t *ids, int32_t *blk_cnt,
                  hipStream_t s);
 
-struct SearchArgs;
-void run_search(pano_index *idx, const float *q, int64_t nq, int k, const int32_t *nprobe_dev,
+void run_search(pano_ctx *ctx, pano_index *idx, const float *q, int64_t nq, int k, const int32_t *nprobe_dev,
                 int nprobe_all, float eps, int64_t *ids, float *dists, const pano_search_params *prm,
                 uint32_t flags, bool brute, hipStream_t s);
+size_t search_scratch_bytes(const pano_index *ix, int64_t nq, int k, bool per_query_np, int nprobe_all,
+                            const pano_search_params *prm, bool brute);
 
 }  // namespace pano

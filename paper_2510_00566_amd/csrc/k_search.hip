@@ -215,6 +215,27 @@ __global__ void k_wl_fill(int64_t nq, int np_max, const int32_t *__restrict__ pr
     }
 }
 
+// Work-item table: item i of the queue-ordered numbering -> (list, query
+// group, block range), so a scan kernel decodes an item with one load.  One
+// workgroup per list position.
+__global__ __launch_bounds__(NT) void k_wl_items(int nlist, int ceil8, int G, int bpi,
+                                                 const int32_t *__restrict__ list_cnt,
+                                                 const int64_t *__restrict__ list_blk,
+                                                 const int64_t *__restrict__ item_off, int4 *__restrict__ items,
+                                                 int64_t items_max)
+{
+    const int pos = blockIdx.x;
+    const int l = (pos % ceil8) * 8 + pos / ceil8;
+    if (l >= nlist) return;
+    const int64_t base = item_off[pos], cnt = item_off[pos + 1] - base;
+    if (cnt <= 0) return;
+    const int groups = (list_cnt[l] + G - 1) / G;
+    // items_max bounds the count by construction; the test only keeps the
+    // writes inside the table
+    for (int64_t i = threadIdx.x; i < cnt && base + i < items_max; i += NT)
+        items[base + i] = make_int4(l, (int)(i % groups), (int)(i / groups), 0);
+}
+
 // ================================================================ index views
 struct IndexView {
     const float *levels;
@@ -347,6 +368,11 @@ struct WorkView {
     int32_t *buf_cnt;      // [nq]
     int32_t *flags;        // [nq]
     unsigned long long *stats;  // optional counters
+    // split scan: pairs that survive the dense levels, for the walk kernel
+    uint4 *pairs;          // [grid][seg_cap] {query, block, bits of the partial distance, slot}
+    int64_t seg_cap;       // pairs per workgroup segment
+    const int4 *items;     // work-item table {list, group, block range} (split scan)
+    int64_t items_max;
 };
 
 // Counters layout (unsigned long long): [0] items, [1] committed, [2] bytes,
@@ -356,31 +382,46 @@ constexpr int ST_ITEMS = 0, ST_COMMIT = 1, ST_BYTES = 2, ST_LEVEL = 8, ST_CYCLES
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 // Dot products of the (up to 16) queries of the group with 64 slots of the
-// block (this wavefront's share) over one level, on the matrix cores:
-// v_mfma_f32_16x16x4f32 with queries as rows and slots as columns.  The
-// reduction index is permuted so that each lane feeds four consecutive
-// dimensions from one 16-byte load: in the group of four steps t, lane
-// (r, q) supplies dimensions 16t + 4q .. 16t + 4q + 3 of query r (from LDS)
-// and of slot r (from the level tile: [group][slot][4] for level 1, slot-major
-// rows of row_w floats for later levels).  Each level is
-// summed in fresh accumulators before being added to acc (chunked sums).
-__device__ inline void level_dots(const float *__restrict__ tile, int B, int kg_count, const float4 *qrows,
-                                  int qstride, int wave_slot0, int lane, floatx4_t acc[4], int row_w = 0)
+// block (this wavefront's share) over one level of at most 64 dimensions
+// (kg_count <= 16 groups of four), on the matrix cores: v_mfma_f32_16x16x4f32
+// with queries as rows and slots as columns.  The reduction index is permuted
+// so that each lane feeds four consecutive dimensions from one 16-byte load:
+// in step t, lane (r, q) supplies dimensions 16t + 4q .. 16t + 4q + 3 of query
+// r (from LDS) and of slot r (from the level tile: [group][slot][4] for level
+// 1, slot-major rows of row_w floats for later levels).  qload(kg) returns
+// the four query values of group kg for this lane's query row.  The loads of
+// step t + 2 are issued before the products of step t, so two steps are
+// always in flight; a lane past the last group reads a valid group and feeds
+// zeros.  The level is summed in fresh accumulators and then added to acc
+// (chunked accumulation, as the error bound assumes); FRESH: acc is
+// overwritten.
+template <bool FRESH = false, typename QLoad>
+__device__ inline void level_dots(const float *__restrict__ tile, int B, int kg_count, QLoad qload, int wave_slot0,
+                                  int lane, floatx4_t acc[4], int row_w = 0)
 {
     const int r16 = lane & 15, kq = lane >> 4;
+    const int T = (kg_count + 3) >> 2;
+    auto fetch = [&](int t, float4 xa[4], float4 &qa) {
+        const int kg = 4 * t + kq;
+        const bool ok = kg < kg_count;
+        const int kgc = ok ? kg : kg_count - 1;
+        const float4 qv4 = qload(kgc);
+        qa = ok ? qv4 : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            // 32-bit offsets from the uniform tile base (a level tile is far
+            // below 4 GiB), so the loads can use scalar-base addressing
+            const uint32_t slot = (uint32_t)(wave_slot0 + nt * 16 + r16);
+            const uint32_t off = row_w ? slot * (uint32_t)row_w + (uint32_t)kgc * 4u
+                                       : ((uint32_t)kgc * (uint32_t)B + slot) * 4u;
+            const float4 v = *reinterpret_cast<const float4 *>(tile + off);
+            xa[nt] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
     floatx4_t part[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) part[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; 4 * t < kg_count; ++t) {
-        const int kg = 4 * t + kq;
-        const bool ok = kg < kg_count;
-        const float4 qa = ok ? qrows[r16 * qstride + kg] : make_float4(0.f, 0.f, 0.f, 0.f);
-        float4 xa[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-            xa[nt] = !ok ? make_float4(0.f, 0.f, 0.f, 0.f)
-                 : row_w ? *reinterpret_cast<const float4 *>(tile + (int64_t)(wave_slot0 + nt * 16 + r16) * row_w + kg * 4)
-                         : *reinterpret_cast<const float4 *>(tile + ((int64_t)kg * B + wave_slot0 + nt * 16 + r16) * 4);
+    auto products = [&](const float4 xa[4], const float4 &qa) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             part[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.x, xa[nt].x, part[nt], 0, 0, 0);
@@ -388,52 +429,64 @@ __device__ inline void level_dots(const float *__restrict__ tile, int B, int kg_
             part[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.z, xa[nt].z, part[nt], 0, 0, 0);
             part[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa.w, xa[nt].w, part[nt], 0, 0, 0);
         }
-    }
+    };
+    float4 xa0[4], xa1[4], qa0, qa1;
+    fetch(0, xa0, qa0);
+    if (T > 1) fetch(1, xa1, qa1);
+    products(xa0, qa0);
+    if (T > 2) fetch(2, xa0, qa0);
+    if (T > 1) products(xa1, qa1);
+    if (T > 3) fetch(3, xa1, qa1);
+    if (T > 2) products(xa0, qa0);
+    if (T > 3) products(xa1, qa1);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] += part[nt];
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = FRESH ? part[nt] : acc[nt] + part[nt];
 }
 
 // The same dot products from the bfloat16 copy x~ of the tiles on
-// v_mfma_f32_16x16x16bf16_1k.  Lane (r, q) feeds dimensions 16t + 4q .. +3 of
-// query r and of slot r.  The FP32 query is split into q_hi + q_lo, both
-// bfloat16 (|q - q_hi - q_lo| <= u_b^2 |q|), so the products are those with
-// x~ up to a u_b^2 relative term.  Each lane also sums the squares of the x~
-// values it feeds; ex[nt] ends as ||x~_level||^2 of slot nt*16 + r16 (summed
-// over the four lanes that share r16).
+// v_mfma_f32_16x16x16bf16_1k (one step covers 16 dimensions).  Lane (r, q)
+// feeds dimensions 16t + 4q .. +3 of query r and of slot r.  The FP32 query
+// is split into q_hi + q_lo, both bfloat16 (|q - q_hi - q_lo| <= u_b^2 |q|),
+// so the products are those with x~ up to a u_b^2 relative term.  Each lane
+// also sums the squares of the x~ values it feeds; ex[nt] ends as
+// ||x~_level||^2 of slot nt*16 + r16 (summed over the four lanes that share
+// r16).  Loads run two steps ahead as in level_dots; acc is overwritten.
 typedef short shortx4_t __attribute__((ext_vector_type(4)));
-__device__ inline void level_dots_bf16(const uint16_t *__restrict__ tile, int B, int kg_count, const float4 *qrows,
-                                       int qstride, int wave_slot0, int lane, floatx4_t acc[4], float ex[4],
-                                       int row_w = 0)
+template <typename QLoad>
+__device__ inline void level_dots_bf16(const uint16_t *__restrict__ tile, int B, int kg_count, QLoad qload,
+                                       int wave_slot0, int lane, floatx4_t acc[4], float ex[4], int row_w = 0)
 {
     const int r16 = lane & 15, kq = lane >> 4;
+    const int T = (kg_count + 3) >> 2;
+    auto fetch = [&](int t, uint2 xr[4], float4 &qf) {
+        const int kg = 4 * t + kq;
+        const bool ok = kg < kg_count;
+        const int kgc = ok ? kg : kg_count - 1;
+        const float4 qv4 = qload(kgc);
+        qf = ok ? qv4 : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const uint32_t slot = (uint32_t)(wave_slot0 + nt * 16 + r16);
+            const uint32_t off = row_w ? slot * (uint32_t)row_w + (uint32_t)kgc * 4u
+                                       : ((uint32_t)kgc * (uint32_t)B + slot) * 4u;
+            const uint2 v = *reinterpret_cast<const uint2 *>(tile + off);
+            xr[nt] = ok ? v : make_uint2(0u, 0u);
+        }
+    };
     floatx4_t part[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         part[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
         ex[nt] = 0.f;
     }
-    for (int t = 0; 4 * t < kg_count; ++t) {
-        const int kg = 4 * t + kq;
-        const bool ok = kg < kg_count;
-        const float4 qf = ok ? qrows[r16 * qstride + kg] : make_float4(0.f, 0.f, 0.f, 0.f);
+    auto products = [&](const uint2 xr[4], const float4 &qf) {
         shortx4_t qh, ql;
-        {
-            const float qv[4] = {qf.x, qf.y, qf.z, qf.w};
+        const float qv[4] = {qf.x, qf.y, qf.z, qf.w};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint16_t h = bf16_bits_rne(qv[e]);
-                qh[e] = (short)h;
-                ql[e] = (short)bf16_bits_rne(qv[e] - bf16_to_f32(h));
-            }
-        }
-        uint2 xr[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int slot = wave_slot0 + nt * 16 + r16;
-            xr[nt] = make_uint2(0u, 0u);
-            if (ok)
-                xr[nt] = row_w ? *reinterpret_cast<const uint2 *>(tile + (int64_t)slot * row_w + kg * 4)
-                               : *reinterpret_cast<const uint2 *>(tile + ((int64_t)kg * B + slot) * 4);
+        for (int e = 0; e < 4; ++e) {
+            const uint16_t h = bf16_bits_rne(qv[e]);
+            qh[e] = (short)h;
+            ql[e] = (short)bf16_bits_rne(qv[e] - bf16_to_f32(h));
         }
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
@@ -451,29 +504,95 @@ __device__ inline void level_dots_bf16(const uint16_t *__restrict__ tile, int B,
             ex[nt] = __builtin_fmaf(x2, x2, ex[nt]);
             ex[nt] = __builtin_fmaf(x3, x3, ex[nt]);
         }
-    }
+    };
+    uint2 xr0[4], xr1[4];
+    float4 qf0, qf1;
+    fetch(0, xr0, qf0);
+    if (T > 1) fetch(1, xr1, qf1);
+    products(xr0, qf0);
+    if (T > 2) fetch(2, xr0, qf0);
+    if (T > 1) products(xr1, qf1);
+    if (T > 3) fetch(3, xr1, qf1);
+    if (T > 2) products(xr0, qf0);
+    if (T > 3) products(xr1, qf1);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        acc[nt] += part[nt];
+        acc[nt] = part[nt];
         ex[nt] += __shfl_xor(ex[nt], 16, 64);
         ex[nt] += __shfl_xor(ex[nt], 32, 64);
     }
 }
 
-// Bounds for bfloat16 tiles.  With x~ the bfloat16 rounding of the stored
-// FP32 row x, ||x_h - x~_h|| <= delta = u_b ||x|| (plus a subnormal term), so
-// by the triangle inequality a certified bracket [s_lo, s_hi] of
-// ||q_h - x~_h||^2 gives one of ||q_h - x_h||^2.  The factors cover the FP32
-// square root and square.
-__device__ inline float bf_head_lower(float s_lo, float delta)
+// Refine one (query, candidate) pair level by level from lv_start (Algorithm 1
+// per candidate, Eq. 3 / Eq. 4 bounds with the certified margin), stopping
+// when its lower bound exceeds th.  sh enters as the head distance of levels
+// before lv_start and leaves as the head distance of the levels read; lv_end
+// is one past the last level read.  Returns true if the pair survives.
+template <bool BF>
+__device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__restrict__ blk,
+                                          const uint16_t *__restrict__ blk16, const float *__restrict__ tl, int ss,
+                                          const float *__restrict__ qrow, const float *qt, float th, float Aq,
+                                          int lv_start, float &sh, int &lv_end)
 {
-    const float r = fmaxf(__builtin_sqrtf(fmaxf(s_lo, 0.f)) * (1.f - 1e-6f) - delta, 0.f);
-    return r * r * (1.f - 1e-6f);
-}
-__device__ inline float bf_head_upper(float s_hi, float delta)
-{
-    const float r = __builtin_sqrtf(fmaxf(s_hi, 0.f)) * (1.f + 1e-6f) + delta;
-    return r * r * (1.f + 1e-6f);
+    const LevelGeom &g = c.g;
+    // four coordinates of level lv of slot ss (FP32 tile, or the bfloat16
+    // copy widened to FP32)
+    auto ld4 = [&](int lv, int c4) -> float4 {
+        const int64_t o = (int64_t)g.B * g.mp[lv] + (int64_t)ss * g.wp[lv] + c4 * 4;
+        if (BF) {
+            const uint2 xr = *reinterpret_cast<const uint2 *>(blk16 + o);
+            return make_float4(__uint_as_float(xr.x << 16), __uint_as_float(xr.x & 0xffff0000u),
+                               __uint_as_float(xr.y << 16), __uint_as_float(xr.y & 0xffff0000u));
+        }
+        return *reinterpret_cast<const float4 *>(blk + o);
+    };
+    auto level_part = [&](int lv) -> float {
+        const int w4 = g.wp[lv] >> 2;
+        const float *qq4 = qrow + g.mp[lv];
+        float part = 0.f;
+#pragma unroll 4
+        for (int c4 = 0; c4 < w4; ++c4) {
+            const float4 x4 = ld4(lv, c4);
+            const float4 q4 = *reinterpret_cast<const float4 *>(qq4 + c4 * 4);
+            float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+            part = __builtin_fmaf(t0, t0, part);
+            part = __builtin_fmaf(t1, t1, part);
+            part = __builtin_fmaf(t2, t2, part);
+            part = __builtin_fmaf(t3, t3, part);
+        }
+        return part;
+    };
+    // bfloat16 rows: ||x - x~|| <= u_b ||x||
+    const float delta = BF ? c.ub * tl[ss] + 1e-37f : 0.f;
+    int lv = lv_start;
+    for (; lv < g.L; ++lv) {
+        const bool last = (lv + 1 == g.L);
+        const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
+        sh += level_part(lv);
+        const float a = last ? 0.f : qt[lv + 1];
+        const float dt = a - b;
+        const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
+        const float ct = c.mg.c_tail * (a + b) * (a + b);
+        const bool pruned = BF ? bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct > th
+                               : (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
+        if (pruned) {
+            lv_end = lv + 1;
+            return false;
+        }
+        // Upper bound (the other side of Cauchy-Schwarz): UB =
+        // ||q_h - x_h||^2 + (||q_t|| + ||x_t||)^2 never grows with the level,
+        // and every later bound (any eps) stays below it.  Once UB is under
+        // the threshold the pair cannot be pruned any more: read the remaining
+        // levels without further tests.
+        const float ubh = BF ? bf_head_upper(sh + err, delta) : sh + err;
+        if (!last && ubh + (a + b) * (a + b) + ct <= th) {
+            for (int lv2 = lv + 1; lv2 < g.L; ++lv2) sh += level_part(lv2);
+            lv_end = g.L;
+            return true;
+        }
+    }
+    lv_end = lv;
+    return true;
 }
 
 template <bool PRUNE, bool BF>
@@ -502,20 +621,27 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
     const LevelGeom &g = c.g;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r16 = lane & 15, kq = lane >> 4;
+    // matrix-core operand of this lane's query row, from the staged slices
+    auto q_lds = [&](int kg) -> float4 { return qrow_s[r16][kg]; };
     int queue = blockIdx.x & 7;
     int tried = 0;
     unsigned long long my_items = 0, my_bytes = 0;
     const int Lc = g.L < 64 ? g.L : 64;
     for (int i = tid; i < 64; i += NT) my_lv[i] = 0;
     if (tid == 0) sparse_bytes_s = 0;
-    unsigned long long cyc[6] = {0, 0, 0, 0, 0, 0};
-    unsigned long long tmark = __builtin_readcyclecounter();
+    // phase cycle counters (thread 0, stats runs only) live in LDS so they
+    // hold no registers in the hot loops
+    __shared__ unsigned long long cyc[7];
+    if (tid == 0) {
+        for (int i = 0; i < 6; ++i) cyc[i] = 0;
+        cyc[6] = __builtin_readcyclecounter();
+    }
 #define PANO_PHASE(i)                                                  \
     do {                                                               \
         if (wk.stats && tid == 0) {                                    \
             unsigned long long now_ = __builtin_readcyclecounter();    \
-            cyc[i] += now_ - tmark;                                    \
-            tmark = now_;                                              \
+            cyc[i] += now_ - cyc[6];                                   \
+            cyc[6] = now_;                                             \
         }                                                              \
     } while (0)
 
@@ -609,23 +735,36 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             floatx4_t acc[4];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-            const int slot0 = wv * 64;
+            // opaque to the optimiser, so the tile addresses derived from it are
+            // recomputed per block instead of being held in registers
+            int slot0 = wv * 64;
+            asm volatile("" : "+v"(slot0));
             const bool wave_live = slot0 < cnt;
             uint32_t mask = 0;  // bit nt*4 + v: pair (query 4kq+v, slot slot0+nt*16+r16) kept
             float sval[16];
             int lv_start = 1;  // first level left to the per-pair walk
+            // tail norms of this lane's slots, requested before the products so
+            // that both loads are in flight together (every slot of a block has
+            // tails, 0 for an empty slot)
+            float tb0[4], tb1[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int sc = min(slot0 + nt * 16 + r16, g.B - 1);
+                tb0[nt] = tl[sc];
+                tb1[nt] = g.L > 1 ? tl[g.B + sc] : 0.f;
+            }
             if (PRUNE && BF) {
                 // level 1 from the bfloat16 tile: the dot-product form gives
                 // ||q_h - x~_h||^2 within A; the triangle inequality moves the
                 // bound to x
                 float ex[4] = {0.f, 0.f, 0.f, 0.f};
-                if (wave_live) level_dots_bf16(blk16, g.B, g.wp[0] >> 2, &qrow_s[0][0], 16, slot0, lane, acc, ex);
+                if (wave_live) level_dots_bf16(blk16, g.B, g.wp[0] >> 2, q_lds, slot0, lane, acc, ex);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
                     const int s = slot0 + nt * 16 + r16;
                     const bool valid = s < cnt;
-                    const float b0 = valid ? tl[s] : 0.f;
-                    const float b1 = (valid && g.L > 1) ? tl[g.B + s] : 0.f;
+                    const float b0 = valid ? tb0[nt] : 0.f;
+                    const float b1 = valid ? tb1[nt] : 0.f;
                     const float delta = c.ub * b0 + 1e-37f;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
@@ -646,13 +785,13 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     if (Lc > 0) my_lv[0] += (unsigned long long)cnt * ng;
                 }
             } else if (PRUNE) {
-                if (wave_live) level_dots(blk, g.B, g.wp[0] >> 2, &qrow_s[0][0], 16, slot0, lane, acc);
+                if (wave_live) level_dots<true>(blk, g.B, g.wp[0] >> 2, q_lds, slot0, lane, acc);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
                     const int s = slot0 + nt * 16 + r16;
                     const bool valid = s < cnt;
-                    const float b0 = valid ? tl[s] : 0.f;
-                    const float b1 = (valid && g.L > 1) ? tl[g.B + s] : 0.f;
+                    const float b0 = valid ? tb0[nt] : 0.f;
+                    const float b1 = valid ? tb1[nt] : 0.f;
                     const float rxh = b0 * b0 - b1 * b1;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
@@ -697,23 +836,30 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) acc2[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
                     float ex2[4] = {0.f, 0.f, 0.f, 0.f};
+                    const bool last = lv + 1 == g.L;
+                    // tails of this level and the next, requested before the products
+                    float tbl[4], tbn[4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int sc = min(slot0 + nt * 16 + r16, g.B - 1);
+                        tbl[nt] = tl[(int64_t)lv * g.B + sc];
+                        tbn[nt] = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + sc];
+                    }
                     if (wave_live) {
                         if (BF)
-                            level_dots_bf16(blk16 + (int64_t)g.B * g.mp[lv], g.B, kgc, &qrow_s[0][0], 16, slot0, lane,
-                                            acc2, ex2, g.wp[lv]);
+                            level_dots_bf16(blk16 + (int64_t)g.B * g.mp[lv], g.B, kgc, q_lds, slot0, lane, acc2, ex2,
+                                            g.wp[lv]);
                         else
-                            level_dots(blk + (int64_t)g.B * g.mp[lv], g.B, kgc, &qrow_s[0][0], 16, slot0, lane, acc2,
-                                       g.wp[lv]);
+                            level_dots<true>(blk + (int64_t)g.B * g.mp[lv], g.B, kgc, q_lds, slot0, lane, acc2, g.wp[lv]);
                     }
-                    const bool last = lv + 1 == g.L;
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) {
                         const int s = slot0 + nt * 16 + r16;
                         const bool valid = s < cnt;
-                        const float bl = valid ? tl[(int64_t)lv * g.B + s] : 0.f;
-                        const float bn = (valid && !last) ? tl[(int64_t)(lv + 1) * g.B + s] : 0.f;
+                        const float bl = valid ? tbl[nt] : 0.f;
+                        const float bn = valid ? tbn[nt] : 0.f;
                         const float rxl = BF ? ex2[nt] : bl * bl - bn * bn;
-                        const float delta = BF ? c.ub * (valid ? tl[s] : 0.f) + 1e-37f : 0.f;
+                        const float delta = BF ? c.ub * (valid ? tb0[nt] : 0.f) + 1e-37f : 0.f;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int b = nt * 4 + v;
@@ -761,9 +907,9 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         __syncthreads();
                         if (wave_live) {
                             if (lv == 0)
-                                level_dots(blk + (int64_t)base * 4 * g.B, g.B, kgn, &qrow_s[0][0], 16, slot0, lane, acc);
+                                level_dots(blk + (int64_t)base * 4 * g.B, g.B, kgn, q_lds, slot0, lane, acc);
                             else
-                                level_dots(blk + (int64_t)g.B * g.mp[lv] + base * 4, g.B, kgn, &qrow_s[0][0], 16, slot0,
+                                level_dots(blk + (int64_t)g.B * g.mp[lv] + base * 4, g.B, kgn, q_lds, slot0,
                                            lane, acc, g.wp[lv]);
                         }
                     }
@@ -810,184 +956,17 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             // after level, until its bound exceeds the threshold or the last
             // level is read (no barrier between levels; the Update and
             // Consolidate phases of Section 6.1 run once, after the walk)
-            if (PRUNE && BF) {
-                // the same walk over the bfloat16 tiles; a pair that survives
-                // every level, or whose upper bound proves it survives, is
-                // rescored from the FP32 tiles before it is committed
-                const int np_ = npairs_s;
-                unsigned long long my_sb = 0;
-                for (int p = tid; p < np_; p += NT) {
-                    const uint32_t pv = pr[p];
-                    const int gq = (int)(pv >> 8), ss = (int)(pv & 255u);
-                    const int qq = qid_s[gq];
-                    const float th = thr_s[gq], Aq = A_s[gq];
-                    const float *qrow = qv.qy + (int64_t)qq * g.d_pad;
-                    const float *qt = &qtl_s[gq][0];
-                    const float delta = c.ub * tl[ss] + 1e-37f;
-                    float sh = pS[p];
-                    bool alive = true;
-                    int lv = lv_start;
-                    for (; lv < g.L; ++lv) {
-                        const int w4 = g.wp[lv] >> 2;
-                        const uint16_t *x = blk16 + (int64_t)g.B * g.mp[lv] + (int64_t)ss * g.wp[lv];
-                        const float *qq4 = qrow + g.mp[lv];
-                        const bool last = (lv + 1 == g.L);
-                        const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
-                        float part = 0.f;
-#pragma unroll 4
-                        for (int c4 = 0; c4 < w4; ++c4) {
-                            const uint2 xr = *reinterpret_cast<const uint2 *>(x + c4 * 4);
-                            const float4 q4 = *reinterpret_cast<const float4 *>(qq4 + c4 * 4);
-                            const float t0 = q4.x - __uint_as_float(xr.x << 16);
-                            const float t1 = q4.y - __uint_as_float(xr.x & 0xffff0000u);
-                            const float t2 = q4.z - __uint_as_float(xr.y << 16);
-                            const float t3 = q4.w - __uint_as_float(xr.y & 0xffff0000u);
-                            part = __builtin_fmaf(t0, t0, part);
-                            part = __builtin_fmaf(t1, t1, part);
-                            part = __builtin_fmaf(t2, t2, part);
-                            part = __builtin_fmaf(t3, t3, part);
-                        }
-                        sh += part;
-                        const float a = last ? 0.f : qt[lv + 1];
-                        const float dt = a - b;
-                        const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
-                        const float ct = c.mg.c_tail * (a + b) * (a + b);
-                        const float lb = bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct;
-                        if (lb > th) {
-                            alive = false;
-                            ++lv;
-                            break;
-                        }
-                        if (!last && bf_head_upper(sh + err, delta) + (a + b) * (a + b) + ct <= th) {
-                            ++lv;
-                            break;
-                        }
-                    }
-                    if (alive) {
-                        // FP32 rescoring: every coordinate, level 1 from its
-                        // interleaved tile, the others slot-major
-                        float full = 0.f;
-                        for (int kg = 0; kg < (g.wp[0] >> 2); ++kg) {
-                            const float4 x4 = *reinterpret_cast<const float4 *>(blk + ((int64_t)kg * g.B + ss) * 4);
-                            const float4 q4 = *reinterpret_cast<const float4 *>(qrow + kg * 4);
-                            float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
-                            full = __builtin_fmaf(t0, t0, full);
-                            full = __builtin_fmaf(t1, t1, full);
-                            full = __builtin_fmaf(t2, t2, full);
-                            full = __builtin_fmaf(t3, t3, full);
-                        }
-                        for (int l2 = 1; l2 < g.L; ++l2) {
-                            const int w42 = g.wp[l2] >> 2;
-                            const float *x2 = blk + (int64_t)g.B * g.mp[l2] + (int64_t)ss * g.wp[l2];
-                            const float *q2 = qrow + g.mp[l2];
-#pragma unroll 4
-                            for (int c4 = 0; c4 < w42; ++c4) {
-                                const float4 x4 = *reinterpret_cast<const float4 *>(x2 + c4 * 4);
-                                const float4 q4 = *reinterpret_cast<const float4 *>(q2 + c4 * 4);
-                                float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
-                                full = __builtin_fmaf(t0, t0, full);
-                                full = __builtin_fmaf(t1, t1, full);
-                                full = __builtin_fmaf(t2, t2, full);
-                                full = __builtin_fmaf(t3, t3, full);
-                            }
-                        }
-                        sh = full;
-                    }
-                    keep[p] = alive ? 1 : 0;
-                    pS[p] = sh;
-                    if (wk.stats) {
-                        for (int v = lv_start; v < lv && v < 64; ++v) atomicAdd(&my_lv[v], 1ull);
-                        my_sb += (unsigned long long)(g.mp[lv < g.L ? lv : g.L] - g.mp[lv_start]) * 2ull +
-                                 (alive ? (unsigned long long)g.d_pad * 4ull : 0ull);
-                    }
-                }
-                if (wk.stats && my_sb) atomicAdd(&sparse_bytes_s, my_sb);
-                __syncthreads();
-                int kept = 0;
-                for (int base = 0; base < np_; base += NT) {
-                    const int i = base + tid;
-                    const bool f = i < np_ && keep[i];
-                    const uint32_t pv = f ? pr[i] : 0u;
-                    const float sv = f ? pS[i] : 0.f;
-                    int tot;
-                    int off = block_exclusive_scan(f ? 1 : 0, wave_tmp, &tot);
-                    if (f) {
-                        pr[kept + off] = pv;
-                        pS[kept + off] = sv;
-                    }
-                    kept += tot;
-                    __syncthreads();
-                }
-                if (tid == 0) npairs_s = kept;
-                __syncthreads();
-            } else if (PRUNE && lv_start < g.L) {
+            if (PRUNE && lv_start < g.L) {
                 const int np_ = npairs_s;
                 unsigned long long my_dims = 0;
                 for (int p = tid; p < np_; p += NT) {
                     const uint32_t pv = pr[p];
                     const int gq = (int)(pv >> 8), ss = (int)(pv & 255u);
                     const int qq = qid_s[gq];
-                    const float th = thr_s[gq], Aq = A_s[gq];
-                    const float *qrow = qv.qy + (int64_t)qq * g.d_pad;
-                    const float *qt = &qtl_s[gq][0];
                     float sh = pS[p];
-                    bool alive = true;
-                    int lv = lv_start;
-                    for (; lv < g.L; ++lv) {
-                        const int w4 = g.wp[lv] >> 2;
-                        const float *x = blk + (int64_t)g.B * g.mp[lv] + (int64_t)ss * g.wp[lv];
-                        const float *qq4 = qrow + g.mp[lv];
-                        const bool last = (lv + 1 == g.L);
-                        const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
-                        float part = 0.f;
-#pragma unroll 4
-                        for (int c4 = 0; c4 < w4; ++c4) {
-                            const float4 x4 = *reinterpret_cast<const float4 *>(x + c4 * 4);
-                            const float4 q4 = *reinterpret_cast<const float4 *>(qq4 + c4 * 4);
-                            float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
-                            part = __builtin_fmaf(t0, t0, part);
-                            part = __builtin_fmaf(t1, t1, part);
-                            part = __builtin_fmaf(t2, t2, part);
-                            part = __builtin_fmaf(t3, t3, part);
-                        }
-                        sh += part;
-                        const float a = last ? 0.f : qt[lv + 1];
-                        const float dt = a - b;
-                        const float lb = sh + dt * dt + c.one_m_eps2 * a * b;
-                        const float eta = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq + c.mg.c_tail * (a + b) * (a + b);
-                        if (lb - eta > th) {
-                            alive = false;
-                            ++lv;
-                            break;
-                        }
-                        // Upper bound (the other side of Cauchy-Schwarz): UB =
-                        // ||q_h - x_h||^2 + (||q_t|| + ||x_t||)^2 never grows with
-                        // the level, and every later bound (any eps) stays below
-                        // it.  Once UB is under the threshold the pair cannot be
-                        // pruned any more: read the remaining levels without
-                        // further tests.
-                        if (!last && sh + (a + b) * (a + b) + eta <= th) {
-                            for (int lv2 = lv + 1; lv2 < g.L; ++lv2) {
-                                const int w42 = g.wp[lv2] >> 2;
-                                const float *x2 = blk + (int64_t)g.B * g.mp[lv2] + (int64_t)ss * g.wp[lv2];
-                                const float *q2 = qrow + g.mp[lv2];
-                                float part2 = 0.f;
-#pragma unroll 4
-                                for (int c4 = 0; c4 < w42; ++c4) {
-                                    const float4 x4 = *reinterpret_cast<const float4 *>(x2 + c4 * 4);
-                                    const float4 q4 = *reinterpret_cast<const float4 *>(q2 + c4 * 4);
-                                    float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
-                                    part2 = __builtin_fmaf(t0, t0, part2);
-                                    part2 = __builtin_fmaf(t1, t1, part2);
-                                    part2 = __builtin_fmaf(t2, t2, part2);
-                                    part2 = __builtin_fmaf(t3, t3, part2);
-                                }
-                                sh += part2;
-                            }
-                            lv = g.L;
-                            break;
-                        }
-                    }
+                    int lv;
+                    const bool alive = walk_pair<BF>(c, blk, blk16, tl, ss, qv.qy + (int64_t)qq * g.d_pad, &qtl_s[gq][0],
+                                                     thr_s[gq], A_s[gq], lv_start, sh, lv);
                     keep[p] = alive ? 1 : 0;
                     pS[p] = sh;
                     if (wk.stats) {
@@ -995,7 +974,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         my_dims += (unsigned long long)(g.mp[lv < g.L ? lv : g.L] - g.mp[lv_start]);
                     }
                 }
-                if (wk.stats && my_dims) atomicAdd(&sparse_bytes_s, my_dims * 4ull);
+                if (wk.stats && my_dims) atomicAdd(&sparse_bytes_s, my_dims * (BF ? 2ull : 4ull));
                 __syncthreads();
                 // one stable compaction of the pairs that survived every level
                 int kept = 0;
@@ -1040,9 +1019,10 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         wave_bitonic_sort(SB, n2, lane);
                         const int keepn = min(c.kc, tot);
                         if (keepn >= c.k)
-                            tnew = fminf(tnew, prune_threshold(key_dist(SB[c.k - 1]), E_s[gq], A_s[gq], c.mg));
+                            tnew = fminf(tnew, prune_threshold(key_dist(SB[c.k - 1]), E_s[gq], A_s[gq], c.mg,
+                                                               c.bfdelta));
                         for (int i = c.kc + lane; i < tot; i += 64)
-                            if (dist_lower(key_dist(SB[i]), A_s[gq], c.mg) <= tnew) ovf = true;
+                            if (dist_lower(key_dist(SB[i]), A_s[gq], c.mg, c.bfdelta) <= tnew) ovf = true;
                         cntk = keepn;
                         napp = 0;
                         __builtin_amdgcn_wave_barrier();
@@ -1089,7 +1069,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             int nout = 0;
             for (int base = 0; base < cntk; base += 64) {
                 const int i = base + lane;
-                const bool f = i < cntk && dist_lower(key_dist(topk[gq * c.kc + i]), Aq, c.mg) <= t;
+                const bool f = i < cntk && dist_lower(key_dist(topk[gq * c.kc + i]), Aq, c.mg, c.bfdelta) <= t;
                 nout += __popcll(__ballot(f));
             }
             int basepos = 0;
@@ -1099,7 +1079,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             for (int base = 0; base < cntk; base += 64) {
                 const int i = base + lane;
                 const uint64_t key = i < cntk ? topk[gq * c.kc + i] : KEY_MAX;
-                const bool f = i < cntk && dist_lower(key_dist(key), Aq, c.mg) <= t;
+                const bool f = i < cntk && dist_lower(key_dist(key), Aq, c.mg, c.bfdelta) <= t;
                 const uint64_t bal = __ballot(f);
                 const int rk = __popcll(bal & ((1ull << lane) - 1ull));
                 if (f) {
@@ -1143,6 +1123,270 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 __global__ __launch_bounds__(NT) void k_scan_brute(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
 {
     scan_body<false, false>(c, ix, qv, wk);
+}
+
+// Split scan.  Each workgroup alternates between two phases over a private
+// segment of the pair list:
+//  * filter: level 1 of one block of a work item against the item's query
+//    group on the matrix cores with the Eq. 3 bound (Compute / Update /
+//    Consolidate of Section 6.1 for the first level); the surviving pairs
+//    are appended to the segment;
+//  * walk: once the segment cannot take another item (or the items are
+//    exhausted), its pairs are refined level-synchronously: one pass per
+//    level reads that level of every live pair, tests the bound with the
+//    certified margin and compacts the survivors in place; after the last
+//    level the survivors are published to their query's result buffer.
+// Every pass gives each pair exactly one level, so no lane idles behind a
+// longer walk, and the segment needs no atomics.  The workgroup's registers
+// fit four per SIMD.
+#ifndef SEG_WAVES
+#define SEG_WAVES 4
+#endif
+template <bool BF>
+__device__ __forceinline__ void seg_body(const SearchConsts &c, const IndexView &ix, const QueryView &qv,
+                                         const WorkView &wk)
+{
+    __shared__ float4 q1_s[GMAX][16];  // level-1 slices of the item's queries
+    __shared__ float a0_s[GMAX], a1_s[GMAX], thr_s[GMAX], A_s[GMAX];
+    __shared__ int qid_s[GMAX];
+    __shared__ int item_s;
+    __shared__ int wave_tmp[NT / 64];
+    __shared__ unsigned long long st_lv[64];
+    __shared__ unsigned long long st_misc[2];  // items, bytes
+    const LevelGeom &g = c.g;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int kg0 = g.wp[0] >> 2;
+    uint4 *seg = wk.pairs + (int64_t)blockIdx.x * wk.seg_cap;
+    int seg_n = 0;  // uniform across the workgroup
+    if (wk.stats) {
+        for (int i = tid; i < 64; i += NT) st_lv[i] = 0;
+        if (tid < 2) st_misc[tid] = 0;
+    }
+    auto q_lds = [&](int kg) -> float4 { return q1_s[r16][kg]; };
+
+    // ---- walk phase over the segment
+    auto walk = [&]() {
+        int n = seg_n;
+        for (int lv = 1; lv < g.L && n > 0; ++lv) {
+            const bool last = lv + 1 == g.L;
+            const int w4 = g.wp[lv] >> 2;
+            const int64_t lvoff = (int64_t)g.B * g.mp[lv];
+            if (wk.stats && tid == 0) {
+                st_lv[lv < 64 ? lv : 63] += (unsigned long long)n;
+                st_misc[1] += (unsigned long long)n * (g.wp[lv] * (BF ? 2 : 4) + 8);
+            }
+            int nout = 0;
+            for (int base = 0; base < n; base += NT) {
+                const int p = base + tid;
+                bool keep = false;
+                uint4 r = make_uint4(0u, 0u, 0u, 0u);
+                float sh = 0.f, th = 0.f, Aq = 0.f;
+                if (p < n) {
+                    r = seg[p];
+                    const int qq = (int)r.x;
+                    const int64_t gb = (int64_t)r.y;
+                    const int ss = (int)(r.w & 0xffffu);
+                    sh = __uint_as_float(r.z);
+                    const float *tl = ix.tails + gb * (int64_t)g.B * g.L;
+                    const float *qrow = qv.qy + (int64_t)qq * g.d_pad + g.mp[lv];
+                    const int64_t xo = gb * (int64_t)g.B * g.d_pad + lvoff + (int64_t)ss * g.wp[lv];
+                    const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
+                    const float a = last ? 0.f : qv.qtail[(int64_t)qq * g.L + lv + 1];
+                    th = __hip_atomic_load(&wk.thr[qq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    Aq = qv.qA[qq];
+                    const float delta = BF ? c.ub * tl[ss] + 1e-37f : 0.f;
+                    float part = 0.f;
+#pragma unroll 4
+                    for (int c4 = 0; c4 < w4; ++c4) {
+                        float4 x4;
+                        if (BF) {
+                            const uint2 xr = *reinterpret_cast<const uint2 *>(ix.levels16 + xo + c4 * 4);
+                            x4 = make_float4(__uint_as_float(xr.x << 16), __uint_as_float(xr.x & 0xffff0000u),
+                                             __uint_as_float(xr.y << 16), __uint_as_float(xr.y & 0xffff0000u));
+                        } else {
+                            x4 = *reinterpret_cast<const float4 *>(ix.levels + xo + c4 * 4);
+                        }
+                        const float4 q4 = *reinterpret_cast<const float4 *>(qrow + c4 * 4);
+                        float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                        part = __builtin_fmaf(t0, t0, part);
+                        part = __builtin_fmaf(t1, t1, part);
+                        part = __builtin_fmaf(t2, t2, part);
+                        part = __builtin_fmaf(t3, t3, part);
+                    }
+                    sh += part;
+                    const float dt = a - b;
+                    const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
+                    const float ct = c.mg.c_tail * (a + b) * (a + b);
+                    const bool pruned = BF ? bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct > th
+                                           : (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
+                    keep = !pruned;
+                }
+                if (last) {
+                    if (keep) {
+                        const int qq = (int)r.x;
+                        const float dsh = fmaxf(sh, 0.f);
+                        if (dist_lower(dsh, Aq, c.mg, c.bfdelta) <= th) {
+                            const int dst = atomicAdd(&wk.buf_cnt[qq], 1);
+                            if (dst < c.capq)
+                                wk.buf[(int64_t)qq * c.capq + dst] =
+                                    make_key(dsh, ix.ids[(int64_t)r.y * g.B + (r.w & 0xffffu)]);
+                            else
+                                atomicOr(&wk.flags[qq], FLAG_OVERFLOW);
+                        }
+                    }
+                } else {
+                    // in-place compaction: every read of this chunk precedes
+                    // the scan's barrier, and the writes land below the chunk
+                    int tot;
+                    const int off = block_exclusive_scan(keep ? 1 : 0, wave_tmp, &tot);
+                    if (keep) seg[nout + off] = make_uint4(r.x, r.y, __float_as_uint(sh), r.w);
+                    nout += tot;
+                }
+            }
+            n = nout;
+            __syncthreads();
+        }
+        seg_n = 0;
+    };
+
+    int queue = blockIdx.x & 7;
+    int tried = 0;
+    while (true) {
+        if (tid == 0) {
+            int it = -1;
+            while (tried < 8) {
+                const int64_t qb = wk.item_off[queue * c.ceil8], qe = wk.item_off[(queue + 1) * c.ceil8];
+                if (qe > qb) {
+                    const int v = atomicAdd(&wk.heads[queue], 1);
+                    if (qb + v < qe) {
+                        it = (int)(qb + v);
+                        break;
+                    }
+                }
+                queue = (queue + 1) & 7;
+                ++tried;
+            }
+            item_s = (it >= 0 && it < wk.items_max) ? it : -1;
+        }
+        __syncthreads();
+        const int item = item_s;
+        if (item < 0) break;
+        const int4 desc = wk.items[item];
+        const int l = desc.x, gi = desc.y;
+        const int64_t gb = ix.list_blk[l] + desc.z;  // one block per item in the split scan
+        const int cnt = ix.blk_cnt[gb];
+        const int ng = min(c.G, wk.list_cnt[l] - gi * c.G);
+        // a full segment is walked before it takes another item
+        if (seg_n + ng * cnt > wk.seg_cap) walk();
+        const int64_t qoff = wk.list_qoff[l] + (int64_t)gi * c.G;
+        {
+            // thread (gq, c4): query gq's id, then its level-1 group c4
+            const int gq = tid >> 4, c4 = tid & 15;
+            const int qq = gq < ng ? wk.list_q[qoff + gq] : -1;
+            q1_s[gq][c4] = (qq >= 0 && c4 < kg0)
+                               ? *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qq * g.d_pad + c4 * 4)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (c4 == 0) {
+                qid_s[gq] = qq;
+                thr_s[gq] = qq >= 0 ? __hip_atomic_load(&wk.thr[qq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.f;
+                A_s[gq] = qq >= 0 ? qv.qA[qq] : 0.f;
+                a0_s[gq] = qq >= 0 ? qv.qtail[(int64_t)qq * g.L] : 0.f;
+                a1_s[gq] = (qq >= 0 && g.L > 1) ? qv.qtail[(int64_t)qq * g.L + 1] : 0.f;
+            }
+        }
+        const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
+        const uint16_t *blk16 = BF ? ix.levels16 + gb * (int64_t)g.B * g.d_pad : nullptr;
+        const float *tl = ix.tails + gb * (int64_t)g.B * g.L;
+        // opaque to the optimiser, so the tile addresses derived from it are
+        // recomputed per item instead of being held in registers across items
+        int slot0 = wv * 64;
+        asm volatile("" : "+v"(slot0));
+        const bool wave_live = slot0 < cnt;
+        float tb0[4], tb1[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int sc = min(slot0 + nt * 16 + r16, g.B - 1);
+            tb0[nt] = tl[sc];
+            tb1[nt] = tl[g.B + sc];  // L >= 2 in the split scan
+        }
+        __syncthreads();
+        floatx4_t acc[4];
+        float ex[4] = {0.f, 0.f, 0.f, 0.f};
+        uint32_t mask = 0;
+        float sval[16];
+        if (wave_live) {
+            if (BF)
+                level_dots_bf16(blk16, g.B, kg0, q_lds, slot0, lane, acc, ex);
+            else
+                level_dots<true>(blk, g.B, kg0, q_lds, slot0, lane, acc);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int s = slot0 + nt * 16 + r16;
+                const bool valid = s < cnt;
+                const float b0 = valid ? tb0[nt] : 0.f;
+                const float b1 = valid ? tb1[nt] : 0.f;
+                const float rxh = BF ? ex[nt] : b0 * b0 - b1 * b1;
+                const float delta = BF ? c.ub * b0 + 1e-37f : 0.f;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int gq = 4 * kq + v;
+                    const bool on = valid && gq < ng;
+                    const float a0 = a0_s[gq], a1 = a1_s[gq];
+                    const float sh = (on ? a0 * a0 - a1 * a1 : 0.f) + rxh - 2.f * acc[nt][v];
+                    const float dt = a1 - b1;
+                    bool sv;
+                    if (BF) {
+                        const float hl = bf_head_lower(sh - A_s[gq], delta);
+                        sv = hl + dt * dt + c.one_m_eps2 * a1 * b1 - c.mg.c_tail * (a1 + b1) * (a1 + b1) <= thr_s[gq];
+                    } else {
+                        const float lb = sh + dt * dt + c.one_m_eps2 * a1 * b1;
+                        const float eta = A_s[gq] + c.mg.c_tail * (a1 + b1) * (a1 + b1);
+                        sv = lb - eta <= thr_s[gq];
+                    }
+                    mask |= (uint32_t)(on && sv) << (nt * 4 + v);
+                    sval[nt * 4 + v] = sh;
+                }
+            }
+        }
+        // ---- append the survivors to the segment
+        int tot;
+        int off = block_exclusive_scan(__popc(mask), wave_tmp, &tot);
+        if (wk.stats && tid == 0) {
+            st_misc[0] += 1;
+            st_lv[0] += (unsigned long long)cnt * ng;
+            st_misc[1] += (unsigned long long)cnt * (g.wp[0] * (BF ? 2 : 4) + 8);
+        }
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            if (!(mask & (1u << b))) continue;
+            const int nt = b >> 2, v = b & 3;
+            seg[seg_n + off] = make_uint4((uint32_t)qid_s[4 * kq + v], (uint32_t)gb, __float_as_uint(sval[b]),
+                                          (uint32_t)(slot0 + nt * 16 + r16));
+            ++off;
+        }
+        seg_n += tot;
+        __syncthreads();
+    }
+    if (seg_n > 0) walk();
+    if (wk.stats && tid == 0) {
+        atomicAdd(&wk.stats[ST_ITEMS], st_misc[0]);
+        atomicAdd(&wk.stats[ST_BYTES], st_misc[1]);
+        for (int i = 0; i < 64 && i < g.L; ++i)
+            if (st_lv[i]) atomicAdd(&wk.stats[ST_LEVEL + i], st_lv[i]);
+    }
+}
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SEG_WAVES, SEG_WAVES))) void k_scan_seg(
+    SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    seg_body<false>(c, ix, qv, wk);
+}
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SEG_WAVES, SEG_WAVES))) void k_scan_seg_bf16(
+    SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    seg_body<true>(c, ix, qv, wk);
 }
 
 // ================================================================ merge
@@ -1189,10 +1433,11 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
                                               int d, int64_t *__restrict__ out_ids, float *__restrict__ out_d,
                                               unsigned long long *stats)
 {
+    // dynamic LDS: [MERGE_LDS_KEYS keys][d floats of the raw query]
     extern __shared__ uint64_t K[];
     __shared__ int nb_s;
     __shared__ int hist[256], sel[2];
-    __shared__ float qrow[4096];
+    float *qrow = reinterpret_cast<float *>(K + MERGE_LDS_KEYS);
     const int64_t q = blockIdx.x;
     for (int j = threadIdx.x; j < d; j += NT) qrow[j] = qraw[q * d + j];
     const int n_all = buf_cnt[q];
@@ -1204,12 +1449,12 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
     int n = n_all;
     if (n > MERGE_LDS_KEYS) {
         const float dk = __uint_as_float(block_kth_dist_bits(bq, n, c.k, hist, sel));
-        const float cut = prune_threshold(dk, qE[q], qA[q], c.mg);
+        const float cut = prune_threshold(dk, qE[q], qA[q], c.mg, c.bfdelta);
         if (threadIdx.x == 0) nb_s = 0;
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += NT) {
             const uint64_t key = bq[i];
-            if (dist_lower(key_dist(key), qA[q], c.mg) <= cut) {
+            if (dist_lower(key_dist(key), qA[q], c.mg, c.bfdelta) <= cut) {
                 const int pos = atomicAdd(&nb_s, 1);
                 if (pos < MERGE_LDS_KEYS) K[pos] = key;
             }
@@ -1232,14 +1477,14 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
     const int P = next_pow2(n > 0 ? n : 1);
     block_bitonic_sort(K, P);
     const float Aq = qA[q];
-    const float thr = n >= c.k ? prune_threshold(key_dist(K[c.k - 1]), qE[q], Aq, c.mg) : INFINITY;
+    const float thr = n >= c.k ? prune_threshold(key_dist(K[c.k - 1]), qE[q], Aq, c.mg, c.bfdelta) : INFINITY;
     if (threadIdx.x == 0) nb_s = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += NT)
-        if (dist_lower(key_dist(K[i]), Aq, c.mg) <= thr) atomicMax(&nb_s, i + 1);
+        if (dist_lower(key_dist(K[i]), Aq, c.mg, c.bfdelta) <= thr) atomicMax(&nb_s, i + 1);
     __syncthreads();
     const int nb = nb_s;
-    if (nb > 4096) {
+    if (nb > MERGE_LDS_KEYS) {
         if (threadIdx.x == 0) atomicOr(&flags[q], FLAG_OVERFLOW);
         return;
     }
@@ -1366,29 +1611,44 @@ struct Carver {
     }
 };
 
-void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t *nprobe_dev, int nprobe_all,
-                float eps, int64_t *ids, float *dists, const pano_search_params *prm, uint32_t flags, bool brute,
-                hipStream_t s)
+// Launch constants and scratch sizes of one search (no device work).
+struct SearchPlan {
+    size_t need[6];     // bytes of scratch slots 0..3 and of the split scan's pair list and item table
+    bool split;         // split scan (filter kernel + per-pair walk) instead of the persistent scan
+    int grid_seg;       // workgroups of the split scan
+    int64_t seg_cap;    // pairs per workgroup segment
+    int64_t items_max;  // work items the item table holds
+};
+
+static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_np, int nprobe_all, float eps,
+                        const pano_search_params *prm, bool brute, SearchConsts &c, SearchPlan &pl)
 {
-    pano_ctx *ctx = ix->ctx;
-    PANO_HIP(hipSetDevice(ctx->device));
     PANO_REQUIRE(k <= 128, "k up to 128 is supported");
     const int d = ix->d, L = ix->L, nlist = ix->nlist;
-    SearchConsts c{};
+    size_t *need = pl.need;
+    c = SearchConsts{};
     c.k = k;
     c.kc = next_pow2(std::max(2 * k, 16));
     int G = 16;
     while (G > 1 && G * c.kc > 2048) G >>= 1;
     if (prm && prm->group > 0) G = std::min(prm->group, G);
     c.G = G;
-    c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1;
+    // scan mode: 1 = persistent scan (dense levels, per-pair walk and local
+    // top-k in one kernel), 2 = segmented split scan (level-1 filter into a
+    // per-workgroup segment, then level-synchronous passes over it, d_k from
+    // the seeding only); 0 = the persistent scan, the faster of the two on
+    // the workloads measured
+    const int mode_req = prm ? prm->reserved[1] : 0;
+    pl.split = !brute && L >= 2 && mode_req == 2;
+    // the split scan's filter works on one block per item
+    c.bpi = pl.split ? 1 : ((prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1);
     // Per-query result buffer: a work item publishes about k entries (its
     // local best k and their margin band), and a query meets about
     // nprobe * ceil(mean blocks per list / bpi) work items.  Twice that
     // estimate, within [2048, 65536] and 4 GiB over the batch; a query that
     // still overflows takes the exact fallback.
     {
-        const int np_est = nprobe_dev ? std::min(nlist, 128) : std::min(nprobe_all, nlist);
+        const int np_est = per_query_np ? std::min(nlist, 128) : std::min(nprobe_all, nlist);
         const double mean_blk = (double)ix->list_blk.back() / std::max(1, nlist);
         const double items = (double)np_est * (std::ceil(mean_blk / c.bpi) + 1.0);
         const double want = 2.0 * items * (k + 8);
@@ -1408,6 +1668,75 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     PANO_REQUIRE(!use_bf16 || ix->has_bf16, "bfloat16 search needs an index built with PANO_BF16");
     c.bf16 = use_bf16 ? 1 : 0;
     c.ub = (float)(std::ldexp(1.0, -8) * (1.0 + 1e-6));
+    // committed distances of the bfloat16 scan are to the rounded rows; their
+    // bracket widens by u_b max ||x|| on the square root
+    c.bfdelta = use_bf16 ? (float)((double)c.ub * std::sqrt((double)ix->mg.b0max2) * (1.0 + 1e-6) + 1e-37) : 0.f;
+    c.g = LevelGeom{};
+    c.g.L = L;
+    c.g.d = d;
+    c.g.d_pad = ix->d_pad;
+    c.g.B = ix->B;
+    for (int l = 0; l <= L; ++l) c.g.mp[l] = ix->mp[l];
+    for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
+    const int np_max = per_query_np ? nlist : std::min(nprobe_all, nlist);
+    need[0] = align_up(sizeof(float) * nq * ix->d_pad) + align_up(sizeof(float) * nq * L) +
+              3 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
+    need[1] = nlist > 1 ? align_up(sizeof(float) * nq * nlist) : 256;
+    need[2] = align_up(sizeof(int32_t) * nq * np_max) * 2 + align_up(sizeof(int32_t) * nq) +
+              2 * align_up(sizeof(int32_t) * nlist) + align_up(sizeof(int32_t) * 8) +
+              align_up(sizeof(int64_t) * (nlist + 1)) + align_up(sizeof(int64_t) * (8 * c.ceil8 + 1));
+    need[3] = 3 * align_up(sizeof(float) * nq) + align_up(sizeof(uint64_t) * nq * c.capq) +
+              align_up(sizeof(unsigned long long) * 128) + align_up(sizeof(int));
+    pl.grid_seg = 0;
+    pl.seg_cap = 0;
+    pl.items_max = 0;
+    need[4] = need[5] = 0;
+    if (pl.split) {
+        // one segment per workgroup: room for at least two items' worth of
+        // survivors (a full segment is walked before the next item), sized
+        // for an eighth of the candidates passing the first level, at most
+        // 2 GiB in all
+        pl.grid_seg = (prm && prm->grid > 0) ? prm->grid : ix->ctx->num_cu * SEG_WAVES;
+        const int np_est = per_query_np ? std::min(nlist, 128) : std::min(nprobe_all, nlist);
+        const double mean_len = (double)ix->n / std::max(1, nlist);
+        const double want = (double)nq * np_est * mean_len / 8.0 / pl.grid_seg;
+        int64_t cap = 2LL * c.G * ix->B;
+        while (cap < want && cap < 65536) cap <<= 1;
+        while (cap > 2LL * c.G * ix->B && (double)cap * pl.grid_seg * 16.0 > 2.0 * 1073741824.0) cap >>= 1;
+        pl.seg_cap = cap;
+        need[4] = align_up(sizeof(uint4) * (size_t)(pl.seg_cap * pl.grid_seg));
+        // item table: sum over lists of ceil(queries / G) * blocks is at most
+        // nq * (blocks of the np_max largest lists) / G + all blocks
+        const int64_t s_np = ix->top_blk_prefix[std::min<int64_t>(np_max, nlist)];
+        pl.items_max = ((int64_t)nq * s_np + c.G - 1) / c.G + ix->nblocks;
+        need[5] = align_up(sizeof(int4) * (size_t)std::max<int64_t>(1, pl.items_max));
+    }
+}
+
+size_t search_scratch_bytes(const pano_index *ix, int64_t nq, int k, bool per_query_np, int nprobe_all,
+                            const pano_search_params *prm, bool brute)
+{
+    SearchConsts c;
+    SearchPlan pl;
+    plan_search(ix, nq, k, per_query_np, nprobe_all, 1.f, prm, brute, c, pl);
+    size_t t = 0;
+    for (int i = 0; i < 6; ++i) t += pl.need[i];
+    return t;
+}
+
+void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k, const int32_t *nprobe_dev,
+                int nprobe_all, float eps, int64_t *ids, float *dists, const pano_search_params *prm,
+                uint32_t flags, bool brute, hipStream_t s)
+{
+    PANO_REQUIRE(ctx->device == ix->ctx->device, "context and index are on different devices");
+    PANO_HIP(hipSetDevice(ctx->device));
+    const int d = ix->d, L = ix->L, nlist = ix->nlist;
+    SearchConsts c;
+    SearchPlan pl;
+    plan_search(ix, nq, k, nprobe_dev != nullptr, nprobe_all, eps, prm, brute, c, pl);
+    const size_t *need = pl.need;
+    const bool use_bf16 = c.bf16 != 0;
+    const bool split = pl.split;
     // Absolute margin of the dot-product form: the bfloat16 scan splits each
     // query value into two bfloat16 terms and reads rows of norm up to
     // (1 + u_b) ||x||, which its own constant covers.
@@ -1417,29 +1746,19 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         mq.b0max2 = (float)((double)ix->mg.b0max2 * (1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -8)) *
                             (1.0 + 1e-6));
     }
-    c.g = LevelGeom{};
-    c.g.L = L;
-    c.g.d = d;
-    c.g.d_pad = ix->d_pad;
-    c.g.B = ix->B;
-    for (int l = 0; l <= L; ++l) c.g.mp[l] = ix->mp[l];
-    for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
     const int seed_pool = std::min(1024, (prm && prm->seed_pool > 0) ? prm->seed_pool : 512);
     const int seed_cnt = std::min(256, std::max(k, (prm && prm->seed_count > 0) ? prm->seed_count : std::max(2 * k, 32)));
     const int grid = (prm && prm->grid > 0) ? prm->grid : ctx->num_cu * (brute ? 2 : 3);
     const int np_max = nprobe_dev ? nlist : std::min(nprobe_all, nlist);
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
     const bool seed_on = !brute && eps >= 1.f;
+    if (split) {
+        ctx->scratch[5].ensure(need[4]);
+        ctx->scratch[6].ensure(need[5]);
+    }
 
     // ---- scratch
-    size_t need0 = align_up(sizeof(float) * nq * ix->d_pad) + align_up(sizeof(float) * nq * L) +
-                   3 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
-    size_t need1 = nlist > 1 ? align_up(sizeof(float) * nq * nlist) : 256;
-    size_t need2 = align_up(sizeof(int32_t) * nq * np_max) * 2 + align_up(sizeof(int32_t) * nq) +
-                   2 * align_up(sizeof(int32_t) * nlist) + align_up(sizeof(int32_t) * 8) +
-                   align_up(sizeof(int64_t) * (nlist + 1)) + align_up(sizeof(int64_t) * (8 * c.ceil8 + 1));
-    size_t need3 = 3 * align_up(sizeof(float) * nq) + align_up(sizeof(uint64_t) * nq * c.capq) +
-                   align_up(sizeof(unsigned long long) * 128) + align_up(sizeof(int));
+    const size_t need0 = need[0], need1 = need[1], need2 = need[2], need3 = need[3];
     ctx->scratch[0].ensure(need0);
     ctx->scratch[1].ensure(need1);
     ctx->scratch[2].ensure(need2);
@@ -1475,7 +1794,7 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
     const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
     const size_t coarse_shm = per_wave * wpb;
     PANO_REQUIRE(nlist == 1 || coarse_shm <= 160 * 1024, "nlist too large for the coarse step");
-    const size_t merge_shm = sizeof(uint64_t) * std::min(next_pow2(c.capq), MERGE_LDS_KEYS);
+    const size_t merge_shm = sizeof(uint64_t) * MERGE_LDS_KEYS + sizeof(float) * (size_t)d;
     const size_t scan_shm = sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
     if (nlist > 1)
         PANO_HIP(hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_shm));
@@ -1486,6 +1805,15 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
                  ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
     QueryView qv{qy, qtail, qE, qA, q};
     WorkView wk{list_cnt, list_qoff, list_q, item_off, heads, thr, buf, buf_cnt, qflags, nullptr};
+    int4 *items = nullptr;
+    if (split) {
+        Carver c5(ctx->scratch[5].p);
+        wk.pairs = c5.take<uint4>(pl.seg_cap * pl.grid_seg);
+        wk.seg_cap = pl.seg_cap;
+        items = ctx->scratch[6].as<int4>();
+        wk.items = items;
+        wk.items_max = pl.items_max;
+    }
 
     // Every device step of one search, in order, on stream st.  No memset
     // nodes: buffers are cleared by a fill kernel so the sequence can be
@@ -1538,13 +1866,21 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
                            ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
         hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_qoff, list_fill,
                            list_q);
+        if (split)
+            hipLaunchKernelGGL(k_wl_items, dim3((unsigned)(8 * c.ceil8)), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi,
+                               list_cnt, ix->list_blk_d.as<int64_t>(), item_off, items, pl.items_max);
         if (seed_on) PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[1], st));
         WorkView w2 = wk;
         w2.stats = stats_on ? stats : nullptr;
-        if (brute)
+        if (brute) {
             hipLaunchKernelGGL(k_scan_brute, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
-        else if (use_bf16)
+        } else if (split) {
+            if (use_bf16)
+                hipLaunchKernelGGL(k_scan_seg_bf16, dim3(pl.grid_seg), dim3(NT), 0, st, c, iv, qv, w2);
+            else
+                hipLaunchKernelGGL(k_scan_seg, dim3(pl.grid_seg), dim3(NT), 0, st, c, iv, qv, w2);
+        } else if (use_bf16)
             hipLaunchKernelGGL(k_scan_pruned_bf16, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
         else
             hipLaunchKernelGGL(k_scan_pruned, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
@@ -1566,7 +1902,8 @@ void run_search(pano_index *ix, const float *q, int64_t nq, int k, const int32_t
         enqueue(ws, true);
     } else if (!(flags & PANO_SEARCH_EAGER)) {
         GraphKey key{ix->serial, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
-                     c.dense_min, c.bf16, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p, ctx->pinned};
+                     c.dense_min, c.bf16, split ? 1 : 0, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
+                     split ? ctx->scratch[5].p : nullptr, split ? ctx->scratch[6].p : nullptr, ctx->pinned};
         if (!ctx->graph_exec || !(ctx->graph_key == key)) {
             ctx->drop_graph();
             hipGraph_t graph;

@@ -7,7 +7,7 @@
 namespace pano {
 
 constexpr int NT = 256;         // threads per workgroup (4 wavefronts)
-constexpr int MERGE_LDS_KEYS = 4096;  // entries the merge sorts in LDS
+constexpr int MERGE_LDS_KEYS = 2048;  // entries the merge sorts in LDS
 constexpr int GMAX = 16;        // max queries per scan work item
 constexpr int SB_MAX = 512;     // per-wave sort buffer (entries)
 constexpr uint64_t KEY_MAX = ~0ull;
@@ -43,6 +43,7 @@ struct SearchConsts {
     int dense_min;     // refine a level densely while at least this many pairs survive
     int bf16;          // 1: read level tiles in bfloat16 (certified margin, FP32 rescoring)
     float ub;          // bfloat16 unit roundoff 2^-8, rounded up (covers the stored-norm rounding)
+    float bfdelta;     // bfloat16 scan: u_b max ||x|| (0 for the FP32 scan)
     float eps;
     float one_m_eps2;  // 2 (1 - eps)
     Margins mg;
@@ -105,16 +106,36 @@ __device__ inline float canon_dist_stream(const float *q_lds, const float *__res
     return (float)s;
 }
 
+// Bounds for bfloat16 tiles.  With x~ the bfloat16 rounding of the stored
+// FP32 row x, ||x_h - x~_h|| <= delta = u_b ||x|| (plus a subnormal term), so
+// by the triangle inequality a certified bracket [s_lo, s_hi] of
+// ||q_h - x~_h||^2 gives one of ||q_h - x_h||^2.  The factors cover the FP32
+// square root and square.
+__device__ inline float bf_head_lower(float s_lo, float delta)
+{
+    const float r = fmaxf(__builtin_sqrtf(fmaxf(s_lo, 0.f)) * (1.f - 1e-6f) - delta, 0.f);
+    return r * r * (1.f - 1e-6f);
+}
+__device__ inline float bf_head_upper(float s_hi, float delta)
+{
+    const float r = __builtin_sqrtf(fmaxf(s_hi, 0.f)) * (1.f + 1e-6f) + delta;
+    return r * r * (1.f + 1e-6f);
+}
+
 // Error model of a computed stored-frame distance Dt of a query with absolute
 // margin A (dot-product form): the exact value lies in
-// [(Dt - A)(1 - c_final), (Dt + A)(1 + c_final)].
-__device__ inline float dist_upper(float Dt, float A, const Margins &mg)
+// [(Dt - A)(1 - c_final), (Dt + A)(1 + c_final)].  A distance computed from
+// bfloat16 rows (dl > 0, dl >= u_b max ||x||) is to the rounded row; the
+// triangle inequality widens the bracket by dl on the square root.
+__device__ inline float dist_upper(float Dt, float A, const Margins &mg, float dl = 0.f)
 {
-    return (Dt + A) * (1.f + mg.c_final) * (1.f + 1e-6f);
+    const float u = (Dt + A) * (1.f + mg.c_final) * (1.f + 1e-6f);
+    return dl == 0.f ? u : bf_head_upper(u, dl);
 }
-__device__ inline float dist_lower(float Dt, float A, const Margins &mg)
+__device__ inline float dist_lower(float Dt, float A, const Margins &mg, float dl = 0.f)
 {
-    return (Dt - A) * (1.f - mg.c_final);
+    const float l = (Dt - A) * (1.f - mg.c_final);
+    return dl == 0.f ? l : bf_head_lower(l, dl);
 }
 
 // Pruning threshold tau^2 from the k-th best computed distance Dk: with
@@ -122,10 +143,10 @@ __device__ inline float dist_lower(float Dt, float A, const Margins &mg)
 // transform, tau = E + rho (sqrt(upper(Dk)) + E).  A candidate whose lower
 // bound exceeds tau^2 has a canonical distance above that of k committed
 // candidates.  Slack covers the FP32 evaluation of the formula itself.
-__device__ inline float prune_threshold(float Dk, float E, float A, const Margins &mg)
+__device__ inline float prune_threshold(float Dk, float E, float A, const Margins &mg, float dl = 0.f)
 {
     if (!(Dk < INFINITY)) return INFINITY;
-    float r = __builtin_sqrtf(dist_upper(Dk, A, mg));
+    float r = __builtin_sqrtf(dist_upper(Dk, A, mg, dl));
     float tau = E + mg.rho * (r + E);
     return tau * tau * (1.f + 1e-6f);
 }

@@ -114,12 +114,14 @@ class Params:
     grid: int = 0
     use_bf16: int = 0
     dense_min: int = 0
+    scan_mode: int = 0  # 0/1 persistent scan, 2 segmented split scan (level-1 filter + level passes)
 
     def c(self):
         p = L.SearchParams()
         p.group, p.blocks_per_item, p.seed_pool = self.group, self.blocks_per_item, self.seed_pool
         p.seed_count, p.grid, p.use_bf16 = self.seed_count, self.grid, self.use_bf16
         p.reserved[0] = self.dense_min
+        p.reserved[1] = self.scan_mode
         return p
 
 
@@ -150,7 +152,9 @@ class Index:
         return ids, dists
 
     def search(self, q_dev, k: int, nprobe=1, eps: float = 1.0, params: Params | None = None,
-               stats: bool = False, stream=None, out=None, eager: bool = False):
+               stats: bool = False, stream=None, out=None, eager: bool = False, ctx: Context | None = None):
+        """k-NN of each row of q_dev among its probed lists.  ctx: run on this
+        context (one per concurrent caller) instead of the index's own."""
         import torch
         ids, dists = out if out is not None else self._outs(q_dev, k)
         np_dev = None
@@ -161,10 +165,21 @@ class Index:
             np_all = int(nprobe)
         prm = params.c() if params is not None else None
         flags = (L.PANO_SEARCH_STATS if stats else 0) | (L.PANO_SEARCH_EAGER if eager else 0)
-        L.check(L.lib().pano_search(self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all, float(eps),
-                                    _ptr(ids), _ptr(dists), C.byref(prm) if prm is not None else None,
-                                    flags, _stream_handle(stream)))
+        c = ctx if ctx is not None else self.ctx
+        L.check(L.lib().pano_search_ctx(c.h, self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all,
+                                        float(eps), _ptr(ids), _ptr(dists),
+                                        C.byref(prm) if prm is not None else None, flags, _stream_handle(stream)))
         return ids, dists
+
+    def scratch_bytes(self, nq: int, k: int, nprobe=1, per_query_nprobe: bool = False,
+                      params: Params | None = None) -> int:
+        """Device scratch a search of nq queries needs on its context."""
+        out = C.c_int64()
+        prm = params.c() if params is not None else None
+        L.check(L.lib().pano_search_scratch_bytes(self.h, int(nq), int(k), 1 if per_query_nprobe else 0,
+                                                  int(nprobe) if not per_query_nprobe else 0,
+                                                  C.byref(prm) if prm is not None else None, C.byref(out)))
+        return out.value
 
     def search_bruteforce(self, q_dev, k: int, nprobe=1, params: Params | None = None, stats: bool = False,
                           stream=None, out=None, eager: bool = False):

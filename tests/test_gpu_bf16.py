@@ -1,5 +1,6 @@
 """GPU parity of the bfloat16 scan: level slices read in bfloat16 under a
-certified margin, survivors rescored from FP32.  Its answer must equal the
+certified margin, the boundary band rescored canonically from the FP32 rows
+in the merge.  Its answer must equal the
 oracle's exactly like the FP32 scan's (ids bit-exact, distances within 1e-5
 relative), on the unit-norm embedding shape (d = 768, 32-wide levels,
 k = 100) and on the GIST shape across the search knobs."""
@@ -69,6 +70,7 @@ BF16_GRID = [
     dict(use_bf16=1, blocks_per_item=4, dense_min=32),
     dict(use_bf16=1, blocks_per_item=3, group=8, dense_min=1 << 30),
     dict(use_bf16=1, group=1, seed_pool=256, seed_count=16, grid=5),
+    dict(use_bf16=1, scan_mode=2),
 ]
 
 

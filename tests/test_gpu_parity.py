@@ -101,6 +101,8 @@ PARAM_GRID = [
     dict(blocks_per_item=8, group=4, seed_pool=256, seed_count=16),
     dict(blocks_per_item=4, dense_min=1 << 30),
     dict(blocks_per_item=2, group=1, grid=7),
+    dict(scan_mode=2),
+    dict(scan_mode=2, group=4, grid=5),
 ]
 
 
