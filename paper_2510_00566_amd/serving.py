@@ -1,0 +1,371 @@
+"""Serving loop over resident indexes: continuous batching with memory-based
+admission.
+
+Requests (a few queries each, with their own k, probe count and index)
+arrive at any time.  Worker threads each own a search context (its own HIP
+streams and scratch memory), so several batches are on the GPU at once.  A
+worker that becomes free forms the next batch at once from the requests
+waiting at that moment: the class (index, k) of the oldest waiting request,
+then that class's requests in arrival order, up to a query cap and within
+the memory budget left by the batches already in flight.  Requests that
+arrive while batches run join the next batch formed; no batch waits for a
+fixed window.  Probe counts may differ inside a batch (a per-query probe
+array), k may not (k sets the result shape).
+
+The search itself is exact at eps = 1, so a request's answer does not depend
+on which other requests share its batch; ``tests/test_gpu_serving.py`` checks
+that.  Everything here is host-side orchestration (threads, queues,
+accounting); each batch is one ``pano_search_ctx`` call.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from typing import Callable
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    index: str
+    queries: np.ndarray       # [m, d] float32
+    k: int
+    nprobe: int
+    arrival: float = 0.0      # seconds, on the server clock
+    start: float = -1.0       # when its batch was launched
+    done: float = -1.0        # when its answer was ready on the host
+    ids: np.ndarray | None = None
+    dists: np.ndarray | None = None
+    batch: int = -1           # id of the batch that served it
+
+    @property
+    def m(self) -> int:
+        return int(self.queries.shape[0])
+
+
+@dataclasses.dataclass
+class Batch:
+    bid: int
+    index: str
+    k: int
+    requests: list
+    bytes: int
+
+    @property
+    def nq(self) -> int:
+        return sum(r.m for r in self.requests)
+
+
+class Scheduler:
+    """Thread-safe admission and batch formation (no GPU here).
+
+    cost(index, nq, k) -> bytes of device memory a batch of nq queries needs
+    while in flight; budget caps the sum over batches in flight.  A single
+    request larger than the whole budget is still admitted alone (it could
+    never run otherwise); the budget is then exceeded by that batch only."""
+
+    def __init__(self, cost: Callable[[str, int, int], int], budget: int, max_batch_queries: int = 4096):
+        self.cost = cost
+        self.budget = int(budget)
+        self.max_q = int(max_batch_queries)
+        self._lock = threading.Condition()
+        self._queues: dict = collections.OrderedDict()  # (index, k) -> deque of Request
+        self._inflight = 0
+        self._peak = 0
+        self._closed = False
+        self._next_bid = 0
+
+    # ---- producer side
+    def submit(self, req: Request):
+        with self._lock:
+            key = (req.index, req.k)
+            self._queues.setdefault(key, collections.deque()).append(req)
+            self._lock.notify_all()
+
+    def close(self):
+        """No more requests will be submitted; workers drain and stop."""
+        with self._lock:
+            self._closed = True
+            self._lock.notify_all()
+
+    # ---- worker side
+    def _oldest_class(self):
+        """The class whose first waiting request is the oldest (arrival, rid)."""
+        best, best_head = None, None
+        for key, q in self._queues.items():
+            if q and (best_head is None or (q[0].arrival, q[0].rid) < best_head):
+                best, best_head = key, (q[0].arrival, q[0].rid)
+        return best
+
+    def next_batch(self) -> Batch | None:
+        """Block until a batch can be formed and admitted; None when closed
+        and drained."""
+        with self._lock:
+            while True:
+                key = self._oldest_class()
+                if key is None:
+                    if self._closed:
+                        return None
+                    self._lock.wait()
+                    continue
+                q = self._queues[key]
+                index, k = key
+                take, nq = [], 0
+                while q and (not take or nq + q[0].m <= self.max_q):
+                    cand = nq + q[0].m
+                    need = self.cost(index, cand, k)
+                    if take and self._inflight + need > self.budget:
+                        break
+                    if not take and self._inflight > 0 and self._inflight + need > self.budget:
+                        break
+                    take.append(q.popleft())
+                    nq = cand
+                if not take:
+                    # the oldest class does not fit next to the batches in
+                    # flight: wait for one of them to finish
+                    self._lock.wait()
+                    continue
+                need = self.cost(index, nq, k)
+                self._inflight += need
+                self._peak = max(self._peak, self._inflight)
+                b = Batch(self._next_bid, index, k, take, need)
+                self._next_bid += 1
+                return b
+
+    def finish(self, batch: Batch):
+        with self._lock:
+            self._inflight -= batch.bytes
+            self._lock.notify_all()
+
+    @property
+    def peak_inflight(self) -> int:
+        return self._peak
+
+    @property
+    def inflight(self) -> int:
+        return self._inflight
+
+
+class Server:
+    """Worker threads that pull batches from a Scheduler and run them with
+    execute(worker_id, batch) -> list of (ids, dists) per request."""
+
+    def __init__(self, scheduler: Scheduler, execute: Callable, n_workers: int = 3,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.sched = scheduler
+        self.execute = execute
+        self.clock = clock
+        self.n_workers = n_workers
+        self.completed: list = []
+        self.batches: list = []
+        self._lock = threading.Lock()
+        self._threads = []
+        self.errors: list = []
+
+    def _run(self, wid: int):
+        while True:
+            b = self.sched.next_batch()
+            if b is None:
+                return
+            t0 = self.clock()
+            for r in b.requests:
+                r.start = t0
+                r.batch = b.bid
+            try:
+                outs = self.execute(wid, b)
+            except Exception as e:  # a failed batch fails its requests, not the server
+                with self._lock:
+                    self.errors.append((b.bid, repr(e)))
+                outs = [(None, None)] * len(b.requests)
+            t1 = self.clock()
+            for r, (ids, dd) in zip(b.requests, outs):
+                r.ids, r.dists, r.done = ids, dd, t1
+            self.sched.finish(b)
+            with self._lock:
+                self.completed.extend(b.requests)
+                self.batches.append((b.bid, wid, b.index, b.k, b.nq, t0, t1))
+
+    def start(self):
+        for w in range(self.n_workers):
+            t = threading.Thread(target=self._run, args=(w,), daemon=True)
+            t.start()
+            self._threads.append(t)
+
+    def join(self):
+        for t in self._threads:
+            t.join()
+
+
+def poisson_requests(pools: dict, rate: float, duration: float, seed: int, sizes=(1, 256), ks=(10, 100),
+                     nprobes=(16, 64)) -> list:
+    """Seeded open-loop request stream: Poisson arrivals at `rate` requests/s
+    over `duration` s; each request draws an index from `pools`
+    (name -> query array), a size uniform in [sizes[0], sizes[1]], a k and a
+    probe count uniformly from the given sets, and its queries from the
+    pool."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([20251001, 77, seed])))
+    names = sorted(pools)
+    reqs, t, rid = [], 0.0, 0
+    while True:
+        t += g.exponential(1.0 / rate)
+        if t > duration:
+            break
+        name = names[int(g.integers(len(names)))]
+        pool = pools[name]
+        m = int(g.integers(sizes[0], sizes[1] + 1))
+        rows = g.integers(0, pool.shape[0], size=m)
+        reqs.append(Request(rid=rid, index=name, queries=np.ascontiguousarray(pool[rows]),
+                            k=int(ks[int(g.integers(len(ks)))]), nprobe=int(nprobes[int(g.integers(len(nprobes)))]),
+                            arrival=t))
+        rid += 1
+    return reqs
+
+
+def replay(server: Server, reqs: list, clock: Callable[[], float] = time.perf_counter,
+           sleep: Callable[[float], None] = time.sleep) -> float:
+    """Submit each request at its arrival offset from now (open loop), then
+    close the scheduler and wait for the workers.  Arrival times are
+    rewritten to the server clock.  Returns the clock value at the start."""
+    t0 = clock()
+    server.start()
+    for r in sorted(reqs, key=lambda r: (r.arrival, r.rid)):
+        wait = t0 + r.arrival - clock()
+        if wait > 0:
+            sleep(wait)
+        r.arrival = t0 + r.arrival
+        server.sched.submit(r)
+    server.sched.close()
+    server.join()
+    return t0
+
+
+def latency_report(reqs: list) -> dict:
+    """p50 / p99 / mean latency (ms, arrival to answer) and throughput over
+    the served requests."""
+    lat = np.array([(r.done - r.arrival) * 1e3 for r in reqs if r.done >= 0])
+    nq = sum(r.m for r in reqs if r.done >= 0)
+    if lat.size == 0:
+        return {"requests": 0}
+    t_first = min(r.arrival for r in reqs)
+    t_last = max(r.done for r in reqs if r.done >= 0)
+    span = max(t_last - t_first, 1e-9)
+    return {"requests": int(lat.size), "queries": int(nq),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+            "qps": float(nq / span), "rps": float(lat.size / span), "span_s": float(span)}
+
+
+# ---------------------------------------------------------------- GPU executor
+class GpuExecutor:
+    """Runs a batch as one search on the worker's own context and stream.
+
+    indexes: name -> Index.  One Context and one torch stream per worker."""
+
+    def __init__(self, indexes: dict, n_workers: int, device: int = 0):
+        import torch
+        from .index import Context
+        self.indexes = indexes
+        self.ctxs = [Context(device) for _ in range(n_workers)]
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_workers)]
+        self.device = device
+
+    def cost(self, index: str, nq: int, k: int) -> int:
+        idx = self.indexes[index]
+        d = idx.d
+        io = nq * (d * 4 + 4 + k * 12)  # queries, probe counts, ids + dists
+        return int(idx.scratch_bytes(nq, k, per_query_nprobe=True) + io)
+
+    def __call__(self, wid: int, b: Batch):
+        import torch
+        idx = self.indexes[b.index]
+        st = self.streams[wid]
+        q = np.concatenate([r.queries for r in b.requests]).astype(np.float32, copy=False)
+        npr = np.concatenate([np.full(r.m, r.nprobe, dtype=np.int32) for r in b.requests])
+        with torch.cuda.stream(st):
+            qd = torch.from_numpy(q).to(f"cuda:{self.device}", non_blocking=False)
+            npd = torch.from_numpy(npr).to(f"cuda:{self.device}", non_blocking=False)
+            # batch shapes vary from call to call: launch eagerly rather than
+            # capture a graph per shape
+            ids, dd = idx.search(qd, b.k, nprobe=npd, ctx=self.ctxs[wid], stream=st, eager=True)
+            ids_h = ids.cpu().numpy()
+            dd_h = dd.cpu().numpy()
+        outs, o = [], 0
+        for r in b.requests:
+            outs.append((ids_h[o:o + r.m].copy(), dd_h[o:o + r.m].copy()))
+            o += r.m
+        return outs
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+
+    import torch
+
+    from . import synth
+    from .index import Context, Index, Transform, ivf_assign
+
+    ap = argparse.ArgumentParser(description="continuous-batching serving loop over two resident indexes")
+    ap.add_argument("--qps", type=float, nargs="+", default=[2000.0, 10000.0, 50000.0],
+                    help="offered loads in queries per second (Poisson request arrivals, mean request size "
+                         "128.5 queries); one JSON line per load")
+    ap.add_argument("--duration", type=float, default=3.0, help="seconds of arrivals")
+    ap.add_argument("--scale", type=float, default=0.1, help="fraction of each index's N")
+    ap.add_argument("--workers", type=int, default=3)
+    ap.add_argument("--budget-gib", type=float, default=8.0)
+    ap.add_argument("--max-batch", type=int, default=4096)
+    ap.add_argument("--seed", type=int, default=1)
+    args = ap.parse_args(argv)
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    ctx = Context(0)
+    indexes, pools = {}, {}
+    for name, wname in (("c3", "ivf_zipf_batched"), ("c4", "ivf_embed_bf16")):
+        w0 = synth.WORKLOADS[wname]
+        w = synth.scaled(w0, n=int(w0.n * args.scale), nq=4096,
+                         nlist=max(64, int(w0.nlist * args.scale)),
+                         n_clusters=max(64, int(w0.n_clusters * args.scale)) if w0.n_clusters else 0)
+        t = time.time()
+        data = synth.generate(w)
+        xd = torch.from_numpy(data["x"]).cuda()
+        cent, assign = ivf_assign(ctx, xd, w.nlist, iters=8, seed=w.cfg_id)
+        rows = np.random.Generator(np.random.PCG64(w.cfg_id)).choice(w.n, min(w.n, 65536), replace=False)
+        c_np, a_np = cent.cpu().numpy(), assign.cpu().numpy()
+        tf = Transform.fit(data["x"][rows] - c_np[a_np[rows]], fit_sample=0, seed=w.cfg_id)
+        indexes[name] = Index.build(ctx, tf, xd, cent, assign, w.level_cuts())
+        pools[name] = data["q"]
+        del xd
+        torch.cuda.synchronize()
+        log(f"[serve] index {name}: n={w.n} d={w.d} nlist={w.nlist} built in {time.time() - t:.1f}s")
+
+    ex = GpuExecutor(indexes, args.workers)
+    # warm every context on both indexes (first-use allocations)
+    warm = poisson_requests(pools, 200.0, 0.05, args.seed + 1000, sizes=(1, 64))
+    srv = Server(Scheduler(ex.cost, int(args.budget_gib * 2 ** 30), args.max_batch), ex, n_workers=args.workers)
+    replay(srv, warm)
+    for qps in args.qps:
+        rate = qps / 128.5
+        sched = Scheduler(ex.cost, int(args.budget_gib * 2 ** 30), args.max_batch)
+        srv = Server(sched, ex, n_workers=args.workers)
+        reqs = poisson_requests(pools, rate, args.duration, args.seed)
+        log(f"[serve] offered {qps:.0f} q/s: {len(reqs)} requests, {sum(r.m for r in reqs)} queries "
+            f"over {args.duration}s")
+        replay(srv, reqs)
+        rep = latency_report(reqs)
+        rep.update({"offered_qps": qps, "workers": args.workers, "rate_rps": rate, "batches": len(srv.batches),
+                    "mean_batch_queries": float(np.mean([b[4] for b in srv.batches])) if srv.batches else 0.0,
+                    "peak_inflight_gib": sched.peak_inflight / 2 ** 30, "errors": len(srv.errors),
+                    "scale": args.scale, "indexes": {n: {"n": int(ix.info()["n"]), "d": ix.d}
+                                                     for n, ix in indexes.items()}})
+        print(json.dumps(rep), flush=True)
+
+
+if __name__ == "__main__":
+    main()

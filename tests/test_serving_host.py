@@ -1,0 +1,155 @@
+"""Host logic of the serving loop, on the CPU with a stand-in executor: batch
+formation by class and arrival order, the query cap, memory-based admission,
+continuous batching (a request that arrives while a batch runs is served by
+another worker without waiting for it), routing of answers, the seeded
+Poisson request stream and the latency report."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2510_00566_amd.serving import Request, Scheduler, Server, latency_report, poisson_requests, replay
+
+
+def _req(rid, index="a", m=4, k=10, nprobe=16, t=0.0, d=8):
+    q = np.full((m, d), float(rid), dtype=np.float32)
+    q[:, 1] = np.arange(m)
+    return Request(rid=rid, index=index, queries=q, k=k, nprobe=nprobe, arrival=t)
+
+
+def _echo(delay=0.0, log=None):
+    """Stand-in for the GPU: each query's answer encodes (request id, row)."""
+    def run(wid, b):
+        if log is not None:
+            log.append((wid, b.bid, b.index, b.k, [r.rid for r in b.requests], time.perf_counter()))
+        if delay:
+            time.sleep(delay)
+        outs = []
+        for r in b.requests:
+            ids = np.repeat((r.queries[:, 0].astype(np.int64) * 1000 + r.queries[:, 1].astype(np.int64))[:, None],
+                            r.k, axis=1)
+            outs.append((ids, np.zeros((r.m, r.k), np.float32)))
+        return outs
+    return run
+
+
+def test_batches_by_class_in_arrival_order():
+    sched = Scheduler(lambda i, nq, k: nq, budget=1 << 30, max_batch_queries=10)
+    reqs = [_req(0, "a", 4, 10, t=0.0), _req(1, "b", 4, 10, t=0.1), _req(2, "a", 4, 100, t=0.2),
+            _req(3, "a", 4, 10, t=0.3), _req(4, "a", 4, 10, t=0.4), _req(5, "b", 4, 10, t=0.5)]
+    for r in reqs:
+        sched.submit(r)
+    sched.close()
+    got = []
+    while True:
+        b = sched.next_batch()
+        if b is None:
+            break
+        got.append((b.index, b.k, [r.rid for r in b.requests]))
+        sched.finish(b)
+    # oldest head first; within a class, arrival order; at most 10 queries
+    assert got == [("a", 10, [0, 3]), ("b", 10, [1, 5]), ("a", 100, [2]), ("a", 10, [4])]
+
+
+def test_admission_keeps_memory_in_flight_within_budget():
+    cost = lambda i, nq, k: 100 * nq  # noqa: E731
+    sched = Scheduler(cost, budget=5000, max_batch_queries=64)
+    srv = Server(sched, _echo(delay=0.01), n_workers=4)
+    reqs = [_req(i, "a" if i % 2 else "b", m=1 + (i % 17), t=0.0) for i in range(60)]
+    for r in reqs:
+        sched.submit(r)
+    sched.close()
+    srv.start()
+    srv.join()
+    assert len(srv.completed) == 60
+    assert sched.peak_inflight <= 5000
+    assert sched.inflight == 0
+    assert all(b[4] <= 50 for b in srv.batches)
+
+
+def test_oversized_request_runs_alone():
+    sched = Scheduler(lambda i, nq, k: 100 * nq, budget=500, max_batch_queries=4096)
+    srv = Server(sched, _echo(), n_workers=2)
+    sched.submit(_req(0, m=20))
+    sched.submit(_req(1, m=2))
+    sched.close()
+    srv.start()
+    srv.join()
+    assert sorted(len(b) for b in [[r for r in srv.completed if r.batch == x[0]] for x in srv.batches]) == [1, 1]
+
+
+def test_answers_are_routed_to_their_request():
+    sched = Scheduler(lambda i, nq, k: nq, budget=1 << 30, max_batch_queries=100)
+    srv = Server(sched, _echo(), n_workers=3)
+    reqs = [_req(i, "ab"[i % 2], m=1 + i % 9, k=(10, 100)[i % 3 == 0], t=0.0) for i in range(40)]
+    for r in reqs:
+        sched.submit(r)
+    sched.close()
+    srv.start()
+    srv.join()
+    assert sorted(r.rid for r in srv.completed) == list(range(40))
+    for r in reqs:
+        assert r.ids.shape == (r.m, r.k)
+        assert (r.ids[:, 0] == r.rid * 1000 + np.arange(r.m)).all()
+
+
+def test_requests_arriving_during_a_batch_overlap_it():
+    log = []
+    sched = Scheduler(lambda i, nq, k: nq, budget=1 << 30, max_batch_queries=100)
+    srv = Server(sched, _echo(delay=0.2, log=log), n_workers=2)
+    srv.start()
+    sched.submit(_req(0, t=time.perf_counter()))
+    time.sleep(0.05)
+    sched.submit(_req(1, t=time.perf_counter()))
+    sched.close()
+    srv.join()
+    (w0, b0, *_r0, t0), (w1, b1, *_r1, t1) = sorted(log, key=lambda e: e[-1])
+    assert w0 != w1
+    assert t1 - t0 < 0.2  # the second batch started before the first finished
+    r0, r1 = sorted(srv.completed, key=lambda r: r.rid)
+    assert r1.start < r0.done
+
+
+def test_poisson_stream_is_seeded_and_has_the_rate():
+    pools = {"a": np.zeros((100, 4), np.float32), "b": np.ones((100, 6), np.float32)}
+    s1 = poisson_requests(pools, rate=1000.0, duration=2.0, seed=3)
+    s2 = poisson_requests(pools, rate=1000.0, duration=2.0, seed=3)
+    assert [(r.index, r.m, r.k, r.nprobe, r.arrival) for r in s1] == [(r.index, r.m, r.k, r.nprobe, r.arrival)
+                                                                      for r in s2]
+    assert 1800 < len(s1) < 2200
+    assert all(1 <= r.m <= 256 and r.k in (10, 100) and r.nprobe in (16, 64) for r in s1)
+    assert all(r.queries.shape[1] == (4 if r.index == "a" else 6) for r in s1)
+    gaps = np.diff([r.arrival for r in s1])
+    assert abs(gaps.mean() - 1e-3) < 1e-4
+
+
+def test_replay_and_latency_report():
+    pools = {"a": np.zeros((50, 4), np.float32)}
+    reqs = poisson_requests(pools, rate=400.0, duration=0.25, seed=5, sizes=(1, 8))
+    sched = Scheduler(lambda i, nq, k: nq, budget=1 << 30)
+    srv = Server(sched, _echo(delay=0.002), n_workers=2)
+    replay(srv, reqs)
+    rep = latency_report(reqs)
+    assert rep["requests"] == len(reqs)
+    lat = np.array([(r.done - r.arrival) * 1e3 for r in reqs])
+    assert (lat > 0).all()
+    assert rep["p50_ms"] == pytest.approx(np.percentile(lat, 50))
+    assert rep["p99_ms"] == pytest.approx(np.percentile(lat, 99))
+    assert rep["queries"] == sum(r.m for r in reqs)
+
+
+def test_failed_batch_does_not_stop_the_server():
+    def flaky(wid, b):
+        if any(r.rid == 3 for r in b.requests):
+            raise RuntimeError("device error")
+        return _echo()(wid, b)
+    sched = Scheduler(lambda i, nq, k: nq, budget=1 << 30, max_batch_queries=1)
+    srv = Server(sched, flaky, n_workers=2)
+    for i in range(6):
+        sched.submit(_req(i, m=1))
+    sched.close()
+    srv.start()
+    srv.join()
+    assert len(srv.completed) == 6 and len(srv.errors) == 1
+    assert [r.ids is None for r in sorted(srv.completed, key=lambda r: r.rid)] == [False] * 3 + [True] + [False] * 2
