@@ -161,7 +161,7 @@ __global__ void k_wl_count(int64_t nq, int np_max, const int32_t *__restrict__ p
 
 // One workgroup: per-list query offsets and the item offsets of the eight
 // XCD queues (lists are ordered by (l mod 8, l div 8)).
-__global__ __launch_bounds__(NT) void k_wl_offsets(int nlist, int ceil8, int G, int bpi,
+__global__ __launch_bounds__(NT) void k_wl_offsets(int nlist, int ceil8, int G, int bpi, int item_cap,
                                                    const int32_t *__restrict__ list_cnt,
                                                    const int64_t *__restrict__ list_blk,
                                                    int64_t *__restrict__ list_qoff,
@@ -189,7 +189,8 @@ __global__ __launch_bounds__(NT) void k_wl_offsets(int nlist, int ceil8, int G, 
             if (l < nlist) {
                 int c = list_cnt[l];
                 int64_t nb = list_blk[l + 1] - list_blk[l];
-                if (c > 0 && nb > 0) items = ((c + G - 1) / G) * (int)((nb + bpi - 1) / bpi);
+                const int b = list_bpi(bpi, nb, item_cap);
+                if (c > 0 && nb > 0) items = ((c + G - 1) / G) * (int)((nb + b - 1) / b);
             }
         }
         int tot;
@@ -682,8 +683,9 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
         const int gi = local % groups, ri = local / groups;
         const int ng = min(c.G, qcnt - gi * c.G);
         const int64_t lb0 = ix.list_blk[l], nblk = ix.list_blk[l + 1] - lb0;
-        const int bstart = ri * c.bpi;
-        const int bend = (int)min<int64_t>(nblk, (int64_t)(ri + 1) * c.bpi);
+        const int bpl = list_bpi(c.bpi, nblk, c.item_cap);
+        const int bstart = ri * bpl;
+        const int bend = (int)min<int64_t>(nblk, (int64_t)(ri + 1) * bpl);
         if (tid < ng) {
             const int qq = wk.list_q[wk.list_qoff[l] + gi * c.G + tid];
             qid_s[tid] = qq;
@@ -1548,35 +1550,66 @@ __global__ __launch_bounds__(NT) void k_fallback_keys(const float *__restrict__ 
     }
 }
 
+// The k smallest of `total` distinct 64-bit keys (KEY_MAX pads empty slots):
+// radix select of the k-th key over the 64 bits, 8 per pass, with a 256-bin
+// histogram in LDS, then the keys up to it are gathered and sorted.
 __global__ __launch_bounds__(NT) void k_fallback_select(const uint64_t *__restrict__ keys, int64_t total, int k,
                                                         int64_t *__restrict__ out_ids, float *__restrict__ out_d)
 {
-    __shared__ unsigned long long best_s;
-    uint64_t prev = 0;
-    bool first = true;
-    for (int r = 0; r < k; ++r) {
-        if (threadIdx.x == 0) best_s = KEY_MAX;
+    __shared__ int hist[256];
+    __shared__ int sel[2];
+    __shared__ int nsel;
+    __shared__ uint64_t best[128];
+    const int kk = (int)min<int64_t>(k, total);
+    uint64_t prefix = 0, mask = 0;
+    int rank = kk;
+    for (int shift = 56; shift >= 0 && kk > 0; shift -= 8) {
+        for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
         __syncthreads();
-        uint64_t mine = KEY_MAX;
         for (int64_t i = threadIdx.x; i < total; i += NT) {
-            uint64_t v = keys[i];
-            if ((first || v > prev) && v < mine) mine = v;
+            const uint64_t v = keys[i];
+            if ((v & mask) == prefix) atomicAdd(&hist[(int)((v >> shift) & 255u)], 1);
         }
-        atomicMin(&best_s, (unsigned long long)mine);
         __syncthreads();
-        const uint64_t b = best_s;
         if (threadIdx.x == 0) {
-            if (b == KEY_MAX) {
-                out_ids[r] = -1;
-                out_d[r] = INFINITY;
-            } else {
-                out_ids[r] = key_id(b);
-                out_d[r] = key_dist(b);
+            int acc = 0, dg = 0;
+            while (dg < 255 && acc + hist[dg] < rank) acc += hist[dg++];
+            sel[0] = dg;
+            sel[1] = rank - acc;
+        }
+        __syncthreads();
+        prefix |= (uint64_t)sel[0] << shift;
+        mask |= (uint64_t)255u << shift;
+        rank = sel[1];
+        __syncthreads();
+    }
+    // prefix is now the kk-th smallest key.  Real keys are distinct, so fewer
+    // than kk keys lie below it; it is added once unless it is the padding
+    if (threadIdx.x == 0) nsel = 0;
+    for (int i = threadIdx.x; i < 128; i += NT) best[i] = KEY_MAX;
+    __syncthreads();
+    if (kk > 0) {
+        for (int64_t i = threadIdx.x; i < total; i += NT) {
+            const uint64_t v = keys[i];
+            if (v < prefix) {
+                const int pos = atomicAdd(&nsel, 1);
+                if (pos < 128) best[pos] = v;
             }
         }
-        prev = b;
-        first = false;
         __syncthreads();
+        if (threadIdx.x == 0 && prefix != KEY_MAX && nsel < 128) best[nsel] = prefix;
+    }
+    __syncthreads();
+    block_bitonic_sort(best, 128);
+    for (int r = threadIdx.x; r < k; r += NT) {
+        const uint64_t b = r < kk ? best[r] : KEY_MAX;
+        if (b == KEY_MAX) {
+            out_ids[r] = -1;
+            out_d[r] = INFINITY;
+        } else {
+            out_ids[r] = key_id(b);
+            out_d[r] = key_dist(b);
+        }
     }
 }
 
@@ -1640,18 +1673,22 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     // the workloads measured
     const int mode_req = prm ? prm->reserved[1] : 0;
     pl.split = !brute && L >= 2 && mode_req == 2;
-    // the split scan's filter works on one block per item
+    // the split scan's filter works on one block per item; the persistent
+    // scan gives a query group at most 32 items per list
     c.bpi = pl.split ? 1 : ((prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1);
-    // Per-query result buffer: a work item publishes about k entries (its
-    // local best k and their margin band), and a query meets about
-    // nprobe * ceil(mean blocks per list / bpi) work items.  Twice that
-    // estimate, within [2048, 65536] and 4 GiB over the batch; a query that
-    // still overflows takes the exact fallback.
+    c.item_cap = pl.split ? 0 : 32;
+    // Per-query result buffer: a work item of the persistent scan publishes
+    // about k entries (its local best k and their margin band), and a query
+    // meets about nprobe * ceil(mean blocks per list / bpi) work items (at
+    // most 32 per list); the split scan publishes its surviving pairs.  Twice
+    // the estimate, within [2048, 65536] (at least 32768 for the split scan)
+    // and 4 GiB over the batch; a query that still overflows takes the exact
+    // fallback.
     {
         const int np_est = per_query_np ? std::min(nlist, 128) : std::min(nprobe_all, nlist);
         const double mean_blk = (double)ix->list_blk.back() / std::max(1, nlist);
-        const double items = (double)np_est * (std::ceil(mean_blk / c.bpi) + 1.0);
-        const double want = 2.0 * items * (k + 8);
+        const double items = (double)np_est * (std::min(32.0, std::ceil(mean_blk / c.bpi)) + 1.0);
+        const double want = std::max(2.0 * items * (k + 8), pl.split ? 32768.0 : 0.0);
         int64_t cap = 2048;
         while (cap < want && cap < 65536) cap <<= 1;
         while (cap > 2048 && (double)cap * 8.0 * (double)nq > 4.0 * 1073741824.0) cap >>= 1;
@@ -1862,7 +1899,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         // work decomposition
         const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
         hipLaunchKernelGGL(k_wl_count, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_cnt);
-        hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi, list_cnt,
+        hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi, c.item_cap, list_cnt,
                            ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
         hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_qoff, list_fill,
                            list_q);

@@ -36,6 +36,7 @@ struct SearchConsts {
     int kc;            // local top-k capacity per query (power of two >= k)
     int G;             // queries per work item
     int bpi;           // blocks per work item
+    int item_cap;      // items per query group and list at most (0 = no cap)
     int capq;          // per-query result buffer capacity
     int nlist;
     int ceil8;         // ceil(nlist / 8)
@@ -214,6 +215,16 @@ __device__ inline uint16_t bf16_bits_rne(float f)
     return (uint16_t)(u >> 16);
 }
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Blocks per work item of a list: bpi, raised for long lists so that a query
+// group meets at most `cap` items per list (0 = no cap).  Fewer, longer items
+// on long lists keep the number of per-item publications per query bounded.
+__host__ __device__ inline int list_bpi(int bpi, int64_t nblk, int cap)
+{
+    if (cap <= 0) return bpi;
+    const int64_t need = (nblk + cap - 1) / cap;
+    return need > bpi ? (int)need : bpi;
+}
 
 __host__ __device__ inline int next_pow2(int v)
 {

@@ -121,7 +121,9 @@ def test_merge_of_long_result_buffers(torch_cuda):
     # a seed threshold from only k candidates keeps d_k loose for longer
     _, _, st = _run(torch_cuda, case, w, q, params=Params(seed_pool=128, seed_count=128))
     _log("published per query", st["committed"] / w.nq, "fallback", st["fallback_queries"])
-    assert st["committed"] > 4096 * w.nq  # so at least one query's buffer exceeds the LDS sort
+    # the merge sorts at most 2048 entries in LDS: on average more than that
+    # were published per query, so at least one buffer took the select path
+    assert st["committed"] > 2048 * w.nq
     assert st["fallback_queries"] == 0
 
 
