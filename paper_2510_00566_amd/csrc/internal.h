@@ -134,7 +134,7 @@ struct pano_ctx {
     // the context's own stream (default priority), events and graph cache
     hipStream_t stream = nullptr, aux = nullptr;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr;
     hipEvent_t ev_in = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     pano::GraphKey graph_key{};
@@ -150,7 +150,8 @@ struct pano_ctx {
                 if (hipEventCreate(&e) != hipSuccess) throw pano::Error{PANO_EDEVICE, "hipEventCreate failed"};
             if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess)
+                hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&ev_fork2, hipEventDisableTiming) != hipSuccess)
                 throw pano::Error{PANO_EDEVICE, "hipEventCreate failed"};
             if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess)
                 throw pano::Error{PANO_EDEVICE, "hipStreamCreate failed"};
@@ -183,6 +184,7 @@ struct pano_ctx {
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
+        if (ev_fork2) (void)hipEventDestroy(ev_fork2);
         if (aux) (void)hipStreamDestroy(aux);
         if (stream) (void)hipStreamDestroy(stream);
     }

@@ -37,8 +37,11 @@ __global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, in
     const int64_t r0 = (int64_t)blockIdx.x * TM;
     const int c0 = blockIdx.y * TN;
     constexpr int NA = (TM * TK) / 256, NB = (TN * TK) / 256;
-    float ra[NA], rb[NB];
-    auto fetch = [&](int k0) {
+    // a register set holds one fetched chunk (this thread's share of A and B)
+    struct RegSet {
+        float a[NA], b[NB];
+    };
+    auto fetch = [&](int k0, RegSet &R) {
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
             const int e = tid + t * 256;
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, in
                 v = A[r * K + kx];
                 if (SUB_MU) v = v - mu[kx];
             }
-            ra[t] = v;
+            R.a[t] = v;
         }
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
@@ -58,31 +61,26 @@ __global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, in
             const int cc = e / TK, kk = e % TK;
             const int c = c0 + cc;
             const int kx = k0 + kk;
-            rb[t] = (c < nb && kx < K) ? Bm[(int64_t)c * K + kx] : 0.f;
+            R.b[t] = (c < nb && kx < K) ? Bm[(int64_t)c * K + kx] : 0.f;
         }
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf, const RegSet &R) {
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
             const int e = tid + t * 256;
-            As[buf][e / TK][e % TK] = ra[t];
+            As[buf][e / TK][e % TK] = R.a[t];
         }
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             const int e = tid + t * 256;
-            Bs[buf][e / TK][e % TK] = rb[t];
+            Bs[buf][e / TK][e % TK] = R.b[t];
         }
     };
     floatx4_t tot[2];
     tot[0] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     tot[1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     const int nchunks = (K + TK - 1) / TK;
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    for (int ch = 0; ch < nchunks; ++ch) {
-        const int buf = ch & 1;
-        if (ch + 1 < nchunks) fetch((ch + 1) * TK);
+    auto compute = [&](int buf) {
         floatx4_t acc[2];
         acc[0] = floatx4_t{0.f, 0.f, 0.f, 0.f};
         acc[1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
@@ -97,8 +95,29 @@ __global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, in
         }
         tot[0] += acc[0];
         tot[1] += acc[1];
-        if (ch + 1 < nchunks) stash(buf ^ 1);
-        __syncthreads();
+    };
+    // Four chunks in flight.  Register set R[j] receives chunks j, j + 4, ...;
+    // step ch computes LDS stage ch & 1, stashes chunk ch + 1 into the other
+    // stage and requests chunk ch + 4 into the set chunk ch left free.  The
+    // loop is unrolled by four so every set keeps a fixed role.
+    RegSet R[4];
+    fetch(0, R[0]);
+    stash(0, R[0]);
+    if (nchunks > 1) fetch(TK, R[1]);
+    if (nchunks > 2) fetch(2 * TK, R[2]);
+    if (nchunks > 3) fetch(3 * TK, R[3]);
+    __syncthreads();
+    for (int base = 0; base < nchunks; base += 4) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ch = base + j;
+            if (ch < nchunks) {
+                compute(j & 1);
+                if (ch + 1 < nchunks) stash((j + 1) & 1, R[(j + 1) & 3]);
+                if (ch + 4 < nchunks) fetch((ch + 4) * TK, R[j]);
+                __syncthreads();
+            }
+        }
     }
     // lane holds rows 4*(lane/16) + v of column lane%16 of each 16 x 16 tile
 #pragma unroll

@@ -1867,10 +1867,14 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         fl.add(qflags, nq, 0u);
         if (stats_on) fl.add(stats, 256, 0u);
         hipLaunchKernelGGL(k_fill_multi, dim3(256), dim3(256), 0, st, fl);
-        // query transform, tails and error bound
-        launch_transform(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy, ix->d_pad, st);
-        launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, st);
-        hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, vnorm, qtail, L, nq,
+        // query transform, tails and error bound on the second stream, beside
+        // the coarse probing on this one (they share only the raw queries)
+        hipStream_t sa = ctx->aux;
+        PANO_HIP(hipEventRecord(ctx->ev_fork2, st));
+        PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork2, 0));
+        launch_transform(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy, ix->d_pad, sa);
+        launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, sa);
+        hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, sa, vnorm, qtail, L, nq,
                            mq, qE, qA, qbad);
         // coarse probing
         if (nlist > 1) {
@@ -1889,13 +1893,14 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         // so the scan could prune the very candidates that set d_k and return
         // fewer than k; without seeding, every d_k comes from committed
         // candidates.
+        // (the second stream runs it after the query transform it needs)
         if (seed_on) {
             PANO_HIP(hipEventRecord(ctx->ev_fork, st));
-            PANO_HIP(hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0));
-            hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, ctx->aux, c, iv, qv, probes, np_max,
+            PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork, 0));
+            hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, sa, c, iv, qv, probes, np_max,
                                ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
-            PANO_HIP(hipEventRecord(ctx->ev_join, ctx->aux));
         }
+        PANO_HIP(hipEventRecord(ctx->ev_join, sa));
         // work decomposition
         const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
         hipLaunchKernelGGL(k_wl_count, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_cnt);
@@ -1906,7 +1911,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         if (split)
             hipLaunchKernelGGL(k_wl_items, dim3((unsigned)(8 * c.ceil8)), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi,
                                list_cnt, ix->list_blk_d.as<int64_t>(), item_off, items, pl.items_max);
-        if (seed_on) PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+        PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[1], st));
         WorkView w2 = wk;
         w2.stats = stats_on ? stats : nullptr;

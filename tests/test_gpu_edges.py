@@ -72,6 +72,10 @@ def test_single_query_k1(torch_cuda):
     _log("case nq=1 k=1 n=5000 d=96 nlist=8")
     case = gc.build_case(w, data={"x": x, "q": q})
     _run(torch_cuda, case, w, q)
+    from paper_2510_00566_amd.index import Params
+    # seeding from one or two exact distances (teams spanning wavefronts)
+    _run(torch_cuda, case, w, q, params=Params(seed_count=1))
+    _run(torch_cuda, case, w, q, k=2, params=Params(seed_count=2))
 
 
 @gpu
