@@ -528,13 +528,16 @@ __device__ inline void level_dots_bf16(const uint16_t *__restrict__ tile, int B,
 // per candidate, Eq. 3 / Eq. 4 bounds with the certified margin), stopping
 // when its lower bound exceeds th.  sh enters as the head distance of levels
 // before lv_start and leaves as the head distance of the levels read; lv_end
-// is one past the last level read.  Returns true if the pair survives.
+// is one past the last level read.  Returns true if the pair survives; then
+// `accepted` tells that its upper bound proved it a survivor before the last
+// level, and the levels from lv_end on are left to the caller to add.
 template <bool BF>
 __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__restrict__ blk,
                                           const uint16_t *__restrict__ blk16, const float *__restrict__ tl, int ss,
                                           const float *__restrict__ qrow, const float *qt, float th, float Aq,
-                                          int lv_start, float &sh, int &lv_end)
+                                          int lv_start, float &sh, int &lv_end, bool &accepted)
 {
+    accepted = false;
     const LevelGeom &g = c.g;
     // four coordinates of level lv of slot ss (FP32 tile, or the bfloat16
     // copy widened to FP32)
@@ -583,12 +586,12 @@ __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__
         // Upper bound (the other side of Cauchy-Schwarz): UB =
         // ||q_h - x_h||^2 + (||q_t|| + ||x_t||)^2 never grows with the level,
         // and every later bound (any eps) stays below it.  Once UB is under
-        // the threshold the pair cannot be pruned any more: read the remaining
-        // levels without further tests.
+        // the threshold the pair cannot be pruned any more: the remaining
+        // levels need no further tests.
         const float ubh = BF ? bf_head_upper(sh + err, delta) : sh + err;
         if (!last && ubh + (a + b) * (a + b) + ct <= th) {
-            for (int lv2 = lv + 1; lv2 < g.L; ++lv2) sh += level_part(lv2);
-            lv_end = g.L;
+            lv_end = lv + 1;
+            accepted = true;
             return true;
         }
     }
@@ -814,6 +817,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     if (Lc > 0) my_lv[0] += (unsigned long long)cnt * ng;
                 }
             }
+            PANO_PHASE(1);
             if (PRUNE) {
                 // While the survivors stay dense (typically the candidates of a
                 // query's own cluster), keep refining whole levels on the matrix
@@ -937,7 +941,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     for (int lv = 0; lv < Lc; ++lv) my_lv[lv] += (unsigned long long)cnt * ng;
                 }
             }
-            PANO_PHASE(1);
+            PANO_PHASE(5);
             // ---- consolidate: survivors into the (query, slot) pair list
             {
                 int tot;
@@ -967,16 +971,65 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     const int qq = qid_s[gq];
                     float sh = pS[p];
                     int lv;
+                    bool acc;
                     const bool alive = walk_pair<BF>(c, blk, blk16, tl, ss, qv.qy + (int64_t)qq * g.d_pad, &qtl_s[gq][0],
-                                                     thr_s[gq], A_s[gq], lv_start, sh, lv);
-                    keep[p] = alive ? 1 : 0;
+                                                     thr_s[gq], A_s[gq], lv_start, sh, lv, acc);
+                    // 0 pruned, 1 complete, 2 + l: accepted, levels from l left
+                    keep[p] = !alive ? 0 : (acc ? (uint8_t)(2 + lv) : 1);
                     pS[p] = sh;
                     if (wk.stats) {
-                        for (int v = lv_start; v < lv && v < 64; ++v) atomicAdd(&my_lv[v], 1ull);
-                        my_dims += (unsigned long long)(g.mp[lv < g.L ? lv : g.L] - g.mp[lv_start]);
+                        const int lr = acc ? g.L : lv;
+                        for (int v = lv_start; v < lr && v < 64; ++v) atomicAdd(&my_lv[v], 1ull);
+                        my_dims += (unsigned long long)(g.mp[lr < g.L ? lr : g.L] - g.mp[lv_start]);
                     }
                 }
                 if (wk.stats && my_dims) atomicAdd(&sparse_bytes_s, my_dims * (BF ? 2ull : 4ull));
+                __syncthreads();
+                // Accepted pairs need their remaining levels summed, no more
+                // tests: a whole wavefront reads them for one pair at a time
+                // (64 lanes over the pair's remaining four-dimension chunks),
+                // so one long read does not hold back the workgroup.
+                for (int base = wv * 64; base < np_; base += NT) {
+                    const int i = base + lane;
+                    const uint64_t bal = __ballot(i < np_ && keep[i] >= 2);
+                    uint64_t todo = bal;
+                    while (todo) {
+                        const int j = base + (int)__builtin_ctzll(todo);
+                        todo &= todo - 1ull;
+                        const uint32_t pv = pr[j];
+                        const int gq = (int)(pv >> 8), ss = (int)(pv & 255u);
+                        const int l0 = keep[j] - 2;
+                        const float *qrow = qv.qy + (int64_t)qid_s[gq] * g.d_pad;
+                        const int f0 = g.mp[l0] >> 2, f1 = g.mp[g.L] >> 2;  // chunk range left
+                        float part = 0.f;
+                        int l = l0;
+#pragma unroll 4
+                        for (int f = f0 + lane; f < f1; f += 64) {
+                            while (4 * f >= g.mp[l + 1]) ++l;
+                            const int64_t o = (int64_t)g.B * g.mp[l] + (int64_t)ss * g.wp[l] + (4 * f - g.mp[l]);
+                            float4 x4;
+                            if (BF) {
+                                const uint2 xr = *reinterpret_cast<const uint2 *>(blk16 + o);
+                                x4 = make_float4(__uint_as_float(xr.x << 16), __uint_as_float(xr.x & 0xffff0000u),
+                                                 __uint_as_float(xr.y << 16), __uint_as_float(xr.y & 0xffff0000u));
+                            } else {
+                                x4 = *reinterpret_cast<const float4 *>(blk + o);
+                            }
+                            const float4 q4 = *reinterpret_cast<const float4 *>(qrow + 4 * f);
+                            float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                            part = __builtin_fmaf(t0, t0, part);
+                            part = __builtin_fmaf(t1, t1, part);
+                            part = __builtin_fmaf(t2, t2, part);
+                            part = __builtin_fmaf(t3, t3, part);
+                        }
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+                        if (lane == 0) {
+                            pS[j] += part;
+                            keep[j] = 1;
+                        }
+                    }
+                }
                 __syncthreads();
                 // one stable compaction of the pairs that survived every level
                 int kept = 0;
