@@ -65,39 +65,40 @@ __device__ inline float canon_dist(const float *__restrict__ q, const float *__r
     return (float)s;
 }
 
-// The same recipe with the query held in LDS and the row streamed in
-// 16-float chunks (the next chunk is in flight while the current one is
-// summed).  Identical arithmetic, identical order.
+// The same value with x read from global memory in 32-float chunks, the next
+// chunk requested while the current one is summed (identical arithmetic,
+// identical order; q in LDS).
 __device__ inline float canon_dist_stream(const float *q_lds, const float *__restrict__ x, int d)
 {
 #pragma clang fp contract(off)
     double s = 0.0;
     int j = 0;
-    if ((d & 3) == 0 && d >= 16) {
+    if ((d & 3) == 0 && d >= 32) {
+        // rows of a multiple of 4 floats start 16-byte aligned
         const float4 *x4 = reinterpret_cast<const float4 *>(x);
-        float4 cur[4], nxt[4];
+        float4 cur[8], nxt[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) cur[u] = x4[u];
-        const int n16 = d >> 4;
-        for (int c = 0; c < n16; ++c) {
-            if (c + 1 < n16) {
+        for (int u = 0; u < 8; ++u) cur[u] = x4[u];
+        const int n32 = d >> 5;
+        for (int c = 0; c < n32; ++c) {
+            if (c + 1 < n32) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) nxt[u] = x4[(c + 1) * 4 + u];
+                for (int u = 0; u < 8; ++u) nxt[u] = x4[(c + 1) * 8 + u];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const float xv[4] = {cur[u].x, cur[u].y, cur[u].z, cur[u].w};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    double t = (double)q_lds[c * 16 + u * 4 + e] - (double)xv[e];
+                    double t = (double)q_lds[c * 32 + u * 4 + e] - (double)xv[e];
                     double t2 = t * t;
                     s = s + t2;
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+            for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
         }
-        j = n16 << 4;
+        j = n32 << 5;
     }
     for (; j < d; ++j) {
         double t = (double)q_lds[j] - (double)x[j];
