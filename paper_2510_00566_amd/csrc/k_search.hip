@@ -415,8 +415,10 @@ __device__ inline void level_dots(const float *__restrict__ tile, int B, int kg_
             const uint32_t slot = (uint32_t)(wave_slot0 + nt * 16 + r16);
             const uint32_t off = row_w ? slot * (uint32_t)row_w + (uint32_t)kgc * 4u
                                        : ((uint32_t)kgc * (uint32_t)B + slot) * 4u;
-            const float4 v = *reinterpret_cast<const float4 *>(tile + off);
-            xa[nt] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+            // read unconditionally (a valid group of the same slot): the
+            // query side is zero for a lane past the last group, so its
+            // products vanish
+            xa[nt] = *reinterpret_cast<const float4 *>(tile + off);
         }
     };
     floatx4_t part[4];
@@ -459,19 +461,21 @@ __device__ inline void level_dots_bf16(const uint16_t *__restrict__ tile, int B,
 {
     const int r16 = lane & 15, kq = lane >> 4;
     const int T = (kg_count + 3) >> 2;
-    auto fetch = [&](int t, uint2 xr[4], float4 &qf) {
+    auto fetch = [&](int t, uint2 xr[4], float4 &qf, bool &okf) {
         const int kg = 4 * t + kq;
         const bool ok = kg < kg_count;
         const int kgc = ok ? kg : kg_count - 1;
         const float4 qv4 = qload(kgc);
         qf = ok ? qv4 : make_float4(0.f, 0.f, 0.f, 0.f);
+        okf = ok;
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const uint32_t slot = (uint32_t)(wave_slot0 + nt * 16 + r16);
             const uint32_t off = row_w ? slot * (uint32_t)row_w + (uint32_t)kgc * 4u
                                        : ((uint32_t)kgc * (uint32_t)B + slot) * 4u;
-            const uint2 v = *reinterpret_cast<const uint2 *>(tile + off);
-            xr[nt] = ok ? v : make_uint2(0u, 0u);
+            // read unconditionally (a valid group of the same slot); a lane
+            // past the last group feeds a zero query and adds nothing to ex
+            xr[nt] = *reinterpret_cast<const uint2 *>(tile + off);
         }
     };
     floatx4_t part[4];
@@ -480,7 +484,7 @@ __device__ inline void level_dots_bf16(const uint16_t *__restrict__ tile, int B,
         part[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
         ex[nt] = 0.f;
     }
-    auto products = [&](const uint2 xr[4], const float4 &qf) {
+    auto products = [&](const uint2 xr[4], const float4 &qf, bool okf) {
         shortx4_t qh, ql;
         const float qv[4] = {qf.x, qf.y, qf.z, qf.w};
 #pragma unroll
@@ -500,22 +504,25 @@ __device__ inline void level_dots_bf16(const uint16_t *__restrict__ tile, int B,
             part[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ql, xa, part[nt], 0, 0, 0);
             const float x0 = __uint_as_float(xr[nt].x << 16), x1 = __uint_as_float(xr[nt].x & 0xffff0000u);
             const float x2 = __uint_as_float(xr[nt].y << 16), x3 = __uint_as_float(xr[nt].y & 0xffff0000u);
-            ex[nt] = __builtin_fmaf(x0, x0, ex[nt]);
-            ex[nt] = __builtin_fmaf(x1, x1, ex[nt]);
-            ex[nt] = __builtin_fmaf(x2, x2, ex[nt]);
-            ex[nt] = __builtin_fmaf(x3, x3, ex[nt]);
+            float e = ex[nt];
+            e = __builtin_fmaf(x0, x0, e);
+            e = __builtin_fmaf(x1, x1, e);
+            e = __builtin_fmaf(x2, x2, e);
+            e = __builtin_fmaf(x3, x3, e);
+            ex[nt] = okf ? e : ex[nt];
         }
     };
     uint2 xr0[4], xr1[4];
     float4 qf0, qf1;
-    fetch(0, xr0, qf0);
-    if (T > 1) fetch(1, xr1, qf1);
-    products(xr0, qf0);
-    if (T > 2) fetch(2, xr0, qf0);
-    if (T > 1) products(xr1, qf1);
-    if (T > 3) fetch(3, xr1, qf1);
-    if (T > 2) products(xr0, qf0);
-    if (T > 3) products(xr1, qf1);
+    bool ok0 = false, ok1 = false;
+    fetch(0, xr0, qf0, ok0);
+    if (T > 1) fetch(1, xr1, qf1, ok1);
+    products(xr0, qf0, ok0);
+    if (T > 2) fetch(2, xr0, qf0, ok0);
+    if (T > 1) products(xr1, qf1, ok1);
+    if (T > 3) fetch(3, xr1, qf1, ok1);
+    if (T > 2) products(xr0, qf0, ok0);
+    if (T > 3) products(xr1, qf1, ok1);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         acc[nt] = part[nt];
@@ -554,15 +561,28 @@ __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__
         const int w4 = g.wp[lv] >> 2;
         const float *qq4 = qrow + g.mp[lv];
         float part = 0.f;
-#pragma unroll 4
-        for (int c4 = 0; c4 < w4; ++c4) {
-            const float4 x4 = ld4(lv, c4);
-            const float4 q4 = *reinterpret_cast<const float4 *>(qq4 + c4 * 4);
-            float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
-            part = __builtin_fmaf(t0, t0, part);
-            part = __builtin_fmaf(t1, t1, part);
-            part = __builtin_fmaf(t2, t2, part);
-            part = __builtin_fmaf(t3, t3, part);
+        // the slice is requested WALK_CHUNKS chunks at a time (one memory
+        // round trip per group instead of one per few chunks), summed in order
+        for (int c0 = 0; c0 < w4; c0 += WALK_CHUNKS) {
+            float4 xs[WALK_CHUNKS], qs[WALK_CHUNKS];
+#pragma unroll
+            for (int j = 0; j < WALK_CHUNKS; ++j) {
+                if (c0 + j < w4) {
+                    xs[j] = ld4(lv, c0 + j);
+                    qs[j] = *reinterpret_cast<const float4 *>(qq4 + (c0 + j) * 4);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < WALK_CHUNKS; ++j) {
+                if (c0 + j < w4) {
+                    float t0 = qs[j].x - xs[j].x, t1 = qs[j].y - xs[j].y, t2 = qs[j].z - xs[j].z,
+                          t3 = qs[j].w - xs[j].w;
+                    part = __builtin_fmaf(t0, t0, part);
+                    part = __builtin_fmaf(t1, t1, part);
+                    part = __builtin_fmaf(t2, t2, part);
+                    part = __builtin_fmaf(t3, t3, part);
+                }
+            }
         }
         return part;
     };

@@ -10,6 +10,7 @@ constexpr int NT = 256;         // threads per workgroup (4 wavefronts)
 constexpr int MERGE_LDS_KEYS = 2048;  // entries the merge sorts in LDS
 constexpr int GMAX = 16;        // max queries per scan work item
 constexpr int SB_MAX = 512;     // per-wave sort buffer (entries)
+constexpr int WALK_CHUNKS = 8;  // four-float chunks of a level the per-pair walk requests at once
 constexpr uint64_t KEY_MAX = ~0ull;
 constexpr int FLAG_OVERFLOW = 1;
 
