@@ -112,14 +112,14 @@ struct GraphKey {
     float eps;
     bool brute;
     const void *ids, *dists;
-    int G, bpi, seed_pool, seed_cnt, grid, dense_min, bf16, split;
+    int G, bpi, seed_pool, seed_cnt, grid, dense_min, bf16, split, walk_lanes;
     const void *s0, *s1, *s2, *s3, *s5, *s6, *pinned;
     bool operator==(const GraphKey &o) const
     {
         return ix_serial == o.ix_serial && q == o.q && nq == o.nq && k == o.k && npd == o.npd && np_all == o.np_all &&
                eps == o.eps && brute == o.brute && ids == o.ids && dists == o.dists && G == o.G && bpi == o.bpi &&
                seed_pool == o.seed_pool && seed_cnt == o.seed_cnt && grid == o.grid && dense_min == o.dense_min &&
-               bf16 == o.bf16 && split == o.split && s0 == o.s0 && s1 == o.s1 &&
+               bf16 == o.bf16 && split == o.split && walk_lanes == o.walk_lanes && s0 == o.s0 && s1 == o.s1 &&
                s2 == o.s2 && s3 == o.s3 && s5 == o.s5 && s6 == o.s6 && pinned == o.pinned;
     }
 };

@@ -542,7 +542,8 @@ template <bool BF>
 __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__restrict__ blk,
                                           const uint16_t *__restrict__ blk16, const float *__restrict__ tl, int ss,
                                           const float *__restrict__ qrow, const float *qt, float th, float Aq,
-                                          int lv_start, float &sh, int &lv_end, bool &accepted)
+                                          int lv_start, float &sh, int &lv_end, bool &accepted, int sub = 0,
+                                          int lpp = 1)
 {
     accepted = false;
     const LevelGeom &g = c.g;
@@ -561,20 +562,23 @@ __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__
         const int w4 = g.wp[lv] >> 2;
         const float *qq4 = qrow + g.mp[lv];
         float part = 0.f;
-        // the slice is requested WALK_CHUNKS chunks at a time (one memory
-        // round trip per group instead of one per few chunks), summed in order
-        for (int c0 = 0; c0 < w4; c0 += WALK_CHUNKS) {
+        // lpp lanes (1, 2 or 4, neighbours in the wavefront) share the pair:
+        // lane sub takes chunks sub, sub + lpp, ...  Each lane requests up to
+        // WALK_CHUNKS chunks at once (one memory round trip per group), sums
+        // them in order, and the lanes' partial sums are added.
+        for (int c0 = sub; c0 < w4; c0 += WALK_CHUNKS * lpp) {
             float4 xs[WALK_CHUNKS], qs[WALK_CHUNKS];
 #pragma unroll
             for (int j = 0; j < WALK_CHUNKS; ++j) {
-                if (c0 + j < w4) {
-                    xs[j] = ld4(lv, c0 + j);
-                    qs[j] = *reinterpret_cast<const float4 *>(qq4 + (c0 + j) * 4);
+                const int c4 = c0 + j * lpp;
+                if (c4 < w4) {
+                    xs[j] = ld4(lv, c4);
+                    qs[j] = *reinterpret_cast<const float4 *>(qq4 + c4 * 4);
                 }
             }
 #pragma unroll
             for (int j = 0; j < WALK_CHUNKS; ++j) {
-                if (c0 + j < w4) {
+                if (c0 + j * lpp < w4) {
                     float t0 = qs[j].x - xs[j].x, t1 = qs[j].y - xs[j].y, t2 = qs[j].z - xs[j].z,
                           t3 = qs[j].w - xs[j].w;
                     part = __builtin_fmaf(t0, t0, part);
@@ -584,6 +588,8 @@ __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__
                 }
             }
         }
+        if (lpp >= 2) part += __shfl_xor(part, 1, 64);
+        if (lpp >= 4) part += __shfl_xor(part, 2, 64);
         return part;
     };
     // bfloat16 rows: ||x - x~|| <= u_b ||x||
@@ -985,7 +991,12 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             if (PRUNE && lv_start < g.L) {
                 const int np_ = npairs_s;
                 unsigned long long my_dims = 0;
-                for (int p = tid; p < np_; p += NT) {
+                // few pairs: several lanes per pair, so that each lane's
+                // share of a level is one memory round trip and the pairs
+                // spread over all four wavefronts
+                const int lpp = c.walk_lanes ? c.walk_lanes : (np_ <= NT / 4 ? 4 : (np_ <= NT / 2 ? 2 : 1));
+                const int sub = tid & (lpp - 1);
+                for (int p = tid / lpp; p < np_; p += NT / lpp) {
                     const uint32_t pv = pr[p];
                     const int gq = (int)(pv >> 8), ss = (int)(pv & 255u);
                     const int qq = qid_s[gq];
@@ -993,11 +1004,12 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     int lv;
                     bool acc;
                     const bool alive = walk_pair<BF>(c, blk, blk16, tl, ss, qv.qy + (int64_t)qq * g.d_pad, &qtl_s[gq][0],
-                                                     thr_s[gq], A_s[gq], lv_start, sh, lv, acc);
+                                                     thr_s[gq], A_s[gq], lv_start, sh, lv, acc, sub, lpp);
                     // 0 pruned, 1 complete, 2 + l: accepted, levels from l left
+                    // (the lanes of a pair hold the same values)
                     keep[p] = !alive ? 0 : (acc ? (uint8_t)(2 + lv) : 1);
                     pS[p] = sh;
-                    if (wk.stats) {
+                    if (wk.stats && sub == 0) {
                         const int lr = acc ? g.L : lv;
                         for (int v = lv_start; v < lr && v < 64; ++v) atomicAdd(&my_lv[v], 1ull);
                         my_dims += (unsigned long long)(g.mp[lr < g.L ? lr : g.L] - g.mp[lv_start]);
@@ -1771,6 +1783,9 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     c.ceil8 = (nlist + 7) / 8;
     c.prune = brute ? 0 : 1;
     c.dense_min = (prm && prm->reserved[0] > 0) ? prm->reserved[0] : 64;
+    c.walk_lanes = prm ? prm->reserved[2] : 0;
+    PANO_REQUIRE(c.walk_lanes == 0 || c.walk_lanes == 1 || c.walk_lanes == 2 || c.walk_lanes == 4,
+                 "walk lanes per pair must be 0, 1, 2 or 4");
     c.eps = eps;
     c.one_m_eps2 = 2.f * (1.f - eps);
     c.mg = ix->mg;
@@ -2017,7 +2032,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         enqueue(ws, true);
     } else if (!(flags & PANO_SEARCH_EAGER)) {
         GraphKey key{ix->serial, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
-                     c.dense_min, c.bf16, split ? 1 : 0, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
+                     c.dense_min, c.bf16, split ? 1 : 0, c.walk_lanes, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
                      split ? ctx->scratch[5].p : nullptr, split ? ctx->scratch[6].p : nullptr, ctx->pinned};
         if (!ctx->graph_exec || !(ctx->graph_key == key)) {
             ctx->drop_graph();

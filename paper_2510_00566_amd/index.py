@@ -115,6 +115,7 @@ class Params:
     use_bf16: int = 0
     dense_min: int = 0
     scan_mode: int = 0  # 0/1 persistent scan, 2 segmented split scan (level-1 filter + level passes)
+    walk_lanes: int = 0  # lanes per pair in the per-pair walk: 1, 2, 4 (0 = by the number of pairs)
 
     def c(self):
         p = L.SearchParams()
@@ -122,6 +123,7 @@ class Params:
         p.seed_count, p.grid, p.use_bf16 = self.seed_count, self.grid, self.use_bf16
         p.reserved[0] = self.dense_min
         p.reserved[1] = self.scan_mode
+        p.reserved[2] = self.walk_lanes
         return p
 
 
