@@ -160,6 +160,11 @@ __device__ inline double wave_sum_f64(double v)
     return v;
 }
 
+// Rows of up to 64 * VPL padded values are read into registers at once
+// (every load in flight together); wider rows loop over the level slices.
+// Both give the same sums in the same order: per lane, its values of the
+// level in increasing column order, then the butterfly of wave_sum_f64.
+template <int VPL>
 __global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, int64_t n, LevelGeom g,
                                                    const float *__restrict__ X,
                                                    const float *__restrict__ mu,
@@ -170,22 +175,55 @@ __global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, 
     if (r >= n) return;
     const float *y = Y + r * g.d_pad;
     double suffix = 0.0;
-    for (int l = g.L - 1; l >= 0; --l) {
-        double e = 0.0;
-        for (int c = g.mp[l] + lane; c < g.mp[l + 1]; c += 64) {
-            double v = (double)y[c];
-            e += v * v;
+    if (VPL > 0) {
+        float v[VPL > 0 ? VPL : 1];
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) v[j] = y[min(j * 64 + lane, g.d_pad - 1)];  // clamped: no branch
+        for (int l = g.L - 1; l >= 0; --l) {
+            const int lo = g.mp[l], hi = g.mp[l + 1];
+            double e = 0.0;
+#pragma unroll
+            for (int j = 0; j < VPL; ++j) {
+                const int c = j * 64 + lane;
+                if (c >= lo && c < hi) {
+                    const double t = (double)v[j];
+                    e += t * t;
+                }
+            }
+            e = wave_sum_f64(e);
+            suffix += e;
+            if (lane == 0) tails[r * g.L + l] = (float)sqrt(suffix);
         }
-        e = wave_sum_f64(e);
-        suffix += e;
-        if (lane == 0) tails[r * g.L + l] = (float)sqrt(suffix);
+    } else {
+        for (int l = g.L - 1; l >= 0; --l) {
+            double e = 0.0;
+            for (int c = g.mp[l] + lane; c < g.mp[l + 1]; c += 64) {
+                double v = (double)y[c];
+                e += v * v;
+            }
+            e = wave_sum_f64(e);
+            suffix += e;
+            if (lane == 0) tails[r * g.L + l] = (float)sqrt(suffix);
+        }
     }
     if (vnorm) {
         const float *x = X + r * g.d;
         double e = 0.0;
-        for (int c = lane; c < g.d; c += 64) {
-            double v = (double)(x[c] - mu[c]);
-            e += v * v;
+        for (int c0 = 0; c0 < g.d; c0 += 64 * 8) {
+            float xv[8], mv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = min(c0 + u * 64 + lane, g.d - 1);  // clamped: no branch
+                xv[u] = x[c];
+                mv[u] = mu[c];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (c0 + u * 64 + lane < g.d) {
+                    const double t = (double)(xv[u] - mv[u]);
+                    e += t * t;
+                }
+            }
         }
         e = wave_sum_f64(e);
         if (lane == 0) vnorm[r] = sqrt(e);
@@ -197,7 +235,12 @@ void launch_row_norms(const float *Y, int64_t n, const LevelGeom &g, const float
 {
     if (n == 0) return;
     dim3 grid((unsigned)((n + 3) / 4));
-    hipLaunchKernelGGL(k_row_norms, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm);
+    if (g.d_pad <= 256)
+        hipLaunchKernelGGL(k_row_norms<4>, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm);
+    else if (g.d_pad <= 1024)
+        hipLaunchKernelGGL(k_row_norms<16>, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm);
+    else
+        hipLaunchKernelGGL(k_row_norms<0>, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm);
     PANO_HIP(hipGetLastError());
 }
 

@@ -31,15 +31,16 @@ __global__ void k_query_consts(const double *__restrict__ vnorm, const float *__
 // recipe and ordered by (D, l).
 __host__ __device__ inline size_t coarse_lds_per_wave(int nlist, int d)
 {
-    return (((size_t)nlist * 20 + (size_t)d * 4 + 1024 + 64) + 15) & ~(size_t)15;
+    // keys [next_pow2(nlist)] (the band's sort pads to a power of two), LO,
+    // UP, list ids [nlist], query row [d], select histogram [256]
+    return (((size_t)next_pow2(nlist) * 8 + (size_t)nlist * 12 + (size_t)d * 4 + 1024 + 64) + 15) & ~(size_t)15;
 }
 
-__global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, const float *__restrict__ qn2,
-                                               const float *__restrict__ cn2, const float *__restrict__ q,
+__global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, const float *__restrict__ cn2, const float *__restrict__ q,
                                                const float *__restrict__ cent, int d, int nlist, int64_t nq,
                                                const int32_t *__restrict__ nprobe_dev, int nprobe_all,
                                                float c_co, int np_max, int32_t *__restrict__ probes,
-                                               int32_t *__restrict__ np_out)
+                                               int32_t *__restrict__ np_out, int32_t *__restrict__ list_cnt)
 {
     extern __shared__ char smc[];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -48,27 +49,63 @@ __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, cons
     if (qi >= nq) return;
     const size_t pw = coarse_lds_per_wave(nlist, d);
     char *base = smc + pw * w;
-    uint64_t *keys = reinterpret_cast<uint64_t *>(base);            // [nlist]
-    float *LO = reinterpret_cast<float *>(keys + nlist);             // [nlist]
+    uint64_t *keys = reinterpret_cast<uint64_t *>(base);            // [next_pow2(nlist)]
+    float *LO = reinterpret_cast<float *>(keys + next_pow2(nlist));  // [nlist]
     float *UP = LO + nlist;                                          // [nlist]
     int32_t *lst = reinterpret_cast<int32_t *>(UP + nlist);          // [nlist]
     float *qrow = reinterpret_cast<float *>(lst + nlist);            // [d]
-    int *hist = reinterpret_cast<int *>(qrow + d);                   // [256]
+    int *hist = reinterpret_cast<int *>(qrow + d);                   // [256] (nlist > 4096)
     int p = nprobe_dev ? nprobe_dev[qi] : nprobe_all;
     p = p < 1 ? 1 : (p > nlist ? nlist : p);
     if (p > np_max) p = np_max;
-    const float qq = qn2[qi];
-    for (int j = lane; j < d; j += 64) qrow[j] = q[qi * d + j];
-    for (int l = lane; l < nlist; l += 64) {
-        const float a = qq + cn2[l] - 2.f * S[qi * nlist + l];
-        const float del = c_co * (qq + cn2[l]);
-        LO[l] = fmaxf(a - del, 0.f) * (1.0f - 1.2e-7f);
-        UP[l] = fmaxf(a + del, 0.f) * (1.0f + 1.2e-7f);
+    // the query row in rounds of eight loads per lane, all in flight
+    // together, and ||q||^2 in FP32: per lane its values in increasing
+    // column order, then a butterfly (the order the error bound c_co counts)
+    float qq = 0.f;
+    for (int j0 = 0; j0 < d; j0 += 512) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u * 64 + lane;
+            v[u] = q[qi * d + min(j, d - 1)];  // clamped: no branch around the load
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u * 64 + lane;
+            if (j < d) {
+                qrow[j] = v[u];
+                qq = __builtin_fmaf(v[u], v[u], qq);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o, 64);
+    for (int l0 = 0; l0 < nlist; l0 += 512) {
+        float cv[8], sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int l = l0 + u * 64 + lane;
+            const int lc = min(l, nlist - 1);  // clamped: no branch around the loads
+            cv[u] = cn2[lc];
+            sv[u] = S[qi * nlist + lc];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int l = l0 + u * 64 + lane;
+            if (l < nlist) {
+                const float a = qq + cv[u] - 2.f * sv[u];
+                const float del = c_co * (qq + cv[u]);
+                LO[l] = fmaxf(a - del, 0.f) * (1.0f - 1.2e-7f);
+                UP[l] = fmaxf(a + del, 0.f) * (1.0f + 1.2e-7f);
+            }
+        }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const float Up = wave_select_nonneg(UP, nlist, p, hist, lane);
-    const float Lp1 = p < nlist ? wave_select_nonneg(LO, nlist, p + 1, hist, lane) : INFINITY;
+    // (the key buffer, not in use yet, holds the selects' candidates)
+    float *cand = reinterpret_cast<float *>(keys);
+    const float Up = wave_select_nonneg(UP, nlist, p, hist, cand, lane);
+    const float Lp1 = p < nlist ? wave_select_nonneg(LO, nlist, p + 1, hist, cand, lane) : INFINITY;
     // certain lists go to the output; uncertain band members are collected
     int ncert = 0, nunc = 0;
     for (int b0 = 0; b0 < nlist; b0 += 64) {
@@ -80,7 +117,10 @@ __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, cons
         const uint64_t below = (1ull << lane) - 1ull;
         if (cert) {
             const int pos = ncert + __popcll(bc & below);
-            if (pos < p) probes[qi * np_max + pos] = l;
+            if (pos < p) {
+                probes[qi * np_max + pos] = l;
+                atomicAdd(&list_cnt[l], 1);  // queries per list, for the work lists
+            }
         }
         if (unc) lst[nunc + __popcll(bu & below)] = l;
         ncert += __popcll(bc);
@@ -92,19 +132,22 @@ __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, cons
     const int need = p - ncert;
     if (need > 0) {
         const int PU = next_pow2(nunc);
-        for (int i = lane; i < PU; i += 64) {
-            if (i < nunc) {
-                const int l = lst[i];
-                keys[i] = make_key(canon_dist_stream(qrow, cent + (int64_t)l * d, d), l);
-            } else {
-                keys[i] = KEY_MAX;
-            }
+        // one band member at a time, each by the whole wavefront
+        for (int i = 0; i < nunc; ++i) {
+            const int l = lst[i];
+            const float dv = wave_canon_dist(qrow, cent + (int64_t)l * d, d, lane);
+            if (lane == 0) keys[i] = make_key(dv, l);
         }
+        for (int i = nunc + lane; i < PU; i += 64) keys[i] = KEY_MAX;
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         wave_bitonic_sort(keys, PU, lane);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int i = lane; i < need; i += 64) probes[qi * np_max + ncert + i] = key_id(keys[i]);
+        for (int i = lane; i < need; i += 64) {
+            const int l = key_id(keys[i]);
+            probes[qi * np_max + ncert + i] = l;
+            atomicAdd(&list_cnt[l], 1);
+        }
     }
     // rank 0 = the probed list with the smallest approximate distance (the
     // seeding step draws its first candidates from it)
@@ -139,26 +182,18 @@ __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, cons
     if (lane == 0) np_out[qi] = p;
 }
 
-__global__ void k_single_list(int64_t nq, int np_max, int32_t *__restrict__ probes, int32_t *__restrict__ np_out)
+__global__ void k_single_list(int64_t nq, int np_max, int32_t *__restrict__ probes, int32_t *__restrict__ np_out,
+                              int32_t *__restrict__ list_cnt)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nq) return;
+    atomicAdd(&list_cnt[0], 1);
     probes[i * np_max] = 0;
     for (int r = 1; r < np_max; ++r) probes[i * np_max + r] = -1;
     np_out[i] = 1;
 }
 
 // ================================================================ work list
-__global__ void k_wl_count(int64_t nq, int np_max, const int32_t *__restrict__ probes,
-                           const int32_t *__restrict__ np, int32_t *__restrict__ list_cnt)
-{
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nq * np_max) return;
-    const int64_t i = t / np_max;
-    const int r = (int)(t % np_max);
-    if (r < np[i]) atomicAdd(&list_cnt[probes[t]], 1);
-}
-
 // One workgroup: per-list query offsets and the item offsets of the eight
 // XCD queues (lists are ordered by (l mod 8, l div 8)).
 __global__ __launch_bounds__(NT) void k_wl_offsets(int nlist, int ceil8, int G, int bpi, int item_cap,
@@ -302,17 +337,27 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
             const int64_t gb = b0 + p / g.B;
             const int s = p % g.B;
             const float *x = ix.levels + gb * (int64_t)g.B * g.d_pad + (int64_t)s * 4;
-            float sh = 0.f;
-            for (int c4 = 0; c4 < w04; ++c4) {
-                const float4 x4 = *reinterpret_cast<const float4 *>(x + (int64_t)c4 * 4 * g.B);
-                const float4 q4 = q1[c4];
-                float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
-                sh = __builtin_fmaf(t0, t0, sh);
-                sh = __builtin_fmaf(t1, t1, sh);
-                sh = __builtin_fmaf(t2, t2, sh);
-                sh = __builtin_fmaf(t3, t3, sh);
-            }
             const float b1 = g.L > 1 ? ix.tails[gb * (int64_t)g.B * g.L + g.B + s] : 0.f;
+            float sh = 0.f;
+            // the level-1 slice in groups of eight chunks, each group's loads
+            // in flight together (clamped, so no branch around them)
+            for (int c0 = 0; c0 < w04; c0 += 8) {
+                float4 xs[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    xs[j] = *reinterpret_cast<const float4 *>(x + (int64_t)min(c0 + j, w04 - 1) * 4 * g.B);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (c0 + j < w04) {
+                        const float4 q4 = q1[c0 + j];
+                        float t0 = q4.x - xs[j].x, t1 = q4.y - xs[j].y, t2 = q4.z - xs[j].z, t3 = q4.w - xs[j].w;
+                        sh = __builtin_fmaf(t0, t0, sh);
+                        sh = __builtin_fmaf(t1, t1, sh);
+                        sh = __builtin_fmaf(t2, t2, sh);
+                        sh = __builtin_fmaf(t3, t3, sh);
+                    }
+                }
+            }
             const float tt = a1 - b1;
             K[p] = make_key(sh + tt * tt, p);
         } else {
@@ -331,15 +376,27 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
             const int64_t gb = b0 + p / g.B;
             const int s = p % g.B;
             const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
-#pragma unroll 4
-            for (int ch = tl; ch < nch; ch += 16) {
-                const float4 x4 = *reinterpret_cast<const float4 *>(blk + chunk_off[ch] + (int64_t)s * chunk_w[ch]);
-                const float4 q4 = *reinterpret_cast<const float4 *>(qy + 4 * ch);
-                float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
-                part = __builtin_fmaf(t0, t0, part);
-                part = __builtin_fmaf(t1, t1, part);
-                part = __builtin_fmaf(t2, t2, part);
-                part = __builtin_fmaf(t3, t3, part);
+            // groups of eight chunks per lane, each group's loads in flight
+            // together (clamped to a valid chunk, so no branch around them)
+            for (int ch0 = tl; ch0 < nch; ch0 += 16 * 8) {
+                float4 xs[8], qs[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int ch = min(ch0 + 16 * j, nch - 1);
+                    xs[j] = *reinterpret_cast<const float4 *>(blk + chunk_off[ch] + (int64_t)s * chunk_w[ch]);
+                    qs[j] = *reinterpret_cast<const float4 *>(qy + 4 * ch);
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (ch0 + 16 * j < nch) {
+                        float t0 = qs[j].x - xs[j].x, t1 = qs[j].y - xs[j].y, t2 = qs[j].z - xs[j].z,
+                              t3 = qs[j].w - xs[j].w;
+                        part = __builtin_fmaf(t0, t0, part);
+                        part = __builtin_fmaf(t1, t1, part);
+                        part = __builtin_fmaf(t2, t2, part);
+                        part = __builtin_fmaf(t3, t3, part);
+                    }
+                }
             }
         }
 #pragma unroll
@@ -1575,10 +1632,15 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
         if (threadIdx.x == 0) atomicOr(&flags[q], FLAG_OVERFLOW);
         return;
     }
-    // canonical rescoring of the band (the band is a prefix of the sort)
-    for (int i = threadIdx.x; i < nb; i += NT) {
-        const int32_t id = key_id(K[i]);
-        K[i] = make_key(canon_dist_stream(qrow, raw + (int64_t)id * d, d), id);
+    // canonical rescoring of the band (the band is a prefix of the sort):
+    // one row per wavefront at a time
+    {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int i = wv; i < nb; i += NT / 64) {
+            const int32_t id = key_id(K[i]);
+            const float dv = wave_canon_dist(qrow, raw + (int64_t)id * d, d, lane);
+            if (lane == 0) K[i] = make_key(dv, id);
+        }
     }
     const int PB = next_pow2(nb > 0 ? nb : 1);
     for (int i = nb + threadIdx.x; i < PB; i += NT) K[i] = KEY_MAX;
@@ -1805,7 +1867,7 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
     const int np_max = per_query_np ? nlist : std::min(nprobe_all, nlist);
     need[0] = align_up(sizeof(float) * nq * ix->d_pad) + align_up(sizeof(float) * nq * L) +
-              3 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
+              2 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
     need[1] = nlist > 1 ? align_up(sizeof(float) * nq * nlist) : 256;
     need[2] = align_up(sizeof(int32_t) * nq * np_max) * 2 + align_up(sizeof(int32_t) * nq) +
               2 * align_up(sizeof(int32_t) * nlist) + align_up(sizeof(int32_t) * 8) +
@@ -1892,7 +1954,6 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     float *qy = c0.take<float>(nq * ix->d_pad);
     float *qtail = c0.take<float>(nq * L);
     float *qE = c0.take<float>(nq);
-    float *qn2 = c0.take<float>(nq);
     float *qA = c0.take<float>(nq);
     int *qbad = c3.take<int>(1);
     double *vnorm = c0.take<double>(nq);
@@ -1967,13 +2028,12 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         // coarse probing
         if (nlist > 1) {
             launch_gemm_nt(q, nq, d, ix->cent.as<float>(), nlist, Sco, st);
-            launch_sqnorms(q, nq, d, qn2, st);
             hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
-                               qn2, ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq,
-                               nprobe_dev, nprobe_all, c_co, np_max, probes, npq);
+                               ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq,
+                               nprobe_dev, nprobe_all, c_co, np_max, probes, npq, list_cnt);
         } else {
             hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, np_max, probes,
-                               npq);
+                               npq, list_cnt);
         }
         // threshold seeding (needs only the probes) runs beside the work
         // decomposition on the context's second stream.  Only for the exact
@@ -1991,7 +2051,6 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         PANO_HIP(hipEventRecord(ctx->ev_join, sa));
         // work decomposition
         const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
-        hipLaunchKernelGGL(k_wl_count, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_cnt);
         hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi, c.item_cap, list_cnt,
                            ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
         hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_qoff, list_fill,

@@ -67,47 +67,52 @@ __device__ inline float canon_dist(const float *__restrict__ q, const float *__r
     return (float)s;
 }
 
-// The same value with x read from global memory in 32-float chunks, the next
-// chunk requested while the current one is summed (identical arithmetic,
-// identical order; q in LDS).
-__device__ inline float canon_dist_stream(const float *q_lds, const float *__restrict__ x, int d)
+// The canonical distance computed by a whole wavefront (all 64 lanes call it
+// with the same arguments and get the same value).  The per-element terms are
+// those of the canonical recipe, t = (double)q_j - (double)x_j and t * t, each
+// rounded; only their summation order differs: lane partial sums, then a
+// butterfly.  Any order of a sum of n non-negative terms lies within
+// gamma(n - 1) S of the exact sum S, so the sequential sum lies within
+// 2 gamma(n - 1) S / (1 - gamma(n - 1)) of this one; when both ends of that
+// interval round to the same float, that float is the canonical value.
+// Otherwise (an interval straddling a float rounding boundary, or a
+// non-finite value) the sequential recipe itself is evaluated.
+__device__ inline float wave_canon_dist(const float *q, const float *__restrict__ x, int d, int lane)
 {
 #pragma clang fp contract(off)
     double s = 0.0;
-    int j = 0;
-    if ((d & 3) == 0 && d >= 32) {
-        // rows of a multiple of 4 floats start 16-byte aligned
-        const float4 *x4 = reinterpret_cast<const float4 *>(x);
-        float4 cur[8], nxt[8];
+    for (int j0 = 0; j0 < d; j0 += 64 * 8) {
+        float xv[8], qv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) cur[u] = x4[u];
-        const int n32 = d >> 5;
-        for (int c = 0; c < n32; ++c) {
-            if (c + 1 < n32) {
-#pragma unroll
-                for (int u = 0; u < 8; ++u) nxt[u] = x4[(c + 1) * 8 + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const float xv[4] = {cur[u].x, cur[u].y, cur[u].z, cur[u].w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    double t = (double)q_lds[c * 32 + u * 4 + e] - (double)xv[e];
-                    double t2 = t * t;
-                    s = s + t2;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
+        for (int u = 0; u < 8; ++u) {
+            const int j = min(j0 + u * 64 + lane, d - 1);  // clamped: no branch around the loads
+            xv[u] = x[j];
+            qv[u] = q[j];
         }
-        j = n32 << 5;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (j0 + u * 64 + lane < d) {
+                const double t = (double)qv[u] - (double)xv[u];
+                const double t2 = t * t;
+                s = s + t2;
+            }
+        }
     }
-    for (; j < d; ++j) {
-        double t = (double)q_lds[j] - (double)x[j];
-        double t2 = t * t;
-        s = s + t2;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s = s + __shfl_xor(s, o, 64);
+    const double gm = (double)d * 0x1p-53;
+    const double gam = gm / (1.0 - gm);
+    const double del = 2.0 * gam * s / (1.0 - gam) * 1.01 + 0x1p-1074;
+    const float lo = (float)(s - del), hi = (float)(s + del);
+    if (lo == hi) return lo;
+    // the sequential recipe (every lane computes it)
+    double r = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double t = (double)q[j] - (double)x[j];
+        const double t2 = t * t;
+        r = r + t2;
     }
-    return (float)s;
+    return (float)r;
 }
 
 // Bounds for bfloat16 tiles.  With x~ the bfloat16 rounding of the stored
@@ -236,11 +241,121 @@ __host__ __device__ inline int next_pow2(int v)
     return p;
 }
 
-// p-th smallest (1-based) of n non-negative floats V[0..n) by one wavefront:
-// an MSB-first radix select over the IEEE bit patterns (monotone for
-// non-negative values), 8 bits per round, with a 256-bin LDS histogram.
-__device__ inline float wave_select_nonneg(const float *V, int n, int p, int *hist, int lane)
+// The p-th smallest (1-based) of the valid values among u[0..VPL) of every
+// lane of one wavefront (n valid in total, 1 <= p <= n), as float bit
+// patterns of non-negative floats (their unsigned order is the float order):
+// a bitwise radix select.  Bits common to every value come from the AND / OR
+// of all values; each remaining bit costs one pass that counts, with ballots,
+// the candidates still matching the prefix whose bit is 0.  It stops as soon
+// as one candidate is left.  No LDS atomics: values that share their leading
+// bits (the usual case) cost nothing extra.
+template <int VPL>
+__device__ inline uint32_t wave_select_core(const uint32_t (&u)[VPL], const bool (&ok)[VPL], int n, int p)
 {
+    uint32_t vor = 0u, vand = ~0u;
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) {
+        vor |= ok[j] ? u[j] : 0u;
+        vand &= ok[j] ? u[j] : ~0u;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        vor |= (uint32_t)__shfl_xor((int)vor, o, 64);
+        vand &= (uint32_t)__shfl_xor((int)vand, o, 64);
+    }
+    const uint32_t diff = vor ^ vand;
+    if (diff == 0u) return vand;  // all values equal
+    const int top = 31 - __builtin_clz(diff);
+    uint32_t mask = top >= 31 ? 0u : ~((2u << top) - 1u);
+    uint32_t prefix = vand & mask;
+    int need = p, left = n;  // rank sought among the `left` candidates matching prefix
+    for (int b = top; b >= 0; --b) {
+        const uint32_t bit = 1u << b;
+        int c0 = 0;
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) c0 += __popcll(__ballot(ok[j] && (u[j] & (mask | bit)) == prefix));
+        mask |= bit;
+        if (need <= c0) {
+            left = c0;
+        } else {
+            need -= c0;
+            left -= c0;
+            prefix |= bit;
+        }
+        if (left == 1) {
+            // the one candidate left: its bits complete the prefix
+            uint32_t found = 0u;
+#pragma unroll
+            for (int j = 0; j < VPL; ++j) {
+                const uint64_t m = __ballot(ok[j] && (u[j] & mask) == prefix);
+                if (m) found = (uint32_t)__shfl((int)u[j], (int)__builtin_ctzll(m), 64);
+            }
+            return found;
+        }
+    }
+    return prefix;
+}
+
+// The p-th smallest of n <= 64 * VPL non-negative floats V[0..n) in LDS.
+template <int VPL>
+__device__ inline float wave_select_regs(const float *V, int n, int p, int lane)
+{
+    uint32_t u[VPL];
+    bool ok[VPL];
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) {
+        const int i = j * 64 + lane;
+        ok[j] = i < n;
+        u[j] = ok[j] ? __float_as_uint(V[i]) : 0u;
+    }
+    return __uint_as_float(wave_select_core<VPL>(u, ok, n, p));
+}
+
+// The same for n <= 64 * VPL and p <= 64, first narrowing the candidates:
+// the p-th smallest of the 64 per-lane minima bounds the answer from above
+// (those p minima are p of the values), so only values at or below it are
+// copied to C (LDS, n entries) and selected among.
+template <int VPL>
+__device__ inline float wave_select_small_p(const float *V, int n, int p, float *C, int lane)
+{
+    uint32_t u[VPL];
+    bool ok[VPL];
+    uint32_t mn = ~0u;
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) {
+        const int i = j * 64 + lane;
+        ok[j] = i < n;
+        u[j] = ok[j] ? __float_as_uint(V[i]) : 0u;
+        mn = ok[j] ? min(mn, u[j]) : mn;
+    }
+    // every lane holds a value when n >= 64
+    const uint32_t m1[1] = {mn};
+    const bool o1[1] = {true};
+    const uint32_t bound = wave_select_core<1>(m1, o1, 64, p);
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) {
+        const bool c = ok[j] && u[j] <= bound;
+        const uint64_t bal = __ballot(c);
+        if (c) C[cnt + __popcll(bal & ((1ull << lane) - 1ull))] = __uint_as_float(u[j]);
+        cnt += __popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (cnt <= 64) return wave_select_regs<1>(C, cnt, p, lane);
+    if (cnt <= 256) return wave_select_regs<4>(C, cnt, p, lane);
+    return __uint_as_float(wave_select_core<VPL>(u, ok, n, p));
+}
+
+// The p-th smallest of any n >= 1 non-negative floats V[0..n) in LDS:
+// values in registers up to 4096 (narrowed through C, n floats of LDS, when
+// p <= 64), else an MSB-first radix select, 8 bits per round, with a 256-bin
+// LDS histogram (hist[256]).
+__device__ inline float wave_select_nonneg(const float *V, int n, int p, int *hist, float *C, int lane)
+{
+    if (n <= 256) return wave_select_regs<4>(V, n, p, lane);
+    if (n <= 1024) return p <= 64 ? wave_select_small_p<16>(V, n, p, C, lane) : wave_select_regs<16>(V, n, p, lane);
+    if (n <= 4096) return p <= 64 ? wave_select_small_p<64>(V, n, p, C, lane) : wave_select_regs<64>(V, n, p, lane);
     uint32_t prefix = 0, mask = 0;
     int need = p;
     for (int shift = 24; shift >= 0; shift -= 8) {

@@ -93,6 +93,33 @@ def test_integer_grid_ties(torch_cuda):
 
 
 @gpu
+def test_distances_at_float_midpoints(torch_cuda):
+    """Integer rows whose squared distances are odd integers just above 2^24,
+    exactly halfway between two floats: the canonical value is the
+    round-to-nearest-even of the exact sum, so the merge's parallel
+    rescoring must fall back to the sequential sum for these rows, and ties
+    after rounding are ordered by id."""
+    from tests import gpu_cases as gc
+    # the margins scale with the row norms (~2^22 here); the other
+    # coordinates spread the distances so that the margin band of each work
+    # item fits its local top-k
+    w = _workload(d=16, k=10, nlist=1, nprobe=1, width=4, n=400, nq=8)
+    x = synth.integer_grid(400, 16, seed=21, span=64)
+    x[:, 0] = 2048.0
+    q = synth.integer_grid(8, 16, seed=22, span=64)
+    q[:, 0] = -2048.0
+    d2 = ((x[None, :, :].astype(np.float64) - q[:, None, :]) ** 2).sum(-1)
+    assert (d2 % 2 == 1).any() and (d2 > 2.0 ** 24).all()
+    _log("case float midpoints n=400 d=16 k=10")
+    case = gc.build_case(w, data={"x": x, "q": q}, transform="identity")
+    ids, dd, st = _run(torch_cuda, case, w, q)
+    assert st["fallback_queries"] == 0
+    # the answers include rows whose exact distance was a rounding midpoint
+    exact = np.take_along_axis(d2, ids.astype(np.int64), axis=1)
+    assert (exact % 2 == 1).any()
+
+
+@gpu
 def test_tie_band_beyond_buffer_takes_fallback(torch_cuda):
     """5000 identical rows tie for every query: the band of equal distances
     exceeds the per-query buffer, the exact fallback runs, and the answer is
