@@ -156,7 +156,10 @@ typedef struct {
                              [2]: lanes per pair in the per-pair walk of the
                              persistent scan: 1, 2 or 4 (0 = 4 when at most
                              64 pairs of a block survive, 2 up to 128, else
-                             1); other values are EINVAL */
+                             1); other values are EINVAL;
+                             [3]: levels per step of the walk with four lanes
+                             per pair: 1, or 2 (both requested together; 0 =
+                             2 when no level is wider than 64 dimensions) */
 } pano_search_params;
 
 /* Search flags. */

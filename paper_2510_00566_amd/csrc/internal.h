@@ -112,14 +112,14 @@ struct GraphKey {
     float eps;
     bool brute;
     const void *ids, *dists;
-    int G, bpi, seed_pool, seed_cnt, grid, dense_min, bf16, split, walk_lanes;
+    int G, bpi, seed_pool, seed_cnt, grid, dense_min, bf16, split, walk_lanes, walk2;
     const void *s0, *s1, *s2, *s3, *s5, *s6, *pinned;
     bool operator==(const GraphKey &o) const
     {
         return ix_serial == o.ix_serial && q == o.q && nq == o.nq && k == o.k && npd == o.npd && np_all == o.np_all &&
                eps == o.eps && brute == o.brute && ids == o.ids && dists == o.dists && G == o.G && bpi == o.bpi &&
                seed_pool == o.seed_pool && seed_cnt == o.seed_cnt && grid == o.grid && dense_min == o.dense_min &&
-               bf16 == o.bf16 && split == o.split && walk_lanes == o.walk_lanes && s0 == o.s0 && s1 == o.s1 &&
+               bf16 == o.bf16 && split == o.split && walk_lanes == o.walk_lanes && walk2 == o.walk2 && s0 == o.s0 && s1 == o.s1 &&
                s2 == o.s2 && s3 == o.s3 && s5 == o.s5 && s6 == o.s6 && pinned == o.pinned;
     }
 };
@@ -134,7 +134,7 @@ struct pano_ctx {
     // the context's own stream (default priority), events and graph cache
     hipStream_t stream = nullptr, aux = nullptr;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_in = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     pano::GraphKey graph_key{};
@@ -150,8 +150,7 @@ struct pano_ctx {
                 if (hipEventCreate(&e) != hipSuccess) throw pano::Error{PANO_EDEVICE, "hipEventCreate failed"};
             if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&ev_fork2, hipEventDisableTiming) != hipSuccess)
+                hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess)
                 throw pano::Error{PANO_EDEVICE, "hipEventCreate failed"};
             if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess)
                 throw pano::Error{PANO_EDEVICE, "hipStreamCreate failed"};
@@ -184,7 +183,6 @@ struct pano_ctx {
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
-        if (ev_fork2) (void)hipEventDestroy(ev_fork2);
         if (aux) (void)hipStreamDestroy(aux);
         if (stream) (void)hipStreamDestroy(stream);
     }
@@ -226,6 +224,26 @@ struct LevelGeom {
     int mp[65];  // padded cuts
     int wp[64];  // padded widths
 };
+
+// One dense product Out[r][outcol ? outcol[c] : c] = sum_k (A[r][k] - mu[k])
+// Bm[c][k] (mu may be null) for r < n, c < nb, K = reduction length, with the
+// chunked FP32 accumulation of launch_transform.
+struct GemmJob {
+    const float *A;
+    int64_t n;
+    int K;
+    const float *Bm;
+    int nb;
+    const float *mu;
+    const int32_t *outcol;
+    float *Out;
+    int ld_out;
+};
+GemmJob transform_job(const float *X, int64_t n, int d, const float *T, const float *mu, const int32_t *padcol,
+                      float *Y, int ld_y);
+GemmJob product_job(const float *A, int64_t n, int d, const float *Bm, int nb, float *S);
+// Both jobs (j1 may be null) in one launch: their tiles run side by side.
+void launch_gemm_jobs(const GemmJob &j0, const GemmJob *j1, hipStream_t s);
 
 // Y[r][padcol[j]] = sum_j T[i][j] * (X[r][j] - mu[j]) with chunked FP32
 // accumulation; Y has ld_y columns (padding columns are left untouched).

@@ -19,13 +19,20 @@ namespace pano {
 constexpr int TM = 32, TN = 64, TK = 32, TLD = 36;
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-template <bool SUB_MU>
-__global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, int64_t n, int K,
-                                                 const float *__restrict__ Bm, int nb,
-                                                 const float *__restrict__ mu,
-                                                 const int32_t *__restrict__ outcol,
-                                                 float *__restrict__ Out, int ld_out)
+// One launch may carry two independent products (jobs): the workgroups with
+// blockIdx.y < y0 take job j0, the others job j1 (column tile blockIdx.y - y0).
+__global__ __launch_bounds__(256) void k_tile_nt(GemmJob j0, GemmJob j1, int y0)
 {
+    const bool first = (int)blockIdx.y < y0;
+    const float *__restrict__ A = first ? j0.A : j1.A;
+    const int64_t n = first ? j0.n : j1.n;
+    const int K = first ? j0.K : j1.K;
+    const float *__restrict__ Bm = first ? j0.Bm : j1.Bm;
+    const int nb = first ? j0.nb : j1.nb;
+    const float *__restrict__ mu = first ? j0.mu : j1.mu;
+    const int32_t *__restrict__ outcol = first ? j0.outcol : j1.outcol;
+    float *__restrict__ Out = first ? j0.Out : j1.Out;
+    const int ld_out = first ? j0.ld_out : j1.ld_out;
     // two LDS stages: the next chunk is fetched into registers while the
     // current one feeds the matrix cores
     __shared__ float As[2][TM][TLD];
@@ -35,45 +42,50 @@ __global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, in
     const int r16 = lane & 15, kq = lane >> 4;
     const int wr = (w >> 1) * 16, wc = (w & 1) * 32;
     const int64_t r0 = (int64_t)blockIdx.x * TM;
-    const int c0 = blockIdx.y * TN;
+    const int c0 = (first ? (int)blockIdx.y : (int)blockIdx.y - y0) * TN;
     constexpr int NA = (TM * TK) / 256, NB = (TN * TK) / 256;
-    // a register set holds one fetched chunk (this thread's share of A and B)
+    // a register set holds one fetched chunk as loaded (this thread's share
+    // of A, mu and B) and the chunk's start; the out-of-range values are
+    // replaced and mu subtracted only when the chunk is stored to LDS, so
+    // nothing waits for the loads before then
     struct RegSet {
-        float a[NA], b[NB];
+        float a[NA], m[NA], b[NB];
+        int k0;
     };
+    // every load is issued from a clamped (valid) index, so no branch
+    // separates the loads of a chunk and they are all in flight together
+    const bool sub_mu = mu != nullptr;
+    const float *__restrict__ mu_ld = sub_mu ? mu : A;  // any valid row when unused
     auto fetch = [&](int k0, RegSet &R) {
+        R.k0 = k0;
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
             const int e = tid + t * 256;
-            const int rr = e / TK, kk = e % TK;
-            const int64_t r = r0 + rr;
-            const int kx = k0 + kk;
-            float v = 0.f;
-            if (r < n && kx < K) {
-                v = A[r * K + kx];
-                if (SUB_MU) v = v - mu[kx];
-            }
-            R.a[t] = v;
+            const int64_t r = min(r0 + e / TK, n - 1);
+            const int kx = min(k0 + e % TK, K - 1);
+            R.a[t] = A[r * K + kx];
+            R.m[t] = mu_ld[kx];
         }
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             const int e = tid + t * 256;
-            const int cc = e / TK, kk = e % TK;
-            const int c = c0 + cc;
-            const int kx = k0 + kk;
-            R.b[t] = (c < nb && kx < K) ? Bm[(int64_t)c * K + kx] : 0.f;
+            const int c = min(c0 + e / TK, nb - 1);
+            const int kx = min(k0 + e % TK, K - 1);
+            R.b[t] = Bm[(int64_t)c * K + kx];
         }
     };
     auto stash = [&](int buf, const RegSet &R) {
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
             const int e = tid + t * 256;
-            As[buf][e / TK][e % TK] = R.a[t];
+            const bool ok = r0 + e / TK < n && R.k0 + e % TK < K;
+            As[buf][e / TK][e % TK] = ok ? (sub_mu ? R.a[t] - R.m[t] : R.a[t]) : 0.f;
         }
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             const int e = tid + t * 256;
-            Bs[buf][e / TK][e % TK] = R.b[t];
+            const bool ok = c0 + e / TK < nb && R.k0 + e % TK < K;
+            Bs[buf][e / TK][e % TK] = ok ? R.b[t] : 0.f;
         }
     };
     floatx4_t tot[2];
@@ -97,26 +109,37 @@ __global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, in
         tot[1] += acc[1];
     };
     // Four chunks in flight.  Register set R[j] receives chunks j, j + 4, ...;
-    // step ch computes LDS stage ch & 1, stashes chunk ch + 1 into the other
-    // stage and requests chunk ch + 4 into the set chunk ch left free.  The
-    // loop is unrolled by four so every set keeps a fixed role.
+    // step ch computes LDS stage ch & 1, stores chunk ch + 1 into the other
+    // stage and requests chunk ch + 4 into the set chunk ch left free.  Full
+    // groups of four steps run without branches (requests past the last
+    // chunk re-read it and are never used), so the waits for each set stay
+    // exact; the last steps follow with their guards.
     RegSet R[4];
     fetch(0, R[0]);
     stash(0, R[0]);
-    if (nchunks > 1) fetch(TK, R[1]);
-    if (nchunks > 2) fetch(2 * TK, R[2]);
-    if (nchunks > 3) fetch(3 * TK, R[3]);
+    fetch(min(1, nchunks - 1) * TK, R[1]);
+    fetch(min(2, nchunks - 1) * TK, R[2]);
+    fetch(min(3, nchunks - 1) * TK, R[3]);
     __syncthreads();
-    for (int base = 0; base < nchunks; base += 4) {
+    int base = 0;
+    for (; base + 4 <= nchunks; base += 4) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int ch = base + j;
-            if (ch < nchunks) {
-                compute(j & 1);
-                if (ch + 1 < nchunks) stash((j + 1) & 1, R[(j + 1) & 3]);
-                if (ch + 4 < nchunks) fetch((ch + 4) * TK, R[j]);
-                __syncthreads();
-            }
+            compute(j & 1);
+            stash((j + 1) & 1, R[(j + 1) & 3]);
+            fetch(min(ch + 4, nchunks - 1) * TK, R[j]);
+            __syncthreads();
+        }
+    }
+    // (unrolled with constant set indices, so the sets stay in registers)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int ch = base + j;
+        if (ch < nchunks) {
+            compute(j & 1);
+            if (ch + 1 < nchunks) stash((j + 1) & 1, R[(j + 1) & 3]);
+            __syncthreads();
         }
     }
     // lane holds rows 4*(lane/16) + v of column lane%16 of each 16 x 16 tile
@@ -133,21 +156,37 @@ __global__ __launch_bounds__(256) void k_tile_nt(const float *__restrict__ A, in
         }
 }
 
+GemmJob transform_job(const float *X, int64_t n, int d, const float *T, const float *mu, const int32_t *padcol,
+                      float *Y, int ld_y)
+{
+    return GemmJob{X, n, d, T, d, mu, padcol, Y, ld_y};
+}
+
+GemmJob product_job(const float *A, int64_t n, int d, const float *Bm, int nb, float *S)
+{
+    return GemmJob{A, n, d, Bm, nb, nullptr, nullptr, S, nb};
+}
+
+void launch_gemm_jobs(const GemmJob &j0, const GemmJob *j1, hipStream_t s)
+{
+    const int64_t n = j1 ? std::max(j0.n, j1->n) : j0.n;
+    if (n == 0) return;
+    const int y0 = (j0.nb + TN - 1) / TN;
+    const int y1 = j1 ? (j1->nb + TN - 1) / TN : 0;
+    dim3 grid((unsigned)((n + TM - 1) / TM), (unsigned)(y0 + y1));
+    hipLaunchKernelGGL(k_tile_nt, grid, dim3(256), 0, s, j0, j1 ? *j1 : j0, y0);
+    PANO_HIP(hipGetLastError());
+}
+
 void launch_transform(const float *X, int64_t n, int d, const float *T, const float *mu,
                       const int32_t *padcol, float *Y, int ld_y, hipStream_t s)
 {
-    if (n == 0) return;
-    dim3 grid((unsigned)((n + TM - 1) / TM), (unsigned)((d + TN - 1) / TN));
-    hipLaunchKernelGGL(k_tile_nt<true>, grid, dim3(256), 0, s, X, n, d, T, d, mu, padcol, Y, ld_y);
-    PANO_HIP(hipGetLastError());
+    launch_gemm_jobs(transform_job(X, n, d, T, mu, padcol, Y, ld_y), nullptr, s);
 }
 
 void launch_gemm_nt(const float *A, int64_t n, int d, const float *Bm, int nb, float *S, hipStream_t s)
 {
-    if (n == 0) return;
-    dim3 grid((unsigned)((n + TM - 1) / TM), (unsigned)((nb + TN - 1) / TN));
-    hipLaunchKernelGGL(k_tile_nt<false>, grid, dim3(256), 0, s, A, n, d, Bm, nb, nullptr, nullptr, S, nb);
-    PANO_HIP(hipGetLastError());
+    launch_gemm_jobs(product_job(A, n, d, Bm, nb, S), nullptr, s);
 }
 
 // ---------------------------------------------------------------- row norms

@@ -651,31 +651,89 @@ __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__
     };
     // bfloat16 rows: ||x - x~|| <= u_b ||x||
     const float delta = BF ? c.ub * tl[ss] + 1e-37f : 0.f;
-    int lv = lv_start;
-    for (; lv < g.L; ++lv) {
+    // the bound of a pair whose head distance sh covers the levels up to lv:
+    // 1 = pruned, 2 = accepted (its upper bound is under the threshold; the
+    // other side of Cauchy-Schwarz, UB = ||q_h - x_h||^2 + (||q_t|| +
+    // ||x_t||)^2, never grows with the level and every later bound, any eps,
+    // stays below it, so the remaining levels need no further tests), 0 = go on
+    auto test = [&](int lv, float b) -> int {
         const bool last = (lv + 1 == g.L);
-        const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
-        sh += level_part(lv);
         const float a = last ? 0.f : qt[lv + 1];
         const float dt = a - b;
         const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
         const float ct = c.mg.c_tail * (a + b) * (a + b);
         const bool pruned = BF ? bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct > th
                                : (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
-        if (pruned) {
-            lv_end = lv + 1;
-            return false;
-        }
-        // Upper bound (the other side of Cauchy-Schwarz): UB =
-        // ||q_h - x_h||^2 + (||q_t|| + ||x_t||)^2 never grows with the level,
-        // and every later bound (any eps) stays below it.  Once UB is under
-        // the threshold the pair cannot be pruned any more: the remaining
-        // levels need no further tests.
+        if (pruned) return 1;
         const float ubh = BF ? bf_head_upper(sh + err, delta) : sh + err;
-        if (!last && ubh + (a + b) * (a + b) + ct <= th) {
+        if (!last && ubh + (a + b) * (a + b) + ct <= th) return 2;
+        return 0;
+    };
+    int lv = lv_start;
+    if (lpp == 4 && c.walk2) {
+        // two levels per memory round trip: with four lanes per pair and
+        // levels of at most 64 dimensions, a lane's share of two levels is at
+        // most eight chunks, all requested together; the second level's
+        // reads are wasted when the first one prunes the pair
+        while (lv < g.L) {
+            const bool has2 = lv + 1 < g.L;
+            float4 xs[8], qs[8];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int l2 = min(lv + h, g.L - 1);
+                const int w4 = g.wp[l2] >> 2;
+                const float *qq4 = qrow + g.mp[l2];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int c4 = sub + 4 * j;
+                    if (c4 < w4 && (h == 0 || has2)) {
+                        xs[h * 4 + j] = ld4(l2, c4);
+                        qs[h * 4 + j] = *reinterpret_cast<const float4 *>(qq4 + c4 * 4);
+                    }
+                }
+            }
+            const float b0 = lv + 1 < g.L ? tl[(int64_t)(lv + 1) * g.B + ss] : 0.f;
+            const float b1 = lv + 2 < g.L ? tl[(int64_t)(lv + 2) * g.B + ss] : 0.f;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h == 1 && !has2) break;
+                const int w4 = g.wp[lv + h] >> 2;
+                float part = 0.f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (sub + 4 * j < w4) {
+                        const float4 x4 = xs[h * 4 + j], q4 = qs[h * 4 + j];
+                        float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
+                        part = __builtin_fmaf(t0, t0, part);
+                        part = __builtin_fmaf(t1, t1, part);
+                        part = __builtin_fmaf(t2, t2, part);
+                        part = __builtin_fmaf(t3, t3, part);
+                    }
+                }
+                part += __shfl_xor(part, 1, 64);
+                part += __shfl_xor(part, 2, 64);
+                sh += part;
+                const int r = test(lv + h, h == 0 ? b0 : b1);
+                if (r) {
+                    lv_end = lv + h + 1;
+                    accepted = r == 2;
+                    return r == 2;
+                }
+            }
+            lv += has2 ? 2 : 1;
+        }
+        lv_end = g.L;
+        return true;
+    }
+    for (; lv < g.L; ++lv) {
+        const bool last = (lv + 1 == g.L);
+        const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
+        sh += level_part(lv);
+        const int r = test(lv, b);
+        if (r) {
             lv_end = lv + 1;
-            accepted = true;
-            return true;
+            accepted = r == 2;
+            return r == 2;
         }
     }
     lv_end = lv;
@@ -1846,6 +1904,15 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     c.prune = brute ? 0 : 1;
     c.dense_min = (prm && prm->reserved[0] > 0) ? prm->reserved[0] : 64;
     c.walk_lanes = prm ? prm->reserved[2] : 0;
+    {
+        // two levels per step of the walk (four lanes per pair) when every
+        // level has at most 64 dimensions, unless one level per step is asked
+        int wmax = 0;
+        for (int l = 0; l < L; ++l) wmax = std::max(wmax, ix->wp[l]);
+        const int step = prm ? prm->reserved[3] : 0;
+        PANO_REQUIRE(step >= 0 && step <= 2, "walk levels per step must be 0, 1 or 2");
+        c.walk2 = (wmax <= 64 && step != 1) ? 1 : 0;
+    }
     PANO_REQUIRE(c.walk_lanes == 0 || c.walk_lanes == 1 || c.walk_lanes == 2 || c.walk_lanes == 4,
                  "walk lanes per pair must be 0, 1, 2 or 4");
     c.eps = eps;
@@ -2016,18 +2083,24 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         fl.add(qflags, nq, 0u);
         if (stats_on) fl.add(stats, 256, 0u);
         hipLaunchKernelGGL(k_fill_multi, dim3(256), dim3(256), 0, st, fl);
-        // query transform, tails and error bound on the second stream, beside
-        // the coarse probing on this one (they share only the raw queries)
-        hipStream_t sa = ctx->aux;
-        PANO_HIP(hipEventRecord(ctx->ev_fork2, st));
-        PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork2, 0));
-        launch_transform(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy, ix->d_pad, sa);
-        launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, sa);
-        hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, sa, vnorm, qtail, L, nq,
+        // query transform and query x centroid products in one launch (their
+        // tiles run side by side), then the transformed queries' tails and
+        // error bounds
+        {
+            const GemmJob jt = transform_job(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(),
+                                             ix->meta.as<int32_t>(), qy, ix->d_pad);
+            if (nlist > 1) {
+                const GemmJob jc = product_job(q, nq, d, ix->cent.as<float>(), nlist, Sco);
+                launch_gemm_jobs(jt, &jc, st);
+            } else {
+                launch_gemm_jobs(jt, nullptr, st);
+            }
+        }
+        launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, st);
+        hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, vnorm, qtail, L, nq,
                            mq, qE, qA, qbad);
-        // coarse probing
+        // coarse probing (and the number of queries per list)
         if (nlist > 1) {
-            launch_gemm_nt(q, nq, d, ix->cent.as<float>(), nlist, Sco, st);
             hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
                                ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq,
                                nprobe_dev, nprobe_all, c_co, np_max, probes, npq, list_cnt);
@@ -2035,20 +2108,20 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, np_max, probes,
                                npq, list_cnt);
         }
-        // threshold seeding (needs only the probes) runs beside the work
-        // decomposition on the context's second stream.  Only for the exact
-        // bound: a seed's own relaxed bound (eps < 1) may exceed its distance,
-        // so the scan could prune the very candidates that set d_k and return
-        // fewer than k; without seeding, every d_k comes from committed
-        // candidates.
-        // (the second stream runs it after the query transform it needs)
+        // threshold seeding (needs the probes and the transformed queries)
+        // runs beside the work decomposition on the context's second stream.
+        // Only for the exact bound: a seed's own relaxed bound (eps < 1) may
+        // exceed its distance, so the scan could prune the very candidates
+        // that set d_k and return fewer than k; without seeding, every d_k
+        // comes from committed candidates.
+        hipStream_t sa = ctx->aux;
         if (seed_on) {
             PANO_HIP(hipEventRecord(ctx->ev_fork, st));
             PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork, 0));
             hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, sa, c, iv, qv, probes, np_max,
                                ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
+            PANO_HIP(hipEventRecord(ctx->ev_join, sa));
         }
-        PANO_HIP(hipEventRecord(ctx->ev_join, sa));
         // work decomposition
         const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
         hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi, c.item_cap, list_cnt,
@@ -2058,7 +2131,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         if (split)
             hipLaunchKernelGGL(k_wl_items, dim3((unsigned)(8 * c.ceil8)), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi,
                                list_cnt, ix->list_blk_d.as<int64_t>(), item_off, items, pl.items_max);
-        PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+        if (seed_on) PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[1], st));
         WorkView w2 = wk;
         w2.stats = stats_on ? stats : nullptr;
@@ -2091,7 +2164,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         enqueue(ws, true);
     } else if (!(flags & PANO_SEARCH_EAGER)) {
         GraphKey key{ix->serial, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
-                     c.dense_min, c.bf16, split ? 1 : 0, c.walk_lanes, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
+                     c.dense_min, c.bf16, split ? 1 : 0, c.walk_lanes, c.walk2, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
                      split ? ctx->scratch[5].p : nullptr, split ? ctx->scratch[6].p : nullptr, ctx->pinned};
         if (!ctx->graph_exec || !(ctx->graph_key == key)) {
             ctx->drop_graph();

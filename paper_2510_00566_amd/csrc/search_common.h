@@ -44,6 +44,7 @@ struct SearchConsts {
     int prune;         // 1 = pruned scan, 0 = brute force
     int dense_min;     // refine a level densely while at least this many pairs survive
     int walk_lanes;    // lanes per pair in the per-pair walk (0 = by the number of pairs)
+    int walk2;         // 1: with four lanes per pair the walk reads two levels per step
     int bf16;          // 1: read level tiles in bfloat16 (certified margin, FP32 rescoring)
     float ub;          // bfloat16 unit roundoff 2^-8, rounded up (covers the stored-norm rounding)
     float bfdelta;     // bfloat16 scan: u_b max ||x|| (0 for the FP32 scan)

@@ -116,6 +116,7 @@ class Params:
     dense_min: int = 0
     scan_mode: int = 0  # 0/1 persistent scan, 2 segmented split scan (level-1 filter + level passes)
     walk_lanes: int = 0  # lanes per pair in the per-pair walk: 1, 2, 4 (0 = by the number of pairs)
+    walk_step: int = 0  # levels per step of the four-lane walk: 1 or 2 (0 = 2 when levels are <= 64 wide)
 
     def c(self):
         p = L.SearchParams()
@@ -124,6 +125,7 @@ class Params:
         p.reserved[0] = self.dense_min
         p.reserved[1] = self.scan_mode
         p.reserved[2] = self.walk_lanes
+        p.reserved[3] = self.walk_step
         return p
 
 
