@@ -142,8 +142,9 @@ def main():
     ids = torch.empty((w.nq, w.k), dtype=torch.int64, device="cuda")
     dists = torch.empty((w.nq, w.k), dtype=torch.float32, device="cuda")
 
-    def step(stats=False):
-        idx.search(qd, w.k, nprobe=npd, eps=1.0, params=prm, stats=stats, out=(ids, dists), eager=args.eager)
+    def step(stats=False, timing=False):
+        idx.search(qd, w.k, nprobe=npd, eps=1.0, params=prm, stats=stats, out=(ids, dists), eager=args.eager,
+                   timing=timing)
 
     for _ in range(args.warmup):
         step()
@@ -172,15 +173,21 @@ def main():
     if args.profile_only:
         print(json.dumps({"profile_only": True, "qps": qps, "ms_per_step": ms_per_step}))
         return
-    # ---- the dominant kernel: HIP events recorded by the library around the
-    # scan kernel on the stream it runs on, over the same number of searches
-    scan_ms, scan_bytes = [], []
-    for _ in range(args.steps):
-        step(stats=True)
-        st = idx.stats()
-        scan_ms.append(st["ms_scan"])
-        scan_bytes.append(st["scan_bytes"])
+    # ---- the dominant kernel: its bytes from the counting instance (one
+    # search), its duration from HIP events recorded by the library around the
+    # uncounted kernel on the stream it runs on, over the same number of
+    # searches as the timed region
+    step(stats=True)
     st = idx.stats()
+    scan_bytes = [st["scan_bytes"]]
+    counted = dict(st)
+    scan_ms, phases = [], []
+    for _ in range(args.steps):
+        step(timing=True)
+        stt = idx.stats()
+        scan_ms.append(stt["ms_scan"])
+        phases.append((stt["ms_prep"], stt["ms_scan"], stt["ms_merge"], stt["ms_total"]))
+    st = counted
     phi = st["dims_read"] / max(1, st["candidates"] * w.d)
 
     # ---- same-GPU brute force over the same probe lists and work decomposition
@@ -224,7 +231,9 @@ def main():
         torch.cuda.synchronize()
         el32 = time.perf_counter() - t1
         idx.search(qd, w.k, nprobe=npd, params=p32, stats=True, out=(fi, fd))
-        st32 = idx.stats()
+        st32 = dict(idx.stats())
+        idx.search(qd, w.k, nprobe=npd, params=p32, timing=True, out=(fi, fd))
+        st32["ms_scan"] = idx.stats()["ms_scan"]
         precision = {"f32_qps": w.nq * args.steps / el32, "f32_ms_per_step": el32 * 1000 / args.steps,
                      "bf16_qps": qps, "same_result_as_f32": bool(torch.equal(fi, ids) and torch.equal(fd, dists)),
                      "f32_scan_ms": st32["ms_scan"], "f32_scan_bytes": st32["scan_bytes"],
@@ -338,8 +347,8 @@ def main():
         "phi": phi,
         "alpha": tf.get()[3],
         "parity": parity,
-        "ms_breakdown": {"prep": st["ms_prep"], "scan": st["ms_scan"], "merge": st["ms_merge"],
-                         "total_device": st["ms_total"]},
+        "ms_breakdown": dict(zip(("prep", "scan", "merge", "total_device"),
+                                 (float(v) for v in np.median(np.asarray(phases), axis=0)))),
         "fallback_queries": st["fallback_queries"],
         "secondary": secondary,
         "precision": precision,

@@ -165,6 +165,10 @@ typedef struct {
 /* Search flags. */
 #define PANO_SEARCH_STATS 1u  /* collect counters, readable with pano_stats_get (runs eagerly) */
 #define PANO_SEARCH_EAGER 2u  /* do not replay the captured graph of the search */
+#define PANO_SEARCH_TIMING 4u /* run eagerly with events around the phases and
+                                 write only the ms_* fields of the counters
+                                 (the kernels are those of an ordinary search,
+                                 without the counting of PANO_SEARCH_STATS) */
 
 /*
  * search: k nearest neighbours of each query among the vectors of its probed

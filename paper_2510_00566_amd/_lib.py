@@ -15,6 +15,7 @@ PANO_OK, PANO_EINVAL, PANO_ENOMEM, PANO_EDEVICE, PANO_EUNSUPPORTED, PANO_EBUSY =
 PANO_F32, PANO_BF16 = 0, 1
 PANO_SEARCH_STATS = 1
 PANO_SEARCH_EAGER = 2
+PANO_SEARCH_TIMING = 4
 
 
 class SearchParams(C.Structure):

@@ -740,7 +740,7 @@ __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__
     return true;
 }
 
-template <bool PRUNE, bool BF>
+template <bool PRUNE, bool BF, bool STATS>
 __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView &ix, const QueryView &qv,
                                           const WorkView &wk)
 {
@@ -783,7 +783,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
     }
 #define PANO_PHASE(i)                                                  \
     do {                                                               \
-        if (wk.stats && tid == 0) {                                    \
+        if (STATS && wk.stats && tid == 0) {                                    \
             unsigned long long now_ = __builtin_readcyclecounter();    \
             cyc[i] += now_ - cyc[6];                                   \
             cyc[6] = now_;                                             \
@@ -809,7 +809,8 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             item_s = it;
         }
         __syncthreads();
-        const int item = item_s;
+        // uniform over the workgroup: kept in scalar registers
+        const int item = __builtin_amdgcn_readfirstlane(item_s);
         PANO_PHASE(0);
         if (item < 0) break;
         // ---- decode: binary search the queue-ordered item offsets
@@ -838,7 +839,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             E_s[tid] = qv.qE[qq];
             A_s[tid] = qv.qA[qq];
         }
-        ++my_items;
+        if (STATS) ++my_items;
         __syncthreads();
         for (int e = tid; e < ng * 64; e += NT) {
             const int gq = e >> 6, lv = e & 63;
@@ -926,7 +927,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         sval[nt * 4 + v] = sh;
                     }
                 }
-                if (tid == 0) {
+                if (STATS && tid == 0) {
                     my_bytes += (unsigned long long)cnt * (g.wp[0] * 2 + (g.L > 1 ? 8 : 4) + 4);
                     if (Lc > 0) my_lv[0] += (unsigned long long)cnt * ng;
                 }
@@ -953,7 +954,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         sval[nt * 4 + v] = sh;
                     }
                 }
-                if (tid == 0) {
+                if (STATS && tid == 0) {
                     my_bytes += (unsigned long long)cnt * (g.wp[0] * 4 + (g.L > 1 ? 8 : 4) + 4);
                     if (Lc > 0) my_lv[0] += (unsigned long long)cnt * ng;
                 }
@@ -967,6 +968,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                 while (lv_start < g.L) {
                     int alive_tot;
                     (void)block_exclusive_scan(__popc(mask), wave_tmp, &alive_tot);
+                    alive_tot = __builtin_amdgcn_readfirstlane(alive_tot);
                     if (alive_tot == 0 || alive_tot < c.dense_min || alive_tot * 4 < cnt) break;
                     const int lv = lv_start;
                     const int kgc = g.wp[lv] >> 2;
@@ -1030,7 +1032,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                             }
                         }
                     }
-                    if (tid == 0) {
+                    if (STATS && tid == 0) {
                         my_bytes += (unsigned long long)cnt * (g.wp[lv] * (BF ? 2 : 4) + 8);
                         if (lv < 64) my_lv[lv] += (unsigned long long)alive_tot;
                     }
@@ -1077,7 +1079,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         sval[nt * 4 + v] = dd;
                     }
                 }
-                if (tid == 0) {
+                if (STATS && tid == 0) {
                     my_bytes += (unsigned long long)cnt * (g.d_pad * 4 + 4 + 4);
                     for (int lv = 0; lv < Lc; ++lv) my_lv[lv] += (unsigned long long)cnt * ng;
                 }
@@ -1104,7 +1106,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             // level is read (no barrier between levels; the Update and
             // Consolidate phases of Section 6.1 run once, after the walk)
             if (PRUNE && lv_start < g.L) {
-                const int np_ = npairs_s;
+                const int np_ = __builtin_amdgcn_readfirstlane(npairs_s);
                 unsigned long long my_dims = 0;
                 // few pairs: several lanes per pair, so that each lane's
                 // share of a level is one memory round trip and the pairs
@@ -1124,13 +1126,13 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     // (the lanes of a pair hold the same values)
                     keep[p] = !alive ? 0 : (acc ? (uint8_t)(2 + lv) : 1);
                     pS[p] = sh;
-                    if (wk.stats && sub == 0) {
+                    if (STATS && wk.stats && sub == 0) {
                         const int lr = acc ? g.L : lv;
                         for (int v = lv_start; v < lr && v < 64; ++v) atomicAdd(&my_lv[v], 1ull);
                         my_dims += (unsigned long long)(g.mp[lr < g.L ? lr : g.L] - g.mp[lv_start]);
                     }
                 }
-                if (wk.stats && my_dims) atomicAdd(&sparse_bytes_s, my_dims * (BF ? 2ull : 4ull));
+                if (STATS && wk.stats && my_dims) atomicAdd(&sparse_bytes_s, my_dims * (BF ? 2ull : 4ull));
                 __syncthreads();
                 // Accepted pairs need their remaining levels summed, no more
                 // tests: a whole wavefront reads them for one pair at a time
@@ -1199,7 +1201,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
             }
             PANO_PHASE(2);
             // ---- commit: merge each query's survivors into its local top-kc
-            const int np_ = npairs_s;
+            const int np_ = __builtin_amdgcn_readfirstlane(npairs_s);
             if (np_ > 0) {
                 for (int i = tid; i < np_; i += NT) atomicAdd(&ncand[pr[i] >> 8], 1);
                 __syncthreads();
@@ -1296,7 +1298,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
         PANO_PHASE(4);
     }
 #undef PANO_PHASE
-    if (wk.stats && tid == 0) {
+    if (STATS && wk.stats && tid == 0) {
         for (int i = 0; i < 6; ++i) atomicAdd(&wk.stats[ST_CYCLES + i], cyc[i]);
         atomicAdd(&wk.stats[ST_ITEMS], my_items);
         atomicAdd(&wk.stats[ST_BYTES], my_bytes + sparse_bytes_s);
@@ -1308,23 +1310,37 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
 // The pruned scan is tuned for three workgroups per CU (its time goes to the
 // latency of the per-pair level walks); the brute-force scan keeps its
 // registers (its time goes to the dense matrix-core phase).
+// The searches themselves run the instances without counters; a search
+// asked for counters runs the *_stats instances (same arithmetic).
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_scan_pruned(SearchConsts c,
                                                                                             IndexView ix,
                                                                                             QueryView qv,
                                                                                             WorkView wk)
 {
-    scan_body<true, false>(c, ix, qv, wk);
+    scan_body<true, false, false>(c, ix, qv, wk);
+}
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_scan_pruned_stats(
+    SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    scan_body<true, false, true>(c, ix, qv, wk);
 }
 
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_scan_pruned_bf16(
     SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
 {
-    scan_body<true, true>(c, ix, qv, wk);
+    scan_body<true, true, false>(c, ix, qv, wk);
+}
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_scan_pruned_bf16_stats(
+    SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    scan_body<true, true, true>(c, ix, qv, wk);
 }
 
 __global__ __launch_bounds__(NT) void k_scan_brute(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
 {
-    scan_body<false, false>(c, ix, qv, wk);
+    scan_body<false, false, true>(c, ix, qv, wk);
 }
 
 // Split scan.  Each workgroup alternates between two phases over a private
@@ -2005,6 +2021,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     const int grid = (prm && prm->grid > 0) ? prm->grid : ctx->num_cu * (brute ? 2 : 3);
     const int np_max = nprobe_dev ? nlist : std::min(nprobe_all, nlist);
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
+    const bool want_timing = !want_stats && (flags & PANO_SEARCH_TIMING) != 0;
     const bool seed_on = !brute && eps >= 1.f;
     if (split) {
         ctx->scratch[5].ensure(need[4]);
@@ -2071,7 +2088,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     // Every device step of one search, in order, on stream st.  No memset
     // nodes: buffers are cleared by a fill kernel so the sequence can be
     // captured into a graph.
-    auto enqueue = [&](hipStream_t st, bool stats_on) {
+    auto enqueue = [&](hipStream_t st, bool stats_on, bool events_on) {
         FillList fl{};
         fl.add(qbad, 1, 0u);
         fl.add(qy, nq * (int64_t)ix->d_pad, 0u);
@@ -2132,7 +2149,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             hipLaunchKernelGGL(k_wl_items, dim3((unsigned)(8 * c.ceil8)), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi,
                                list_cnt, ix->list_blk_d.as<int64_t>(), item_off, items, pl.items_max);
         if (seed_on) PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
-        if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[1], st));
+        if (events_on) PANO_HIP(hipEventRecord(ctx->ev[1], st));
         WorkView w2 = wk;
         w2.stats = stats_on ? stats : nullptr;
         if (brute) {
@@ -2142,14 +2159,21 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
                 hipLaunchKernelGGL(k_scan_seg_bf16, dim3(pl.grid_seg), dim3(NT), 0, st, c, iv, qv, w2);
             else
                 hipLaunchKernelGGL(k_scan_seg, dim3(pl.grid_seg), dim3(NT), 0, st, c, iv, qv, w2);
-        } else if (use_bf16)
-            hipLaunchKernelGGL(k_scan_pruned_bf16, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
-        else
-            hipLaunchKernelGGL(k_scan_pruned, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
-        if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[2], st));
+        } else if (use_bf16) {
+            if (stats_on)
+                hipLaunchKernelGGL(k_scan_pruned_bf16_stats, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+            else
+                hipLaunchKernelGGL(k_scan_pruned_bf16, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+        } else {
+            if (stats_on)
+                hipLaunchKernelGGL(k_scan_pruned_stats, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+            else
+                hipLaunchKernelGGL(k_scan_pruned, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+        }
+        if (events_on) PANO_HIP(hipEventRecord(ctx->ev[2], st));
         hipLaunchKernelGGL(k_merge, dim3((unsigned)nq), dim3(NT), merge_shm, st, c, buf, buf_cnt, qflags, qE, qA, q,
                            ix->raw.as<float>(), d, ids, dists, stats_on ? stats : nullptr);
-        if (stats_on) PANO_HIP(hipEventRecord(ctx->ev[3], st));
+        if (events_on) PANO_HIP(hipEventRecord(ctx->ev[3], st));
         PANO_HIP(hipMemcpyAsync(h_flags, qflags, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
         PANO_HIP(hipMemcpyAsync(h_flags + nq, qbad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         PANO_HIP(hipGetLastError());
@@ -2159,9 +2183,9 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     hipStream_t ws = ctx->work_stream();
     PANO_HIP(hipEventRecord(ctx->ev_in, s));
     PANO_HIP(hipStreamWaitEvent(ws, ctx->ev_in, 0));
-    if (want_stats) {
+    if (want_stats || want_timing) {
         PANO_HIP(hipEventRecord(ctx->ev[0], ws));
-        enqueue(ws, true);
+        enqueue(ws, want_stats, true);
     } else if (!(flags & PANO_SEARCH_EAGER)) {
         GraphKey key{ix->serial, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
                      c.dense_min, c.bf16, split ? 1 : 0, c.walk_lanes, c.walk2, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
@@ -2171,7 +2195,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             hipGraph_t graph;
             PANO_HIP(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
             try {
-                enqueue(ws, false);
+                enqueue(ws, false, false);
             } catch (...) {
                 hipGraph_t dummy;
                 (void)hipStreamEndCapture(ws, &dummy);
@@ -2185,7 +2209,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         }
         PANO_HIP(hipGraphLaunch(ctx->graph_exec, ws));
     } else {
-        enqueue(ws, false);
+        enqueue(ws, false, false);
     }
     PANO_HIP(hipStreamSynchronize(ws));
     std::vector<int32_t> hflags(h_flags, h_flags + nq);
@@ -2216,6 +2240,20 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         hipLaunchKernelGGL(k_fallback_select, dim3(1), dim3(NT), 0, s, keys, total, k, ids + qi * k, dists + qi * k);
         PANO_HIP(hipGetLastError());
         PANO_HIP(hipStreamSynchronize(s));
+    }
+    if (want_timing) {
+        PANO_HIP(hipEventRecord(ctx->ev[4], s));
+        PANO_HIP(hipEventSynchronize(ctx->ev[4]));
+        pano_stats_t &st = ix->stats;
+        float t;
+        PANO_HIP(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[4]));
+        st.ms_total = t;
+        PANO_HIP(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
+        st.ms_prep = t;
+        PANO_HIP(hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[2]));
+        st.ms_scan = t;
+        PANO_HIP(hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3]));
+        st.ms_merge = t;
     }
     if (want_stats) {
         PANO_HIP(hipEventRecord(ctx->ev[4], s));

@@ -156,9 +156,11 @@ class Index:
         return ids, dists
 
     def search(self, q_dev, k: int, nprobe=1, eps: float = 1.0, params: Params | None = None,
-               stats: bool = False, stream=None, out=None, eager: bool = False, ctx: Context | None = None):
+               stats: bool = False, stream=None, out=None, eager: bool = False, ctx: Context | None = None,
+               timing: bool = False):
         """k-NN of each row of q_dev among its probed lists.  ctx: run on this
-        context (one per concurrent caller) instead of the index's own."""
+        context (one per concurrent caller) instead of the index's own.
+        timing: phase durations of an ordinary (uncounted) search in stats()."""
         import torch
         ids, dists = out if out is not None else self._outs(q_dev, k)
         np_dev = None
@@ -168,7 +170,8 @@ class Index:
         else:
             np_all = int(nprobe)
         prm = params.c() if params is not None else None
-        flags = (L.PANO_SEARCH_STATS if stats else 0) | (L.PANO_SEARCH_EAGER if eager else 0)
+        flags = ((L.PANO_SEARCH_STATS if stats else 0) | (L.PANO_SEARCH_EAGER if eager else 0) |
+                 (L.PANO_SEARCH_TIMING if timing else 0))
         c = ctx if ctx is not None else self.ctx
         L.check(L.lib().pano_search_ctx(c.h, self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all,
                                         float(eps), _ptr(ids), _ptr(dists),
