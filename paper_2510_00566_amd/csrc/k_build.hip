@@ -16,12 +16,14 @@ namespace pano {
 // the running total, so every output carries a rounding error of at most
 // gamma(32 + ceil(K/32) + 1) times the sum of the absolute products (the
 // bound the pruning margins are built on).
-constexpr int TM = 32, TN = 64, TK = 32, TLD = 36;
+constexpr int TM = 64, TN = 64, TK = 32, TLD = 36;
+constexpr int RF = TM / 32;  // 16-row fragments per wavefront (waves in a 2 x 2 grid)
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 // One launch may carry two independent products (jobs): the workgroups with
 // blockIdx.y < y0 take job j0, the others job j1 (column tile blockIdx.y - y0).
-__global__ __launch_bounds__(256) void k_tile_nt(GemmJob j0, GemmJob j1, int y0)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tile_nt(GemmJob j0, GemmJob j1,
+                                                                                           int y0)
 {
     const bool first = (int)blockIdx.y < y0;
     const float *__restrict__ A = first ? j0.A : j1.A;
@@ -40,31 +42,33 @@ __global__ __launch_bounds__(256) void k_tile_nt(GemmJob j0, GemmJob j1, int y0)
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int r16 = lane & 15, kq = lane >> 4;
-    const int wr = (w >> 1) * 16, wc = (w & 1) * 32;
+    const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * 32;
     const int64_t r0 = (int64_t)blockIdx.x * TM;
     const int c0 = (first ? (int)blockIdx.y : (int)blockIdx.y - y0) * TN;
     constexpr int NA = (TM * TK) / 256, NB = (TN * TK) / 256;
     // a register set holds one fetched chunk as loaded (this thread's share
-    // of A, mu and B) and the chunk's start; the out-of-range values are
-    // replaced and mu subtracted only when the chunk is stored to LDS, so
-    // nothing waits for the loads before then
+    // of A and B, and the one mu value of its column: e % TK is tid % TK for
+    // every element e of the thread) and the chunk's start; the out-of-range
+    // values are replaced and mu subtracted only when the chunk is stored to
+    // LDS, so nothing waits for the loads before then
+    static_assert(256 % TK == 0, "a thread keeps one column of each chunk");
     struct RegSet {
-        float a[NA], m[NA], b[NB];
+        float a[NA], b[NB], m;
         int k0;
     };
-    // every load is issued from a clamped (valid) index, so no branch
-    // separates the loads of a chunk and they are all in flight together
     const bool sub_mu = mu != nullptr;
     const float *__restrict__ mu_ld = sub_mu ? mu : A;  // any valid row when unused
+    // every load is issued from a clamped (valid) index, so no branch
+    // separates the loads of a chunk and they are all in flight together
     auto fetch = [&](int k0, RegSet &R) {
         R.k0 = k0;
+        R.m = mu_ld[min(k0 + tid % TK, K - 1)];
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
             const int e = tid + t * 256;
             const int64_t r = min(r0 + e / TK, n - 1);
             const int kx = min(k0 + e % TK, K - 1);
             R.a[t] = A[r * K + kx];
-            R.m[t] = mu_ld[kx];
         }
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
@@ -79,7 +83,7 @@ __global__ __launch_bounds__(256) void k_tile_nt(GemmJob j0, GemmJob j1, int y0)
         for (int t = 0; t < NA; ++t) {
             const int e = tid + t * 256;
             const bool ok = r0 + e / TK < n && R.k0 + e % TK < K;
-            As[buf][e / TK][e % TK] = ok ? (sub_mu ? R.a[t] - R.m[t] : R.a[t]) : 0.f;
+            As[buf][e / TK][e % TK] = ok ? (sub_mu ? R.a[t] - R.m : R.a[t]) : 0.f;
         }
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
@@ -88,25 +92,31 @@ __global__ __launch_bounds__(256) void k_tile_nt(GemmJob j0, GemmJob j1, int y0)
             Bs[buf][e / TK][e % TK] = ok ? R.b[t] : 0.f;
         }
     };
-    floatx4_t tot[2];
-    tot[0] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    tot[1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    floatx4_t tot[RF][2];
+#pragma unroll
+    for (int i = 0; i < RF; ++i) tot[i][0] = tot[i][1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     const int nchunks = (K + TK - 1) / TK;
     auto compute = [&](int buf) {
-        floatx4_t acc[2];
-        acc[0] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-        acc[1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        floatx4_t acc[RF][2];
+#pragma unroll
+        for (int i = 0; i < RF; ++i) acc[i][0] = acc[i][1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < TK / 4; ++ks) {
-            const float a = As[buf][wr + r16][ks * 4 + kq];
+            float a[RF], b[2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const float b = Bs[buf][wc + j * 16 + r16][ks * 4 + kq];
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
-            }
+            for (int i = 0; i < RF; ++i) a[i] = As[buf][wr + i * 16 + r16][ks * 4 + kq];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[buf][wc + j * 16 + r16][ks * 4 + kq];
+#pragma unroll
+            for (int i = 0; i < RF; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        tot[0] += acc[0];
-        tot[1] += acc[1];
+#pragma unroll
+        for (int i = 0; i < RF; ++i) {
+            tot[i][0] += acc[i][0];
+            tot[i][1] += acc[i][1];
+        }
     };
     // Four chunks in flight.  Register set R[j] receives chunks j, j + 4, ...;
     // step ch computes LDS stage ch & 1, stores chunk ch + 1 into the other
@@ -144,16 +154,18 @@ __global__ __launch_bounds__(256) void k_tile_nt(GemmJob j0, GemmJob j1, int y0)
     }
     // lane holds rows 4*(lane/16) + v of column lane%16 of each 16 x 16 tile
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < RF; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t r = r0 + wr + 4 * kq + v;
-            const int c = c0 + wc + j * 16 + r16;
-            if (r < n && c < nb) {
-                const int oc = outcol ? outcol[c] : c;
-                Out[r * ld_out + oc] = tot[j][v];
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t r = r0 + wr + i * 16 + 4 * kq + v;
+                const int c = c0 + wc + j * 16 + r16;
+                if (r < n && c < nb) {
+                    const int oc = outcol ? outcol[c] : c;
+                    Out[r * ld_out + oc] = tot[i][j][v];
+                }
             }
-        }
 }
 
 GemmJob transform_job(const float *X, int64_t n, int d, const float *T, const float *mu, const int32_t *padcol,
