@@ -253,10 +253,19 @@ void launch_transform(const float *X, int64_t n, int d, const float *T, const fl
 // coarse step.
 void launch_gemm_nt(const float *A, int64_t n, int d, const float *Bm, int nb, float *S,
                     hipStream_t s);
+// Optional per-query outputs of launch_row_norms: the error bound E_q, the
+// absolute margin A_q of the dot-product form, and a flag set when a query
+// has a non-finite value.
+struct QueryConstsOut {
+    Margins mg;
+    float *qE = nullptr;
+    float *qA = nullptr;
+    int *bad = nullptr;
+};
 // Per row: tail norms sqrt(sum_{j >= mp_l} y_j^2) for l = 0..L-1 (FP64 sums),
-// and ||fl(x - mu)|| in FP64 (vnorm).
+// and ||fl(x - mu)|| in FP64 (vnorm); with qc, the query constants too.
 void launch_row_norms(const float *Y, int64_t n, const LevelGeom &g, const float *X, const float *mu,
-                      float *tails_rowmajor, double *vnorm, hipStream_t s);
+                      float *tails_rowmajor, double *vnorm, hipStream_t s, const QueryConstsOut *qc = nullptr);
 void launch_argmin_rows(const float *S, int64_t n, int nb, const float *cnorm, int32_t *assign,
                         hipStream_t s);
 void launch_centroid_update(const float *X, int d, const int64_t *perm, const int64_t *off, int nlist,

@@ -219,13 +219,15 @@ template <int VPL>
 __global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, int64_t n, LevelGeom g,
                                                    const float *__restrict__ X,
                                                    const float *__restrict__ mu,
-                                                   float *__restrict__ tails, double *__restrict__ vnorm)
+                                                   float *__restrict__ tails, double *__restrict__ vnorm,
+                                                   QueryConstsOut qc)
 {
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= n) return;
     const float *y = Y + r * g.d_pad;
     double suffix = 0.0;
+    float tail0 = 0.f;  // the tail norm after level 0 (the row's norm), last one computed
     if (VPL > 0) {
         float v[VPL > 0 ? VPL : 1];
 #pragma unroll
@@ -243,7 +245,9 @@ __global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, 
             }
             e = wave_sum_f64(e);
             suffix += e;
-            if (lane == 0) tails[r * g.L + l] = (float)sqrt(suffix);
+            const float tv = (float)sqrt(suffix);
+            if (lane == 0) tails[r * g.L + l] = tv;
+            tail0 = tv;
         }
     } else {
         for (int l = g.L - 1; l >= 0; --l) {
@@ -254,7 +258,9 @@ __global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, 
             }
             e = wave_sum_f64(e);
             suffix += e;
-            if (lane == 0) tails[r * g.L + l] = (float)sqrt(suffix);
+            const float tv = (float)sqrt(suffix);
+            if (lane == 0) tails[r * g.L + l] = tv;
+            tail0 = tv;
         }
     }
     if (vnorm) {
@@ -277,21 +283,33 @@ __global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, 
             }
         }
         e = wave_sum_f64(e);
-        if (lane == 0) vnorm[r] = sqrt(e);
+        const double vn = sqrt(e);
+        if (lane == 0) vnorm[r] = vn;
+        if (qc.qE && lane == 0) {
+            // the query's error bound E_q = kappa ||fl(q - mu)|| + e_max and
+            // absolute margin A_q = c_abs (a_0^2 + b0max2), each rounded up
+            // by a relative 1e-6 to cover the FP32 rounding
+            if (!isfinite(vn)) atomicOr(qc.bad, 1);
+            qc.qE[r] = (float)((double)qc.mg.kappa * vn * (1.0 + 1e-6)) + qc.mg.e_max;
+            const double a0 = (double)tail0;
+            qc.qA[r] = (float)((double)qc.mg.c_abs * (a0 * a0 * (1.0 + 1e-6) + (double)qc.mg.b0max2) * (1.0 + 1e-6));
+        }
     }
 }
 
 void launch_row_norms(const float *Y, int64_t n, const LevelGeom &g, const float *X, const float *mu,
-                      float *tails_rowmajor, double *vnorm, hipStream_t s)
+                      float *tails_rowmajor, double *vnorm, hipStream_t s, const QueryConstsOut *qc)
 {
     if (n == 0) return;
     dim3 grid((unsigned)((n + 3) / 4));
+    QueryConstsOut q{};
+    if (qc) q = *qc;
     if (g.d_pad <= 256)
-        hipLaunchKernelGGL(k_row_norms<4>, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm);
+        hipLaunchKernelGGL(k_row_norms<4>, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm, q);
     else if (g.d_pad <= 1024)
-        hipLaunchKernelGGL(k_row_norms<16>, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm);
+        hipLaunchKernelGGL(k_row_norms<16>, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm, q);
     else
-        hipLaunchKernelGGL(k_row_norms<0>, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm);
+        hipLaunchKernelGGL(k_row_norms<0>, grid, dim3(256), 0, s, Y, n, g, X, mu, tails_rowmajor, vnorm, q);
     PANO_HIP(hipGetLastError());
 }
 

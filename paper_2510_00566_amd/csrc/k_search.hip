@@ -10,18 +10,6 @@
 namespace pano {
 
 // ================================================================ query prep
-__global__ void k_query_consts(const double *__restrict__ vnorm, const float *__restrict__ qtail, int L, int64_t nq,
-                               Margins mg, float *__restrict__ qE, float *__restrict__ qA, int *__restrict__ bad)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nq) return;
-    if (!isfinite(vnorm[i])) atomicOr(bad, 1);
-    // Rounded up by a relative 1e-6 to cover the FP32 rounding of these bounds.
-    qE[i] = (float)((double)mg.kappa * vnorm[i] * (1.0 + 1e-6)) + mg.e_max;
-    const double a0 = (double)qtail[i * L];
-    qA[i] = (float)((double)mg.c_abs * (a0 * a0 * (1.0 + 1e-6) + (double)mg.b0max2) * (1.0 + 1e-6));
-}
-
 // ================================================================ coarse probing
 // One wavefront per query.  Approximate distances to every centroid come from
 // the dense product S = q . c (chunked FP32 on the matrix cores), with a
@@ -2113,9 +2101,14 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
                 launch_gemm_jobs(jt, nullptr, st);
             }
         }
-        launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, st);
-        hipLaunchKernelGGL(k_query_consts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, vnorm, qtail, L, nq,
-                           mq, qE, qA, qbad);
+        {
+            QueryConstsOut qc;
+            qc.mg = mq;
+            qc.qE = qE;
+            qc.qA = qA;
+            qc.bad = qbad;
+            launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, st, &qc);
+        }
         // coarse probing (and the number of queries per list)
         if (nlist > 1) {
             hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
