@@ -137,35 +137,6 @@ __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, cons
             atomicAdd(&list_cnt[l], 1);
         }
     }
-    // rank 0 = the probed list with the smallest approximate distance (the
-    // seeding step draws its first candidates from it)
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    float bestv = INFINITY;
-    int bestpos = 0x7fffffff, bestl = 0x7fffffff;
-    for (int i = lane; i < p; i += 64) {
-        const int l = probes[qi * np_max + i];
-        const float v = 0.5f * (LO[l] + UP[l]);
-        if (v < bestv || (v == bestv && l < bestl)) {
-            bestv = v;
-            bestl = l;
-            bestpos = i;
-        }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const float ov = __shfl_xor(bestv, o, 64);
-        const int ol = __shfl_xor(bestl, o, 64), op = __shfl_xor(bestpos, o, 64);
-        if (ov < bestv || (ov == bestv && ol < bestl)) {
-            bestv = ov;
-            bestl = ol;
-            bestpos = op;
-        }
-    }
-    if (lane == 0 && bestpos != 0 && bestpos < p) {
-        const int first = probes[qi * np_max];
-        probes[qi * np_max] = bestl;
-        probes[qi * np_max + bestpos] = first;
-    }
     for (int i = p + lane; i < np_max; i += 64) probes[qi * np_max + i] = -1;
     if (lane == 0) np_out[qi] = p;
 }
@@ -285,7 +256,9 @@ struct QueryView {
 // `cnt` most promising ones and start d_k from their k-th best (Algorithm 1
 // seeds its heap with exact distances before the first batch).
 __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, QueryView qv,
-                                             const int32_t *__restrict__ probes, int np_max,
+                                             const float *__restrict__ S_, const float *__restrict__ cn2,
+                                             int d, int nlist, const int32_t *__restrict__ nprobe_dev,
+                                             int nprobe_all, int np_max, float c_co,
                                              const int64_t *__restrict__ list_len, int pool, int cnt,
                                              float *__restrict__ thr)
 {
@@ -293,8 +266,79 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
     __shared__ float Ds[256];
     __shared__ float4 q1[16];
     __shared__ int chunk_off[1024], chunk_w[1024];
+    __shared__ float red_f[NT / 64];
+    __shared__ int red_i[NT / 64];
     const int64_t q = blockIdx.x;
-    const int l0 = probes[q * np_max];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // The list to seed from: the centroid nearest by the approximate
+    // distances of the coarse products, taken only when it is certainly in
+    // the probe set, i.e. fewer than p other lists have a lower bound at or
+    // below its upper bound (the bounds are those of the coarse step).  This
+    // needs no result of the coarse step, so the two run side by side.
+    int l0 = 0;
+    if (nlist > 1) {
+        int p = nprobe_dev ? nprobe_dev[q] : nprobe_all;
+        p = p < 1 ? 1 : (p > nlist ? nlist : p);
+        if (p > np_max) p = np_max;
+        // ||q||^2 in the coarse step's FP32 order (per lane, columns in
+        // increasing order, then a butterfly)
+        float qq = 0.f;
+        for (int j = lane; j < d; j += 64) {
+            const float v = qv.qraw[q * d + j];
+            qq = __builtin_fmaf(v, v, qq);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o, 64);
+        const float *Sq = S_ + q * nlist;
+        float bu = INFINITY;
+        int bl = 0x7fffffff;
+        for (int l = threadIdx.x; l < nlist; l += NT) {
+            const float a = qq + cn2[l] - 2.f * Sq[l];
+            const float del = c_co * (qq + cn2[l]);
+            const float up = fmaxf(a + del, 0.f) * (1.0f + 1.2e-7f);
+            if (up < bu) {
+                bu = up;
+                bl = l;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const float ou = __shfl_xor(bu, o, 64);
+            const int ol = __shfl_xor(bl, o, 64);
+            if (ou < bu || (ou == bu && ol < bl)) {
+                bu = ou;
+                bl = ol;
+            }
+        }
+        if (lane == 0) {
+            red_f[wv] = bu;
+            red_i[wv] = bl;
+        }
+        __syncthreads();
+        bu = red_f[0];
+        bl = red_i[0];
+        for (int w = 1; w < NT / 64; ++w)
+            if (red_f[w] < bu || (red_f[w] == bu && red_i[w] < bl)) {
+                bu = red_f[w];
+                bl = red_i[w];
+            }
+        int before = 0;
+        for (int l = threadIdx.x; l < nlist; l += NT) {
+            const float a = qq + cn2[l] - 2.f * Sq[l];
+            const float del = c_co * (qq + cn2[l]);
+            const float lo = fmaxf(a - del, 0.f) * (1.0f - 1.2e-7f);
+            before += (l != bl && lo <= bu) ? 1 : 0;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
+        __syncthreads();
+        if (lane == 0) red_i[wv] = before;
+        __syncthreads();
+        int tot = 0;
+        for (int w = 0; w < NT / 64; ++w) tot += red_i[w];
+        if (tot >= p) return;  // not certain to be probed: no seed for this query
+        l0 = bl;
+    }
     const int64_t len = list_len[l0];
     const int P = (int)min<int64_t>(pool, len);
     const int S = min(cnt, P);
@@ -2109,6 +2153,8 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             qc.bad = qbad;
             launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, st, &qc);
         }
+        hipStream_t sa = ctx->aux;
+        if (seed_on) PANO_HIP(hipEventRecord(ctx->ev_fork, st));
         // coarse probing (and the number of queries per list)
         if (nlist > 1) {
             hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
@@ -2118,18 +2164,19 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, np_max, probes,
                                npq, list_cnt);
         }
-        // threshold seeding (needs the probes and the transformed queries)
-        // runs beside the work decomposition on the context's second stream.
-        // Only for the exact bound: a seed's own relaxed bound (eps < 1) may
-        // exceed its distance, so the scan could prune the very candidates
-        // that set d_k and return fewer than k; without seeding, every d_k
-        // comes from committed candidates.
-        hipStream_t sa = ctx->aux;
+        // threshold seeding (needs the transformed queries and the coarse
+        // products, not the probe sets) runs on the context's second stream
+        // beside the coarse probing and the work decomposition; it is
+        // launched after the coarse step so that step's waves are dispatched
+        // first.  Only for the exact bound: a seed's own relaxed bound
+        // (eps < 1) may exceed its distance, so the scan could prune the very
+        // candidates that set d_k and return fewer than k; without seeding,
+        // every d_k comes from committed candidates.
         if (seed_on) {
-            PANO_HIP(hipEventRecord(ctx->ev_fork, st));
             PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork, 0));
-            hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, sa, c, iv, qv, probes, np_max,
-                               ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
+            hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, sa, c, iv, qv, Sco,
+                               ix->cent.as<float>() + (size_t)nlist * d, d, nlist, nprobe_dev, nprobe_all, np_max,
+                               c_co, ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
             PANO_HIP(hipEventRecord(ctx->ev_join, sa));
         }
         // work decomposition
