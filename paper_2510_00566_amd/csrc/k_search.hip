@@ -1372,6 +1372,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 
 __global__ __launch_bounds__(NT) void k_scan_brute(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
 {
+    scan_body<false, false, false>(c, ix, qv, wk);
+}
+
+__global__ __launch_bounds__(NT) void k_scan_brute_stats(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
     scan_body<false, false, true>(c, ix, qv, wk);
 }
 
@@ -2193,7 +2198,10 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         WorkView w2 = wk;
         w2.stats = stats_on ? stats : nullptr;
         if (brute) {
-            hipLaunchKernelGGL(k_scan_brute, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+            if (stats_on)
+                hipLaunchKernelGGL(k_scan_brute_stats, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+            else
+                hipLaunchKernelGGL(k_scan_brute, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
         } else if (split) {
             if (use_bf16)
                 hipLaunchKernelGGL(k_scan_seg_bf16, dim3(pl.grid_seg), dim3(NT), 0, st, c, iv, qv, w2);
