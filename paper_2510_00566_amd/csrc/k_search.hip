@@ -776,7 +776,7 @@ template <bool PRUNE, bool BF, bool STATS>
 __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView &ix, const QueryView &qv,
                                           const WorkView &wk)
 {
-    __shared__ uint32_t pr[GMAX * 256];
+    __shared__ uint16_t pr[GMAX * 256];  // (query in group) << 8 | slot
     __shared__ float pS[GMAX * 256];
     // dynamic LDS: [per-wave sort buffers: 4 x sbw][local top-kc: G x kc]; the
     // walk's keep flags alias the sort buffers (never live at the same time)
@@ -1125,7 +1125,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                 for (int b = 0; b < 16; ++b) {
                     if (mask & (1u << b)) {
                         const int nt = b >> 2, v = b & 3;
-                        pr[off] = ((uint32_t)(4 * kq + v) << 8) | (uint32_t)(slot0 + nt * 16 + r16);
+                        pr[off] = (uint16_t)(((4 * kq + v) << 8) | (slot0 + nt * 16 + r16));
                         pS[off] = sval[b];
                         ++off;
                     }
@@ -1222,7 +1222,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     int tot;
                     int off = block_exclusive_scan(f ? 1 : 0, wave_tmp, &tot);
                     if (f) {
-                        pr[kept + off] = pv;
+                        pr[kept + off] = (uint16_t)pv;
                         pS[kept + off] = sv;
                     }
                     kept += tot;
@@ -1919,7 +1919,11 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     size_t *need = pl.need;
     c = SearchConsts{};
     c.k = k;
-    c.kc = next_pow2(std::max(2 * k, 16));
+    // local top-k per query of a work item: its k best and their margin
+    // band; the bfloat16 scan's wider bracket makes the band longer, so
+    // it keeps at least 64
+    const bool bf16_req = !brute && prm && prm->use_bf16;
+    c.kc = next_pow2(std::max(2 * k, bf16_req ? 64 : 16));
     int G = 16;
     while (G > 1 && G * c.kc > 2048) G >>= 1;
     if (prm && prm->group > 0) G = std::min(prm->group, G);
