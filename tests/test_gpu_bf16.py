@@ -91,6 +91,13 @@ def test_bf16_gist_shape_knobs(torch_cuda, kw):
     q = torch_cuda.from_numpy(case["data"]["q"]).cuda()
     ids, dd = case["idx"].search(q, w.k, nprobe=w.nprobe, params=Params(**kw))
     gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
+    si, sd = case["idx"].search(q, w.k, nprobe=w.nprobe, params=Params(**kw), stats=True)
+    gc.compare(si.cpu().numpy(), sd.cpu().numpy(), ref_i, ref_d)
+    st = case["idx"].stats()
+    _log("bf16", kw, "fallback queries", st["fallback_queries"], "band", st["band"])
+    if kw == dict(use_bf16=1):
+        # the local top-k holds the widened band: no query needs the fallback
+        assert st["fallback_queries"] == 0
     ei, ed = case["idx"].search(q, w.k, nprobe=w.nprobe, params=Params(**kw), eager=True)
     gc.compare(ei.cpu().numpy(), ed.cpu().numpy(), ref_i, ref_d)
 
