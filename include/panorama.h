@@ -152,7 +152,10 @@ typedef struct {
                              with a local top-k per work item, 2 = segmented
                              split scan (level-1 filter, then one pass per
                              level over each workgroup's surviving pairs;
-                             needs L >= 2, else the persistent scan runs);
+                             needs L >= 2, else the persistent scan runs),
+                             3 = no pruning (the brute-force scan of
+                             pano_search_bruteforce; same answer), for
+                             workloads whose bounds prune too little;
                              [2]: lanes per pair in the per-pair walk of the
                              persistent scan: 1, 2 or 4 (0 = 4 when at most
                              64 pairs of a block survive, 2 up to 128, else

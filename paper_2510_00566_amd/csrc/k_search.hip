@@ -1914,6 +1914,10 @@ struct SearchPlan {
 static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_np, int nprobe_all, float eps,
                         const pano_search_params *prm, bool brute, SearchConsts &c, SearchPlan &pl)
 {
+    // scan mode 3: every candidate's full distance, no pruning (the brute-force
+    // scan), chosen by the tuner where the bounds prune too little to pay
+    if (prm && prm->reserved[1] == 3) brute = true;
+    PANO_REQUIRE(!prm || (prm->reserved[1] >= 0 && prm->reserved[1] <= 3), "scan mode must be 0, 1, 2 or 3");
     PANO_REQUIRE(k <= 128, "k up to 128 is supported");
     const int d = ix->d, L = ix->L, nlist = ix->nlist;
     size_t *need = pl.need;
@@ -2041,6 +2045,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
 {
     PANO_REQUIRE(ctx->device == ix->ctx->device, "context and index are on different devices");
     PANO_HIP(hipSetDevice(ctx->device));
+    if (prm && prm->reserved[1] == 3) brute = true;  // scan mode 3: no pruning
     const int d = ix->d, L = ix->L, nlist = ix->nlist;
     SearchConsts c;
     SearchPlan pl;

@@ -114,7 +114,7 @@ class Params:
     grid: int = 0
     use_bf16: int = 0
     dense_min: int = 0
-    scan_mode: int = 0  # 0/1 persistent scan, 2 segmented split scan (level-1 filter + level passes)
+    scan_mode: int = 0  # 0/1 persistent scan, 2 segmented split scan, 3 no pruning (brute-force scan)
     walk_lanes: int = 0  # lanes per pair in the per-pair walk: 1, 2, 4 (0 = by the number of pairs)
     walk_step: int = 0  # levels per step of the four-lane walk: 1 or 2 (0 = 2 when levels are <= 64 wide)
 

@@ -103,6 +103,10 @@ PARAM_GRID = [
     dict(blocks_per_item=2, group=1, grid=7),
     dict(scan_mode=2),
     dict(scan_mode=2, group=4, grid=5),
+    dict(scan_mode=3),
+    dict(walk_lanes=1),
+    dict(walk_lanes=2),
+    dict(walk_lanes=4, walk_step=1),
 ]
 
 
