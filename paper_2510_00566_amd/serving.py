@@ -263,12 +263,14 @@ def latency_report(reqs: list) -> dict:
 class GpuExecutor:
     """Runs a batch as one search on the worker's own context and stream.
 
-    indexes: name -> Index.  One Context and one torch stream per worker."""
+    indexes: name -> Index; params: name -> search Params (None: library
+    defaults).  One Context and one torch stream per worker."""
 
-    def __init__(self, indexes: dict, n_workers: int, device: int = 0):
+    def __init__(self, indexes: dict, n_workers: int, device: int = 0, params: dict | None = None):
         import torch
         from .index import Context
         self.indexes = indexes
+        self.params = params or {}
         self.ctxs = [Context(device) for _ in range(n_workers)]
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_workers)]
         self.device = device
@@ -277,7 +279,7 @@ class GpuExecutor:
         idx = self.indexes[index]
         d = idx.d
         io = nq * (d * 4 + 4 + k * 12)  # queries, probe counts, ids + dists
-        return int(idx.scratch_bytes(nq, k, per_query_nprobe=True) + io)
+        return int(idx.scratch_bytes(nq, k, per_query_nprobe=True, params=self.params.get(index)) + io)
 
     def __call__(self, wid: int, b: Batch):
         import torch
@@ -290,7 +292,8 @@ class GpuExecutor:
             npd = torch.from_numpy(npr).to(f"cuda:{self.device}", non_blocking=False)
             # batch shapes vary from call to call: launch eagerly rather than
             # capture a graph per shape
-            ids, dd = idx.search(qd, b.k, nprobe=npd, ctx=self.ctxs[wid], stream=st, eager=True)
+            ids, dd = idx.search(qd, b.k, nprobe=npd, ctx=self.ctxs[wid], stream=st, eager=True,
+                                 params=self.params.get(b.index))
             ids_h = ids.cpu().numpy()
             dd_h = dd.cpu().numpy()
         outs, o = [], 0
@@ -307,7 +310,7 @@ def main(argv=None):
 
     import torch
 
-    from . import synth
+    from . import autotune, synth
     from .index import Context, Index, Transform, ivf_assign
 
     ap = argparse.ArgumentParser(description="continuous-batching serving loop over two resident indexes")
@@ -326,7 +329,7 @@ def main(argv=None):
         print(*a, file=sys.stderr, flush=True)
 
     ctx = Context(0)
-    indexes, pools = {}, {}
+    indexes, pools, params = {}, {}, {}
     for name, wname in (("c3", "ivf_zipf_batched"), ("c4", "ivf_embed_bf16")):
         w0 = synth.WORKLOADS[wname]
         w = synth.scaled(w0, n=int(w0.n * args.scale), nq=4096,
@@ -341,11 +344,21 @@ def main(argv=None):
         tf = Transform.fit(data["x"][rows] - c_np[a_np[rows]], fit_sample=0, seed=w.cfg_id)
         indexes[name] = Index.build(ctx, tf, xd, cent, assign, w.level_cuts())
         pools[name] = data["q"]
+        # the tuner's choice for the workload this index is shaped like (an
+        # entry for either storage type; the index here is FP32)
+        npv = w0.nprobe_range[1] if w0.nprobe_range else w0.nprobe
+        for store in ("f32", "bf16"):
+            p, _ = autotune.lookup(autotune.signature("gfx950", w.d, store, w.n, npv, w0.k))
+            if p is not None:
+                p.use_bf16 = 0
+                params[name] = p
+                break
         del xd
         torch.cuda.synchronize()
         log(f"[serve] index {name}: n={w.n} d={w.d} nlist={w.nlist} built in {time.time() - t:.1f}s")
 
-    ex = GpuExecutor(indexes, args.workers)
+    log(f"[serve] search params {params}")
+    ex = GpuExecutor(indexes, args.workers, params=params)
     # warm every context on both indexes (first-use allocations)
     warm = poisson_requests(pools, 200.0, 0.05, args.seed + 1000, sizes=(1, 64))
     srv = Server(Scheduler(ex.cost, int(args.budget_gib * 2 ** 30), args.max_batch), ex, n_workers=args.workers)
