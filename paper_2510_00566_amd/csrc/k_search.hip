@@ -251,21 +251,31 @@ struct QueryView {
 };
 
 // ================================================================ seeding
+__host__ __device__ inline size_t seed_key_bytes(int pool) { return ((size_t)8 * next_pow2(pool) + 15) / 16 * 16; }
+__host__ __device__ inline size_t seed_lds_bytes(int pool, int d_pad)
+{
+    return seed_key_bytes(pool) + (size_t)(d_pad >> 2) * (16 + 8);
+}
 // One workgroup per query: rank the first `pool` candidates of the query's
 // nearest list by their level-1 lower bound, compute the full distance of the
 // `cnt` most promising ones and start d_k from their k-th best (Algorithm 1
 // seeds its heap with exact distances before the first batch).
-__global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, QueryView qv,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_seed(SearchConsts c, IndexView ix, QueryView qv,
                                              const float *__restrict__ S_, const float *__restrict__ cn2,
                                              int d, int nlist, const int32_t *__restrict__ nprobe_dev,
                                              int nprobe_all, int np_max, float c_co,
                                              const int64_t *__restrict__ list_len, int pool, int cnt,
                                              float *__restrict__ thr)
 {
-    __shared__ uint64_t K[1024];
+    // dynamic LDS (seed_lds_bytes): keys [next_pow2(pool)], the rotated
+    // query [d_pad / 4] float4, chunk offsets and widths [d_pad / 4] each;
+    // sized to the workload so that the coarse step's waves fit beside it
+    extern __shared__ __align__(16) char seed_sm[];
+    uint64_t *K = reinterpret_cast<uint64_t *>(seed_sm);
+    float4 *qs_l = reinterpret_cast<float4 *>(seed_sm + seed_key_bytes(pool));
+    int *chunk_off = reinterpret_cast<int *>(qs_l + (c.g.d_pad >> 2));
+    int *chunk_w = chunk_off + (c.g.d_pad >> 2);
     __shared__ float Ds[256];
-    __shared__ float4 q1[16];
-    __shared__ int chunk_off[1024], chunk_w[1024];
     __shared__ float red_f[NT / 64];
     __shared__ int red_i[NT / 64];
     const int64_t q = blockIdx.x;
@@ -282,23 +292,42 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
         if (p > np_max) p = np_max;
         // ||q||^2 in the coarse step's FP32 order (per lane, columns in
         // increasing order, then a butterfly)
+        // (eight loads per lane in flight together, clamped so that no
+        // branch surrounds them; the summation order is unchanged)
         float qq = 0.f;
-        for (int j = lane; j < d; j += 64) {
-            const float v = qv.qraw[q * d + j];
-            qq = __builtin_fmaf(v, v, qq);
+        for (int j0 = 0; j0 < d; j0 += 512) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = qv.qraw[q * d + min(j0 + u * 64 + lane, d - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j0 + u * 64 + lane < d) qq = __builtin_fmaf(v[u], v[u], qq);
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o, 64);
         const float *Sq = S_ + q * nlist;
         float bu = INFINITY;
         int bl = 0x7fffffff;
-        for (int l = threadIdx.x; l < nlist; l += NT) {
-            const float a = qq + cn2[l] - 2.f * Sq[l];
-            const float del = c_co * (qq + cn2[l]);
-            const float up = fmaxf(a + del, 0.f) * (1.0f + 1.2e-7f);
-            if (up < bu) {
-                bu = up;
-                bl = l;
+        for (int l0 = 0; l0 < nlist; l0 += 8 * NT) {
+            float cv[8], sv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int lc = min(l0 + u * NT + (int)threadIdx.x, nlist - 1);
+                cv[u] = cn2[lc];
+                sv[u] = Sq[lc];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int l = l0 + u * NT + (int)threadIdx.x;
+                if (l < nlist) {
+                    const float a = qq + cv[u] - 2.f * sv[u];
+                    const float del = c_co * (qq + cv[u]);
+                    const float up = fmaxf(a + del, 0.f) * (1.0f + 1.2e-7f);
+                    if (up < bu) {
+                        bu = up;
+                        bl = l;
+                    }
+                }
             }
         }
 #pragma unroll
@@ -323,11 +352,22 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
                 bl = red_i[w];
             }
         int before = 0;
-        for (int l = threadIdx.x; l < nlist; l += NT) {
-            const float a = qq + cn2[l] - 2.f * Sq[l];
-            const float del = c_co * (qq + cn2[l]);
-            const float lo = fmaxf(a - del, 0.f) * (1.0f - 1.2e-7f);
-            before += (l != bl && lo <= bu) ? 1 : 0;
+        for (int l0 = 0; l0 < nlist; l0 += 8 * NT) {
+            float cv[8], sv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int lc = min(l0 + u * NT + (int)threadIdx.x, nlist - 1);
+                cv[u] = cn2[lc];
+                sv[u] = Sq[lc];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int l = l0 + u * NT + (int)threadIdx.x;
+                const float a = qq + cv[u] - 2.f * sv[u];
+                const float del = c_co * (qq + cv[u]);
+                const float lo = fmaxf(a - del, 0.f) * (1.0f - 1.2e-7f);
+                before += (l < nlist && l != bl && lo <= bu) ? 1 : 0;
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
@@ -349,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
     const float a1 = g.L > 1 ? qv.qtail[q * g.L + 1] : 0.f;
     const int w0 = g.wp[0], w04 = w0 >> 2;
     const int nch = g.d_pad >> 2;
-    if (threadIdx.x < w04) q1[threadIdx.x] = *reinterpret_cast<const float4 *>(qy + threadIdx.x * 4);
+    for (int ch = threadIdx.x; ch < nch; ch += NT) qs_l[ch] = *reinterpret_cast<const float4 *>(qy + ch * 4);
     for (int ch = threadIdx.x; ch < nch; ch += NT) {
         int lv = 0;
         while (4 * ch >= g.mp[lv + 1]) ++lv;
@@ -362,45 +402,46 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
         }
     }
     __syncthreads();
-    // level-1 lower bound of every pool candidate
+    // level-1 lower bound of every pool candidate (the level-1 slice is at
+    // most 16 chunks, all loads in flight together; clamped addresses, so no
+    // branch surrounds them)
     const int PP = next_pow2(P);
     for (int p = threadIdx.x; p < PP; p += NT) {
-        if (p < P) {
-            const int64_t gb = b0 + p / g.B;
-            const int s = p % g.B;
-            const float *x = ix.levels + gb * (int64_t)g.B * g.d_pad + (int64_t)s * 4;
-            const float b1 = g.L > 1 ? ix.tails[gb * (int64_t)g.B * g.L + g.B + s] : 0.f;
-            float sh = 0.f;
-            // the level-1 slice in groups of eight chunks, each group's loads
-            // in flight together (clamped, so no branch around them)
-            for (int c0 = 0; c0 < w04; c0 += 8) {
-                float4 xs[8];
+        // (the query chunks are read from LDS in each iteration: kept in
+        // registers across iterations they would push the kernel past the
+        // register budget of four workgroups per compute unit)
+        asm volatile("" ::: "memory");
+        const int pc = min(p, P - 1);
+        const int64_t gb = b0 + pc / g.B;
+        const int s = pc % g.B;
+        const float *x = ix.levels + gb * (int64_t)g.B * g.d_pad + (int64_t)s * 4;
+        const float b1 = g.L > 1 ? ix.tails[gb * (int64_t)g.B * g.L + g.B + s] : 0.f;
+        float4 xs[16];
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    xs[j] = *reinterpret_cast<const float4 *>(x + (int64_t)min(c0 + j, w04 - 1) * 4 * g.B);
+        for (int j = 0; j < 16; ++j)
+            xs[j] = *reinterpret_cast<const float4 *>(x + (int64_t)min(j, w04 - 1) * 4 * g.B);
+        float sh = 0.f;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    if (c0 + j < w04) {
-                        const float4 q4 = q1[c0 + j];
-                        float t0 = q4.x - xs[j].x, t1 = q4.y - xs[j].y, t2 = q4.z - xs[j].z, t3 = q4.w - xs[j].w;
-                        sh = __builtin_fmaf(t0, t0, sh);
-                        sh = __builtin_fmaf(t1, t1, sh);
-                        sh = __builtin_fmaf(t2, t2, sh);
-                        sh = __builtin_fmaf(t3, t3, sh);
-                    }
-                }
+        for (int j = 0; j < 16; ++j) {
+            if (j < w04) {
+                const float4 q4 = qs_l[j];
+                float t0 = q4.x - xs[j].x, t1 = q4.y - xs[j].y, t2 = q4.z - xs[j].z, t3 = q4.w - xs[j].w;
+                sh = __builtin_fmaf(t0, t0, sh);
+                sh = __builtin_fmaf(t1, t1, sh);
+                sh = __builtin_fmaf(t2, t2, sh);
+                sh = __builtin_fmaf(t3, t3, sh);
             }
-            const float tt = a1 - b1;
-            K[p] = make_key(sh + tt * tt, p);
-        } else {
-            K[p] = KEY_MAX;
         }
+        const float tt = a1 - b1;
+        K[p] = p < P ? make_key(sh + tt * tt, p) : KEY_MAX;
     }
     __syncthreads();
     block_bitonic_sort(K, PP);
-    // full distance of the S most promising candidates: 16 lanes per candidate
-    const int team = threadIdx.x >> 4, tl = threadIdx.x & 15;
-    for (int base = 0; base < S; base += NT / 16) {
+    // full distance of the S most promising candidates: 8 lanes per
+    // candidate, 32 candidates per round, each lane's chunks in groups of
+    // sixteen loads in flight together (clamped to a valid chunk)
+    const int team = threadIdx.x >> 3, tl = threadIdx.x & 7;
+    for (int base = 0; base < S; base += NT / 8) {
         const int si = base + team;
         float part = 0.f;
         if (si < S) {
@@ -408,21 +449,19 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
             const int64_t gb = b0 + p / g.B;
             const int s = p % g.B;
             const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
-            // groups of eight chunks per lane, each group's loads in flight
-            // together (clamped to a valid chunk, so no branch around them)
-            for (int ch0 = tl; ch0 < nch; ch0 += 16 * 8) {
-                float4 xs[8], qs[8];
+            for (int ch0 = tl; ch0 < nch; ch0 += 8 * 16) {
+                float4 xs[16];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int ch = min(ch0 + 16 * j, nch - 1);
+                for (int j = 0; j < 16; ++j) {
+                    const int ch = min(ch0 + 8 * j, nch - 1);
                     xs[j] = *reinterpret_cast<const float4 *>(blk + chunk_off[ch] + (int64_t)s * chunk_w[ch]);
-                    qs[j] = *reinterpret_cast<const float4 *>(qy + 4 * ch);
                 }
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    if (ch0 + 16 * j < nch) {
-                        float t0 = qs[j].x - xs[j].x, t1 = qs[j].y - xs[j].y, t2 = qs[j].z - xs[j].z,
-                              t3 = qs[j].w - xs[j].w;
+                for (int j = 0; j < 16; ++j) {
+                    if (ch0 + 8 * j < nch) {
+                        const float4 q4 = qs_l[ch0 + 8 * j];
+                        float t0 = q4.x - xs[j].x, t1 = q4.y - xs[j].y, t2 = q4.z - xs[j].z,
+                              t3 = q4.w - xs[j].w;
                         part = __builtin_fmaf(t0, t0, part);
                         part = __builtin_fmaf(t1, t1, part);
                         part = __builtin_fmaf(t2, t2, part);
@@ -432,7 +471,7 @@ __global__ __launch_bounds__(NT) void k_seed(SearchConsts c, IndexView ix, Query
             }
         }
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        for (int o = 4; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
         if (si < S && tl == 0) Ds[si] = part;
     }
     __syncthreads();
@@ -2188,7 +2227,8 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         // every d_k comes from committed candidates.
         if (seed_on) {
             PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork, 0));
-            hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), 0, sa, c, iv, qv, Sco,
+            hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), seed_lds_bytes(seed_pool, c.g.d_pad), sa, c, iv,
+                               qv, Sco,
                                ix->cent.as<float>() + (size_t)nlist * d, d, nlist, nprobe_dev, nprobe_all, np_max,
                                c_co, ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
             PANO_HIP(hipEventRecord(ctx->ev_join, sa));
