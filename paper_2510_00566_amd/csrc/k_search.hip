@@ -1718,14 +1718,14 @@ __device__ uint32_t block_kth_dist_bits(const uint64_t *__restrict__ keys, int n
 // computed distance, rescore every entry of the boundary band with the
 // canonical recipe and emit the first k by (D, id).  A buffer longer than the
 // LDS sort holds is first cut to the entries that can reach the band: the k-th
-// smallest distance is found by radix select in global memory.
-__global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__restrict__ buf,
-                                              const int32_t *__restrict__ buf_cnt,
-                                              int32_t *__restrict__ flags, const float *__restrict__ qE,
-                                              const float *__restrict__ qA,
-                                              const float *__restrict__ qraw, const float *__restrict__ raw,
-                                              int d, int64_t *__restrict__ out_ids, float *__restrict__ out_d,
-                                              unsigned long long *stats)
+// smallest distance is found by radix select in global memory.  Every return
+// is taken by the whole workgroup, and only thread 0 changes flags[q].
+__device__ __forceinline__ void merge_query(const SearchConsts &c, const uint64_t *__restrict__ buf,
+                                            const int32_t *__restrict__ buf_cnt, int32_t *__restrict__ flags,
+                                            const float *__restrict__ qE, const float *__restrict__ qA,
+                                            const float *__restrict__ qraw, const float *__restrict__ raw, int d,
+                                            int64_t *__restrict__ out_ids, float *__restrict__ out_d,
+                                            unsigned long long *stats)
 {
     // dynamic LDS: [MERGE_LDS_KEYS keys][d floats of the raw query]
     extern __shared__ uint64_t K[];
@@ -1808,6 +1808,26 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
     if (stats && threadIdx.x == 0) {
         atomicAdd(&stats[ST_COMMIT], (unsigned long long)n_all);
         atomicAdd(&stats[3], (unsigned long long)nb);
+    }
+}
+
+// The merge kernel: one workgroup per query.  When hflags (pinned host memory
+// of nq + 1 words) is given, each query's final flag word goes to hflags[q]
+// and the non-finite-query word to hflags[nq], so the host reads both after
+// the stream completes without copies of its own.
+__global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__restrict__ buf,
+                                              const int32_t *__restrict__ buf_cnt,
+                                              int32_t *__restrict__ flags, const float *__restrict__ qE,
+                                              const float *__restrict__ qA,
+                                              const float *__restrict__ qraw, const float *__restrict__ raw,
+                                              int d, int64_t *__restrict__ out_ids, float *__restrict__ out_d,
+                                              unsigned long long *stats, int32_t *hflags,
+                                              const int32_t *__restrict__ qbad)
+{
+    merge_query(c, buf, buf_cnt, flags, qE, qA, qraw, raw, d, out_ids, out_d, stats);
+    if (hflags != nullptr && threadIdx.x == 0) {
+        hflags[blockIdx.x] = flags[blockIdx.x];
+        if (blockIdx.x == 0) hflags[gridDim.x] = *qbad;
     }
 }
 
@@ -2269,10 +2289,8 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         }
         if (events_on) PANO_HIP(hipEventRecord(ctx->ev[2], st));
         hipLaunchKernelGGL(k_merge, dim3((unsigned)nq), dim3(NT), merge_shm, st, c, buf, buf_cnt, qflags, qE, qA, q,
-                           ix->raw.as<float>(), d, ids, dists, stats_on ? stats : nullptr);
+                           ix->raw.as<float>(), d, ids, dists, stats_on ? stats : nullptr, h_flags, qbad);
         if (events_on) PANO_HIP(hipEventRecord(ctx->ev[3], st));
-        PANO_HIP(hipMemcpyAsync(h_flags, qflags, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
-        PANO_HIP(hipMemcpyAsync(h_flags + nq, qbad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         PANO_HIP(hipGetLastError());
     };
 
