@@ -260,7 +260,8 @@ struct QueryConstsOut {
     Margins mg;
     float *qE = nullptr;
     float *qA = nullptr;
-    int *bad = nullptr;
+    int32_t *badq = nullptr;  // per row: 1 if the row has a non-finite value, else 0
+    FillList clear{};         // buffers the kernel fills before its own work
 };
 // Per row: tail norms sqrt(sum_{j >= mp_l} y_j^2) for l = 0..L-1 (FP64 sums),
 // and ||fl(x - mu)|| in FP64 (vnorm); with qc, the query constants too.

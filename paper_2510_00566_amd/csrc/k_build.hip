@@ -222,6 +222,15 @@ __global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, 
                                                    float *__restrict__ tails, double *__restrict__ vnorm,
                                                    QueryConstsOut qc)
 {
+    // buffers of the caller that must hold a value before its next kernels
+    // (none of them is read here)
+    for (int sgm = 0; sgm < qc.clear.m; ++sgm) {
+        uint32_t *p = reinterpret_cast<uint32_t *>(qc.clear.p[sgm]);
+        const uint32_t v = qc.clear.v[sgm];
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qc.clear.n[sgm];
+             i += (int64_t)gridDim.x * blockDim.x)
+            p[i] = v;
+    }
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= n) return;
@@ -289,7 +298,7 @@ __global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, 
             // the query's error bound E_q = kappa ||fl(q - mu)|| + e_max and
             // absolute margin A_q = c_abs (a_0^2 + b0max2), each rounded up
             // by a relative 1e-6 to cover the FP32 rounding
-            if (!isfinite(vn)) atomicOr(qc.bad, 1);
+            if (qc.badq) qc.badq[r] = isfinite(vn) ? 0 : 1;
             qc.qE[r] = (float)((double)qc.mg.kappa * vn * (1.0 + 1e-6)) + qc.mg.e_max;
             const double a0 = (double)tail0;
             qc.qA[r] = (float)((double)qc.mg.c_abs * (a0 * a0 * (1.0 + 1e-6) + (double)qc.mg.b0max2) * (1.0 + 1e-6));

@@ -1812,9 +1812,9 @@ __device__ __forceinline__ void merge_query(const SearchConsts &c, const uint64_
 }
 
 // The merge kernel: one workgroup per query.  When hflags (pinned host memory
-// of nq + 1 words) is given, each query's final flag word goes to hflags[q]
-// and the non-finite-query word to hflags[nq], so the host reads both after
-// the stream completes without copies of its own.
+// of nq words) is given, each query's final flag word, with FLAG_NONFINITE
+// set for a query that has a non-finite value, goes to hflags[q], so the
+// host reads them after the stream completes without copies of its own.
 __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__restrict__ buf,
                                               const int32_t *__restrict__ buf_cnt,
                                               int32_t *__restrict__ flags, const float *__restrict__ qE,
@@ -1825,10 +1825,8 @@ __global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__
                                               const int32_t *__restrict__ qbad)
 {
     merge_query(c, buf, buf_cnt, flags, qE, qA, qraw, raw, d, out_ids, out_d, stats);
-    if (hflags != nullptr && threadIdx.x == 0) {
-        hflags[blockIdx.x] = flags[blockIdx.x];
-        if (blockIdx.x == 0) hflags[gridDim.x] = *qbad;
-    }
+    if (hflags != nullptr && threadIdx.x == 0)
+        hflags[blockIdx.x] = flags[blockIdx.x] | (qbad[blockIdx.x] ? FLAG_NONFINITE : 0);
 }
 
 // ================================================================ fallback
@@ -2059,8 +2057,8 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     need[2] = align_up(sizeof(int32_t) * nq * np_max) * 2 + align_up(sizeof(int32_t) * nq) +
               2 * align_up(sizeof(int32_t) * nlist) + align_up(sizeof(int32_t) * 8) +
               align_up(sizeof(int64_t) * (nlist + 1)) + align_up(sizeof(int64_t) * (8 * c.ceil8 + 1));
-    need[3] = 3 * align_up(sizeof(float) * nq) + align_up(sizeof(uint64_t) * nq * c.capq) +
-              align_up(sizeof(unsigned long long) * 128) + align_up(sizeof(int));
+    need[3] = 4 * align_up(sizeof(float) * nq) + align_up(sizeof(uint64_t) * nq * c.capq) +
+              align_up(sizeof(unsigned long long) * 128);
     pl.grid_seg = 0;
     pl.seg_cap = 0;
     pl.items_max = 0;
@@ -2144,7 +2142,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     float *qtail = c0.take<float>(nq * L);
     float *qE = c0.take<float>(nq);
     float *qA = c0.take<float>(nq);
-    int *qbad = c3.take<int>(1);
+    int32_t *qbad = c3.take<int32_t>(nq);
     double *vnorm = c0.take<double>(nq);
     float *Sco = ctx->scratch[1].as<float>();
     int32_t *probes = c2.take<int32_t>(nq * np_max);
@@ -2174,7 +2172,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     if (nlist > 1)
         PANO_HIP(hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_shm));
     PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_shm));
-    ctx->pinned_ensure(sizeof(int32_t) * (nq + 1));
+    ctx->pinned_ensure(sizeof(int32_t) * nq);
     int32_t *h_flags = reinterpret_cast<int32_t *>(ctx->pinned);
     IndexView iv{ix->levels.as<float>(), ix->has_bf16 ? ix->levels_bf16.as<uint16_t>() : nullptr, ix->tails.as<float>(), ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
                  ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
@@ -2191,12 +2189,13 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     }
 
     // Every device step of one search, in order, on stream st.  No memset
-    // nodes: buffers are cleared by a fill kernel so the sequence can be
-    // captured into a graph.
+    // nodes: buffers are cleared by kernels so the sequence can be captured
+    // into a graph.  The row-norms kernel clears the counters, thresholds and
+    // flags (its successors are the first to use them); the transformed
+    // queries are cleared beforehand only when the levels have padding
+    // columns, which the transform does not write.
     auto enqueue = [&](hipStream_t st, bool stats_on, bool events_on) {
         FillList fl{};
-        fl.add(qbad, 1, 0u);
-        fl.add(qy, nq * (int64_t)ix->d_pad, 0u);
         fl.add(list_cnt, nlist, 0u);
         fl.add(list_fill, nlist, 0u);
         fl.add(heads, 8, 0u);
@@ -2204,7 +2203,11 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         fl.add(buf_cnt, nq, 0u);
         fl.add(qflags, nq, 0u);
         if (stats_on) fl.add(stats, 256, 0u);
-        hipLaunchKernelGGL(k_fill_multi, dim3(256), dim3(256), 0, st, fl);
+        if (ix->d_pad != ix->d) {
+            FillList fq{};
+            fq.add(qy, nq * (int64_t)ix->d_pad, 0u);
+            hipLaunchKernelGGL(k_fill_multi, dim3(256), dim3(256), 0, st, fq);
+        }
         // query transform and query x centroid products in one launch (their
         // tiles run side by side), then the transformed queries' tails and
         // error bounds
@@ -2223,7 +2226,8 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             qc.mg = mq;
             qc.qE = qE;
             qc.qA = qA;
-            qc.bad = qbad;
+            qc.badq = qbad;
+            qc.clear = fl;
             launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, st, &qc);
         }
         hipStream_t sa = ctx->aux;
@@ -2328,7 +2332,8 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     }
     PANO_HIP(hipStreamSynchronize(ws));
     std::vector<int32_t> hflags(h_flags, h_flags + nq);
-    PANO_REQUIRE(h_flags[nq] == 0, "a query has a non-finite value");
+    for (int64_t qi = 0; qi < nq; ++qi)
+        PANO_REQUIRE(!(hflags[qi] & FLAG_NONFINITE), "a query has a non-finite value");
     s = ws;
     // ---- exact fallback for queries whose bounded buffers overflowed
 

@@ -13,6 +13,7 @@ constexpr int SB_MAX = 512;     // per-wave sort buffer (entries)
 constexpr int WALK_CHUNKS = 8;  // four-float chunks of a level the per-pair walk requests at once
 constexpr uint64_t KEY_MAX = ~0ull;
 constexpr int FLAG_OVERFLOW = 1;
+constexpr int FLAG_NONFINITE = 2;  // host flag word only: the query has a non-finite value
 
 // Wave-uniform reads of query slices go through the constant address space so
 // that they become scalar loads into SGPRs (a free broadcast to all lanes).
