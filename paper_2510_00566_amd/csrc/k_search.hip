@@ -2298,14 +2298,22 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         PANO_HIP(hipGetLastError());
     };
 
-    // The search runs on the context's own stream, ordered after the caller's.
+    // A graph is captured on the context's own stream (the caller's may be
+    // the null stream, which cannot be captured) and launched on the
+    // caller's stream, so it is ordered after the caller's work without an
+    // event.  Eager searches run on the context's stream, ordered after the
+    // caller's by an event.
     hipStream_t ws = ctx->work_stream();
-    PANO_HIP(hipEventRecord(ctx->ev_in, s));
-    PANO_HIP(hipStreamWaitEvent(ws, ctx->ev_in, 0));
+    hipStream_t rs = ws;  // the stream the search ran on
+    const bool use_graph = !want_stats && !want_timing && !(flags & PANO_SEARCH_EAGER);
+    if (!use_graph) {
+        PANO_HIP(hipEventRecord(ctx->ev_in, s));
+        PANO_HIP(hipStreamWaitEvent(ws, ctx->ev_in, 0));
+    }
     if (want_stats || want_timing) {
         PANO_HIP(hipEventRecord(ctx->ev[0], ws));
         enqueue(ws, want_stats, true);
-    } else if (!(flags & PANO_SEARCH_EAGER)) {
+    } else if (use_graph) {
         GraphKey key{ix->serial, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
                      c.dense_min, c.bf16, split ? 1 : 0, c.walk_lanes, c.walk2, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
                      split ? ctx->scratch[5].p : nullptr, split ? ctx->scratch[6].p : nullptr, ctx->pinned};
@@ -2326,11 +2334,12 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             PANO_HIP(ie);
             ctx->graph_key = key;
         }
-        PANO_HIP(hipGraphLaunch(ctx->graph_exec, ws));
+        PANO_HIP(hipGraphLaunch(ctx->graph_exec, s));
+        rs = s;
     } else {
         enqueue(ws, false, false);
     }
-    PANO_HIP(hipStreamSynchronize(ws));
+    PANO_HIP(hipStreamSynchronize(rs));
     std::vector<int32_t> hflags(h_flags, h_flags + nq);
     for (int64_t qi = 0; qi < nq; ++qi)
         PANO_REQUIRE(!(hflags[qi] & FLAG_NONFINITE), "a query has a non-finite value");

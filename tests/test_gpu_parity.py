@@ -162,3 +162,27 @@ def test_graph_not_reused_across_indexes(torch_cuda):
             gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
         case["idx"].free()
         del case
+
+
+@gpu
+def test_search_ordered_after_callers_stream(torch_cuda):
+    """A search on a caller's stream sees the work queued before it on that
+    stream: the queries are written by copies enqueued on a side stream just
+    before each search (no host synchronisation in between), and every answer
+    must be the oracle's for the queries just written."""
+    from tests import gpu_cases as gc
+    w = _ivf_small()
+    _log("case ivf stream ordering n=20000 d=960 nlist=32 nprobe=4")
+    case = gc.build_case(w)
+    q = case["data"]["q"]
+    qs = [np.ascontiguousarray(q), np.ascontiguousarray(q[::-1])]
+    refs = [gc.oracle_answer(case, x, w.nprobe, w.k) for x in qs]
+    host = [torch_cuda.from_numpy(x).pin_memory() for x in qs]
+    qd = torch_cuda.empty(q.shape, dtype=torch_cuda.float32, device="cuda")
+    st = torch_cuda.cuda.Stream()
+    for rnd in range(4):
+        j = rnd % 2
+        with torch_cuda.cuda.stream(st):
+            qd.copy_(host[j], non_blocking=True)
+            ids, dd = case["idx"].search(qd, w.k, nprobe=w.nprobe, stream=st)
+        gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), *refs[j])
