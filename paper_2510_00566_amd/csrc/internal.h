@@ -132,9 +132,9 @@ struct pano_ctx {
     int num_cu = 256;
     pano::DevMem scratch[12];
     // the context's own stream (default priority), events and graph cache
-    hipStream_t stream = nullptr, aux = nullptr;
+    hipStream_t stream = nullptr, aux = nullptr, aux2 = nullptr;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
     hipEvent_t ev_in = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     pano::GraphKey graph_key{};
@@ -150,9 +150,11 @@ struct pano_ctx {
                 if (hipEventCreate(&e) != hipSuccess) throw pano::Error{PANO_EDEVICE, "hipEventCreate failed"};
             if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess)
+                hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&ev_join2, hipEventDisableTiming) != hipSuccess)
                 throw pano::Error{PANO_EDEVICE, "hipEventCreate failed"};
-            if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess)
+            if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess ||
+                hipStreamCreateWithFlags(&aux2, hipStreamNonBlocking) != hipSuccess)
                 throw pano::Error{PANO_EDEVICE, "hipStreamCreate failed"};
         }
         return stream;
@@ -183,7 +185,9 @@ struct pano_ctx {
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
+        if (ev_join2) (void)hipEventDestroy(ev_join2);
         if (aux) (void)hipStreamDestroy(aux);
+        if (aux2) (void)hipStreamDestroy(aux2);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -243,7 +247,8 @@ GemmJob transform_job(const float *X, int64_t n, int d, const float *T, const fl
                       float *Y, int ld_y);
 GemmJob product_job(const float *A, int64_t n, int d, const float *Bm, int nb, float *S);
 // Both jobs (j1 may be null) in one launch: their tiles run side by side.
-void launch_gemm_jobs(const GemmJob &j0, const GemmJob *j1, hipStream_t s);
+// clear: buffers the kernel fills in a prologue (none of them is read by it)
+void launch_gemm_jobs(const GemmJob &j0, const GemmJob *j1, hipStream_t s, const FillList *clear = nullptr);
 
 // Y[r][padcol[j]] = sum_j T[i][j] * (X[r][j] - mu[j]) with chunked FP32
 // accumulation; Y has ld_y columns (padding columns are left untouched).
@@ -261,7 +266,6 @@ struct QueryConstsOut {
     float *qE = nullptr;
     float *qA = nullptr;
     int32_t *badq = nullptr;  // per row: 1 if the row has a non-finite value, else 0
-    FillList clear{};         // buffers the kernel fills before its own work
 };
 // Per row: tail norms sqrt(sum_{j >= mp_l} y_j^2) for l = 0..L-1 (FP64 sums),
 // and ||fl(x - mu)|| in FP64 (vnorm); with qc, the query constants too.

@@ -23,8 +23,16 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 // One launch may carry two independent products (jobs): the workgroups with
 // blockIdx.y < y0 take job j0, the others job j1 (column tile blockIdx.y - y0).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tile_nt(GemmJob j0, GemmJob j1,
-                                                                                           int y0)
+                                                                                           int y0, FillList clear)
 {
+    for (int sgm = 0; sgm < clear.m; ++sgm) {
+        uint32_t *p = reinterpret_cast<uint32_t *>(clear.p[sgm]);
+        const uint32_t v = clear.v[sgm];
+        const int64_t nthr = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+        for (int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; i < clear.n[sgm];
+             i += nthr)
+            p[i] = v;
+    }
     const bool first = (int)blockIdx.y < y0;
     const float *__restrict__ A = first ? j0.A : j1.A;
     const int64_t n = first ? j0.n : j1.n;
@@ -179,14 +187,15 @@ GemmJob product_job(const float *A, int64_t n, int d, const float *Bm, int nb, f
     return GemmJob{A, n, d, Bm, nb, nullptr, nullptr, S, nb};
 }
 
-void launch_gemm_jobs(const GemmJob &j0, const GemmJob *j1, hipStream_t s)
+void launch_gemm_jobs(const GemmJob &j0, const GemmJob *j1, hipStream_t s, const FillList *clear)
 {
     const int64_t n = j1 ? std::max(j0.n, j1->n) : j0.n;
     if (n == 0) return;
     const int y0 = (j0.nb + TN - 1) / TN;
     const int y1 = j1 ? (j1->nb + TN - 1) / TN : 0;
     dim3 grid((unsigned)((n + TM - 1) / TM), (unsigned)(y0 + y1));
-    hipLaunchKernelGGL(k_tile_nt, grid, dim3(256), 0, s, j0, j1 ? *j1 : j0, y0);
+    FillList none{};
+    hipLaunchKernelGGL(k_tile_nt, grid, dim3(256), 0, s, j0, j1 ? *j1 : j0, y0, clear ? *clear : none);
     PANO_HIP(hipGetLastError());
 }
 
@@ -222,15 +231,6 @@ __global__ __launch_bounds__(256) void k_row_norms(const float *__restrict__ Y, 
                                                    float *__restrict__ tails, double *__restrict__ vnorm,
                                                    QueryConstsOut qc)
 {
-    // buffers of the caller that must hold a value before its next kernels
-    // (none of them is read here)
-    for (int sgm = 0; sgm < qc.clear.m; ++sgm) {
-        uint32_t *p = reinterpret_cast<uint32_t *>(qc.clear.p[sgm]);
-        const uint32_t v = qc.clear.v[sgm];
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qc.clear.n[sgm];
-             i += (int64_t)gridDim.x * blockDim.x)
-            p[i] = v;
-    }
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= n) return;

@@ -259,12 +259,18 @@ __host__ __device__ inline size_t seed_lds_bytes(int pool, int d_pad)
 // One workgroup per query: rank the first `pool` candidates of the query's
 // nearest list by their level-1 lower bound, compute the full distance of the
 // `cnt` most promising ones and start d_k from their k-th best (Algorithm 1
-// seeds its heap with exact distances before the first batch).
+// seeds its heap with exact distances before the first batch).  The kernel
+// needs only the transformed queries and the coarse products: the query's
+// norms and its constants E_q, A_q (the formulas of the row-norms kernel,
+// with FP64 sums in another order, far inside their 1e-6 rounding slack) are
+// computed here, so it runs beside the row norms and the coarse step.
+// qa_cabs, qa_b0max2: the A_q constants of the scan that uses the threshold.
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_seed(SearchConsts c, IndexView ix, QueryView qv,
                                              const float *__restrict__ S_, const float *__restrict__ cn2,
                                              int d, int nlist, const int32_t *__restrict__ nprobe_dev,
                                              int nprobe_all, int np_max, float c_co,
                                              const int64_t *__restrict__ list_len, int pool, int cnt,
+                                             const float *__restrict__ mu, float qa_cabs, float qa_b0max2,
                                              float *__restrict__ thr)
 {
     // dynamic LDS (seed_lds_bytes): keys [next_pow2(pool)], the rotated
@@ -386,10 +392,46 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     const LevelGeom &g = c.g;
     const int64_t b0 = ix.list_blk[l0];
     const float *qy = qv.qy + q * g.d_pad;
-    const float a1 = g.L > 1 ? qv.qtail[q * g.L + 1] : 0.f;
     const int w0 = g.wp[0], w04 = w0 >> 2;
     const int nch = g.d_pad >> 2;
-    for (int ch = threadIdx.x; ch < nch; ch += NT) qs_l[ch] = *reinterpret_cast<const float4 *>(qy + ch * 4);
+    // ||q'||^2 and the energy after level 1 from the rotated query, and
+    // ||fl(q - mu)||^2 from the raw one, in FP64 (per thread, then per wave,
+    // then over the four waves)
+    double e0 = 0.0, e1 = 0.0, ev = 0.0;
+    for (int ch = threadIdx.x; ch < nch; ch += NT) {
+        const float4 v = *reinterpret_cast<const float4 *>(qy + ch * 4);
+        qs_l[ch] = v;
+        const double s2 = (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+        e0 += s2;
+        if (4 * ch >= g.mp[1]) e1 += s2;  // never for a single level (mp[1] = d_pad)
+    }
+    for (int j0 = 0; j0 < d; j0 += 4 * NT) {
+        float xv[4], mv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = min(j0 + u * NT + (int)threadIdx.x, d - 1);  // clamped: no branch
+            xv[u] = qv.qraw[q * d + j];
+            mv[u] = mu[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (j0 + u * NT + (int)threadIdx.x < d) {
+                const double t = (double)(xv[u] - mv[u]);
+                ev += t * t;
+            }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        e0 += __shfl_xor(e0, o, 64);
+        e1 += __shfl_xor(e1, o, 64);
+        ev += __shfl_xor(ev, o, 64);
+    }
+    __shared__ double red_d[3][NT / 64];
+    if (lane == 0) {
+        red_d[0][wv] = e0;
+        red_d[1][wv] = e1;
+        red_d[2][wv] = ev;
+    }
     for (int ch = threadIdx.x; ch < nch; ch += NT) {
         int lv = 0;
         while (4 * ch >= g.mp[lv + 1]) ++lv;
@@ -402,6 +444,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         }
     }
     __syncthreads();
+    e0 = e1 = ev = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+        e0 += red_d[0][w];
+        e1 += red_d[1][w];
+        ev += red_d[2][w];
+    }
+    const float a0 = (float)sqrt(e0);  // the tail norm after level 0, rounded to FP32
+    const float a1 = (float)sqrt(e1);
+    const float qE_s = (float)((double)c.mg.kappa * sqrt(ev) * (1.0 + 1e-6)) + c.mg.e_max;
+    const float qA_s =
+        (float)((double)qa_cabs * ((double)a0 * (double)a0 * (1.0 + 1e-6) + (double)qa_b0max2) * (1.0 + 1e-6));
+    if (!isfinite(qE_s) || !isfinite(qA_s)) return;  // a non-finite query: no seed
     // level-1 lower bound of every pool candidate (the level-1 slice is at
     // most 16 chunks, all loads in flight together; clamped addresses, so no
     // branch surrounds them)
@@ -480,7 +534,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     __syncthreads();
     block_bitonic_sort(K, PS);
     if (threadIdx.x == 0) {
-        float t = prune_threshold(key_dist(K[c.k - 1]), qv.qE[q], qv.qA[q], c.mg);
+        float t = prune_threshold(key_dist(K[c.k - 1]), qE_s, qA_s, c.mg);
         atomic_min_nonneg(&thr[q], t);
     }
 }
@@ -833,9 +887,18 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
     // query rows for the matrix-core dot products: level-1 slices (pruned
     // scan) or one level at a time (brute force), [query][group of 4]
     __shared__ float4 qrow_s[GMAX][16];
+    // the queue-ordered item offsets (up to 1024 lists), copied once per
+    // workgroup so that pulling and decoding an item costs LDS reads, not a
+    // chain of dependent global loads; item numbers fit in 32 bits
+    __shared__ int32_t ioff_s[IOFF_LDS];
 
     const LevelGeom &g = c.g;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n_ioff = 8 * c.ceil8 + 1;
+    const bool ioff_in_lds = n_ioff <= IOFF_LDS;
+    if (ioff_in_lds)
+        for (int i = tid; i < n_ioff; i += NT) ioff_s[i] = (int32_t)wk.item_off[i];
+    auto ioff = [&](int i) -> int64_t { return ioff_in_lds ? (int64_t)ioff_s[i] : wk.item_off[i]; };
     const int r16 = lane & 15, kq = lane >> 4;
     // matrix-core operand of this lane's query row, from the staged slices
     auto q_lds = [&](int kg) -> float4 { return qrow_s[r16][kg]; };
@@ -861,12 +924,13 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
         }                                                              \
     } while (0)
 
+    __syncthreads();
     while (true) {
         // ---- pull the next item from this workgroup's XCD queue, then steal
         if (tid == 0) {
             int it = -1;
             while (tried < 8) {
-                const int64_t qb = wk.item_off[queue * c.ceil8], qe = wk.item_off[(queue + 1) * c.ceil8];
+                const int64_t qb = ioff(queue * c.ceil8), qe = ioff((queue + 1) * c.ceil8);
                 if (qe > qb) {
                     int v = atomicAdd(&wk.heads[queue], 1);
                     if (qb + v < qe) {
@@ -888,12 +952,12 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
         int lo = 0, hi = 8 * c.ceil8;
         while (hi - lo > 1) {
             int mid = (lo + hi) >> 1;
-            if (wk.item_off[mid] <= item) lo = mid;
+            if (ioff(mid) <= item) lo = mid;
             else hi = mid;
         }
         const int pos = lo;
         const int l = (pos % c.ceil8) * 8 + pos / c.ceil8;
-        const int local = (int)(item - wk.item_off[pos]);
+        const int local = (int)(item - ioff(pos));
         const int qcnt = wk.list_cnt[l];
         const int groups = (qcnt + c.G - 1) / c.G;
         const int gi = local % groups, ri = local / groups;
@@ -2188,12 +2252,21 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         wk.items_max = pl.items_max;
     }
 
-    // Every device step of one search, in order, on stream st.  No memset
-    // nodes: buffers are cleared by kernels so the sequence can be captured
-    // into a graph.  The row-norms kernel clears the counters, thresholds and
-    // flags (its successors are the first to use them); the transformed
-    // queries are cleared beforehand only when the levels have padding
-    // columns, which the transform does not write.
+    // Every device step of one search, on stream st (and, with seeding, two
+    // more branches).  No memset nodes: buffers are cleared by kernels so the
+    // sequence can be captured into a graph.  The products kernel clears the
+    // counters, thresholds and flags in a prologue (every later kernel may
+    // use them); the transformed queries are cleared beforehand only when the
+    // levels have padding columns, which the transform does not write.
+    //
+    // After the products the search forks three ways: the coarse probing and
+    // the work decomposition on st, the threshold seeding on the context's
+    // second stream and the row norms (tails, E_q, A_q, needed from the scan
+    // on) on its third; both side branches join st before the scan.  Seeding
+    // runs only for the exact bound: a seed's own relaxed bound (eps < 1) may
+    // exceed its distance, so the scan could prune the very candidates that
+    // set d_k and return fewer than k; without seeding, every d_k comes from
+    // committed candidates.
     auto enqueue = [&](hipStream_t st, bool stats_on, bool events_on) {
         FillList fl{};
         fl.add(list_cnt, nlist, 0u);
@@ -2209,30 +2282,34 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             hipLaunchKernelGGL(k_fill_multi, dim3(256), dim3(256), 0, st, fq);
         }
         // query transform and query x centroid products in one launch (their
-        // tiles run side by side), then the transformed queries' tails and
-        // error bounds
+        // tiles run side by side)
         {
             const GemmJob jt = transform_job(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(),
                                              ix->meta.as<int32_t>(), qy, ix->d_pad);
             if (nlist > 1) {
                 const GemmJob jc = product_job(q, nq, d, ix->cent.as<float>(), nlist, Sco);
-                launch_gemm_jobs(jt, &jc, st);
+                launch_gemm_jobs(jt, &jc, st, &fl);
             } else {
-                launch_gemm_jobs(jt, nullptr, st);
+                launch_gemm_jobs(jt, nullptr, st, &fl);
             }
         }
-        {
+        // the transformed queries' tails and error bounds
+        auto row_norms = [&](hipStream_t rs_) {
             QueryConstsOut qc;
             qc.mg = mq;
             qc.qE = qE;
             qc.qA = qA;
             qc.badq = qbad;
-            qc.clear = fl;
-            launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, st, &qc);
+            launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, rs_, &qc);
+        };
+        hipStream_t sa = ctx->aux, sb = ctx->aux2;
+        if (seed_on) {
+            PANO_HIP(hipEventRecord(ctx->ev_fork, st));
+        } else {
+            row_norms(st);
         }
-        hipStream_t sa = ctx->aux;
-        if (seed_on) PANO_HIP(hipEventRecord(ctx->ev_fork, st));
-        // coarse probing (and the number of queries per list)
+        // coarse probing (and the number of queries per list), launched first
+        // so that its waves are dispatched before the side branches'
         if (nlist > 1) {
             hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
                                ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq,
@@ -2241,21 +2318,16 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, np_max, probes,
                                npq, list_cnt);
         }
-        // threshold seeding (needs the transformed queries and the coarse
-        // products, not the probe sets) runs on the context's second stream
-        // beside the coarse probing and the work decomposition; it is
-        // launched after the coarse step so that step's waves are dispatched
-        // first.  Only for the exact bound: a seed's own relaxed bound
-        // (eps < 1) may exceed its distance, so the scan could prune the very
-        // candidates that set d_k and return fewer than k; without seeding,
-        // every d_k comes from committed candidates.
         if (seed_on) {
             PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork, 0));
             hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), seed_lds_bytes(seed_pool, c.g.d_pad), sa, c, iv,
-                               qv, Sco,
-                               ix->cent.as<float>() + (size_t)nlist * d, d, nlist, nprobe_dev, nprobe_all, np_max,
-                               c_co, ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt, thr);
+                               qv, Sco, ix->cent.as<float>() + (size_t)nlist * d, d, nlist, nprobe_dev, nprobe_all,
+                               np_max, c_co, ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt,
+                               ix->mu32.as<float>(), mq.c_abs, mq.b0max2, thr);
             PANO_HIP(hipEventRecord(ctx->ev_join, sa));
+            PANO_HIP(hipStreamWaitEvent(sb, ctx->ev_fork, 0));
+            row_norms(sb);
+            PANO_HIP(hipEventRecord(ctx->ev_join2, sb));
         }
         // work decomposition
         const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
@@ -2266,7 +2338,10 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         if (split)
             hipLaunchKernelGGL(k_wl_items, dim3((unsigned)(8 * c.ceil8)), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi,
                                list_cnt, ix->list_blk_d.as<int64_t>(), item_off, items, pl.items_max);
-        if (seed_on) PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+        if (seed_on) {
+            PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+            PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join2, 0));
+        }
         if (events_on) PANO_HIP(hipEventRecord(ctx->ev[1], st));
         WorkView w2 = wk;
         w2.stats = stats_on ? stats : nullptr;

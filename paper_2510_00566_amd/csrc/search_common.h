@@ -8,6 +8,7 @@ namespace pano {
 
 constexpr int NT = 256;         // threads per workgroup (4 wavefronts)
 constexpr int MERGE_LDS_KEYS = 2048;  // entries the merge sorts in LDS
+constexpr int IOFF_LDS = 1032;  // item offsets a scan workgroup keeps in LDS (lists up to 1024)
 constexpr int GMAX = 16;        // max queries per scan work item
 constexpr int SB_MAX = 512;     // per-wave sort buffer (entries)
 constexpr int WALK_CHUNKS = 8;  // four-float chunks of a level the per-pair walk requests at once
