@@ -2308,8 +2308,17 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         } else {
             row_norms(st);
         }
-        // coarse probing (and the number of queries per list), launched first
-        // so that its waves are dispatched before the side branches'
+        // the seeding, the longest branch, is launched first so that its waves
+        // are dispatched first
+        if (seed_on) {
+            PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork, 0));
+            hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), seed_lds_bytes(seed_pool, c.g.d_pad), sa, c, iv,
+                               qv, Sco, ix->cent.as<float>() + (size_t)nlist * d, d, nlist, nprobe_dev, nprobe_all,
+                               np_max, c_co, ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt,
+                               ix->mu32.as<float>(), mq.c_abs, mq.b0max2, thr);
+            PANO_HIP(hipEventRecord(ctx->ev_join, sa));
+        }
+        // coarse probing (and the number of queries per list)
         if (nlist > 1) {
             hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
                                ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq,
@@ -2319,12 +2328,6 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
                                npq, list_cnt);
         }
         if (seed_on) {
-            PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork, 0));
-            hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), seed_lds_bytes(seed_pool, c.g.d_pad), sa, c, iv,
-                               qv, Sco, ix->cent.as<float>() + (size_t)nlist * d, d, nlist, nprobe_dev, nprobe_all,
-                               np_max, c_co, ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt,
-                               ix->mu32.as<float>(), mq.c_abs, mq.b0max2, thr);
-            PANO_HIP(hipEventRecord(ctx->ev_join, sa));
             PANO_HIP(hipStreamWaitEvent(sb, ctx->ev_fork, 0));
             row_norms(sb);
             PANO_HIP(hipEventRecord(ctx->ev_join2, sb));
