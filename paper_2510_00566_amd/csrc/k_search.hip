@@ -1847,13 +1847,23 @@ __device__ __forceinline__ void merge_query(const SearchConsts &c, const uint64_
         return;
     }
     // canonical rescoring of the band (the band is a prefix of the sort):
-    // one row per wavefront at a time
+    // two rows per wavefront at a time (the last one alone)
     {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        for (int i = wv; i < nb; i += NT / 64) {
-            const int32_t id = key_id(K[i]);
-            const float dv = wave_canon_dist(qrow, raw + (int64_t)id * d, d, lane);
-            if (lane == 0) K[i] = make_key(dv, id);
+        for (int i = 2 * wv; i < nb; i += 2 * (NT / 64)) {
+            const int32_t id0 = key_id(K[i]);
+            if (i + 1 < nb) {
+                const int32_t id1 = key_id(K[i + 1]);
+                float d0, d1;
+                wave_canon_dist2(qrow, raw + (int64_t)id0 * d, raw + (int64_t)id1 * d, d, lane, d0, d1);
+                if (lane == 0) {
+                    K[i] = make_key(d0, id0);
+                    K[i + 1] = make_key(d1, id1);
+                }
+            } else {
+                const float dv = wave_canon_dist(qrow, raw + (int64_t)id0 * d, d, lane);
+                if (lane == 0) K[i] = make_key(dv, id0);
+            }
         }
     }
     const int PB = next_pow2(nb > 0 ? nb : 1);

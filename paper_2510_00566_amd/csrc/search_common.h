@@ -80,6 +80,29 @@ __device__ inline float canon_dist(const float *__restrict__ q, const float *__r
 // interval round to the same float, that float is the canonical value.
 // Otherwise (an interval straddling a float rounding boundary, or a
 // non-finite value) the sequential recipe itself is evaluated.
+// The certified rounding of a parallel FP64 sum s of the d squared
+// differences: any summation order of d non-negative terms lies within
+// gamma_53(d - 1) s of the exact sum, so the sequential sum lies within
+// del of s; when both ends of [s - del, s + del] round to the same float,
+// that float is the canonical value, otherwise the sequential recipe runs
+// (every lane computes it).
+__device__ inline float canon_finish(double s, const float *q, const float *__restrict__ x, int d)
+{
+#pragma clang fp contract(off)
+    const double gm = (double)d * 0x1p-53;
+    const double gam = gm / (1.0 - gm);
+    const double del = 2.0 * gam * s / (1.0 - gam) * 1.01 + 0x1p-1074;
+    const float lo = (float)(s - del), hi = (float)(s + del);
+    if (lo == hi) return lo;
+    double r = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double t = (double)q[j] - (double)x[j];
+        const double t2 = t * t;
+        r = r + t2;
+    }
+    return (float)r;
+}
+
 __device__ inline float wave_canon_dist(const float *q, const float *__restrict__ x, int d, int lane)
 {
 #pragma clang fp contract(off)
@@ -103,19 +126,45 @@ __device__ inline float wave_canon_dist(const float *q, const float *__restrict_
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s = s + __shfl_xor(s, o, 64);
-    const double gm = (double)d * 0x1p-53;
-    const double gam = gm / (1.0 - gm);
-    const double del = 2.0 * gam * s / (1.0 - gam) * 1.01 + 0x1p-1074;
-    const float lo = (float)(s - del), hi = (float)(s + del);
-    if (lo == hi) return lo;
-    // the sequential recipe (every lane computes it)
-    double r = 0.0;
-    for (int j = 0; j < d; ++j) {
-        const double t = (double)q[j] - (double)x[j];
-        const double t2 = t * t;
-        r = r + t2;
+    return canon_finish(s, q, x, d);
+}
+
+// Two rows at a time, for callers with several rows per wavefront: both
+// rows' loads in flight together, sixteen per lane (a row of up to 1024
+// values takes one round trip); each sum is certified by canon_finish.
+__device__ inline void wave_canon_dist2(const float *q, const float *__restrict__ x0, const float *__restrict__ x1,
+                                        int d, int lane, float &r0, float &r1)
+{
+#pragma clang fp contract(off)
+    double s0 = 0.0, s1 = 0.0;
+    for (int j0 = 0; j0 < d; j0 += 64 * 16) {
+        float a[16], b[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int j = min(j0 + u * 64 + lane, d - 1);  // clamped: no branch around the loads
+            a[u] = x0[j];
+            b[u] = x1[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int j = j0 + u * 64 + lane;
+            if (j < d) {
+                const double qd = (double)q[j];
+                const double t0 = qd - (double)a[u];
+                const double t1 = qd - (double)b[u];
+                const double p0 = t0 * t0, p1 = t1 * t1;
+                s0 = s0 + p0;
+                s1 = s1 + p1;
+            }
+        }
     }
-    return (float)r;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s0 = s0 + __shfl_xor(s0, o, 64);
+        s1 = s1 + __shfl_xor(s1, o, 64);
+    }
+    r0 = canon_finish(s0, q, x0, d);
+    r1 = canon_finish(s1, q, x1, d);
 }
 
 // Bounds for bfloat16 tiles.  With x~ the bfloat16 rounding of the stored
