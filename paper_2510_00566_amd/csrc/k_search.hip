@@ -24,6 +24,7 @@ __host__ __device__ inline size_t coarse_lds_per_wave(int nlist, int d)
     return (((size_t)next_pow2(nlist) * 8 + (size_t)nlist * 12 + (size_t)d * 4 + 1024 + 64) + 15) & ~(size_t)15;
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, const float *__restrict__ cn2, const float *__restrict__ q,
                                                const float *__restrict__ cent, int d, int nlist, int64_t nq,
                                                const int32_t *__restrict__ nprobe_dev, int nprobe_all,
@@ -92,8 +93,8 @@ __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, cons
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     // (the key buffer, not in use yet, holds the selects' candidates)
     float *cand = reinterpret_cast<float *>(keys);
-    const float Up = wave_select_nonneg(UP, nlist, p, hist, cand, lane);
-    const float Lp1 = p < nlist ? wave_select_nonneg(LO, nlist, p + 1, hist, cand, lane) : INFINITY;
+    const float Up = wave_select_nonneg<NMAX>(UP, nlist, p, hist, cand, lane);
+    const float Lp1 = p < nlist ? wave_select_nonneg<NMAX>(LO, nlist, p + 1, hist, cand, lane) : INFINITY;
     // certain lists go to the output; uncertain band members are collected
     int ncert = 0, nunc = 0;
     for (int b0 = 0; b0 < nlist; b0 += 64) {
@@ -2243,8 +2244,11 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     PANO_REQUIRE(nlist == 1 || coarse_shm <= 160 * 1024, "nlist too large for the coarse step");
     const size_t merge_shm = sizeof(uint64_t) * MERGE_LDS_KEYS + sizeof(float) * (size_t)d;
     const size_t scan_shm = sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
+    // the coarse kernel instance compiled for at most this many lists
+    auto coarse_kernel = nlist <= 1024 ? k_coarse<1024> : (nlist <= 4096 ? k_coarse<4096> : k_coarse<(1 << 30)>);
     if (nlist > 1)
-        PANO_HIP(hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_shm));
+        PANO_HIP(hipFuncSetAttribute((const void *)coarse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)coarse_shm));
     PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_shm));
     ctx->pinned_ensure(sizeof(int32_t) * nq);
     int32_t *h_flags = reinterpret_cast<int32_t *>(ctx->pinned);
@@ -2330,7 +2334,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         }
         // coarse probing (and the number of queries per list)
         if (nlist > 1) {
-            hipLaunchKernelGGL(k_coarse, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
+            hipLaunchKernelGGL(coarse_kernel, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
                                ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq,
                                nprobe_dev, nprobe_all, c_co, np_max, probes, npq, list_cnt);
         } else {

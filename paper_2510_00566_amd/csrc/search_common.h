@@ -403,11 +403,17 @@ __device__ inline float wave_select_small_p(const float *V, int n, int p, float 
 // values in registers up to 4096 (narrowed through C, n floats of LDS, when
 // p <= 64), else an MSB-first radix select, 8 bits per round, with a 256-bin
 // LDS histogram (hist[256]).
+// NMAX: the largest n of the caller; only the register-resident forms that n
+// can reach are compiled (their register needs grow with the values per
+// lane), so a caller with few lists keeps a small register footprint.
+template <int NMAX>
 __device__ inline float wave_select_nonneg(const float *V, int n, int p, int *hist, float *C, int lane)
 {
     if (n <= 256) return wave_select_regs<4>(V, n, p, lane);
-    if (n <= 1024) return p <= 64 ? wave_select_small_p<16>(V, n, p, C, lane) : wave_select_regs<16>(V, n, p, lane);
-    if (n <= 4096) return p <= 64 ? wave_select_small_p<64>(V, n, p, C, lane) : wave_select_regs<64>(V, n, p, lane);
+    if (NMAX > 256 && n <= 1024)
+        return p <= 64 ? wave_select_small_p<16>(V, n, p, C, lane) : wave_select_regs<16>(V, n, p, lane);
+    if (NMAX > 1024 && n <= 4096)
+        return p <= 64 ? wave_select_small_p<64>(V, n, p, C, lane) : wave_select_regs<64>(V, n, p, lane);
     uint32_t prefix = 0, mask = 0;
     int need = p;
     for (int shift = 24; shift >= 0; shift -= 8) {
