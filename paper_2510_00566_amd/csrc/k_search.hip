@@ -154,25 +154,31 @@ __global__ void k_single_list(int64_t nq, int np_max, int32_t *__restrict__ prob
 }
 
 // ================================================================ work list
-// One workgroup: per-list query offsets and the item offsets of the eight
-// XCD queues (lists are ordered by (l mod 8, l div 8)).
-__global__ __launch_bounds__(NT) void k_wl_offsets(int nlist, int ceil8, int G, int bpi, int item_cap,
-                                                   const int32_t *__restrict__ list_cnt,
-                                                   const int64_t *__restrict__ list_blk,
-                                                   int64_t *__restrict__ list_qoff,
-                                                   int64_t *__restrict__ item_off)
+// One workgroup: per-list query offsets (to list_qoff in global memory and/or
+// qoff_lds, 32-bit, in LDS) and, when item_off is given, the item offsets of
+// the eight XCD queues (lists are ordered by (l mod 8, l div 8)).
+__device__ inline void wl_offsets_block(int nlist, int ceil8, int G, int bpi, int item_cap,
+                                        const int32_t *__restrict__ list_cnt, const int64_t *__restrict__ list_blk,
+                                        int64_t *__restrict__ list_qoff, int32_t *qoff_lds,
+                                        int64_t *__restrict__ item_off, int *wave_tmp)
 {
-    __shared__ int wave_tmp[NT / 64];
     int64_t run = 0;
     for (int base = 0; base < nlist; base += NT) {
         int l = base + threadIdx.x;
         int c = l < nlist ? list_cnt[l] : 0;
         int tot;
         int o = block_exclusive_scan(c, wave_tmp, &tot);
-        if (l < nlist) list_qoff[l] = run + o;
+        if (l < nlist) {
+            if (list_qoff) list_qoff[l] = run + o;
+            if (qoff_lds) qoff_lds[l] = (int32_t)(run + o);
+        }
         run += tot;
     }
-    if (threadIdx.x == 0) list_qoff[nlist] = run;
+    if (threadIdx.x == 0) {
+        if (list_qoff) list_qoff[nlist] = run;
+        if (qoff_lds) qoff_lds[nlist] = (int32_t)run;
+    }
+    if (item_off == nullptr) return;
     __syncthreads();
     const int npos = 8 * ceil8;
     int64_t irun = 0;
@@ -194,6 +200,45 @@ __global__ __launch_bounds__(NT) void k_wl_offsets(int nlist, int ceil8, int G, 
         irun += tot;
     }
     if (threadIdx.x == 0) item_off[npos] = irun;
+}
+
+__global__ __launch_bounds__(NT) void k_wl_offsets(int nlist, int ceil8, int G, int bpi, int item_cap,
+                                                   const int32_t *__restrict__ list_cnt,
+                                                   const int64_t *__restrict__ list_blk,
+                                                   int64_t *__restrict__ list_qoff,
+                                                   int64_t *__restrict__ item_off)
+{
+    __shared__ int wave_tmp[NT / 64];
+    wl_offsets_block(nlist, ceil8, G, bpi, item_cap, list_cnt, list_blk, list_qoff, nullptr, item_off, wave_tmp);
+}
+
+// The per-list query arrays in one launch (up to WL_FUSED_LISTS lists): every
+// workgroup derives the per-list query offsets from the counts in its LDS
+// (workgroup 0 also publishes them and the item offsets for the scan), then
+// places its share of the (query, probe) pairs.
+constexpr int WL_FUSED_LISTS = 8192;
+__global__ __launch_bounds__(NT) void k_wl_fill_fused(int64_t nq, int np_max, const int32_t *__restrict__ probes,
+                                                      const int32_t *__restrict__ np, int nlist, int ceil8, int G,
+                                                      int bpi, int item_cap, const int32_t *__restrict__ list_cnt,
+                                                      const int64_t *__restrict__ list_blk,
+                                                      int64_t *__restrict__ list_qoff, int64_t *__restrict__ item_off,
+                                                      int32_t *__restrict__ list_fill, int32_t *__restrict__ list_q)
+{
+    extern __shared__ int32_t qoff_s[];  // [nlist + 1]
+    __shared__ int wave_tmp[NT / 64];
+    const bool first = blockIdx.x == 0;
+    wl_offsets_block(nlist, ceil8, G, bpi, item_cap, list_cnt, list_blk, first ? list_qoff : nullptr, qoff_s,
+                     first ? item_off : nullptr, wave_tmp);
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nq * np_max) return;
+    const int64_t i = t / np_max;
+    const int r = (int)(t % np_max);
+    if (r < np[i]) {
+        const int l = probes[t];
+        const int pos = atomicAdd(&list_fill[l], 1);
+        list_q[qoff_s[l] + pos] = (int32_t)i;
+    }
 }
 
 __global__ void k_wl_fill(int64_t nq, int np_max, const int32_t *__restrict__ probes,
@@ -2348,10 +2393,16 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         }
         // work decomposition
         const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
-        hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi, c.item_cap, list_cnt,
-                           ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
-        hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_qoff, list_fill,
-                           list_q);
+        if (nlist <= WL_FUSED_LISTS) {
+            hipLaunchKernelGGL(k_wl_fill_fused, dim3(wl_grid), dim3(NT), sizeof(int32_t) * (size_t)(nlist + 1), st, nq,
+                               np_max, probes, npq, nlist, c.ceil8, c.G, c.bpi, c.item_cap, list_cnt,
+                               ix->list_blk_d.as<int64_t>(), list_qoff, item_off, list_fill, list_q);
+        } else {
+            hipLaunchKernelGGL(k_wl_offsets, dim3(1), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi, c.item_cap,
+                               list_cnt, ix->list_blk_d.as<int64_t>(), list_qoff, item_off);
+            hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_qoff,
+                               list_fill, list_q);
+        }
         if (split)
             hipLaunchKernelGGL(k_wl_items, dim3((unsigned)(8 * c.ceil8)), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi,
                                list_cnt, ix->list_blk_d.as<int64_t>(), item_off, items, pl.items_max);
