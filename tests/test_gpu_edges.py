@@ -245,3 +245,18 @@ def test_relaxed_bound_properties(torch_cuda):
             assert (dd[i] >= ref_d[i]).all()
     ids, dd = case["idx"].search(qd, w.k, nprobe=w.nprobe, eps=1.0)
     gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
+
+
+@gpu
+@pytest.mark.parametrize("nlist,nprobe", [(2000, 40), (2000, 100), (5000, 40), (5000, 100)])
+def test_many_lists(torch_cuda, nlist, nprobe):
+    """The coarse step with many lists: the instance for up to 4096 lists
+    (register-resident selects of 64 values per lane) and the general one
+    (8-bit radix passes over an LDS histogram beyond 4096 lists), with
+    p <= 64 (narrowed through the per-lane minima) and p > 64."""
+    from tests import gpu_cases as gc
+    w = _workload(d=32, k=10, nlist=nlist, nprobe=nprobe, width=8, n=4 * nlist, nq=16)
+    _log(f"case many lists n={4 * nlist} d=32 nlist={nlist} nprobe={nprobe}")
+    case = gc.build_case(w)
+    _, _, st = _run(torch_cuda, case, w, case["data"]["q"])
+    assert st["fallback_queries"] == 0
