@@ -183,7 +183,10 @@ typedef struct {
  * ids_dev [nq][k] int64 (row index of the vector in build_levels' x) and
  * dists_dev [nq][k] float32 (canonical D), ascending by (D, id).  `params`
  * may be NULL.  Errors: EINVAL if k < 1, nq < 0, eps outside [0, 1] or a
- * query is non-finite; ENOMEM if scratch cannot be allocated.
+ * query is non-finite; ENOMEM if scratch cannot be allocated.  An ordinary
+ * search launches a graph (captured once per launch configuration on the
+ * context's own stream) on `stream`; eager, counting and timing searches run
+ * on the context's streams after the work already queued on `stream`.
  */
 pano_status pano_search(pano_index *idx, const float *q_dev, int64_t nq, int32_t k,
                         const int32_t *nprobe_dev, int32_t nprobe_all, float eps,
