@@ -84,7 +84,7 @@ struct Margins {
     float b0max2;       // bound on the largest stored squared norm
 };
 
-// Up to ten buffers cleared (or set to a 32-bit pattern) by one kernel.
+// Up to MAXSEG buffers cleared (or set to a 32-bit pattern) by one kernel.
 struct FillList {
     static constexpr int MAXSEG = 14;
     void *p[MAXSEG];
