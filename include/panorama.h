@@ -68,6 +68,17 @@ pano_status pano_ctx_create(int device, pano_ctx **out);
 /* Destroy a context; every index built on it must be freed first. */
 void pano_ctx_destroy(pano_ctx *ctx);
 
+/* Device memory (bytes) the context currently keeps for search scratch.  A
+ * context grows its scratch to the largest search it has run (by 1.25x the
+ * request when it grows) and keeps it; a serving loop charges this resident
+ * amount against its memory budget. */
+pano_status pano_ctx_scratch_bytes(const pano_ctx *ctx, int64_t *bytes);
+
+/* Release the context's search scratch memory and its captured search graph
+ * (the next search allocates again).  Call only while no search runs on the
+ * context. */
+pano_status pano_ctx_trim(pano_ctx *ctx);
+
 /*
  * build_transform: the PCA basis of Section 4.1, fitted on the host in FP64.
  * x_host [n][d] float32 rows.  The mean mu and covariance are accumulated in
@@ -116,15 +127,19 @@ pano_status pano_ivf_assign(pano_ctx *ctx, const float *x_dev, int64_t n, int32_
  * build_levels: pack the index (Section 6.1 level-major batches, Section 6.5
  * tail energies).  x_dev [n][d] raw rows; centroids_dev [nlist][d];
  * assign_dev [n] in [0, nlist).  m_host [L+1] level cuts with m[0] = 0 <
- * m[1] < ... < m[L] = d (Eq. 2).  `block` is the batch size B (a multiple of
- * 64, 64..1024; 0 = 256).  Each list is cut into blocks of B vectors; within a
- * block all B level-l slices are contiguous, then level l+1 (each slice padded
- * to a multiple of 4 floats with zeros).  Per vector the tail norms
+ * m[1] < ... < m[L] = d (Eq. 2), 1 <= L <= 64.  `block` is the batch size B:
+ * 64, 128 or 256 (0 = 256; the scan encodes a slot in 8 bits).  The first
+ * level may hold at most 64 dimensions, and the level widths, each padded to a
+ * multiple of 4, may sum to at most 4096.  Each list is cut into blocks of B
+ * vectors; within a block all B level-l slices are contiguous, then level l+1
+ * (each slice padded to a multiple of 4 floats with zeros).  Per vector the tail norms
  * sqrt(R_x^(l,d)) for l = 0..L-1 are stored (4L bytes).  The index keeps a
  * device copy of the raw rows (used for the canonical rescoring) and of the
  * centroids; it lives in device memory and is owned by the handle.
  * store = PANO_BF16 additionally stores the level slices in bfloat16.
- * Errors: EINVAL on inconsistent shapes or cuts; ENOMEM.
+ * Errors: EINVAL on inconsistent shapes or cuts or a block size outside
+ * {0, 64, 128, 256} (checked before anything else, so these are reported even
+ * for null handles); ENOMEM.
  */
 pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const float *x_dev,
                               int64_t n, int32_t d, const float *centroids_dev,
@@ -178,7 +193,9 @@ typedef struct {
  * lists (exact at probe for eps = 1; Algorithm 1 with Eq. 4 for eps < 1).
  * q_dev [nq][d] float32.  nprobe_dev [nq] int32 per-query probe counts, or
  * NULL to use nprobe_all for every query; probe counts are clamped to
- * [1, nlist].  The probe set of a query is its nprobe nearest lists by
+ * [1, nlist].  With nprobe_dev, a positive nprobe_all is an upper bound on
+ * the per-query counts (larger ones are clamped to it) and sizes the probe
+ * tables as nq x nprobe_all; 0 sizes them for nlist probes per query.  The probe set of a query is its nprobe nearest lists by
  * (D(q, centroid), list id).  eps in [0, 1] (Eq. 4; 1 = exact).  Outputs
  * ids_dev [nq][k] int64 (row index of the vector in build_levels' x) and
  * dists_dev [nq][k] float32 (canonical D), ascending by (D, id).  `params`
@@ -210,8 +227,11 @@ pano_status pano_search_ctx(pano_ctx *ctx, pano_index *idx, const float *q_dev, 
 /*
  * search_scratch_bytes: device scratch memory (bytes) that a pano_search of
  * nq queries with this k, probe setting (per_query_nprobe != 0: a per-query
- * array, else nprobe_all for all) and params needs on its context, beside
- * the caller's queries and outputs.  Used for memory-based admission.
+ * array bounded by nprobe_all, or by nlist if nprobe_all is 0; else
+ * nprobe_all for all) and params needs on its context, beside the caller's
+ * queries and outputs.  Includes the key buffer of the exact fallback for one
+ * query (8 bytes per slot of its largest possible probe set).  Used for
+ * memory-based admission.
  */
 pano_status pano_search_scratch_bytes(const pano_index *idx, int64_t nq, int32_t k,
                                       int32_t per_query_nprobe, int32_t nprobe_all,

@@ -144,6 +144,27 @@ pano_status pano_ctx_create(int device, pano_ctx **out)
 
 void pano_ctx_destroy(pano_ctx *ctx) { delete ctx; }
 
+pano_status pano_ctx_scratch_bytes(const pano_ctx *ctx, int64_t *bytes)
+{
+    return guarded([&] {
+        PANO_REQUIRE(ctx && bytes, "null argument");
+        int64_t t = 0;
+        for (const auto &m : ctx->scratch) t += (int64_t)m.bytes;
+        *bytes = t;
+    });
+}
+
+pano_status pano_ctx_trim(pano_ctx *ctx)
+{
+    return guarded([&] {
+        PANO_REQUIRE(ctx, "null argument");
+        PANO_HIP(hipSetDevice(ctx->device));
+        if (ctx->stream) PANO_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->drop_graph();
+        for (auto &m : ctx->scratch) m.release();
+    });
+}
+
 pano_status pano_build_transform(const float *x_host, int64_t n, int32_t d, int64_t fit_sample, uint64_t seed,
                                  pano_transform **out)
 {
@@ -340,15 +361,23 @@ pano_status pano_build_levels(pano_ctx *ctx, const pano_transform *tf, const flo
                               void *stream)
 {
     return guarded([&] {
-        PANO_REQUIRE(ctx && tf && x_dev && centroids_dev && assign_dev && m_host && out, "null argument");
-        PANO_REQUIRE(tf->d == d, "transform dimension does not match d");
-        PANO_REQUIRE(n >= 1 && d >= 1 && nlist >= 1, "bad sizes");
-        PANO_REQUIRE(L >= 1 && L <= 64, "L must be in [1, 64]");
-        PANO_REQUIRE(m_host[0] == 0 && m_host[L] == d, "level cuts must start at 0 and end at d");
-        for (int l = 0; l < L; ++l) PANO_REQUIRE(m_host[l] < m_host[l + 1], "level cuts must increase");
+        // argument values first, so that they are reported even for null handles
         if (block == 0) block = 256;
         PANO_REQUIRE(block == 64 || block == 128 || block == 256, "block must be 64, 128 or 256");
         PANO_REQUIRE(store == PANO_F32 || store == PANO_BF16, "unknown storage dtype");
+        PANO_REQUIRE(n >= 1 && d >= 1 && nlist >= 1, "bad sizes");
+        PANO_REQUIRE(L >= 1 && L <= 64, "L must be in [1, 64]");
+        PANO_REQUIRE(m_host != nullptr, "null argument");
+        PANO_REQUIRE(m_host[0] == 0 && m_host[L] == d, "level cuts must start at 0 and end at d");
+        for (int l = 0; l < L; ++l) PANO_REQUIRE(m_host[l] < m_host[l + 1], "level cuts must increase");
+        {
+            int w0 = (m_host[1] + 3) / 4 * 4, dp = 0;
+            for (int l = 0; l < L; ++l) dp += (m_host[l + 1] - m_host[l] + 3) / 4 * 4;
+            PANO_REQUIRE(w0 <= 64, "the first level may hold at most 64 dimensions");
+            PANO_REQUIRE(dp <= 4096, "d up to 4096 is supported");
+        }
+        PANO_REQUIRE(ctx && tf && x_dev && centroids_dev && assign_dev && out, "null argument");
+        PANO_REQUIRE(tf->d == d, "transform dimension does not match d");
         PANO_HIP(hipSetDevice(ctx->device));
         hipStream_t s = (hipStream_t)stream;
         auto ix = std::make_unique<pano_index>();

@@ -2081,12 +2081,22 @@ struct Carver {
 
 // Launch constants and scratch sizes of one search (no device work).
 struct SearchPlan {
-    size_t need[6];     // bytes of scratch slots 0..3 and of the split scan's pair list and item table
+    size_t need[7];     // bytes of scratch slots 0..3, of the split scan's pair list and item table,
+                        // and the bound on the exact fallback's key buffer (one query)
     bool split;         // split scan (filter kernel + per-pair walk) instead of the persistent scan
     int grid_seg;       // workgroups of the split scan
     int64_t seg_cap;    // pairs per workgroup segment
     int64_t items_max;  // work items the item table holds
 };
+
+// Probe slots per query: nprobe_all (at most nlist) for a common probe count;
+// for per-query counts, nprobe_all when positive (an upper bound the kernels
+// clamp to), else nlist.
+static int probe_cap(bool per_query_np, int nprobe_all, int nlist)
+{
+    if (per_query_np) return nprobe_all > 0 ? std::min(nprobe_all, nlist) : nlist;
+    return std::min(nprobe_all, nlist);
+}
 
 static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_np, int nprobe_all, float eps,
                         const pano_search_params *prm, bool brute, SearchConsts &c, SearchPlan &pl)
@@ -2170,7 +2180,7 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     c.g.B = ix->B;
     for (int l = 0; l <= L; ++l) c.g.mp[l] = ix->mp[l];
     for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
-    const int np_max = per_query_np ? nlist : std::min(nprobe_all, nlist);
+    const int np_max = probe_cap(per_query_np, nprobe_all, nlist);
     need[0] = align_up(sizeof(float) * nq * ix->d_pad) + align_up(sizeof(float) * nq * L) +
               2 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
     need[1] = nlist > 1 ? align_up(sizeof(float) * nq * nlist) : 256;
@@ -2183,6 +2193,13 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     pl.seg_cap = 0;
     pl.items_max = 0;
     need[4] = need[5] = 0;
+    {
+        // the exact fallback of one query: its probed list ids and one 64-bit
+        // key per slot of its probe set, at most the np_max largest lists
+        const int64_t s_np = ix->top_blk_prefix[std::min<int64_t>(np_max, nlist)];
+        need[6] = align_up(sizeof(int32_t) * (size_t)std::max(1, np_max)) +
+                  align_up(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, s_np * ix->B));
+    }
     if (pl.split) {
         // one segment per workgroup: room for at least two items' worth of
         // survivors (a full segment is walked before the next item), sized
@@ -2212,7 +2229,7 @@ size_t search_scratch_bytes(const pano_index *ix, int64_t nq, int k, bool per_qu
     SearchPlan pl;
     plan_search(ix, nq, k, per_query_np, nprobe_all, 1.f, prm, brute, c, pl);
     size_t t = 0;
-    for (int i = 0; i < 6; ++i) t += pl.need[i];
+    for (int i = 0; i < 7; ++i) t += pl.need[i];
     return t;
 }
 
@@ -2242,7 +2259,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     const int seed_pool = std::min(1024, (prm && prm->seed_pool > 0) ? prm->seed_pool : 512);
     const int seed_cnt = std::min(256, std::max(k, (prm && prm->seed_count > 0) ? prm->seed_count : std::max(2 * k, 32)));
     const int grid = (prm && prm->grid > 0) ? prm->grid : ctx->num_cu * (brute ? 2 : 3);
-    const int np_max = nprobe_dev ? nlist : std::min(nprobe_all, nlist);
+    const int np_max = probe_cap(nprobe_dev != nullptr, nprobe_all, nlist);
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
     const bool want_timing = !want_stats && (flags & PANO_SEARCH_TIMING) != 0;
     const bool seed_on = !brute && eps >= 1.f;
@@ -2392,8 +2409,10 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             PANO_HIP(hipEventRecord(ctx->ev_join2, sb));
         }
         // work decomposition
+        // one launch when the fill grid is small (every fill workgroup derives
+        // the offsets itself); else the offsets once, then the fill
         const unsigned wl_grid = (unsigned)((nq * np_max + 255) / 256);
-        if (nlist <= WL_FUSED_LISTS) {
+        if (nlist <= WL_FUSED_LISTS && (int64_t)wl_grid * nlist <= (int64_t)1 << 21) {
             hipLaunchKernelGGL(k_wl_fill_fused, dim3(wl_grid), dim3(NT), sizeof(int32_t) * (size_t)(nlist + 1), st, nq,
                                np_max, probes, npq, nlist, c.ceil8, c.G, c.bpi, c.item_cap, list_cnt,
                                ix->list_blk_d.as<int64_t>(), list_qoff, item_off, list_fill, list_q);

@@ -33,6 +33,16 @@ class Context:
         self.device = device
         self._indexes = weakref.WeakSet()
 
+    def scratch_bytes(self) -> int:
+        """Device memory the context keeps for search scratch."""
+        out = C.c_int64()
+        L.check(L.lib().pano_ctx_scratch_bytes(self.h, C.byref(out)))
+        return out.value
+
+    def trim(self):
+        """Release the context's search scratch (no search may be running on it)."""
+        L.check(L.lib().pano_ctx_trim(self.h))
+
     def close(self):
         """Destroy the context; indexes built on it are freed first."""
         if self.h:
@@ -129,6 +139,14 @@ class Params:
         return p
 
 
+def _probe_args(nprobe, nprobe_max: int):
+    """(per-query count tensor or None, nprobe_all) of the C ABI."""
+    import torch
+    if isinstance(nprobe, torch.Tensor):
+        return nprobe, int(nprobe_max)
+    return None, int(nprobe)
+
+
 class Index:
     def __init__(self, h, ctx: Context, d: int):
         self.h = h
@@ -157,18 +175,15 @@ class Index:
 
     def search(self, q_dev, k: int, nprobe=1, eps: float = 1.0, params: Params | None = None,
                stats: bool = False, stream=None, out=None, eager: bool = False, ctx: Context | None = None,
-               timing: bool = False):
-        """k-NN of each row of q_dev among its probed lists.  ctx: run on this
-        context (one per concurrent caller) instead of the index's own.
-        timing: phase durations of an ordinary (uncounted) search in stats()."""
+               timing: bool = False, nprobe_max: int = 0):
+        """k-NN of each row of q_dev among its probed lists.  nprobe: an int,
+        or a device tensor of per-query counts (bounded by nprobe_max when
+        positive).  ctx: run on this context (one per concurrent caller)
+        instead of the index's own.  timing: phase durations of an ordinary
+        (uncounted) search in stats()."""
         import torch
         ids, dists = out if out is not None else self._outs(q_dev, k)
-        np_dev = None
-        np_all = 0
-        if isinstance(nprobe, torch.Tensor):
-            np_dev = nprobe
-        else:
-            np_all = int(nprobe)
+        np_dev, np_all = _probe_args(nprobe, nprobe_max)
         prm = params.c() if params is not None else None
         flags = ((L.PANO_SEARCH_STATS if stats else 0) | (L.PANO_SEARCH_EAGER if eager else 0) |
                  (L.PANO_SEARCH_TIMING if timing else 0))
@@ -180,24 +195,19 @@ class Index:
 
     def scratch_bytes(self, nq: int, k: int, nprobe=1, per_query_nprobe: bool = False,
                       params: Params | None = None) -> int:
-        """Device scratch a search of nq queries needs on its context."""
+        """Device scratch a search of nq queries needs on its context.  With
+        per_query_nprobe, nprobe is the largest per-query count (0: nlist)."""
         out = C.c_int64()
         prm = params.c() if params is not None else None
         L.check(L.lib().pano_search_scratch_bytes(self.h, int(nq), int(k), 1 if per_query_nprobe else 0,
-                                                  int(nprobe) if not per_query_nprobe else 0,
-                                                  C.byref(prm) if prm is not None else None, C.byref(out)))
+                                                  int(nprobe), C.byref(prm) if prm is not None else None,
+                                                  C.byref(out)))
         return out.value
 
     def search_bruteforce(self, q_dev, k: int, nprobe=1, params: Params | None = None, stats: bool = False,
-                          stream=None, out=None, eager: bool = False):
-        import torch
+                          stream=None, out=None, eager: bool = False, nprobe_max: int = 0):
         ids, dists = out if out is not None else self._outs(q_dev, k)
-        np_dev = None
-        np_all = 0
-        if isinstance(nprobe, torch.Tensor):
-            np_dev = nprobe
-        else:
-            np_all = int(nprobe)
+        np_dev, np_all = _probe_args(nprobe, nprobe_max)
         prm = params.c() if params is not None else None
         L.check(L.lib().pano_search_bruteforce(self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all,
                                                _ptr(ids), _ptr(dists), C.byref(prm) if prm is not None else None,

@@ -12,6 +12,14 @@ arrive while batches run join the next batch formed; no batch waits for a
 fixed window.  Probe counts may differ inside a batch (a per-query probe
 array), k may not (k sets the result shape).
 
+Memory admission counts what stays allocated, not only what a batch uses: a
+worker's context keeps its scratch at the largest size it has needed (grown
+by the library's factor of 1.25), so the scheduler charges each worker its
+resident scratch, raises the charge when a batch may grow it, and lowers it
+only when the worker reports a smaller resident size after trimming its
+context.  A worker whose context holds more than its share of the budget
+(budget / workers) after a batch trims it.
+
 The search itself is exact at eps = 1, so a request's answer does not depend
 on which other requests share its batch; ``tests/test_gpu_serving.py`` checks
 that.  Everything here is host-side orchestration (threads, queues,
@@ -54,6 +62,9 @@ class Batch:
     k: int
     requests: list
     bytes: int
+    worker: int = 0
+    prev_charge: int = 0
+    trim: bool = False       # no requests: the worker releases its context's memory
 
     @property
     def nq(self) -> int:
@@ -64,17 +75,26 @@ class Scheduler:
     """Thread-safe admission and batch formation (no GPU here).
 
     cost(index, nq, k) -> bytes of device memory a batch of nq queries needs
-    while in flight; budget caps the sum over batches in flight.  A single
-    request larger than the whole budget is still admitted alone (it could
-    never run otherwise); the budget is then exceeded by that batch only."""
+    while in flight.  Each worker is charged its resident bytes: a batch of
+    cost c on worker w raises w's charge to max(charge_w, growth * c), and
+    budget caps the sum of the charges of all workers.  finish() sets the
+    worker's charge to the resident size it reports (0 after a trim).  A
+    single request that cannot fit even when no other batch is in flight is
+    still admitted alone (it could never run otherwise); the budget is then
+    exceeded by that batch only."""
 
-    def __init__(self, cost: Callable[[str, int, int], int], budget: int, max_batch_queries: int = 4096):
+    def __init__(self, cost: Callable[[str, int, int], int], budget: int, max_batch_queries: int = 4096,
+                 growth: float = 1.25):
         self.cost = cost
         self.budget = int(budget)
         self.max_q = int(max_batch_queries)
+        self.growth = float(growth)
         self._lock = threading.Condition()
         self._queues: dict = collections.OrderedDict()  # (index, k) -> deque of Request
-        self._inflight = 0
+        self._charge: dict = {}  # worker id -> bytes charged for its context
+        self._busy = 0  # batches in flight
+        self._idle: set = set()  # workers waiting in next_batch
+        self._pressure = False  # idle workers holding memory should trim
         self._peak = 0
         self._closed = False
         self._next_bid = 0
@@ -101,58 +121,102 @@ class Scheduler:
                 best, best_head = key, (q[0].arrival, q[0].rid)
         return best
 
-    def next_batch(self) -> Batch | None:
-        """Block until a batch can be formed and admitted; None when closed
-        and drained."""
-        with self._lock:
-            while True:
-                key = self._oldest_class()
-                if key is None:
-                    if self._closed:
-                        return None
-                    self._lock.wait()
-                    continue
-                q = self._queues[key]
-                index, k = key
-                take, nq = [], 0
-                while q and (not take or nq + q[0].m <= self.max_q):
-                    cand = nq + q[0].m
-                    need = self.cost(index, cand, k)
-                    if take and self._inflight + need > self.budget:
-                        break
-                    if not take and self._inflight > 0 and self._inflight + need > self.budget:
-                        break
-                    take.append(q.popleft())
-                    nq = cand
-                if not take:
-                    # the oldest class does not fit next to the batches in
-                    # flight: wait for one of them to finish
-                    self._lock.wait()
-                    continue
-                need = self.cost(index, nq, k)
-                self._inflight += need
-                self._peak = max(self._peak, self._inflight)
-                b = Batch(self._next_bid, index, k, take, need)
-                self._next_bid += 1
-                return b
+    def _charged_with(self, wid: int, need: int) -> int:
+        """Total charge if worker wid runs a batch of cost `need`."""
+        mine = max(self._charge.get(wid, 0), int(self.growth * need))
+        return sum(v for w, v in self._charge.items() if w != wid) + mine
 
-    def finish(self, batch: Batch):
+    def next_batch(self, wid: int = 0) -> Batch | None:
+        """Block until a batch can be formed and admitted for worker wid;
+        None when closed and drained.  Returns a batch without requests
+        (trim=True) when the worker should release its context's memory
+        first: another worker's batch does not fit beside the memory that
+        idle workers keep."""
         with self._lock:
-            self._inflight -= batch.bytes
+            self._idle.add(wid)
+            try:
+                return self._next_locked(wid)
+            finally:
+                self._idle.discard(wid)
+
+    def _next_locked(self, wid: int) -> Batch | None:
+        while True:
+            if self._pressure and self._charge.get(wid, 0) > 0:
+                # asked to make room: release this context's memory
+                b = Batch(-1, "", 0, [], 0, worker=wid, prev_charge=self._charge[wid], trim=True)
+                self._busy += 1
+                return b
+            key = self._oldest_class()
+            if key is None:
+                if self._closed:
+                    return None
+                self._lock.wait()
+                continue
+            q = self._queues[key]
+            index, k = key
+            others_hold = any(v > 0 for w, v in self._charge.items() if w != wid)
+            take, nq = [], 0
+            while q and (not take or nq + q[0].m <= self.max_q):
+                cand = nq + q[0].m
+                need = self.cost(index, cand, k)
+                if self._charged_with(wid, need) > self.budget and (take or self._busy > 0 or others_hold):
+                    break
+                take.append(q.popleft())
+                nq = cand
+            if not take:
+                # the oldest class does not fit beside the memory the other
+                # workers hold: idle ones are asked to trim, busy ones may
+                # trim when they finish
+                if any(self._charge.get(w, 0) > 0 for w in self._idle if w != wid):
+                    self._pressure = True
+                self._lock.notify_all()
+                self._lock.wait()
+                continue
+            self._pressure = False
+            need = self.cost(index, nq, k)
+            prev = self._charge.get(wid, 0)
+            self._charge[wid] = max(prev, int(self.growth * need))
+            self._busy += 1
+            self._peak = max(self._peak, sum(self._charge.values()))
+            b = Batch(self._next_bid, index, k, take, need, worker=wid, prev_charge=prev)
+            self._next_bid += 1
+            return b
+
+    def finish(self, batch: Batch, resident: int | None = None):
+        """Batch done; resident: the bytes its worker's context now keeps
+        (None: an executor that keeps nothing between batches, so the charge
+        returns to what it was before the batch)."""
+        with self._lock:
+            self._busy -= 1
+            self._charge[batch.worker] = int(resident) if resident is not None else batch.prev_charge
             self._lock.notify_all()
+
+    def share(self, n_workers: int) -> int:
+        """Resident bytes a worker may keep between batches."""
+        return self.budget // max(1, n_workers)
 
     @property
     def peak_inflight(self) -> int:
+        """Largest total charge seen (bytes)."""
         return self._peak
 
     @property
     def inflight(self) -> int:
-        return self._inflight
+        """Current total charge (bytes), resident memory of idle workers included."""
+        with self._lock:
+            return sum(self._charge.values())
+
+    @property
+    def busy(self) -> int:
+        return self._busy
 
 
 class Server:
     """Worker threads that pull batches from a Scheduler and run them with
-    execute(worker_id, batch) -> list of (ids, dists) per request."""
+    execute(worker_id, batch) -> list of (ids, dists) per request.  If the
+    executor has resident(wid) and trim(wid), a worker reports its context's
+    resident bytes after each batch and trims the context first when it holds
+    more than its share of the budget."""
 
     def __init__(self, scheduler: Scheduler, execute: Callable, n_workers: int = 3,
                  clock: Callable[[], float] = time.perf_counter):
@@ -166,11 +230,27 @@ class Server:
         self._threads = []
         self.errors: list = []
 
+    def _resident_after(self, wid: int):
+        ex = self.execute
+        if not (hasattr(ex, "resident") and hasattr(ex, "trim")):
+            return None
+        r = ex.resident(wid)
+        if r > self.sched.share(self.n_workers):
+            ex.trim(wid)
+            r = ex.resident(wid)
+        return r
+
     def _run(self, wid: int):
         while True:
-            b = self.sched.next_batch()
+            b = self.sched.next_batch(wid)
             if b is None:
                 return
+            if b.trim:
+                ex = self.execute
+                if hasattr(ex, "trim"):
+                    ex.trim(wid)
+                self.sched.finish(b, ex.resident(wid) if hasattr(ex, "resident") else 0)
+                continue
             t0 = self.clock()
             for r in b.requests:
                 r.start = t0
@@ -184,7 +264,7 @@ class Server:
             t1 = self.clock()
             for r, (ids, dd) in zip(b.requests, outs):
                 r.ids, r.dists, r.done = ids, dd, t1
-            self.sched.finish(b)
+            self.sched.finish(b, self._resident_after(wid))
             with self._lock:
                 self.completed.extend(b.requests)
                 self.batches.append((b.bid, wid, b.index, b.k, b.nq, t0, t1))
@@ -266,7 +346,8 @@ class GpuExecutor:
     indexes: name -> Index; params: name -> search Params (None: library
     defaults).  One Context and one torch stream per worker."""
 
-    def __init__(self, indexes: dict, n_workers: int, device: int = 0, params: dict | None = None):
+    def __init__(self, indexes: dict, n_workers: int, device: int = 0, params: dict | None = None,
+                 nprobe_max: int = 64):
         import torch
         from .index import Context
         self.indexes = indexes
@@ -274,12 +355,22 @@ class GpuExecutor:
         self.ctxs = [Context(device) for _ in range(n_workers)]
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_workers)]
         self.device = device
+        self.nprobe_max = int(nprobe_max)
 
     def cost(self, index: str, nq: int, k: int) -> int:
         idx = self.indexes[index]
         d = idx.d
         io = nq * (d * 4 + 4 + k * 12)  # queries, probe counts, ids + dists
-        return int(idx.scratch_bytes(nq, k, per_query_nprobe=True, params=self.params.get(index)) + io)
+        return int(idx.scratch_bytes(nq, k, nprobe=self.nprobe_max, per_query_nprobe=True,
+                                     params=self.params.get(index)) + io)
+
+    def resident(self, wid: int) -> int:
+        """Device bytes worker wid's context keeps for search scratch (the
+        batch's query and result tensors are charged while it runs)."""
+        return int(self.ctxs[wid].scratch_bytes())
+
+    def trim(self, wid: int):
+        self.ctxs[wid].trim()
 
     def __call__(self, wid: int, b: Batch):
         import torch
@@ -293,7 +384,7 @@ class GpuExecutor:
             # batch shapes vary from call to call: launch eagerly rather than
             # capture a graph per shape
             ids, dd = idx.search(qd, b.k, nprobe=npd, ctx=self.ctxs[wid], stream=st, eager=True,
-                                 params=self.params.get(b.index))
+                                 params=self.params.get(b.index), nprobe_max=self.nprobe_max)
             ids_h = ids.cpu().numpy()
             dd_h = dd.cpu().numpy()
         outs, o = [], 0

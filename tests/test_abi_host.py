@@ -88,3 +88,32 @@ def test_transform_from_rejects_non_orthonormal(lib):
         Transform.from_matrix(np.zeros(3), np.ones((3, 3)))
     tf = Transform.from_matrix(np.zeros(2), np.array([[0.6, 0.8], [-0.8, 0.6]]))
     assert np.allclose(tf.get()[1], [[0.6, 0.8], [-0.8, 0.6]])
+
+
+def test_build_levels_rejects_bad_geometry_without_gpu(lib):
+    """Block sizes outside {0, 64, 128, 256}, a first level wider than 64
+    dimensions and padded widths summing past 4096 are rejected before any
+    handle is used."""
+    import ctypes as C
+    h = C.c_void_p()
+
+    def build(block, m):
+        m = np.ascontiguousarray(m, dtype=np.int32)
+        return lib.pano_build_levels(None, None, None, 10, int(m[-1]), None, None, 1,
+                                     m.ctypes.data_as(C.c_void_p), m.size - 1, block, L.PANO_F32, C.byref(h), None)
+
+    assert build(512, [0, 8, 16]) == L.PANO_EINVAL and b"block" in lib.pano_last_error()
+    assert build(96, [0, 8, 16]) == L.PANO_EINVAL
+    assert build(256, [0, 68, 80]) == L.PANO_EINVAL and b"first level" in lib.pano_last_error()
+    assert build(256, [0, 64, 4097]) == L.PANO_EINVAL and b"4096" in lib.pano_last_error()
+    assert build(256, [0, 8, 8]) == L.PANO_EINVAL and b"increase" in lib.pano_last_error()
+    # a valid geometry gets as far as the null handles
+    assert build(0, [0, 8, 16]) == L.PANO_EINVAL and b"null" in lib.pano_last_error()
+    assert build(128, [0, 64, 4096]) == L.PANO_EINVAL and b"null" in lib.pano_last_error()
+
+
+def test_ctx_calls_reject_null_without_gpu(lib):
+    import ctypes as C
+    out = C.c_int64()
+    assert lib.pano_ctx_scratch_bytes(None, C.byref(out)) == L.PANO_EINVAL
+    assert lib.pano_ctx_trim(None) == L.PANO_EINVAL

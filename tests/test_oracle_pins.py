@@ -396,3 +396,185 @@ def test_planted_mistakes_are_caught(monkeypatch):
     bad = panorama.panorama_knn(q2, xs_, np.arange(3000), mu2, t2, m, 10, batch=64)[0]
     assert not np.array_equal(bad, bi[0])
     monkeypatch.setattr(panorama, "relaxed_lower_bound", orig_lb)
+
+
+# ---------------------------------------------------------------- Eq. 4 (eps < 1)
+
+def test_relaxed_lower_bound_golden():
+    """relaxed_lower_bound (the function Algorithm 1 calls) on the hand-worked
+    Hadamard quantities: Eq. 4 gives LB_0.5 = 8 - 2 * 0.5 * 2 = 6 for x at
+    level 1 and LB_eps = 4 for x2 at every level (its tail after level 1 is
+    empty, and at level 0 C = 4)."""
+    g = _read_golden("bounds_hadamard_d4.txt")
+    # x: R_q^(0,d) = R_x^(0,d) = 4; level 0: p = 0, tails 4, 4; level 1: p = 0,
+    # tails 2, 2; level 2: p = 0, tails 0
+    rq0 = rx0 = 4.0
+    for lv, (p, rql, rxl) in enumerate([(0.0, 4.0, 4.0), (0.0, 2.0, 2.0), (0.0, 0.0, 0.0)]):
+        assert panorama.relaxed_lower_bound(rq0, rx0, p, rql, rxl, 0.5) == g["LBeps05_x"][lv]
+        assert panorama.relaxed_lower_bound(rq0, rx0, p, rql, rxl, 1.0) == g["LB_x"][lv]
+    # x2: level 0: p = 0, tails 4, 4; level 1: p = 2, tails 2, 0; level 2: p = 2
+    for lv, (p, rql, rxl) in enumerate([(0.0, 4.0, 4.0), (2.0, 2.0, 0.0), (2.0, 0.0, 0.0)]):
+        assert panorama.relaxed_lower_bound(rq0, rx0, p, rql, rxl, 0.5) == g["LBeps05_x2"][lv]
+        assert panorama.relaxed_lower_bound(rq0, rx0, p, rql, rxl, 1.0) == g["LB_x2"][lv]
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.25, 0.5, 0.9, 1.0])
+def test_relaxed_lower_bound_gap_identity(eps):
+    """The gap identity of the appendix (Lemma for Prop. 5.3) through
+    relaxed_lower_bound itself: ||q - x||^2 - LB_eps = 2 C (eps - rho) with
+    rho C = pi the tail inner product.  The inputs (partial products and
+    tails) are formed here from a random orthogonal basis, not by the oracle."""
+    g = np.random.Generator(np.random.PCG64(77))
+    d, m = 9, [0, 2, 5, 9]
+    t, _ = np.linalg.qr(g.standard_normal((d, d)))
+    for _ in range(40):
+        q, x = g.standard_normal(d), g.standard_normal(d)
+        tq, tx = t @ q, t @ x
+        dd = float((q - x) @ (q - x))
+        for lv in range(len(m)):
+            p = float(tq[:m[lv]] @ tx[:m[lv]])
+            rql, rxl = float(tq[m[lv]:] @ tq[m[lv]:]), float(tx[m[lv]:] @ tx[m[lv]:])
+            pi = float(tq[m[lv]:] @ tx[m[lv]:])
+            lb = panorama.relaxed_lower_bound(float(tq @ tq), float(tx @ tx), p, rql, rxl, eps)
+            c = math.sqrt(rql * rxl)
+            assert abs((dd - lb) - 2.0 * (eps * c - pi)) < 1e-9 * (1.0 + dd)
+
+
+def _hadamard_scan(cands, eps, scan):
+    """Algorithm 1 on the Hadamard fixture: k = 1, batch 1, candidates in the
+    given order (the first seeds the heap)."""
+    q = np.array([2, 0, 0, 0], dtype=np.float32)
+    xs = np.asarray(cands, dtype=np.float32)
+    return scan(q, xs, eps)
+
+
+def _numpy_scan(q, xs, eps):
+    ids, dd, rho = panorama.panorama_knn(q, xs, np.arange(xs.shape[0]), np.zeros(4), H4, [0, 2, 4], 1,
+                                         batch=1, eps=eps)
+    return ids, dd, rho
+
+
+def test_algorithm1_eps_golden():
+    """Algorithm 1's pruning at eps < 1 against hand-worked decisions: with
+    d_k = 6.5 from the seed, x (LB_eps = 8 - 4 eps at level 1) survives level 1
+    for eps >= 0.375 and is pruned there below it; x2 (LB_eps = 4 <= d_k = 5)
+    survives for every eps and becomes the answer."""
+    g = _read_golden("bounds_hadamard_d4.txt")
+    r = g["rho_x_by_eps"]
+    for eps, want in zip(r[0::2], r[1::2]):
+        ids, dd, rho = _hadamard_scan([g["seed_s"], g["x"]], eps, _numpy_scan)
+        assert rho[1] == want, (eps, rho)
+        assert ids[0] == 0 and dd[0] == np.float32(6.5)
+    for eps in (0.0, 0.3, 0.5, 1.0):
+        ids, dd, rho = _hadamard_scan([g["seed_s2"], g["x2"]], eps, _numpy_scan)
+        assert ids[0] == 1 and dd[0] == np.float32(4.0) and rho[1] == 4
+
+
+def test_planted_eps_mistakes_are_caught(monkeypatch):
+    """Plausible slips in Eq. 4 (eps squared, eps applied to the partial
+    product instead of the tail term) each fail a pin above."""
+    orig = panorama.relaxed_lower_bound
+
+    def fails(fn):
+        try:
+            fn()
+        except AssertionError:
+            return True
+        return False
+
+    monkeypatch.setattr(panorama, "relaxed_lower_bound",
+                        lambda rq0, rx0, p, rql, rxl, eps: orig(rq0, rx0, p, rql, rxl, eps * eps))
+    assert fails(test_relaxed_lower_bound_golden)
+    assert fails(test_algorithm1_eps_golden)
+    monkeypatch.setattr(panorama, "relaxed_lower_bound",
+                        lambda rq0, rx0, p, rql, rxl, eps:
+                        rq0 + rx0 - 2.0 * eps * p - 2.0 * np.sqrt(rql * rxl))
+    assert fails(test_relaxed_lower_bound_golden)
+    assert fails(test_algorithm1_eps_golden)
+    monkeypatch.setattr(panorama, "relaxed_lower_bound", orig)
+    test_relaxed_lower_bound_golden()
+    test_algorithm1_eps_golden()
+
+
+def test_eps_result_keeps_neighbours_the_relaxed_bound_cannot_reach():
+    """A consequence of the gap identity for Algorithm 1 at eps < 1: d_k never
+    falls below the true k-th distance, so a true k-NN member whose tail
+    alignment rho_l stays at or below eps at every level (LB_eps <= D) is never
+    pruned and must be in the result."""
+    w = synth.scaled(synth.WORKLOADS["flat_sift_like"], n=3000, nq=4)
+    data = synth.generate(w)
+    x, q = data["x"], data["q"]
+    mu, t, _ = panorama.pca_fit(x)
+    m = [int(v) for v in w.level_cuts()]
+    k = 10
+    checked = 0
+    for eps in (0.3, 0.6, 0.9):
+        for qi in range(q.shape[0]):
+            ids, _, _ = panorama.panorama_knn(q[qi], x, np.arange(x.shape[0]), mu, t, m, k, batch=64, eps=eps)
+            bi, _ = brute.knn_flat(q[qi:qi + 1], x, k)
+            tq = (q[qi].astype(np.float64) - mu) @ t.T
+            for i in bi[0]:
+                tx = (x[i].astype(np.float64) - mu) @ t.T
+                safe = True
+                for lv in range(1, len(m) - 1):
+                    a, b = tq[m[lv]:], tx[m[lv]:]
+                    c = math.sqrt(float(a @ a) * float(b @ b))
+                    if c > 0 and float(a @ b) > eps * c * (1 - 1e-9):
+                        safe = False
+                if safe:
+                    assert i in ids, (eps, qi, i)
+                    checked += 1
+    assert checked > 20
+
+
+def test_c_oracle_eps_matches_hand_worked_and_numpy(c_oracle):
+    """orc_panorama at eps < 1: the hand-worked decisions above (dims read),
+    and the numpy oracle's result on a random case at eps = 0.5."""
+    g = _read_golden("bounds_hadamard_d4.txt")
+    q = np.array([[2, 0, 0, 0]], dtype=np.float32)
+    r = g["rho_x_by_eps"]
+    for eps, want in zip(r[0::2], r[1::2]):
+        xs = np.asarray([g["seed_s"], g["x"]], dtype=np.float32)
+        ys, R = c_oracle.prepare(xs, np.zeros(4), H4, [0, 2, 4])
+        off = np.array([0, 2], np.int64)
+        ids, dd, dims = c_oracle.panorama(q, xs, ys, R, np.zeros(4), H4, [0, 2, 4], off,
+                                          np.array([0, 1], np.int64), 1, batch=1, eps=eps)
+        assert dims[0] == 4 + want and ids[0, 0] == 0 and dd[0, 0] == np.float32(6.5)
+    w = synth.scaled(synth.WORKLOADS["flat_sift_like"], n=4000, nq=5)
+    data = synth.generate(w)
+    x, qs = data["x"], data["q"]
+    mu, t, _ = panorama.pca_fit(x)
+    m = w.level_cuts()
+    ys, R = c_oracle.prepare(x, mu, t, m)
+    off = np.arange(qs.shape[0] + 1, dtype=np.int64) * x.shape[0]
+    cand = np.tile(np.arange(x.shape[0], dtype=np.int64), qs.shape[0])
+    ic, dc, _ = c_oracle.panorama(qs, x, ys, R, mu, t, m, off, cand, 10, batch=256, eps=0.5)
+    for qi in range(qs.shape[0]):
+        i_n, d_n, _ = panorama.panorama_knn(qs[qi], x, np.arange(x.shape[0]), mu, t, m, 10, batch=256, eps=0.5)
+        assert np.array_equal(ic[qi], i_n) and np.array_equal(dc[qi], d_n)
+
+
+# ---------------------------------------------------------------- soft check of O2
+
+def test_assignment_mismatches_enumerated():
+    """The soft check counts rows not assigned to their (D, l)-nearest
+    centroid.  1-D case worked by hand: centroids at 0 and 2; the row at 1 is
+    equidistant and belongs to list 0 (smaller id)."""
+    cent = np.array([[0.0], [2.0]], dtype=np.float32)
+    xs = np.array([[-1.0], [0.5], [1.0], [1.5], [3.0]], dtype=np.float32)
+    right = np.array([0, 0, 0, 1, 1])
+    assert brute.assignment_mismatches(xs, cent, right) == 0
+    assert brute.assignment_mismatches(xs, cent, np.array([0, 0, 1, 1, 1])) == 1  # the tie
+    assert brute.assignment_mismatches(xs, cent, np.array([1, 1, 1, 0, 0])) == 5
+    # integer grid against every centroid by exact rational distances
+    x = synth.integer_grid(60, 3, 4, span=2)
+    c = synth.integer_grid(5, 3, 5, span=2)
+    best = []
+    for r in x:
+        dd = [_exact_sqdist(r, cc) for cc in c]
+        best.append(min(range(len(c)), key=lambda l: (dd[l], l)))
+    best = np.asarray(best)
+    assert brute.assignment_mismatches(x, c, best) == 0
+    wrong = best.copy()
+    wrong[:7] = (wrong[:7] + 1) % len(c)
+    assert brute.assignment_mismatches(x, c, wrong) == 7

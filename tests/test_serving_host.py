@@ -153,3 +153,59 @@ def test_failed_batch_does_not_stop_the_server():
     srv.join()
     assert len(srv.completed) == 6 and len(srv.errors) == 1
     assert [r.ids is None for r in sorted(srv.completed, key=lambda r: r.rid)] == [False] * 3 + [True] + [False] * 2
+
+
+class _FakeCtxExecutor:
+    """Stand-in executor with a context memory model like the library's: a
+    batch of cost c grows the worker's resident scratch to at least c (by
+    1.25x when it grows) and nothing shrinks it but trim()."""
+
+    def __init__(self, n_workers, cost, delay=0.002):
+        self.res = [0] * n_workers
+        self.cost = cost
+        self.delay = delay
+        self.lock = threading.Lock()
+        self.samples = []
+        self.trims = 0
+
+    def __call__(self, wid, b):
+        need = self.cost(b.index, b.nq, b.k)
+        with self.lock:
+            if need > self.res[wid]:
+                self.res[wid] = int(need * 1.25)
+            self.samples.append(sum(self.res))
+        time.sleep(self.delay)
+        return _echo()(wid, b)
+
+    def resident(self, wid):
+        return self.res[wid]
+
+    def trim(self, wid):
+        with self.lock:
+            self.res[wid] = 0
+            self.trims += 1
+
+
+def test_resident_scratch_stays_within_budget():
+    """Memory admission counts the scratch the workers' contexts keep after
+    their batches: the sum of resident bytes never exceeds the budget."""
+    cost = lambda i, nq, k: 1000 * nq  # noqa: E731
+    budget = 120_000
+    ex = _FakeCtxExecutor(3, cost)
+    sched = Scheduler(cost, budget=budget, max_batch_queries=64)
+    srv = Server(sched, ex, n_workers=3)
+    g = np.random.Generator(np.random.PCG64(5))
+    reqs = [_req(i, "a" if i % 3 else "b", m=int(g.integers(1, 60)), t=0.0) for i in range(120)]
+    for r in reqs:
+        sched.submit(r)
+    sched.close()
+    srv.start()
+    srv.join()
+    assert len(srv.completed) == 120 and not srv.errors
+    assert max(ex.samples) <= budget
+    assert sched.peak_inflight <= budget
+    assert sched.busy == 0
+    # what the scheduler still charges is what the contexts keep
+    assert sched.inflight == sum(ex.res)
+    # a worker above its share (budget / 3) trims after its batch
+    assert all(r <= budget // 3 for r in ex.res)
