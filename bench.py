@@ -5,9 +5,13 @@ transform, coarse probing, work decomposition, threshold seeding, pruned scan,
 merge with canonical rescoring), inputs already resident in HBM.  Prints one
 JSON line.
 
-Workload (default): IVFFlat exact-at-probe, N = 1,000,000 vectors, d = 960,
-1,024-cluster Gaussian mixture, k-means nlist = 1024, nprobe = 32, 1,000
-queries, k = 10, 16 levels x 60 dims, eps = 1.
+Workload (default, the largest single-GPU configuration): batched IVFFlat,
+N = 10,000,000 vectors, d = 128, 4,096-cluster Gaussian mixture with Zipf(1.1)
+cluster sizes, k-means nlist = 4096, nprobe drawn per query uniformly in
+[8, 128], 10,000 queries, k = 10, eps = 1, level width from the tuner's cache
+(16 by default).  The GIST-shaped IVF workload (1M x 960, nprobe 32) and the
+flat SIFT-shaped one (100k x 128) follow as secondary entries, each with its
+own brute-force comparison, parity sample and roofline figures.
 """
 from __future__ import annotations
 
@@ -15,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -24,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+METRIC = "QPS at exact recall@10 (eps=1) vs same-GPU brute-force scan; HBM GB/s"
 
 
 def log(*a):
@@ -51,20 +57,322 @@ def traffic_from_profiles(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+class Run:
+    """One workload on the GPU: data, index, tuned parameters."""
+
+    def __init__(self, name, args, ctx):
+        import torch
+        from paper_2510_00566_amd import autotune, synth
+        from paper_2510_00566_amd.index import Params, ivf_assign
+
+        self.args = args
+        self.ctx = ctx
+        w = synth.WORKLOADS[name]
+        if args.scale != 1.0:
+            w = synth.scaled(w, n=int(w.n * args.scale), nq=w.nq)
+        self.store = args.store
+        npv = w.nprobe_range[1] if w.nprobe_range else w.nprobe
+        self.sig = autotune.signature("gfx950", w.d, self.store, w.n, npv, w.k)
+        prm, width = autotune.lookup(self.sig)
+        if width:
+            w.level_width = int(width)
+        self.w = w
+        t0 = time.time()
+        data = synth.generate(w)
+        self.data = data
+        self.x, self.q = data["x"], data["q"]
+        log(f"[bench] generated {w.name}: x {self.x.shape} q {self.q.shape} in {time.time() - t0:.1f}s")
+        self.xd = torch.from_numpy(self.x).cuda()
+        self.qd = torch.from_numpy(self.q).cuda()
+        self.np_max = int(w.nprobe_range[1]) if w.nprobe_range is not None else 0
+        self.npd = torch.from_numpy(data["nprobe"]).cuda() if w.nprobe_range is not None else w.nprobe
+        t0 = time.time()
+        self.cent, self.assign = ivf_assign(ctx, self.xd, w.nlist, iters=10 if w.nlist > 1 else 0, seed=w.cfg_id)
+        torch.cuda.synchronize()
+        log(f"[bench] k-means nlist={w.nlist} in {time.time() - t0:.1f}s")
+        self.c_np, self.a_np = self.cent.cpu().numpy(), self.assign.cpu().numpy()
+        self.transform_kind = args.transform if w.nlist > 1 else "data"
+        self.tf = self.fit_transform(self.transform_kind)
+        self.idx = self.build(self.tf, w.level_width)
+        self.use_bf16 = 1 if self.store == "bf16" else 0
+        if args.tune:
+            prm = self.tune()
+        self.prm = prm if prm is not None else Params()
+        self.prm.use_bf16 = self.use_bf16
+        log(f"[bench] {w.name} search params {self.prm}")
+        self.ids = torch.empty((w.nq, w.k), dtype=torch.int64, device="cuda")
+        self.dists = torch.empty((w.nq, w.k), dtype=torch.float32, device="cuda")
+
+    def fit_transform(self, kind):
+        from paper_2510_00566_amd.index import Transform
+        w = self.w
+        t1 = time.time()
+        if kind == "residual" and w.nlist > 1:
+            # PCA of the within-list residuals x - c(x): the covariance that
+            # governs the distances refined inside probed lists
+            rows = np.random.Generator(np.random.PCG64(w.cfg_id)).choice(w.n, min(w.n, 131072), replace=False)
+            tf_ = Transform.fit(self.x[rows] - self.c_np[self.a_np[rows]], fit_sample=0, seed=w.cfg_id)
+        else:
+            tf_ = Transform.fit(self.x, fit_sample=min(w.n, 131072), seed=w.cfg_id)
+        log(f"[bench] PCA fit ({kind}) in {time.time() - t1:.1f}s, alpha {tf_.get()[3]:.2f}")
+        return tf_
+
+    def cuts(self, width):
+        d = self.w.d
+        return np.asarray(list(range(0, d, width)) + [d], dtype=np.int32)
+
+    def build(self, tf, width):
+        import torch
+        from paper_2510_00566_amd.index import Index
+        t0 = time.time()
+        idx = Index.build(self.ctx, tf, self.xd, self.cent, self.assign, self.cuts(width), store=self.store)
+        torch.cuda.synchronize()
+        info = idx.info()
+        log(f"[bench] index built in {time.time() - t0:.1f}s: width {width}, {info['nblocks']} blocks, "
+            f"levels {info['bytes_levels'] / 1e9:.2f} GB")
+        return idx
+
+    def tune(self):
+        """Level width (a build-time knob: one index per width) and the search
+        knobs, stored in the tuner's cache."""
+        from paper_2510_00566_amd import autotune
+        w = self.w
+        widths = (8, 16, 32) if w.d <= 256 else (w.level_width,)
+        self.idx.free()
+        best, prm, results = autotune.tune_level_width(lambda wd: self.build(self.tf, wd), self.qd, w.k, self.npd,
+                                                       widths=widths, log=log, nprobe_max=self.np_max,
+                                                       use_bf16=self.use_bf16)
+        autotune.store(self.sig, prm, best, results[best][1])
+        w.level_width = best
+        self.idx = self.build(self.tf, best)
+        return prm
+
+    def search(self, idx=None, prm=None, out=None, **kw):
+        idx = idx or self.idx
+        return idx.search(self.qd, self.w.k, nprobe=self.npd, eps=1.0, params=prm or self.prm,
+                          out=out or (self.ids, self.dists), nprobe_max=self.np_max, **kw)
+
+    def time_steps(self, fn, steps, warmup):
+        import torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = t0
+        for i in range(steps):
+            fn()
+            now = time.perf_counter()
+            if now - last > 30.0:  # progress on very slow configurations only
+                log(f"[bench] step {i + 1}/{steps} at {now - t0:.1f}s")
+                last = now
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def kernel_figures(self, steps):
+        """The dominant kernel's bytes (counting instance, one search) and its
+        average duration from HIP events the library records on the stream
+        the kernel runs on (uncounted instance, as many searches as timed)."""
+        self.search(stats=True)
+        st = dict(self.idx.stats())
+        scan_ms, phases = [], []
+        for _ in range(steps):
+            self.search(timing=True)
+            stt = self.idx.stats()
+            scan_ms.append(stt["ms_scan"])
+            phases.append((stt["ms_prep"], stt["ms_scan"], stt["ms_merge"], stt["ms_total"]))
+        return st, float(np.mean(scan_ms)), phases
+
+    def bruteforce(self, ref_ids, ref_d):
+        """Same probe lists, tiles and work decomposition, no bounds: the
+        faster of the pruned scan's decomposition and the library defaults."""
+        import torch
+        from paper_2510_00566_amd.index import Params
+        w = self.w
+        bi, bd = torch.empty_like(self.ids), torch.empty_like(self.dists)
+        best = None
+        for tag, bprm in (("same-decomposition", self.prm), ("default", Params())):
+            bprm = Params(**vars(bprm))
+            bprm.use_bf16 = 0
+            bsteps = max(3, self.args.steps // 4)
+            el = self.time_steps(lambda: self.idx.search_bruteforce(self.qd, w.k, nprobe=self.npd, params=bprm,
+                                                                    out=(bi, bd), nprobe_max=self.np_max),
+                                 bsteps, max(1, self.args.warmup))
+            rec = {"qps": w.nq * bsteps / el, "ms_per_step": el * 1000 / bsteps, "params": tag,
+                   "same_result": bool(torch.equal(bi, ref_ids) and torch.equal(bd, ref_d))}
+            self.idx.search_bruteforce(self.qd, w.k, nprobe=self.npd, params=bprm, out=(bi, bd), stats=True,
+                                       nprobe_max=self.np_max)
+            sb = self.idx.stats()
+            rec["scan_ms"] = None
+            rec["scan_bytes"] = float(sb["scan_bytes"])
+            log(f"[bench] brute force {rec}")
+            if best is None or rec["qps"] > best["qps"]:
+                best = rec
+        return best
+
+    def parity(self, n):
+        from oracle import brute
+        w = self.w
+        rs = np.random.Generator(np.random.PCG64(12345))
+        sample = np.sort(rs.choice(w.nq, size=min(n, w.nq), replace=False))
+        npv = self.data["nprobe"][sample] if w.nprobe_range is not None else w.nprobe
+        if w.nlist == 1:
+            ri, rd = brute.knn_flat(self.q[sample], self.x, w.k)
+        else:
+            ri, rd, _ = brute.knn_ivf(self.q[sample], self.x, self.c_np, self.a_np, npv, w.k)
+        gi, gd = self.ids.cpu().numpy()[sample], self.dists.cpu().numpy()[sample]
+        fin = np.isfinite(rd)
+        rel = np.abs(gd[fin].astype(np.float64) - rd[fin]) / np.maximum(rd[fin], 1e-30)
+        rec = {"queries": int(sample.size), "id_mismatch_queries": int((gi != ri).any(axis=1).sum()),
+               "max_rel_dist_err": float(rel.max()) if rel.size else 0.0}
+        log(f"[bench] parity {rec}")
+        return rec
+
+    def cpu_baseline(self, sample_n, single_n):
+        """The C oracle on the host cores: its serial pruned scan (Algorithm 1,
+        FP64 levels, B = 1024) with OpenMP over the sampled queries on all
+        cores and on one thread, and its FP64 brute force over the same
+        candidates; median of three runs each."""
+        from oracle import c_oracle
+        w = self.w
+        c_oracle.build(force=False)
+        nthreads = len(os.sched_getaffinity(0))
+        rs = np.random.Generator(np.random.PCG64(777))
+        sample = np.sort(rs.choice(w.nq, size=min(sample_n, w.nq), replace=False))
+        mu64, t64, _, _ = self.tf.get()
+        npv = self.data["nprobe"][sample] if w.nprobe_range is not None else w.nprobe
+        probes = c_oracle.probe(self.q[sample], self.c_np, npv, threads=nthreads) if w.nlist > 1 else \
+            [np.zeros(1, np.int64) for _ in sample]
+        members = c_oracle.list_members(self.a_np, w.nlist)
+        off, cand = c_oracle.candidates_csr(probes, members)
+        rows = np.unique(cand)
+        remap = np.full(w.n, -1, dtype=np.int64)
+        remap[rows] = np.arange(rows.size)
+        m = self.cuts(w.level_width)
+        xs_sub = np.ascontiguousarray(self.x[rows])
+        # build step of the CPU scan (not timed): FP64 rotated rows and tails
+        ys, R = c_oracle.prepare(xs_sub, mu64, t64, m, threads=nthreads)
+        cand_local = remap[cand]
+        qs = self.q[sample]
+
+        def timed(fn, reps=3):
+            ts = []
+            out = None
+            for _ in range(reps):
+                t1 = time.perf_counter()
+                out = fn()
+                ts.append(time.perf_counter() - t1)
+            return statistics.median(ts), out
+
+        tp, (ci, cd, dims) = timed(lambda: c_oracle.panorama(qs, xs_sub, ys, R, mu64, t64, m, off, cand_local,
+                                                             w.k, batch=1024, eps=1.0, threads=nthreads))
+        ns = min(single_n, sample.size)
+        off1 = off[: ns + 1]
+        t1s, _ = timed(lambda: c_oracle.panorama(qs[:ns], xs_sub, ys, R, mu64, t64, m, off1,
+                                                 cand_local[: off1[-1]], w.k, batch=1024, eps=1.0, threads=1))
+        tb, (bi, _) = timed(lambda: c_oracle.knn_lists(qs, xs_sub, off, cand_local, w.k, threads=nthreads))
+        rec = {"value": float(sample.size / tp), "unit": "queries/s", "cores": int(nthreads), "kind": "oracle",
+               "sample": f"{sample.size} of {w.nq} queries (single thread: {ns}); plain C serial pruned scan "
+                         f"(Algorithm 1, FP64 levels, B=1024) with OpenMP over queries, median of 3; FP64 "
+                         f"rotated rows built outside the timed region",
+               "single_thread_qps": float(ns / t1s),
+               "bruteforce_qps": float(sample.size / tb),
+               "same_ids_as_bruteforce": bool(np.array_equal(ci, bi)),
+               "phi": float(dims.sum() / max(1, off[-1] * w.d))}
+        log(f"[bench] cpu baseline {rec}")
+        return rec
+
+    def data_fit(self, ref_qps, bf_qps):
+        """The same search with the PCA fitted on the raw data (Section 4.1's
+        fit) instead of the list residuals."""
+        import torch
+        w = self.w
+        tf2 = self.fit_transform("data")
+        idx2 = self.build(tf2, w.level_width)
+        fi, fd = torch.empty_like(self.ids), torch.empty_like(self.dists)
+        el = self.time_steps(lambda: self.search(idx=idx2, out=(fi, fd)), self.args.steps, self.args.warmup)
+        self.search(idx=idx2, out=(fi, fd), stats=True)
+        st2 = idx2.stats()
+        qps = w.nq * self.args.steps / el
+        rec = {"transform": "pca_fit_on_data", "qps": qps, "ms_per_step": el * 1000 / self.args.steps,
+               "alpha": tf2.get()[3], "phi": st2["dims_read"] / max(1, st2["candidates"] * w.d),
+               "speedup_vs_bruteforce": qps / bf_qps if bf_qps else None,
+               "same_result": bool(torch.equal(fi, self.ids) and torch.equal(fd, self.dists))}
+        log(f"[bench] data-fit PCA {rec}")
+        idx2.free()
+        return rec
+
+    def free(self):
+        import torch
+        self.idx.free()
+        del self.xd, self.qd
+        torch.cuda.empty_cache()
+
+
+def measure(run: Run, args, primary: bool) -> dict:
+    """Every figure of one workload's entry."""
+    import torch
+    w = run.w
+    elapsed = run.time_steps(lambda: run.search(eager=args.eager), args.steps, args.warmup)
+    ms_per_step = elapsed * 1000.0 / args.steps
+    qps = w.nq * args.steps / elapsed
+    log(f"[bench] {w.name}: timed {args.steps} steps in {elapsed:.3f}s ({qps:.0f} QPS)")
+    res = {"qps": qps, "ms_per_step": ms_per_step}
+    if args.profile_only:
+        return res
+    ids_ref, d_ref = run.ids.clone(), run.dists.clone()
+    st, scan_ms, phases = run.kernel_figures(args.steps)
+    phi = st["dims_read"] / max(1, st["candidates"] * w.d)
+    bf = None if args.no_bruteforce else run.bruteforce(ids_ref, d_ref)
+    run.ids.copy_(ids_ref)
+    run.dists.copy_(d_ref)
+    kernel = "k_scan_pruned_bf16" if run.use_bf16 else "k_scan_pruned"
+    achieved = (st["scan_bytes"] / 1e9) / (scan_ms / 1e3)
+    res.update({
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "nq": w.nq, "k": w.k, "nlist": w.nlist,
+                   "nprobe": (list(w.nprobe_range) if w.nprobe_range else w.nprobe), "levels": w.L,
+                   "level_width": w.level_width, "eps": 1.0, "store": run.store,
+                   "transform": "pca_fit_on_list_residuals" if run.transform_kind == "residual" else "pca_fit_on_data",
+                   "search_params": {k_: v_ for k_, v_ in vars(run.prm).items()}},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_from_profiles(kernel, w.name),
+                     "kernel": kernel, "bytes_per_launch": float(st["scan_bytes"]), "ms_per_launch": scan_ms},
+        "bruteforce": bf,
+        "speedup_vs_bruteforce": (qps / bf["qps"]) if bf else None,
+        "phi": phi,
+        "alpha": run.tf.get()[3],
+        "level_reads": [int(v) for v in st["level_reads"][:w.L]],
+        "candidates": int(st["candidates"]),
+        "ms_breakdown": dict(zip(("prep", "scan", "merge", "total_device"),
+                                 (float(v) for v in np.median(np.asarray(phases), axis=0)))),
+        "fallback_queries": st["fallback_queries"],
+    })
+    if args.parity_sample > 0:
+        res["parity"] = run.parity(args.parity_sample)
+    if not args.no_secondary and w.nlist > 1 and run.transform_kind == "residual":
+        res["data_fit"] = run.data_fit(qps, bf["qps"] if bf else None)
+    if primary and not args.no_cpu_baseline:
+        res["cpu_baseline"] = run.cpu_baseline(args.cpu_sample, args.cpu_single)
+    torch.cuda.synchronize()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ivf_gist_like")
+    ap.add_argument("--workload", default="ivf_zipf_batched")
+    ap.add_argument("--secondary-workloads", default="ivf_gist_like,flat_sift_like",
+                    help="comma-separated workloads measured after the primary one ('' for none)")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of N (smoke runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bruteforce", action="store_true")
     ap.add_argument("--parity-sample", type=int, default=16)
-    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-single", type=int, default=8, help="queries of the single-thread CPU run")
     ap.add_argument("--profile-only", action="store_true", help="warm up and run the timed steps only")
     ap.add_argument("--transform", default="residual", choices=["residual", "data"])
-    ap.add_argument("--tune", action="store_true", help="run the autotuner and store its choice")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner (level width and search knobs)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the data-fit PCA comparison")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no graph replay)")
     ap.add_argument("--store", default="f32", choices=["f32", "bf16"],
@@ -86,273 +394,42 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}))
         return
-    from paper_2510_00566_amd import synth
-    from paper_2510_00566_amd import autotune
-    from paper_2510_00566_amd.index import Context, Index, Params, Transform, ivf_assign
-
-    w = synth.WORKLOADS[args.workload]
-    if args.scale != 1.0:
-        w = synth.scaled(w, n=int(w.n * args.scale), nq=w.nq)
-    t0 = time.time()
-    data = synth.generate(w)
-    x, q = data["x"], data["q"]
-    log(f"[bench] generated {w.name}: x {x.shape} q {q.shape} in {time.time() - t0:.1f}s")
+    from paper_2510_00566_amd.index import Context
 
     ctx = Context(0)
-    xd = torch.from_numpy(x).cuda()
-    qd = torch.from_numpy(q).cuda()
-    npd = torch.from_numpy(data["nprobe"]).cuda() if w.nprobe_range is not None else w.nprobe
-    t0 = time.time()
-    cent, assign = ivf_assign(ctx, xd, w.nlist, iters=10 if w.nlist > 1 else 0, seed=w.cfg_id)
-    torch.cuda.synchronize()
-    log(f"[bench] k-means nlist={w.nlist} in {time.time() - t0:.1f}s")
-    c_np, a_np = cent.cpu().numpy(), assign.cpu().numpy()
-
-    def fit_transform(kind):
-        t1 = time.time()
-        if kind == "residual" and w.nlist > 1:
-            # PCA of the within-list residuals x - c(x): the covariance that
-            # governs the distances refined inside probed lists
-            rows = np.random.Generator(np.random.PCG64(w.cfg_id)).choice(w.n, min(w.n, 131072), replace=False)
-            tf_ = Transform.fit(x[rows] - c_np[a_np[rows]], fit_sample=0, seed=w.cfg_id)
-        else:
-            tf_ = Transform.fit(x, fit_sample=min(w.n, 131072), seed=w.cfg_id)
-        log(f"[bench] PCA fit ({kind}) in {time.time() - t1:.1f}s, alpha {tf_.get()[3]:.2f}")
-        return tf_
-
-    tf = fit_transform(args.transform)
-    t0 = time.time()
-    idx = Index.build(ctx, tf, xd, cent, assign, w.level_cuts(), store=args.store)
-    torch.cuda.synchronize()
-    info = idx.info()
-    log(f"[bench] index built in {time.time() - t0:.1f}s: {info['nblocks']} blocks, "
-        f"levels {info['bytes_levels'] / 1e9:.2f} GB")
-
-    use_bf16 = 1 if args.store == "bf16" else 0
-    sig = autotune.signature("gfx950", w.d, args.store, w.n, w.nprobe_range[1] if w.nprobe_range else w.nprobe, w.k)
-    prm, _ = autotune.lookup(sig)
-    if args.tune or prm is None:
-        if args.tune:
-            prm, tbest = autotune.tune_search(idx, qd, w.k, npd, log=log, use_bf16=use_bf16)
-            autotune.store(sig, prm, w.level_width, tbest)
-        else:
-            prm = Params()
-    prm.use_bf16 = use_bf16
-    log(f"[bench] search params {prm}")
-    ids = torch.empty((w.nq, w.k), dtype=torch.int64, device="cuda")
-    dists = torch.empty((w.nq, w.k), dtype=torch.float32, device="cuda")
-
-    def step(stats=False, timing=False):
-        idx.search(qd, w.k, nprobe=npd, eps=1.0, params=prm, stats=stats, out=(ids, dists), eager=args.eager,
-                   timing=timing)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    step(stats=True)
-    st0 = idx.stats()
-    log(f"[bench] warmup done; one eager search {1e3 * (time.perf_counter() - t1):.1f} ms, "
-        f"scan {st0['ms_scan']:.2f} ms, fallback queries {st0['fallback_queries']}")
-    # ---- timed region: K whole searches (the search sequence is captured
-    # once into a HIP graph and replayed)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    last = t0
-    for i in range(args.steps):
-        step()
-        now = time.perf_counter()
-        if now - last > 30.0:  # progress on very slow configurations only
-            log(f"[bench] step {i + 1}/{args.steps} at {now - t0:.1f}s")
-            last = now
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"[bench] timed {args.steps} steps in {elapsed:.3f}s")
-    ms_per_step = elapsed * 1000.0 / args.steps
-    qps = w.nq * args.steps / elapsed
+    run = Run(args.workload, args, ctx)
+    prim = measure(run, args, primary=True)
+    w = run.w
     if args.profile_only:
-        print(json.dumps({"profile_only": True, "qps": qps, "ms_per_step": ms_per_step}))
+        print(json.dumps({"profile_only": True, "workload": w.name, **prim}))
         return
-    # ---- the dominant kernel: its bytes from the counting instance (one
-    # search), its duration from HIP events recorded by the library around the
-    # uncounted kernel on the stream it runs on, over the same number of
-    # searches as the timed region
-    step(stats=True)
-    st = idx.stats()
-    scan_bytes = [st["scan_bytes"]]
-    counted = dict(st)
-    scan_ms, phases = [], []
-    for _ in range(args.steps):
-        step(timing=True)
-        stt = idx.stats()
-        scan_ms.append(stt["ms_scan"])
-        phases.append((stt["ms_prep"], stt["ms_scan"], stt["ms_merge"], stt["ms_total"]))
-    st = counted
-    phi = st["dims_read"] / max(1, st["candidates"] * w.d)
+    run.free()
+    del run
+    secondaries = []
+    for name in [s for s in args.secondary_workloads.split(",") if s and s != args.workload]:
+        r2 = Run(name, args, ctx)
+        rec = measure(r2, args, primary=False)
+        rec["workload"] = name
+        secondaries.append(rec)
+        r2.free()
+        del r2
 
-    # ---- same-GPU brute force over the same probe lists and work decomposition
-    bf = None
-    if not args.no_bruteforce:
-        bi = torch.empty_like(ids)
-        bd = torch.empty_like(dists)
-        best = None
-        # the faster of the brute-force scan with the pruned scan's work
-        # decomposition and with the library defaults
-        for tag, bprm in (("same-decomposition", prm), ("default", Params())):
-            for _ in range(max(1, args.warmup)):
-                idx.search_bruteforce(qd, w.k, nprobe=npd, params=bprm, out=(bi, bd))
-            torch.cuda.synchronize()
-            bsteps = max(3, args.steps // 4)
-            t1 = time.perf_counter()
-            for _ in range(bsteps):
-                idx.search_bruteforce(qd, w.k, nprobe=npd, params=bprm, out=(bi, bd))
-            torch.cuda.synchronize()
-            bel = time.perf_counter() - t1
-            rec = {"qps": w.nq * bsteps / bel, "ms_per_step": bel * 1000 / bsteps, "params": tag,
-                   "same_result": bool(torch.equal(bi, ids) and torch.equal(bd, dists))}
-            log(f"[bench] brute force {rec}")
-            if best is None or rec["qps"] > best["qps"]:
-                best = rec
-        bf = best
-
-    # ---- bfloat16 scan against the FP32 scan of the same index
-    precision = None
-    if use_bf16:
-        fi = torch.empty_like(ids)
-        fd = torch.empty_like(dists)
-        p32 = Params(**{k_: v_ for k_, v_ in vars(prm).items()})
-        p32.use_bf16 = 0
-        for _ in range(max(1, args.warmup)):
-            idx.search(qd, w.k, nprobe=npd, params=p32, out=(fi, fd))
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            idx.search(qd, w.k, nprobe=npd, params=p32, out=(fi, fd))
-        torch.cuda.synchronize()
-        el32 = time.perf_counter() - t1
-        idx.search(qd, w.k, nprobe=npd, params=p32, stats=True, out=(fi, fd))
-        st32 = dict(idx.stats())
-        idx.search(qd, w.k, nprobe=npd, params=p32, timing=True, out=(fi, fd))
-        st32["ms_scan"] = idx.stats()["ms_scan"]
-        precision = {"f32_qps": w.nq * args.steps / el32, "f32_ms_per_step": el32 * 1000 / args.steps,
-                     "bf16_qps": qps, "same_result_as_f32": bool(torch.equal(fi, ids) and torch.equal(fd, dists)),
-                     "f32_scan_ms": st32["ms_scan"], "f32_scan_bytes": st32["scan_bytes"],
-                     "bf16_scan_ms": float(np.mean(scan_ms)), "bf16_scan_bytes": float(np.mean(scan_bytes))}
-        log(f"[bench] precision {precision}")
-
-    # ---- sampled parity against the oracle at full size
-    parity = None
-    if args.parity_sample > 0:
-        from oracle import brute
-        rs = np.random.Generator(np.random.PCG64(12345))
-        sample = np.sort(rs.choice(w.nq, size=min(args.parity_sample, w.nq), replace=False))
-        npv = data["nprobe"][sample] if w.nprobe_range is not None else w.nprobe
-        if w.nlist == 1:
-            ri, rd = brute.knn_flat(q[sample], x, w.k)
-        else:
-            ri, rd, _ = brute.knn_ivf(q[sample], x, c_np, a_np, npv, w.k)
-        gi, gd = ids.cpu().numpy()[sample], dists.cpu().numpy()[sample]
-        fin = np.isfinite(rd)
-        rel = np.abs(gd[fin].astype(np.float64) - rd[fin]) / np.maximum(rd[fin], 1e-30)
-        parity = {"queries": int(sample.size), "id_mismatch_queries": int((gi != ri).any(axis=1).sum()),
-                  "max_rel_dist_err": float(rel.max()) if rel.size else 0.0}
-        log(f"[bench] parity {parity}")
-
-    # ---- CPU baseline: the C oracle's serial pruned scan on a query sample
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import c_oracle
-        c_oracle.build(force=False)
-        nthreads = len(os.sched_getaffinity(0))
-        rs = np.random.Generator(np.random.PCG64(777))
-        sample = np.sort(rs.choice(w.nq, size=min(args.cpu_sample, w.nq), replace=False))
-        mu64, t64, _, _ = tf.get()
-        npv = data["nprobe"][sample] if w.nprobe_range is not None else w.nprobe
-        probes = c_oracle.probe(q[sample], c_np, npv, threads=nthreads) if w.nlist > 1 else \
-            [np.zeros(1, np.int64) for _ in sample]
-        members = c_oracle.list_members(a_np, w.nlist)
-        off, cand = c_oracle.candidates_csr(probes, members)
-        rows = np.unique(cand)
-        # build step of the CPU scan (not timed): FP64 rotated rows and tails
-        ys = np.zeros((1, w.d))
-        R = np.zeros((1, w.L + 1))
-        remap = np.full(w.n, -1, dtype=np.int64)
-        remap[rows] = np.arange(rows.size)
-        ys = (x[rows].astype(np.float64) - mu64) @ t64.T
-        m = w.level_cuts()
-        sq = ys * ys
-        R = np.stack([sq[:, m[l]:].sum(axis=1) for l in range(len(m))], axis=1)
-        xs_sub = np.ascontiguousarray(x[rows])
-        cand_local = remap[cand]
-        t1 = time.perf_counter()
-        ci, cd, dims = c_oracle.panorama(q[sample], xs_sub, ys, R, mu64, t64, m, off, cand_local, w.k,
-                                         batch=1024, eps=1.0, threads=nthreads)
-        cel = time.perf_counter() - t1
-        cpu = {"value": float(sample.size / cel), "unit": "queries/s", "cores": int(nthreads), "kind": "oracle",
-               "sample": f"{sample.size} of {w.nq} queries, plain C serial pruned scan (Algorithm 1, FP64, "
-                         f"B=1024) with OpenMP over queries; build of FP64 rotated rows not timed",
-               "phi": float(dims.sum() / max(1, (off[-1]) * w.d))}
-        log(f"[bench] cpu baseline {cpu}")
-
-    # ---- secondary: the same search with the PCA fitted on the raw data
-    secondary = None
-    if not args.no_secondary and w.nlist > 1 and args.transform == "residual":
-        tf2 = fit_transform("data")
-        idx2 = Index.build(ctx, tf2, xd, cent, assign, w.level_cuts())
-        for _ in range(args.warmup):
-            idx2.search(qd, w.k, nprobe=npd, params=prm, out=(ids, dists))
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            idx2.search(qd, w.k, nprobe=npd, params=prm, out=(ids, dists))
-        torch.cuda.synchronize()
-        el2 = time.perf_counter() - t1
-        idx2.search(qd, w.k, nprobe=npd, params=prm, stats=True, out=(ids, dists))
-        st2 = idx2.stats()
-        secondary = {"transform": "pca_fit_on_data", "qps": w.nq * args.steps / el2,
-                     "ms_per_step": el2 * 1000 / args.steps, "alpha": tf2.get()[3],
-                     "phi": st2["dims_read"] / max(1, st2["candidates"] * w.d),
-                     "speedup_vs_bruteforce": (w.nq * args.steps / el2) / bf["qps"] if bf else None}
-        log(f"[bench] secondary {secondary}")
-        idx2.free()
-
-    achieved = (np.mean(scan_bytes) / 1e9) / (np.mean(scan_ms) / 1e3)
-    kernel = "k_scan_pruned_bf16" if use_bf16 else "k_scan_pruned"
     out = {
-        "metric": f"QPS at exact recall@{w.k} (eps=1) vs same-GPU brute-force scan; HBM GB/s",
-        "value": qps,
+        "metric": METRIC,
+        "value": prim["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": prim["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if use_bf16 else "f32",
+        "dtype": "bf16" if args.store == "bf16" else "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "d": w.d, "nq": w.nq, "k": w.k, "nlist": w.nlist,
-                   "nprobe": (list(w.nprobe_range) if w.nprobe_range else w.nprobe), "levels": w.L,
-                   "level_width": w.level_width, "eps": 1.0, "store": args.store,
-                   "transform": "pca_fit_on_list_residuals" if (args.transform == "residual" and w.nlist > 1)
-                   else "pca_fit_on_data", "search_params": {k_: v_ for k_, v_ in vars(prm).items()}},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_from_profiles(kernel, w.name),
-                     "kernel": kernel,
-                     "bytes_per_launch": float(np.mean(scan_bytes)),
-                     "ms_per_launch": float(np.mean(scan_ms))},
-        "cpu_baseline": cpu,
-        "bruteforce": bf,
-        "speedup_vs_bruteforce": (qps / bf["qps"]) if bf else None,
-        "phi": phi,
-        "alpha": tf.get()[3],
-        "parity": parity,
-        "ms_breakdown": dict(zip(("prep", "scan", "merge", "total_device"),
-                                 (float(v) for v in np.median(np.asarray(phases), axis=0)))),
-        "fallback_queries": st["fallback_queries"],
-        "secondary": secondary,
-        "precision": precision,
     }
+    out.update({k_: v_ for k_, v_ in prim.items() if k_ not in ("qps", "ms_per_step")})
+    out["secondary_workloads"] = secondaries
     print(json.dumps(out))
 
 

@@ -54,9 +54,9 @@ def _time(fn, reps: int) -> float:
 
 
 def tune_search(idx, q_dev, k: int, nprobe, reps: int = 5, space: dict | None = None, log=None,
-                use_bf16: int = 0) -> tuple[Params, float]:
+                use_bf16: int = 0, nprobe_max: int = 0) -> tuple[Params, float]:
     """Coordinate-wise sweep of the search knobs; returns the best Params and
-    its time per search (seconds)."""
+    its time per search (seconds).  nprobe_max bounds per-query probe counts."""
     space = space or SEARCH_SPACE
     best = Params()
     cur = {"scan_mode": 0, "blocks_per_item": 1, "group": 16, "seed": (512, 32), "dense_min": 64}
@@ -68,7 +68,7 @@ def tune_search(idx, q_dev, k: int, nprobe, reps: int = 5, space: dict | None = 
 
     def run(cfg):
         p = mk(cfg)
-        return _time(lambda: idx.search(q_dev, k, nprobe=nprobe, params=p), reps)
+        return _time(lambda: idx.search(q_dev, k, nprobe=nprobe, params=p, nprobe_max=nprobe_max), reps)
 
     best_t = run(cur)
     for _ in range(2):  # two passes of coordinate descent
@@ -87,13 +87,14 @@ def tune_search(idx, q_dev, k: int, nprobe, reps: int = 5, space: dict | None = 
     return best, best_t
 
 
-def tune_level_width(build_index, q_dev, k: int, nprobe, widths=(8, 16, 32), reps: int = 5, log=None):
+def tune_level_width(build_index, q_dev, k: int, nprobe, widths=(8, 16, 32), reps: int = 5, log=None,
+                     nprobe_max: int = 0, use_bf16: int = 0):
     """Build one index per level width (build_index(width) -> Index) and keep
     the width whose tuned search is fastest."""
     results = {}
     for wdt in widths:
         idx = build_index(wdt)
-        p, t = tune_search(idx, q_dev, k, nprobe, reps=reps, log=log)
+        p, t = tune_search(idx, q_dev, k, nprobe, reps=reps, log=log, nprobe_max=nprobe_max, use_bf16=use_bf16)
         results[wdt] = (p, t)
         if log:
             log(f"[autotune] width {wdt}: {t * 1e3:.3f} ms with {p}")

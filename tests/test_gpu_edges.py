@@ -200,6 +200,17 @@ def test_zipf_lists_per_query_nprobe(torch_cuda):
     ids, _, st = _run(torch_cuda, case, w, data["q"], nprobe=npq)
     _log("zipf stats", {k: st[k] for k in ("candidates", "dims_read", "fallback_queries")})
     assert st["fallback_queries"] == 0
+    # a positive nprobe_all bounds the per-query counts (larger ones are
+    # clamped to it): the oracle gets the clamped counts
+    from tests import gpu_cases as gc
+    qd = torch_cuda.from_numpy(data["q"]).cuda()
+    npd = torch_cuda.from_numpy(npq).cuda()
+    for cap in (16, 64):
+        ids, dd = case["idx"].search(qd, w.k, nprobe=npd, nprobe_max=cap)
+        ref_i, ref_d = gc.oracle_answer(case, data["q"], np.minimum(npq, cap), w.k)
+        gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
+        bi, bd = case["idx"].search_bruteforce(qd, w.k, nprobe=npd, nprobe_max=cap)
+        gc.compare(bi.cpu().numpy(), bd.cpu().numpy(), ref_i, ref_d)
 
 
 @gpu

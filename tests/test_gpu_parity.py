@@ -186,3 +186,29 @@ def test_search_ordered_after_callers_stream(torch_cuda):
             qd.copy_(host[j], non_blocking=True)
             ids, dd = case["idx"].search(qd, w.k, nprobe=w.nprobe, stream=st)
         gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), *refs[j])
+
+
+@gpu
+def test_flat_full_size_config(torch_cuda):
+    """The flat configuration at full size: N = 100,000, d = 128 (spectrum
+    j^-1.2), 8 levels of 16, all 100 queries, k = 10; ids bit-exact against
+    brute force (the C oracle's, pinned bit for bit to the numpy oracle)."""
+    from oracle import c_oracle
+    from tests import gpu_cases as gc
+    w = synth.WORKLOADS["flat_sift_like"]
+    _log("case flat full n=100000 d=128 nq=100 L=8 k=10")
+    case = gc.build_case(w)
+    q = case["data"]["q"]
+    qd = torch_cuda.from_numpy(q).cuda()
+    ids, dd = case["idx"].search(qd, w.k, nprobe=1, stats=True)
+    st = case["idx"].stats()
+    c_oracle.build(force=False)
+    n = case["x"].shape[0]
+    off = np.arange(q.shape[0] + 1, dtype=np.int64) * n
+    cand = np.tile(np.arange(n, dtype=np.int64), q.shape[0])
+    ref_i, ref_d = c_oracle.knn_lists(q, case["x"], off, cand, w.k, threads=16)
+    gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
+    assert st["fallback_queries"] == 0 and st["candidates"] == n * q.shape[0]
+    _log("phi", st["dims_read"] / (st["candidates"] * w.d))
+    bi, bd = case["idx"].search_bruteforce(qd, w.k, nprobe=1)
+    gc.compare(bi.cpu().numpy(), bd.cpu().numpy(), ref_i, ref_d)
