@@ -225,6 +225,26 @@ pano_status pano_search_ctx(pano_ctx *ctx, pano_index *idx, const float *q_dev, 
                             void *stream);
 
 /*
+ * search_noalloc: pano_search for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, semantics and results as pano_search without
+ * flags, but no call allocates: every scratch buffer of the search comes from
+ * a fixed device array of 64 MiB per GPU that the library reserves when it
+ * is loaded (set up on the first context created on that GPU, or on the first
+ * call) and keeps until the process ends; no graph is captured, every kernel
+ * runs on `stream` in order, and the call returns when the results are in
+ * ids_dev / dists_dev.  A search whose scratch (about nq x (nlist +
+ * 2 nprobe + d) x 4 bytes plus the per-query result buffers) exceeds the array
+ * fails with EINVAL and a message giving the bytes it needs; split the batch.
+ * Every call on one GPU shares that GPU's array and each call clears what it
+ * needs cleared: calls that overlap on one GPU (from several threads or
+ * streams) race and must be serialised by the caller.
+ */
+pano_status pano_search_noalloc(pano_index *idx, const float *q_dev, int64_t nq, int32_t k,
+                                const int32_t *nprobe_dev, int32_t nprobe_all, float eps, int64_t *ids_dev,
+                                float *dists_dev, const pano_search_params *params, void *stream);
+
+/*
  * search_scratch_bytes: device scratch memory (bytes) that a pano_search of
  * nq queries with this k, probe setting (per_query_nprobe != 0: a per-query
  * array bounded by nprobe_all, or by nlist if nprobe_all is 0; else

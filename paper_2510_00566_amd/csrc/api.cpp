@@ -134,6 +134,9 @@ pano_status pano_ctx_create(int device, pano_ctx **out)
         PANO_HIP(hipGetDeviceCount(&count));
         PANO_REQUIRE(device >= 0 && device < count, "device index out of range");
         PANO_HIP(hipSetDevice(device));
+        // set up this device's fixed scratch of the allocation-free search
+        // while the device is current
+        (void)fixed_scratch(device);
         auto *c = new pano_ctx();
         c->device = device;
         hipDeviceProp_t prop;
@@ -543,6 +546,23 @@ pano_status pano_search(pano_index *idx, const float *q_dev, int64_t nq, int32_t
     }
     return pano_search_ctx(idx->ctx, idx, q_dev, nq, k, nprobe_dev, nprobe_all, eps, ids_dev, dists_dev, params,
                            flags, stream);
+}
+
+pano_status pano_search_noalloc(pano_index *idx, const float *q_dev, int64_t nq, int32_t k,
+                                const int32_t *nprobe_dev, int32_t nprobe_all, float eps, int64_t *ids_dev,
+                                float *dists_dev, const pano_search_params *params, void *stream)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx && (nq == 0 || (q_dev && ids_dev && dists_dev)), "null argument");
+        PANO_REQUIRE(k >= 1 && nq >= 0, "need k >= 1 and nq >= 0");
+        PANO_REQUIRE(eps >= 0.f && eps <= 1.f, "eps must be in [0, 1]");
+        PANO_REQUIRE(nprobe_dev != nullptr || nprobe_all >= 1, "nprobe_all must be >= 1");
+        if (nq == 0) return;
+        PANO_HIP(hipSetDevice(idx->ctx->device));
+        void *fx = fixed_scratch(idx->ctx->device);
+        run_search(idx->ctx, idx, q_dev, nq, k, nprobe_dev, nprobe_all, eps, ids_dev, dists_dev, params, 0u, false,
+                   (hipStream_t)stream, fx, NOALLOC_SCRATCH_BYTES);
+    });
 }
 
 pano_status pano_search_scratch_bytes(const pano_index *idx, int64_t nq, int32_t k, int32_t per_query_nprobe,

@@ -13,6 +13,11 @@
 
 namespace pano {
 
+// Size of the fixed device scratch array of the allocation-free search (per
+// GPU), and the devices it is set up for.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int MAX_DEVICES = 64;
+
 // ---------------------------------------------------------------- errors
 void set_error(const std::string &msg);
 struct Error {
@@ -285,9 +290,18 @@ void launch_pack(const float *Y, const float *tails_row, const int64_t *perm, co
                  float *levels, uint16_t *levels_bf16, float *tails, int32_t *ids, int32_t *blk_cnt,
                  hipStream_t s);
 
+// fixed: when not null, every scratch buffer of the search is carved from
+// this device memory of fixed_bytes (the allocation-free entry point): no
+// allocation, no graph, every kernel on stream s.
 void run_search(pano_ctx *ctx, pano_index *idx, const float *q, int64_t nq, int k, const int32_t *nprobe_dev,
                 int nprobe_all, float eps, int64_t *ids, float *dists, const pano_search_params *prm,
-                uint32_t flags, bool brute, hipStream_t s);
+                uint32_t flags, bool brute, hipStream_t s, void *fixed = nullptr, size_t fixed_bytes = 0);
+// Bytes of fixed scratch a search needs (the allocation-free entry point).
+size_t search_fixed_bytes(const pano_index *ix, int64_t nq, int k, bool per_query_np, int nprobe_all,
+                          const pano_search_params *prm);
+// Device address of this device's fixed scratch array (set up on first use
+// with the device current).
+void *fixed_scratch(int device);
 size_t search_scratch_bytes(const pano_index *ix, int64_t nq, int k, bool per_query_np, int nprobe_all,
                             const pano_search_params *prm, bool brute);
 

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 namespace pano {
 
@@ -2048,6 +2049,30 @@ __global__ __launch_bounds__(NT) void k_fallback_select(const uint64_t *__restri
     }
 }
 
+// Slots of a query's probe set (the exact fallback's key count), for callers
+// that keep the probe list on the device.
+__global__ void k_probe_slots(const int32_t *__restrict__ lists, int nl, const int64_t *__restrict__ list_blk, int B,
+                              int64_t *__restrict__ total)
+{
+    __shared__ int64_t part[NT];
+    int64_t t = 0;
+    for (int i = threadIdx.x; i < nl; i += NT) t += (list_blk[lists[i] + 1] - list_blk[lists[i]]) * B;
+    part[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = part[0];
+}
+
+// ================================================================ fixed scratch
+// Device scratch of the allocation-free search: one array per GPU, in the
+// code object, held until the process ends.  Host code never uses its name
+// as an address: fixed_scratch() returns the device address that
+// hipGetSymbolAddress reports for the current device.
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
 // ================================================================ buffer clearing
 __global__ void k_fill_multi(FillList f)
 {
@@ -2065,6 +2090,24 @@ __global__ void k_fill_multi(FillList f)
 namespace pano {
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static std::mutex g_fixed_mu;
+static void *g_fixed_ptr[MAX_DEVICES];
+
+void *fixed_scratch(int device)
+{
+    PANO_REQUIRE(device >= 0 && device < MAX_DEVICES, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    if (!g_fixed_ptr[device]) {
+        // the address of this device's copy of the array (the caller has
+        // made `device` current)
+        void *p = nullptr;
+        PANO_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        PANO_REQUIRE(p != nullptr, "no device address for the fixed scratch");
+        g_fixed_ptr[device] = p;
+    }
+    return g_fixed_ptr[device];
+}
 
 // Carves consecutive sub-buffers out of one device allocation.
 struct Carver {
@@ -2233,9 +2276,65 @@ size_t search_scratch_bytes(const pano_index *ix, int64_t nq, int k, bool per_qu
     return t;
 }
 
+size_t search_fixed_bytes(const pano_index *ix, int64_t nq, int k, bool per_query_np, int nprobe_all,
+                          const pano_search_params *prm)
+{
+    SearchConsts c;
+    SearchPlan pl;
+    plan_search(ix, nq, k, per_query_np, nprobe_all, 1.f, prm, false, c, pl);
+    size_t t = align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(1, nq)) + align_up(sizeof(int64_t));
+    for (int i = 0; i < 7; ++i) t += pl.need[i];
+    return t;
+}
+
+// The allocation-free search after planning: every kernel on the caller's
+// stream s, then the per-query flag words read back through a buffer on the
+// stack, and the exact fallback for flagged queries with its keys in the
+// fixed scratch (fb_keys, fb_bytes) and its probe list read on the device.
+template <class Enqueue>
+static void run_fixed_tail(pano_index *ix, const float *q, int64_t nq, int k, int d, int np_max, int64_t *ids,
+                           float *dists, const int32_t *probes, const int32_t *npq, const int32_t *flags_dev,
+                           int64_t *fb_total, void *fb_keys, size_t fb_bytes, hipStream_t s, Enqueue enqueue)
+{
+    enqueue(s);
+    PANO_HIP(hipGetLastError());
+    constexpr int CH = 1024;
+    int32_t hf[CH];
+    for (int64_t c0 = 0; c0 < nq; c0 += CH) {
+        const int64_t cn = std::min<int64_t>(CH, nq - c0);
+        PANO_HIP(hipMemcpyAsync(hf, flags_dev + c0, sizeof(int32_t) * cn, hipMemcpyDeviceToHost, s));
+        PANO_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < cn; ++i) PANO_REQUIRE(!(hf[i] & FLAG_NONFINITE), "a query has a non-finite value");
+        for (int64_t i = 0; i < cn; ++i) {
+            if (!(hf[i] & FLAG_OVERFLOW)) continue;
+            const int64_t qi = c0 + i;
+            int32_t npv = 0;
+            PANO_HIP(hipMemcpyAsync(&npv, npq + qi, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            PANO_HIP(hipStreamSynchronize(s));
+            const int32_t *lists = probes + qi * np_max;
+            hipLaunchKernelGGL(k_probe_slots, dim3(1), dim3(NT), 0, s, lists, npv, ix->list_blk_d.as<int64_t>(),
+                               ix->B, fb_total);
+            int64_t total = 0;
+            PANO_HIP(hipMemcpyAsync(&total, fb_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            PANO_HIP(hipStreamSynchronize(s));
+            PANO_REQUIRE((size_t)std::max<int64_t>(1, total) * sizeof(uint64_t) <= fb_bytes,
+                         "fallback keys exceed the fixed scratch");
+            uint64_t *keys = reinterpret_cast<uint64_t *>(fb_keys);
+            unsigned gr = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (total + NT - 1) / NT));
+            hipLaunchKernelGGL(k_fallback_keys, dim3(gr), dim3(NT), 0, s, q + qi * d, d, lists, npv,
+                               ix->list_blk_d.as<int64_t>(), ix->B, ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
+                               ix->raw.as<float>(), total, keys);
+            hipLaunchKernelGGL(k_fallback_select, dim3(1), dim3(NT), 0, s, keys, total, k, ids + qi * k,
+                               dists + qi * k);
+            PANO_HIP(hipGetLastError());
+            PANO_HIP(hipStreamSynchronize(s));
+        }
+    }
+}
+
 void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k, const int32_t *nprobe_dev,
                 int nprobe_all, float eps, int64_t *ids, float *dists, const pano_search_params *prm,
-                uint32_t flags, bool brute, hipStream_t s)
+                uint32_t flags, bool brute, hipStream_t s, void *fixed, size_t fixed_bytes)
 {
     PANO_REQUIRE(ctx->device == ix->ctx->device, "context and index are on different devices");
     PANO_HIP(hipSetDevice(ctx->device));
@@ -2263,25 +2362,51 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
     const bool want_timing = !want_stats && (flags & PANO_SEARCH_TIMING) != 0;
     const bool seed_on = !brute && eps >= 1.f;
-    if (split) {
-        ctx->scratch[5].ensure(need[4]);
-        ctx->scratch[6].ensure(need[5]);
-    }
-
-    // ---- scratch
+    // ---- scratch: the context's buffers (grown on demand), or consecutive
+    // regions of the caller's fixed memory
     const size_t need0 = need[0], need1 = need[1], need2 = need[2], need3 = need[3];
-    ctx->scratch[0].ensure(need0);
-    ctx->scratch[1].ensure(need1);
-    ctx->scratch[2].ensure(need2);
-    ctx->scratch[3].ensure(need3);
-    Carver c0(ctx->scratch[0].p), c2(ctx->scratch[2].p), c3(ctx->scratch[3].p);
+    void *sp[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int32_t *flags_dev = nullptr;
+    int64_t *fb_total = nullptr;
+    if (fixed) {
+        PANO_REQUIRE((flags & (PANO_SEARCH_STATS | PANO_SEARCH_TIMING)) == 0,
+                     "the allocation-free search takes no stats or timing flags");
+        const size_t want = search_fixed_bytes(ix, nq, k, nprobe_dev != nullptr, nprobe_all, prm);
+        if (want > fixed_bytes)
+            throw Error{PANO_EINVAL, "this search needs " + std::to_string(want) +
+                                         " bytes of scratch; the allocation-free search has " +
+                                         std::to_string(fixed_bytes) + " (fewer queries per call fit)"};
+        Carver cf(fixed);
+        sp[0] = cf.take<char>(need0);
+        sp[1] = cf.take<char>(need1);
+        sp[2] = cf.take<char>(need2);
+        sp[3] = cf.take<char>(need3);
+        sp[5] = cf.take<char>(need[4]);
+        sp[6] = cf.take<char>(need[5]);
+        sp[4] = cf.take<char>(need[6]);
+        flags_dev = cf.take<int32_t>(nq);
+        fb_total = cf.take<int64_t>(1);
+    } else {
+        if (split) {
+            ctx->scratch[5].ensure(need[4]);
+            ctx->scratch[6].ensure(need[5]);
+            sp[5] = ctx->scratch[5].p;
+            sp[6] = ctx->scratch[6].p;
+        }
+        ctx->scratch[0].ensure(need0);
+        ctx->scratch[1].ensure(need1);
+        ctx->scratch[2].ensure(need2);
+        ctx->scratch[3].ensure(need3);
+        for (int i = 0; i < 4; ++i) sp[i] = ctx->scratch[i].p;
+    }
+    Carver c0(sp[0]), c2(sp[2]), c3(sp[3]);
     float *qy = c0.take<float>(nq * ix->d_pad);
     float *qtail = c0.take<float>(nq * L);
     float *qE = c0.take<float>(nq);
     float *qA = c0.take<float>(nq);
     int32_t *qbad = c3.take<int32_t>(nq);
     double *vnorm = c0.take<double>(nq);
-    float *Sco = ctx->scratch[1].as<float>();
+    float *Sco = reinterpret_cast<float *>(sp[1]);
     int32_t *probes = c2.take<int32_t>(nq * np_max);
     int32_t *list_q = c2.take<int32_t>(nq * np_max);
     int32_t *npq = c2.take<int32_t>(nq);
@@ -2312,18 +2437,23 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         PANO_HIP(hipFuncSetAttribute((const void *)coarse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)coarse_shm));
     PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_shm));
-    ctx->pinned_ensure(sizeof(int32_t) * nq);
-    int32_t *h_flags = reinterpret_cast<int32_t *>(ctx->pinned);
+    // per-query flag words written by the merge: pinned host memory, or the
+    // fixed scratch (read back in chunks)
+    int32_t *h_flags = flags_dev;
+    if (!fixed) {
+        ctx->pinned_ensure(sizeof(int32_t) * nq);
+        h_flags = reinterpret_cast<int32_t *>(ctx->pinned);
+    }
     IndexView iv{ix->levels.as<float>(), ix->has_bf16 ? ix->levels_bf16.as<uint16_t>() : nullptr, ix->tails.as<float>(), ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
                  ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
     QueryView qv{qy, qtail, qE, qA, q};
     WorkView wk{list_cnt, list_qoff, list_q, item_off, heads, thr, buf, buf_cnt, qflags, nullptr};
     int4 *items = nullptr;
     if (split) {
-        Carver c5(ctx->scratch[5].p);
+        Carver c5(sp[5]);
         wk.pairs = c5.take<uint4>(pl.seg_cap * pl.grid_seg);
         wk.seg_cap = pl.seg_cap;
-        items = ctx->scratch[6].as<int4>();
+        items = reinterpret_cast<int4 *>(sp[6]);
         wk.items = items;
         wk.items_max = pl.items_max;
     }
@@ -2378,8 +2508,10 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             qc.badq = qbad;
             launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, rs_, &qc);
         };
-        hipStream_t sa = ctx->aux, sb = ctx->aux2;
-        if (seed_on) {
+        // the allocation-free search runs every kernel on st, in order
+        const bool fork = seed_on && !fixed;
+        hipStream_t sa = fork ? ctx->aux : st, sb = fork ? ctx->aux2 : st;
+        if (fork) {
             PANO_HIP(hipEventRecord(ctx->ev_fork, st));
         } else {
             row_norms(st);
@@ -2387,12 +2519,12 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         // the seeding, the longest branch, is launched first so that its waves
         // are dispatched first
         if (seed_on) {
-            PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork, 0));
+            if (fork) PANO_HIP(hipStreamWaitEvent(sa, ctx->ev_fork, 0));
             hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), seed_lds_bytes(seed_pool, c.g.d_pad), sa, c, iv,
                                qv, Sco, ix->cent.as<float>() + (size_t)nlist * d, d, nlist, nprobe_dev, nprobe_all,
                                np_max, c_co, ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt,
                                ix->mu32.as<float>(), mq.c_abs, mq.b0max2, thr);
-            PANO_HIP(hipEventRecord(ctx->ev_join, sa));
+            if (fork) PANO_HIP(hipEventRecord(ctx->ev_join, sa));
         }
         // coarse probing (and the number of queries per list)
         if (nlist > 1) {
@@ -2403,7 +2535,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, np_max, probes,
                                npq, list_cnt);
         }
-        if (seed_on) {
+        if (fork) {
             PANO_HIP(hipStreamWaitEvent(sb, ctx->ev_fork, 0));
             row_norms(sb);
             PANO_HIP(hipEventRecord(ctx->ev_join2, sb));
@@ -2425,7 +2557,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         if (split)
             hipLaunchKernelGGL(k_wl_items, dim3((unsigned)(8 * c.ceil8)), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi,
                                list_cnt, ix->list_blk_d.as<int64_t>(), item_off, items, pl.items_max);
-        if (seed_on) {
+        if (fork) {
             PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
             PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join2, 0));
         }
@@ -2465,6 +2597,11 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     // caller's stream, so it is ordered after the caller's work without an
     // event.  Eager searches run on the context's stream, ordered after the
     // caller's by an event.
+    if (fixed) {
+        run_fixed_tail(ix, q, nq, k, d, np_max, ids, dists, probes, npq, h_flags, fb_total, sp[4], need[6], s,
+                       [&](hipStream_t st) { enqueue(st, false, false); });
+        return;
+    }
     hipStream_t ws = ctx->work_stream();
     hipStream_t rs = ws;  // the stream the search ran on
     const bool use_graph = !want_stats && !want_timing && !(flags & PANO_SEARCH_EAGER);

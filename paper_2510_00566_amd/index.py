@@ -193,6 +193,19 @@ class Index:
                                         C.byref(prm) if prm is not None else None, flags, _stream_handle(stream)))
         return ids, dists
 
+    def search_noalloc(self, q_dev, k: int, nprobe=1, eps: float = 1.0, params: Params | None = None,
+                       stream=None, out=None, nprobe_max: int = 0):
+        """The same search with no allocation inside the library: its scratch
+        is the library's fixed per-GPU array (calls on one GPU must not
+        overlap).  out: caller-allocated (ids, dists)."""
+        ids, dists = out if out is not None else self._outs(q_dev, k)
+        np_dev, np_all = _probe_args(nprobe, nprobe_max)
+        prm = params.c() if params is not None else None
+        L.check(L.lib().pano_search_noalloc(self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all,
+                                            float(eps), _ptr(ids), _ptr(dists),
+                                            C.byref(prm) if prm is not None else None, _stream_handle(stream)))
+        return ids, dists
+
     def scratch_bytes(self, nq: int, k: int, nprobe=1, per_query_nprobe: bool = False,
                       params: Params | None = None) -> int:
         """Device scratch a search of nq queries needs on its context.  With
