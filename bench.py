@@ -184,13 +184,15 @@ class Run:
 
     def bruteforce(self, ref_ids, ref_d):
         """Same probe lists, tiles and work decomposition, no bounds: the
-        faster of the pruned scan's decomposition and the library defaults."""
+        fastest of the pruned scan's decomposition, the library defaults and
+        the per-wave scan's brute-force instance (every level on the matrix
+        cores, each wavefront its own worker)."""
         import torch
         from paper_2510_00566_amd.index import Params
         w = self.w
         bi, bd = torch.empty_like(self.ids), torch.empty_like(self.dists)
         best = None
-        for tag, bprm in (("same-decomposition", self.prm), ("default", Params())):
+        for tag, bprm in (("same-decomposition", self.prm), ("default", Params()), ("per-wave", Params(scan_mode=4))):
             bprm = Params(**vars(bprm))
             bprm.use_bf16 = 0
             bsteps = max(3, self.args.steps // 4)

@@ -162,22 +162,30 @@ typedef struct {
                              boundary band from the FP32 rows, so the result
                              equals the FP32 search's */
     int32_t reserved[6];  /* [0]: refine a whole level on the matrix cores while at
-                             least this many pairs of a block survive (0 = 64);
-                             [1]: scan mode, 0 or 1 = one persistent kernel
-                             with a local top-k per work item, 2 = segmented
-                             split scan (level-1 filter, then one pass per
-                             level over each workgroup's surviving pairs;
-                             needs L >= 2, else the persistent scan runs),
+                             least this many pairs of a block (workgroup scan) or
+                             of a 64-slot step (per-wave scan) survive (0 = 64);
+                             [1]: scan mode: 0 or 1 = the workgroup scan (one
+                             persistent kernel, a local top-k per work item),
                              3 = no pruning (the brute-force scan of
                              pano_search_bruteforce; same answer), for
-                             workloads whose bounds prune too little;
+                             workloads whose bounds prune too little, 4 = the
+                             per-wave scan (every wavefront pulls its own work
+                             items; level 1 and dense levels on the matrix
+                             cores, later levels level-synchronously over a
+                             compacted pair list, survivors appended to the
+                             result buffers); other values are EINVAL;
                              [2]: lanes per pair in the per-pair walk of the
-                             persistent scan: 1, 2 or 4 (0 = 4 when at most
+                             workgroup scan: 1, 2 or 4 (0 = 4 when at most
                              64 pairs of a block survive, 2 up to 128, else
                              1); other values are EINVAL;
                              [3]: levels per step of the walk with four lanes
                              per pair: 1, or 2 (both requested together; 0 =
-                             2 when no level is wider than 64 dimensions) */
+                             2 when no level is wider than 64 dimensions);
+                             [4]: 1 = keep each list's queries in arrival
+                             order; 0 = order them by their approximate
+                             distance to the list's centroid, so that a query
+                             group holds queries at similar distance (work
+                             order only, the answer is the same) */
 } pano_search_params;
 
 /* Search flags. */

@@ -1,7 +1,8 @@
 """Project autotuner for the pruned scan.
 
-Search-time knobs (blocks per work item, queries per group, seeding pool and
-count, the density at which a level is refined on the matrix cores, and
+Search-time knobs (the scan kernel: workgroup or per-wave; blocks per work
+item, queries per group, seeding pool and count, the density at which a
+level is refined on the matrix cores, the order of each list's queries, and
 whether to prune at all: where the bounds prune too little the brute-force
 scan of the same candidates is faster and gives the same answer) are swept
 by timing real searches on a sample of the workload's queries; the level
@@ -23,11 +24,12 @@ from .index import Params
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 SEARCH_SPACE = {
-    "scan_mode": [0, 3],
-    "blocks_per_item": [1, 2, 3, 4, 8],
+    "scan_mode": [0, 4, 3],
+    "blocks_per_item": [1, 2, 4, 8],
     "group": [16, 8],
     "seed": [(512, 32), (1024, 64), (256, 32)],
-    "dense_min": [64, 32, 1 << 30],
+    "dense_min": [64, 256, 1, 1 << 30],
+    "arrival_order": [0, 1],
 }
 
 
@@ -59,12 +61,14 @@ def tune_search(idx, q_dev, k: int, nprobe, reps: int = 5, space: dict | None = 
     its time per search (seconds).  nprobe_max bounds per-query probe counts."""
     space = space or SEARCH_SPACE
     best = Params()
-    cur = {"scan_mode": 0, "blocks_per_item": 1, "group": 16, "seed": (512, 32), "dense_min": 64}
+    cur = {"scan_mode": 0, "blocks_per_item": 1, "group": 16, "seed": (512, 32), "dense_min": 64,
+           "arrival_order": 0}
 
     def mk(cfg):
         return Params(group=cfg["group"], blocks_per_item=cfg["blocks_per_item"],
                       seed_pool=cfg["seed"][0], seed_count=cfg["seed"][1], dense_min=cfg["dense_min"],
-                      use_bf16=use_bf16 if cfg["scan_mode"] != 3 else 0, scan_mode=cfg["scan_mode"])
+                      use_bf16=use_bf16 if cfg["scan_mode"] != 3 else 0, scan_mode=cfg["scan_mode"],
+                      arrival_order=cfg["arrival_order"])
 
     def run(cfg):
         p = mk(cfg)

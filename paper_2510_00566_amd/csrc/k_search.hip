@@ -30,7 +30,8 @@ __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, cons
                                                const float *__restrict__ cent, int d, int nlist, int64_t nq,
                                                const int32_t *__restrict__ nprobe_dev, int nprobe_all,
                                                float c_co, int np_max, int32_t *__restrict__ probes,
-                                               int32_t *__restrict__ np_out, int32_t *__restrict__ list_cnt)
+                                               int32_t *__restrict__ np_out, int32_t *__restrict__ list_cnt,
+                                               float *__restrict__ qn2)
 {
     extern __shared__ char smc[];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, cons
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o, 64);
+    if (qn2 != nullptr && lane == 0) qn2[qi] = qq;
     for (int l0 = 0; l0 < nlist; l0 += 512) {
         float cv[8], sv[8];
 #pragma unroll
@@ -257,26 +259,38 @@ __global__ void k_wl_fill(int64_t nq, int np_max, const int32_t *__restrict__ pr
     }
 }
 
-// Work-item table: item i of the queue-ordered numbering -> (list, query
-// group, block range), so a scan kernel decodes an item with one load.  One
-// workgroup per list position.
-__global__ __launch_bounds__(NT) void k_wl_items(int nlist, int ceil8, int G, int bpi,
-                                                 const int32_t *__restrict__ list_cnt,
-                                                 const int64_t *__restrict__ list_blk,
-                                                 const int64_t *__restrict__ item_off, int4 *__restrict__ items,
-                                                 int64_t items_max)
+// Orders each list's queries by their approximate distance to the list's
+// centroid (from the coarse products), so that a query group holds queries
+// at similar distance: the queries of the list's own cluster come first and
+// the far ones, whose candidates fail the level-1 bound, share groups of
+// their own.  A pure reordering of the work; the answer does not change.
+// One workgroup per list; lists of more than `cap` queries keep their order.
+__global__ __launch_bounds__(NT) void k_wl_sort(int nlist, const int32_t *__restrict__ list_cnt,
+                                                const int64_t *__restrict__ list_qoff, int32_t *__restrict__ list_q,
+                                                const float *__restrict__ S, const float *__restrict__ qn2,
+                                                const float *__restrict__ cn2, int cap)
 {
-    const int pos = blockIdx.x;
-    const int l = (pos % ceil8) * 8 + pos / ceil8;
-    if (l >= nlist) return;
-    const int64_t base = item_off[pos], cnt = item_off[pos + 1] - base;
-    if (cnt <= 0) return;
-    const int groups = (list_cnt[l] + G - 1) / G;
-    // items_max bounds the count by construction; the test only keeps the
-    // writes inside the table
-    for (int64_t i = threadIdx.x; i < cnt && base + i < items_max; i += NT)
-        items[base + i] = make_int4(l, (int)(i % groups), (int)(i / groups), 0);
+    extern __shared__ uint64_t Kq[];
+    const int l = blockIdx.x;
+    const int cnt = list_cnt[l];
+    if (cnt < 2 || cnt > cap) return;
+    const int64_t off = list_qoff[l];
+    const int P = next_pow2(cnt);
+    const float c2 = cn2[l];
+    for (int i = threadIdx.x; i < P; i += NT) {
+        if (i < cnt) {
+            const int32_t qq = list_q[off + i];
+            const float dv = fmaxf(qn2[qq] + c2 - 2.f * S[(int64_t)qq * nlist + l], 0.f);
+            Kq[i] = make_key(dv, qq);
+        } else {
+            Kq[i] = KEY_MAX;
+        }
+    }
+    __syncthreads();
+    block_bitonic_sort(Kq, P);
+    for (int i = threadIdx.x; i < cnt; i += NT) list_q[off + i] = key_id(Kq[i]);
 }
+
 
 // ================================================================ index views
 struct IndexView {
@@ -598,11 +612,6 @@ struct WorkView {
     int32_t *buf_cnt;      // [nq]
     int32_t *flags;        // [nq]
     unsigned long long *stats;  // optional counters
-    // split scan: pairs that survive the dense levels, for the walk kernel
-    uint4 *pairs;          // [grid][seg_cap] {query, block, bits of the partial distance, slot}
-    int64_t seg_cap;       // pairs per workgroup segment
-    const int4 *items;     // work-item table {list, group, block range} (split scan)
-    int64_t items_max;
 };
 
 // Counters layout (unsigned long long): [0] items, [1] committed, [2] bytes,
@@ -1530,138 +1539,92 @@ __global__ __launch_bounds__(NT) void k_scan_brute_stats(SearchConsts c, IndexVi
     scan_body<false, false, true>(c, ix, qv, wk);
 }
 
-// Split scan.  Each workgroup alternates between two phases over a private
-// segment of the pair list:
-//  * filter: level 1 of one block of a work item against the item's query
-//    group on the matrix cores with the Eq. 3 bound (Compute / Update /
-//    Consolidate of Section 6.1 for the first level); the surviving pairs
-//    are appended to the segment;
-//  * walk: once the segment cannot take another item (or the items are
-//    exhausted), its pairs are refined level-synchronously: one pass per
-//    level reads that level of every live pair, tests the bound with the
-//    certified margin and compacts the survivors in place; after the last
-//    level the survivors are published to their query's result buffer.
-// Every pass gives each pair exactly one level, so no lane idles behind a
-// longer walk, and the segment needs no atomics.  The workgroup's registers
-// fit four per SIMD.
-#ifndef SEG_WAVES
-#define SEG_WAVES 4
+// ================================================================ per-wave scan
+// Every wavefront is its own worker: it pulls work items (list, group of up to
+// 16 queries, block range) from the XCD queues and walks each block in steps
+// of 64 slots, with no barrier shared with the other wavefronts of its
+// workgroup.  One step is Algorithm 1 for a batch of 16 x 64 (query, slot)
+// pairs:
+//  * Compute / Update for level 1 on the matrix cores (the dot-product form of
+//    the Eq. 3 bound with its certified margin), the query slices held in
+//    registers for the whole item;
+//  * Consolidate: the surviving pairs are compacted by ballot and prefix sum
+//    into the wave's pair list in LDS;
+//  * the later levels level-synchronously over that list: each pass reads one
+//    level of every live pair (one, two or four lanes per pair by the level
+//    width), adds its exact partial distance, tests the bound and compacts
+//    the list in place;
+//  * commit: a pair that survives the last level has its FP32 distance; it is
+//    appended to its query's result buffer if it can still reach the final
+//    band, and the k best distances the wave has committed for the query give
+//    its threshold (published with atomicMin).
+// The brute-force instance reads every level of every pair on the matrix
+// cores and commits the pairs within the threshold.
+#ifndef WAVE_SCAN_WPE
+#define WAVE_SCAN_WPE 3  // wavefronts per SIMD the per-wave scan is compiled for
 #endif
 template <bool BF>
-__device__ __forceinline__ void seg_body(const SearchConsts &c, const IndexView &ix, const QueryView &qv,
-                                         const WorkView &wk)
+__device__ __forceinline__ float4 wave_ld4(const float *__restrict__ blk, const uint16_t *__restrict__ blk16,
+                                           int64_t o)
 {
-    __shared__ float4 q1_s[GMAX][16];  // level-1 slices of the item's queries
-    __shared__ float a0_s[GMAX], a1_s[GMAX], thr_s[GMAX], A_s[GMAX];
-    __shared__ int qid_s[GMAX];
-    __shared__ int item_s;
-    __shared__ int wave_tmp[NT / 64];
+    if (BF) {
+        const uint2 xr = *reinterpret_cast<const uint2 *>(blk16 + o);
+        return make_float4(__uint_as_float(xr.x << 16), __uint_as_float(xr.x & 0xffff0000u),
+                           __uint_as_float(xr.y << 16), __uint_as_float(xr.y & 0xffff0000u));
+    }
+    return *reinterpret_cast<const float4 *>(blk + o);
+}
+
+template <bool PRUNE, bool BF, bool STATS>
+__device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const IndexView &ix, const QueryView &qv,
+                                               const WorkView &wk)
+{
+    extern __shared__ __align__(16) char wdyn[];
+    __shared__ int32_t ioff_s[IOFF_LDS];
     __shared__ unsigned long long st_lv[64];
     __shared__ unsigned long long st_misc[2];  // items, bytes
     const LevelGeom &g = c.g;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int r16 = lane & 15, kq = lane >> 4;
-    const int kg0 = g.wp[0] >> 2;
-    uint4 *seg = wk.pairs + (int64_t)blockIdx.x * wk.seg_cap;
-    int seg_n = 0;  // uniform across the workgroup
-    if (wk.stats) {
+    const int n_ioff = 8 * c.ceil8 + 1;
+    const bool ioff_in_lds = n_ioff <= IOFF_LDS;
+    if (ioff_in_lds)
+        for (int i = tid; i < n_ioff; i += NT) ioff_s[i] = (int32_t)wk.item_off[i];
+    if (STATS) {
         for (int i = tid; i < 64; i += NT) st_lv[i] = 0;
         if (tid < 2) st_misc[tid] = 0;
     }
-    auto q_lds = [&](int kg) -> float4 { return q1_s[r16][kg]; };
-
-    // ---- walk phase over the segment
-    auto walk = [&]() {
-        int n = seg_n;
-        for (int lv = 1; lv < g.L && n > 0; ++lv) {
-            const bool last = lv + 1 == g.L;
-            const int w4 = g.wp[lv] >> 2;
-            const int64_t lvoff = (int64_t)g.B * g.mp[lv];
-            if (wk.stats && tid == 0) {
-                st_lv[lv < 64 ? lv : 63] += (unsigned long long)n;
-                st_misc[1] += (unsigned long long)n * (g.wp[lv] * (BF ? 2 : 4) + 8);
-            }
-            int nout = 0;
-            for (int base = 0; base < n; base += NT) {
-                const int p = base + tid;
-                bool keep = false;
-                uint4 r = make_uint4(0u, 0u, 0u, 0u);
-                float sh = 0.f, th = 0.f, Aq = 0.f;
-                if (p < n) {
-                    r = seg[p];
-                    const int qq = (int)r.x;
-                    const int64_t gb = (int64_t)r.y;
-                    const int ss = (int)(r.w & 0xffffu);
-                    sh = __uint_as_float(r.z);
-                    const float *tl = ix.tails + gb * (int64_t)g.B * g.L;
-                    const float *qrow = qv.qy + (int64_t)qq * g.d_pad + g.mp[lv];
-                    const int64_t xo = gb * (int64_t)g.B * g.d_pad + lvoff + (int64_t)ss * g.wp[lv];
-                    const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
-                    const float a = last ? 0.f : qv.qtail[(int64_t)qq * g.L + lv + 1];
-                    th = __hip_atomic_load(&wk.thr[qq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    Aq = qv.qA[qq];
-                    const float delta = BF ? c.ub * tl[ss] + 1e-37f : 0.f;
-                    float part = 0.f;
-#pragma unroll 4
-                    for (int c4 = 0; c4 < w4; ++c4) {
-                        float4 x4;
-                        if (BF) {
-                            const uint2 xr = *reinterpret_cast<const uint2 *>(ix.levels16 + xo + c4 * 4);
-                            x4 = make_float4(__uint_as_float(xr.x << 16), __uint_as_float(xr.x & 0xffff0000u),
-                                             __uint_as_float(xr.y << 16), __uint_as_float(xr.y & 0xffff0000u));
-                        } else {
-                            x4 = *reinterpret_cast<const float4 *>(ix.levels + xo + c4 * 4);
-                        }
-                        const float4 q4 = *reinterpret_cast<const float4 *>(qrow + c4 * 4);
-                        float t0 = q4.x - x4.x, t1 = q4.y - x4.y, t2 = q4.z - x4.z, t3 = q4.w - x4.w;
-                        part = __builtin_fmaf(t0, t0, part);
-                        part = __builtin_fmaf(t1, t1, part);
-                        part = __builtin_fmaf(t2, t2, part);
-                        part = __builtin_fmaf(t3, t3, part);
-                    }
-                    sh += part;
-                    const float dt = a - b;
-                    const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
-                    const float ct = c.mg.c_tail * (a + b) * (a + b);
-                    const bool pruned = BF ? bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct > th
-                                           : (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
-                    keep = !pruned;
-                }
-                if (last) {
-                    if (keep) {
-                        const int qq = (int)r.x;
-                        const float dsh = fmaxf(sh, 0.f);
-                        if (dist_lower(dsh, Aq, c.mg, c.bfdelta) <= th) {
-                            const int dst = atomicAdd(&wk.buf_cnt[qq], 1);
-                            if (dst < c.capq)
-                                wk.buf[(int64_t)qq * c.capq + dst] =
-                                    make_key(dsh, ix.ids[(int64_t)r.y * g.B + (r.w & 0xffffu)]);
-                            else
-                                atomicOr(&wk.flags[qq], FLAG_OVERFLOW);
-                        }
-                    }
-                } else {
-                    // in-place compaction: every read of this chunk precedes
-                    // the scan's barrier, and the writes land below the chunk
-                    int tot;
-                    const int off = block_exclusive_scan(keep ? 1 : 0, wave_tmp, &tot);
-                    if (keep) seg[nout + off] = make_uint4(r.x, r.y, __float_as_uint(sh), r.w);
-                    nout += tot;
-                }
-            }
-            n = nout;
-            __syncthreads();
-        }
-        seg_n = 0;
+    // the only workgroup barrier before the end: the waves run independently
+    __syncthreads();
+    auto ioff = [&](int i) -> int64_t { return ioff_in_lds ? (int64_t)ioff_s[i] : wk.item_off[i]; };
+    const WaveLds &lay = c.wl;
+    char *wb = wdyn + (size_t)wv * lay.bytes;
+    int *qid_w = reinterpret_cast<int *>(wb + lay.qid);
+    float *thr_w = reinterpret_cast<float *>(wb + lay.thr);
+    float *A_w = reinterpret_cast<float *>(wb + lay.A);
+    float *E_w = reinterpret_cast<float *>(wb + lay.E);
+    int *kc_w = reinterpret_cast<int *>(wb + lay.kc);
+    float *qtl = reinterpret_cast<float *>(wb + lay.qtl);  // [16][L]
+    float *kb = reinterpret_cast<float *>(wb + lay.kb);    // [16][k]
+    float *sb = reinterpret_cast<float *>(wb + lay.sb);
+    uint16_t *pcode = reinterpret_cast<uint16_t *>(wb + lay.code);
+    float *pS = reinterpret_cast<float *>(wb + lay.pS);
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int L = g.L;
+    const int kg0 = g.wp[0] >> 2;  // four-dimension chunks of level 1 (at most 16)
+    const int T0 = (kg0 + 3) >> 2;
+    const uint64_t below = (1ull << lane) - 1ull;
+    auto wave_sync = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     };
-
     int queue = blockIdx.x & 7;
     int tried = 0;
     while (true) {
-        if (tid == 0) {
-            int it = -1;
+        // ---- pull an item from this workgroup's XCD queue, then steal
+        int it = -1;
+        if (lane == 0) {
             while (tried < 8) {
-                const int64_t qb = wk.item_off[queue * c.ceil8], qe = wk.item_off[(queue + 1) * c.ceil8];
+                const int64_t qb = ioff(queue * c.ceil8), qe = ioff((queue + 1) * c.ceil8);
                 if (qe > qb) {
                     const int v = atomicAdd(&wk.heads[queue], 1);
                     if (qb + v < qe) {
@@ -1672,127 +1635,555 @@ __device__ __forceinline__ void seg_body(const SearchConsts &c, const IndexView 
                 queue = (queue + 1) & 7;
                 ++tried;
             }
-            item_s = (it >= 0 && it < wk.items_max) ? it : -1;
         }
-        __syncthreads();
-        const int item = item_s;
+        const int item = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
         if (item < 0) break;
-        const int4 desc = wk.items[item];
-        const int l = desc.x, gi = desc.y;
-        const int64_t gb = ix.list_blk[l] + desc.z;  // one block per item in the split scan
-        const int cnt = ix.blk_cnt[gb];
-        const int ng = min(c.G, wk.list_cnt[l] - gi * c.G);
-        // a full segment is walked before it takes another item
-        if (seg_n + ng * cnt > wk.seg_cap) walk();
-        const int64_t qoff = wk.list_qoff[l] + (int64_t)gi * c.G;
-        {
-            // thread (gq, c4): query gq's id, then its level-1 group c4
-            const int gq = tid >> 4, c4 = tid & 15;
-            const int qq = gq < ng ? wk.list_q[qoff + gq] : -1;
-            q1_s[gq][c4] = (qq >= 0 && c4 < kg0)
-                               ? *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qq * g.d_pad + c4 * 4)
-                               : make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c4 == 0) {
-                qid_s[gq] = qq;
-                thr_s[gq] = qq >= 0 ? __hip_atomic_load(&wk.thr[qq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.f;
-                A_s[gq] = qq >= 0 ? qv.qA[qq] : 0.f;
-                a0_s[gq] = qq >= 0 ? qv.qtail[(int64_t)qq * g.L] : 0.f;
-                a1_s[gq] = (qq >= 0 && g.L > 1) ? qv.qtail[(int64_t)qq * g.L + 1] : 0.f;
-            }
+        // ---- decode: binary search of the queue-ordered item offsets
+        int lo = 0, hi = 8 * c.ceil8;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (ioff(mid) <= item) lo = mid;
+            else hi = mid;
         }
-        const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
-        const uint16_t *blk16 = BF ? ix.levels16 + gb * (int64_t)g.B * g.d_pad : nullptr;
-        const float *tl = ix.tails + gb * (int64_t)g.B * g.L;
-        // opaque to the optimiser, so the tile addresses derived from it are
-        // recomputed per item instead of being held in registers across items
-        int slot0 = wv * 64;
-        asm volatile("" : "+v"(slot0));
-        const bool wave_live = slot0 < cnt;
-        float tb0[4], tb1[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int sc = min(slot0 + nt * 16 + r16, g.B - 1);
-            tb0[nt] = tl[sc];
-            tb1[nt] = tl[g.B + sc];  // L >= 2 in the split scan
+        const int l = (lo % c.ceil8) * 8 + lo / c.ceil8;
+        const int local = (int)(item - ioff(lo));
+        const int qcnt = wk.list_cnt[l];
+        const int groups = (qcnt + c.G - 1) / c.G;
+        const int gi = local % groups, ri = local / groups;
+        const int ng = min(c.G, qcnt - gi * c.G);
+        const int64_t lb0 = ix.list_blk[l], nblk = ix.list_blk[l + 1] - lb0;
+        const int bpl = list_bpi(c.bpi, nblk, c.item_cap);
+        const int bstart = ri * bpl;
+        const int bend = (int)min<int64_t>(nblk, (int64_t)(ri + 1) * bpl);
+        // ---- the item's queries
+        if (lane < 16) {
+            const bool on = lane < ng;
+            const int qq = on ? wk.list_q[wk.list_qoff[l] + (int64_t)gi * c.G + lane] : 0;
+            qid_w[lane] = on ? qq : -1;
+            thr_w[lane] = INFINITY;
+            A_w[lane] = on ? qv.qA[qq] : 0.f;
+            E_w[lane] = on ? qv.qE[qq] : 0.f;
+            kc_w[lane] = 0;
         }
-        __syncthreads();
-        floatx4_t acc[4];
-        float ex[4] = {0.f, 0.f, 0.f, 0.f};
-        uint32_t mask = 0;
-        float sval[16];
-        if (wave_live) {
-            if (BF)
-                level_dots_bf16(blk16, g.B, kg0, q_lds, slot0, lane, acc, ex);
-            else
-                level_dots<true>(blk, g.B, kg0, q_lds, slot0, lane, acc);
+        wave_sync();
+        for (int e = lane; e < 16 * L; e += 64) {
+            const int gq = e / L, lv = e - gq * L;
+            qtl[e] = gq < ng ? qv.qtail[(int64_t)qid_w[gq] * L + lv] : 0.f;
+        }
+        wave_sync();
+        // the level-1 query slices of this lane's row (query r16), read at
+        // every step beside the tile (they stay in the cache for the item)
+        const float *q1row = qv.qy + (int64_t)(r16 < ng ? qid_w[r16] : 0) * g.d_pad;
+        if (STATS && lane == 0) atomicAdd(&st_misc[0], 1ull);
+
+        for (int bb = bstart; bb < bend; ++bb) {
+            const int64_t gb = lb0 + bb;
+            const int cnt = ix.blk_cnt[gb];
+            const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
+            const uint16_t *blk16 = BF ? ix.levels16 + gb * (int64_t)g.B * g.d_pad : nullptr;
+            const float *tl = ix.tails + gb * (int64_t)g.B * L;
+            for (int slot0 = 0; slot0 < cnt; slot0 += 64) {
+                // ---- thresholds: the queries' current d_k
+                if (lane < ng)
+                    thr_w[lane] = fminf(thr_w[lane],
+                                        __hip_atomic_load(&wk.thr[qid_w[lane]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                wave_sync();
+                float tb0[4], tb1[4];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int s = slot0 + nt * 16 + r16;
-                const bool valid = s < cnt;
-                const float b0 = valid ? tb0[nt] : 0.f;
-                const float b1 = valid ? tb1[nt] : 0.f;
-                const float rxh = BF ? ex[nt] : b0 * b0 - b1 * b1;
-                const float delta = BF ? c.ub * b0 + 1e-37f : 0.f;
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int sc = min(slot0 + nt * 16 + r16, g.B - 1);
+                    tb0[nt] = tl[sc];
+                    tb1[nt] = L > 1 ? tl[g.B + sc] : 0.f;
+                }
+                floatx4_t acc[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int gq = 4 * kq + v;
-                    const bool on = valid && gq < ng;
-                    const float a0 = a0_s[gq], a1 = a1_s[gq];
-                    const float sh = (on ? a0 * a0 - a1 * a1 : 0.f) + rxh - 2.f * acc[nt][v];
-                    const float dt = a1 - b1;
-                    bool sv;
-                    if (BF) {
-                        const float hl = bf_head_lower(sh - A_s[gq], delta);
-                        sv = hl + dt * dt + c.one_m_eps2 * a1 * b1 - c.mg.c_tail * (a1 + b1) * (a1 + b1) <= thr_s[gq];
-                    } else {
-                        const float lb = sh + dt * dt + c.one_m_eps2 * a1 * b1;
-                        const float eta = A_s[gq] + c.mg.c_tail * (a1 + b1) * (a1 + b1);
-                        sv = lb - eta <= thr_s[gq];
+                for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+                float ex[4] = {0.f, 0.f, 0.f, 0.f};
+                uint32_t mask = 0;
+                float sval[16];
+                if (PRUNE) {
+                    // query operand: chunks 4 t + kq of query r16, zero past
+                    // the group or the level
+                    float4 qa[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int kg = 4 * t + kq;
+                        qa[t] = (t < T0 && r16 < ng && kg < kg0) ? *reinterpret_cast<const float4 *>(q1row + kg * 4)
+                                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
                     }
-                    mask |= (uint32_t)(on && sv) << (nt * 4 + v);
-                    sval[nt * 4 + v] = sh;
+                    // level 1 of the 64 slots against the group, on the matrix cores
+                    if (BF) {
+                        // bfloat16 tiles on v_mfma_f32_16x16x16bf16_1k (16
+                        // dimensions per step); the FP32 query is split into
+                        // two bfloat16 terms, and each lane also sums the
+                        // squares of the tile values it feeds (||x~_h||^2)
+                        uint2 xr[4][4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            if (t < T0) {
+                                const int kgc = min(4 * t + kq, kg0 - 1);
+#pragma unroll
+                                for (int nt = 0; nt < 4; ++nt) {
+                                    const uint32_t slot = (uint32_t)(slot0 + nt * 16 + r16);
+                                    xr[t][nt] = *reinterpret_cast<const uint2 *>(
+                                        blk16 + ((uint32_t)kgc * (uint32_t)g.B + slot) * 4u);
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            if (t < T0) {
+                                const bool okq = 4 * t + kq < kg0;
+                                shortx4_t qh, ql;
+                                const float qv4[4] = {qa[t].x, qa[t].y, qa[t].z, qa[t].w};
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    const uint16_t h = bf16_bits_rne(qv4[e]);
+                                    qh[e] = (short)h;
+                                    ql[e] = (short)bf16_bits_rne(qv4[e] - bf16_to_f32(h));
+                                }
+#pragma unroll
+                                for (int nt = 0; nt < 4; ++nt) {
+                                    shortx4_t xa;
+                                    xa[0] = (short)(xr[t][nt].x & 0xffffu);
+                                    xa[1] = (short)(xr[t][nt].x >> 16);
+                                    xa[2] = (short)(xr[t][nt].y & 0xffffu);
+                                    xa[3] = (short)(xr[t][nt].y >> 16);
+                                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qh, xa, acc[nt], 0, 0, 0);
+                                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ql, xa, acc[nt], 0, 0, 0);
+                                    const float x0 = __uint_as_float(xr[t][nt].x << 16);
+                                    const float x1 = __uint_as_float(xr[t][nt].x & 0xffff0000u);
+                                    const float x2 = __uint_as_float(xr[t][nt].y << 16);
+                                    const float x3 = __uint_as_float(xr[t][nt].y & 0xffff0000u);
+                                    float e2 = ex[nt];
+                                    e2 = __builtin_fmaf(x0, x0, e2);
+                                    e2 = __builtin_fmaf(x1, x1, e2);
+                                    e2 = __builtin_fmaf(x2, x2, e2);
+                                    e2 = __builtin_fmaf(x3, x3, e2);
+                                    ex[nt] = okq ? e2 : ex[nt];
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            ex[nt] += __shfl_xor(ex[nt], 16, 64);
+                            ex[nt] += __shfl_xor(ex[nt], 32, 64);
+                        }
+                    } else {
+                        const int T = T0;
+                        auto fetch = [&](int t, float4 xa[4]) {
+                            const int kgc = min(4 * t + kq, kg0 - 1);
+#pragma unroll
+                            for (int nt = 0; nt < 4; ++nt) {
+                                const uint32_t slot = (uint32_t)(slot0 + nt * 16 + r16);
+                                xa[nt] = *reinterpret_cast<const float4 *>(blk + ((uint32_t)kgc * (uint32_t)g.B + slot) * 4u);
+                            }
+                        };
+                        auto products = [&](const float4 xa[4], const float4 &q4) {
+#pragma unroll
+                            for (int nt = 0; nt < 4; ++nt) {
+                                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(q4.x, xa[nt].x, acc[nt], 0, 0, 0);
+                                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(q4.y, xa[nt].y, acc[nt], 0, 0, 0);
+                                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(q4.z, xa[nt].z, acc[nt], 0, 0, 0);
+                                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(q4.w, xa[nt].w, acc[nt], 0, 0, 0);
+                            }
+                        };
+                        float4 xa0[4], xa1[4];
+                        fetch(0, xa0);
+                        if (T > 1) fetch(1, xa1);
+                        products(xa0, qa[0]);
+                        if (T > 2) fetch(2, xa0);
+                        if (T > 1) products(xa1, qa[1]);
+                        if (T > 3) fetch(3, xa1);
+                        if (T > 2) products(xa0, qa[2]);
+                        if (T > 3) products(xa1, qa[3]);
+                    }
+                    // this lane's queries 4 kq + v: threshold, level-1 head
+                    // energy, tail after level 1, margin
+                    float th[4], rqh[4], a1q[4], Aq[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int gq = 4 * kq + v;
+                        const bool on = gq < ng;
+                        const float a0 = on ? qtl[gq * L] : 0.f;
+                        const float a1 = (on && L > 1) ? qtl[gq * L + 1] : 0.f;
+                        th[v] = thr_w[gq];
+                        rqh[v] = a0 * a0 - a1 * a1;
+                        a1q[v] = a1;
+                        Aq[v] = on ? A_w[gq] : 0.f;
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int s = slot0 + nt * 16 + r16;
+                        const bool valid = s < cnt;
+                        const float b0 = valid ? tb0[nt] : 0.f;
+                        const float b1 = valid ? tb1[nt] : 0.f;
+                        const float rxh = b0 * b0 - b1 * b1;
+                        const float delta = BF ? c.ub * b0 + 1e-37f : 0.f;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int gq = 4 * kq + v;
+                            const bool on = valid && gq < ng;
+                            const float a1 = a1q[v];
+                            const float sh = rqh[v] + (BF ? ex[nt] : rxh) - 2.f * acc[nt][v];
+                            const float dt = a1 - b1;
+                            bool sv;
+                            if (BF) {
+                                const float hl = bf_head_lower(sh - Aq[v], delta);
+                                sv = on && (hl + dt * dt + c.one_m_eps2 * a1 * b1 -
+                                                c.mg.c_tail * (a1 + b1) * (a1 + b1) <=
+                                            th[v]);
+                            } else {
+                                const float lb = sh + dt * dt + c.one_m_eps2 * a1 * b1;
+                                const float eta = Aq[v] + c.mg.c_tail * (a1 + b1) * (a1 + b1);
+                                sv = on && (lb - eta <= th[v]);
+                            }
+                            mask |= (uint32_t)sv << (nt * 4 + v);
+                            sval[nt * 4 + v] = sh;
+                        }
+                    }
+                    if (STATS && lane == 0) {
+                        const int cs = min(64, cnt - slot0);
+                        atomicAdd(&st_lv[0], (unsigned long long)cs * ng);
+                        atomicAdd(&st_misc[1], (unsigned long long)cs * (g.wp[0] * (BF ? 2 : 4) + (L > 1 ? 8 : 4)));
+                    }
+                } else {
+                    // brute force: every level on the matrix cores, the query
+                    // operand loaded per level
+                    const int qq = r16 < ng ? qid_w[r16] : 0;
+                    for (int lv = 0; lv < L; ++lv) {
+                        const int kgc = g.wp[lv] >> 2;
+                        for (int base = 0; base < kgc; base += 16) {
+                            const int kgn = min(16, kgc - base);
+                            const float *qrow = qv.qy + (int64_t)qq * g.d_pad + g.mp[lv] + base * 4;
+                            auto qload = [&](int kg) -> float4 {
+                                return r16 < ng ? *reinterpret_cast<const float4 *>(qrow + kg * 4)
+                                                : make_float4(0.f, 0.f, 0.f, 0.f);
+                            };
+                            if (lv == 0)
+                                level_dots(blk + (int64_t)base * 4 * g.B, g.B, kgn, qload, slot0, lane, acc);
+                            else
+                                level_dots(blk + (int64_t)g.B * g.mp[lv] + base * 4, g.B, kgn, qload, slot0, lane, acc,
+                                           g.wp[lv]);
+                        }
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int s = slot0 + nt * 16 + r16;
+                        const bool valid = s < cnt;
+                        const float b0 = valid ? tb0[nt] : 0.f;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int gq = 4 * kq + v;
+                            const bool on = valid && gq < ng;
+                            const float a0 = on ? qtl[gq * L] : 0.f;
+                            const float dd = a0 * a0 + b0 * b0 - 2.f * acc[nt][v];
+                            const bool sv = on && dist_lower(dd, A_w[gq], c.mg) <= thr_w[gq];
+                            mask |= (uint32_t)sv << (nt * 4 + v);
+                            sval[nt * 4 + v] = dd;
+                        }
+                    }
+                    if (STATS && lane == 0) {
+                        const int cs = min(64, cnt - slot0);
+                        for (int lv = 0; lv < L && lv < 64; ++lv) atomicAdd(&st_lv[lv], (unsigned long long)cs * ng);
+                        atomicAdd(&st_misc[1], (unsigned long long)cs * (g.d_pad * 4 + 4 + 4));
+                    }
+                }
+                // ---- while many pairs of the step are alive, refine the next
+                // level densely on the matrix cores (one pass over the 64
+                // slots' level tile serves all of them; the dot-product form
+                // with the margins of level 1)
+                int lv_first = 1;  // first level left to the sparse passes
+                if (PRUNE) {
+                    int alive = __popc(mask);
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) alive += __shfl_xor(alive, o, 64);
+                    while (lv_first < L && alive >= c.dense_min && g.wp[lv_first] <= 64) {
+                        const int lv = lv_first;
+                        const bool last = lv + 1 == L;
+                        const int kgc = g.wp[lv] >> 2;
+                        const float *qrow = qv.qy + (int64_t)(r16 < ng ? qid_w[r16] : 0) * g.d_pad + g.mp[lv];
+                        float tbl[4], tbn[4];
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const int sc = min(slot0 + nt * 16 + r16, g.B - 1);
+                            tbl[nt] = tl[(int64_t)lv * g.B + sc];
+                            tbn[nt] = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + sc];
+                        }
+                        floatx4_t acc2[4];
+                        float ex2[4] = {0.f, 0.f, 0.f, 0.f};
+                        auto qload = [&](int kg) -> float4 {
+                            return r16 < ng ? *reinterpret_cast<const float4 *>(qrow + kg * 4)
+                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+                        };
+                        if (BF)
+                            level_dots_bf16(blk16 + (int64_t)g.B * g.mp[lv], g.B, kgc, qload, slot0, lane, acc2, ex2,
+                                            g.wp[lv]);
+                        else
+                            level_dots<true>(blk + (int64_t)g.B * g.mp[lv], g.B, kgc, qload, slot0, lane, acc2, g.wp[lv]);
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const int sidx = slot0 + nt * 16 + r16;
+                            const bool valid = sidx < cnt;
+                            const float bl = valid ? tbl[nt] : 0.f;
+                            const float bn = valid ? tbn[nt] : 0.f;
+                            const float rxl = BF ? ex2[nt] : bl * bl - bn * bn;
+                            const float delta = BF ? c.ub * (valid ? tb0[nt] : 0.f) + 1e-37f : 0.f;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int b = nt * 4 + v;
+                                const int gq = 4 * kq + v;
+                                const bool live = (mask >> b) & 1u;
+                                const float al = live ? qtl[gq * L + lv] : 0.f;
+                                const float an = (live && !last) ? qtl[gq * L + lv + 1] : 0.f;
+                                const float sh = sval[b] + (al * al - an * an) + rxl - 2.f * acc2[nt][v];
+                                const float dt = an - bn;
+                                const float Ag = live ? A_w[gq] : 0.f;
+                                const float th = live ? thr_w[gq] : 0.f;
+                                bool pruned;
+                                if (BF) {
+                                    const float hl = bf_head_lower(sh - c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) - Ag, delta);
+                                    pruned = hl + dt * dt + c.one_m_eps2 * an * bn - c.mg.c_tail * (an + bn) * (an + bn) > th;
+                                } else {
+                                    const float lb = sh + dt * dt + c.one_m_eps2 * an * bn;
+                                    const float eta = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Ag +
+                                                      c.mg.c_tail * (an + bn) * (an + bn);
+                                    pruned = lb - eta > th;
+                                }
+                                sval[b] = sh;
+                                if (live && pruned) mask &= ~(1u << b);
+                            }
+                        }
+                        if (STATS && lane == 0) {
+                            const int cs = min(64, cnt - slot0);
+                            atomicAdd(&st_lv[lv < 64 ? lv : 63], (unsigned long long)alive);
+                            atomicAdd(&st_misc[1], (unsigned long long)cs * (g.wp[lv] * (BF ? 2 : 4) + 8));
+                        }
+                        ++lv_first;
+                        alive = __popc(mask);
+#pragma unroll
+                        for (int o = 1; o < 64; o <<= 1) alive += __shfl_xor(alive, o, 64);
+                    }
+                }
+                // ---- consolidate into the pair list, refine the later levels,
+                // commit; in two halves (slots 0-31, 32-63) when more pairs
+                // survive than the list holds
+                int na = __popc(mask);
+                int tot = na;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_xor(tot, o, 64);
+                    tot += t;
+                }
+                const int halves = tot > WAVE_PAIRS ? 2 : 1;
+                for (int hf = 0; hf < halves; ++hf) {
+                    const uint32_t m = halves == 1 ? mask : (mask & (hf == 0 ? 0x00ffu : 0xff00u));
+                    const int nm = __popc(m);
+                    int incl = nm;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int t = __shfl_up(incl, o, 64);
+                        if (lane >= o) incl += t;
+                    }
+                    int off = incl - nm;
+                    int n = __shfl(incl, 63, 64);
+                    if (n == 0) continue;
+#pragma unroll
+                    for (int b = 0; b < 16; ++b) {
+                        if (m & (1u << b)) {
+                            const int nt = b >> 2, v = b & 3;
+                            pcode[off] = (uint16_t)(((4 * kq + v) << 8) | (slot0 + nt * 16 + r16));
+                            pS[off] = sval[b];
+                            ++off;
+                        }
+                    }
+                    wave_sync();
+                    // ---- later levels, one pass per level over the live pairs
+                    for (int lv = lv_first; PRUNE && lv < L && n > 0; ++lv) {
+                        const bool last = lv + 1 == L;
+                        const int w4 = g.wp[lv] >> 2;
+                        const int lpp = (w4 <= 4 && n > 16) ? 1 : ((w4 <= 8 && n > 16) ? 2 : 4);
+                        const int sub = lane & (lpp - 1);
+                        const int ppi = 64 / lpp;
+                        const float *lvbase = blk + (int64_t)g.B * g.mp[lv];
+                        const uint16_t *lvbase16 = BF ? blk16 + (int64_t)g.B * g.mp[lv] : nullptr;
+                        int nout = 0;
+                        if (STATS && lane == 0) {
+                            atomicAdd(&st_lv[lv < 64 ? lv : 63], (unsigned long long)n);
+                            atomicAdd(&st_misc[1], (unsigned long long)n * (g.wp[lv] * (BF ? 2 : 4) + 4));
+                        }
+                        for (int base = 0; base < n; base += ppi) {
+                            const int i = base + lane / lpp;
+                            const bool act = i < n;
+                            const int ic = act ? i : n - 1;
+                            const uint32_t pc = pcode[ic];
+                            float sh = pS[ic];
+                            const int gq = (int)(pc >> 8), ss = (int)(pc & 255u);
+                            const float *qrow = qv.qy + (int64_t)qid_w[gq] * g.d_pad + g.mp[lv];
+                            const float b = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
+                            float part = 0.f;
+                            for (int c0 = sub; c0 < w4; c0 += 4 * lpp) {
+                                float4 xs[4], qs4[4];
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    const int cc = min(c0 + j * lpp, w4 - 1);
+                                    xs[j] = wave_ld4<BF>(lvbase, lvbase16, (int64_t)ss * g.wp[lv] + cc * 4);
+                                    qs4[j] = *reinterpret_cast<const float4 *>(qrow + cc * 4);
+                                }
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    if (c0 + j * lpp < w4) {
+                                        const float t0 = qs4[j].x - xs[j].x, t1 = qs4[j].y - xs[j].y,
+                                                    t2 = qs4[j].z - xs[j].z, t3 = qs4[j].w - xs[j].w;
+                                        part = __builtin_fmaf(t0, t0, part);
+                                        part = __builtin_fmaf(t1, t1, part);
+                                        part = __builtin_fmaf(t2, t2, part);
+                                        part = __builtin_fmaf(t3, t3, part);
+                                    }
+                                }
+                            }
+                            if (lpp >= 2) part += __shfl_xor(part, 1, 64);
+                            if (lpp >= 4) part += __shfl_xor(part, 2, 64);
+                            sh += part;
+                            // the bound after this level (Eq. 3 / Eq. 4 with the
+                            // certified margin)
+                            const float a = last ? 0.f : qtl[gq * L + lv + 1];
+                            const float dt = a - b;
+                            const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + A_w[gq];
+                            const float ct = c.mg.c_tail * (a + b) * (a + b);
+                            const float th = thr_w[gq];
+                            bool pruned;
+                            if (BF) {
+                                const float delta = c.ub * tl[ss] + 1e-37f;
+                                pruned = bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct > th;
+                            } else {
+                                pruned = (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
+                            }
+                            const bool keep = act && !pruned && sub == 0;
+                            const uint64_t bal = __ballot(keep);
+                            if (keep) {
+                                const int pos = nout + __popcll(bal & below);
+                                pcode[pos] = (uint16_t)pc;
+                                pS[pos] = sh;
+                            }
+                            nout += __popcll(bal);
+                        }
+                        n = nout;
+                        wave_sync();
+                    }
+                    if (n == 0) continue;
+                    // ---- commit the survivors: append those that can reach the
+                    // final band to their query's result buffer, keep the k
+                    // best distances, publish the threshold
+                    uint32_t qm = 0;
+                    for (int base = 0; base < n; base += 64) {
+                        const int i = base + lane;
+                        if (i < n) qm |= 1u << (pcode[i] >> 8);
+                    }
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) qm |= (uint32_t)__shfl_xor((int)qm, o, 64);
+                    while (qm) {
+                        const int gq = __builtin_ctz(qm);
+                        qm &= qm - 1u;
+                        const int qq = qid_w[gq];
+                        float th = thr_w[gq];
+                        const float Aqq = A_w[gq];
+                        int cntk = kc_w[gq];
+                        bool ovf = false;
+                        for (int base = 0; base < n; base += 64) {
+                            const int i = base + lane;
+                            const uint32_t pc = i < n ? pcode[i] : 0xffffu;
+                            const bool f = i < n && (int)(pc >> 8) == gq;
+                            const float D = f ? fmaxf(pS[i], 0.f) : 0.f;
+                            const bool keep = f && dist_lower(D, Aqq, c.mg, c.bfdelta) <= th;
+                            const uint64_t bal = __ballot(keep);
+                            const int nk = __popcll(bal);
+                            if (nk == 0) continue;
+                            int bpos = 0;
+                            if (lane == 0) bpos = atomicAdd(&wk.buf_cnt[qq], nk);
+                            bpos = __shfl(bpos, 0, 64);
+                            const int rk = __popcll(bal & below);
+                            if (keep) {
+                                const int dst = bpos + rk;
+                                const int32_t id = ix.ids[gb * g.B + (pc & 255u)];
+                                if (dst < c.capq) wk.buf[(int64_t)qq * c.capq + dst] = make_key(D, id);
+                                else ovf = true;
+                            }
+                            // the k best distances so far
+                            for (int j = lane; j < cntk; j += 64) sb[j] = kb[gq * c.k + j];
+                            if (keep) sb[cntk + rk] = D;
+                            const int tn = cntk + nk;
+                            const int P2 = next_pow2(tn);
+                            for (int j = tn + lane; j < P2; j += 64) sb[j] = INFINITY;
+                            wave_sync();
+                            wave_bitonic_sort_f(sb, P2, lane);
+                            wave_sync();
+                            cntk = min(c.k, tn);
+                            for (int j = lane; j < cntk; j += 64) kb[gq * c.k + j] = sb[j];
+                            if (cntk == c.k) th = fminf(th, prune_threshold(sb[c.k - 1], E_w[gq], Aqq, c.mg, c.bfdelta));
+                            wave_sync();
+                        }
+                        const bool anyovf = __ballot(ovf) != 0ull;
+                        if (lane == 0) {
+                            kc_w[gq] = cntk;
+                            thr_w[gq] = th;
+                            if (th < INFINITY) atomic_min_nonneg(&wk.thr[qq], th);
+                            if (anyovf) atomicOr(&wk.flags[qq], FLAG_OVERFLOW);
+                        }
+                        wave_sync();
+                    }
                 }
             }
         }
-        // ---- append the survivors to the segment
-        int tot;
-        int off = block_exclusive_scan(__popc(mask), wave_tmp, &tot);
-        if (wk.stats && tid == 0) {
-            st_misc[0] += 1;
-            st_lv[0] += (unsigned long long)cnt * ng;
-            st_misc[1] += (unsigned long long)cnt * (g.wp[0] * (BF ? 2 : 4) + 8);
-        }
-#pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            if (!(mask & (1u << b))) continue;
-            const int nt = b >> 2, v = b & 3;
-            seg[seg_n + off] = make_uint4((uint32_t)qid_s[4 * kq + v], (uint32_t)gb, __float_as_uint(sval[b]),
-                                          (uint32_t)(slot0 + nt * 16 + r16));
-            ++off;
-        }
-        seg_n += tot;
+    }
+    if (STATS && wk.stats) {
         __syncthreads();
-    }
-    if (seg_n > 0) walk();
-    if (wk.stats && tid == 0) {
-        atomicAdd(&wk.stats[ST_ITEMS], st_misc[0]);
-        atomicAdd(&wk.stats[ST_BYTES], st_misc[1]);
-        for (int i = 0; i < 64 && i < g.L; ++i)
+        for (int i = tid; i < 64; i += NT)
             if (st_lv[i]) atomicAdd(&wk.stats[ST_LEVEL + i], st_lv[i]);
+        if (tid == 0) {
+            atomicAdd(&wk.stats[ST_ITEMS], st_misc[0]);
+            atomicAdd(&wk.stats[ST_BYTES], st_misc[1]);
+        }
     }
 }
 
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SEG_WAVES, SEG_WAVES))) void k_scan_seg(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave(SearchConsts c, IndexView ix,
+                                                                                            QueryView qv, WorkView wk)
+{
+    wave_scan_body<true, false, false>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_stats(SearchConsts c,
+                                                                                                  IndexView ix,
+                                                                                                  QueryView qv,
+                                                                                                  WorkView wk)
+{
+    wave_scan_body<true, false, true>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_bf16(SearchConsts c,
+                                                                                                 IndexView ix,
+                                                                                                 QueryView qv,
+                                                                                                 WorkView wk)
+{
+    wave_scan_body<true, true, false>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_bf16_stats(
     SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
 {
-    seg_body<false>(c, ix, qv, wk);
+    wave_scan_body<true, true, true>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_brute(SearchConsts c,
+                                                                                                  IndexView ix,
+                                                                                                  QueryView qv,
+                                                                                                  WorkView wk)
+{
+    wave_scan_body<false, false, false>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_brute_stats(
+    SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    wave_scan_body<false, false, true>(c, ix, qv, wk);
 }
 
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SEG_WAVES, SEG_WAVES))) void k_scan_seg_bf16(
-    SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
-{
-    seg_body<true>(c, ix, qv, wk);
-}
 
 // ================================================================ merge
 // Distance bits of the k-th smallest of n keys in global memory: radix
@@ -2091,6 +2482,21 @@ namespace pano {
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Workgroups of NT threads that fit on one compute unit for this kernel and
+// dynamic LDS (at least 1), cached per kernel and size.
+static std::mutex g_occ_mu;
+static int resident_blocks(const void *kern, size_t shm)
+{
+    static std::vector<std::pair<std::pair<const void *, size_t>, int>> cache;
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    for (auto &e : cache)
+        if (e.first.first == kern && e.first.second == shm) return e.second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, shm) != hipSuccess || nb < 1) nb = 1;
+    cache.push_back({{kern, shm}, nb});
+    return nb;
+}
+
 static std::mutex g_fixed_mu;
 static void *g_fixed_ptr[MAX_DEVICES];
 
@@ -2124,12 +2530,9 @@ struct Carver {
 
 // Launch constants and scratch sizes of one search (no device work).
 struct SearchPlan {
-    size_t need[7];     // bytes of scratch slots 0..3, of the split scan's pair list and item table,
-                        // and the bound on the exact fallback's key buffer (one query)
-    bool split;         // split scan (filter kernel + per-pair walk) instead of the persistent scan
-    int grid_seg;       // workgroups of the split scan
-    int64_t seg_cap;    // pairs per workgroup segment
-    int64_t items_max;  // work items the item table holds
+    size_t need[7];     // bytes of scratch slots 0..3 (4, 5 unused) and the bound on the exact
+                        // fallback's key buffer (one query)
+    bool wave;          // per-wave scan (every wavefront its own worker)
 };
 
 // Probe slots per query: nprobe_all (at most nlist) for a common probe count;
@@ -2147,7 +2550,8 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     // scan mode 3: every candidate's full distance, no pruning (the brute-force
     // scan), chosen by the tuner where the bounds prune too little to pay
     if (prm && prm->reserved[1] == 3) brute = true;
-    PANO_REQUIRE(!prm || (prm->reserved[1] >= 0 && prm->reserved[1] <= 3), "scan mode must be 0, 1, 2 or 3");
+    PANO_REQUIRE(!prm || (prm->reserved[1] >= 0 && prm->reserved[1] <= 4 && prm->reserved[1] != 2),
+                 "scan mode must be 0, 1, 3 or 4");
     PANO_REQUIRE(k <= 128, "k up to 128 is supported");
     const int d = ix->d, L = ix->L, nlist = ix->nlist;
     size_t *need = pl.need;
@@ -2162,29 +2566,26 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     while (G > 1 && G * c.kc > 2048) G >>= 1;
     if (prm && prm->group > 0) G = std::min(prm->group, G);
     c.G = G;
-    // scan mode: 1 = persistent scan (dense levels, per-pair walk and local
-    // top-k in one kernel), 2 = segmented split scan (level-1 filter into a
-    // per-workgroup segment, then level-synchronous passes over it, d_k from
-    // the seeding only); 0 = the persistent scan, the faster of the two on
-    // the workloads measured
+    // scan mode: 0 or 1 = the workgroup scan (dense levels, per-pair walk
+    // and local top-k per work item), 4 = the per-wave scan (every wavefront
+    // its own worker, survivors appended to the result buffers)
     const int mode_req = prm ? prm->reserved[1] : 0;
-    pl.split = !brute && L >= 2 && mode_req == 2;
-    // the split scan's filter works on one block per item; the persistent
-    // scan gives a query group at most 32 items per list
-    c.bpi = pl.split ? 1 : ((prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1);
-    c.item_cap = pl.split ? 0 : 32;
-    // Per-query result buffer: a work item of the persistent scan publishes
+    pl.wave = mode_req == 4;
+    c.wl = wave_lds_layout(L, k);
+    // a query group meets at most 32 work items per list
+    c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1;
+    c.item_cap = 32;
+    // Per-query result buffer: a work item of the workgroup scan publishes
     // about k entries (its local best k and their margin band), and a query
     // meets about nprobe * ceil(mean blocks per list / bpi) work items (at
-    // most 32 per list); the split scan publishes its surviving pairs.  Twice
-    // the estimate, within [2048, 65536] (at least 32768 for the split scan)
-    // and 4 GiB over the batch; a query that still overflows takes the exact
-    // fallback.
+    // most 32 per list); the per-wave scan appends its surviving pairs.
+    // Twice the estimate, within [2048, 65536] and 4 GiB over the batch; a
+    // query that still overflows takes the exact fallback.
     {
         const int np_est = per_query_np ? std::min(nlist, 128) : std::min(nprobe_all, nlist);
         const double mean_blk = (double)ix->list_blk.back() / std::max(1, nlist);
         const double items = (double)np_est * (std::min(32.0, std::ceil(mean_blk / c.bpi)) + 1.0);
-        const double want = std::max(2.0 * items * (k + 8), pl.split ? 32768.0 : 0.0);
+        const double want = 2.0 * items * (k + 8);
         int64_t cap = 2048;
         while (cap < want && cap < 65536) cap <<= 1;
         while (cap > 2048 && (double)cap * 8.0 * (double)nq > 4.0 * 1073741824.0) cap >>= 1;
@@ -2225,16 +2626,13 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
     const int np_max = probe_cap(per_query_np, nprobe_all, nlist);
     need[0] = align_up(sizeof(float) * nq * ix->d_pad) + align_up(sizeof(float) * nq * L) +
-              2 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
+              3 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
     need[1] = nlist > 1 ? align_up(sizeof(float) * nq * nlist) : 256;
     need[2] = align_up(sizeof(int32_t) * nq * np_max) * 2 + align_up(sizeof(int32_t) * nq) +
               2 * align_up(sizeof(int32_t) * nlist) + align_up(sizeof(int32_t) * 8) +
               align_up(sizeof(int64_t) * (nlist + 1)) + align_up(sizeof(int64_t) * (8 * c.ceil8 + 1));
     need[3] = 4 * align_up(sizeof(float) * nq) + align_up(sizeof(uint64_t) * nq * c.capq) +
               align_up(sizeof(unsigned long long) * 128);
-    pl.grid_seg = 0;
-    pl.seg_cap = 0;
-    pl.items_max = 0;
     need[4] = need[5] = 0;
     {
         // the exact fallback of one query: its probed list ids and one 64-bit
@@ -2242,26 +2640,6 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
         const int64_t s_np = ix->top_blk_prefix[std::min<int64_t>(np_max, nlist)];
         need[6] = align_up(sizeof(int32_t) * (size_t)std::max(1, np_max)) +
                   align_up(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, s_np * ix->B));
-    }
-    if (pl.split) {
-        // one segment per workgroup: room for at least two items' worth of
-        // survivors (a full segment is walked before the next item), sized
-        // for an eighth of the candidates passing the first level, at most
-        // 2 GiB in all
-        pl.grid_seg = (prm && prm->grid > 0) ? prm->grid : ix->ctx->num_cu * SEG_WAVES;
-        const int np_est = per_query_np ? std::min(nlist, 128) : std::min(nprobe_all, nlist);
-        const double mean_len = (double)ix->n / std::max(1, nlist);
-        const double want = (double)nq * np_est * mean_len / 8.0 / pl.grid_seg;
-        int64_t cap = 2LL * c.G * ix->B;
-        while (cap < want && cap < 65536) cap <<= 1;
-        while (cap > 2LL * c.G * ix->B && (double)cap * pl.grid_seg * 16.0 > 2.0 * 1073741824.0) cap >>= 1;
-        pl.seg_cap = cap;
-        need[4] = align_up(sizeof(uint4) * (size_t)(pl.seg_cap * pl.grid_seg));
-        // item table: sum over lists of ceil(queries / G) * blocks is at most
-        // nq * (blocks of the np_max largest lists) / G + all blocks
-        const int64_t s_np = ix->top_blk_prefix[std::min<int64_t>(np_max, nlist)];
-        pl.items_max = ((int64_t)nq * s_np + c.G - 1) / c.G + ix->nblocks;
-        need[5] = align_up(sizeof(int4) * (size_t)std::max<int64_t>(1, pl.items_max));
     }
 }
 
@@ -2339,13 +2717,13 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     PANO_REQUIRE(ctx->device == ix->ctx->device, "context and index are on different devices");
     PANO_HIP(hipSetDevice(ctx->device));
     if (prm && prm->reserved[1] == 3) brute = true;  // scan mode 3: no pruning
+    const bool wave = prm && prm->reserved[1] == 4;
     const int d = ix->d, L = ix->L, nlist = ix->nlist;
     SearchConsts c;
     SearchPlan pl;
     plan_search(ix, nq, k, nprobe_dev != nullptr, nprobe_all, eps, prm, brute, c, pl);
     const size_t *need = pl.need;
     const bool use_bf16 = c.bf16 != 0;
-    const bool split = pl.split;
     // Absolute margin of the dot-product form: the bfloat16 scan splits each
     // query value into two bfloat16 terms and reads rows of norm up to
     // (1 + u_b) ||x||, which its own constant covers.
@@ -2361,7 +2739,9 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     const int np_max = probe_cap(nprobe_dev != nullptr, nprobe_all, nlist);
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
     const bool want_timing = !want_stats && (flags & PANO_SEARCH_TIMING) != 0;
-    const bool seed_on = !brute && eps >= 1.f;
+    // the seeding gives the brute-force scan its starting threshold too (it
+    // then commits fewer candidates; every distance is still computed)
+    const bool seed_on = eps >= 1.f;
     // ---- scratch: the context's buffers (grown on demand), or consecutive
     // regions of the caller's fixed memory
     const size_t need0 = need[0], need1 = need[1], need2 = need[2], need3 = need[3];
@@ -2381,18 +2761,10 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         sp[1] = cf.take<char>(need1);
         sp[2] = cf.take<char>(need2);
         sp[3] = cf.take<char>(need3);
-        sp[5] = cf.take<char>(need[4]);
-        sp[6] = cf.take<char>(need[5]);
         sp[4] = cf.take<char>(need[6]);
         flags_dev = cf.take<int32_t>(nq);
         fb_total = cf.take<int64_t>(1);
     } else {
-        if (split) {
-            ctx->scratch[5].ensure(need[4]);
-            ctx->scratch[6].ensure(need[5]);
-            sp[5] = ctx->scratch[5].p;
-            sp[6] = ctx->scratch[6].p;
-        }
         ctx->scratch[0].ensure(need0);
         ctx->scratch[1].ensure(need1);
         ctx->scratch[2].ensure(need2);
@@ -2406,6 +2778,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     float *qA = c0.take<float>(nq);
     int32_t *qbad = c3.take<int32_t>(nq);
     double *vnorm = c0.take<double>(nq);
+    float *qn2 = c0.take<float>(nq);
     float *Sco = reinterpret_cast<float *>(sp[1]);
     int32_t *probes = c2.take<int32_t>(nq * np_max);
     int32_t *list_q = c2.take<int32_t>(nq * np_max);
@@ -2430,13 +2803,32 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     const size_t coarse_shm = per_wave * wpb;
     PANO_REQUIRE(nlist == 1 || coarse_shm <= 160 * 1024, "nlist too large for the coarse step");
     const size_t merge_shm = sizeof(uint64_t) * MERGE_LDS_KEYS + sizeof(float) * (size_t)d;
-    const size_t scan_shm = sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
+    const size_t scan_shm = wave ? (size_t)(NT / 64) * c.wl.bytes
+                                 : sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
     // the coarse kernel instance compiled for at most this many lists
     auto coarse_kernel = nlist <= 1024 ? k_coarse<1024> : (nlist <= 4096 ? k_coarse<4096> : k_coarse<(1 << 30)>);
     if (nlist > 1)
         PANO_HIP(hipFuncSetAttribute((const void *)coarse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)coarse_shm));
     PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_shm));
+    // query groups ordered by distance to the list (reserved[4] = 1 keeps the
+    // arrival order); at most 16384 queries of a list are ordered
+    const bool sort_groups = nlist > 1 && !(prm && prm->reserved[4] == 1) && nq > c.G;
+    const int sort_cap = (int)std::min<int64_t>(nq, 16384);
+    const size_t sort_shm = sizeof(uint64_t) * (size_t)next_pow2(sort_cap);
+    if (sort_groups)
+        PANO_HIP(hipFuncSetAttribute((const void *)k_wl_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_shm));
+    // the per-wave scan instance of this search (and its counting twin)
+    typedef void (*ScanKernel)(SearchConsts, IndexView, QueryView, WorkView);
+    const ScanKernel wave_kern = brute ? k_scan_wave_brute : (use_bf16 ? k_scan_wave_bf16 : k_scan_wave);
+    const ScanKernel wave_kern_stats =
+        brute ? k_scan_wave_brute_stats : (use_bf16 ? k_scan_wave_bf16_stats : k_scan_wave_stats);
+    if (wave) {
+        PANO_REQUIRE(scan_shm <= 160 * 1024, "k and L too large for the per-wave scan's LDS");
+        PANO_HIP(hipFuncSetAttribute((const void *)wave_kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)scan_shm));
+        PANO_HIP(hipFuncSetAttribute((const void *)wave_kern_stats, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)scan_shm));
+    }
     // per-query flag words written by the merge: pinned host memory, or the
     // fixed scratch (read back in chunks)
     int32_t *h_flags = flags_dev;
@@ -2448,15 +2840,6 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
                  ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
     QueryView qv{qy, qtail, qE, qA, q};
     WorkView wk{list_cnt, list_qoff, list_q, item_off, heads, thr, buf, buf_cnt, qflags, nullptr};
-    int4 *items = nullptr;
-    if (split) {
-        Carver c5(sp[5]);
-        wk.pairs = c5.take<uint4>(pl.seg_cap * pl.grid_seg);
-        wk.seg_cap = pl.seg_cap;
-        items = reinterpret_cast<int4 *>(sp[6]);
-        wk.items = items;
-        wk.items_max = pl.items_max;
-    }
 
     // Every device step of one search, on stream st (and, with seeding, two
     // more branches).  No memset nodes: buffers are cleared by kernels so the
@@ -2530,7 +2913,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         if (nlist > 1) {
             hipLaunchKernelGGL(coarse_kernel, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
                                ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq,
-                               nprobe_dev, nprobe_all, c_co, np_max, probes, npq, list_cnt);
+                               nprobe_dev, nprobe_all, c_co, np_max, probes, npq, list_cnt, qn2);
         } else {
             hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, np_max, probes,
                                npq, list_cnt);
@@ -2554,9 +2937,9 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             hipLaunchKernelGGL(k_wl_fill, dim3(wl_grid), dim3(256), 0, st, nq, np_max, probes, npq, list_qoff,
                                list_fill, list_q);
         }
-        if (split)
-            hipLaunchKernelGGL(k_wl_items, dim3((unsigned)(8 * c.ceil8)), dim3(NT), 0, st, nlist, c.ceil8, c.G, c.bpi,
-                               list_cnt, ix->list_blk_d.as<int64_t>(), item_off, items, pl.items_max);
+        if (sort_groups)
+            hipLaunchKernelGGL(k_wl_sort, dim3((unsigned)nlist), dim3(NT), sort_shm, st, nlist, list_cnt, list_qoff,
+                               list_q, Sco, qn2, ix->cent.as<float>() + (size_t)nlist * d, sort_cap);
         if (fork) {
             PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
             PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join2, 0));
@@ -2564,16 +2947,15 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         if (events_on) PANO_HIP(hipEventRecord(ctx->ev[1], st));
         WorkView w2 = wk;
         w2.stats = stats_on ? stats : nullptr;
-        if (brute) {
+        if (wave) {
+            auto kern = stats_on ? wave_kern_stats : wave_kern;
+            const int wgrid = (prm && prm->grid > 0) ? prm->grid : ctx->num_cu * resident_blocks((const void *)kern, scan_shm);
+            hipLaunchKernelGGL(kern, dim3(wgrid), dim3(NT), scan_shm, st, c, iv, qv, w2);
+        } else if (brute) {
             if (stats_on)
                 hipLaunchKernelGGL(k_scan_brute_stats, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
             else
                 hipLaunchKernelGGL(k_scan_brute, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
-        } else if (split) {
-            if (use_bf16)
-                hipLaunchKernelGGL(k_scan_seg_bf16, dim3(pl.grid_seg), dim3(NT), 0, st, c, iv, qv, w2);
-            else
-                hipLaunchKernelGGL(k_scan_seg, dim3(pl.grid_seg), dim3(NT), 0, st, c, iv, qv, w2);
         } else if (use_bf16) {
             if (stats_on)
                 hipLaunchKernelGGL(k_scan_pruned_bf16_stats, dim3(grid), dim3(NT), scan_shm, st, c, iv, qv, w2);
@@ -2614,8 +2996,8 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         enqueue(ws, want_stats, true);
     } else if (use_graph) {
         GraphKey key{ix->serial, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
-                     c.dense_min, c.bf16, split ? 1 : 0, c.walk_lanes, c.walk2, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
-                     split ? ctx->scratch[5].p : nullptr, split ? ctx->scratch[6].p : nullptr, ctx->pinned};
+                     c.dense_min, c.bf16, (wave ? 2 : 0) | (sort_groups ? 4 : 0), c.walk_lanes, c.walk2, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
+                     nullptr, nullptr, ctx->pinned};
         if (!ctx->graph_exec || !(ctx->graph_key == key)) {
             ctx->drop_graph();
             hipGraph_t graph;

@@ -33,6 +33,43 @@ struct UniformF4 {
 };
 __device__ inline UniformF4 uniform_f4(const float *p) { return UniformF4{p}; }
 
+constexpr int WAVE_PAIRS = 512;  // pair list of one wavefront in the per-wave scan
+
+// LDS of one wavefront of the per-wave scan: byte offsets of its arrays.
+struct WaveLds {
+    int qid, thr, A, E, kc;  // [16] each: query ids, thresholds, margins, k-best counts
+    int qtl;                 // [16][L] query tail norms
+    int kb;                  // [16][k] the k best committed distances per query
+    int sb;                  // [next_pow2(k + 64)] sort buffer
+    int code, pS;            // [WAVE_PAIRS] pair codes (query << 8 | slot), partial distances
+    int bytes;
+};
+__host__ __device__ inline int wl_take(int &o, int b)
+{
+    const int r = o;
+    o += (b + 15) & ~15;
+    return r;
+}
+__host__ __device__ inline WaveLds wave_lds_layout(int L, int k)
+{
+    WaveLds w{};
+    int o = 0;
+    w.qid = wl_take(o, 64);
+    w.thr = wl_take(o, 64);
+    w.A = wl_take(o, 64);
+    w.E = wl_take(o, 64);
+    w.kc = wl_take(o, 64);
+    w.qtl = wl_take(o, 16 * L * 4);
+    w.kb = wl_take(o, 16 * k * 4);
+    int p = 1;
+    while (p < k + 64) p <<= 1;
+    w.sb = wl_take(o, p * 4);
+    w.code = wl_take(o, WAVE_PAIRS * 2);
+    w.pS = wl_take(o, WAVE_PAIRS * 4);
+    w.bytes = o;
+    return w;
+}
+
 // Scalars of one search, passed by value.
 struct SearchConsts {
     int k;
@@ -54,6 +91,7 @@ struct SearchConsts {
     float one_m_eps2;  // 2 (1 - eps)
     Margins mg;
     LevelGeom g;
+    WaveLds wl;        // per-wave scan: LDS layout of one wavefront
 };
 
 // Canonical distance: sequential FP64 sum of ((double)q_j - (double)x_j)^2,
@@ -239,6 +277,28 @@ __device__ inline void wave_bitonic_sort(volatile uint64_t *buf, int n, int lane
                     if ((a > b) == up) {
                         buf[i] = b;
                         buf[ixj] = a;
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// The same for non-negative floats (and +inf), compared as bit patterns.
+__device__ inline void wave_bitonic_sort_f(volatile float *buf, int n, int lane)
+{
+    volatile uint32_t *u = reinterpret_cast<volatile uint32_t *>(buf);
+    for (int kk = 2; kk <= n; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < n; i += 64) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    uint32_t a = u[i], b = u[ixj];
+                    bool up = (i & kk) == 0;
+                    if ((a > b) == up) {
+                        u[i] = b;
+                        u[ixj] = a;
                     }
                 }
             }

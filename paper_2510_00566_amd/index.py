@@ -124,9 +124,10 @@ class Params:
     grid: int = 0
     use_bf16: int = 0
     dense_min: int = 0
-    scan_mode: int = 0  # 0/1 persistent scan, 2 segmented split scan, 3 no pruning (brute-force scan)
+    scan_mode: int = 0  # 0/1 workgroup scan, 3 no pruning (brute-force scan), 4 per-wave scan
     walk_lanes: int = 0  # lanes per pair in the per-pair walk: 1, 2, 4 (0 = by the number of pairs)
     walk_step: int = 0  # levels per step of the four-lane walk: 1 or 2 (0 = 2 when levels are <= 64 wide)
+    arrival_order: int = 0  # 1: keep each list's queries in arrival order (0 = ordered by distance to the list)
 
     def c(self):
         p = L.SearchParams()
@@ -136,6 +137,7 @@ class Params:
         p.reserved[1] = self.scan_mode
         p.reserved[2] = self.walk_lanes
         p.reserved[3] = self.walk_step
+        p.reserved[4] = self.arrival_order
         return p
 
 

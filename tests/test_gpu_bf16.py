@@ -70,7 +70,8 @@ BF16_GRID = [
     dict(use_bf16=1, blocks_per_item=4, dense_min=32),
     dict(use_bf16=1, blocks_per_item=3, group=8, dense_min=1 << 30),
     dict(use_bf16=1, group=1, seed_pool=256, seed_count=16, grid=5),
-    dict(use_bf16=1, scan_mode=2),
+    dict(use_bf16=1, scan_mode=4),
+    dict(use_bf16=1, scan_mode=4, dense_min=1 << 30, group=8),
 ]
 
 

@@ -101,9 +101,11 @@ PARAM_GRID = [
     dict(blocks_per_item=8, group=4, seed_pool=256, seed_count=16),
     dict(blocks_per_item=4, dense_min=1 << 30),
     dict(blocks_per_item=2, group=1, grid=7),
-    dict(scan_mode=2),
-    dict(scan_mode=2, group=4, grid=5),
+    dict(scan_mode=4),
+    dict(scan_mode=4, group=4, grid=5, dense_min=1),
+    dict(scan_mode=4, blocks_per_item=3, dense_min=1 << 30, arrival_order=1),
     dict(scan_mode=3),
+    dict(arrival_order=1),
     dict(walk_lanes=1),
     dict(walk_lanes=2),
     dict(walk_lanes=4, walk_step=1),
