@@ -74,7 +74,7 @@ class Run:
         npv = w.nprobe_range[1] if w.nprobe_range else w.nprobe
         self.sig = autotune.signature("gfx950", w.d, self.store, w.n, npv, w.k)
         prm, width = autotune.lookup(self.sig)
-        if width:
+        if width and w.tune_width:
             w.level_width = int(width)
         self.w = w
         t0 = time.time()
@@ -137,7 +137,8 @@ class Run:
         knobs, stored in the tuner's cache."""
         from paper_2510_00566_amd import autotune
         w = self.w
-        widths = (8, 16, 32) if w.d <= 256 else (w.level_width,)
+        # the configuration's widths {8, 16, 32}, where they give at most 64 levels
+        widths = tuple(wd for wd in (8, 16, 32) if -(-w.d // wd) <= 64) if w.tune_width else (w.level_width,)
         self.idx.free()
         best, prm, results = autotune.tune_level_width(lambda wd: self.build(self.tf, wd), self.qd, w.k, self.npd,
                                                        widths=widths, log=log, nprobe_max=self.np_max,
@@ -194,7 +195,7 @@ class Run:
         best = None
         for tag, bprm in (("same-decomposition", self.prm), ("default", Params()), ("per-wave", Params(scan_mode=4))):
             bprm = Params(**vars(bprm))
-            bprm.use_bf16 = 0
+            bprm.use_bf16 = self.use_bf16  # the same storage precision as the pruned scan
             bsteps = max(3, self.args.steps // 4)
             el = self.time_steps(lambda: self.idx.search_bruteforce(self.qd, w.k, nprobe=self.npd, params=bprm,
                                                                     out=(bi, bd), nprobe_max=self.np_max),
@@ -210,6 +211,29 @@ class Run:
             if best is None or rec["qps"] > best["qps"]:
                 best = rec
         return best
+
+    def precision_vs_f32(self, ref_ids, ref_d):
+        """The bfloat16 search against the FP32 search and the FP32 brute
+        force on the same index: times and whether the answers are equal."""
+        import torch
+        from paper_2510_00566_amd.index import Params
+        w = self.w
+        p32 = Params(**vars(self.prm))
+        p32.use_bf16 = 0
+        fi, fd = torch.empty_like(self.ids), torch.empty_like(self.dists)
+        el = self.time_steps(lambda: self.search(prm=p32, out=(fi, fd)), self.args.steps, self.args.warmup)
+        rec = {"f32_qps": w.nq * self.args.steps / el, "f32_ms_per_step": el * 1000 / self.args.steps,
+               "f32_params": vars(p32), "same_result_as_f32": bool(torch.equal(fi, ref_ids) and torch.equal(fd, ref_d))}
+        b32 = Params(**vars(self.prm))
+        b32.use_bf16 = 0
+        bsteps = max(3, self.args.steps // 4)
+        el = self.time_steps(lambda: self.idx.search_bruteforce(self.qd, w.k, nprobe=self.npd, params=b32,
+                                                                out=(fi, fd), nprobe_max=self.np_max),
+                             bsteps, max(1, self.args.warmup))
+        rec["f32_bruteforce_ms_per_step"] = el * 1000 / bsteps
+        rec["f32_bruteforce_same_result"] = bool(torch.equal(fi, ref_ids) and torch.equal(fd, ref_d))
+        log(f"[bench] precision {rec}")
+        return rec
 
     def parity(self, n):
         from oracle import brute
@@ -348,6 +372,8 @@ def measure(run: Run, args, primary: bool) -> dict:
                                  (float(v) for v in np.median(np.asarray(phases), axis=0)))),
         "fallback_queries": st["fallback_queries"],
     })
+    if run.use_bf16:
+        res["precision"] = run.precision_vs_f32(ids_ref, d_ref)
     if args.parity_sample > 0:
         res["parity"] = run.parity(args.parity_sample)
     if not args.no_secondary and w.nlist > 1 and run.transform_kind == "residual":
@@ -356,6 +382,129 @@ def measure(run: Run, args, primary: bool) -> dict:
         res["cpu_baseline"] = run.cpu_baseline(args.cpu_sample, args.cpu_single)
     torch.cuda.synchronize()
     return res
+
+
+def energy_alpha(y: np.ndarray) -> float:
+    """Decay rate alpha of the mean tail-energy profile E(m) of rows y in a
+    given basis (E(m) ~ exp(-alpha m / d), Section 4.1), fitted by least
+    squares through the origin on log E over the range E >= 1e-3."""
+    y = np.asarray(y, dtype=np.float64)
+    d = y.shape[1]
+    sq = y * y
+    tail = np.cumsum(sq[:, ::-1], axis=1)[:, ::-1]  # [n, d]: sum_{j >= m}
+    e = (tail / np.maximum(tail[:, :1], 1e-300)).mean(axis=0)
+    m = np.arange(d, dtype=np.float64)
+    ok = e >= 1e-3
+    xm, ly = m[ok] / d, np.log(e[ok])
+    return float(-(xm @ ly) / max(xm @ xm, 1e-300))
+
+
+def recall_at_k(ids: np.ndarray, ref: np.ndarray) -> float:
+    """Mean over queries of |ids ∩ ref| / k (padding -1 excluded from ref)."""
+    hits, tot = 0, 0
+    for a, b in zip(ids, ref):
+        bb = set(int(v) for v in b if v >= 0)
+        hits += len(bb.intersection(int(v) for v in a))
+        tot += len(bb)
+    return hits / max(1, tot)
+
+
+def eps_sweep(run: Run, args) -> dict:
+    """Eq. 4 relaxation: QPS and recall@k against the exact answer of the
+    oracle (O2, all queries) for each eps, with the speedup that Prop. 5.3
+    predicts, 1 / (1 + ln eps) (valid for eps > 1/e)."""
+    import math
+    from oracle import c_oracle
+    w = run.w
+    c_oracle.build(force=False)
+    nthreads = len(os.sched_getaffinity(0))
+    npv = run.data["nprobe"] if w.nprobe_range is not None else w.nprobe
+    probes = c_oracle.probe(run.q, run.c_np, npv, threads=nthreads) if w.nlist > 1 else \
+        [np.zeros(1, np.int64) for _ in range(w.nq)]
+    off, cand = c_oracle.candidates_csr(probes, c_oracle.list_members(run.a_np, w.nlist))
+    ref_i, _ = c_oracle.knn_lists(run.q, run.x, off, cand, w.k, threads=nthreads)
+    out = []
+    base = None
+    for eps in [float(v) for v in args.eps_values.split(",")]:
+        el = run.time_steps(lambda: run.idx.search(run.qd, w.k, nprobe=run.npd, eps=eps, params=run.prm,
+                                                   out=(run.ids, run.dists), nprobe_max=run.np_max),
+                            args.steps, args.warmup)
+        run.idx.search(run.qd, w.k, nprobe=run.npd, eps=eps, params=run.prm, out=(run.ids, run.dists),
+                       nprobe_max=run.np_max, stats=True)
+        st = run.idx.stats()
+        qps = w.nq * args.steps / el
+        base = qps if base is None else base
+        rec = {"eps": eps, "qps": qps, "ms_per_step": el * 1000 / args.steps,
+               "recall": recall_at_k(run.ids.cpu().numpy(), ref_i),
+               "phi": st["dims_read"] / max(1, st["candidates"] * w.d),
+               "speedup_vs_eps1": qps / base,
+               "predicted_speedup": (1.0 / (1.0 + math.log(eps))) if eps > math.exp(-1) else None}
+        log(f"[bench] eps sweep {rec}")
+        out.append(rec)
+    return {"mode": "eps_sweep", "workload": w.name, "recall_reference": "oracle O2 (C), all queries",
+            "params": vars(run.prm), "alpha": run.tf.get()[3], "sweep": out}
+
+
+def ood_sweep(run: Run, args) -> dict:
+    """Out-of-distribution queries (Prop. 5.2): the same index searched with
+    queries whose spectrum decays more slowly than the data's.  For each query
+    law: alpha_q of the queries' energy profile in the data's PCA basis,
+    alpha_eff = (alpha_q + alpha_x) / 2, the fraction of dimensions read and
+    its ratio to the in-distribution one against the predicted
+    alpha_x / alpha_eff, QPS against the brute-force scan, parity against the
+    oracle on a sample (the answer stays exact)."""
+    import dataclasses
+    import torch
+    from paper_2510_00566_amd import synth
+    from paper_2510_00566_amd.index import Params
+    w0 = run.w
+    mu, t64, _, _ = run.tf.get()
+    # the data's alpha in its own PCA basis: residuals of sampled rows to their list centroids
+    samp = np.random.Generator(np.random.PCG64(5)).choice(w0.n, min(w0.n, 20000), replace=False)
+    yx = (run.x[samp].astype(np.float64) - run.c_np[run.a_np[samp]] - mu) @ t64.T
+    alpha_x = energy_alpha(yx)
+    out, phi0 = [], None
+    for qp in [float(v) for v in args.ood_q_spec.split(",")]:
+        wq = dataclasses.replace(w0, q_spec_p=qp)
+        qdat = synth.queries(wq)
+        q = qdat["q"]
+        qd = torch.from_numpy(q).cuda()
+        # the queries' energy in the data's basis, around the nearest centroid
+        nearest = np.argmin(np.maximum((q.astype(np.float64) ** 2).sum(1)[:, None]
+                                       + (run.c_np.astype(np.float64) ** 2).sum(1)[None, :]
+                                       - 2.0 * q.astype(np.float64) @ run.c_np.astype(np.float64).T, 0), axis=1)
+        yq = (q.astype(np.float64) - run.c_np[nearest] - mu) @ t64.T
+        alpha_q = energy_alpha(yq)
+        el = run.time_steps(lambda: run.idx.search(qd, w0.k, nprobe=run.npd, params=run.prm, out=(run.ids, run.dists),
+                                                   nprobe_max=run.np_max), args.steps, args.warmup)
+        run.idx.search(qd, w0.k, nprobe=run.npd, params=run.prm, out=(run.ids, run.dists), nprobe_max=run.np_max,
+                       stats=True)
+        st = run.idx.stats()
+        phi = st["dims_read"] / max(1, st["candidates"] * w0.d)
+        phi0 = phi if phi0 is None else phi0
+        bi, bd = torch.empty_like(run.ids), torch.empty_like(run.dists)
+        bprm = Params(**vars(run.prm))
+        bsteps = max(3, args.steps // 4)
+        elb = min(run.time_steps(lambda: run.idx.search_bruteforce(qd, w0.k, nprobe=run.npd, params=bp, out=(bi, bd),
+                                                                   nprobe_max=run.np_max), bsteps, 1)
+                  for bp in (bprm, Params(scan_mode=4)))
+        from oracle import brute
+        smp = np.sort(np.random.Generator(np.random.PCG64(99)).choice(w0.nq, min(args.parity_sample, w0.nq),
+                                                                      replace=False))
+        ri, rd, _ = brute.knn_ivf(q[smp], run.x, run.c_np, run.a_np, w0.nprobe, w0.k)
+        gi = run.ids.cpu().numpy()[smp]
+        aeff = 0.5 * (alpha_q + alpha_x)
+        rec = {"q_spec_p": qp, "alpha_q": alpha_q, "alpha_x": alpha_x, "alpha_eff": aeff,
+               "qps": w0.nq * args.steps / el, "speedup_vs_bruteforce": (bsteps / elb) / (args.steps / el),
+               "phi": phi, "phi_ratio_to_in_distribution": phi / phi0,
+               "predicted_phi_ratio": None,
+               "parity": {"queries": int(smp.size), "id_mismatch_queries": int((gi != ri).any(axis=1).sum())}}
+        if out:
+            rec["predicted_phi_ratio"] = out[0]["alpha_eff"] / aeff
+        log(f"[bench] ood {rec}")
+        out.append(rec)
+        del qd
+    return {"mode": "ood", "workload": w0.name, "params": vars(run.prm), "sweep": out}
 
 
 def main():
@@ -381,6 +530,12 @@ def main():
                     help="bf16: keep bfloat16 level slices and scan them (certified margin, FP32 rescoring)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (to calibrate HBM byte counters)")
+    ap.add_argument("--eps-sweep", action="store_true",
+                    help="QPS and recall@k against the oracle for each eps of --eps-values (Eq. 4, Prop. 5.3)")
+    ap.add_argument("--eps-values", default="1,0.95,0.9,0.8,0.7,0.6,0.5,0.4")
+    ap.add_argument("--ood", action="store_true",
+                    help="out-of-distribution queries (Prop. 5.2): query spectra of --ood-q-spec on the same index")
+    ap.add_argument("--ood-q-spec", default="0.01,0.005,0.0025,0.001,0")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the search path here is single-GPU "
@@ -399,6 +554,10 @@ def main():
     from paper_2510_00566_amd.index import Context
 
     ctx = Context(0)
+    if args.eps_sweep or args.ood:
+        run = Run(args.workload, args, ctx)
+        print(json.dumps(eps_sweep(run, args) if args.eps_sweep else ood_sweep(run, args)))
+        return
     run = Run(args.workload, args, ctx)
     prim = measure(run, args, primary=True)
     w = run.w

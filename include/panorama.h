@@ -233,6 +233,27 @@ pano_status pano_search_ctx(pano_ctx *ctx, pano_index *idx, const float *q_dev, 
                             void *stream);
 
 /*
+ * refine: k nearest neighbours of each query among its own candidate ids
+ * (a first pass's top-kprime, e.g. from a quantized index), with the
+ * point-centric form of Algorithm 1 (batch B = 1 in the table of the two
+ * modes; Section 6.4, Refine): candidates are taken in groups of 64 in the
+ * given order, each refined level by level from the index's level-major
+ * blocks and dropped at its first level whose bound (Eq. 3; Eq. 4 for
+ * eps < 1) exceeds the query's running d_k; the first group seeds d_k.
+ * q_dev [nq][d] float32; cand_dev [nq][kprime] int64 row ids of
+ * build_levels' x, -1 for an empty slot; the ids of one row must be
+ * distinct.  Outputs ids_dev [nq][k] int64 and dists_dev [nq][k] float32
+ * (canonical D, ascending (D, id); -1 / +inf padding).  At eps = 1 the
+ * result is the exact k-NN over the candidate set.  Runs on the index's
+ * context, after the work queued on `stream`; returns when done.  Errors:
+ * EINVAL if k < 1, kprime < 1, eps outside [0, 1], a query is non-finite or
+ * a candidate id is outside [-1, n).  The first call on an index builds a
+ * map from row id to block position (8 bytes per row, kept by the index).
+ */
+pano_status pano_refine(pano_index *idx, const float *q_dev, int64_t nq, int32_t k, const int64_t *cand_dev,
+                        int32_t kprime, float eps, int64_t *ids_dev, float *dists_dev, void *stream);
+
+/*
  * search_noalloc: pano_search for callers that cannot allocate memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, semantics and results as pano_search without

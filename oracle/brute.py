@@ -134,3 +134,19 @@ def assignment_mismatches(xs: np.ndarray, centroids: np.ndarray, assign: np.ndar
             best = np.lexsort((lids, dd[r]))[0]
             bad += int(best != assign[s + r])
     return bad
+
+
+def knn_candidates(qs: np.ndarray, xs: np.ndarray, cand: np.ndarray, k: int):
+    """Refine (Section 6.4): exact k-NN of each query among its own candidate
+    ids cand [nq][k'] (a first pass's top-k'; -1 marks an empty slot), by the
+    (D, id) key.  Returns ids [nq,k] int64, dists [nq,k] float32."""
+    qs = np.atleast_2d(qs)
+    cand = np.atleast_2d(np.asarray(cand, dtype=np.int64))
+    out_i = np.full((qs.shape[0], k), -1, dtype=np.int64)
+    out_d = np.full((qs.shape[0], k), np.inf, dtype=np.float32)
+    for qi in range(qs.shape[0]):
+        ids = np.unique(cand[qi][cand[qi] >= 0])
+        if ids.size == 0:
+            continue
+        out_i[qi], out_d[qi] = topk_by_key(canonical_dist(qs[qi], xs[ids]), ids, k)
+    return out_i, out_d

@@ -177,6 +177,16 @@ def _crop(dist, ids, k):
     return ids[order], dist[order]
 
 
+def panorama_refine(q: np.ndarray, xs: np.ndarray, cand: np.ndarray, mu, t, m, k: int, eps: float = 1.0):
+    """Refine with the point-centric form of Algorithm 1 (Table of the two
+    modes: B = 1; Section 6.4): the query's candidate ids in their given order
+    (-1 entries skipped), each early-abandoned at its first level whose bound
+    exceeds the running d_k, which every survivor updates."""
+    cand = np.asarray(cand, dtype=np.int64)
+    ids = cand[cand >= 0]
+    return panorama_knn(q, xs[ids], ids, mu, t, m, k, batch=1, eps=eps)
+
+
 def ivf_candidates(probes, assign: np.ndarray) -> np.ndarray:
     """Candidate order for the IVF scan: probe rank, then position in the list
     (ascending row id)."""

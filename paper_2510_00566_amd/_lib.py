@@ -77,6 +77,7 @@ def lib():
         "pano_search_ctx": (C.c_int, [P, P, P, i64, i32, P, i32, f32, P, P, P, u32, P]),
         "pano_search_scratch_bytes": (C.c_int, [P, i64, i32, i32, i32, P, P]),
         "pano_search_noalloc": (C.c_int, [P, P, i64, i32, P, i32, f32, P, P, P, P]),
+        "pano_refine": (C.c_int, [P, P, i64, i32, P, i32, f32, P, P, P]),
         "pano_search_bruteforce": (C.c_int, [P, P, i64, i32, P, i32, P, P, P, u32, P]),
         "pano_index_info": (C.c_int, [P, P]),
         "pano_index_layout": (C.c_int, [P, P, P]),
@@ -102,5 +103,5 @@ def exported_symbols():
             "pano_ctx_scratch_bytes", "pano_ctx_trim",
             "pano_build_transform", "pano_transform_identity", "pano_transform_from",
             "pano_transform_get", "pano_transform_free", "pano_ivf_assign", "pano_build_levels",
-            "pano_search", "pano_search_ctx", "pano_search_scratch_bytes", "pano_search_noalloc", "pano_search_bruteforce", "pano_index_info", "pano_index_layout",
+            "pano_search", "pano_search_ctx", "pano_search_scratch_bytes", "pano_search_noalloc", "pano_refine", "pano_search_bruteforce", "pano_index_info", "pano_index_layout",
             "pano_stats_get", "pano_index_free"]

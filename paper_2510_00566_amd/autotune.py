@@ -67,7 +67,7 @@ def tune_search(idx, q_dev, k: int, nprobe, reps: int = 5, space: dict | None = 
     def mk(cfg):
         return Params(group=cfg["group"], blocks_per_item=cfg["blocks_per_item"],
                       seed_pool=cfg["seed"][0], seed_count=cfg["seed"][1], dense_min=cfg["dense_min"],
-                      use_bf16=use_bf16 if cfg["scan_mode"] != 3 else 0, scan_mode=cfg["scan_mode"],
+                      use_bf16=use_bf16, scan_mode=cfg["scan_mode"],
                       arrival_order=cfg["arrival_order"])
 
     def run(cfg):

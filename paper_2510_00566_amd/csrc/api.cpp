@@ -565,6 +565,18 @@ pano_status pano_search_noalloc(pano_index *idx, const float *q_dev, int64_t nq,
     });
 }
 
+pano_status pano_refine(pano_index *idx, const float *q_dev, int64_t nq, int32_t k, const int64_t *cand_dev,
+                        int32_t kprime, float eps, int64_t *ids_dev, float *dists_dev, void *stream)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx && (nq == 0 || (q_dev && cand_dev && ids_dev && dists_dev)), "null argument");
+        PANO_REQUIRE(k >= 1 && nq >= 0 && kprime >= 1, "need k >= 1, kprime >= 1 and nq >= 0");
+        PANO_REQUIRE(eps >= 0.f && eps <= 1.f, "eps must be in [0, 1]");
+        if (nq == 0) return;
+        run_refine(idx->ctx, idx, q_dev, nq, k, cand_dev, kprime, eps, ids_dev, dists_dev, (hipStream_t)stream);
+    });
+}
+
 pano_status pano_search_scratch_bytes(const pano_index *idx, int64_t nq, int32_t k, int32_t per_query_nprobe,
                                       int32_t nprobe_all, const pano_search_params *params, int64_t *bytes)
 {

@@ -215,6 +215,7 @@ struct pano_index {
     int64_t nblocks = 0, max_list_len = 0, max_list_blocks = 0;
     pano::DevMem mu32, T32, cent, raw, levels, levels_bf16, tails, ids, blk_cnt, list_blk_d,
         list_len_d, meta;
+    pano::DevMem idpos;  // row id -> block * B + slot (built on the first refine)
     pano::Margins mg{};
     double transform_err_max = 0.0, sigma_ratio = 1.0;
     float c_abs_bf = 0.f;  // c_abs of the bfloat16 scan (two query terms per product, u_b^2 split error)
@@ -296,6 +297,9 @@ void launch_pack(const float *Y, const float *tails_row, const int64_t *perm, co
 void run_search(pano_ctx *ctx, pano_index *idx, const float *q, int64_t nq, int k, const int32_t *nprobe_dev,
                 int nprobe_all, float eps, int64_t *ids, float *dists, const pano_search_params *prm,
                 uint32_t flags, bool brute, hipStream_t s, void *fixed = nullptr, size_t fixed_bytes = 0);
+// The point-centric refine of given candidate ids (synchronous).
+void run_refine(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k, const int64_t *cand, int kprime,
+                float eps, int64_t *ids, float *dists, hipStream_t s);
 // Bytes of fixed scratch a search needs (the allocation-free entry point).
 size_t search_fixed_bytes(const pano_index *ix, int64_t nq, int k, bool per_query_np, int nprobe_all,
                           const pano_search_params *prm);

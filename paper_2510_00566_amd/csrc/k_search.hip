@@ -830,8 +830,8 @@ __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__
         if (lpp >= 4) part += __shfl_xor(part, 2, 64);
         return part;
     };
-    // bfloat16 rows: ||x - x~|| <= u_b ||x||
-    const float delta = BF ? c.ub * tl[ss] + 1e-37f : 0.f;
+    // bfloat16 rows: ||x_h - x~_h|| <= u_b ||x_h|| for the head read so far
+    const float b0row = BF ? tl[ss] : 0.f;
     // the bound of a pair whose head distance sh covers the levels up to lv:
     // 1 = pruned, 2 = accepted (its upper bound is under the threshold; the
     // other side of Cauchy-Schwarz, UB = ||q_h - x_h||^2 + (||q_t|| +
@@ -843,6 +843,7 @@ __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__
         const float dt = a - b;
         const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
         const float ct = c.mg.c_tail * (a + b) * (a + b);
+        const float delta = BF ? c.ub * head_norm_upper(b0row, b) + 1e-37f : 0.f;
         const bool pruned = BF ? bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct > th
                                : (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
         if (pruned) return 1;
@@ -1103,7 +1104,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     const bool valid = s < cnt;
                     const float b0 = valid ? tb0[nt] : 0.f;
                     const float b1 = valid ? tb1[nt] : 0.f;
-                    const float delta = c.ub * b0 + 1e-37f;
+                    const float delta = c.ub * head_norm_upper(b0, b1) + 1e-37f;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int gq = 4 * kq + v;
@@ -1199,7 +1200,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         const float bl = valid ? tbl[nt] : 0.f;
                         const float bn = valid ? tbn[nt] : 0.f;
                         const float rxl = BF ? ex2[nt] : bl * bl - bn * bn;
-                        const float delta = BF ? c.ub * (valid ? tb0[nt] : 0.f) + 1e-37f : 0.f;
+                        const float delta = BF ? c.ub * head_norm_upper(valid ? tb0[nt] : 0.f, bn) + 1e-37f : 0.f;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int b = nt * 4 + v;
@@ -1819,7 +1820,7 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                         const float b0 = valid ? tb0[nt] : 0.f;
                         const float b1 = valid ? tb1[nt] : 0.f;
                         const float rxh = b0 * b0 - b1 * b1;
-                        const float delta = BF ? c.ub * b0 + 1e-37f : 0.f;
+                        const float delta = BF ? c.ub * head_norm_upper(b0, b1) + 1e-37f : 0.f;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int gq = 4 * kq + v;
@@ -1849,7 +1850,9 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                     }
                 } else {
                     // brute force: every level on the matrix cores, the query
-                    // operand loaded per level
+                    // operand loaded per level; from bfloat16 tiles, the
+                    // distance is to the rounded row (its squared norm summed
+                    // from the values fed) and carries the bfloat16 bracket
                     const int qq = r16 < ng ? qid_w[r16] : 0;
                     for (int lv = 0; lv < L; ++lv) {
                         const int kgc = g.wp[lv] >> 2;
@@ -1860,11 +1863,25 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                                 return r16 < ng ? *reinterpret_cast<const float4 *>(qrow + kg * 4)
                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
                             };
-                            if (lv == 0)
+                            if (BF) {
+                                floatx4_t part[4];
+                                float ex2[4];
+                                if (lv == 0)
+                                    level_dots_bf16(blk16 + (int64_t)base * 4 * g.B, g.B, kgn, qload, slot0, lane, part, ex2);
+                                else
+                                    level_dots_bf16(blk16 + (int64_t)g.B * g.mp[lv] + base * 4, g.B, kgn, qload, slot0,
+                                                    lane, part, ex2, g.wp[lv]);
+#pragma unroll
+                                for (int nt = 0; nt < 4; ++nt) {
+                                    acc[nt] += part[nt];
+                                    ex[nt] += ex2[nt];
+                                }
+                            } else if (lv == 0) {
                                 level_dots(blk + (int64_t)base * 4 * g.B, g.B, kgn, qload, slot0, lane, acc);
-                            else
+                            } else {
                                 level_dots(blk + (int64_t)g.B * g.mp[lv] + base * 4, g.B, kgn, qload, slot0, lane, acc,
                                            g.wp[lv]);
+                            }
                         }
                     }
 #pragma unroll
@@ -1877,8 +1894,8 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             const int gq = 4 * kq + v;
                             const bool on = valid && gq < ng;
                             const float a0 = on ? qtl[gq * L] : 0.f;
-                            const float dd = a0 * a0 + b0 * b0 - 2.f * acc[nt][v];
-                            const bool sv = on && dist_lower(dd, A_w[gq], c.mg) <= thr_w[gq];
+                            const float dd = a0 * a0 + (BF ? ex[nt] : b0 * b0) - 2.f * acc[nt][v];
+                            const bool sv = on && dist_lower(dd, A_w[gq], c.mg, c.bfdelta) <= thr_w[gq];
                             mask |= (uint32_t)sv << (nt * 4 + v);
                             sval[nt * 4 + v] = dd;
                         }
@@ -1886,7 +1903,7 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                     if (STATS && lane == 0) {
                         const int cs = min(64, cnt - slot0);
                         for (int lv = 0; lv < L && lv < 64; ++lv) atomicAdd(&st_lv[lv], (unsigned long long)cs * ng);
-                        atomicAdd(&st_misc[1], (unsigned long long)cs * (g.d_pad * 4 + 4 + 4));
+                        atomicAdd(&st_misc[1], (unsigned long long)cs * (g.d_pad * (BF ? 2 : 4) + 4 + 4));
                     }
                 }
                 // ---- while many pairs of the step are alive, refine the next
@@ -1928,7 +1945,7 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             const float bl = valid ? tbl[nt] : 0.f;
                             const float bn = valid ? tbn[nt] : 0.f;
                             const float rxl = BF ? ex2[nt] : bl * bl - bn * bn;
-                            const float delta = BF ? c.ub * (valid ? tb0[nt] : 0.f) + 1e-37f : 0.f;
+                            const float delta = BF ? c.ub * head_norm_upper(valid ? tb0[nt] : 0.f, bn) + 1e-37f : 0.f;
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 const int b = nt * 4 + v;
@@ -2054,7 +2071,7 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             const float th = thr_w[gq];
                             bool pruned;
                             if (BF) {
-                                const float delta = c.ub * tl[ss] + 1e-37f;
+                                const float delta = c.ub * head_norm_upper(tl[ss], b) + 1e-37f;
                                 pruned = bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct > th;
                             } else {
                                 pruned = (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
@@ -2182,6 +2199,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WP
     SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
 {
     wave_scan_body<false, false, true>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_brute_bf16(
+    SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    wave_scan_body<false, true, false>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_brute_bf16_stats(
+    SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    wave_scan_body<false, true, true>(c, ix, qv, wk);
 }
 
 
@@ -2457,6 +2484,135 @@ __global__ void k_probe_slots(const int32_t *__restrict__ lists, int nl, const i
     if (threadIdx.x == 0) *total = part[0];
 }
 
+// ================================================================ refine
+// Position of every row in the level-major blocks (block * B + slot), so that
+// a scattered candidate id finds its level slices and tails.
+__global__ void k_build_idpos(const int32_t *__restrict__ ids, const int32_t *__restrict__ blk_cnt, int64_t nblocks,
+                              int B, int64_t *__restrict__ idpos)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblocks * B) return;
+    const int64_t gb = t / B;
+    const int s = (int)(t % B);
+    if (s < blk_cnt[gb]) idpos[ids[t]] = t;
+}
+
+// The point-centric form of Algorithm 1 (B = 1 in the paper's table of its
+// two modes; Section 6.4, Refine): each query's own candidate ids, scattered
+// over the index, taken in groups of 64 (one lane per candidate, the group's
+// ids read in one sweep), each candidate refined level by level and dropped
+// at its first level whose bound (Eq. 3 / Eq. 4 with the certified margin)
+// exceeds the query's d_k; the survivors of a group update d_k before the
+// next group (the first group runs without a threshold and seeds it, as the
+// first k candidates seed the heap).  One wavefront per query.  Survivors
+// that can still reach the final band are appended to the query's result
+// buffer for the merge's canonical rescoring.
+__global__ __launch_bounds__(NT) void k_refine(SearchConsts c, IndexView ix, QueryView qv, WorkView wk,
+                                               const int64_t *__restrict__ cand, int kprime, int64_t nq,
+                                               const int64_t *__restrict__ idpos, int64_t n)
+{
+    extern __shared__ __align__(16) float rdyn[];  // per wave: k best [k], sort buffer [next_pow2(k + 64)]
+    const LevelGeom &g = c.g;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t qi = (int64_t)blockIdx.x * (NT / 64) + wv;
+    if (qi >= nq) return;
+    const int sbn = next_pow2(c.k + 64);
+    float *kb = rdyn + (size_t)wv * (c.k + sbn);
+    float *sb = kb + c.k;
+    const int L = g.L;
+    const float *qrow = qv.qy + qi * g.d_pad;
+    const float *qt = qv.qtail + qi * L;
+    const float Aq = qv.qA[qi], Eq = qv.qE[qi];
+    const uint64_t below = (1ull << lane) - 1ull;
+    float th = INFINITY;
+    int cntk = 0;
+    bool bad = false;
+    for (int base = 0; base < kprime; base += 64) {
+        const int ci = base + lane;
+        const int64_t id = ci < kprime ? cand[qi * kprime + ci] : -1;
+        bad |= id < -1 || id >= n;
+        bool act = id >= 0 && id < n;
+        const int64_t pos = act ? idpos[id] : 0;
+        const int64_t gb = pos / g.B;
+        const int ss = (int)(pos - gb * g.B);
+        const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
+        const float *tl = ix.tails + gb * (int64_t)g.B * L;
+        float sh = 0.f;
+        for (int lv = 0; lv < L; ++lv) {
+            if (__ballot(act) == 0ull) break;
+            const bool last = lv + 1 == L;
+            const int w4 = g.wp[lv] >> 2;
+            const float b = (act && !last) ? tl[(int64_t)(lv + 1) * g.B + ss] : 0.f;
+            float part = 0.f;
+            if (act) {
+                for (int c0 = 0; c0 < w4; c0 += 4) {
+                    float4 xs[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int cc = min(c0 + j, w4 - 1);
+                        // level 1 is interleaved by groups of four dimensions,
+                        // later levels are slot-contiguous
+                        const int64_t o = lv == 0 ? ((int64_t)cc * g.B + ss) * 4
+                                                  : (int64_t)g.B * g.mp[lv] + (int64_t)ss * g.wp[lv] + cc * 4;
+                        xs[j] = *reinterpret_cast<const float4 *>(blk + o);
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (c0 + j < w4) {
+                            const float4 q4 = *reinterpret_cast<const float4 *>(qrow + g.mp[lv] + (c0 + j) * 4);
+                            const float t0 = q4.x - xs[j].x, t1 = q4.y - xs[j].y, t2 = q4.z - xs[j].z,
+                                        t3 = q4.w - xs[j].w;
+                            part = __builtin_fmaf(t0, t0, part);
+                            part = __builtin_fmaf(t1, t1, part);
+                            part = __builtin_fmaf(t2, t2, part);
+                            part = __builtin_fmaf(t3, t3, part);
+                        }
+                    }
+                }
+            }
+            sh += part;
+            const float a = last ? 0.f : qt[lv + 1];
+            const float dt = a - b;
+            const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
+            const float ct = c.mg.c_tail * (a + b) * (a + b);
+            const bool pruned = (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
+            act = act && !pruned;
+        }
+        // commit the group's survivors: append those that can reach the final
+        // band, keep the k best distances, refresh d_k
+        const float D = act ? fmaxf(sh, 0.f) : 0.f;
+        const bool keep = act && dist_lower(D, Aq, c.mg) <= th;
+        const uint64_t bal = __ballot(keep);
+        const int nk = __popcll(bal);
+        if (nk == 0) continue;
+        int bpos = 0;
+        if (lane == 0) bpos = atomicAdd(&wk.buf_cnt[qi], nk);
+        bpos = __shfl(bpos, 0, 64);
+        const int rk = __popcll(bal & below);
+        if (keep) {
+            const int dst = bpos + rk;
+            const int32_t rid = ix.ids[gb * g.B + ss];
+            if (dst < c.capq) wk.buf[qi * c.capq + dst] = make_key(D, rid);
+            else atomicOr(&wk.flags[qi], FLAG_OVERFLOW);
+        }
+        for (int j = lane; j < cntk; j += 64) sb[j] = kb[j];
+        if (keep) sb[cntk + rk] = D;
+        const int tn = cntk + nk;
+        const int P2 = next_pow2(tn);
+        for (int j = tn + lane; j < P2; j += 64) sb[j] = INFINITY;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        wave_bitonic_sort_f(sb, P2, lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        cntk = min(c.k, tn);
+        for (int j = lane; j < cntk; j += 64) kb[j] = sb[j];
+        if (cntk == c.k) th = fminf(th, prune_threshold(sb[c.k - 1], Eq, Aq, c.mg));
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&wk.flags[qi], FLAG_BADID);
+}
+
 // ================================================================ fixed scratch
 // Device scratch of the allocation-free search: one array per GPU, in the
 // code object, held until the process ends.  Host code never uses its name
@@ -2560,7 +2716,7 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     // local top-k per query of a work item: its k best and their margin
     // band; the bfloat16 scan's wider bracket makes the band longer, so
     // it keeps at least 64
-    const bool bf16_req = !brute && prm && prm->use_bf16;
+    const bool bf16_req = prm && prm->use_bf16;
     c.kc = next_pow2(std::max(2 * k, bf16_req ? 64 : 16));
     int G = 16;
     while (G > 1 && G * c.kc > 2048) G >>= 1;
@@ -2570,7 +2726,8 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     // and local top-k per work item), 4 = the per-wave scan (every wavefront
     // its own worker, survivors appended to the result buffers)
     const int mode_req = prm ? prm->reserved[1] : 0;
-    pl.wave = mode_req == 4;
+    // the brute-force scan of bfloat16 tiles is an instance of the per-wave scan
+    pl.wave = mode_req == 4 || (brute && bf16_req);
     c.wl = wave_lds_layout(L, k);
     // a query group meets at most 32 work items per list
     c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1;
@@ -2610,7 +2767,7 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     c.eps = eps;
     c.one_m_eps2 = 2.f * (1.f - eps);
     c.mg = ix->mg;
-    const bool use_bf16 = !brute && prm && prm->use_bf16;
+    const bool use_bf16 = prm && prm->use_bf16;
     PANO_REQUIRE(!use_bf16 || ix->has_bf16, "bfloat16 search needs an index built with PANO_BF16");
     c.bf16 = use_bf16 ? 1 : 0;
     c.ub = (float)(std::ldexp(1.0, -8) * (1.0 + 1e-6));
@@ -2717,7 +2874,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     PANO_REQUIRE(ctx->device == ix->ctx->device, "context and index are on different devices");
     PANO_HIP(hipSetDevice(ctx->device));
     if (prm && prm->reserved[1] == 3) brute = true;  // scan mode 3: no pruning
-    const bool wave = prm && prm->reserved[1] == 4;
+    const bool wave = (prm && prm->reserved[1] == 4) || (brute && prm && prm->use_bf16);
     const int d = ix->d, L = ix->L, nlist = ix->nlist;
     SearchConsts c;
     SearchPlan pl;
@@ -2820,9 +2977,10 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         PANO_HIP(hipFuncSetAttribute((const void *)k_wl_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_shm));
     // the per-wave scan instance of this search (and its counting twin)
     typedef void (*ScanKernel)(SearchConsts, IndexView, QueryView, WorkView);
-    const ScanKernel wave_kern = brute ? k_scan_wave_brute : (use_bf16 ? k_scan_wave_bf16 : k_scan_wave);
-    const ScanKernel wave_kern_stats =
-        brute ? k_scan_wave_brute_stats : (use_bf16 ? k_scan_wave_bf16_stats : k_scan_wave_stats);
+    const ScanKernel wave_kern = brute ? (use_bf16 ? k_scan_wave_brute_bf16 : k_scan_wave_brute)
+                                       : (use_bf16 ? k_scan_wave_bf16 : k_scan_wave);
+    const ScanKernel wave_kern_stats = brute ? (use_bf16 ? k_scan_wave_brute_bf16_stats : k_scan_wave_brute_stats)
+                                             : (use_bf16 ? k_scan_wave_bf16_stats : k_scan_wave_stats);
     if (wave) {
         PANO_REQUIRE(scan_shm <= 160 * 1024, "k and L too large for the per-wave scan's LDS");
         PANO_HIP(hipFuncSetAttribute((const void *)wave_kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)scan_shm));
@@ -3095,6 +3253,102 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         PANO_HIP(hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3]));
         st.ms_merge = t;
         for (int i = 0; i < 6; ++i) st.scan_cycles[i] = (int64_t)hs[ST_CYCLES + i];
+    }
+}
+
+
+// Refine (the point-centric scan of given candidate ids): query transform
+// and constants, k_refine, and the merge's canonical rescoring, on the
+// context's stream; the caller's stream is ordered before by an event.
+void run_refine(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k, const int64_t *cand, int kprime,
+                float eps, int64_t *ids, float *dists, hipStream_t s)
+{
+    PANO_HIP(hipSetDevice(ctx->device));
+    PANO_REQUIRE(k <= 128, "k up to 128 is supported");
+    const int d = ix->d, L = ix->L;
+    SearchConsts c{};
+    c.k = k;
+    c.kc = next_pow2(std::max(2 * k, 16));
+    // every candidate is appended at most once: the buffer cannot overflow
+    c.capq = next_pow2(std::max(kprime, 64));
+    c.nlist = ix->nlist;
+    c.prune = 1;
+    c.eps = eps;
+    c.one_m_eps2 = 2.f * (1.f - eps);
+    c.mg = ix->mg;
+    c.g = LevelGeom{};
+    c.g.L = L;
+    c.g.d = d;
+    c.g.d_pad = ix->d_pad;
+    c.g.B = ix->B;
+    for (int l = 0; l <= L; ++l) c.g.mp[l] = ix->mp[l];
+    for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
+    c.wl = wave_lds_layout(L, k);
+    if (!ix->idpos.p) {
+        ix->idpos.alloc(sizeof(int64_t) * (size_t)ix->n);
+        const int64_t slots = ix->nblocks * ix->B;
+        hipLaunchKernelGGL(k_build_idpos, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, ctx->work_stream(),
+                           ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(), ix->nblocks, ix->B,
+                           ix->idpos.as<int64_t>());
+        PANO_HIP(hipGetLastError());
+    }
+    const size_t need0 = align_up(sizeof(float) * nq * ix->d_pad) + align_up(sizeof(float) * nq * L) +
+                         3 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
+    const size_t need3 = 4 * align_up(sizeof(float) * nq) + align_up(sizeof(uint64_t) * nq * c.capq) +
+                         align_up(sizeof(unsigned long long) * 128);
+    ctx->scratch[0].ensure(need0);
+    ctx->scratch[3].ensure(need3);
+    Carver c0(ctx->scratch[0].p), c3(ctx->scratch[3].p);
+    float *qy = c0.take<float>(nq * ix->d_pad);
+    float *qtail = c0.take<float>(nq * L);
+    float *qE = c0.take<float>(nq);
+    float *qA = c0.take<float>(nq);
+    double *vnorm = c0.take<double>(nq);
+    int32_t *qbad = c3.take<int32_t>(nq);
+    float *thr = c3.take<float>(nq);
+    int32_t *buf_cnt = c3.take<int32_t>(nq);
+    int32_t *qflags = c3.take<int32_t>(nq);
+    uint64_t *buf = c3.take<uint64_t>(nq * c.capq);
+    (void)thr;
+    ctx->pinned_ensure(sizeof(int32_t) * nq);
+    int32_t *h_flags = reinterpret_cast<int32_t *>(ctx->pinned);
+    const size_t merge_shm = sizeof(uint64_t) * MERGE_LDS_KEYS + sizeof(float) * (size_t)d;
+    PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_shm));
+    hipStream_t ws = ctx->work_stream();
+    PANO_HIP(hipEventRecord(ctx->ev_in, s));
+    PANO_HIP(hipStreamWaitEvent(ws, ctx->ev_in, 0));
+    FillList fl{};
+    fl.add(buf_cnt, nq, 0u);
+    fl.add(qflags, nq, 0u);
+    if (ix->d_pad != ix->d) {
+        FillList fq{};
+        fq.add(qy, nq * (int64_t)ix->d_pad, 0u);
+        hipLaunchKernelGGL(k_fill_multi, dim3(256), dim3(256), 0, ws, fq);
+    }
+    const GemmJob jt = transform_job(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy,
+                                     ix->d_pad);
+    launch_gemm_jobs(jt, nullptr, ws, &fl);
+    QueryConstsOut qc;
+    qc.mg = ix->mg;
+    qc.qE = qE;
+    qc.qA = qA;
+    qc.badq = qbad;
+    launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, ws, &qc);
+    IndexView iv{ix->levels.as<float>(), nullptr, ix->tails.as<float>(), ix->ids.as<int32_t>(),
+                 ix->blk_cnt.as<int32_t>(), ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
+    QueryView qv{qy, qtail, qE, qA, q};
+    WorkView wk{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, buf, buf_cnt, qflags, nullptr};
+    const size_t rshm = sizeof(float) * (size_t)(NT / 64) * (k + next_pow2(k + 64));
+    hipLaunchKernelGGL(k_refine, dim3((unsigned)((nq + NT / 64 - 1) / (NT / 64))), dim3(NT), rshm, ws, c, iv, qv, wk,
+                       cand, kprime, nq, ix->idpos.as<int64_t>(), ix->n);
+    hipLaunchKernelGGL(k_merge, dim3((unsigned)nq), dim3(NT), merge_shm, ws, c, buf, buf_cnt, qflags, qE, qA, q,
+                       ix->raw.as<float>(), d, ids, dists, nullptr, h_flags, qbad);
+    PANO_HIP(hipGetLastError());
+    PANO_HIP(hipStreamSynchronize(ws));
+    for (int64_t qi = 0; qi < nq; ++qi) {
+        PANO_REQUIRE(!(h_flags[qi] & FLAG_NONFINITE), "a query has a non-finite value");
+        PANO_REQUIRE(!(h_flags[qi] & FLAG_BADID), "a candidate id is outside [-1, n)");
+        PANO_REQUIRE(!(h_flags[qi] & FLAG_OVERFLOW), "refine result buffer overflow");
     }
 }
 

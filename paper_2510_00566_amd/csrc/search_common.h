@@ -15,6 +15,7 @@ constexpr int WALK_CHUNKS = 8;  // four-float chunks of a level the per-pair wal
 constexpr uint64_t KEY_MAX = ~0ull;
 constexpr int FLAG_OVERFLOW = 1;
 constexpr int FLAG_NONFINITE = 2;  // host flag word only: the query has a non-finite value
+constexpr int FLAG_BADID = 4;      // refine: a candidate id outside [-1, n)
 
 // Wave-uniform reads of query slices go through the constant address space so
 // that they become scalar loads into SGPRs (a free broadcast to all lanes).
@@ -210,6 +211,18 @@ __device__ inline void wave_canon_dist2(const float *q, const float *__restrict_
 // by the triangle inequality a certified bracket [s_lo, s_hi] of
 // ||q_h - x~_h||^2 gives one of ||q_h - x_h||^2.  The factors cover the FP32
 // square root and square.
+// Certified upper bound on the norm of a stored row's head (the coordinates
+// before the tail whose norm is bl) from its stored norm b0 and tail norm bl,
+// each within a relative 2^-24 of the exact value: the slack 8u on both
+// squares covers those and the FP32 products and difference (u = 2^-24).
+// With bfloat16 tiles, ||x_h - x~_h|| <= u_b ||x_h|| (elementwise rounding),
+// so the bracket of a head distance widens by u_b times this, not by u_b ||x||.
+__device__ inline float head_norm_upper(float b0, float bl)
+{
+    const float h2 = b0 * b0 * (1.f + 4.8e-7f) - bl * bl * (1.f - 4.8e-7f);
+    return __builtin_sqrtf(fmaxf(h2, 0.f)) * (1.f + 2.4e-7f);
+}
+
 __device__ inline float bf_head_lower(float s_lo, float delta)
 {
     const float r = fmaxf(__builtin_sqrtf(fmaxf(s_lo, 0.f)) * (1.f - 1e-6f) - delta, 0.f);

@@ -195,6 +195,14 @@ class Index:
                                         C.byref(prm) if prm is not None else None, flags, _stream_handle(stream)))
         return ids, dists
 
+    def refine(self, q_dev, k: int, cand_dev, eps: float = 1.0, stream=None, out=None):
+        """k-NN of each query among its own candidate ids cand_dev [nq][k']
+        (int64, -1 = empty), by the point-centric scan."""
+        ids, dists = out if out is not None else self._outs(q_dev, k)
+        L.check(L.lib().pano_refine(self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(cand_dev), cand_dev.shape[1],
+                                    float(eps), _ptr(ids), _ptr(dists), _stream_handle(stream)))
+        return ids, dists
+
     def search_noalloc(self, q_dev, k: int, nprobe=1, eps: float = 1.0, params: Params | None = None,
                        stream=None, out=None, nprobe_max: int = 0):
         """The same search with no allocation inside the library: its scratch

@@ -91,6 +91,8 @@ class Workload:
     nprobe: int = 1
     nprobe_range: tuple | None = None   # per-query nprobe ~ U{lo..hi}
     level_width: int = 16
+    tune_width: bool = False     # the level width is the tuner's choice (else fixed by the configuration)
+    q_spec_p: float | None = None  # out-of-distribution queries: their own decay law parameter (None = the data's)
     note: str = ""
 
     @property
@@ -111,10 +113,10 @@ WORKLOADS = {
                               note="IVFFlat exact-at-probe, 16 levels x 60 dims"),
     "ivf_zipf_batched": Workload("ivf_zipf_batched", 3, 10_000_000, 128, 10_000, 10, "power", 1.0,
                                  n_clusters=4096, zipf_s=1.1, nlist=4096, nprobe=68,
-                                 nprobe_range=(8, 128), level_width=16,
+                                 nprobe_range=(8, 128), level_width=16, tune_width=True,
                                  note="batched IVFFlat, Zipf(1.1) list sizes, nprobe ~ U[8,128]"),
     "ivf_embed_bf16": Workload("ivf_embed_bf16", 4, 5_000_000, 768, 10_000, 100, "power", 0.8,
-                               normalize=True, nlist=4096, nprobe=64, level_width=32,
+                               normalize=True, nlist=4096, nprobe=64, level_width=32, tune_width=True,
                                note="unit-normed embeddings, BF16 levels + FP32 rescoring"),
 }
 
@@ -188,15 +190,37 @@ def generate(w: Workload, with_queries: bool = True):
     x = _draw(w, w.n, labels, centers, rot, sq, gdb)
     out = {"x": x, "labels": labels, "lambda": lam}
     if with_queries:
-        gq = rng(w.cfg_id, STREAM_QUERIES)
-        qlab = _cluster_labels(w, gq, w.nq, None)
-        out["q"] = _draw(w, w.nq, qlab, centers, rot, sq, gq)
-        out["qlabels"] = qlab
-        if w.nprobe_range is not None:
-            lo, hi = w.nprobe_range
-            out["nprobe"] = rng(w.cfg_id, STREAM_NPROBE).integers(lo, hi + 1, size=w.nq).astype(np.int32)
-        else:
-            out["nprobe"] = np.full(w.nq, w.nprobe, dtype=np.int32)
+        out.update(queries(w, rot=rot, centers=centers))
+    return out
+
+
+def queries(w: Workload, rot: np.ndarray | None = None, centers: np.ndarray | None = None):
+    """The workload's queries alone: dict(q [nq,d] f32, qlabels [nq], nprobe
+    [nq] int32).  They follow the data's law (same rotation and centres), with
+    the spectrum of q_spec_p when it is set (scaled to the same total energy):
+    a slower decay spreads a query's energy over more principal directions of
+    the data (out-of-distribution queries whose tail energy decays at a rate
+    of their own)."""
+    if rot is None:
+        rot = haar_rotation(w.d, rng(w.cfg_id, STREAM_ROTATION))
+    if centers is None and w.n_clusters > 0:
+        gc = rng(w.cfg_id, STREAM_CENTERS)
+        centers = (gc.standard_normal((w.n_clusters, w.d)) * np.sqrt(w.center_var)).astype(np.float32)
+    lam = spectrum(w.spec_kind, w.d, w.spec_p)
+    if w.q_spec_p is not None:
+        # the queries' own decay, scaled to the data's total energy so that
+        # only how the energy spreads over the directions differs
+        lq = spectrum(w.spec_kind, w.d, w.q_spec_p)
+        lam = lq * (lam.sum() / lq.sum())
+    sq = np.sqrt(lam)
+    gq = rng(w.cfg_id, STREAM_QUERIES)
+    qlab = _cluster_labels(w, gq, w.nq, None)
+    out = {"q": _draw(w, w.nq, qlab, centers, rot, sq, gq), "qlabels": qlab}
+    if w.nprobe_range is not None:
+        lo, hi = w.nprobe_range
+        out["nprobe"] = rng(w.cfg_id, STREAM_NPROBE).integers(lo, hi + 1, size=w.nq).astype(np.int32)
+    else:
+        out["nprobe"] = np.full(w.nq, w.nprobe, dtype=np.int32)
     return out
 
 

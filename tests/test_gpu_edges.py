@@ -271,3 +271,17 @@ def test_many_lists(torch_cuda, nlist, nprobe):
     case = gc.build_case(w)
     _, _, st = _run(torch_cuda, case, w, case["data"]["q"])
     assert st["fallback_queries"] == 0
+
+
+@gpu
+def test_out_of_distribution_queries_stay_exact(torch_cuda):
+    """Queries whose spectrum is flat in the data's PCA basis (no energy
+    compaction, Prop. 5.2's alpha_q -> 0) still get the exact answer."""
+    from tests import gpu_cases as gc
+    w = synth.scaled(synth.WORKLOADS["ivf_gist_like"], n=20000, nq=24, nlist=32, nprobe=4, n_clusters=32)
+    case = gc.build_case(w)
+    for qp in (0.0, 0.003):
+        q = synth.queries(dataclasses.replace(w, q_spec_p=qp))["q"]
+        _log(f"case ood q_spec_p={qp} n=20000 d=960")
+        _, _, st = _run(torch_cuda, case, w, q)
+        assert st["fallback_queries"] == 0

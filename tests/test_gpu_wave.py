@@ -42,6 +42,11 @@ def _check(torch_cuda, case, w, q, nprobe, k=None, store_bf16=False, eps=1.0):
     gc.compare(ids2.cpu().numpy(), dd2.cpu().numpy(), ref_i, ref_d)
     bi, bd = case["idx"].search_bruteforce(qd, k, nprobe=npd, params=Params(scan_mode=4))
     gc.compare(bi.cpu().numpy(), bd.cpu().numpy(), ref_i, ref_d)
+    if store_bf16:
+        # the brute-force scan of the bfloat16 tiles (bracketed commits,
+        # canonical rescoring from the FP32 rows)
+        bi, bd = case["idx"].search_bruteforce(qd, k, nprobe=npd, params=Params(use_bf16=1))
+        gc.compare(bi.cpu().numpy(), bd.cpu().numpy(), ref_i, ref_d)
     return st
 
 

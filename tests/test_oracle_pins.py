@@ -578,3 +578,42 @@ def test_assignment_mismatches_enumerated():
     wrong = best.copy()
     wrong[:7] = (wrong[:7] + 1) % len(c)
     assert brute.assignment_mismatches(x, c, wrong) == 7
+
+
+# ---------------------------------------------------------------- refine (Section 6.4)
+
+def test_refine_oracle_definition_pins():
+    """knn_candidates is exact k-NN over the candidate set: with every row as
+    candidate it is the flat brute force; -1 slots and the order of ids do not
+    matter; a worked 2-D case by hand; and the point-centric scan (B = 1)
+    reaches the same answer at eps = 1."""
+    x = synth.integer_grid(300, 5, 21, span=3)
+    q = synth.integer_grid(3, 5, 22, span=3)
+    allc = np.tile(np.arange(300), (3, 1))
+    bi, bd = brute.knn_flat(q, x, 7)
+    ri, rd = brute.knn_candidates(q, x, allc, 7)
+    assert np.array_equal(ri, bi) and np.array_equal(rd, bd)
+    g = np.random.Generator(np.random.PCG64(3))
+    sub = np.stack([g.permutation(300)[:40] for _ in range(3)])
+    sub_pad = np.concatenate([sub, -np.ones((3, 5), np.int64)], axis=1)[:, g.permutation(45)]
+    ri, rd = brute.knn_candidates(q, x, sub_pad, 7)
+    for i in range(3):
+        keys = sorted((_exact_sqdist(q[i], x[j]), int(j)) for j in sub[i])[:7]
+        assert [j for _, j in keys] == ri[i].tolist()
+    # by hand: q = (0, 0); candidates 2 (3,4) D=25, 5 (0,1) D=1, 7 (1,0) D=1, 9 (0,0) D=0
+    xs = np.zeros((10, 2), np.float32)
+    xs[2], xs[5], xs[7], xs[9] = (3, 4), (0, 1), (1, 0), (0, 0)
+    ri, rd = brute.knn_candidates(np.zeros((1, 2), np.float32), xs, np.array([[2, 7, -1, 5, 9]]), 3)
+    assert ri.tolist() == [[9, 5, 7]] and rd.tolist() == [[0.0, 1.0, 1.0]]
+    ri, rd = brute.knn_candidates(np.zeros((1, 2), np.float32), xs, np.array([[2, -1]]), 3)
+    assert ri.tolist() == [[2, -1, -1]] and rd[0, 0] == 25.0 and np.isinf(rd[0, 1:]).all()
+    # point-centric Algorithm 1 over the candidate order
+    xr, _ = _pca_data(n=2000, d=16, seed=4)
+    mu, t, _ = panorama.pca_fit(xr)
+    cand = np.random.Generator(np.random.PCG64(8)).permutation(2000)[:500]
+    for qi in range(3):
+        qv = xr[qi] + 0.05
+        pi, pd, rho = panorama.panorama_refine(qv, xr, cand, mu, t, [0, 4, 8, 12, 16], 10)
+        ri, rd = brute.knn_candidates(qv[None], xr, cand[None], 10)
+        assert np.array_equal(pi, ri[0]) and np.array_equal(pd, rd[0])
+        assert rho.sum() < 500 * 16
