@@ -425,6 +425,10 @@ def eps_sweep(run: Run, args) -> dict:
     ref_i, _ = c_oracle.knn_lists(run.q, run.x, off, cand, w.k, threads=nthreads)
     out = []
     base = None
+    if run.prm.scan_mode == 3:
+        # the tuner's choice does not prune here; eps acts on a pruned scan
+        from paper_2510_00566_amd.index import Params
+        run.prm = Params(use_bf16=run.use_bf16)
     for eps in [float(v) for v in args.eps_values.split(",")]:
         el = run.time_steps(lambda: run.idx.search(run.qd, w.k, nprobe=run.npd, eps=eps, params=run.prm,
                                                    out=(run.ids, run.dists), nprobe_max=run.np_max),
@@ -495,7 +499,7 @@ def ood_sweep(run: Run, args) -> dict:
         gi = run.ids.cpu().numpy()[smp]
         aeff = 0.5 * (alpha_q + alpha_x)
         rec = {"q_spec_p": qp, "alpha_q": alpha_q, "alpha_x": alpha_x, "alpha_eff": aeff,
-               "qps": w0.nq * args.steps / el, "speedup_vs_bruteforce": (bsteps / elb) / (args.steps / el),
+               "qps": w0.nq * args.steps / el, "speedup_vs_bruteforce": (args.steps / el) / (bsteps / elb),
                "phi": phi, "phi_ratio_to_in_distribution": phi / phi0,
                "predicted_phi_ratio": None,
                "parity": {"queries": int(smp.size), "id_mismatch_queries": int((gi != ri).any(axis=1).sum())}}

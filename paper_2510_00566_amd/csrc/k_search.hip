@@ -332,7 +332,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                                              int nprobe_all, int np_max, float c_co,
                                              const int64_t *__restrict__ list_len, int pool, int cnt,
                                              const float *__restrict__ mu, float qa_cabs, float qa_b0max2,
-                                             float *__restrict__ thr)
+                                             float *__restrict__ thr, uint64_t *__restrict__ buf,
+                                             int32_t *__restrict__ buf_cnt, int capq, int32_t *__restrict__ flags)
 {
     // dynamic LDS (seed_lds_bytes): keys [next_pow2(pool)], the rotated
     // query [d_pad / 4] float4, chunk offsets and widths [d_pad / 4] each;
@@ -343,6 +344,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     int *chunk_off = reinterpret_cast<int *>(qs_l + (c.g.d_pad >> 2));
     int *chunk_w = chunk_off + (c.g.d_pad >> 2);
     __shared__ float Ds[256];
+    __shared__ int Ps[256];  // pool position of the i-th most promising candidate
     __shared__ float red_f[NT / 64];
     __shared__ int red_i[NT / 64];
     const int64_t q = blockIdx.x;
@@ -561,6 +563,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         float part = 0.f;
         if (si < S) {
             const int p = key_id(K[si]);
+            if (tl == 0) Ps[si] = p;
             const int64_t gb = b0 + p / g.B;
             const int s = p % g.B;
             const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
@@ -594,6 +597,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     for (int i = threadIdx.x; i < PS; i += NT) K[i] = i < S ? make_key(Ds[i], i) : KEY_MAX;
     __syncthreads();
     block_bitonic_sort(K, PS);
+    // the k best seeds go to the query's result buffer, so the threshold
+    // stands on committed candidates even if a relaxed bound (eps < 1)
+    // prunes them when the scan meets them (the merge keeps one copy of a
+    // candidate committed twice)
+    // (the seeding runs before the scan on an empty buffer, so bpos is 0 and
+    // k <= 128 keys fit)
+    __shared__ int bpos_s;
+    if (threadIdx.x == 0) {
+        bpos_s = atomicAdd(&buf_cnt[q], c.k);
+        atomicOr(&flags[q], FLAG_SEEDED);
+    }
+    __syncthreads();
+    {
+        const int bpos = bpos_s;
+        for (int i = threadIdx.x; i < c.k; i += NT) {
+            const int p = Ps[key_id(K[i])];
+            const int64_t gb = b0 + p / g.B;
+            if (bpos + i < capq) buf[q * capq + bpos + i] = make_key(key_dist(K[i]), ix.ids[gb * g.B + p % g.B]);
+        }
+    }
     if (threadIdx.x == 0) {
         float t = prune_threshold(key_dist(K[c.k - 1]), qE_s, qA_s, c.mg);
         atomic_min_nonneg(&thr[q], t);
@@ -2249,7 +2272,7 @@ __device__ uint32_t block_kth_dist_bits(const uint64_t *__restrict__ keys, int n
 // LDS sort holds is first cut to the entries that can reach the band: the k-th
 // smallest distance is found by radix select in global memory.  Every return
 // is taken by the whole workgroup, and only thread 0 changes flags[q].
-__device__ __forceinline__ void merge_query(const SearchConsts &c, const uint64_t *__restrict__ buf,
+__device__ __forceinline__ void merge_query(const SearchConsts &c, uint64_t *__restrict__ buf,
                                             const int32_t *__restrict__ buf_cnt, int32_t *__restrict__ flags,
                                             const float *__restrict__ qE, const float *__restrict__ qA,
                                             const float *__restrict__ qraw, const float *__restrict__ raw, int d,
@@ -2268,8 +2291,34 @@ __device__ __forceinline__ void merge_query(const SearchConsts &c, const uint64_
         if (threadIdx.x == 0) atomicOr(&flags[q], FLAG_OVERFLOW);
         return;
     }
-    const uint64_t *bq = buf + q * c.capq;
+    uint64_t *bq = buf + q * c.capq;
     int n = n_all;
+    if ((flags[q] & FLAG_SEEDED) && n > c.k) {
+        // the first k entries are the seeding's; the scan may have committed
+        // the same candidates again (with another FP32 rounding of their
+        // distance): drop those copies, in place, so that every candidate
+        // counts once when the k-th distance and the band are taken
+        __shared__ int32_t sid[128];
+        __shared__ int wtmp[NT / 64];
+        for (int i = threadIdx.x; i < c.k; i += NT) sid[i] = key_id(bq[i]);
+        __syncthreads();
+        int kept = c.k;
+        for (int base = c.k; base < n; base += NT) {
+            const int i = base + threadIdx.x;
+            const uint64_t v = i < n ? bq[i] : KEY_MAX;
+            bool keep = i < n;
+            if (keep) {
+                const int32_t id = key_id(v);
+                for (int j = 0; j < c.k; ++j) keep = keep && sid[j] != id;
+            }
+            int tot;
+            const int off = block_exclusive_scan(keep ? 1 : 0, wtmp, &tot);
+            if (keep) bq[kept + off] = v;
+            kept += tot;
+            __syncthreads();
+        }
+        n = kept;
+    }
     if (n > MERGE_LDS_KEYS) {
         const float dk = __uint_as_float(block_kth_dist_bits(bq, n, c.k, hist, sel));
         const float cut = prune_threshold(dk, qE[q], qA[q], c.mg, c.bfdelta);
@@ -2335,11 +2384,17 @@ __device__ __forceinline__ void merge_query(const SearchConsts &c, const uint64_
     for (int i = nb + threadIdx.x; i < PB; i += NT) K[i] = KEY_MAX;
     __syncthreads();
     block_bitonic_sort(K, PB);
-    for (int r = threadIdx.x; r < c.k; r += NT) {
-        if (r < nb) {
-            out_ids[q * c.k + r] = key_id(K[r]);
-            out_d[q * c.k + r] = key_dist(K[r]);
-        } else {
+    // a candidate committed twice (by the seeding and by the scan) has the
+    // same canonical key twice, next to each other: keep one
+    if (threadIdx.x == 0) {
+        int r = 0;
+        for (int i = 0; i < nb && r < c.k; ++i) {
+            if (i > 0 && K[i] == K[i - 1]) continue;
+            out_ids[q * c.k + r] = key_id(K[i]);
+            out_d[q * c.k + r] = key_dist(K[i]);
+            ++r;
+        }
+        for (; r < c.k; ++r) {
             out_ids[q * c.k + r] = -1;
             out_d[q * c.k + r] = INFINITY;
         }
@@ -2354,7 +2409,7 @@ __device__ __forceinline__ void merge_query(const SearchConsts &c, const uint64_
 // of nq words) is given, each query's final flag word, with FLAG_NONFINITE
 // set for a query that has a non-finite value, goes to hflags[q], so the
 // host reads them after the stream completes without copies of its own.
-__global__ __launch_bounds__(NT) void k_merge(SearchConsts c, const uint64_t *__restrict__ buf,
+__global__ __launch_bounds__(NT) void k_merge(SearchConsts c, uint64_t *__restrict__ buf,
                                               const int32_t *__restrict__ buf_cnt,
                                               int32_t *__restrict__ flags, const float *__restrict__ qE,
                                               const float *__restrict__ qA,
@@ -2896,9 +2951,12 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     const int np_max = probe_cap(nprobe_dev != nullptr, nprobe_all, nlist);
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
     const bool want_timing = !want_stats && (flags & PANO_SEARCH_TIMING) != 0;
-    // the seeding gives the brute-force scan its starting threshold too (it
-    // then commits fewer candidates; every distance is still computed)
-    const bool seed_on = eps >= 1.f;
+    // the seeding starts every scan's threshold, the brute-force scan's too
+    // (it then commits fewer candidates; every distance is still computed),
+    // and at eps < 1 as well: its k best are committed, so the threshold
+    // stands on candidates of the answer set even if the relaxed bound
+    // prunes them in the scan
+    const bool seed_on = true;
     // ---- scratch: the context's buffers (grown on demand), or consecutive
     // regions of the caller's fixed memory
     const size_t need0 = need[0], need1 = need[1], need2 = need[2], need3 = need[3];
@@ -3064,7 +3122,7 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             hipLaunchKernelGGL(k_seed, dim3((unsigned)nq), dim3(NT), seed_lds_bytes(seed_pool, c.g.d_pad), sa, c, iv,
                                qv, Sco, ix->cent.as<float>() + (size_t)nlist * d, d, nlist, nprobe_dev, nprobe_all,
                                np_max, c_co, ix->list_len_d.as<int64_t>(), seed_pool, seed_cnt,
-                               ix->mu32.as<float>(), mq.c_abs, mq.b0max2, thr);
+                               ix->mu32.as<float>(), mq.c_abs, mq.b0max2, thr, buf, buf_cnt, c.capq, qflags);
             if (fork) PANO_HIP(hipEventRecord(ctx->ev_join, sa));
         }
         // coarse probing (and the number of queries per list)

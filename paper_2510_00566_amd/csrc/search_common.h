@@ -16,6 +16,7 @@ constexpr uint64_t KEY_MAX = ~0ull;
 constexpr int FLAG_OVERFLOW = 1;
 constexpr int FLAG_NONFINITE = 2;  // host flag word only: the query has a non-finite value
 constexpr int FLAG_BADID = 4;      // refine: a candidate id outside [-1, n)
+constexpr int FLAG_SEEDED = 8;     // the seeding committed the query's first k buffer entries
 
 // Wave-uniform reads of query slices go through the constant address space so
 // that they become scalar loads into SGPRs (a free broadcast to all lanes).
