@@ -344,6 +344,16 @@ def measure(run: Run, args, primary: bool) -> dict:
     log(f"[bench] {w.name}: timed {args.steps} steps in {elapsed:.3f}s ({qps:.0f} QPS)")
     res = {"qps": qps, "ms_per_step": ms_per_step}
     if args.profile_only:
+        if args.profile_brute:
+            # the brute-force scans of the baseline (same decomposition and per-wave)
+            from paper_2510_00566_amd.index import Params
+            for bprm in (run.prm, Params(scan_mode=4)):
+                bp = Params(**vars(bprm))
+                bp.use_bf16 = run.use_bf16
+                for _ in range(2):
+                    run.idx.search_bruteforce(run.qd, w.k, nprobe=run.npd, params=bp, out=(run.ids, run.dists),
+                                              nprobe_max=run.np_max, eager=args.eager)
+            torch.cuda.synchronize()
         return res
     ids_ref, d_ref = run.ids.clone(), run.dists.clone()
     st, scan_ms, phases = run.kernel_figures(args.steps)
@@ -526,6 +536,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--cpu-single", type=int, default=8, help="queries of the single-thread CPU run")
     ap.add_argument("--profile-only", action="store_true", help="warm up and run the timed steps only")
+    ap.add_argument("--profile-brute", action="store_true",
+                    help="with --profile-only: also run the brute-force scans twice each")
     ap.add_argument("--transform", default="residual", choices=["residual", "data"])
     ap.add_argument("--tune", action="store_true", help="run the autotuner (level width and search knobs)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the data-fit PCA comparison")

@@ -24,7 +24,9 @@
  *    length d unless stated otherwise.
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
  *    stream).  Calls enqueue their GPU work on it and return when the results
- *    are in the output arrays (they synchronise the stream before returning).
+ *    are in the output arrays (they synchronise the stream before returning),
+ *    except a search with PANO_SEARCH_ASYNC, whose results are complete in
+ *    stream order.
  *  - Distances are squared Euclidean distances.  The reported distance of a
  *    result is the canonical D(q, x): sum over j = 0..d-1, in that order, of
  *    ((double)q_j - (double)x_j)^2 with every product and sum rounded to
@@ -74,6 +76,12 @@ void pano_ctx_destroy(pano_ctx *ctx);
  * amount against its memory budget. */
 pano_status pano_ctx_scratch_bytes(const pano_ctx *ctx, int64_t *bytes);
 
+/* Wait for all work on the context's device and report, in
+ * *nonfinite_queries, the queries with a non-finite value that asynchronous
+ * searches (PANO_SEARCH_ASYNC) on this context met since the last call;
+ * EINVAL if there were any.  The count is reset. */
+pano_status pano_ctx_status(pano_ctx *ctx, int64_t *nonfinite_queries);
+
 /* Release the context's search scratch memory and its captured search graph
  * (the next search allocates again).  Call only while no search runs on the
  * context. */
@@ -115,7 +123,12 @@ void pano_transform_free(pano_transform *tf);
  * 64 nlist)) rows (all rows if n is smaller), drawn with `seed`; each of
  * `iters` iterations assigns every row to its nearest centroid
  * on the GPU and recomputes the means (an empty cluster keeps its centroid).
- * The final assignment pass uses the same nearest-centroid rule.  nlist = 1
+ * The final assignment pass gives each row the list with the smallest key
+ * (D, l), D the canonical distance (the FP64 sum of squared differences in
+ * coordinate order, rounded to float32) and ties to the smaller list: an FP32
+ * score with a certified margin keeps the lists that can hold that key, and
+ * these are rescored canonically (the iterations before it assign by the FP32
+ * score ||c||^2 - 2 <x, c> alone).  nlist = 1
  * gives the flat index (centroid = mean, every row in list 0).
  * Errors: EINVAL if nlist < 1 or nlist > n.
  */
@@ -195,6 +208,19 @@ typedef struct {
                                  write only the ms_* fields of the counters
                                  (the kernels are those of an ordinary search,
                                  without the counting of PANO_SEARCH_STATS) */
+#define PANO_SEARCH_ASYNC 8u  /* return without waiting: the results are
+                                 complete in stream order on `stream` (a
+                                 query whose result buffer overflows is
+                                 answered by an exact fallback on the device);
+                                 a query with a non-finite value gets
+                                 (-1, +inf) and is reported by the next
+                                 pano_ctx_status call on the context.
+                                 A later search on the same context, on any
+                                 stream, is ordered after it (they share the
+                                 context's scratch); the caller keeps the
+                                 query and output buffers alive until the
+                                 stream reaches the end.  Not with STATS or
+                                 TIMING. */
 
 /*
  * search: k nearest neighbours of each query among the vectors of its probed

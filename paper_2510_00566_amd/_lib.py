@@ -16,6 +16,7 @@ PANO_F32, PANO_BF16 = 0, 1
 PANO_SEARCH_STATS = 1
 PANO_SEARCH_EAGER = 2
 PANO_SEARCH_TIMING = 4
+PANO_SEARCH_ASYNC = 8
 
 
 class SearchParams(C.Structure):
@@ -66,6 +67,7 @@ def lib():
         "pano_ctx_destroy": (None, [P]),
         "pano_ctx_scratch_bytes": (C.c_int, [P, P]),
         "pano_ctx_trim": (C.c_int, [P]),
+        "pano_ctx_status": (C.c_int, [P, P]),
         "pano_build_transform": (C.c_int, [P, i64, i32, i64, u64, PP]),
         "pano_transform_identity": (C.c_int, [i32, PP]),
         "pano_transform_from": (C.c_int, [i32, P, P, PP]),
@@ -100,7 +102,7 @@ def check(status: int):
 
 def exported_symbols():
     return ["pano_last_error", "pano_version", "pano_ctx_create", "pano_ctx_destroy",
-            "pano_ctx_scratch_bytes", "pano_ctx_trim",
+            "pano_ctx_scratch_bytes", "pano_ctx_trim", "pano_ctx_status",
             "pano_build_transform", "pano_transform_identity", "pano_transform_from",
             "pano_transform_get", "pano_transform_free", "pano_ivf_assign", "pano_build_levels",
             "pano_search", "pano_search_ctx", "pano_search_scratch_bytes", "pano_search_noalloc", "pano_refine", "pano_search_bruteforce", "pano_index_info", "pano_index_layout",

@@ -157,6 +157,22 @@ pano_status pano_ctx_scratch_bytes(const pano_ctx *ctx, int64_t *bytes)
     });
 }
 
+pano_status pano_ctx_status(pano_ctx *ctx, int64_t *nonfinite_queries)
+{
+    return guarded([&] {
+        PANO_REQUIRE(ctx && nonfinite_queries, "null argument");
+        PANO_HIP(hipSetDevice(ctx->device));
+        PANO_HIP(hipDeviceSynchronize());
+        unsigned long long v = 0;
+        if (ctx->status.p) {
+            PANO_HIP(hipMemcpy(&v, ctx->status.p, sizeof(v), hipMemcpyDeviceToHost));
+            PANO_HIP(hipMemset(ctx->status.p, 0, sizeof(v)));
+        }
+        *nonfinite_queries = (int64_t)v;
+        PANO_REQUIRE(v == 0, "asynchronous searches met queries with a non-finite value");
+    });
+}
+
 pano_status pano_ctx_trim(pano_ctx *ctx)
 {
     return guarded([&] {
@@ -331,16 +347,22 @@ pano_status pano_ivf_assign(pano_ctx *ctx, const float *x_dev, int64_t n, int32_
         off_d.alloc(sizeof(int64_t) * (nlist + 1));
         std::vector<int32_t> asg(n);
         std::vector<int64_t> perm(n), off(nlist + 1);
-        auto assign_pass = [&]() {
+        // the iterations assign by the FP32 score; the final pass by the
+        // canonical (D, l) key
+        auto assign_pass = [&](bool canonical) {
             launch_sqnorms(centroids_dev, nlist, d, cn.as<float>(), s);
             for (int64_t r0 = 0; r0 < n; r0 += chunk) {
                 int64_t rn = std::min(chunk, n - r0);
                 launch_gemm_nt(x_dev + r0 * d, rn, d, centroids_dev, nlist, S.as<float>(), s);
-                launch_argmin_rows(S.as<float>(), rn, nlist, cn.as<float>(), assign_dev + r0, s);
+                if (canonical)
+                    launch_assign_canon(S.as<float>(), rn, nlist, cn.as<float>(), x_dev + r0 * d, centroids_dev, d,
+                                        assign_dev + r0, s);
+                else
+                    launch_argmin_rows(S.as<float>(), rn, nlist, cn.as<float>(), assign_dev + r0, s);
             }
         };
         for (int it = 0; it < iters; ++it) {
-            assign_pass();
+            assign_pass(false);
             PANO_HIP(hipMemcpyAsync(asg.data(), assign_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
             PANO_HIP(hipStreamSynchronize(s));
             std::fill(off.begin(), off.end(), 0);
@@ -353,7 +375,7 @@ pano_status pano_ivf_assign(pano_ctx *ctx, const float *x_dev, int64_t n, int32_
             launch_centroid_update(x_dev, d, perm_d.as<int64_t>(), off_d.as<int64_t>(), nlist, centroids_dev, s);
             PANO_HIP(hipStreamSynchronize(s));
         }
-        assign_pass();
+        assign_pass(true);
         PANO_HIP(hipStreamSynchronize(s));
     });
 }

@@ -141,10 +141,22 @@ struct pano_ctx {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
     hipEvent_t ev_in = nullptr;
+    // the end of the last asynchronous search, while it may still run: the
+    // next search is ordered after it, and nothing it uses is freed before it
+    hipEvent_t ev_async = nullptr;
+    bool async_pending = false;
     hipGraphExec_t graph_exec = nullptr;
     pano::GraphKey graph_key{};
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
+    pano::DevMem status;  // asynchronous searches: count of non-finite queries since the last status call
+
+    void status_ensure()
+    {
+        if (status.p) return;
+        status.alloc(256);
+        if (hipMemset(status.p, 0, 256) != hipSuccess) throw pano::Error{PANO_EDEVICE, "hipMemset failed"};
+    }
 
     hipStream_t work_stream()
     {
@@ -156,7 +168,8 @@ struct pano_ctx {
             if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&ev_join2, hipEventDisableTiming) != hipSuccess)
+                hipEventCreateWithFlags(&ev_join2, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&ev_async, hipEventDisableTiming) != hipSuccess)
                 throw pano::Error{PANO_EDEVICE, "hipEventCreate failed"};
             if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess ||
                 hipStreamCreateWithFlags(&aux2, hipStreamNonBlocking) != hipSuccess)
@@ -176,13 +189,23 @@ struct pano_ctx {
             throw pano::Error{PANO_ENOMEM, "hipHostMalloc failed"};
         pinned_bytes = nb;
     }
+    // wait for the last asynchronous search (before its memory or graph goes)
+    void quiesce()
+    {
+        if (!async_pending) return;
+        async_pending = false;
+        if (hipEventSynchronize(ev_async) != hipSuccess) throw pano::Error{PANO_EDEVICE, "hipEventSynchronize failed"};
+    }
     void drop_graph()
     {
+        quiesce();
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         graph_exec = nullptr;
     }
     ~pano_ctx()
     {
+        if (async_pending) (void)hipEventSynchronize(ev_async);
+        async_pending = false;
         drop_graph();
         if (pinned) (void)hipHostFree(pinned);
         for (auto &e : ev)
@@ -191,6 +214,7 @@ struct pano_ctx {
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (ev_join2) (void)hipEventDestroy(ev_join2);
+        if (ev_async) (void)hipEventDestroy(ev_async);
         if (aux) (void)hipStreamDestroy(aux);
         if (aux2) (void)hipStreamDestroy(aux2);
         if (stream) (void)hipStreamDestroy(stream);
@@ -279,6 +303,8 @@ void launch_row_norms(const float *Y, int64_t n, const LevelGeom &g, const float
                       float *tails_rowmajor, double *vnorm, hipStream_t s, const QueryConstsOut *qc = nullptr);
 void launch_argmin_rows(const float *S, int64_t n, int nb, const float *cnorm, int32_t *assign,
                         hipStream_t s);
+void launch_assign_canon(const float *S, int64_t n, int nb, const float *cnorm, const float *X, const float *cent,
+                         int d, int32_t *assign, hipStream_t s);
 void launch_centroid_update(const float *X, int d, const int64_t *perm, const int64_t *off, int nlist,
                             float *cent, hipStream_t s);
 void launch_sqnorms(const float *X, int64_t n, int d, float *out, hipStream_t s);

@@ -3,8 +3,10 @@
 // update (the IVF coarse quantiser of Section 6.1), per-row tail norms
 // (Section 6.5) and the level-major packing of Section 6.1.
 #include "internal.h"
+#include "search_common.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace pano {
 
@@ -377,6 +379,108 @@ void launch_argmin_rows(const float *S, int64_t n, int nb, const float *cnorm, i
 {
     if (n == 0) return;
     hipLaunchKernelGGL(k_argmin_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, S, n, nb, cnorm, assign);
+    PANO_HIP(hipGetLastError());
+}
+
+// The final assignment by the canonical (D, l) rule, D the canonical distance
+// (sequential FP64 over the raw rows, rounded to FP32), ties to the smaller
+// list.  One wavefront per row.  The FP32 score a_l = ||c_l||^2 - 2 <x, c_l>
+// lies within del_l = c_as (||x||^2 + ||c_l||^2) + 2^-22 |a_l| of its exact
+// value (c_as covers the rounding of the norms and of the tiled products);
+// with U the smallest a_l + del_l, widened by 2^-20 (||x||^2 + |U|) for the
+// FP32 rounding of D, only lists with a_l - del_l <= U can hold the smallest
+// key.  A single such list is the answer; several are rescored with the
+// canonical distance.  Rows without any (a non-finite value) keep the FP32
+// argmin.
+__global__ __launch_bounds__(256) void k_assign_canon(const float *__restrict__ S, int64_t n, int nb,
+                                                      const float *__restrict__ cnorm, const float *__restrict__ X,
+                                                      const float *__restrict__ cent, int d, float c_as,
+                                                      int32_t *__restrict__ assign)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    const float *x = X + r * d;
+    float xx = 0.f;
+    for (int j = lane; j < d; j += 64) xx = __builtin_fmaf(x[j], x[j], xx);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) xx += __shfl_xor(xx, o, 64);
+    const float *srow = S + r * nb;
+    float ub = INFINITY, best = INFINITY;
+    int bi = 0x7fffffff;
+    for (int c = lane; c < nb; c += 64) {
+        const float a = cnorm[c] - 2.f * srow[c];
+        const float del = c_as * (xx + cnorm[c]) + 0x1p-22f * fabsf(a);
+        ub = fminf(ub, a + del);
+        if (a < best || (a == best && c < bi)) {
+            best = a;
+            bi = c;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ub = fminf(ub, __shfl_xor(ub, o, 64));
+        const float ov = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov < best || (ov == best && oi < bi)) {
+            best = ov;
+            bi = oi;
+        }
+    }
+    const float U = ub + 0x1p-20f * (xx + fabsf(ub));
+    // the lists that can hold the smallest key: count them, keep one
+    int cnt = 0, one = -1;
+    for (int c0 = 0; c0 < nb; c0 += 64) {
+        const int c = c0 + lane;
+        bool mem = false;
+        if (c < nb) {
+            const float a = cnorm[c] - 2.f * srow[c];
+            const float del = c_as * (xx + cnorm[c]) + 0x1p-22f * fabsf(a);
+            mem = a - del <= U;
+        }
+        const uint64_t bm = __ballot(mem);
+        if (bm != 0 && one < 0) one = c0 + __ffsll((long long)bm) - 1;
+        cnt += __popcll(bm);
+    }
+    int ans = bi;
+    if (cnt == 1) {
+        ans = one;
+    } else if (cnt > 1) {
+        uint64_t key = KEY_MAX;
+        for (int c0 = 0; c0 < nb; c0 += 64) {
+            const int c = c0 + lane;
+            if (c < nb) {
+                const float a = cnorm[c] - 2.f * srow[c];
+                const float del = c_as * (xx + cnorm[c]) + 0x1p-22f * fabsf(a);
+                if (a - del <= U) {
+                    const uint64_t kc = make_key(canon_dist(x, cent + (int64_t)c * d, d), c);
+                    key = kc < key ? kc : key;
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t lo = __shfl_xor((uint32_t)key, o, 64), hi = __shfl_xor((uint32_t)(key >> 32), o, 64);
+            const uint64_t ok = ((uint64_t)hi << 32) | lo;
+            key = ok < key ? ok : key;
+        }
+        if (key != KEY_MAX) ans = key_id(key);
+    }
+    if (lane == 0) assign[r] = ans;
+}
+
+void launch_assign_canon(const float *S, int64_t n, int nb, const float *cnorm, const float *X, const float *cent,
+                         int d, int32_t *assign, hipStream_t s)
+{
+    if (n == 0) return;
+    // rounding of ||c||^2 (per-lane FMA chains over d / 64 terms, then six
+    // additions) and of the tiled product (gamma(32 + ceil(d / 32) + 1) of the
+    // absolute products, which sum to at most (||x||^2 + ||c||^2) / 2, twice)
+    const double u = std::ldexp(1.0, -24);
+    auto gam = [&](double m) { return m * u / (1.0 - m * u); };
+    const float c_as = (float)(1.25 * (gam(d / 64.0 + 8) + gam(33.0 + (d + 31) / 32) + 2 * u));
+    hipLaunchKernelGGL(k_assign_canon, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, S, n, nb, cnorm, X, cent, d,
+                       c_as, assign);
     PANO_HIP(hipGetLastError());
 }
 

@@ -2462,8 +2462,8 @@ __global__ __launch_bounds__(NT) void k_fallback_keys(const float *__restrict__ 
 // The k smallest of `total` distinct 64-bit keys (KEY_MAX pads empty slots):
 // radix select of the k-th key over the 64 bits, 8 per pass, with a 256-bin
 // histogram in LDS, then the keys up to it are gathered and sorted.
-__global__ __launch_bounds__(NT) void k_fallback_select(const uint64_t *__restrict__ keys, int64_t total, int k,
-                                                        int64_t *__restrict__ out_ids, float *__restrict__ out_d)
+__device__ __forceinline__ void fallback_select_block(const uint64_t *__restrict__ keys, int64_t total, int k,
+                                                      int64_t *__restrict__ out_ids, float *__restrict__ out_d)
 {
     __shared__ int hist[256];
     __shared__ int sel[2];
@@ -2518,6 +2518,77 @@ __global__ __launch_bounds__(NT) void k_fallback_select(const uint64_t *__restri
         } else {
             out_ids[r] = key_id(b);
             out_d[r] = key_dist(b);
+        }
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_fallback_select(const uint64_t *__restrict__ keys, int64_t total, int k,
+                                                        int64_t *__restrict__ out_ids, float *__restrict__ out_d)
+{
+    fallback_select_block(keys, total, k, out_ids, out_d);
+}
+
+// The exact fallback on the device, for searches that do not wait on the
+// host: one workgroup checks the queries NT at a time; a query with a
+// non-finite value gets (-1, +inf) and is counted in nonfinite[0]; a query
+// whose result buffer overflowed gets the canonical distances of all its
+// probed candidates (keys in `keys`, room for the largest probe set) and the
+// k smallest of them.  Overflow is rare, so the queries that need it are
+// handled one after another.
+__global__ __launch_bounds__(NT) void k_fallback_device(int64_t nq, int k, int d, int np_max,
+                                                        const int32_t *__restrict__ qflags,
+                                                        const int32_t *__restrict__ qbad,
+                                                        const int32_t *__restrict__ probes,
+                                                        const int32_t *__restrict__ npq, const float *__restrict__ q,
+                                                        const int64_t *__restrict__ list_blk, int B,
+                                                        const int32_t *__restrict__ ids,
+                                                        const int32_t *__restrict__ blk_cnt,
+                                                        const float *__restrict__ raw, uint64_t *__restrict__ keys,
+                                                        int64_t *__restrict__ out_ids, float *__restrict__ out_d,
+                                                        unsigned long long *__restrict__ nonfinite)
+{
+    __shared__ int32_t todo[NT];
+    __shared__ int ntodo;
+    for (int64_t q0 = 0; q0 < nq; q0 += NT) {
+        if (threadIdx.x == 0) ntodo = 0;
+        __syncthreads();
+        const int64_t qi = q0 + threadIdx.x;
+        if (qi < nq) {
+            if (qbad[qi]) {
+                for (int r = 0; r < k; ++r) {
+                    out_ids[qi * k + r] = -1;
+                    out_d[qi * k + r] = INFINITY;
+                }
+                atomicAdd(nonfinite, 1ull);
+            } else if (qflags[qi] & FLAG_OVERFLOW) {
+                todo[atomicAdd(&ntodo, 1)] = (int32_t)threadIdx.x;
+            }
+        }
+        __syncthreads();
+        const int nt = ntodo;
+        for (int j = 0; j < nt; ++j) {
+            const int64_t qj = q0 + todo[j];
+            const int npv = npq[qj];
+            const int32_t *lists = probes + qj * np_max;
+            int64_t total = 0;
+            for (int li = 0; li < npv; ++li) {
+                const int l = lists[li];
+                const int64_t nslots = (list_blk[l + 1] - list_blk[l]) * B;
+                for (int64_t t = threadIdx.x; t < nslots; t += NT) {
+                    const int64_t gb = list_blk[l] + t / B;
+                    const int sl = (int)(t % B);
+                    uint64_t key = KEY_MAX;
+                    if (sl < blk_cnt[gb]) {
+                        const int32_t id = ids[gb * B + sl];
+                        key = make_key(canon_dist(q + qj * d, raw + (int64_t)id * d, d), id);
+                    }
+                    keys[total + t] = key;
+                }
+                total += nslots;
+            }
+            __syncthreads();
+            fallback_select_block(keys, total, k, out_ids + qj * k, out_d + qj * k);
+            __syncthreads();
         }
     }
 }
@@ -2951,6 +3022,11 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     const int np_max = probe_cap(nprobe_dev != nullptr, nprobe_all, nlist);
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
     const bool want_timing = !want_stats && (flags & PANO_SEARCH_TIMING) != 0;
+    // a search that does not wait: the exact fallback runs on the device and
+    // non-finite queries are counted for pano_ctx_status
+    const bool async_mode = (flags & PANO_SEARCH_ASYNC) != 0;
+    PANO_REQUIRE(!async_mode || (!want_stats && !want_timing && !fixed),
+                 "an asynchronous search takes no stats or timing flags");
     // the seeding starts every scan's threshold, the brute-force scan's too
     // (it then commits fewer candidates; every distance is still computed),
     // and at eps < 1 as well: its k best are committed, so the threshold
@@ -2980,11 +3056,25 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         flags_dev = cf.take<int32_t>(nq);
         fb_total = cf.take<int64_t>(1);
     } else {
+        // a search is ordered after the context's last asynchronous one (they
+        // share its scratch), and buffers that must grow wait for it to end
+        if (ctx->async_pending) {
+            PANO_HIP(hipStreamWaitEvent(s, ctx->ev_async, 0));
+            if (need0 > ctx->scratch[0].bytes || need1 > ctx->scratch[1].bytes || need2 > ctx->scratch[2].bytes ||
+                need3 > ctx->scratch[3].bytes || (async_mode && need[6] > ctx->scratch[4].bytes) ||
+                sizeof(int32_t) * (size_t)nq > ctx->pinned_bytes)
+                ctx->quiesce();
+        }
         ctx->scratch[0].ensure(need0);
         ctx->scratch[1].ensure(need1);
         ctx->scratch[2].ensure(need2);
         ctx->scratch[3].ensure(need3);
         for (int i = 0; i < 4; ++i) sp[i] = ctx->scratch[i].p;
+        if (async_mode) {
+            ctx->scratch[4].ensure(need[6]);
+            sp[4] = ctx->scratch[4].p;
+            ctx->status_ensure();
+        }
     }
     Carver c0(sp[0]), c2(sp[2]), c3(sp[3]);
     float *qy = c0.take<float>(nq * ix->d_pad);
@@ -3185,7 +3275,16 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         }
         if (events_on) PANO_HIP(hipEventRecord(ctx->ev[2], st));
         hipLaunchKernelGGL(k_merge, dim3((unsigned)nq), dim3(NT), merge_shm, st, c, buf, buf_cnt, qflags, qE, qA, q,
-                           ix->raw.as<float>(), d, ids, dists, stats_on ? stats : nullptr, h_flags, qbad);
+                           ix->raw.as<float>(), d, ids, dists, stats_on ? stats : nullptr, async_mode ? nullptr : h_flags,
+                           qbad);
+        if (async_mode) {
+            Carver c4(sp[4]);
+            (void)c4.take<int32_t>(std::max(1, np_max));
+            hipLaunchKernelGGL(k_fallback_device, dim3(1), dim3(NT), 0, st, nq, k, d, np_max, qflags, qbad, probes, npq,
+                               q, ix->list_blk_d.as<int64_t>(), ix->B, ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(),
+                               ix->raw.as<float>(), c4.take<uint64_t>(1), ids, dists,
+                               reinterpret_cast<unsigned long long *>(ctx->status.p));
+        }
         if (events_on) PANO_HIP(hipEventRecord(ctx->ev[3], st));
         PANO_HIP(hipGetLastError());
     };
@@ -3212,8 +3311,8 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         enqueue(ws, want_stats, true);
     } else if (use_graph) {
         GraphKey key{ix->serial, q, nq, k, nprobe_dev, nprobe_all, eps, brute, ids, dists, c.G, c.bpi, seed_pool, seed_cnt, grid,
-                     c.dense_min, c.bf16, (wave ? 2 : 0) | (sort_groups ? 4 : 0), c.walk_lanes, c.walk2, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
-                     nullptr, nullptr, ctx->pinned};
+                     c.dense_min, c.bf16, (wave ? 2 : 0) | (sort_groups ? 4 : 0) | (async_mode ? 8 : 0), c.walk_lanes, c.walk2, ctx->scratch[0].p, ctx->scratch[1].p, ctx->scratch[2].p, ctx->scratch[3].p,
+                     async_mode ? sp[4] : nullptr, async_mode ? ctx->status.p : nullptr, ctx->pinned};
         if (!ctx->graph_exec || !(ctx->graph_key == key)) {
             ctx->drop_graph();
             hipGraph_t graph;
@@ -3235,6 +3334,17 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
         rs = s;
     } else {
         enqueue(ws, false, false);
+    }
+    if (async_mode) {
+        // ordered on the caller's stream (graph) or after it (eager); results
+        // are complete in stream order, nothing waits here
+        if (!use_graph) {
+            PANO_HIP(hipEventRecord(ctx->ev_in, ws));
+            PANO_HIP(hipStreamWaitEvent(s, ctx->ev_in, 0));
+        }
+        PANO_HIP(hipEventRecord(ctx->ev_async, s));
+        ctx->async_pending = true;
+        return;
     }
     PANO_HIP(hipStreamSynchronize(rs));
     std::vector<int32_t> hflags(h_flags, h_flags + nq);
@@ -3354,6 +3464,7 @@ void run_refine(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
                          3 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
     const size_t need3 = 4 * align_up(sizeof(float) * nq) + align_up(sizeof(uint64_t) * nq * c.capq) +
                          align_up(sizeof(unsigned long long) * 128);
+    ctx->quiesce();  // the scratch is the one an asynchronous search may still use
     ctx->scratch[0].ensure(need0);
     ctx->scratch[3].ensure(need3);
     Carver c0(ctx->scratch[0].p), c3(ctx->scratch[3].p);

@@ -39,6 +39,15 @@ class Context:
         L.check(L.lib().pano_ctx_scratch_bytes(self.h, C.byref(out)))
         return out.value
 
+    def status(self) -> int:
+        """Wait for the device; raise if asynchronous searches met non-finite
+        queries since the last call (their count is in the error)."""
+        out = C.c_int64()
+        st = L.lib().pano_ctx_status(self.h, C.byref(out))
+        if st != L.PANO_OK:
+            raise L.PanoError(st, L.lib().pano_last_error().decode(errors="replace") + f" ({out.value})")
+        return out.value
+
     def trim(self):
         """Release the context's search scratch (no search may be running on it)."""
         L.check(L.lib().pano_ctx_trim(self.h))
@@ -177,18 +186,19 @@ class Index:
 
     def search(self, q_dev, k: int, nprobe=1, eps: float = 1.0, params: Params | None = None,
                stats: bool = False, stream=None, out=None, eager: bool = False, ctx: Context | None = None,
-               timing: bool = False, nprobe_max: int = 0):
+               timing: bool = False, nprobe_max: int = 0, asynchronous: bool = False):
         """k-NN of each row of q_dev among its probed lists.  nprobe: an int,
         or a device tensor of per-query counts (bounded by nprobe_max when
         positive).  ctx: run on this context (one per concurrent caller)
         instead of the index's own.  timing: phase durations of an ordinary
-        (uncounted) search in stats()."""
+        (uncounted) search in stats().  asynchronous: return without waiting
+        (results complete in stream order; see Context.status)."""
         import torch
         ids, dists = out if out is not None else self._outs(q_dev, k)
         np_dev, np_all = _probe_args(nprobe, nprobe_max)
         prm = params.c() if params is not None else None
         flags = ((L.PANO_SEARCH_STATS if stats else 0) | (L.PANO_SEARCH_EAGER if eager else 0) |
-                 (L.PANO_SEARCH_TIMING if timing else 0))
+                 (L.PANO_SEARCH_TIMING if timing else 0) | (L.PANO_SEARCH_ASYNC if asynchronous else 0))
         c = ctx if ctx is not None else self.ctx
         L.check(L.lib().pano_search_ctx(c.h, self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all,
                                         float(eps), _ptr(ids), _ptr(dists),

@@ -285,3 +285,19 @@ def test_out_of_distribution_queries_stay_exact(torch_cuda):
         _log(f"case ood q_spec_p={qp} n=20000 d=960")
         _, _, st = _run(torch_cuda, case, w, q)
         assert st["fallback_queries"] == 0
+
+
+@gpu
+@pytest.mark.parametrize("name,n,nlist", [("ivf_gist_like", 12000, 48), ("ivf_zipf_batched", 40000, 96)])
+def test_ivf_assign_final_pass_canonical(torch_cuda, name, n, nlist):
+    """The k-means' final pass gives every row the list with the smallest
+    (canonical D, list id) key: the oracle's count of rows that are not so
+    assigned is zero."""
+    from tests import gpu_cases as gc
+    w = synth.scaled(synth.WORKLOADS[name], n=n, nq=1, nlist=nlist, n_clusters=nlist)
+    data = synth.generate(w, with_queries=False)
+    _log(f"case canonical assignment {name} n={n} nlist={nlist}")
+    case = gc.build_case(w, data={"x": data["x"]})
+    bad = brute.assignment_mismatches(case["x"], case["cent"], case["assign"])
+    _log("assignment mismatches", bad)
+    assert bad == 0
