@@ -11,7 +11,8 @@ What it follows:
     mean(E_l).  Levels are visited front to back; a level over the cap is
     rotated together with the fewest following coordinates s >= 1 for which
     its expected energy after a Haar rotation of that block, b_l / (b_l + s)
-    times the block's total, is at most tau (s stops at the last coordinate).
+    times the block's total, is at most tau (s stops at the last coordinate;
+    "at most" allows a relative 1e-9 for rounding).
     After the rotation every coordinate of the block carries the block's mean
     variance.  The plan is the ordered list of rotated blocks.
   * Section 4.2, Procedure 2 (intra-level isotropization): one Haar rotation
@@ -53,27 +54,31 @@ def robin_hood_plan(lam, cuts, kappa: float):
     """Procedure 1 on expected variances.  Returns (blocks, v): blocks is a
     list of (start, length) coordinate ranges, rotated in this order; v the
     expected per-coordinate variances afterwards."""
-    v = np.asarray(lam, dtype=np.float64).copy()
+    # every sum is taken in coordinate order (Python's sum adds left to right)
+    v = [float(x) for x in np.asarray(lam, dtype=np.float64)]
     m = [int(c) for c in cuts]
     L = len(m) - 1
     d = m[-1]
-    tau = kappa * v.sum() / L
+    # an energy within a relative 1e-9 of the cap counts as within it, so that
+    # rounding alone never asks for a rotation
+    tau = kappa * sum(v) / L
+    cap = tau * (1.0 + 1e-9)
     blocks = []
     for l in range(L):
         lo, hi = m[l], m[l + 1]
         b = hi - lo
-        if v[lo:hi].sum() <= tau:
+        if sum(v[lo:hi]) <= cap:
             continue
         s = 1
-        while hi + s < d and b / (b + s) * v[lo:hi + s].sum() > tau:
+        while hi + s < d and b / (b + s) * sum(v[lo:hi + s]) > cap:
             s += 1
         s = min(s, d - hi)
         if s == 0:
             continue
-        blk = v[lo:hi + s]
-        v[lo:hi + s] = blk.sum() / (b + s)
+        mean = sum(v[lo:hi + s]) / (b + s)
+        v[lo:hi + s] = [mean] * (b + s)
         blocks.append((lo, b + s))
-    return blocks, v
+    return blocks, np.asarray(v)
 
 
 def level_energies(v, cuts) -> np.ndarray:
