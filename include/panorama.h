@@ -56,6 +56,7 @@ typedef enum { PANO_F32 = 0, PANO_BF16 = 1 } pano_dtype;
 typedef struct pano_ctx pano_ctx;
 typedef struct pano_transform pano_transform;
 typedef struct pano_index pano_index;
+typedef struct pano_pq_index pano_pq_index;
 
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char *pano_last_error(void);
@@ -373,6 +374,109 @@ pano_status pano_stats_get(const pano_index *idx, pano_stats_t *out);
  * for this index).  Call before destroying the index's context.  NULL is a
  * no-op. */
 void pano_index_free(pano_index *idx);
+
+/* ===================================================================== IVFPQ
+ * The method over product-quantized vectors (Section 4.2 spectrum shaping,
+ * Section 6.2 the IVFPQ scan).
+ */
+
+/*
+ * shape_plan: Procedure 1 of Section 4.2 (Robin Hood inter-level shaping) on
+ * expected per-coordinate variances lambda_host [d] (the PCA eigenvalues,
+ * descending).  Level energies are sums of the variances over the levels cut
+ * by m_host [L+1] (m[0] = 0 < ... < m[L] = d); the cap is tau = kappa times
+ * their mean (kappa >= 1).  Levels are visited front to back; a level above
+ * the cap is rotated together with the fewest following coordinates s >= 1
+ * that bring its expected energy after a Haar rotation of the block,
+ * b / (b + s) times the block total, to tau or below (s stops at the last
+ * coordinate); the block's coordinates then carry its mean variance.  All
+ * sums run in coordinate order, and an energy within a relative 1e-9 of tau
+ * counts as within the cap.  Writes the rotated blocks as (start,
+ * length) pairs into blocks_host [2 * cap] in plan order and their count into
+ * *nblocks.  Host only.  Errors: EINVAL on bad cuts, kappa < 1 or a plan
+ * longer than cap (then *nblocks is the length needed).
+ */
+pano_status pano_shape_plan(const double *lambda_host, int32_t d, const int32_t *m_host, int32_t L,
+                            double kappa, int32_t *blocks_host, int32_t cap, int32_t *nblocks);
+
+/*
+ * transform_shape: the shaped transform U R T_PCA of Section 4.2.  R applies
+ * a Haar-random rotation to each block of pano_shape_plan (with the
+ * transform's eigenvalues and the given cuts and kappa), in plan order; when
+ * isotropize is nonzero, U applies an independent Haar rotation within each
+ * level (Procedure 2).  The rotations come from a counter-based generator
+ * seeded by `seed` (splitmix64, Box-Muller normals, Householder QR with the
+ * sign fix that makes Q Haar-distributed).  The result keeps mu; its lambda
+ * holds the expected per-coordinate variances after shaping.  A transform
+ * without eigenvalues (pano_transform_from) gets no R.  Host only; the caller
+ * owns *out.  Errors: EINVAL on bad cuts or kappa < 1.
+ */
+pano_status pano_transform_shape(const pano_transform *pca, const int32_t *m_host, int32_t L, double kappa,
+                                 int32_t isotropize, uint64_t seed, pano_transform **out);
+
+/*
+ * pq_build: the IVFPQ index of Section 6.2 over the shaped frame of tf.
+ * Rows x_dev [n][d] (device, FP32) are mapped to y = T (x - mu) and split into
+ * M = d / dsub sub-vectors of dsub coordinates (dsub in {1, 2, 4, 8, 16};
+ * M <= 128, since the scan keeps a query's table of M x 256 floats in LDS);
+ * each sub-quantizer has 256 codewords, trained by Lloyd iterations (`iters`,
+ * FP64 means, an empty cell keeps its codeword) on a seeded sample of
+ * max(256, min(n, sample)) rows from 256 sample rows spread over the sample,
+ * and every row is coded by its nearest codewords (FP32 distance, ties to the
+ * smaller code).  Codes describe y itself, not its offset from the list
+ * centroid.  The levels m_host [L+1] (1 <= L <= 64) must fall on sub-vector
+ * boundaries.  Lists follow assign_dev [n] in [0, nlist) with
+ * centroids_dev [nlist][d] (raw space, for probing).  Layout in device
+ * memory, per list, blocks of 256 slots: the codes of a block sub-quantizer
+ * by sub-quantizer, 256 bytes each (one byte per slot), then the norms of each
+ * slot's reconstruction beyond levels 1..L-1 (FP32, level-major), then the
+ * slot ids.  The index owns its memory.  Errors: EINVAL on shapes, cuts,
+ * dsub or M; ENOMEM.
+ */
+pano_status pano_pq_build(pano_ctx *ctx, const pano_transform *tf, const float *x_dev, int64_t n, int32_t d,
+                          const float *centroids_dev, const int32_t *assign_dev, int32_t nlist,
+                          const int32_t *m_host, int32_t L, int32_t dsub, int32_t iters, int64_t sample,
+                          uint64_t seed, pano_pq_index **out, void *stream);
+
+#define PANO_PQ_BRUTE 16u /* pq_search: read every sub-quantizer of every
+                             candidate (no pruning): the brute-force scan of
+                             the same codes */
+
+/*
+ * pq_search: k nearest candidates of each query by the PQ distance over its
+ * probed lists (Section 6.2 with Algorithm 1's level loop).  The probe set is
+ * that of pano_search (canonical (D, l) order in raw space).  The query's
+ * shaped coordinates y_i = sum_j T_ij (q_j - mu_j) are summed in coordinate
+ * order in FP64; its table entry (m, c) is float32 of the FP64 sum of
+ * (y_j - C[m][c][j])^2 over the sub-vector in order; a candidate's distance
+ * is float32 of the FP64 sum of its M entries in sub-quantizer order.  A
+ * candidate is dropped after a level once the bound P + (a - b)^2 +
+ * 2 (1 - eps) a b (Eq. 3/4: P the entries read so far, a and b the norms of
+ * the query and of the reconstruction beyond the level, with certified
+ * rounding margins) exceeds the running k-th distance; at eps = 1 the answer
+ * is the first k by (distance, id), exactly, padded with (-1, +inf).
+ * q_dev [nq][d]; nprobe as in pano_search (at most 1024 lists per query);
+ * 1 <= k <= 128; ids_dev [nq][k] int64, dists_dev [nq][k] float.  flags:
+ * PANO_PQ_BRUTE, PANO_SEARCH_STATS (counts for pano_pq_stats).  Blocks until
+ * the results are written.  Errors: EINVAL (sizes, a query with a non-finite
+ * value), ENOMEM.
+ */
+pano_status pano_pq_search(pano_ctx *ctx, pano_pq_index *idx, const float *q_dev, int64_t nq, int32_t k,
+                           const int32_t *nprobe_dev, int32_t nprobe_all, float eps, int64_t *ids_dev,
+                           float *dists_dev, uint32_t flags, void *stream);
+
+/* Counters of the last pq_search with PANO_SEARCH_STATS: out[0] table
+ * look-ups done, out[1] look-ups of the unpruned scan (candidates x M),
+ * out[2] queries answered by the exact fallback, out[3] candidates;
+ * *ms_scan the scan kernel's duration. */
+pano_status pano_pq_stats(const pano_pq_index *idx, int64_t *out4, double *ms_scan);
+
+/* Copy out the trained quantizer: codebooks_host [M][256][dsub] FP32 and
+ * codes_host [n][M] (row order); either may be NULL.  *M_out and *dsub_out
+ * if non-NULL. */
+pano_status pano_pq_export(const pano_pq_index *idx, float *codebooks_host, uint8_t *codes_host, int32_t *M_out,
+                           int32_t *dsub_out);
+void pano_pq_free(pano_pq_index *idx);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,7 @@ PANO_SEARCH_STATS = 1
 PANO_SEARCH_EAGER = 2
 PANO_SEARCH_TIMING = 4
 PANO_SEARCH_ASYNC = 8
+PANO_PQ_BRUTE = 16
 
 
 class SearchParams(C.Structure):
@@ -85,6 +86,13 @@ def lib():
         "pano_index_layout": (C.c_int, [P, P, P]),
         "pano_stats_get": (C.c_int, [P, P]),
         "pano_index_free": (None, [P]),
+        "pano_shape_plan": (C.c_int, [P, i32, P, i32, C.c_double, P, i32, P]),
+        "pano_transform_shape": (C.c_int, [P, P, i32, C.c_double, i32, u64, PP]),
+        "pano_pq_build": (C.c_int, [P, P, P, i64, i32, P, P, i32, P, i32, i32, i32, i64, u64, PP, P]),
+        "pano_pq_search": (C.c_int, [P, P, P, i64, i32, P, i32, f32, P, P, u32, P]),
+        "pano_pq_stats": (C.c_int, [P, P, P]),
+        "pano_pq_export": (C.c_int, [P, P, P, P, P]),
+        "pano_pq_free": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -106,4 +114,5 @@ def exported_symbols():
             "pano_build_transform", "pano_transform_identity", "pano_transform_from",
             "pano_transform_get", "pano_transform_free", "pano_ivf_assign", "pano_build_levels",
             "pano_search", "pano_search_ctx", "pano_search_scratch_bytes", "pano_search_noalloc", "pano_refine", "pano_search_bruteforce", "pano_index_info", "pano_index_layout",
-            "pano_stats_get", "pano_index_free"]
+            "pano_stats_get", "pano_index_free", "pano_shape_plan", "pano_transform_shape", "pano_pq_build",
+            "pano_pq_search", "pano_pq_stats", "pano_pq_export", "pano_pq_free"]

@@ -674,4 +674,132 @@ void pano_index_free(pano_index *idx)
     delete idx;
 }
 
+// ---------------------------------------------------------------- IVFPQ
+static std::vector<int> checked_cuts(const int32_t *m_host, int32_t L, int32_t d)
+{
+    PANO_REQUIRE(m_host != nullptr, "null argument");
+    PANO_REQUIRE(L >= 1 && L <= 64, "L must be in [1, 64]");
+    PANO_REQUIRE(m_host[0] == 0 && m_host[L] == d, "level cuts must start at 0 and end at d");
+    for (int l = 0; l < L; ++l) PANO_REQUIRE(m_host[l] < m_host[l + 1], "level cuts must increase");
+    return std::vector<int>(m_host, m_host + L + 1);
+}
+
+pano_status pano_shape_plan(const double *lambda_host, int32_t d, const int32_t *m_host, int32_t L, double kappa,
+                            int32_t *blocks_host, int32_t cap, int32_t *nblocks)
+{
+    return guarded([&] {
+        PANO_REQUIRE(lambda_host && nblocks && (cap == 0 || blocks_host), "null argument");
+        PANO_REQUIRE(d >= 1, "d must be >= 1");
+        PANO_REQUIRE(kappa >= 1.0, "kappa must be >= 1");
+        const std::vector<int> cuts = checked_cuts(m_host, L, d);
+        const auto blocks = shape_plan(std::vector<double>(lambda_host, lambda_host + d), cuts, kappa, nullptr);
+        *nblocks = (int32_t)blocks.size();
+        PANO_REQUIRE((int32_t)blocks.size() <= cap, "the plan has more blocks than cap");
+        for (size_t i = 0; i < blocks.size(); ++i) {
+            blocks_host[2 * i] = blocks[i].first;
+            blocks_host[2 * i + 1] = blocks[i].second;
+        }
+    });
+}
+
+pano_status pano_transform_shape(const pano_transform *pca, const int32_t *m_host, int32_t L, double kappa,
+                                 int32_t isotropize, uint64_t seed, pano_transform **out)
+{
+    return guarded([&] {
+        PANO_REQUIRE(pca && out, "null argument");
+        PANO_REQUIRE(kappa >= 1.0, "kappa must be >= 1");
+        const std::vector<int> cuts = checked_cuts(m_host, L, pca->d);
+        auto tf = std::make_unique<pano_transform>();
+        tf->d = pca->d;
+        tf->mu = pca->mu;
+        tf->T = pca->T;
+        tf->alpha = pca->alpha;
+        std::vector<double> lam = pca->lambda;
+        if (lam.size() != (size_t)pca->d) lam.assign(pca->d, 0.0);
+        tf->lambda = shape_transform(tf->T, pca->d, lam, cuts, kappa, isotropize != 0, seed);
+        *out = tf.release();
+    });
+}
+
+pano_status pano_pq_build(pano_ctx *ctx, const pano_transform *tf, const float *x_dev, int64_t n, int32_t d,
+                          const float *centroids_dev, const int32_t *assign_dev, int32_t nlist, const int32_t *m_host,
+                          int32_t L, int32_t dsub, int32_t iters, int64_t sample, uint64_t seed, pano_pq_index **out,
+                          void *stream)
+{
+    return guarded([&] {
+        PANO_REQUIRE(n >= 256 && d >= 1 && nlist >= 1 && nlist <= n, "need n >= 256 and 1 <= nlist <= n");
+        PANO_REQUIRE(dsub == 1 || dsub == 2 || dsub == 4 || dsub == 8 || dsub == 16, "dsub must be 1, 2, 4, 8 or 16");
+        PANO_REQUIRE(d % dsub == 0 && d / dsub <= 128, "need d divisible by dsub and M = d / dsub <= 128");
+        PANO_REQUIRE(iters >= 0, "iters must be >= 0");
+        const std::vector<int> cuts = checked_cuts(m_host, L, d);
+        for (int l = 0; l <= L; ++l) PANO_REQUIRE(cuts[l] % dsub == 0, "level cuts must fall on sub-vector boundaries");
+        PANO_REQUIRE(ctx && tf && x_dev && centroids_dev && assign_dev && out, "null argument");
+        PANO_REQUIRE(tf->d == d, "transform dimension does not match d");
+        PANO_HIP(hipSetDevice(ctx->device));
+        auto ix = std::make_unique<pano_pq_index>();
+        ix->ctx = ctx;
+        ix->n = n;
+        ix->d = d;
+        ix->nlist = nlist;
+        ix->L = L;
+        ix->dsub = dsub;
+        ix->M = d / dsub;
+        ix->cuts = cuts;
+        ix->sub_off.resize(L + 1);
+        for (int l = 0; l <= L; ++l) ix->sub_off[l] = cuts[l] / dsub;
+        run_pq_build(ctx, ix.get(), tf, x_dev, centroids_dev, assign_dev, iters, sample, seed, (hipStream_t)stream);
+        *out = ix.release();
+    });
+}
+
+pano_status pano_pq_search(pano_ctx *ctx, pano_pq_index *idx, const float *q_dev, int64_t nq, int32_t k,
+                           const int32_t *nprobe_dev, int32_t nprobe_all, float eps, int64_t *ids_dev,
+                           float *dists_dev, uint32_t flags, void *stream)
+{
+    return guarded([&] {
+        PANO_REQUIRE(ctx && idx && (nq == 0 || (q_dev && ids_dev && dists_dev)), "null argument");
+        PANO_REQUIRE(k >= 1 && k <= 128 && nq >= 0, "need 1 <= k <= 128 and nq >= 0");
+        PANO_REQUIRE(eps >= 0.f && eps <= 1.f, "eps must be in [0, 1]");
+        PANO_REQUIRE(nprobe_dev != nullptr || nprobe_all >= 1, "nprobe_all must be >= 1");
+        PANO_REQUIRE((flags & ~(PANO_PQ_BRUTE | PANO_SEARCH_STATS)) == 0, "unsupported flags");
+        if (nq == 0) return;
+        PANO_HIP(hipSetDevice(ctx->device));
+        run_pq_search(ctx, idx, q_dev, nq, k, nprobe_dev, nprobe_all, eps, ids_dev, dists_dev, flags,
+                      (hipStream_t)stream);
+    });
+}
+
+pano_status pano_pq_stats(const pano_pq_index *idx, int64_t *out4, double *ms_scan)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx && out4, "null argument");
+        for (int i = 0; i < 4; ++i) out4[i] = idx->last_stats[i];
+        if (ms_scan) *ms_scan = idx->last_ms_scan;
+    });
+}
+
+pano_status pano_pq_export(const pano_pq_index *idx, float *codebooks_host, uint8_t *codes_host, int32_t *M_out,
+                           int32_t *dsub_out)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx, "null argument");
+        if (M_out) *M_out = idx->M;
+        if (dsub_out) *dsub_out = idx->dsub;
+        if (!codebooks_host && !codes_host) return;
+        PANO_HIP(hipSetDevice(idx->ctx->device));
+        if (codebooks_host)
+            PANO_HIP(hipMemcpy(codebooks_host, idx->codebooks.p, sizeof(float) * (size_t)idx->M * 256 * idx->dsub,
+                               hipMemcpyDeviceToHost));
+        if (codes_host)
+            PANO_HIP(hipMemcpy(codes_host, idx->codes_row.p, (size_t)idx->n * idx->M, hipMemcpyDeviceToHost));
+    });
+}
+
+void pano_pq_free(pano_pq_index *idx)
+{
+    if (!idx) return;
+    if (idx->ctx) idx->ctx->quiesce();
+    delete idx;
+}
+
 }  // extern "C"

@@ -221,6 +221,29 @@ struct pano_ctx {
     }
 };
 
+// the IVFPQ index: shaped transform, PQ codebooks and the sub-quantizer-major
+// block layout of the codes
+struct pano_pq_index {
+    pano_ctx *ctx = nullptr;
+    int64_t n = 0;
+    int d = 0, nlist = 0, L = 0, M = 0, dsub = 0;
+    std::vector<int> cuts;     // level cuts in coordinates
+    std::vector<int> sub_off;  // level cuts in sub-quantizers
+    std::vector<int64_t> list_blk, list_len, top_blk_prefix;
+    int64_t nblocks = 0;
+    pano::DevMem Tt64, mu64;  // shaped transform in FP64, transposed (Tt[j][i] = T[i][j]), and the mean
+    pano::DevMem codebooks;   // [M][256][dsub] FP32
+    pano::DevMem codes_row;   // [n][M] codes in row order
+    pano::DevMem codes;       // [nblocks][M][256]
+    pano::DevMem tails;       // [nblocks][L - 1][256] norms of xhat beyond levels 1..L-1
+    pano::DevMem ids;         // [nblocks][256], -1 for empty slots
+    pano::DevMem blk_cnt;     // [nblocks]
+    pano::DevMem list_blk_d;  // [nlist + 1]
+    pano::DevMem cent;        // [nlist][d] raw-space centroids, then their squared norms
+    int64_t last_stats[4] = {0, 0, 0, 0};
+    double last_ms_scan = 0.0;
+};
+
 struct pano_transform {
     int d = 0;
     std::vector<double> mu, T, lambda;
@@ -311,6 +334,19 @@ void launch_sqnorms(const float *X, int64_t n, int d, float *out, hipStream_t s)
 void launch_update_mind(const float *X, int64_t n, int d, const float *c, float *mind, hipStream_t s);
 void launch_cand_potential(const float *X, int64_t n, int d, const float *cand, int nc, const float *mind,
                            double *pot, hipStream_t s);
+std::vector<std::pair<int, int>> shape_plan(const std::vector<double> &lam, const std::vector<int> &cuts, double kappa,
+                                            std::vector<double> *v_out);
+void haar_rotation(int n, uint64_t seed, uint64_t stream, std::vector<double> &Q);
+std::vector<double> shape_transform(std::vector<double> &T, int d, const std::vector<double> &lam,
+                                    const std::vector<int> &cuts, double kappa, bool isotropize, uint64_t seed);
+void launch_coarse_probes(const float *S, const float *cn2, const float *q, const float *cent, int d, int nlist,
+                          int64_t nq, const int32_t *nprobe_dev, int nprobe_all, int np_max, int32_t *probes,
+                          int32_t *npq, int32_t *list_cnt, float *qn2, hipStream_t s);
+void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, const float *x_dev,
+                  const float *centroids_dev, const int32_t *assign_dev, int iters, int64_t sample, uint64_t seed,
+                  hipStream_t s);
+void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq, int k, const int32_t *nprobe_dev,
+                   int nprobe_all, float eps, int64_t *ids, float *dists, uint32_t flags, hipStream_t s);
 void launch_gather_rows(const float *X, const int64_t *rows, int64_t n, int d, float *out, hipStream_t s);
 void launch_pack(const float *Y, const float *tails_row, const int64_t *perm, const int64_t *list_start,
                  const int64_t *list_blk, const int32_t *block_list, int64_t nblocks, const LevelGeom &g,

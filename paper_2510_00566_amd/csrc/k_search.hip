@@ -2459,69 +2459,6 @@ __global__ __launch_bounds__(NT) void k_fallback_keys(const float *__restrict__ 
     }
 }
 
-// The k smallest of `total` distinct 64-bit keys (KEY_MAX pads empty slots):
-// radix select of the k-th key over the 64 bits, 8 per pass, with a 256-bin
-// histogram in LDS, then the keys up to it are gathered and sorted.
-__device__ __forceinline__ void fallback_select_block(const uint64_t *__restrict__ keys, int64_t total, int k,
-                                                      int64_t *__restrict__ out_ids, float *__restrict__ out_d)
-{
-    __shared__ int hist[256];
-    __shared__ int sel[2];
-    __shared__ int nsel;
-    __shared__ uint64_t best[128];
-    const int kk = (int)min<int64_t>(k, total);
-    uint64_t prefix = 0, mask = 0;
-    int rank = kk;
-    for (int shift = 56; shift >= 0 && kk > 0; shift -= 8) {
-        for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
-        __syncthreads();
-        for (int64_t i = threadIdx.x; i < total; i += NT) {
-            const uint64_t v = keys[i];
-            if ((v & mask) == prefix) atomicAdd(&hist[(int)((v >> shift) & 255u)], 1);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0, dg = 0;
-            while (dg < 255 && acc + hist[dg] < rank) acc += hist[dg++];
-            sel[0] = dg;
-            sel[1] = rank - acc;
-        }
-        __syncthreads();
-        prefix |= (uint64_t)sel[0] << shift;
-        mask |= (uint64_t)255u << shift;
-        rank = sel[1];
-        __syncthreads();
-    }
-    // prefix is now the kk-th smallest key.  Real keys are distinct, so fewer
-    // than kk keys lie below it; it is added once unless it is the padding
-    if (threadIdx.x == 0) nsel = 0;
-    for (int i = threadIdx.x; i < 128; i += NT) best[i] = KEY_MAX;
-    __syncthreads();
-    if (kk > 0) {
-        for (int64_t i = threadIdx.x; i < total; i += NT) {
-            const uint64_t v = keys[i];
-            if (v < prefix) {
-                const int pos = atomicAdd(&nsel, 1);
-                if (pos < 128) best[pos] = v;
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0 && prefix != KEY_MAX && nsel < 128) best[nsel] = prefix;
-    }
-    __syncthreads();
-    block_bitonic_sort(best, 128);
-    for (int r = threadIdx.x; r < k; r += NT) {
-        const uint64_t b = r < kk ? best[r] : KEY_MAX;
-        if (b == KEY_MAX) {
-            out_ids[r] = -1;
-            out_d[r] = INFINITY;
-        } else {
-            out_ids[r] = key_id(b);
-            out_d[r] = key_dist(b);
-        }
-    }
-}
-
 __global__ __launch_bounds__(NT) void k_fallback_select(const uint64_t *__restrict__ keys, int64_t total, int k,
                                                         int64_t *__restrict__ out_ids, float *__restrict__ out_d)
 {
@@ -2591,6 +2528,35 @@ __global__ __launch_bounds__(NT) void k_fallback_device(int64_t nq, int k, int d
             __syncthreads();
         }
     }
+}
+
+// Coarse probing for the PQ index: S [nq][nlist] = q c^T from launch_gemm_nt
+// (the same tiled product, so the same error bound), probes and counts as in
+// a search; list_cnt (nlist ints) must be zero.  nlist = 1 puts every query
+// on list 0.
+void launch_coarse_probes(const float *S, const float *cn2, const float *q, const float *cent, int d, int nlist,
+                          int64_t nq, const int32_t *nprobe_dev, int nprobe_all, int np_max, int32_t *probes,
+                          int32_t *npq, int32_t *list_cnt, float *qn2, hipStream_t s)
+{
+    if (nq == 0) return;
+    if (nlist == 1) {
+        hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, np_max, probes, npq,
+                           list_cnt);
+        PANO_HIP(hipGetLastError());
+        return;
+    }
+    const double u_ = std::ldexp(1.0, -24);
+    auto gam = [&](double nn) { return nn * u_ / (1.0 - nn * u_); };
+    const float c_co = (float)((gam(d / 64.0 + 8) + gam(2.0 * (32.0 + (d + 31) / 32 + 2)) + 4 * u_) * 1.1);
+    const size_t per_wave = coarse_lds_per_wave(nlist, d);
+    const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
+    const size_t shm = per_wave * wpb;
+    PANO_REQUIRE(shm <= 160 * 1024, "nlist too large for the coarse step");
+    auto kern = nlist <= 1024 ? k_coarse<1024> : (nlist <= 4096 ? k_coarse<4096> : k_coarse<(1 << 30)>);
+    PANO_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    hipLaunchKernelGGL(kern, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), shm, s, S, cn2, q, cent, d, nlist,
+                       nq, nprobe_dev, nprobe_all, c_co, np_max, probes, npq, list_cnt, qn2);
+    PANO_HIP(hipGetLastError());
 }
 
 // Slots of a query's probe set (the exact fallback's key count), for callers

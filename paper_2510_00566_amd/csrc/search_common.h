@@ -567,4 +567,68 @@ __device__ inline int block_exclusive_scan(int v, int *wave_tmp, int *total)
     return base + incl - v;
 }
 
+// The k smallest (k <= 128) of `total` distinct 64-bit keys (KEY_MAX pads
+// empty slots), by one workgroup of NT threads:
+// radix select of the k-th key over the 64 bits, 8 per pass, with a 256-bin
+// histogram in LDS, then the keys up to it are gathered and sorted.
+__device__ __forceinline__ void fallback_select_block(const uint64_t *__restrict__ keys, int64_t total, int k,
+                                                      int64_t *__restrict__ out_ids, float *__restrict__ out_d)
+{
+    __shared__ int hist[256];
+    __shared__ int sel[2];
+    __shared__ int nsel;
+    __shared__ uint64_t best[128];
+    const int kk = (int)min<int64_t>(k, total);
+    uint64_t prefix = 0, mask = 0;
+    int rank = kk;
+    for (int shift = 56; shift >= 0 && kk > 0; shift -= 8) {
+        for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < total; i += NT) {
+            const uint64_t v = keys[i];
+            if ((v & mask) == prefix) atomicAdd(&hist[(int)((v >> shift) & 255u)], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0, dg = 0;
+            while (dg < 255 && acc + hist[dg] < rank) acc += hist[dg++];
+            sel[0] = dg;
+            sel[1] = rank - acc;
+        }
+        __syncthreads();
+        prefix |= (uint64_t)sel[0] << shift;
+        mask |= (uint64_t)255u << shift;
+        rank = sel[1];
+        __syncthreads();
+    }
+    // prefix is now the kk-th smallest key.  Real keys are distinct, so fewer
+    // than kk keys lie below it; it is added once unless it is the padding
+    if (threadIdx.x == 0) nsel = 0;
+    for (int i = threadIdx.x; i < 128; i += NT) best[i] = KEY_MAX;
+    __syncthreads();
+    if (kk > 0) {
+        for (int64_t i = threadIdx.x; i < total; i += NT) {
+            const uint64_t v = keys[i];
+            if (v < prefix) {
+                const int pos = atomicAdd(&nsel, 1);
+                if (pos < 128) best[pos] = v;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && prefix != KEY_MAX && nsel < 128) best[nsel] = prefix;
+    }
+    __syncthreads();
+    block_bitonic_sort(best, 128);
+    for (int r = threadIdx.x; r < k; r += NT) {
+        const uint64_t b = r < kk ? best[r] : KEY_MAX;
+        if (b == KEY_MAX) {
+            out_ids[r] = -1;
+            out_d[r] = INFINITY;
+        } else {
+            out_ids[r] = key_id(b);
+            out_d[r] = key_dist(b);
+        }
+    }
+}
+
 }  // namespace pano

@@ -94,6 +94,14 @@ class Transform:
         L.check(L.lib().pano_transform_from(mu.shape[0], _np_ptr(mu), _np_ptr(t), C.byref(h)))
         return cls(h, mu.shape[0])
 
+    def shape(self, m, kappa: float, isotropize: bool = True, seed: int = 0) -> "Transform":
+        """The shaped transform U R T of Section 4.2 for level cuts m."""
+        m = np.ascontiguousarray(m, dtype=np.int32)
+        h = C.c_void_p()
+        L.check(L.lib().pano_transform_shape(self.h, _np_ptr(m), m.size - 1, float(kappa), 1 if isotropize else 0,
+                                             int(seed), C.byref(h)))
+        return Transform(h, self.d)
+
     def get(self):
         d = self.d
         mu = np.empty(d)
@@ -110,6 +118,84 @@ class Transform:
             if self.h:
                 L.lib().pano_transform_free(self.h)
                 self.h = None
+        except Exception:
+            pass
+
+
+def shape_plan(lam, m, kappa: float):
+    """Procedure 1's plan: list of (start, length) coordinate blocks."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    m = np.ascontiguousarray(m, dtype=np.int32)
+    cap = int(m.size) + 1
+    out = np.zeros(2 * cap, dtype=np.int32)
+    nb = C.c_int32()
+    L.check(L.lib().pano_shape_plan(_np_ptr(lam), lam.size, _np_ptr(m), m.size - 1, float(kappa), _np_ptr(out), cap,
+                                    C.byref(nb)))
+    return [(int(out[2 * i]), int(out[2 * i + 1])) for i in range(nb.value)]
+
+
+class PQIndex:
+    """IVFPQ index over the shaped frame (Section 6.2): codes, codebooks and
+    the sub-quantizer-major block layout live in device memory."""
+
+    def __init__(self, h, ctx, n, d, m, dsub):
+        self.h = h
+        self.ctx = ctx
+        self.n = n
+        self.d = d
+        self.m = np.asarray(m, dtype=np.int32)
+        self.dsub = dsub
+        self.M = d // dsub
+
+    @classmethod
+    def build(cls, ctx: Context, tf: Transform, x_dev, centroids_dev, assign_dev, m, dsub: int, iters: int = 10,
+              sample: int = 65536, seed: int = 0, stream=None) -> "PQIndex":
+        m = np.ascontiguousarray(m, dtype=np.int32)
+        n, d = x_dev.shape
+        h = C.c_void_p()
+        L.check(L.lib().pano_pq_build(ctx.h, tf.h, _ptr(x_dev), n, d, _ptr(centroids_dev), _ptr(assign_dev),
+                                      centroids_dev.shape[0], _np_ptr(m), m.size - 1, int(dsub), int(iters),
+                                      int(sample), int(seed), C.byref(h), _stream_handle(stream)))
+        return cls(h, ctx, n, d, m, dsub)
+
+    def search(self, q_dev, k: int, nprobe=1, eps: float = 1.0, brute: bool = False, stats: bool = False,
+               stream=None, nprobe_max: int = 0, out=None):
+        import torch
+        nq = q_dev.shape[0]
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=q_dev.device)
+            dists = torch.empty((nq, k), dtype=torch.float32, device=q_dev.device)
+        else:
+            ids, dists = out
+        np_dev, np_all = _probe_args(nprobe, nprobe_max)
+        flags = (L.PANO_PQ_BRUTE if brute else 0) | (L.PANO_SEARCH_STATS if stats else 0)
+        L.check(L.lib().pano_pq_search(self.ctx.h, self.h, _ptr(q_dev), nq, k, _ptr(np_dev), np_all, float(eps),
+                                       _ptr(ids), _ptr(dists), flags, _stream_handle(stream)))
+        return ids, dists
+
+    def stats(self) -> dict:
+        out = np.zeros(4, dtype=np.int64)
+        ms = C.c_double()
+        L.check(L.lib().pano_pq_stats(self.h, _np_ptr(out), C.byref(ms)))
+        return {"lookups": int(out[0]), "lookups_full": int(out[1]), "fallback_queries": int(out[2]),
+                "candidates": int(out[3]), "ms_scan": ms.value,
+                "phi": float(out[0]) / max(1, int(out[1]))}
+
+    def export(self):
+        """(codebooks [M, 256, dsub] float32, codes [n, M] uint8)."""
+        cb = np.empty((self.M, 256, self.dsub), dtype=np.float32)
+        codes = np.empty((self.n, self.M), dtype=np.uint8)
+        L.check(L.lib().pano_pq_export(self.h, _np_ptr(cb), _np_ptr(codes), None, None))
+        return cb, codes
+
+    def free(self):
+        if self.h:
+            L.lib().pano_pq_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
         except Exception:
             pass
 
