@@ -394,6 +394,100 @@ def measure(run: Run, args, primary: bool) -> dict:
     return res
 
 
+PEAK_LDS_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clock x 2.4 GHz (LDS bandwidth)
+
+
+def pq_measure(name: str, args, ctx) -> dict:
+    """The IVFPQ form (Section 4.2 shaping, Section 6.2 scan) on one workload:
+    QPS of the pruned scan and of the brute-force scan of the same codes (same
+    kernel, no bounds), phi, parity of a query sample with the oracle (same
+    trained quantizer), recall@k against the exact k-NN over the same probed
+    lists, and the scan kernel's bytes and table look-ups per second."""
+    import torch
+    from oracle import brute, pq
+    from paper_2510_00566_amd import synth
+    from paper_2510_00566_amd.index import PQIndex, Transform, ivf_assign
+    w = synth.WORKLOADS[name]
+    if args.scale != 1.0:
+        w = synth.scaled(w, n=int(w.n * args.scale), nq=w.nq)
+    t0 = time.time()
+    data = synth.generate(w)
+    x, q = data["x"], data["q"]
+    xd, qd = torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda()
+    cent, assign = ivf_assign(ctx, xd, w.nlist, iters=10 if w.nlist > 1 else 0, seed=w.cfg_id)
+    cuts = w.level_cuts()
+    # the codes are residuals against the list centroids: the PCA that
+    # front-loads their energy is fitted on the residuals x - c(x)
+    c_np, a_np = cent.cpu().numpy(), assign.cpu().numpy()
+    rows = np.random.Generator(np.random.PCG64(w.cfg_id)).choice(w.n, min(w.n, 131072), replace=False)
+    pca = Transform.fit(x[rows] - c_np[a_np[rows]], fit_sample=0, seed=w.cfg_id)
+    t1 = time.time()
+    tf = pca.shape(cuts, w.pq_kappa, isotropize=True, seed=w.cfg_id)
+    idx = PQIndex.build(ctx, tf, xd, cent, assign, cuts, w.pq_dsub, iters=10, sample=65536, seed=w.cfg_id)
+    torch.cuda.synchronize()
+    build_s = time.time() - t1
+    log(f"[bench] {name}: data+kmeans+PCA {t1 - t0:.1f}s, shaping+PQ build {build_s:.1f}s")
+    ids = torch.empty((w.nq, w.k), dtype=torch.int64, device="cuda")
+    dd = torch.empty((w.nq, w.k), dtype=torch.float32, device="cuda")
+    bi, bd = torch.empty_like(ids), torch.empty_like(dd)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    el = timed(lambda: idx.search(qd, w.k, nprobe=w.nprobe, out=(ids, dd)), args.steps, args.warmup)
+    qps = w.nq * args.steps / el
+    bsteps = max(3, args.steps // 2)
+    elb = timed(lambda: idx.search(qd, w.k, nprobe=w.nprobe, brute=True, out=(bi, bd)), bsteps, 1)
+    bqps = w.nq * bsteps / elb
+    same = bool(torch.equal(ids, bi) and torch.equal(dd, bd))
+    idx.search(qd, w.k, nprobe=w.nprobe, stats=True, out=(ids, dd))
+    st = idx.stats()
+    idx.search(qd, w.k, nprobe=w.nprobe, brute=True, stats=True, out=(bi, bd))
+    sb = idx.stats()
+    log(f"[bench] {name}: pruned {qps:.0f} QPS, brute {bqps:.0f} QPS, phi {st['phi']:.4f}, same {same}")
+    rec = {"workload": name, "kind": "ivfpq",
+           "config": {"workload": name, "n": w.n, "d": w.d, "nq": w.nq, "k": w.k, "nlist": w.nlist,
+                      "nprobe": w.nprobe, "levels": w.L, "level_width": w.level_width, "dsub": w.pq_dsub,
+                      "M": w.d // w.pq_dsub, "bits": 8, "kappa": w.pq_kappa, "eps": 1.0,
+                      "codes": "residuals against the list centroids, shaped frame U R T_PCA",
+                      "transform": "pca_fit_on_list_residuals, shaped (Procedures 1-2)"},
+           "qps": qps, "ms_per_step": el * 1000 / args.steps,
+           "bruteforce": {"qps": bqps, "ms_per_step": elb * 1000 / bsteps, "same_result": same,
+                          "scan_ms": sb["ms_scan"], "scan_bytes": sb["scan_bytes"]},
+           "speedup_vs_bruteforce": qps / bqps, "phi": st["phi"], "build_s": build_s,
+           "fallback_queries": st["fallback_queries"]}
+    for tag, s_ in (("roofline", st), ("bruteforce_roofline", sb)):
+        gbs = s_["scan_bytes"] / 1e9 / (s_["ms_scan"] / 1e3)
+        lds = s_["lookups"] * 4 / 1e9 / (s_["ms_scan"] / 1e3)
+        rec[tag] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                    "kernel": "k_pq_scan", "bytes_per_launch": float(s_["scan_bytes"]), "ms_per_launch": s_["ms_scan"],
+                    "lds_lookup_GBs": lds, "lds_peak_GBs": PEAK_LDS_GBS, "lds_frac": lds / PEAK_LDS_GBS,
+                    "lookups_per_launch": s_["lookups"], "traffic": None}
+    if args.parity_sample > 0:
+        rs = np.random.Generator(np.random.PCG64(4242))
+        sample = np.sort(rs.choice(w.nq, size=min(args.parity_sample, w.nq), replace=False))
+        mu, t, _, _ = tf.get()
+        cb, codes = idx.export()
+        ri, rd = pq.pq_knn_ivf(q[sample], mu, t, cb, codes, c_np, a_np, w.nprobe, w.k)
+        gi, gd = ids.cpu().numpy()[sample], dd.cpu().numpy()[sample]
+        rec["parity"] = {"queries": int(sample.size), "id_mismatch_queries": int((gi != ri).any(axis=1).sum()),
+                         "dist_mismatch_queries": int((gd != rd).any(axis=1).sum())}
+        ei, _, _ = brute.knn_ivf(q[sample], x, c_np, a_np, w.nprobe, w.k)
+        rec["recall_at_k_vs_exact"] = recall_at_k(gi, ei)
+        log(f"[bench] {name}: parity {rec['parity']} recall@{w.k} {rec['recall_at_k_vs_exact']:.4f}")
+    idx.free()
+    del xd, qd
+    torch.cuda.empty_cache()
+    return rec
+
+
 def energy_alpha(y: np.ndarray) -> float:
     """Decay rate alpha of the mean tail-energy profile E(m) of rows y in a
     given basis (E(m) ~ exp(-alpha m / d), Section 4.1), fitted by least
@@ -529,6 +623,9 @@ def main():
     ap.add_argument("--workload", default="ivf_zipf_batched")
     ap.add_argument("--secondary-workloads", default="ivf_gist_like,flat_sift_like",
                     help="comma-separated workloads measured after the primary one ('' for none)")
+    ap.add_argument("--pq-workloads", default="ivfpq_gist_like",
+                    help="comma-separated IVFPQ workloads measured last ('' for none)")
+    ap.add_argument("--pq-only", action="store_true", help="measure only the IVFPQ workloads")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of N (smoke runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bruteforce", action="store_true")
@@ -570,6 +667,9 @@ def main():
     from paper_2510_00566_amd.index import Context
 
     ctx = Context(0)
+    if args.pq_only:
+        print(json.dumps({"pq": [pq_measure(n_, args, ctx) for n_ in args.pq_workloads.split(",") if n_]}))
+        return
     if args.eps_sweep or args.ood:
         run = Run(args.workload, args, ctx)
         print(json.dumps(eps_sweep(run, args) if args.eps_sweep else ood_sweep(run, args)))
@@ -606,6 +706,8 @@ def main():
         "data": "synthetic",
     }
     out.update({k_: v_ for k_, v_ in prim.items() if k_ not in ("qps", "ms_per_step")})
+    for name in [s for s in args.pq_workloads.split(",") if s]:
+        secondaries.append(pq_measure(name, args, ctx))
     out["secondary_workloads"] = secondaries
     print(json.dumps(out))
 

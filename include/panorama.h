@@ -416,15 +416,16 @@ pano_status pano_transform_shape(const pano_transform *pca, const int32_t *m_hos
 
 /*
  * pq_build: the IVFPQ index of Section 6.2 over the shaped frame of tf.
- * Rows x_dev [n][d] (device, FP32) are mapped to y = T (x - mu) and split into
+ * Each row x of x_dev [n][d] (device, FP32), assigned to list l, is coded by
+ * its residual T (x - mu) - y_c(l) in the shaped frame, y_c(l) = T (c_l - mu)
+ * (FP64, each coordinate summed in order; kept for the search), split into
  * M = d / dsub sub-vectors of dsub coordinates (dsub in {1, 2, 4, 8, 16};
  * M <= 128, since the scan keeps a query's table of M x 256 floats in LDS);
  * each sub-quantizer has 256 codewords, trained by Lloyd iterations (`iters`,
  * FP64 means, an empty cell keeps its codeword) on a seeded sample of
  * max(256, min(n, sample)) rows from 256 sample rows spread over the sample,
  * and every row is coded by its nearest codewords (FP32 distance, ties to the
- * smaller code).  Codes describe y itself, not its offset from the list
- * centroid.  The levels m_host [L+1] (1 <= L <= 64) must fall on sub-vector
+ * smaller code).  The levels m_host [L+1] (1 <= L <= 64) must fall on sub-vector
  * boundaries.  Lists follow assign_dev [n] in [0, nlist) with
  * centroids_dev [nlist][d] (raw space, for probing).  Layout in device
  * memory, per list, blocks of 256 slots: the codes of a block sub-quantizer
@@ -447,13 +448,14 @@ pano_status pano_pq_build(pano_ctx *ctx, const pano_transform *tf, const float *
  * probed lists (Section 6.2 with Algorithm 1's level loop).  The probe set is
  * that of pano_search (canonical (D, l) order in raw space).  The query's
  * shaped coordinates y_i = sum_j T_ij (q_j - mu_j) are summed in coordinate
- * order in FP64; its table entry (m, c) is float32 of the FP64 sum of
- * (y_j - C[m][c][j])^2 over the sub-vector in order; a candidate's distance
- * is float32 of the FP64 sum of its M entries in sub-quantizer order.  A
- * candidate is dropped after a level once the bound P + (a - b)^2 +
- * 2 (1 - eps) a b (Eq. 3/4: P the entries read so far, a and b the norms of
- * the query and of the reconstruction beyond the level, with certified
- * rounding margins) exceeds the running k-th distance; at eps = 1 the answer
+ * order in FP64, and its residual for list l is z = y - y_c(l); the list's
+ * table entry (m, c) is float32 of the FP64 sum of (z_j - C[m][c][j])^2 over
+ * the sub-vector in order; a candidate's distance is float32 of the FP64 sum
+ * of its M entries in sub-quantizer order.  A candidate is dropped after a
+ * level once the bound P + (a - b)^2 + 2 (1 - eps) a b (Eq. 3/4: P the
+ * entries read so far, a and b the norms of the residual z and of the
+ * reconstruction beyond the level, with certified rounding margins) exceeds
+ * the running k-th distance; at eps = 1 the answer
  * is the first k by (distance, id), exactly, padded with (-1, +inf).
  * q_dev [nq][d]; nprobe as in pano_search (at most 1024 lists per query);
  * 1 <= k <= 128; ids_dev [nq][k] int64, dists_dev [nq][k] float.  flags:
@@ -467,9 +469,11 @@ pano_status pano_pq_search(pano_ctx *ctx, pano_pq_index *idx, const float *q_dev
 
 /* Counters of the last pq_search with PANO_SEARCH_STATS: out[0] table
  * look-ups done, out[1] look-ups of the unpruned scan (candidates x M),
- * out[2] queries answered by the exact fallback, out[3] candidates;
- * *ms_scan the scan kernel's duration. */
-pano_status pano_pq_stats(const pano_pq_index *idx, int64_t *out4, double *ms_scan);
+ * out[2] queries answered by the exact fallback, out[3] candidates, out[4]
+ * bytes of codes and tail norms the scan read (a block's level is read
+ * whole once any of its slots is alive); *ms_scan the scan kernel's
+ * duration. */
+pano_status pano_pq_stats(const pano_pq_index *idx, int64_t *out5, double *ms_scan);
 
 /* Copy out the trained quantizer: codebooks_host [M][256][dsub] FP32 and
  * codes_host [n][M] (row order); either may be NULL.  *M_out and *dsub_out

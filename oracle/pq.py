@@ -17,11 +17,12 @@ What it follows:
     variance.  The plan is the ordered list of rotated blocks.
   * Section 4.2, Procedure 2 (intra-level isotropization): one Haar rotation
     per level's coordinates.  The combined transform is U R T_PCA.
-  * Section 6.2 (IVFPQ): each vector of the shaped frame is split into M
-    sub-vectors of dsub coordinates, each coded by one of 256 codewords; the
-    query's look-up table holds the squared distance of each query
-    sub-vector to each codeword, and a candidate's distance is the sum of its
-    M table entries (asymmetric distance computation).
+  * Section 6.2 (IVFPQ): each vector's residual against its list centroid,
+    in the shaped frame, is split into M sub-vectors of dsub coordinates, each
+    coded by one of 256 codewords; per probed list the query's look-up table
+    holds the squared distance of each sub-vector of the query's residual
+    against that list's centroid to each codeword, and a candidate's distance
+    is the sum of its M table entries (asymmetric distance computation).
   * The bound of Eq. 3/4 applied to the reconstruction xhat: after the
     levels 1..l the partial sum P_l of the table entries is the head term,
     and LB = P_l + (a - b)^2 + 2 (1 - eps) a b with a, b the norms of the query
@@ -38,8 +39,11 @@ Readings (where the paper is silent):
     sequential FP64 sum of the candidate's M entries in sub-quantizer order.
   * The answer is the first k candidates by (ADC, id) over the probed lists
     (probe sets as in oracle.brute); the PQ codes are not re-ranked.
-  * Non-residual codes: a vector's code describes T (x - mu) itself, not its
-    offset from the list centroid.
+  * Residual codes, as IVFPQ stores them: a vector of list l is coded as
+    T (x - mu) - y_c(l), with y_c(l) = T (c_l - mu) by the same sequential
+    FP64 recipe as the queries; the query's residual for list l is
+    z = y - y_c(l) (FP64 differences), and its tail norms beyond each level are
+    those of z.
 """
 from __future__ import annotations
 
@@ -182,19 +186,24 @@ def _topk(dist, ids, k):
 
 def pq_knn_ivf(qs, mu, t, codebooks, codes, centroids, assign, nprobe, k):
     """O-PQ1: first k by (ADC, id) over each query's probed lists (brute force
-    over the codes).  Returns ids [nq, k] int64, dists [nq, k] float32."""
+    over the codes, each list with its own table).  Returns ids [nq, k] int64,
+    dists [nq, k] float32."""
     qs = np.atleast_2d(qs)
     probes = probe_lists(qs, centroids, nprobe)
     mem = _members(assign, centroids.shape[0])
     y = shaped_query(qs, mu, t)
+    yc = shaped_query(centroids, mu, t)
     out_i = np.full((qs.shape[0], k), -1, dtype=np.int64)
     out_d = np.full((qs.shape[0], k), np.inf, dtype=np.float32)
     for qi in range(qs.shape[0]):
-        cand = np.concatenate([mem[int(l)] for l in probes[qi]]).astype(np.int64)
-        if cand.size == 0:
-            continue
-        tab = lut(y[qi], codebooks)
-        out_i[qi], out_d[qi] = _topk(adc(tab, codes[cand]), cand, k)
+        ids, dist = [], []
+        for l in probes[qi]:
+            mm = mem[int(l)]
+            if mm.size:
+                ids.append(mm.astype(np.int64))
+                dist.append(adc(lut(y[qi] - yc[int(l)], codebooks), codes[mm]))
+        if ids:
+            out_i[qi], out_d[qi] = _topk(np.concatenate(dist), np.concatenate(ids), k)
     return out_i, out_d
 
 
@@ -203,21 +212,31 @@ def pq_lower_bound(p, a, b, eps):
     return p + (a - b) ** 2 + 2.0 * (1.0 - eps) * a * b
 
 
-def panorama_pq_knn(y, tab, codes, xt, ids, sub_cuts, k, batch=1024, eps=1.0):
-    """Algorithm 1 over one query's candidates in the given order.  y [d] the
-    shaped query, tab [M, 256] its table, codes [n, M], xt [n, L+1] the norms of
-    xhat beyond each level, sub_cuts the level cuts in sub-quantizer units.
-    Returns (ids [k], dists [k], subs_read [n])."""
+def panorama_pq_knn(zs, tabs, which, codes, xt, ids, sub_cuts, k, batch=1024, eps=1.0):
+    """Algorithm 1 over one query's candidates in the given order.  zs [p, d]
+    the query's residuals against its p probed lists, tabs [p, M, 256] their
+    tables, which [n] the list (index into zs) of each candidate, codes [n, M],
+    xt [n, L+1] the norms of xhat beyond each level, sub_cuts the level cuts in
+    sub-quantizer units.  Returns (ids [k], dists [k], subs_read [n])."""
     sub_cuts = [int(c) for c in sub_cuts]
     L = len(sub_cuts) - 1
     M = sub_cuts[-1]
-    dsub = y.shape[0] // M
+    dsub = zs.shape[1] // M
     n = codes.shape[0]
     ids = np.asarray(ids, dtype=np.int64)
-    yt = tails(y[None, :], [c * dsub for c in sub_cuts])[0]
+    which = np.asarray(which, dtype=np.int64)
+    zt = tails(zs, [c * dsub for c in sub_cuts])  # [p, L+1]
     read = np.zeros(n, dtype=np.int64)
+
+    def full(rows):
+        out = np.zeros(rows.size, dtype=np.float32)
+        for w in np.unique(which[rows]):
+            sel = which[rows] == w
+            out[sel] = adc(tabs[w], codes[rows[sel]])
+        return out
+
     s = min(k, n)
-    h_d = adc(tab, codes[:s])
+    h_d = full(np.arange(s))
     h_i = ids[:s].copy()
     read[:s] = M
     h_i, h_d = _crop(h_d, h_i, k)
@@ -228,18 +247,20 @@ def panorama_pq_knn(y, tab, codes, xt, ids, sub_cuts, k, batch=1024, eps=1.0):
         p = np.zeros(b1 - b0)
         for l in range(1, L + 1):
             act = np.nonzero(active)[0]
+            wl = which[b0 + act]
             for mm in range(sub_cuts[l - 1], sub_cuts[l]):
-                p[act] += tab[mm, codes[b0 + act, mm]].astype(np.float64)
+                p[act] += tabs[wl, mm, codes[b0 + act, mm]].astype(np.float64)
             read[b0 + act] = sub_cuts[l]
             if l == L:
                 break
-            lb = pq_lower_bound(p[act], yt[l], xt[b0 + act, l], eps)
+            a = zt[wl, l]
+            lb = pq_lower_bound(p[act], a, xt[b0 + act, l], eps)
             # slack for the FP32 rounding of the table entries and of ADC
-            pruned = lb > dk + 2.0 ** -20 * (dk + p[act] + (yt[l] + xt[b0 + act, l]) ** 2)
+            pruned = lb > dk + 2.0 ** -20 * (dk + p[act] + (a + xt[b0 + act, l]) ** 2)
             active[act[pruned]] = False
         surv = np.nonzero(active)[0]
         if surv.size:
-            dd = adc(tab, codes[b0 + surv])
+            dd = full(b0 + surv)
             h_d = np.concatenate([h_d, dd])
             h_i = np.concatenate([h_i, ids[b0 + surv]])
             h_i, h_d = _crop(h_d, h_i, k)
@@ -264,6 +285,7 @@ def panorama_pq_knn_ivf(qs, mu, t, codebooks, codes, centroids, assign, nprobe, 
     probes = probe_lists(qs, centroids, nprobe)
     mem = _members(assign, centroids.shape[0])
     y = shaped_query(qs, mu, t)
+    yc = shaped_query(centroids, mu, t)
     cb = np.asarray(codebooks)
     M, _, dsub = cb.shape
     xt = tails(reconstruct(codes, cb), [c * dsub for c in sub_cuts])
@@ -271,11 +293,14 @@ def panorama_pq_knn_ivf(qs, mu, t, codebooks, codes, centroids, assign, nprobe, 
     out_d = np.full((qs.shape[0], k), np.inf, dtype=np.float32)
     frac = np.zeros(qs.shape[0])
     for qi in range(qs.shape[0]):
-        cand = np.concatenate([mem[int(l)] for l in probes[qi]]).astype(np.int64)
+        parts = [mem[int(l)] for l in probes[qi]]
+        cand = np.concatenate(parts).astype(np.int64)
         if cand.size == 0:
             continue
-        tab = lut(y[qi], cb)
-        out_i[qi], out_d[qi], rd = panorama_pq_knn(y[qi], tab, codes[cand], xt[cand], cand, sub_cuts, k,
+        which = np.concatenate([np.full(pp.size, i, np.int64) for i, pp in enumerate(parts)])
+        zs = np.stack([y[qi] - yc[int(l)] for l in probes[qi]])
+        tabs = np.stack([lut(z, cb) for z in zs])
+        out_i[qi], out_d[qi], rd = panorama_pq_knn(zs, tabs, which, codes[cand], xt[cand], cand, sub_cuts, k,
                                                    batch, eps)
         frac[qi] = rd.sum() / (cand.size * M)
     return out_i, out_d, frac

@@ -769,11 +769,11 @@ pano_status pano_pq_search(pano_ctx *ctx, pano_pq_index *idx, const float *q_dev
     });
 }
 
-pano_status pano_pq_stats(const pano_pq_index *idx, int64_t *out4, double *ms_scan)
+pano_status pano_pq_stats(const pano_pq_index *idx, int64_t *out5, double *ms_scan)
 {
     return guarded([&] {
-        PANO_REQUIRE(idx && out4, "null argument");
-        for (int i = 0; i < 4; ++i) out4[i] = idx->last_stats[i];
+        PANO_REQUIRE(idx && out5, "null argument");
+        for (int i = 0; i < 5; ++i) out5[i] = idx->last_stats[i];
         if (ms_scan) *ms_scan = idx->last_ms_scan;
     });
 }

@@ -233,14 +233,16 @@ struct pano_pq_index {
     int64_t nblocks = 0;
     pano::DevMem Tt64, mu64;  // shaped transform in FP64, transposed (Tt[j][i] = T[i][j]), and the mean
     pano::DevMem codebooks;   // [M][256][dsub] FP32
-    pano::DevMem codes_row;   // [n][M] codes in row order
+    pano::DevMem codes_row;   // [n][M] codes of the residuals T (x - c) in row order
     pano::DevMem codes;       // [nblocks][M][256]
     pano::DevMem tails;       // [nblocks][L - 1][256] norms of xhat beyond levels 1..L-1
     pano::DevMem ids;         // [nblocks][256], -1 for empty slots
     pano::DevMem blk_cnt;     // [nblocks]
     pano::DevMem list_blk_d;  // [nlist + 1]
     pano::DevMem cent;        // [nlist][d] raw-space centroids, then their squared norms
-    int64_t last_stats[4] = {0, 0, 0, 0};
+    pano::DevMem yc64;        // [nlist][d] the centroids in the shaped frame, FP64
+    pano::DevMem block_list;  // [nblocks] the list of each block
+    int64_t last_stats[5] = {0, 0, 0, 0, 0};
     double last_ms_scan = 0.0;
 };
 

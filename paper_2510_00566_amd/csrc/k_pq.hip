@@ -132,6 +132,18 @@ static void launch_assign_sub(const float *Y, int64_t n, int ldy, int M, int dsu
     PANO_HIP(hipGetLastError());
 }
 
+// Y[r] -= yc[assign[r]] for r < n (the residual of each row in the shaped
+// frame, FP32).
+__global__ __launch_bounds__(256) void k_pq_residual(float *__restrict__ Y, int64_t n, int d,
+                                                     const int32_t *__restrict__ assign, const float *__restrict__ yc)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n * d) return;
+    const int64_t r = t / d;
+    const int j = (int)(t - r * d);
+    Y[t] -= yc[(int64_t)assign[r] * d + j];
+}
+
 // One thread per slot: the sub-quantizer-major codes of its block, the norms
 // of its reconstruction beyond levels 1..L-1 (FP64 sums of the codeword
 // energies cwe [M][256]), its id.
@@ -176,28 +188,94 @@ __global__ __launch_bounds__(256) void k_pq_pack(PqGeom g, const uint8_t *__rest
 struct PqScan {
     PqGeom g;
     int64_t nq;
-    int k, np_max, cap, waves;
+    int k, np_max, cap, waves, nlr;  // nlr: lists whose tables share LDS in one round
     float eps;
     float g_part;  // relative error of an FP32 partial sum of table entries
     float g_adc;   // |canonical - FP32 sum| <= g_adc * FP32 sum
-    const double *y;
+    const double *y;   // [nq][d] the queries in the shaped frame
+    const double *yc;  // [nlist][d] the list centroids in the shaped frame
     const float *codebooks;
     const int32_t *probes, *npq;
     const int64_t *list_blk;
     const int32_t *blk_cnt;
+    const int32_t *block_list;
     const uint8_t *codes;
     const float *tails;
     const int32_t *ids;
     int32_t *qflags;
     int64_t *out_ids;
     float *out_d;
-    unsigned long long *stats;  // [0] look-ups, [1] candidates, [2] overflowed queries
+    unsigned long long *stats;  // [0] look-ups, [1] candidates, [2] overflowed queries, [3] bytes of codes and tails read
 };
 
+// Table entry (m, c) from a residual z staged in LDS (FP64) and the codeword
+// cw: float32 of the sequential FP64 sum over the sub-vector of
+// (z_j - cw_j)^2 (DS = dsub, unrolled so the codeword's loads issue together).
+template <int DS>
+__device__ __forceinline__ float pq_entry_z(const double *__restrict__ z, const float *__restrict__ cw)
+{
+#pragma clang fp contract(off)
+    float c[DS];
+#pragma unroll
+    for (int j = 0; j < DS; ++j) c[j] = cw[j];
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < DS; ++j) {
+        const double t = z[j] - (double)c[j];
+        const double t2 = t * t;
+        s = s + t2;
+    }
+    return (float)s;
+}
+
+template <int DS>
+__device__ void pq_build_tables(float *__restrict__ luts, const double *__restrict__ zs, int nl, int M, int d,
+                                const float *__restrict__ codebooks)
+{
+    for (int e = threadIdx.x; e < nl * M * 256; e += blockDim.x) {
+        const int li = e / (M * 256), ee = e - li * M * 256;
+        luts[e] = pq_entry_z<DS>(zs + (size_t)li * d + (ee >> 8) * DS, codebooks + (size_t)ee * DS);
+    }
+}
+
+// Table entry (m, c) of the residual query z = y - y_c(list): float32 of the
+// sequential FP64 sum over the sub-vector of (z_j - C[m][c][j])^2.
+__device__ __forceinline__ float pq_entry(const double *__restrict__ yq, const double *__restrict__ yl,
+                                          const float *__restrict__ cw, int m, int dsub)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int j = 0; j < dsub; ++j) {
+        const double z = yq[m * dsub + j] - yl[m * dsub + j];
+        const double t = z - (double)cw[j];
+        const double t2 = t * t;
+        s = s + t2;
+    }
+    return (float)s;
+}
+
+// The canonical distance of the candidate in `slot` (its list's table
+// entries recomputed, summed in FP64 in sub-quantizer order, then rounded).
+__device__ __forceinline__ float pq_canonical(const PqScan &a, const double *yq, int64_t slot)
+{
+#pragma clang fp contract(off)
+    const int M = a.g.M, dsub = a.g.dsub, d = a.g.d;
+    const int64_t b = slot / PQ_B;
+    const double *yl = a.yc + (int64_t)a.block_list[b] * d;
+    const uint8_t *cs = a.codes + (size_t)b * M * PQ_B + (slot % PQ_B);
+    double s = 0.0;
+    for (int m = 0; m < M; ++m) {
+        const int c = cs[(size_t)m * PQ_B];
+        s = s + (double)pq_entry(yq, yl, a.codebooks + ((size_t)m * 256 + c) * dsub, m, dsub);
+    }
+    return (float)s;
+}
+
 // A certified lower bound on the canonical distance from the FP32 partial sum
-// p of the levels read and the tail norms a (query) and b (reconstruction):
-// P + (a - b)^2 of Eq. 3 (plus 2 (1 - eps) a b, Eq. 4), with room for the
-// rounding of p, a, b, the table entries and the final float32 rounding.
+// p of the levels read and the tail norms a (query residual) and b
+// (reconstruction): P + (a - b)^2 of Eq. 3 (plus 2 (1 - eps) a b, Eq. 4),
+// with room for the rounding of p, a, b, the table entries and the final
+// float32 rounding.
 __device__ __forceinline__ float pq_lower_bound(float p, float a, float b, float eps, float g_part)
 {
     const float dab = fabsf(a - b) - 0x1p-22f * (a + b);
@@ -208,7 +286,7 @@ __device__ __forceinline__ float pq_lower_bound(float p, float a, float b, float
 // Sort the wavefront's buffer and keep the k smallest plus every entry that
 // may still reach the answer (sum * (1 - g) <= T, T = k-th * (1 + g), an upper
 // bound on the canonical k-th distance of the query); T goes to the shared
-// threshold.
+// threshold.  Returns the new count.
 __device__ __noinline__ int pq_wave_trim(uint64_t *wb, int wc, int cap, int k, float g, unsigned *thr, int lane)
 {
     for (int i = wc + lane; i < cap; i += 64) wb[i] = KEY_MAX;
@@ -230,17 +308,27 @@ __device__ __noinline__ int pq_wave_trim(uint64_t *wb, int wc, int cap, int k, f
     return keep;
 }
 
+// One workgroup per query.  The probed lists are taken in probe order, nlr at
+// a time: their tables (one per list: the query's residual against the list
+// centroid) are built in LDS, then the wavefronts take quarter blocks (64
+// slots, one per lane) of those lists from a shared counter and run the
+// level loop: a level's table entries are summed in FP32, the bound is
+// checked against the shared threshold, and a wavefront stops once no slot
+// is alive.  Survivors that may reach the answer go to the wavefront's LDS
+// buffer.  At the end every buffered entry that may reach the answer is
+// rescored canonically and the k smallest (distance, id) keys are written.
 template <bool PRUNE>
 __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
 {
     extern __shared__ __align__(16) char sm[];
-    const int M = a.g.M, L = a.g.L, d = a.g.d, dsub = a.g.dsub;
-    float *lut = reinterpret_cast<float *>(sm);                              // [M][256]
-    uint64_t *wbuf = reinterpret_cast<uint64_t *>(lut + (size_t)M * 256);    // [waves][cap]
-    int32_t *pref = reinterpret_cast<int32_t *>(wbuf + (size_t)a.waves * a.cap);  // [np_max + 1]
-    int32_t *plist = pref + a.np_max + 1;                                    // [np_max]
-    float *qa = reinterpret_cast<float *>(plist + a.np_max);                 // [L]
-    __shared__ double e2[PQ_MAXL];
+    const int M = a.g.M, L = a.g.L, d = a.g.d, dsub = a.g.dsub, nlr = a.nlr;
+    float *luts = reinterpret_cast<float *>(sm);                                  // [nlr][M][256]
+    uint64_t *wbuf = reinterpret_cast<uint64_t *>(luts + (size_t)nlr * M * 256);  // [waves][cap]
+    float *qa = reinterpret_cast<float *>(wbuf + (size_t)a.waves * a.cap);        // [nlr][L]
+    double *e2 = reinterpret_cast<double *>(qa + (size_t)nlr * L + ((nlr * L) & 1));  // [nlr][L]
+    double *zs = e2 + (size_t)nlr * L;                                          // [nlr][d]
+    int32_t *rpref = reinterpret_cast<int32_t *>(zs + (size_t)nlr * d);         // [nlr + 1]
+    int32_t *rlist = rpref + nlr + 1;                                            // [nlr]
     __shared__ unsigned thr;
     __shared__ int task, ovf;
     __shared__ int wcount[16];
@@ -257,130 +345,110 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
         return;
     }
     const int np = a.npq[qi];
-    for (int i = tid; i < np; i += blockDim.x) plist[i] = a.probes[qi * a.np_max + i];
+    const double *yq = a.y + qi * d;
     if (tid == 0) {
         thr = 0x7f800000u;  // +inf
-        task = 0;
         ovf = 0;
     }
-    // the query's table: entry (m, c) by one thread, sequential FP64
-    {
-#pragma clang fp contract(off)
-        const double *yq = a.y + qi * d;
-        for (int e = tid; e < M * 256; e += blockDim.x) {
-            const int m = e >> 8;
-            const float *cw = a.codebooks + (size_t)e * dsub;
-            double s = 0.0;
-            for (int j = 0; j < dsub; ++j) {
-                const double t = yq[m * dsub + j] - (double)cw[j];
-                const double t2 = t * t;
-                s = s + t2;
-            }
-            lut[e] = (float)s;
-        }
-        if (tid < L) {
-            double s = 0.0;
-            for (int j = a.g.cut[tid]; j < a.g.cut[tid + 1]; ++j) s += yq[j] * yq[j];
-            e2[tid] = s;
-        }
-    }
-    __syncthreads();
-    if (w == 0) {
-        // blocks of the probed lists, as an exclusive prefix over the probe order
-        int run = 0;
-        for (int c0 = 0; c0 < np; c0 += 64) {
-            const int i = c0 + lane;
-            const int v = i < np ? (int)(a.list_blk[plist[i] + 1] - a.list_blk[plist[i]]) : 0;
-            int inc = v;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int t = __shfl_up(inc, o, 64);
-                if (lane >= o) inc += t;
-            }
-            if (i < np) pref[i] = run + inc - v;
-            run += __shfl(inc, 63, 64);
-        }
-        if (lane == 0) {
-            pref[np] = run;
-            // the query's norm beyond level l, l = 1..L-1
-            double acc = 0.0;
-            for (int l = L - 1; l >= 1; --l) {
-                acc += e2[l];
-                qa[l - 1] = (float)sqrt(acc);
-            }
-        }
-    }
-    __syncthreads();
-    const int ntask = pref[np];
     const int cap = a.cap;
     uint64_t *wb = wbuf + (size_t)w * cap;
     int wc = 0;
-    unsigned long long looks = 0, cands = 0;
+    unsigned long long looks = 0, cands = 0, bytes = 0;
     const float g_adc = a.g_adc;
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(&task, 1);
-        t = __shfl(t, 0, 64);
-        if (t >= ntask) break;
-        int lo = 0, hi = np;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (pref[mid] <= t) lo = mid;
-            else hi = mid;
+    for (int r0 = 0; r0 < np; r0 += nlr) {
+        const int nl = min(nlr, np - r0);
+        __syncthreads();  // the previous round's tables are no longer read
+        if (tid < nl) rlist[tid] = a.probes[qi * a.np_max + r0 + tid];
+        if (tid == 0) task = 0;
+        __syncthreads();
+        // the residuals of this round's lists, then their tables and level energies
+        for (int e = tid; e < nl * d; e += blockDim.x) {
+            const int li = e / d, j = e - li * d;
+            zs[e] = yq[j] - a.yc[(int64_t)rlist[li] * d + j];
         }
-        const int64_t b = a.list_blk[plist[lo]] + (t - pref[lo]);
-        const int cnt = a.blk_cnt[b];
-        const int s0 = lane * 4;
-        unsigned alive = 0;
+        __syncthreads();
+        switch (dsub) {
+        case 1: pq_build_tables<1>(luts, zs, nl, M, d, a.codebooks); break;
+        case 2: pq_build_tables<2>(luts, zs, nl, M, d, a.codebooks); break;
+        case 4: pq_build_tables<4>(luts, zs, nl, M, d, a.codebooks); break;
+        case 8: pq_build_tables<8>(luts, zs, nl, M, d, a.codebooks); break;
+        default: pq_build_tables<16>(luts, zs, nl, M, d, a.codebooks); break;
+        }
+        for (int e = tid; e < nl * L; e += blockDim.x) {
+            const int li = e / L, lv = e - li * L;
+            const double *z = zs + (size_t)li * d;
+            double s = 0.0;
+            for (int j = a.g.cut[lv]; j < a.g.cut[lv + 1]; ++j) s += z[j] * z[j];
+            e2[e] = s;
+        }
+        if (tid == 0) {
+            // quarter blocks of the round's lists, as an exclusive prefix
+            int run = 0;
+            for (int li = 0; li < nl; ++li) {
+                rpref[li] = run;
+                const int l = rlist[li];
+                run += 4 * (int)(a.list_blk[l + 1] - a.list_blk[l]);
+            }
+            rpref[nl] = run;
+        }
+        __syncthreads();
+        if (tid < nl) {
+            // the residual's norm beyond level l, l = 1..L-1
+            double acc = 0.0;
+            for (int lv = L - 1; lv >= 1; --lv) {
+                acc += e2[tid * L + lv];
+                qa[tid * L + lv - 1] = (float)sqrt(acc);
+            }
+        }
+        __syncthreads();
+        const int ntask = rpref[nl];
+        for (;;) {
+            int t = 0;
+            if (lane == 0) t = atomicAdd(&task, 1);
+            t = __shfl(t, 0, 64);
+            if (t >= ntask) break;
+            int li = 0;
+            while (li + 1 < nl && rpref[li + 1] <= t) ++li;
+            const int l = rlist[li];
+            const int64_t b = a.list_blk[l] + (t - rpref[li]) / 4;
+            const int slot = ((t - rpref[li]) & 3) * 64 + lane;
+            const int cnt = a.blk_cnt[b];
+            if (__ballot(slot < cnt) == 0) continue;  // an empty quarter of the last block
+            bool alive = slot < cnt;
+            cands += alive ? 1ull : 0ull;
+            float p = 0.f;
+            const float *lut = luts + (size_t)li * M * 256;
+            const float *qal = qa + li * L;
+            const uint8_t *cb = a.codes + (size_t)b * M * PQ_B + slot;
+            const float *tb = a.tails + (size_t)b * (L - 1) * PQ_B + slot;
+            for (int lv = 0; lv < L; ++lv) {
+                if (PRUNE && __ballot(alive) == 0) break;
+                const int m0 = a.g.sub_off[lv], m1 = a.g.sub_off[lv + 1];
+                looks += alive ? (unsigned long long)(m1 - m0) : 0ull;
+                if (lane == 0) bytes += (unsigned long long)((m1 - m0) * 64 + (PRUNE && lv + 1 < L ? 256 : 0));
+                int m = m0;
+                for (; m + 8 <= m1; m += 8) {
+                    uint32_t cv[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (s0 + j < cnt) alive |= 1u << j;
-        cands += (lane == 0) ? (unsigned long long)cnt : 0ull;
-        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-        const uint8_t *cb = a.codes + (size_t)b * M * PQ_B + s0;
-        const float *tb = a.tails + (size_t)b * (L - 1) * PQ_B + s0;
-        for (int l = 0; l < L; ++l) {
-            if (PRUNE && __ballot(alive != 0) == 0) break;
-            const int m0 = a.g.sub_off[l], m1 = a.g.sub_off[l + 1];
-            looks += (unsigned long long)(__popc(alive) * (m1 - m0));
-            int m = m0;
-            for (; m + 4 <= m1; m += 4) {
-                uint32_t wv[4];
+                    for (int u = 0; u < 8; ++u) cv[u] = cb[(size_t)(m + u) * PQ_B];
+                    if (alive) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) wv[u] = *reinterpret_cast<const uint32_t *>(cb + (size_t)(m + u) * PQ_B);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float *lm = lut + (m + u) * 256;
-                    if (alive & 1) p0 += lm[wv[u] & 255u];
-                    if (alive & 2) p1 += lm[(wv[u] >> 8) & 255u];
-                    if (alive & 4) p2 += lm[(wv[u] >> 16) & 255u];
-                    if (alive & 8) p3 += lm[wv[u] >> 24];
+                        for (int u = 0; u < 8; ++u) p += lut[(m + u) * 256 + cv[u]];
+                    }
+                }
+                for (; m < m1; ++m) {
+                    const uint32_t cv = cb[(size_t)m * PQ_B];
+                    if (alive) p += lut[m * 256 + cv];
+                }
+                if (PRUNE && lv + 1 < L && alive) {
+                    const float bt = tb[(size_t)lv * PQ_B];
+                    const float T = __uint_as_float(*(volatile unsigned *)&thr);
+                    if (pq_lower_bound(p, qal[lv], bt, a.eps, a.g_part) > T) alive = false;
                 }
             }
-            for (; m < m1; ++m) {
-                const uint32_t wv = *reinterpret_cast<const uint32_t *>(cb + (size_t)m * PQ_B);
-                const float *lm = lut + m * 256;
-                if (alive & 1) p0 += lm[wv & 255u];
-                if (alive & 2) p1 += lm[(wv >> 8) & 255u];
-                if (alive & 4) p2 += lm[(wv >> 16) & 255u];
-                if (alive & 8) p3 += lm[wv >> 24];
-            }
-            if (PRUNE && l + 1 < L && alive) {
-                const float4 bt = *reinterpret_cast<const float4 *>(tb + (size_t)l * PQ_B);
-                const float T = __uint_as_float(*(volatile unsigned *)&thr);
-                const float av = qa[l];
-                if ((alive & 1) && pq_lower_bound(p0, av, bt.x, a.eps, a.g_part) > T) alive &= ~1u;
-                if ((alive & 2) && pq_lower_bound(p1, av, bt.y, a.eps, a.g_part) > T) alive &= ~2u;
-                if ((alive & 4) && pq_lower_bound(p2, av, bt.z, a.eps, a.g_part) > T) alive &= ~4u;
-                if ((alive & 8) && pq_lower_bound(p3, av, bt.w, a.eps, a.g_part) > T) alive &= ~8u;
-            }
-        }
-        // commit the candidates that may reach the answer
-        const float pv[4] = {p0, p1, p2, p3};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
+            // commit a candidate that may reach the answer
             const float T = __uint_as_float(*(volatile unsigned *)&thr);
-            const bool has = ((alive >> j) & 1u) && pv[j] * (1.f - g_adc) <= T;
+            const bool has = alive && p * (1.f - g_adc) <= T;
             const uint64_t bm = __ballot(has);
             if (bm == 0) continue;
             const int nn = __popcll(bm);
@@ -391,10 +459,7 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
                     continue;
                 }
             }
-            if (has) {
-                const int pos = wc + __popcll(bm & ((1ull << lane) - 1ull));
-                wb[pos] = make_key(pv[j], (int32_t)(b * PQ_B + s0 + j));
-            }
+            if (has) wb[wc + __popcll(bm & ((1ull << lane) - 1ull))] = make_key(p, (int32_t)(b * PQ_B + slot));
             wc += nn;
         }
     }
@@ -404,10 +469,12 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
     for (int o = 32; o > 0; o >>= 1) {
         looks += __shfl_xor(looks, o, 64);
         cands += __shfl_xor(cands, o, 64);
+        bytes += __shfl_xor(bytes, o, 64);
     }
     if (lane == 0 && a.stats) {
         atomicAdd(&a.stats[0], looks);
         atomicAdd(&a.stats[1], cands);
+        atomicAdd(&a.stats[3], bytes);
     }
     __syncthreads();
     if (ovf) {
@@ -426,12 +493,8 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
         if (r < wcount[ww]) {
             const uint64_t e = wbuf[i];
             if (key_dist(e) * (1.f - g_adc) <= T) {
-#pragma clang fp contract(off)
                 const int32_t slot = key_id(e);
-                const uint8_t *cs = a.codes + (size_t)(slot / PQ_B) * M * PQ_B + (slot % PQ_B);
-                double s = 0.0;
-                for (int m = 0; m < M; ++m) s = s + (double)lut[m * 256 + cs[(size_t)m * PQ_B]];
-                key = make_key((float)s, a.ids[slot]);
+                key = make_key(pq_canonical(a, yq, slot), a.ids[slot]);
             }
         }
         wbuf[i] = key;
@@ -451,70 +514,44 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
 }
 
 // The exact answer of each query whose buffers overflowed (a band of equal
-// or nearly equal distances wider than the buffers): one workgroup rebuilds
-// its table, takes the canonical distance of every probed candidate into
-// `keys` and selects the k smallest (distance, id) keys.
+// or nearly equal distances wider than the buffers): one workgroup takes the
+// canonical distance of every probed candidate into `keys` and selects the k
+// smallest (distance, id) keys.  The flags are checked NT queries at a time;
+// overflow is rare, so the queries that need it are handled one after another.
 __global__ __launch_bounds__(NT) void k_pq_fallback(PqScan a, uint64_t *__restrict__ keys)
 {
-    extern __shared__ __align__(16) char sm[];
-    float *lut = reinterpret_cast<float *>(sm);
     __shared__ int32_t todo[NT];
     __shared__ int ntodo;
-    const int M = a.g.M, d = a.g.d, dsub = a.g.dsub;
-    // the flags are checked NT queries at a time; overflow is rare, so the
-    // queries that need the fallback are handled one after another
+    const int d = a.g.d;
     for (int64_t q0 = 0; q0 < a.nq; q0 += NT) {
-      if (threadIdx.x == 0) ntodo = 0;
-      __syncthreads();
-      {
-        const int64_t qq = q0 + threadIdx.x;
-        if (qq < a.nq && (a.qflags[qq] & FLAG_OVERFLOW) && !(a.qflags[qq] & FLAG_NONFINITE))
-            todo[atomicAdd(&ntodo, 1)] = (int32_t)threadIdx.x;
-      }
-      __syncthreads();
-      const int nt = ntodo;
-      for (int jt = 0; jt < nt; ++jt) {
-        const int64_t qi = q0 + todo[jt];
+        if (threadIdx.x == 0) ntodo = 0;
+        __syncthreads();
         {
-#pragma clang fp contract(off)
+            const int64_t qq = q0 + threadIdx.x;
+            if (qq < a.nq && (a.qflags[qq] & FLAG_OVERFLOW) && !(a.qflags[qq] & FLAG_NONFINITE))
+                todo[atomicAdd(&ntodo, 1)] = (int32_t)threadIdx.x;
+        }
+        __syncthreads();
+        const int nt = ntodo;
+        for (int jt = 0; jt < nt; ++jt) {
+            const int64_t qi = q0 + todo[jt];
             const double *yq = a.y + qi * d;
-            for (int e = threadIdx.x; e < M * 256; e += NT) {
-                const int m = e >> 8;
-                const float *cw = a.codebooks + (size_t)e * dsub;
-                double s = 0.0;
-                for (int j = 0; j < dsub; ++j) {
-                    const double t = yq[m * dsub + j] - (double)cw[j];
-                    const double t2 = t * t;
-                    s = s + t2;
+            const int np = a.npq[qi];
+            int64_t total = 0;
+            for (int li = 0; li < np; ++li) {
+                const int l = a.probes[qi * a.np_max + li];
+                const int64_t nslots = (a.list_blk[l + 1] - a.list_blk[l]) * PQ_B;
+                for (int64_t t = threadIdx.x; t < nslots; t += NT) {
+                    const int64_t slot = a.list_blk[l] * PQ_B + t;
+                    const int32_t id = a.ids[slot];
+                    keys[total + t] = id >= 0 ? make_key(pq_canonical(a, yq, slot), id) : KEY_MAX;
                 }
-                lut[e] = (float)s;
+                total += nslots;
             }
+            __syncthreads();
+            fallback_select_block(keys, total, a.k, a.out_ids + qi * a.k, a.out_d + qi * a.k);
+            __syncthreads();
         }
-        __syncthreads();
-        const int np = a.npq[qi];
-        int64_t total = 0;
-        for (int li = 0; li < np; ++li) {
-            const int l = a.probes[qi * a.np_max + li];
-            const int64_t nslots = (a.list_blk[l + 1] - a.list_blk[l]) * PQ_B;
-            for (int64_t t = threadIdx.x; t < nslots; t += NT) {
-#pragma clang fp contract(off)
-                const int64_t slot = a.list_blk[l] * PQ_B + t;
-                uint64_t key = KEY_MAX;
-                const int32_t id = a.ids[slot];
-                if (id >= 0) {
-                    const uint8_t *cs = a.codes + (size_t)(slot / PQ_B) * M * PQ_B + (slot % PQ_B);
-                    double s = 0.0;
-                    for (int m = 0; m < M; ++m) s = s + (double)lut[m * 256 + cs[(size_t)m * PQ_B]];
-                    key = make_key((float)s, id);
-                }
-                keys[total + t] = key;
-            }
-            total += nslots;
-        }
-        __syncthreads();
-        fallback_select_block(keys, total, a.k, a.out_ids + qi * a.k, a.out_d + qi * a.k);
-        __syncthreads();
-      }
     }
 }
 
@@ -563,7 +600,38 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
     PANO_HIP(hipMemcpyAsync(ix->mu64.p, tf->mu.data(), sizeof(double) * d, hipMemcpyHostToDevice, s));
     PANO_HIP(hipMemcpyAsync(padcol_d.p, padcol.data(), sizeof(int32_t) * d, hipMemcpyHostToDevice, s));
 
-    // training sample in the shaped frame
+    // the list centroids in the shaped frame: FP64, each coordinate a sequential
+    // sum over j (the recipe of the queries' coordinates)
+    std::vector<float> ch_cent((size_t)nlist * d);
+    PANO_HIP(hipMemcpyAsync(ch_cent.data(), centroids_dev, sizeof(float) * ch_cent.size(), hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> asg(n);
+    PANO_HIP(hipMemcpyAsync(asg.data(), assign_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    PANO_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i) PANO_REQUIRE(asg[i] >= 0 && asg[i] < nlist, "assignment out of range");
+    std::vector<double> yc((size_t)nlist * d);
+    std::vector<float> yc32((size_t)nlist * d);
+    parallel_for(nlist, 1, [&](int64_t l0, int64_t l1) {
+#pragma clang fp contract(off)
+        std::vector<double> cc(d);
+        for (int64_t l = l0; l < l1; ++l) {
+            for (int j = 0; j < d; ++j) cc[j] = (double)ch_cent[(size_t)l * d + j] - tf->mu[j];
+            for (int i = 0; i < d; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < d; ++j) {
+                    const double pr = tf->T[(size_t)i * d + j] * cc[j];
+                    acc = acc + pr;
+                }
+                yc[(size_t)l * d + i] = acc;
+                yc32[(size_t)l * d + i] = (float)acc;
+            }
+        }
+    });
+    ix->yc64.alloc(sizeof(double) * yc.size());
+    PANO_HIP(hipMemcpyAsync(ix->yc64.p, yc.data(), sizeof(double) * yc.size(), hipMemcpyHostToDevice, s));
+    DevMem yc32d;
+    yc32d.alloc(sizeof(float) * yc32.size());
+    PANO_HIP(hipMemcpyAsync(yc32d.p, yc32.data(), sizeof(float) * yc32.size(), hipMemcpyHostToDevice, s));
+    // training sample: residuals in the shaped frame
     const int64_t ns = std::min<int64_t>(n, std::max<int64_t>(256, sample));
     std::vector<int64_t> rows = seeded_sample(n, ns, seed ^ 0x2545F4914F6CDD1Dull);
     DevMem rows_d, xs, Ys, codes_s, cb;
@@ -579,6 +647,11 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
     PANO_HIP(hipMemcpyAsync(Yh.data(), Ys.p, sizeof(float) * Yh.size(), hipMemcpyDeviceToHost, s));
     PANO_HIP(hipStreamSynchronize(s));
     for (float v : Yh) PANO_REQUIRE(std::isfinite(v), "x has a non-finite value");
+    for (int64_t r = 0; r < ns; ++r) {
+        const float *c = yc32.data() + (size_t)asg[rows[r]] * d;
+        for (int j = 0; j < d; ++j) Yh[(size_t)r * d + j] -= c[j];
+    }
+    PANO_HIP(hipMemcpyAsync(Ys.p, Yh.data(), sizeof(float) * Yh.size(), hipMemcpyHostToDevice, s));
     // initial codewords: 256 sample rows spread over the sample
     std::vector<float> C((size_t)M * 256 * dsub);
     for (int c = 0; c < 256; ++c) {
@@ -625,6 +698,9 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
             const int64_t rn = std::min(chunk, n - r0);
             launch_transform(x_dev + r0 * d, rn, d, T32d.as<float>(), mu32d.as<float>(), padcol_d.as<int32_t>(),
                              Yc.as<float>(), d, s);
+            hipLaunchKernelGGL(k_pq_residual, dim3((unsigned)((rn * d + 255) / 256)), dim3(256), 0, s, Yc.as<float>(),
+                               rn, d, assign_dev + r0, yc32d.as<float>());
+            PANO_HIP(hipGetLastError());
             launch_assign_sub(Yc.as<float>(), rn, d, M, dsub, ix->codebooks.as<float>(),
                               ix->codes_row.as<uint8_t>() + r0 * M, s);
         }
@@ -638,14 +714,8 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
         cwe[e] = acc;
     }
     // lists: stable counting sort by assignment, blocks of 256 slots
-    std::vector<int32_t> asg(n);
-    PANO_HIP(hipMemcpyAsync(asg.data(), assign_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-    PANO_HIP(hipStreamSynchronize(s));
     ix->list_len.assign(nlist, 0);
-    for (int64_t i = 0; i < n; ++i) {
-        PANO_REQUIRE(asg[i] >= 0 && asg[i] < nlist, "assignment out of range");
-        ix->list_len[asg[i]]++;
-    }
+    for (int64_t i = 0; i < n; ++i) ix->list_len[asg[i]]++;
     std::vector<int64_t> start(nlist + 1, 0);
     for (int l = 0; l < nlist; ++l) start[l + 1] = start[l] + ix->list_len[l];
     std::vector<int64_t> perm(n);
@@ -667,7 +737,8 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
     std::vector<int32_t> block_list(std::max<int64_t>(1, ix->nblocks));
     for (int l = 0; l < nlist; ++l)
         for (int64_t b = ix->list_blk[l]; b < ix->list_blk[l + 1]; ++b) block_list[b] = l;
-    DevMem perm_d, start_d, block_list_d, cwe_d;
+    DevMem perm_d, start_d, cwe_d;
+    DevMem &block_list_d = ix->block_list;
     perm_d.alloc(sizeof(int64_t) * n);
     start_d.alloc(sizeof(int64_t) * (nlist + 1));
     block_list_d.alloc(sizeof(int32_t) * block_list.size());
@@ -725,15 +796,17 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     const bool brute = (flags & PANO_PQ_BRUTE) != 0;
     const bool want_stats = (flags & PANO_SEARCH_STATS) != 0;
     ctx->quiesce();
-    // scan geometry: the table, then per-wave buffers of cap keys
+    // scan geometry: per-wave buffers of cap keys, then as many lists' tables
+    // (with their tail norms) as fit
     int cap = 1;
     while (cap < k + 96) cap <<= 1;
-    const size_t fixed_lds = (size_t)M * 256 * 4 + (size_t)(2 * np_max + 1) * 4 + (size_t)L * 4 + 64;
+    const size_t per_list = (size_t)M * 256 * 4 + (size_t)L * 12 + (size_t)d * 8 + 8;
+    const size_t budget = (size_t)PQ_LDS - 2048 - 64;
     int waves = 16;
-    while (waves > 1 && fixed_lds + (size_t)waves * cap * 8 > (size_t)PQ_LDS - 2048) waves >>= 1;
-    PANO_REQUIRE(fixed_lds + (size_t)waves * cap * 8 <= (size_t)PQ_LDS - 2048 && waves >= 2,
-                 "k and M too large for the PQ scan's LDS");
-    const size_t scan_shm = fixed_lds + (size_t)waves * cap * 8;
+    while (waves > 2 && (size_t)waves * cap * 8 + per_list > budget) waves >>= 1;
+    PANO_REQUIRE((size_t)waves * cap * 8 + per_list <= budget, "k and M too large for the PQ scan's LDS");
+    const int nlr = (int)std::min<size_t>({(budget - (size_t)waves * cap * 8) / per_list, (size_t)np_max, (size_t)16});
+    const size_t scan_shm = (size_t)waves * cap * 8 + (size_t)nlr * per_list + 64;
     // scratch
     const size_t nS = nlist > 1 ? aup(sizeof(float) * nq * nlist) : 256;
     const size_t nP = aup(sizeof(int32_t) * nq * np_max) + aup(sizeof(int32_t) * nq) + aup(sizeof(int32_t) * nlist) +
@@ -774,11 +847,14 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     a.np_max = np_max;
     a.cap = cap;
     a.waves = waves;
+    a.nlr = nlr;
     a.eps = eps;
     const double u = std::ldexp(1.0, -24);
     a.g_part = (float)(2.0 * (M + 2) * u);
     a.g_adc = (float)((4.0 * (M + 2) + 2.0) * u);
     a.y = y;
+    a.yc = ix->yc64.as<double>();
+    a.block_list = ix->block_list.as<int32_t>();
     a.codebooks = ix->codebooks.as<float>();
     a.probes = probes;
     a.npq = npq;
@@ -797,9 +873,7 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     hipLaunchKernelGGL(kern, dim3((unsigned)nq), dim3(64 * waves), scan_shm, ws, a);
     PANO_HIP(hipGetLastError());
     if (want_stats) PANO_HIP(hipEventRecord(ctx->ev[2], ws));
-    const size_t fb_shm = (size_t)M * 256 * 4;
-    PANO_HIP(hipFuncSetAttribute((const void *)k_pq_fallback, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fb_shm));
-    hipLaunchKernelGGL(k_pq_fallback, dim3(1), dim3(NT), fb_shm, ws, a, keys);
+    hipLaunchKernelGGL(k_pq_fallback, dim3(1), dim3(NT), 0, ws, a, keys);
     PANO_HIP(hipGetLastError());
     std::vector<int32_t> hf(nq);
     PANO_HIP(hipMemcpyAsync(hf.data(), qflags, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, ws));
@@ -817,6 +891,7 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
         ix->last_stats[1] = (int64_t)hs[1] * M;
         ix->last_stats[2] = (int64_t)hs[2];
         ix->last_stats[3] = (int64_t)hs[1];
+        ix->last_stats[4] = (int64_t)hs[3];
     }
 }
 

@@ -174,11 +174,11 @@ class PQIndex:
         return ids, dists
 
     def stats(self) -> dict:
-        out = np.zeros(4, dtype=np.int64)
+        out = np.zeros(5, dtype=np.int64)
         ms = C.c_double()
         L.check(L.lib().pano_pq_stats(self.h, _np_ptr(out), C.byref(ms)))
         return {"lookups": int(out[0]), "lookups_full": int(out[1]), "fallback_queries": int(out[2]),
-                "candidates": int(out[3]), "ms_scan": ms.value,
+                "candidates": int(out[3]), "scan_bytes": int(out[4]), "ms_scan": ms.value,
                 "phi": float(out[0]) / max(1, int(out[1]))}
 
     def export(self):

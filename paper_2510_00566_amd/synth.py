@@ -93,6 +93,8 @@ class Workload:
     level_width: int = 16
     tune_width: bool = False     # the level width is the tuner's choice (else fixed by the configuration)
     q_spec_p: float | None = None  # out-of-distribution queries: their own decay law parameter (None = the data's)
+    pq_dsub: int = 0             # IVFPQ: coordinates per sub-quantizer (0: not a PQ workload)
+    pq_kappa: float = 0.0        # IVFPQ: the energy cap of the spectrum shaping (Section 4.2)
     note: str = ""
 
     @property
@@ -118,6 +120,11 @@ WORKLOADS = {
     "ivf_embed_bf16": Workload("ivf_embed_bf16", 4, 5_000_000, 768, 10_000, 100, "power", 0.8,
                                normalize=True, nlist=4096, nprobe=64, level_width=32, tune_width=True,
                                note="unit-normed embeddings, BF16 levels + FP32 rescoring"),
+    # IVFPQ over the GIST-like data (the same rows and queries as
+    # ivf_gist_like): 120 sub-quantizers of 8 coordinates, 12 levels of 80
+    "ivfpq_gist_like": Workload("ivfpq_gist_like", 2, 1_000_000, 960, 1000, 10, "exp", 0.01,
+                                n_clusters=1024, nlist=1024, nprobe=32, level_width=80, pq_dsub=8, pq_kappa=2.0,
+                                note="IVFPQ (M=120, 8 bits), shaped PCA (kappa 2), 12 levels x 80 dims"),
 }
 
 

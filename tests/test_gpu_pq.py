@@ -86,7 +86,8 @@ def test_pq_sift_like_shape(torch_cuda):
     assert st[False]["phi"] < 1.0
     # the codes: nearest codewords (FP32 on the GPU), softly against FP64
     y = pq.shaped_query(case["x"][:2000], case["mu"], case["t"])
-    mism = (pq.encode(y, case["cb"]) != case["codes"][:2000]).mean()
+    yc = pq.shaped_query(case["cent"], case["mu"], case["t"])
+    mism = (pq.encode(y - yc[case["assign"][:2000]], case["cb"]) != case["codes"][:2000]).mean()
     _log("code mismatches vs the FP64 rule", mism)
     assert mism < 1e-3
 
@@ -161,10 +162,12 @@ def test_pq_relaxed_bound_and_nonfinite(torch_cuda):
     ids, dd = case["idx"].search(qd, 10, nprobe=3, eps=0.5)
     gi, gd = ids.cpu().numpy(), dd.cpu().numpy()
     y = pq.shaped_query(q, case["mu"], case["t"])
+    yc = pq.shaped_query(case["cent"], case["mu"], case["t"])
     for qi in range(q.shape[0]):
-        tab = pq.lut(y[qi], case["cb"])
         ok = gi[qi] >= 0
-        assert np.array_equal(pq.adc(tab, case["codes"][gi[qi][ok]]), gd[qi][ok])
+        for r in np.nonzero(ok)[0]:
+            tab = pq.lut(y[qi] - yc[case["assign"][gi[qi][r]]], case["cb"])
+            assert pq.adc(tab, case["codes"][gi[qi][r:r + 1]])[0] == gd[qi][r]
         assert (gd[qi][ok] >= rd[qi][ok]).all()
     bad = q.copy()
     bad[2, 5] = np.nan

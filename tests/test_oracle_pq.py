@@ -259,3 +259,62 @@ def test_pq_knn_ivf_probes_and_ties():
     # distances: row 0: 9 + 9, rows 1, 2: 1 + 1 (tie, by id)
     assert ids[0].tolist() == [1, 2, 0, -1]
     assert dd[0, :3].tolist() == [2.0, 2.0, 18.0] and np.isinf(dd[0, 3])
+
+
+def test_residual_table_hand_example():
+    """A member of list 1 (centroid (10, 10, 10, 10)) coded (1, 1) with
+    codewords C[0][1] = (1, 0) and C[1][1] = (0, 1) is reconstructed as
+    (11, 10, 10, 11); for q = (10, 10, 10, 10) the residual is 0 and the
+    distance is 1 + 1."""
+    cb = np.full((2, 256, 2), 50.0, np.float32)
+    cb[0, 1] = (1.0, 0.0)
+    cb[1, 1] = (0.0, 1.0)
+    cent = np.array([[0, 0, 0, 0], [10, 10, 10, 10]], np.float32)
+    codes = np.array([[0, 0], [1, 1]], np.uint8)
+    assign = np.array([0, 1])
+    q = np.full((1, 4), 10.0, np.float32)
+    ids, dd = pq.pq_knn_ivf(q, np.zeros(4), np.eye(4), cb, codes, cent, assign, 1, 2)
+    assert ids[0].tolist() == [1, -1] and dd[0, 0] == 2.0
+    ids, dd = pq.pq_knn_ivf(q, np.zeros(4), np.eye(4), cb, codes, cent, assign, 2, 2)
+    # row 0 (list 0, centroid 0, codewords (50, 50) twice): 4 * 40^2
+    assert ids[0].tolist() == [1, 0] and dd[0].tolist() == [2.0, 6400.0]
+
+
+@pytest.mark.parametrize("seed", [4, 9])
+def test_panorama_pq_residual_lists_equal_brute(seed):
+    """Four clusters with their own centroids, residual codes, two probed
+    lists: Algorithm 1 with per-list tables equals the brute force at eps = 1,
+    and LB <= distance for every candidate at every level."""
+    g = np.random.default_rng(seed)
+    d, dsub, n = 32, 4, 800
+    M = d // dsub
+    cent = (g.standard_normal((4, d)) * 6).astype(np.float32)
+    assign = g.integers(0, 4, size=n)
+    lam = np.exp(-0.2 * np.arange(d))
+    x = (cent[assign] + g.standard_normal((n, d)) * np.sqrt(lam)).astype(np.float32)
+    qs = (cent[g.integers(0, 4, size=5)] + g.standard_normal((5, d)) * np.sqrt(lam)).astype(np.float32)
+    mu, t = np.zeros(d), np.eye(d)
+    yc = pq.shaped_query(cent, mu, t)
+    resid = pq.shaped_query(x, mu, t) - yc[assign]
+    cb = (g.standard_normal((M, 256, dsub)) * np.sqrt(lam.reshape(M, dsub))[:, None, :]).astype(np.float32)
+    codes = pq.encode(resid, cb)
+    sub_cuts = [0, 2, 4, 6, 8]
+    ri, rd = pq.pq_knn_ivf(qs, mu, t, cb, codes, cent, assign, 2, 10)
+    gi, gd, frac = pq.panorama_pq_knn_ivf(qs, mu, t, cb, codes, cent, assign, 2, 10, sub_cuts, batch=32)
+    assert np.array_equal(gi, ri) and np.array_equal(gd, rd)
+    assert frac.mean() < 1.0
+    # the bound on every candidate of every list
+    xt = pq.tails(pq.reconstruct(codes, cb), [c * dsub for c in sub_cuts])
+    y = pq.shaped_query(qs, mu, t)
+    for qi in range(qs.shape[0]):
+        for l in range(4):
+            mm = np.nonzero(assign == l)[0]
+            z = y[qi] - yc[l]
+            tab = pq.lut(z, cb)
+            full = pq.adc(tab, codes[mm]).astype(np.float64)
+            zt = pq.tails(z[None, :], [c * dsub for c in sub_cuts])[0]
+            p = np.zeros(mm.size)
+            for lv in range(1, 5):
+                for m in range(sub_cuts[lv - 1], sub_cuts[lv]):
+                    p += tab[m, codes[mm, m]].astype(np.float64)
+                assert (pq.pq_lower_bound(p, zt[lv], xt[mm, lv], 1.0) <= full * (1 + 1e-6) + 1e-9).all()
