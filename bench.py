@@ -44,9 +44,21 @@ def scan_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def scan_kernel_name(scan_mode: int, bf16: int) -> str:
+    """The scan kernel a search runs: scan mode 4 is the per-wave scan, mode 3
+    the brute-force scan (per-wave when the levels are bfloat16), else the
+    workgroup scan."""
+    if scan_mode == 4:
+        return "k_scan_wave_bf16" if bf16 else "k_scan_wave"
+    if scan_mode == 3:
+        return "k_scan_wave_brute_bf16" if bf16 else "k_scan_brute"
+    return "k_scan_pruned_bf16" if bf16 else "k_scan_pruned"
+
+
 def traffic_from_profiles(kernel: str, workload: str):
-    """HBM bytes per scan launch from the committed rocprofv3 counter summary,
-    if it was taken on the current scan kernel source."""
+    """HBM bytes per scan launch from the committed rocprofv3 counter summary
+    (L2-to-memory read requests by size plus written bytes), if it was taken
+    on the current scan kernel source."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
@@ -76,6 +88,10 @@ class Run:
         prm, width = autotune.lookup(self.sig)
         if width and w.tune_width:
             w.level_width = int(width)
+        if args.level_width:
+            w.level_width = int(args.level_width)
+        if args.params:
+            prm = Params(**json.loads(args.params))
         self.w = w
         t0 = time.time()
         data = synth.generate(w)
@@ -361,7 +377,7 @@ def measure(run: Run, args, primary: bool) -> dict:
     bf = None if args.no_bruteforce else run.bruteforce(ids_ref, d_ref)
     run.ids.copy_(ids_ref)
     run.dists.copy_(d_ref)
-    kernel = "k_scan_pruned_bf16" if run.use_bf16 else "k_scan_pruned"
+    kernel = scan_kernel_name(run.prm.scan_mode, run.use_bf16)
     achieved = (st["scan_bytes"] / 1e9) / (scan_ms / 1e3)
     res.update({
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nq": w.nq, "k": w.k, "nlist": w.nlist,
@@ -637,6 +653,8 @@ def main():
                     help="with --profile-only: also run the brute-force scans twice each")
     ap.add_argument("--transform", default="residual", choices=["residual", "data"])
     ap.add_argument("--tune", action="store_true", help="run the autotuner (level width and search knobs)")
+    ap.add_argument("--params", default="", help="search parameters as JSON (overrides the tuner's cache)")
+    ap.add_argument("--level-width", type=int, default=0, help="level width (overrides the tuner's cache)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the data-fit PCA comparison")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no graph replay)")
     ap.add_argument("--store", default="f32", choices=["f32", "bf16"],

@@ -425,14 +425,15 @@ pano_status pano_transform_shape(const pano_transform *pca, const int32_t *m_hos
  * FP64 means, an empty cell keeps its codeword) on a seeded sample of
  * max(256, min(n, sample)) rows from 256 sample rows spread over the sample,
  * and every row is coded by its nearest codewords (FP32 distance, ties to the
- * smaller code).  The levels m_host [L+1] (1 <= L <= 64) must fall on sub-vector
- * boundaries.  Lists follow assign_dev [n] in [0, nlist) with
+ * smaller code).  The levels m_host [L+1] (1 <= L <= 64) must have equal
+ * widths that fall on sub-vector boundaries, with at most 16 sub-quantizers
+ * per level.  Lists follow assign_dev [n] in [0, nlist) with
  * centroids_dev [nlist][d] (raw space, for probing).  Layout in device
- * memory, per list, blocks of 256 slots: the codes of a block sub-quantizer
- * by sub-quantizer, 256 bytes each (one byte per slot), then the norms of each
- * slot's reconstruction beyond levels 1..L-1 (FP32, level-major), then the
- * slot ids.  The index owns its memory.  Errors: EINVAL on shapes, cuts,
- * dsub or M; ENOMEM.
+ * memory, per list, blocks of 256 slots: the codes of a block level by level,
+ * each level slot by slot (a slot's codes of the level in 4 * ceil(M/L/4)
+ * bytes, zero padded), then the norms of each slot's reconstruction beyond
+ * levels 1..L-1 (FP32, level-major), then the slot ids.  The index owns its
+ * memory.  Errors: EINVAL on shapes, cuts, dsub or M; ENOMEM.
  */
 pano_status pano_pq_build(pano_ctx *ctx, const pano_transform *tf, const float *x_dev, int64_t n, int32_t d,
                           const float *centroids_dev, const int32_t *assign_dev, int32_t nlist,

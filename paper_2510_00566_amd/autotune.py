@@ -72,6 +72,8 @@ def tune_search(idx, q_dev, k: int, nprobe, reps: int = 5, space: dict | None = 
 
     def run(cfg):
         p = mk(cfg)
+        if log:
+            log(f"[autotune] trying {cfg}")
         return _time(lambda: idx.search(q_dev, k, nprobe=nprobe, params=p, nprobe_max=nprobe_max), reps)
 
     best_t = run(cur)

@@ -733,6 +733,9 @@ pano_status pano_pq_build(pano_ctx *ctx, const pano_transform *tf, const float *
         PANO_REQUIRE(iters >= 0, "iters must be >= 0");
         const std::vector<int> cuts = checked_cuts(m_host, L, d);
         for (int l = 0; l <= L; ++l) PANO_REQUIRE(cuts[l] % dsub == 0, "level cuts must fall on sub-vector boundaries");
+        for (int l = 0; l < L; ++l)
+            PANO_REQUIRE(cuts[l + 1] - cuts[l] == d / L, "the PQ index takes levels of equal width");
+        PANO_REQUIRE(d / dsub / L <= 16, "at most 16 sub-quantizers per level");
         PANO_REQUIRE(ctx && tf && x_dev && centroids_dev && assign_dev && out, "null argument");
         PANO_REQUIRE(tf->d == d, "transform dimension does not match d");
         PANO_HIP(hipSetDevice(ctx->device));

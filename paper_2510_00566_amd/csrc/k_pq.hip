@@ -28,6 +28,7 @@ constexpr int PQ_LDS = 160 * 1024;
 
 struct PqGeom {
     int M, dsub, L, d;
+    int ml, mw;                // sub-quantizers per level; 32-bit words per slot and level (ml <= 4 mw)
     int sub_off[PQ_MAXL + 1];  // level cuts in sub-quantizers
     int cut[PQ_MAXL + 1];      // level cuts in coordinates
 };
@@ -152,7 +153,8 @@ __global__ __launch_bounds__(256) void k_pq_pack(PqGeom g, const uint8_t *__rest
                                                  const int64_t *__restrict__ start, const int64_t *__restrict__ list_blk,
                                                  const int32_t *__restrict__ block_list, int64_t nblocks,
                                                  uint8_t *__restrict__ codes, float *__restrict__ tails,
-                                                 int32_t *__restrict__ ids, int32_t *__restrict__ blk_cnt)
+                                                 int32_t *__restrict__ ids, int32_t *__restrict__ blk_cnt,
+                                                 float *__restrict__ list_b0max)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= nblocks * PQ_B) return;
@@ -162,11 +164,13 @@ __global__ __launch_bounds__(256) void k_pq_pack(PqGeom g, const uint8_t *__rest
     const int64_t pos = (b - list_blk[l]) * PQ_B + sl;
     const int64_t len = start[l + 1] - start[l];
     const int M = g.M, L = g.L;
-    uint8_t *cb = codes + (size_t)b * M * PQ_B + sl;
+    const int ml = g.ml, wb = 4 * g.mw;  // a slot's codes of one level: wb bytes (ml used)
+    uint8_t *cb = codes + (size_t)b * L * PQ_B * wb + (size_t)sl * wb;
     float *tb = tails + (size_t)b * (L - 1) * PQ_B + sl;
     if (sl == 0) blk_cnt[b] = (int32_t)min<int64_t>(PQ_B, len - (b - list_blk[l]) * PQ_B);
     if (pos >= len) {
-        for (int m = 0; m < M; ++m) cb[(size_t)m * PQ_B] = 0;
+        for (int lv = 0; lv < L; ++lv)
+            for (int j = 0; j < wb; ++j) cb[(size_t)lv * PQ_B * wb + j] = 0;
         for (int lv = 0; lv + 1 < L; ++lv) tb[(size_t)lv * PQ_B] = 0.f;
         ids[b * PQ_B + sl] = -1;
         return;
@@ -180,8 +184,49 @@ __global__ __launch_bounds__(256) void k_pq_pack(PqGeom g, const uint8_t *__rest
         suffix += e;
         tb[(size_t)(lv - 1) * PQ_B] = (float)sqrt(suffix);
     }
-    for (int m = 0; m < M; ++m) cb[(size_t)m * PQ_B] = cr[m];
+    for (int m = g.sub_off[0]; m < g.sub_off[1]; ++m) suffix += cwe[m * 256 + cr[m]];
+    // the largest reconstruction norm of the list, rounded up (non-negative
+    // floats order as their bit patterns)
+    atomicMax(reinterpret_cast<int *>(list_b0max + l), __float_as_int((float)sqrt(suffix) * (1.f + 0x1p-20f)));
+    for (int lv = 0; lv < L; ++lv)
+        for (int j = 0; j < wb; ++j) cb[(size_t)lv * PQ_B * wb + j] = j < ml ? cr[lv * ml + j] : 0;
+    (void)M;
     ids[b * PQ_B + sl] = (int32_t)row;
+}
+
+// ---------------------------------------------------------------- table terms
+// The table entry of list l splits as ||z_m||^2 + T1[l][m][c] + T2[q][m][c]
+// with T1 = ||C_mc||^2 + 2 <y_c(l)_m, C_mc> (per list, built once) and
+// T2 = -2 <y_m, C_mc> (per query); each term is an FP64 sum rounded to FP32.
+__global__ __launch_bounds__(256) void k_pq_t1(const double *__restrict__ yc, int64_t nlist, int M, int dsub,
+                                               const float *__restrict__ cb, float *__restrict__ t1)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nlist * M * 256) return;
+    const int64_t l = e / (M * 256);
+    const int ee = (int)(e - l * M * 256), m = ee >> 8;
+    const float *cw = cb + (size_t)ee * dsub;
+    const double *y = yc + l * (int64_t)M * dsub + m * dsub;
+    double nn = 0.0, dot = 0.0;
+    for (int j = 0; j < dsub; ++j) {
+        nn += (double)cw[j] * cw[j];
+        dot += y[j] * cw[j];
+    }
+    t1[e] = (float)(nn + 2.0 * dot);
+}
+
+__global__ __launch_bounds__(256) void k_pq_t2(const double *__restrict__ yq, int64_t nq, int M, int dsub,
+                                               const float *__restrict__ cb, float *__restrict__ t2)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nq * M * 256) return;
+    const int64_t q = e / (M * 256);
+    const int ee = (int)(e - q * M * 256), m = ee >> 8;
+    const float *cw = cb + (size_t)ee * dsub;
+    const double *y = yq + q * (int64_t)M * dsub + m * dsub;
+    double dot = 0.0;
+    for (int j = 0; j < dsub; ++j) dot += y[j] * cw[j];
+    t2[e] = (float)(-2.0 * dot);
 }
 
 // ---------------------------------------------------------------- the scan
@@ -194,6 +239,10 @@ struct PqScan {
     float g_adc;   // |canonical - FP32 sum| <= g_adc * FP32 sum
     const double *y;   // [nq][d] the queries in the shaped frame
     const double *yc;  // [nlist][d] the list centroids in the shaped frame
+    const float *t1;   // [nlist][M][256] list terms of the tables
+    const float *t2;   // [nq][M][256] query terms of the tables
+    const float *ycn;  // [nlist] ||y_c(l)||
+    const float *b0max;  // [nlist] the largest reconstruction norm of each list
     const float *codebooks;
     const int32_t *probes, *npq;
     const int64_t *list_blk;
@@ -262,10 +311,12 @@ __device__ __forceinline__ float pq_canonical(const PqScan &a, const double *yq,
     const int M = a.g.M, dsub = a.g.dsub, d = a.g.d;
     const int64_t b = slot / PQ_B;
     const double *yl = a.yc + (int64_t)a.block_list[b] * d;
-    const uint8_t *cs = a.codes + (size_t)b * M * PQ_B + (slot % PQ_B);
+    const int ml = a.g.ml, wb = 4 * a.g.mw;
+    const uint8_t *cs = a.codes + (size_t)b * a.g.L * PQ_B * wb + (size_t)(slot % PQ_B) * wb;
     double s = 0.0;
     for (int m = 0; m < M; ++m) {
-        const int c = cs[(size_t)m * PQ_B];
+        const int lv = m / ml;
+        const int c = cs[(size_t)lv * PQ_B * wb + (m - lv * ml)];
         s = s + (double)pq_entry(yq, yl, a.codebooks + ((size_t)m * 256 + c) * dsub, m, dsub);
     }
     return (float)s;
@@ -274,20 +325,22 @@ __device__ __forceinline__ float pq_canonical(const PqScan &a, const double *yq,
 // A certified lower bound on the canonical distance from the FP32 partial sum
 // p of the levels read and the tail norms a (query residual) and b
 // (reconstruction): P + (a - b)^2 of Eq. 3 (plus 2 (1 - eps) a b, Eq. 4),
-// with room for the rounding of p, a, b, the table entries and the final
-// float32 rounding.
-__device__ __forceinline__ float pq_lower_bound(float p, float a, float b, float eps, float g_part)
+// with room for the rounding of p, a, b, the split table entries (dl, the
+// list's bound on their summed error) and the final float32 rounding.
+__device__ __forceinline__ float pq_lower_bound(float p, float a, float b, float eps, float g_part, float dl)
 {
     const float dab = fabsf(a - b) - 0x1p-22f * (a + b);
     const float t = dab > 0.f ? dab * dab : 0.f;
-    return (p * (1.f - g_part) + t * (1.f - 0x1p-22f) + 2.f * (1.f - eps) * a * b) * (1.f - 0x1p-21f);
+    return (p * (1.f - g_part) - dl + t * (1.f - 0x1p-22f) + 2.f * (1.f - eps) * a * b) * (1.f - 0x1p-21f);
 }
 
-// Sort the wavefront's buffer and keep the k smallest plus every entry that
-// may still reach the answer (sum * (1 - g) <= T, T = k-th * (1 + g), an upper
-// bound on the canonical k-th distance of the query); T goes to the shared
-// threshold.  Returns the new count.
-__device__ __noinline__ int pq_wave_trim(uint64_t *wb, int wc, int cap, int k, float g, unsigned *thr, int lane)
+// Sort the wavefront's buffer (keys: upper bounds on the canonical
+// distances) and keep the k smallest plus every entry that may still reach
+// the answer: T, the k-th upper bound, bounds the query's canonical k-th
+// distance from above, and an entry's lower bound is at least its upper bound
+// minus 2 (g up + dm).  T goes to the shared threshold.  Returns the new count.
+__device__ __noinline__ int pq_wave_trim(uint64_t *wb, int wc, int cap, int k, float g, float dm, unsigned *thr,
+                                         int lane)
 {
     for (int i = wc + lane; i < cap; i += 64) wb[i] = KEY_MAX;
     __builtin_amdgcn_wave_barrier();
@@ -295,11 +348,12 @@ __device__ __noinline__ int pq_wave_trim(uint64_t *wb, int wc, int cap, int k, f
     wave_bitonic_sort(wb, cap, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (wc < k) return wc;
-    const float T = key_dist(wb[k - 1]) * (1.f + g);
+    const float T = key_dist(wb[k - 1]);
     int keep = k;
     for (int i0 = k; i0 < wc; i0 += 64) {
         const int i = i0 + lane;
-        const bool in = i < wc && key_dist(wb[i]) * (1.f - g) <= T;
+        const float up = i < wc ? key_dist(wb[i]) : 0.f;
+        const bool in = i < wc && up - 2.f * (g * up + dm) <= T;
         const uint64_t bm = __ballot(in);
         keep += __popcll(bm);
         if (bm != (i0 + 64 <= wc ? ~0ull : ((1ull << (wc - i0)) - 1ull))) break;
@@ -317,7 +371,7 @@ __device__ __noinline__ int pq_wave_trim(uint64_t *wb, int wc, int cap, int k, f
 // is alive.  Survivors that may reach the answer go to the wavefront's LDS
 // buffer.  At the end every buffered entry that may reach the answer is
 // rescored canonically and the k smallest (distance, id) keys are written.
-template <bool PRUNE>
+template <bool PRUNE, int MW>
 __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
 {
     extern __shared__ __align__(16) char sm[];
@@ -327,9 +381,13 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
     float *qa = reinterpret_cast<float *>(wbuf + (size_t)a.waves * a.cap);        // [nlr][L]
     double *e2 = reinterpret_cast<double *>(qa + (size_t)nlr * L + ((nlr * L) & 1));  // [nlr][L]
     double *zs = e2 + (size_t)nlr * L;                                          // [nlr][d]
-    int32_t *rpref = reinterpret_cast<int32_t *>(zs + (size_t)nlr * d);         // [nlr + 1]
+    float *zn = reinterpret_cast<float *>(zs + (size_t)nlr * d);                 // [nlr][M]
+    float *dl = zn + (size_t)nlr * M;                                            // [nlr]
+    int32_t *rpref = reinterpret_cast<int32_t *>(dl + nlr);                     // [nlr + 1]
     int32_t *rlist = rpref + nlr + 1;                                            // [nlr]
-    __shared__ unsigned thr;
+    __shared__ unsigned thr, dmax;
+    __shared__ float ynorm;
+    __shared__ double ysq[16];
     __shared__ int task, ovf;
     __shared__ int wcount[16];
     const int64_t qi = blockIdx.x;
@@ -348,7 +406,22 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
     const double *yq = a.y + qi * d;
     if (tid == 0) {
         thr = 0x7f800000u;  // +inf
+        dmax = 0u;
         ovf = 0;
+    }
+    {
+        // ||y|| (for the error bound of the split tables)
+        double s = 0.0;
+        for (int j = tid; j < d; j += blockDim.x) s += yq[j] * yq[j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) ysq[w] = s;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += ysq[i];
+            ynorm = (float)(sqrt(t) * (1.0 + 1e-6));
+        }
     }
     const int cap = a.cap;
     uint64_t *wb = wbuf + (size_t)w * cap;
@@ -367,12 +440,45 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
             zs[e] = yq[j] - a.yc[(int64_t)rlist[li] * d + j];
         }
         __syncthreads();
-        switch (dsub) {
-        case 1: pq_build_tables<1>(luts, zs, nl, M, d, a.codebooks); break;
-        case 2: pq_build_tables<2>(luts, zs, nl, M, d, a.codebooks); break;
-        case 4: pq_build_tables<4>(luts, zs, nl, M, d, a.codebooks); break;
-        case 8: pq_build_tables<8>(luts, zs, nl, M, d, a.codebooks); break;
-        default: pq_build_tables<16>(luts, zs, nl, M, d, a.codebooks); break;
+        for (int e = tid; e < nl * M; e += blockDim.x) {
+            const int li = e / M, m = e - li * M;
+            const double *z = zs + (size_t)li * d + m * dsub;
+            double s = 0.0;
+            for (int j = 0; j < dsub; ++j) s += z[j] * z[j];
+            zn[e] = (float)s;
+        }
+        __syncthreads();
+        // tables: (||z_m||^2 + T1) + T2 in FP32, four entries per thread per step
+        {
+            // four float4 of each term in flight per thread
+            const float4 *t2q = reinterpret_cast<const float4 *>(a.t2 + (size_t)qi * M * 256);
+            const int n4 = M * 64, tot = nl * n4, nt = blockDim.x;
+            for (int e0 = tid; e0 < tot; e0 += 4 * nt) {
+                float4 u1[4], u2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * nt;
+                    if (e < tot) {
+                        const int li = e / n4, e4 = e - li * n4;
+                        u1[u] = reinterpret_cast<const float4 *>(a.t1 + (size_t)rlist[li] * M * 256)[e4];
+                        u2[u] = t2q[e4];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * nt;
+                    if (e < tot) {
+                        const int li = e / n4, e4 = e - li * n4;
+                        const float z2 = zn[li * M + (e4 >> 6)];
+                        float4 o;
+                        o.x = (z2 + u1[u].x) + u2[u].x;
+                        o.y = (z2 + u1[u].y) + u2[u].y;
+                        o.z = (z2 + u1[u].z) + u2[u].z;
+                        o.w = (z2 + u1[u].w) + u2[u].w;
+                        reinterpret_cast<float4 *>(luts + (size_t)li * M * 256)[e4] = o;
+                    }
+                }
+            }
         }
         for (int e = tid; e < nl * L; e += blockDim.x) {
             const int li = e / L, lv = e - li * L;
@@ -399,6 +505,16 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
                 acc += e2[tid * L + lv];
                 qa[tid * L + lv - 1] = (float)sqrt(acc);
             }
+            acc += e2[tid * L];
+            // the error of a distance summed from the split tables: each entry
+            // within 3u (||z_m||^2 + |T1| + |T2|) of the direct one; by
+            // Cauchy-Schwarz the sum over a candidate's entries is at most
+            // ||z||^2 + b^2 + 2 (||y_c|| + ||y||) b with b its reconstruction norm
+            const int l = rlist[tid];
+            const double b = a.b0max[l];
+            const float dlv = (float)(4.0 * 0x1p-24 * (acc + b * b + 2.0 * ((double)a.ycn[l] + ynorm) * b) * 1.01);
+            dl[tid] = dlv;
+            atomicMax(&dmax, __float_as_uint(dlv));
         }
         __syncthreads();
         const int ntask = rpref[nl];
@@ -419,51 +535,66 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
             float p = 0.f;
             const float *lut = luts + (size_t)li * M * 256;
             const float *qal = qa + li * L;
-            const uint8_t *cb = a.codes + (size_t)b * M * PQ_B + slot;
+            const float dlv = dl[li];
+            // this slot's codes, level by level (MW words each): the words and
+            // tail norms of CH levels are requested together, then summed
+            constexpr int CH = MW == 1 ? 12 : 12 / MW;
+            const uint32_t *cw = reinterpret_cast<const uint32_t *>(a.codes) + ((size_t)b * L * PQ_B + slot) * MW;
             const float *tb = a.tails + (size_t)b * (L - 1) * PQ_B + slot;
-            for (int lv = 0; lv < L; ++lv) {
+            const int ml = a.g.ml;
+            for (int l0 = 0; l0 < L; l0 += CH) {
                 if (PRUNE && __ballot(alive) == 0) break;
-                const int m0 = a.g.sub_off[lv], m1 = a.g.sub_off[lv + 1];
-                looks += alive ? (unsigned long long)(m1 - m0) : 0ull;
-                if (lane == 0) bytes += (unsigned long long)((m1 - m0) * 64 + (PRUNE && lv + 1 < L ? 256 : 0));
-                int m = m0;
-                for (; m + 8 <= m1; m += 8) {
-                    uint32_t cv[8];
+                uint32_t cv[CH][MW];
+                float tv[CH];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) cv[u] = cb[(size_t)(m + u) * PQ_B];
-                    if (alive) {
+                for (int c = 0; c < CH; ++c) {
+                    const int lv = l0 + c;
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) p += lut[(m + u) * 256 + cv[u]];
+                    for (int u = 0; u < MW; ++u) cv[c][u] = lv < L ? cw[(size_t)lv * PQ_B * MW + u] : 0u;
+                    tv[c] = (PRUNE && lv + 1 < L) ? tb[(size_t)lv * PQ_B] : 0.f;
+                }
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int lv = l0 + c;
+                    if (lv < L && alive) {
+                        looks += (unsigned long long)ml;
+                        const float *lm = lut + (size_t)lv * ml * 256;
+#pragma unroll
+                        for (int j = 0; j < 4 * MW; ++j)
+                            if (j < ml) p += lm[j * 256 + ((cv[c][j >> 2] >> (8 * (j & 3))) & 255u)];
+                        if (PRUNE && lv + 1 < L) {
+                            const float T = __uint_as_float(*(volatile unsigned *)&thr);
+                            if (pq_lower_bound(p, qal[lv], tv[c], a.eps, a.g_part, dlv) > T) alive = false;
+                        }
                     }
                 }
-                for (; m < m1; ++m) {
-                    const uint32_t cv = cb[(size_t)m * PQ_B];
-                    if (alive) p += lut[m * 256 + cv];
-                }
-                if (PRUNE && lv + 1 < L && alive) {
-                    const float bt = tb[(size_t)lv * PQ_B];
-                    const float T = __uint_as_float(*(volatile unsigned *)&thr);
-                    if (pq_lower_bound(p, qal[lv], bt, a.eps, a.g_part) > T) alive = false;
+                if (lane == 0) {
+                    const int nlv = min(CH, L - l0);
+                    bytes += (unsigned long long)(nlv * 64 * 4 * MW + (PRUNE ? 256 * min(nlv, L - 1 - l0) : 0));
                 }
             }
-            // commit a candidate that may reach the answer
+            // commit a candidate that may reach the answer; its key is an
+            // upper bound on its canonical distance
             const float T = __uint_as_float(*(volatile unsigned *)&thr);
-            const bool has = alive && p * (1.f - g_adc) <= T;
+            const float up = p * (1.f + g_adc) + dlv;
+            const float dm = __uint_as_float(*(volatile unsigned *)&dmax);
+            const bool has = alive && up - 2.f * (g_adc * up + dm) <= T;
             const uint64_t bm = __ballot(has);
             if (bm == 0) continue;
             const int nn = __popcll(bm);
             if (wc + nn > cap) {
-                wc = pq_wave_trim(wb, wc, cap, k, g_adc, &thr, lane);
+                wc = pq_wave_trim(wb, wc, cap, k, g_adc, dm, &thr, lane);
                 if (wc + nn > cap) {
                     if (lane == 0) ovf = 1;
                     continue;
                 }
             }
-            if (has) wb[wc + __popcll(bm & ((1ull << lane) - 1ull))] = make_key(p, (int32_t)(b * PQ_B + slot));
+            if (has) wb[wc + __popcll(bm & ((1ull << lane) - 1ull))] = make_key(up, (int32_t)(b * PQ_B + slot));
             wc += nn;
         }
     }
-    wc = pq_wave_trim(wb, wc, cap, k, g_adc, &thr, lane);
+    const float dmf = __uint_as_float(*(volatile unsigned *)&dmax);
+    wc = pq_wave_trim(wb, wc, cap, k, g_adc, dmf, &thr, lane);
     if (lane == 0) wcount[w] = wc;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -492,7 +623,8 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
         uint64_t key = KEY_MAX;
         if (r < wcount[ww]) {
             const uint64_t e = wbuf[i];
-            if (key_dist(e) * (1.f - g_adc) <= T) {
+            const float up = key_dist(e);
+            if (up - 2.f * (g_adc * up + dmf) <= T) {
                 const int32_t slot = key_id(e);
                 key = make_key(pq_canonical(a, yq, slot), a.ids[slot]);
             }
@@ -563,6 +695,8 @@ static PqGeom geom_of(const pano_pq_index *ix)
     g.dsub = ix->dsub;
     g.L = ix->L;
     g.d = ix->d;
+    g.ml = ix->M / ix->L;
+    g.mw = (g.ml + 3) / 4;
     for (int l = 0; l <= ix->L; ++l) {
         g.sub_off[l] = ix->sub_off[l];
         g.cut[l] = ix->cuts[l];
@@ -628,6 +762,17 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
     });
     ix->yc64.alloc(sizeof(double) * yc.size());
     PANO_HIP(hipMemcpyAsync(ix->yc64.p, yc.data(), sizeof(double) * yc.size(), hipMemcpyHostToDevice, s));
+    {
+        std::vector<float> ycn(nlist);
+        for (int l = 0; l < nlist; ++l) {
+            double acc = 0.0;
+            for (int i = 0; i < d; ++i) acc += yc[(size_t)l * d + i] * yc[(size_t)l * d + i];
+            ycn[l] = (float)(std::sqrt(acc) * (1.0 + 1e-6));
+        }
+        ix->ycn.alloc(sizeof(float) * nlist);
+        PANO_HIP(hipMemcpyAsync(ix->ycn.p, ycn.data(), sizeof(float) * nlist, hipMemcpyHostToDevice, s));
+        PANO_HIP(hipStreamSynchronize(s));
+    }
     DevMem yc32d;
     yc32d.alloc(sizeof(float) * yc32.size());
     PANO_HIP(hipMemcpyAsync(yc32d.p, yc32.data(), sizeof(float) * yc32.size(), hipMemcpyHostToDevice, s));
@@ -688,6 +833,11 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
     }
     ix->codebooks.alloc(sizeof(float) * C.size());
     PANO_HIP(hipMemcpyAsync(ix->codebooks.p, C.data(), sizeof(float) * C.size(), hipMemcpyHostToDevice, s));
+    // list terms of the query tables
+    ix->t1.alloc(sizeof(float) * (size_t)nlist * M * 256);
+    hipLaunchKernelGGL(k_pq_t1, dim3((unsigned)(((int64_t)nlist * M * 256 + 255) / 256)), dim3(256), 0, s,
+                       ix->yc64.as<double>(), (int64_t)nlist, M, dsub, ix->codebooks.as<float>(), ix->t1.as<float>());
+    PANO_HIP(hipGetLastError());
     // encode every row, in chunks
     ix->codes_row.alloc((size_t)n * M);
     {
@@ -752,16 +902,18 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
     PANO_HIP(hipMemcpyAsync(ix->list_blk_d.p, ix->list_blk.data(), sizeof(int64_t) * (nlist + 1),
                             hipMemcpyHostToDevice, s));
     const size_t slots = (size_t)std::max<int64_t>(1, ix->nblocks) * PQ_B;
-    ix->codes.alloc(slots * M);
+    ix->codes.alloc(slots * L * 4 * ((M / L + 3) / 4));
     ix->tails.alloc(sizeof(float) * slots * std::max(1, L - 1));
     ix->ids.alloc(sizeof(int32_t) * slots);
     ix->blk_cnt.alloc(sizeof(int32_t) * std::max<int64_t>(1, ix->nblocks));
+    ix->b0max.alloc(sizeof(float) * nlist);
+    PANO_HIP(hipMemsetAsync(ix->b0max.p, 0, sizeof(float) * nlist, s));
     if (ix->nblocks > 0) {
         hipLaunchKernelGGL(k_pq_pack, dim3((unsigned)((ix->nblocks * PQ_B + 255) / 256)), dim3(256), 0, s, geom_of(ix),
                            ix->codes_row.as<uint8_t>(), cwe_d.as<double>(), perm_d.as<int64_t>(),
                            start_d.as<int64_t>(), ix->list_blk_d.as<int64_t>(), block_list_d.as<int32_t>(),
                            ix->nblocks, ix->codes.as<uint8_t>(), ix->tails.as<float>(), ix->ids.as<int32_t>(),
-                           ix->blk_cnt.as<int32_t>());
+                           ix->blk_cnt.as<int32_t>(), ix->b0max.as<float>());
         PANO_HIP(hipGetLastError());
     }
     ix->cent.alloc(sizeof(float) * ((size_t)nlist * d + nlist));
@@ -800,7 +952,7 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     // (with their tail norms) as fit
     int cap = 1;
     while (cap < k + 96) cap <<= 1;
-    const size_t per_list = (size_t)M * 256 * 4 + (size_t)L * 12 + (size_t)d * 8 + 8;
+    const size_t per_list = (size_t)M * 256 * 4 + (size_t)L * 12 + (size_t)d * 8 + (size_t)M * 4 + 16;
     const size_t budget = (size_t)PQ_LDS - 2048 - 64;
     int waves = 16;
     while (waves > 2 && (size_t)waves * cap * 8 + per_list > budget) waves >>= 1;
@@ -811,7 +963,7 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     const size_t nS = nlist > 1 ? aup(sizeof(float) * nq * nlist) : 256;
     const size_t nP = aup(sizeof(int32_t) * nq * np_max) + aup(sizeof(int32_t) * nq) + aup(sizeof(int32_t) * nlist) +
                       aup(sizeof(float) * nq) + aup(sizeof(int32_t) * nq) + aup(sizeof(unsigned long long) * 4);
-    const size_t nY = aup(sizeof(double) * nq * d);
+    const size_t nY = aup(sizeof(double) * nq * d) + aup(sizeof(float) * nq * M * 256);
     const int64_t s_np = ix->top_blk_prefix[std::min<int64_t>(np_max, nlist)];
     const size_t nK = aup(sizeof(uint64_t) * std::max<int64_t>(1, s_np * PQ_B));
     ctx->scratch[5].ensure(nS);
@@ -827,6 +979,7 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     int32_t *qflags = cp.take<int32_t>(nq);
     unsigned long long *stats = cp.take<unsigned long long>(4);
     double *y = ctx->scratch[7].as<double>();
+    float *t2 = reinterpret_cast<float *>(reinterpret_cast<char *>(ctx->scratch[7].p) + aup(sizeof(double) * nq * d));
     uint64_t *keys = ctx->scratch[8].as<uint64_t>();
     hipStream_t ws = ctx->work_stream();
     PANO_HIP(hipEventRecord(ctx->ev_in, s));
@@ -839,6 +992,9 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
                          nprobe_all, np_max, probes, npq, list_cnt, qn2, ws);
     hipLaunchKernelGGL(k_pq_yseq, dim3((unsigned)((d + 63) / 64), (unsigned)((nq + 63) / 64)), dim3(256), 0, ws, q, nq,
                        d, ix->Tt64.as<double>(), ix->mu64.as<double>(), y, qflags);
+    PANO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_pq_t2, dim3((unsigned)((nq * M * 256 + 255) / 256)), dim3(256), 0, ws, y, nq, M, ix->dsub,
+                       ix->codebooks.as<float>(), t2);
     PANO_HIP(hipGetLastError());
     PqScan a{};
     a.g = geom_of(ix);
@@ -854,6 +1010,10 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     a.g_adc = (float)((4.0 * (M + 2) + 2.0) * u);
     a.y = y;
     a.yc = ix->yc64.as<double>();
+    a.t1 = ix->t1.as<float>();
+    a.t2 = t2;
+    a.ycn = ix->ycn.as<float>();
+    a.b0max = ix->b0max.as<float>();
     a.block_list = ix->block_list.as<int32_t>();
     a.codebooks = ix->codebooks.as<float>();
     a.probes = probes;
@@ -867,7 +1027,12 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     a.out_ids = ids;
     a.out_d = dists;
     a.stats = want_stats ? stats : nullptr;
-    auto kern = brute ? k_pq_scan<false> : k_pq_scan<true>;
+    typedef void (*PqKern)(PqScan);
+    const int mw = (M / L + 3) / 4;
+    static const PqKern kp[4] = {k_pq_scan<true, 1>, k_pq_scan<true, 2>, k_pq_scan<true, 3>, k_pq_scan<true, 4>};
+    static const PqKern kb[4] = {k_pq_scan<false, 1>, k_pq_scan<false, 2>, k_pq_scan<false, 3>, k_pq_scan<false, 4>};
+    PANO_REQUIRE(mw >= 1 && mw <= 4, "at most 16 sub-quantizers per level");
+    const PqKern kern = brute ? kb[mw - 1] : kp[mw - 1];
     PANO_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)scan_shm));
     if (want_stats) PANO_HIP(hipEventRecord(ctx->ev[1], ws));
     hipLaunchKernelGGL(kern, dim3((unsigned)nq), dim3(64 * waves), scan_shm, ws, a);
