@@ -241,7 +241,7 @@ struct pano_pq_index {
     pano::DevMem list_blk_d;  // [nlist + 1]
     pano::DevMem cent;        // [nlist][d] raw-space centroids, then their squared norms
     pano::DevMem yc64;        // [nlist][d] the centroids in the shaped frame, FP64
-    pano::DevMem t1;          // [nlist][M][256] list terms of the query tables
+    pano::DevMem sx;          // [nblocks][L][256] per slot and level: sum of ||C||^2 + 2 <y_c, C> over its codes
     pano::DevMem ycn;         // [nlist] norms of the shaped centroids (rounded up)
     pano::DevMem b0max;       // [nlist] the largest reconstruction norm of each list (rounded up)
     pano::DevMem block_list;  // [nblocks] the list of each block

@@ -154,7 +154,8 @@ __global__ __launch_bounds__(256) void k_pq_pack(PqGeom g, const uint8_t *__rest
                                                  const int32_t *__restrict__ block_list, int64_t nblocks,
                                                  uint8_t *__restrict__ codes, float *__restrict__ tails,
                                                  int32_t *__restrict__ ids, int32_t *__restrict__ blk_cnt,
-                                                 float *__restrict__ list_b0max)
+                                                 float *__restrict__ list_b0max, const double *__restrict__ yc,
+                                                 const float *__restrict__ cbook, float *__restrict__ sx)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= nblocks * PQ_B) return;
@@ -167,11 +168,13 @@ __global__ __launch_bounds__(256) void k_pq_pack(PqGeom g, const uint8_t *__rest
     const int ml = g.ml, wb = 4 * g.mw;  // a slot's codes of one level: wb bytes (ml used)
     uint8_t *cb = codes + (size_t)b * L * PQ_B * wb + (size_t)sl * wb;
     float *tb = tails + (size_t)b * (L - 1) * PQ_B + sl;
+    float *sbp = sx + (size_t)b * L * PQ_B + sl;
     if (sl == 0) blk_cnt[b] = (int32_t)min<int64_t>(PQ_B, len - (b - list_blk[l]) * PQ_B);
     if (pos >= len) {
         for (int lv = 0; lv < L; ++lv)
             for (int j = 0; j < wb; ++j) cb[(size_t)lv * PQ_B * wb + j] = 0;
         for (int lv = 0; lv + 1 < L; ++lv) tb[(size_t)lv * PQ_B] = 0.f;
+        for (int lv = 0; lv < L; ++lv) sbp[(size_t)lv * PQ_B] = 0.f;
         ids[b * PQ_B + sl] = -1;
         return;
     }
@@ -190,57 +193,38 @@ __global__ __launch_bounds__(256) void k_pq_pack(PqGeom g, const uint8_t *__rest
     atomicMax(reinterpret_cast<int *>(list_b0max + l), __float_as_int((float)sqrt(suffix) * (1.f + 0x1p-20f)));
     for (int lv = 0; lv < L; ++lv)
         for (int j = 0; j < wb; ++j) cb[(size_t)lv * PQ_B * wb + j] = j < ml ? cr[lv * ml + j] : 0;
+    // per level: the sum over its codes of ||C||^2 + 2 <y_c, C> (FP64, one rounding)
+    const int dsub = g.dsub;
+    const double *yl = yc + (int64_t)l * g.d;
+    for (int lv = 0; lv < L; ++lv) {
+        double acc = 0.0;
+        for (int m = lv * ml; m < (lv + 1) * ml; ++m) {
+            const float *cw = cbook + ((size_t)m * 256 + cr[m]) * dsub;
+            for (int j = 0; j < dsub; ++j) acc += (double)cw[j] * ((double)cw[j] + 2.0 * yl[m * dsub + j]);
+        }
+        sbp[(size_t)lv * PQ_B] = (float)acc;
+    }
     (void)M;
     ids[b * PQ_B + sl] = (int32_t)row;
 }
 
-// ---------------------------------------------------------------- table terms
-// The table entry of list l splits as ||z_m||^2 + T1[l][m][c] + T2[q][m][c]
-// with T1 = ||C_mc||^2 + 2 <y_c(l)_m, C_mc> (per list, built once) and
-// T2 = -2 <y_m, C_mc> (per query); each term is an FP64 sum rounded to FP32.
-__global__ __launch_bounds__(256) void k_pq_t1(const double *__restrict__ yc, int64_t nlist, int M, int dsub,
-                                               const float *__restrict__ cb, float *__restrict__ t1)
-{
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= nlist * M * 256) return;
-    const int64_t l = e / (M * 256);
-    const int ee = (int)(e - l * M * 256), m = ee >> 8;
-    const float *cw = cb + (size_t)ee * dsub;
-    const double *y = yc + l * (int64_t)M * dsub + m * dsub;
-    double nn = 0.0, dot = 0.0;
-    for (int j = 0; j < dsub; ++j) {
-        nn += (double)cw[j] * cw[j];
-        dot += y[j] * cw[j];
-    }
-    t1[e] = (float)(nn + 2.0 * dot);
-}
-
-__global__ __launch_bounds__(256) void k_pq_t2(const double *__restrict__ yq, int64_t nq, int M, int dsub,
-                                               const float *__restrict__ cb, float *__restrict__ t2)
-{
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= nq * M * 256) return;
-    const int64_t q = e / (M * 256);
-    const int ee = (int)(e - q * M * 256), m = ee >> 8;
-    const float *cw = cb + (size_t)ee * dsub;
-    const double *y = yq + q * (int64_t)M * dsub + m * dsub;
-    double dot = 0.0;
-    for (int j = 0; j < dsub; ++j) dot += y[j] * cw[j];
-    t2[e] = (float)(-2.0 * dot);
-}
-
 // ---------------------------------------------------------------- the scan
+// A table entry splits as ||z_m - C||^2 = ||z_m||^2 + (||C||^2 + 2 <y_c, C>)
+// - 2 <y_m, C> with z = y - y_c(list).  The middle term, summed over a
+// level's sub-quantizers, depends on the stored vector alone and is kept per
+// slot and level (sx); the last is the query's table, built once per query
+// in LDS; the first is the residual's energy per level.  A level's
+// contribution is zl + sx + the level's table look-ups.
 struct PqScan {
     PqGeom g;
     int64_t nq;
-    int k, np_max, cap, waves, nlr;  // nlr: lists whose tables share LDS in one round
+    int k, np_max, cap, waves, nlr;  // nlr: probed lists whose constants share LDS in one round
     float eps;
     float g_part;  // relative error of an FP32 partial sum of table entries
     float g_adc;   // |canonical - FP32 sum| <= g_adc * FP32 sum
     const double *y;   // [nq][d] the queries in the shaped frame
     const double *yc;  // [nlist][d] the list centroids in the shaped frame
-    const float *t1;   // [nlist][M][256] list terms of the tables
-    const float *t2;   // [nq][M][256] query terms of the tables
+    const float *sx;   // [nblocks][L][256] per slot and level: sum of ||C||^2 + 2 <y_c, C> over its codes
     const float *ycn;  // [nlist] ||y_c(l)||
     const float *b0max;  // [nlist] the largest reconstruction norm of each list
     const float *codebooks;
@@ -256,36 +240,6 @@ struct PqScan {
     float *out_d;
     unsigned long long *stats;  // [0] look-ups, [1] candidates, [2] overflowed queries, [3] bytes of codes and tails read
 };
-
-// Table entry (m, c) from a residual z staged in LDS (FP64) and the codeword
-// cw: float32 of the sequential FP64 sum over the sub-vector of
-// (z_j - cw_j)^2 (DS = dsub, unrolled so the codeword's loads issue together).
-template <int DS>
-__device__ __forceinline__ float pq_entry_z(const double *__restrict__ z, const float *__restrict__ cw)
-{
-#pragma clang fp contract(off)
-    float c[DS];
-#pragma unroll
-    for (int j = 0; j < DS; ++j) c[j] = cw[j];
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < DS; ++j) {
-        const double t = z[j] - (double)c[j];
-        const double t2 = t * t;
-        s = s + t2;
-    }
-    return (float)s;
-}
-
-template <int DS>
-__device__ void pq_build_tables(float *__restrict__ luts, const double *__restrict__ zs, int nl, int M, int d,
-                                const float *__restrict__ codebooks)
-{
-    for (int e = threadIdx.x; e < nl * M * 256; e += blockDim.x) {
-        const int li = e / (M * 256), ee = e - li * M * 256;
-        luts[e] = pq_entry_z<DS>(zs + (size_t)li * d + (ee >> 8) * DS, codebooks + (size_t)ee * DS);
-    }
-}
 
 // Table entry (m, c) of the residual query z = y - y_c(list): float32 of the
 // sequential FP64 sum over the sub-vector of (z_j - C[m][c][j])^2.
@@ -319,6 +273,52 @@ __device__ __forceinline__ float pq_canonical(const PqScan &a, const double *yq,
         const int c = cs[(size_t)lv * PQ_B * wb + (m - lv * ml)];
         s = s + (double)pq_entry(yq, yl, a.codebooks + ((size_t)m * 256 + c) * dsub, m, dsub);
     }
+    return (float)s;
+}
+
+// The same canonical distance computed by a whole wavefront (every lane gets
+// it): lane t takes sub-quantizers t and t + 64 (their entries by the same
+// recipe, four coordinates' loads issued together), then the entries are
+// added in sub-quantizer order in FP64 through lane broadcasts.
+__device__ __forceinline__ float pq_canonical_wave(const PqScan &a, const double *yq, int64_t slot, int lane)
+{
+#pragma clang fp contract(off)
+    const int M = a.g.M, d = a.g.d, ml = a.g.ml, wb = 4 * a.g.mw, dsub = a.g.dsub;
+    const int64_t b = slot / PQ_B;
+    const double *yl = a.yc + (int64_t)a.block_list[b] * d;
+    const uint8_t *cs = a.codes + (size_t)b * a.g.L * PQ_B * wb + (size_t)(slot % PQ_B) * wb;
+    auto entry = [&](int m) -> float {
+        if (m >= M) return 0.f;
+        const int lv = m / ml;
+        const int c = cs[(size_t)lv * PQ_B * wb + (m - lv * ml)];
+        const float *cw = a.codebooks + ((size_t)m * 256 + c) * dsub;
+        double s = 0.0;
+        for (int j0 = 0; j0 < dsub; j0 += 4) {
+            double yv[4], lv2[4];
+            float cv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int jj = min(j0 + j, dsub - 1);
+                yv[j] = yq[m * dsub + jj];
+                lv2[j] = yl[m * dsub + jj];
+                cv[j] = cw[jj];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j0 + j < dsub) {
+                    const double z = yv[j] - lv2[j];
+                    const double t = z - (double)cv[j];
+                    const double t2 = t * t;
+                    s = s + t2;
+                }
+            }
+        }
+        return (float)s;
+    };
+    const float e0 = entry(lane);
+    const float e1 = entry(lane + 64);
+    double s = 0.0;
+    for (int m = 0; m < M; ++m) s = s + (double)__shfl(m < 64 ? e0 : e1, m & 63, 64);
     return (float)s;
 }
 
@@ -362,41 +362,90 @@ __device__ __noinline__ int pq_wave_trim(uint64_t *wb, int wc, int cap, int k, f
     return keep;
 }
 
-// One workgroup per query.  The probed lists are taken in probe order, nlr at
-// a time: their tables (one per list: the query's residual against the list
-// centroid) are built in LDS, then the wavefronts take quarter blocks (64
-// slots, one per lane) of those lists from a shared counter and run the
-// level loop: a level's table entries are summed in FP32, the bound is
-// checked against the shared threshold, and a wavefront stops once no slot
-// is alive.  Survivors that may reach the answer go to the wavefront's LDS
-// buffer.  At the end every buffered entry that may reach the answer is
-// rescored canonically and the k smallest (distance, id) keys are written.
+// One workgroup per query.  Its table (-2 <y_m, C_mc>, FP64 then rounded) is
+// built once in LDS; the probed lists are taken nlr at a time: their
+// residual energies per level, tail norms and error bounds go to LDS, then
+// the wavefronts take quarter blocks (64 slots, one per lane) of those lists
+// from a shared counter and run the level loop: a level's terms are summed in
+// FP32, the bound is checked against the shared threshold, and a wavefront
+// stops once no slot is alive.  Survivors that may reach the answer go to the
+// wavefront's LDS buffer.  At the end every buffered entry that may reach
+// the answer is rescored canonically and the k smallest (distance, id) keys
+// are written.
+// The query's table -2 <y_m, C_mc> (FP64 dots, rounded once) in LDS: each
+// thread keeps one sub-vector y_m in registers and takes a run of codewords,
+// four at a time with their loads issued together.
+template <int DS>
+__device__ void pq_query_table(float *__restrict__ lut, const double *__restrict__ yq,
+                               const float *__restrict__ cb, int M, int tid, int nt)
+{
+    const int tpm = max(1, nt / M);  // threads per sub-quantizer
+    const int per = (256 + tpm - 1) / tpm;
+    for (int slot = tid; slot < M * tpm; slot += nt) {
+        const int m = slot / tpm, c0 = (slot - m * tpm) * per, c1 = min(256, c0 + per);
+        double y[DS];
+#pragma unroll
+        for (int j = 0; j < DS; ++j) y[j] = yq[m * DS + j];
+        for (int c = c0; c < c1; c += 4) {
+            float w[4][DS];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int cc = min(c + u, c1 - 1);
+#pragma unroll
+                for (int j = 0; j < DS; ++j) w[u][j] = cb[((size_t)m * 256 + cc) * DS + j];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                double dot = 0.0;
+#pragma unroll
+                for (int j = 0; j < DS; ++j) dot += y[j] * (double)w[u][j];
+                if (c + u < c1) lut[m * 256 + c + u] = (float)(-2.0 * dot);
+            }
+        }
+    }
+}
+
+// One level's look-ups of a slot: the codes of its ml sub-quantizers packed
+// in MW 32-bit words, against the level's slice of the table.
+template <int MW>
+__device__ __forceinline__ float pq_level_sum(const float *__restrict__ lm, const uint32_t (&wv)[MW], int ml, float p)
+{
+#pragma unroll
+    for (int u = 0; u < MW; ++u) {
+        const uint32_t x = wv[u];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (4 * u + e < ml) p += lm[(4 * u + e) * 256 + ((x >> (8 * e)) & 255u)];
+    }
+    return p;
+}
+
 template <bool PRUNE, int MW>
 __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
 {
     extern __shared__ __align__(16) char sm[];
     const int M = a.g.M, L = a.g.L, d = a.g.d, dsub = a.g.dsub, nlr = a.nlr;
-    float *luts = reinterpret_cast<float *>(sm);                                  // [nlr][M][256]
-    uint64_t *wbuf = reinterpret_cast<uint64_t *>(luts + (size_t)nlr * M * 256);  // [waves][cap]
-    float *qa = reinterpret_cast<float *>(wbuf + (size_t)a.waves * a.cap);        // [nlr][L]
-    double *e2 = reinterpret_cast<double *>(qa + (size_t)nlr * L + ((nlr * L) & 1));  // [nlr][L]
-    double *zs = e2 + (size_t)nlr * L;                                          // [nlr][d]
-    float *zn = reinterpret_cast<float *>(zs + (size_t)nlr * d);                 // [nlr][M]
-    float *dl = zn + (size_t)nlr * M;                                            // [nlr]
+    float *lut = reinterpret_cast<float *>(sm);                                   // [M][256]
+    uint64_t *wbuf = reinterpret_cast<uint64_t *>(lut + (size_t)M * 256);         // [waves][cap]
+    double *e2 = reinterpret_cast<double *>(wbuf + (size_t)a.waves * a.cap);     // [nlr][L]
+    int64_t *rb0 = reinterpret_cast<int64_t *>(e2 + (size_t)nlr * L);            // [nlr]
+    float *zl = reinterpret_cast<float *>(rb0 + nlr);                            // [nlr][L]
+    float *qa = zl + (size_t)nlr * L;                                            // [nlr][L]
+    float *dl = qa + (size_t)nlr * L;                                            // [nlr]
     int32_t *rpref = reinterpret_cast<int32_t *>(dl + nlr);                     // [nlr + 1]
-    int32_t *rlist = rpref + nlr + 1;                                            // [nlr]
+    int32_t *rnb = rpref + nlr + 1;                                              // [nlr]
     __shared__ unsigned thr, dmax;
     __shared__ float ynorm;
     __shared__ double ysq[16];
     __shared__ int task, ovf;
     __shared__ int wcount[16];
     const int64_t qi = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nt = blockDim.x;
     const int k = a.k;
     int64_t *oi = a.out_ids + qi * k;
     float *od = a.out_d + qi * k;
     if (a.qflags[qi] & FLAG_NONFINITE) {
-        for (int r = tid; r < k; r += blockDim.x) {
+        for (int r = tid; r < k; r += nt) {
             oi[r] = -1;
             od[r] = INFINITY;
         }
@@ -410,16 +459,23 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
         ovf = 0;
     }
     {
-        // ||y|| (for the error bound of the split tables)
+        // the query's table, and ||y|| (for the error bound)
+        switch (dsub) {
+        case 1: pq_query_table<1>(lut, yq, a.codebooks, M, tid, nt); break;
+        case 2: pq_query_table<2>(lut, yq, a.codebooks, M, tid, nt); break;
+        case 4: pq_query_table<4>(lut, yq, a.codebooks, M, tid, nt); break;
+        case 8: pq_query_table<8>(lut, yq, a.codebooks, M, tid, nt); break;
+        default: pq_query_table<16>(lut, yq, a.codebooks, M, tid, nt); break;
+        }
         double s = 0.0;
-        for (int j = tid; j < d; j += blockDim.x) s += yq[j] * yq[j];
+        for (int j = tid; j < d; j += nt) s += yq[j] * yq[j];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
         if (lane == 0) ysq[w] = s;
         __syncthreads();
         if (tid == 0) {
             double t = 0.0;
-            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += ysq[i];
+            for (int i = 0; i < (nt >> 6); ++i) t += ysq[i];
             ynorm = (float)(sqrt(t) * (1.0 + 1e-6));
         }
     }
@@ -428,74 +484,27 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
     int wc = 0;
     unsigned long long looks = 0, cands = 0, bytes = 0;
     const float g_adc = a.g_adc;
+    const int ml = a.g.ml;
     for (int r0 = 0; r0 < np; r0 += nlr) {
         const int nl = min(nlr, np - r0);
-        __syncthreads();  // the previous round's tables are no longer read
-        if (tid < nl) rlist[tid] = a.probes[qi * a.np_max + r0 + tid];
+        __syncthreads();  // the previous round's constants are no longer read
         if (tid == 0) task = 0;
-        __syncthreads();
-        // the residuals of this round's lists, then their tables and level energies
-        for (int e = tid; e < nl * d; e += blockDim.x) {
-            const int li = e / d, j = e - li * d;
-            zs[e] = yq[j] - a.yc[(int64_t)rlist[li] * d + j];
-        }
-        __syncthreads();
-        for (int e = tid; e < nl * M; e += blockDim.x) {
-            const int li = e / M, m = e - li * M;
-            const double *z = zs + (size_t)li * d + m * dsub;
-            double s = 0.0;
-            for (int j = 0; j < dsub; ++j) s += z[j] * z[j];
-            zn[e] = (float)s;
-        }
-        __syncthreads();
-        // tables: (||z_m||^2 + T1) + T2 in FP32, four entries per thread per step
-        {
-            // four float4 of each term in flight per thread
-            const float4 *t2q = reinterpret_cast<const float4 *>(a.t2 + (size_t)qi * M * 256);
-            const int n4 = M * 64, tot = nl * n4, nt = blockDim.x;
-            for (int e0 = tid; e0 < tot; e0 += 4 * nt) {
-                float4 u1[4], u2[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int e = e0 + u * nt;
-                    if (e < tot) {
-                        const int li = e / n4, e4 = e - li * n4;
-                        u1[u] = reinterpret_cast<const float4 *>(a.t1 + (size_t)rlist[li] * M * 256)[e4];
-                        u2[u] = t2q[e4];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int e = e0 + u * nt;
-                    if (e < tot) {
-                        const int li = e / n4, e4 = e - li * n4;
-                        const float z2 = zn[li * M + (e4 >> 6)];
-                        float4 o;
-                        o.x = (z2 + u1[u].x) + u2[u].x;
-                        o.y = (z2 + u1[u].y) + u2[u].y;
-                        o.z = (z2 + u1[u].z) + u2[u].z;
-                        o.w = (z2 + u1[u].w) + u2[u].w;
-                        reinterpret_cast<float4 *>(luts + (size_t)li * M * 256)[e4] = o;
-                    }
-                }
-            }
-        }
-        for (int e = tid; e < nl * L; e += blockDim.x) {
+        // the residual z = y - y_c(list): its energy per level, in FP64
+        for (int e = tid; e < nl * L; e += nt) {
             const int li = e / L, lv = e - li * L;
-            const double *z = zs + (size_t)li * d;
+            const double *yl = a.yc + (int64_t)a.probes[qi * a.np_max + r0 + li] * d;
             double s = 0.0;
-            for (int j = a.g.cut[lv]; j < a.g.cut[lv + 1]; ++j) s += z[j] * z[j];
-            e2[e] = s;
-        }
-        if (tid == 0) {
-            // quarter blocks of the round's lists, as an exclusive prefix
-            int run = 0;
-            for (int li = 0; li < nl; ++li) {
-                rpref[li] = run;
-                const int l = rlist[li];
-                run += 4 * (int)(a.list_blk[l + 1] - a.list_blk[l]);
+            for (int j = a.g.cut[lv]; j < a.g.cut[lv + 1]; ++j) {
+                const double z = yq[j] - yl[j];
+                s += z * z;
             }
-            rpref[nl] = run;
+            e2[e] = s;
+            zl[e] = (float)s;
+        }
+        if (tid < nl) {
+            const int l = a.probes[qi * a.np_max + r0 + tid];
+            rb0[tid] = a.list_blk[l];
+            rnb[tid] = (int)(a.list_blk[l + 1] - a.list_blk[l]);
         }
         __syncthreads();
         if (tid < nl) {
@@ -506,15 +515,25 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
                 qa[tid * L + lv - 1] = (float)sqrt(acc);
             }
             acc += e2[tid * L];
-            // the error of a distance summed from the split tables: each entry
-            // within 3u (||z_m||^2 + |T1| + |T2|) of the direct one; by
-            // Cauchy-Schwarz the sum over a candidate's entries is at most
-            // ||z||^2 + b^2 + 2 (||y_c|| + ||y||) b with b its reconstruction norm
-            const int l = rlist[tid];
+            // the error of a distance summed from the split terms: each term is
+            // an FP64 value rounded once and the FP32 sum runs over M + 2 L
+            // terms; the terms' magnitudes sum to at most ||z||^2 + b^2 +
+            // 2 (||y_c|| + ||y||) b (Cauchy-Schwarz), b the reconstruction norm
+            const int l = a.probes[qi * a.np_max + r0 + tid];
             const double b = a.b0max[l];
-            const float dlv = (float)(4.0 * 0x1p-24 * (acc + b * b + 2.0 * ((double)a.ycn[l] + ynorm) * b) * 1.01);
+            const double S = acc + b * b + 2.0 * ((double)a.ycn[l] + ynorm) * b;
+            const float dlv = (float)((M + 2 * L + 8) * 1.1 * 0x1p-24 * S);
             dl[tid] = dlv;
             atomicMax(&dmax, __float_as_uint(dlv));
+        }
+        if (tid == 0) {
+            // quarter blocks of the round's lists, as an exclusive prefix
+            int run = 0;
+            for (int li = 0; li < nl; ++li) {
+                rpref[li] = run;
+                run += 4 * rnb[li];
+            }
+            rpref[nl] = run;
         }
         __syncthreads();
         const int ntask = rpref[nl];
@@ -525,32 +544,30 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
             if (t >= ntask) break;
             int li = 0;
             while (li + 1 < nl && rpref[li + 1] <= t) ++li;
-            const int l = rlist[li];
-            const int64_t b = a.list_blk[l] + (t - rpref[li]) / 4;
+            const int64_t b = rb0[li] + (t - rpref[li]) / 4;
             const int slot = ((t - rpref[li]) & 3) * 64 + lane;
-            const int cnt = a.blk_cnt[b];
-            if (__ballot(slot < cnt) == 0) continue;  // an empty quarter of the last block
-            bool alive = slot < cnt;
+            bool alive = a.ids[b * PQ_B + slot] >= 0;  // empty slots hold id -1
             cands += alive ? 1ull : 0ull;
             float p = 0.f;
-            const float *lut = luts + (size_t)li * M * 256;
             const float *qal = qa + li * L;
+            const float *zll = zl + li * L;
             const float dlv = dl[li];
-            // this slot's codes, level by level (MW words each): the words and
-            // tail norms of CH levels are requested together, then summed
-            constexpr int CH = MW == 1 ? 12 : 12 / MW;
+            // this slot's codes, level by level (MW words each), its level terms
+            // and tail norms: those of CH levels are requested together
+            constexpr int CH = MW == 1 ? 8 : 12 / MW;
             const uint32_t *cw = reinterpret_cast<const uint32_t *>(a.codes) + ((size_t)b * L * PQ_B + slot) * MW;
             const float *tb = a.tails + (size_t)b * (L - 1) * PQ_B + slot;
-            const int ml = a.g.ml;
+            const float *sb = a.sx + (size_t)b * L * PQ_B + slot;
             for (int l0 = 0; l0 < L; l0 += CH) {
                 if (PRUNE && __ballot(alive) == 0) break;
                 uint32_t cv[CH][MW];
-                float tv[CH];
+                float tv[CH], sv[CH];
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     const int lv = l0 + c;
 #pragma unroll
                     for (int u = 0; u < MW; ++u) cv[c][u] = lv < L ? cw[(size_t)lv * PQ_B * MW + u] : 0u;
+                    sv[c] = lv < L ? sb[(size_t)lv * PQ_B] : 0.f;
                     tv[c] = (PRUNE && lv + 1 < L) ? tb[(size_t)lv * PQ_B] : 0.f;
                 }
 #pragma unroll
@@ -558,26 +575,25 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
                     const int lv = l0 + c;
                     if (lv < L && alive) {
                         looks += (unsigned long long)ml;
-                        const float *lm = lut + (size_t)lv * ml * 256;
-#pragma unroll
-                        for (int j = 0; j < 4 * MW; ++j)
-                            if (j < ml) p += lm[j * 256 + ((cv[c][j >> 2] >> (8 * (j & 3))) & 255u)];
+                        p += zll[lv];
+                        p += sv[c];
+                        p = pq_level_sum<MW>(lut + (size_t)lv * ml * 256, cv[c], ml, p);
                         if (PRUNE && lv + 1 < L) {
-                            const float T = __uint_as_float(*(volatile unsigned *)&thr);
+                            const float T = __uint_as_float(__hip_atomic_load(&thr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
                             if (pq_lower_bound(p, qal[lv], tv[c], a.eps, a.g_part, dlv) > T) alive = false;
                         }
                     }
                 }
                 if (lane == 0) {
                     const int nlv = min(CH, L - l0);
-                    bytes += (unsigned long long)(nlv * 64 * 4 * MW + (PRUNE ? 256 * min(nlv, L - 1 - l0) : 0));
+                    bytes += (unsigned long long)(nlv * 64 * (4 * MW + 4) + (PRUNE ? 256 * min(nlv, L - 1 - l0) : 0));
                 }
             }
             // commit a candidate that may reach the answer; its key is an
             // upper bound on its canonical distance
-            const float T = __uint_as_float(*(volatile unsigned *)&thr);
+            const float T = __uint_as_float(__hip_atomic_load(&thr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
             const float up = p * (1.f + g_adc) + dlv;
-            const float dm = __uint_as_float(*(volatile unsigned *)&dmax);
+            const float dm = __uint_as_float(__hip_atomic_load(&dmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
             const bool has = alive && up - 2.f * (g_adc * up + dm) <= T;
             const uint64_t bm = __ballot(has);
             if (bm == 0) continue;
@@ -593,7 +609,7 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
             wc += nn;
         }
     }
-    const float dmf = __uint_as_float(*(volatile unsigned *)&dmax);
+    const float dmf = __uint_as_float(__hip_atomic_load(&dmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
     wc = pq_wave_trim(wb, wc, cap, k, g_adc, dmf, &thr, lane);
     if (lane == 0) wcount[w] = wc;
 #pragma unroll
@@ -615,25 +631,35 @@ __global__ __launch_bounds__(1024) void k_pq_scan(PqScan a)
         }
         return;
     }
-    // canonical distances of every entry that may reach the answer
+    // canonical distances of every entry that may reach the answer: each
+    // wavefront rescores its own buffer, one entry at a time (the buffer is
+    // sorted, so the entries that qualify come first)
     const float T = __uint_as_float(thr);
     const int tot = a.waves * cap;
-    for (int i = tid; i < tot; i += blockDim.x) {
-        const int ww = i / cap, r = i - ww * cap;
-        uint64_t key = KEY_MAX;
-        if (r < wcount[ww]) {
-            const uint64_t e = wbuf[i];
-            const float up = key_dist(e);
-            if (up - 2.f * (g_adc * up + dmf) <= T) {
-                const int32_t slot = key_id(e);
-                key = make_key(pq_canonical(a, yq, slot), a.ids[slot]);
+    {
+        const int n_w = wcount[w];
+        for (int r = 0; r < cap; ++r) {
+            uint64_t key = KEY_MAX;
+            if (r < n_w) {
+                const uint64_t e = wb[r];
+                const float up = key_dist(e);
+                if (up - 2.f * (g_adc * up + dmf) <= T) {
+                    const int32_t slot = key_id(e);
+                    key = make_key(pq_canonical_wave(a, yq, slot, lane), a.ids[slot]);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) wb[r] = key;
+            __builtin_amdgcn_wave_barrier();
+            if (r >= n_w) {
+                for (int i = r + lane; i < cap; i += 64) wb[i] = KEY_MAX;
+                break;
             }
         }
-        wbuf[i] = key;
     }
     __syncthreads();
     block_bitonic_sort(wbuf, tot);
-    for (int r = tid; r < k; r += blockDim.x) {
+    for (int r = tid; r < k; r += nt) {
         const uint64_t e = wbuf[r];
         if (e == KEY_MAX) {
             oi[r] = -1;
@@ -833,11 +859,7 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
     }
     ix->codebooks.alloc(sizeof(float) * C.size());
     PANO_HIP(hipMemcpyAsync(ix->codebooks.p, C.data(), sizeof(float) * C.size(), hipMemcpyHostToDevice, s));
-    // list terms of the query tables
-    ix->t1.alloc(sizeof(float) * (size_t)nlist * M * 256);
-    hipLaunchKernelGGL(k_pq_t1, dim3((unsigned)(((int64_t)nlist * M * 256 + 255) / 256)), dim3(256), 0, s,
-                       ix->yc64.as<double>(), (int64_t)nlist, M, dsub, ix->codebooks.as<float>(), ix->t1.as<float>());
-    PANO_HIP(hipGetLastError());
+
     // encode every row, in chunks
     ix->codes_row.alloc((size_t)n * M);
     {
@@ -907,13 +929,15 @@ void run_pq_build(pano_ctx *ctx, pano_pq_index *ix, const pano_transform *tf, co
     ix->ids.alloc(sizeof(int32_t) * slots);
     ix->blk_cnt.alloc(sizeof(int32_t) * std::max<int64_t>(1, ix->nblocks));
     ix->b0max.alloc(sizeof(float) * nlist);
+    ix->sx.alloc(sizeof(float) * slots * L);
     PANO_HIP(hipMemsetAsync(ix->b0max.p, 0, sizeof(float) * nlist, s));
     if (ix->nblocks > 0) {
         hipLaunchKernelGGL(k_pq_pack, dim3((unsigned)((ix->nblocks * PQ_B + 255) / 256)), dim3(256), 0, s, geom_of(ix),
                            ix->codes_row.as<uint8_t>(), cwe_d.as<double>(), perm_d.as<int64_t>(),
                            start_d.as<int64_t>(), ix->list_blk_d.as<int64_t>(), block_list_d.as<int32_t>(),
                            ix->nblocks, ix->codes.as<uint8_t>(), ix->tails.as<float>(), ix->ids.as<int32_t>(),
-                           ix->blk_cnt.as<int32_t>(), ix->b0max.as<float>());
+                           ix->blk_cnt.as<int32_t>(), ix->b0max.as<float>(), ix->yc64.as<double>(),
+                           ix->codebooks.as<float>(), ix->sx.as<float>());
         PANO_HIP(hipGetLastError());
     }
     ix->cent.alloc(sizeof(float) * ((size_t)nlist * d + nlist));
@@ -952,18 +976,18 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     // (with their tail norms) as fit
     int cap = 1;
     while (cap < k + 96) cap <<= 1;
-    const size_t per_list = (size_t)M * 256 * 4 + (size_t)L * 12 + (size_t)d * 8 + (size_t)M * 4 + 16;
-    const size_t budget = (size_t)PQ_LDS - 2048 - 64;
+    const size_t per_list = (size_t)L * 16 + 24;
+    const size_t budget = (size_t)PQ_LDS - 2048 - 64 - (size_t)M * 256 * 4;
     int waves = 16;
     while (waves > 2 && (size_t)waves * cap * 8 + per_list > budget) waves >>= 1;
     PANO_REQUIRE((size_t)waves * cap * 8 + per_list <= budget, "k and M too large for the PQ scan's LDS");
-    const int nlr = (int)std::min<size_t>({(budget - (size_t)waves * cap * 8) / per_list, (size_t)np_max, (size_t)16});
-    const size_t scan_shm = (size_t)waves * cap * 8 + (size_t)nlr * per_list + 64;
+    const int nlr = (int)std::min<size_t>({(budget - (size_t)waves * cap * 8) / per_list, (size_t)np_max, (size_t)128});
+    const size_t scan_shm = (size_t)M * 256 * 4 + (size_t)waves * cap * 8 + (size_t)nlr * per_list + 64;
     // scratch
     const size_t nS = nlist > 1 ? aup(sizeof(float) * nq * nlist) : 256;
     const size_t nP = aup(sizeof(int32_t) * nq * np_max) + aup(sizeof(int32_t) * nq) + aup(sizeof(int32_t) * nlist) +
                       aup(sizeof(float) * nq) + aup(sizeof(int32_t) * nq) + aup(sizeof(unsigned long long) * 4);
-    const size_t nY = aup(sizeof(double) * nq * d) + aup(sizeof(float) * nq * M * 256);
+    const size_t nY = aup(sizeof(double) * nq * d);
     const int64_t s_np = ix->top_blk_prefix[std::min<int64_t>(np_max, nlist)];
     const size_t nK = aup(sizeof(uint64_t) * std::max<int64_t>(1, s_np * PQ_B));
     ctx->scratch[5].ensure(nS);
@@ -979,7 +1003,6 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     int32_t *qflags = cp.take<int32_t>(nq);
     unsigned long long *stats = cp.take<unsigned long long>(4);
     double *y = ctx->scratch[7].as<double>();
-    float *t2 = reinterpret_cast<float *>(reinterpret_cast<char *>(ctx->scratch[7].p) + aup(sizeof(double) * nq * d));
     uint64_t *keys = ctx->scratch[8].as<uint64_t>();
     hipStream_t ws = ctx->work_stream();
     PANO_HIP(hipEventRecord(ctx->ev_in, s));
@@ -992,9 +1015,6 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
                          nprobe_all, np_max, probes, npq, list_cnt, qn2, ws);
     hipLaunchKernelGGL(k_pq_yseq, dim3((unsigned)((d + 63) / 64), (unsigned)((nq + 63) / 64)), dim3(256), 0, ws, q, nq,
                        d, ix->Tt64.as<double>(), ix->mu64.as<double>(), y, qflags);
-    PANO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_pq_t2, dim3((unsigned)((nq * M * 256 + 255) / 256)), dim3(256), 0, ws, y, nq, M, ix->dsub,
-                       ix->codebooks.as<float>(), t2);
     PANO_HIP(hipGetLastError());
     PqScan a{};
     a.g = geom_of(ix);
@@ -1010,8 +1030,7 @@ void run_pq_search(pano_ctx *ctx, pano_pq_index *ix, const float *q, int64_t nq,
     a.g_adc = (float)((4.0 * (M + 2) + 2.0) * u);
     a.y = y;
     a.yc = ix->yc64.as<double>();
-    a.t1 = ix->t1.as<float>();
-    a.t2 = t2;
+    a.sx = ix->sx.as<float>();
     a.ycn = ix->ycn.as<float>();
     a.b0max = ix->b0max.as<float>();
     a.block_list = ix->block_list.as<int32_t>();
