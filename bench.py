@@ -38,7 +38,7 @@ def log(*a):
 
 def scan_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("k_search.hip", "search_common.h"):
+    for f in ("k_search.hip", "k_pq.hip", "search_common.h"):
         with open(os.path.join(ROOT, "paper_2510_00566_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -485,7 +485,8 @@ def pq_measure(name: str, args, ctx) -> dict:
         rec[tag] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
                     "kernel": "k_pq_scan", "bytes_per_launch": float(s_["scan_bytes"]), "ms_per_launch": s_["ms_scan"],
                     "lds_lookup_GBs": lds, "lds_peak_GBs": PEAK_LDS_GBS, "lds_frac": lds / PEAK_LDS_GBS,
-                    "lookups_per_launch": s_["lookups"], "traffic": None}
+                    "lookups_per_launch": s_["lookups"],
+                    "traffic": traffic_from_profiles("k_pq_scan" if tag == "roofline" else "k_pq_scan_brute", name)}
     if args.parity_sample > 0:
         rs = np.random.Generator(np.random.PCG64(4242))
         sample = np.sort(rs.choice(w.nq, size=min(args.parity_sample, w.nq), replace=False))
@@ -498,6 +499,30 @@ def pq_measure(name: str, args, ctx) -> dict:
         ei, _, _ = brute.knn_ivf(q[sample], x, c_np, a_np, w.nprobe, w.k)
         rec["recall_at_k_vs_exact"] = recall_at_k(gi, ei)
         log(f"[bench] {name}: parity {rec['parity']} recall@{w.k} {rec['recall_at_k_vs_exact']:.4f}")
+    if args.pq_kappas:
+        # Section 4.2's cap: per kappa a new shaped transform and quantizer on
+        # the same lists; phi, QPS and recall against the exact answer
+        sweep = []
+        rs = np.random.Generator(np.random.PCG64(4242))
+        sample = np.sort(rs.choice(w.nq, size=min(max(args.parity_sample, 16), w.nq), replace=False))
+        ei, _, _ = brute.knn_ivf(q[sample], x, c_np, a_np, w.nprobe, w.k)
+        for kap in [float(v) for v in args.pq_kappas.split(",") if v]:
+            idx.free()
+            tf_k = pca.shape(cuts, kap, isotropize=True, seed=w.cfg_id)
+            idx = PQIndex.build(ctx, tf_k, xd, cent, assign, cuts, w.pq_dsub, iters=10, sample=65536, seed=w.cfg_id)
+            el_k = timed(lambda: idx.search(qd, w.k, nprobe=w.nprobe, out=(ids, dd)), args.steps, 1)
+            elb_k = timed(lambda: idx.search(qd, w.k, nprobe=w.nprobe, brute=True, out=(bi, bd)), max(3, args.steps // 2), 1)
+            idx.search(qd, w.k, nprobe=w.nprobe, stats=True, out=(ids, dd))
+            st_k = idx.stats()
+            _, _, lam_k, _ = tf_k.get()
+            cut_e = [float(np.sum(lam_k[cuts[i]:cuts[i + 1]])) for i in range(len(cuts) - 1)]
+            ent = {"kappa": kap, "qps": w.nq * args.steps / el_k, "speedup_vs_bruteforce":
+                   (w.nq * args.steps / el_k) / (w.nq * max(3, args.steps // 2) / elb_k), "phi": st_k["phi"],
+                   "recall_at_k_vs_exact": recall_at_k(ids.cpu().numpy()[sample], ei),
+                   "level_energy_first_last": [cut_e[0], cut_e[-1]]}
+            log(f"[bench] {name}: kappa sweep {ent}")
+            sweep.append(ent)
+        rec["kappa_sweep"] = sweep
     idx.free()
     del xd, qd
     torch.cuda.empty_cache()
@@ -642,6 +667,7 @@ def main():
     ap.add_argument("--pq-workloads", default="ivfpq_gist_like",
                     help="comma-separated IVFPQ workloads measured last ('' for none)")
     ap.add_argument("--pq-only", action="store_true", help="measure only the IVFPQ workloads")
+    ap.add_argument("--pq-kappas", default="", help="IVFPQ: comma-separated kappa values to sweep (Section 4.2)")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of N (smoke runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bruteforce", action="store_true")

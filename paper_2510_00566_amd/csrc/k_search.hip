@@ -1707,11 +1707,12 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
             const uint16_t *blk16 = BF ? ix.levels16 + gb * (int64_t)g.B * g.d_pad : nullptr;
             const float *tl = ix.tails + gb * (int64_t)g.B * L;
             for (int slot0 = 0; slot0 < cnt; slot0 += 64) {
-                // ---- thresholds: the queries' current d_k
-                if (lane < ng)
-                    thr_w[lane] = fminf(thr_w[lane],
-                                        __hip_atomic_load(&wk.thr[qid_w[lane]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                wave_sync();
+                // ---- thresholds: the queries' current d_k, requested now and
+                // published to the wave's copy once the step's level-1 products
+                // are done (the load overlaps the tile loads)
+                const float thr_new =
+                    lane < ng ? __hip_atomic_load(&wk.thr[qid_w[lane]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : INFINITY;
                 float tb0[4], tb1[4];
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
@@ -1822,6 +1823,8 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                         if (T > 2) products(xa0, qa[2]);
                         if (T > 3) products(xa1, qa[3]);
                     }
+                    if (lane < ng) thr_w[lane] = fminf(thr_w[lane], thr_new);
+                    wave_sync();
                     // this lane's queries 4 kq + v: threshold, level-1 head
                     // energy, tail after level 1, margin
                     float th[4], rqh[4], a1q[4], Aq[4];
@@ -1907,6 +1910,8 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             }
                         }
                     }
+                    if (lane < ng) thr_w[lane] = fminf(thr_w[lane], thr_new);
+                    wave_sync();
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) {
                         const int s = slot0 + nt * 16 + r16;
