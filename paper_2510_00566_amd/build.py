@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libpanorama.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["api.cpp", "host_linalg.cpp", "pq_host.cpp", "k_build.hip", "k_search.hip", "k_pq.hip"]
+SOURCES = ["api.cpp", "host_linalg.cpp", "pq_host.cpp", "k_build.hip", "k_search.hip", "k_coarse.hip", "k_pq.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -344,6 +344,26 @@ std::vector<std::pair<int, int>> shape_plan(const std::vector<double> &lam, cons
 void haar_rotation(int n, uint64_t seed, uint64_t stream, std::vector<double> &Q);
 std::vector<double> shape_transform(std::vector<double> &T, int d, const std::vector<double> &lam,
                                     const std::vector<int> &cuts, double kappa, bool isotropize, uint64_t seed);
+// The coarse step: every query's p = min(nprobe, nlist, np_max) nearest lists
+// by (canonical D, list id), written to probes[q][0..p) (the rest -1) and
+// npq[q] = p, with list_cnt[l] += queries probing l (list_cnt must be zero
+// before).  S [nq][nlist] = q c^T from the tiled FP32 product (launch_gemm_nt
+// or the search's product job), cn2 the centroids' squared norms, qn2 (may be
+// null) receives ||q||^2.  nlist = 1 puts every query on list 0.
+// coarse_prepare picks the kernels for (nlist, d) and sets their attributes
+// (call it outside graph capture); coarse_enqueue only launches.
+struct CoarsePlan {
+    int nlist = 1, d = 0;
+    float c_co = 0.f;         // relative error bound of the product-form distances
+    size_t lds_wave = 0;      // LDS bytes per wavefront of the LDS instance
+    int wpb = 1;              // wavefronts per workgroup of the LDS instance
+    const void *regs = nullptr, *finish = nullptr, *lds = nullptr;
+};
+float coarse_error_bound(int d);
+CoarsePlan coarse_prepare(int nlist, int d);
+void coarse_enqueue(const CoarsePlan &cp, const float *S, const float *cn2, const float *q, const float *cent, int64_t nq,
+                    const int32_t *nprobe_dev, int nprobe_all, int np_max, int32_t *probes, int32_t *npq,
+                    int32_t *list_cnt, float *qn2, hipStream_t s);
 void launch_coarse_probes(const float *S, const float *cn2, const float *q, const float *cent, int d, int nlist,
                           int64_t nq, const int32_t *nprobe_dev, int nprobe_all, int np_max, int32_t *probes,
                           int32_t *npq, int32_t *list_cnt, float *qn2, hipStream_t s);

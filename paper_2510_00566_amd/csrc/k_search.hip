@@ -10,152 +10,6 @@
 
 namespace pano {
 
-// ================================================================ query prep
-// ================================================================ coarse probing
-// One wavefront per query.  Approximate distances to every centroid come from
-// the dense product S = q . c (chunked FP32 on the matrix cores), with a
-// certified absolute error bound c_co (||q||^2 + ||c||^2).  A list is
-// certainly in the probe set if its upper bound is below the (p+1)-th smallest
-// lower bound; the uncertain lists of the band are rescored with the canonical
-// recipe and ordered by (D, l).
-__host__ __device__ inline size_t coarse_lds_per_wave(int nlist, int d)
-{
-    // keys [next_pow2(nlist)] (the band's sort pads to a power of two), LO,
-    // UP, list ids [nlist], query row [d], select histogram [256]
-    return (((size_t)next_pow2(nlist) * 8 + (size_t)nlist * 12 + (size_t)d * 4 + 1024 + 64) + 15) & ~(size_t)15;
-}
-
-template <int NMAX>
-__global__ __launch_bounds__(NT) void k_coarse(const float *__restrict__ S, const float *__restrict__ cn2, const float *__restrict__ q,
-                                               const float *__restrict__ cent, int d, int nlist, int64_t nq,
-                                               const int32_t *__restrict__ nprobe_dev, int nprobe_all,
-                                               float c_co, int np_max, int32_t *__restrict__ probes,
-                                               int32_t *__restrict__ np_out, int32_t *__restrict__ list_cnt,
-                                               float *__restrict__ qn2)
-{
-    extern __shared__ char smc[];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    const int64_t qi = (int64_t)blockIdx.x * wpb + w;
-    if (qi >= nq) return;
-    const size_t pw = coarse_lds_per_wave(nlist, d);
-    char *base = smc + pw * w;
-    uint64_t *keys = reinterpret_cast<uint64_t *>(base);            // [next_pow2(nlist)]
-    float *LO = reinterpret_cast<float *>(keys + next_pow2(nlist));  // [nlist]
-    float *UP = LO + nlist;                                          // [nlist]
-    int32_t *lst = reinterpret_cast<int32_t *>(UP + nlist);          // [nlist]
-    float *qrow = reinterpret_cast<float *>(lst + nlist);            // [d]
-    int *hist = reinterpret_cast<int *>(qrow + d);                   // [256] (nlist > 4096)
-    int p = nprobe_dev ? nprobe_dev[qi] : nprobe_all;
-    p = p < 1 ? 1 : (p > nlist ? nlist : p);
-    if (p > np_max) p = np_max;
-    // the query row in rounds of eight loads per lane, all in flight
-    // together, and ||q||^2 in FP32: per lane its values in increasing
-    // column order, then a butterfly (the order the error bound c_co counts)
-    float qq = 0.f;
-    for (int j0 = 0; j0 < d; j0 += 512) {
-        float v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = j0 + u * 64 + lane;
-            v[u] = q[qi * d + min(j, d - 1)];  // clamped: no branch around the load
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = j0 + u * 64 + lane;
-            if (j < d) {
-                qrow[j] = v[u];
-                qq = __builtin_fmaf(v[u], v[u], qq);
-            }
-        }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o, 64);
-    if (qn2 != nullptr && lane == 0) qn2[qi] = qq;
-    for (int l0 = 0; l0 < nlist; l0 += 512) {
-        float cv[8], sv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int l = l0 + u * 64 + lane;
-            const int lc = min(l, nlist - 1);  // clamped: no branch around the loads
-            cv[u] = cn2[lc];
-            sv[u] = S[qi * nlist + lc];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int l = l0 + u * 64 + lane;
-            if (l < nlist) {
-                const float a = qq + cv[u] - 2.f * sv[u];
-                const float del = c_co * (qq + cv[u]);
-                LO[l] = fmaxf(a - del, 0.f) * (1.0f - 1.2e-7f);
-                UP[l] = fmaxf(a + del, 0.f) * (1.0f + 1.2e-7f);
-            }
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    // (the key buffer, not in use yet, holds the selects' candidates)
-    float *cand = reinterpret_cast<float *>(keys);
-    const float Up = wave_select_nonneg<NMAX>(UP, nlist, p, hist, cand, lane);
-    const float Lp1 = p < nlist ? wave_select_nonneg<NMAX>(LO, nlist, p + 1, hist, cand, lane) : INFINITY;
-    // certain lists go to the output; uncertain band members are collected
-    int ncert = 0, nunc = 0;
-    for (int b0 = 0; b0 < nlist; b0 += 64) {
-        const int l = b0 + lane;
-        const bool inb = l < nlist && LO[l] <= Up;
-        const bool cert = inb && UP[l] < Lp1;
-        const bool unc = inb && !cert;
-        const uint64_t bc = __ballot(cert), bu = __ballot(unc);
-        const uint64_t below = (1ull << lane) - 1ull;
-        if (cert) {
-            const int pos = ncert + __popcll(bc & below);
-            if (pos < p) {
-                probes[qi * np_max + pos] = l;
-                atomicAdd(&list_cnt[l], 1);  // queries per list, for the work lists
-            }
-        }
-        if (unc) lst[nunc + __popcll(bu & below)] = l;
-        ncert += __popcll(bc);
-        nunc += __popcll(bu);
-    }
-    if (ncert > p) ncert = p;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int need = p - ncert;
-    if (need > 0) {
-        const int PU = next_pow2(nunc);
-        // one band member at a time, each by the whole wavefront
-        for (int i = 0; i < nunc; ++i) {
-            const int l = lst[i];
-            const float dv = wave_canon_dist(qrow, cent + (int64_t)l * d, d, lane);
-            if (lane == 0) keys[i] = make_key(dv, l);
-        }
-        for (int i = nunc + lane; i < PU; i += 64) keys[i] = KEY_MAX;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        wave_bitonic_sort(keys, PU, lane);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int i = lane; i < need; i += 64) {
-            const int l = key_id(keys[i]);
-            probes[qi * np_max + ncert + i] = l;
-            atomicAdd(&list_cnt[l], 1);
-        }
-    }
-    for (int i = p + lane; i < np_max; i += 64) probes[qi * np_max + i] = -1;
-    if (lane == 0) np_out[qi] = p;
-}
-
-__global__ void k_single_list(int64_t nq, int np_max, int32_t *__restrict__ probes, int32_t *__restrict__ np_out,
-                              int32_t *__restrict__ list_cnt)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nq) return;
-    atomicAdd(&list_cnt[0], 1);
-    probes[i * np_max] = 0;
-    for (int r = 1; r < np_max; ++r) probes[i * np_max + r] = -1;
-    np_out[i] = 1;
-}
-
 // ================================================================ work list
 // One workgroup: per-list query offsets (to list_qoff in global memory and/or
 // qoff_lds, 32-bit, in LDS) and, when item_off is given, the item offsets of
@@ -2535,34 +2389,6 @@ __global__ __launch_bounds__(NT) void k_fallback_device(int64_t nq, int k, int d
     }
 }
 
-// Coarse probing for the PQ index: S [nq][nlist] = q c^T from launch_gemm_nt
-// (the same tiled product, so the same error bound), probes and counts as in
-// a search; list_cnt (nlist ints) must be zero.  nlist = 1 puts every query
-// on list 0.
-void launch_coarse_probes(const float *S, const float *cn2, const float *q, const float *cent, int d, int nlist,
-                          int64_t nq, const int32_t *nprobe_dev, int nprobe_all, int np_max, int32_t *probes,
-                          int32_t *npq, int32_t *list_cnt, float *qn2, hipStream_t s)
-{
-    if (nq == 0) return;
-    if (nlist == 1) {
-        hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, np_max, probes, npq,
-                           list_cnt);
-        PANO_HIP(hipGetLastError());
-        return;
-    }
-    const double u_ = std::ldexp(1.0, -24);
-    auto gam = [&](double nn) { return nn * u_ / (1.0 - nn * u_); };
-    const float c_co = (float)((gam(d / 64.0 + 8) + gam(2.0 * (32.0 + (d + 31) / 32 + 2)) + 4 * u_) * 1.1);
-    const size_t per_wave = coarse_lds_per_wave(nlist, d);
-    const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
-    const size_t shm = per_wave * wpb;
-    PANO_REQUIRE(shm <= 160 * 1024, "nlist too large for the coarse step");
-    auto kern = nlist <= 1024 ? k_coarse<1024> : (nlist <= 4096 ? k_coarse<4096> : k_coarse<(1 << 30)>);
-    PANO_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    hipLaunchKernelGGL(kern, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), shm, s, S, cn2, q, cent, d, nlist,
-                       nq, nprobe_dev, nprobe_all, c_co, np_max, probes, npq, list_cnt, qn2);
-    PANO_HIP(hipGetLastError());
-}
 
 // Slots of a query's probe set (the exact fallback's key count), for callers
 // that keep the probe list on the device.
@@ -3071,21 +2897,11 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     unsigned long long *stats = c3.take<unsigned long long>(128);
 
     // ---- launch geometry that does not depend on the stream
-    const double u_ = std::ldexp(1.0, -24);
-    auto gam = [&](double nn) { return nn * u_ / (1.0 - nn * u_); };
-    const float c_co = (float)((gam(d / 64.0 + 8) + gam(2.0 * (32.0 + (d + 31) / 32 + 2)) + 4 * u_) * 1.1);
-    const size_t per_wave = coarse_lds_per_wave(nlist, d);
-    const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / per_wave));
-    const size_t coarse_shm = per_wave * wpb;
-    PANO_REQUIRE(nlist == 1 || coarse_shm <= 160 * 1024, "nlist too large for the coarse step");
+    const CoarsePlan coarse = coarse_prepare(nlist, d);
+    const float c_co = coarse.c_co;
     const size_t merge_shm = sizeof(uint64_t) * MERGE_LDS_KEYS + sizeof(float) * (size_t)d;
     const size_t scan_shm = wave ? (size_t)(NT / 64) * c.wl.bytes
                                  : sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
-    // the coarse kernel instance compiled for at most this many lists
-    auto coarse_kernel = nlist <= 1024 ? k_coarse<1024> : (nlist <= 4096 ? k_coarse<4096> : k_coarse<(1 << 30)>);
-    if (nlist > 1)
-        PANO_HIP(hipFuncSetAttribute((const void *)coarse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)coarse_shm));
     PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_shm));
     // query groups ordered by distance to the list (reserved[4] = 1 keeps the
     // arrival order); at most 16384 queries of a list are ordered
@@ -3187,14 +3003,8 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
             if (fork) PANO_HIP(hipEventRecord(ctx->ev_join, sa));
         }
         // coarse probing (and the number of queries per list)
-        if (nlist > 1) {
-            hipLaunchKernelGGL(coarse_kernel, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), coarse_shm, st, Sco,
-                               ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), d, nlist, nq,
-                               nprobe_dev, nprobe_all, c_co, np_max, probes, npq, list_cnt, qn2);
-        } else {
-            hipLaunchKernelGGL(k_single_list, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nq, np_max, probes,
-                               npq, list_cnt);
-        }
+        coarse_enqueue(coarse, Sco, ix->cent.as<float>() + (size_t)nlist * d, q, ix->cent.as<float>(), nq, nprobe_dev,
+                       nprobe_all, np_max, probes, npq, list_cnt, qn2, st);
         if (fork) {
             PANO_HIP(hipStreamWaitEvent(sb, ctx->ev_fork, 0));
             row_norms(sb);

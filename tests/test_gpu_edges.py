@@ -274,6 +274,36 @@ def test_many_lists(torch_cuda, nlist, nprobe):
 
 
 @gpu
+@pytest.mark.parametrize("nlist,nprobe", [(200, 40), (200, 150), (1000, 40), (1000, 300), (3000, 100)])
+def test_coarse_band_of_equal_centroid_distances(torch_cuda, nlist, nprobe):
+    """Every centroid has the same norm (entries +-1), so a query at the
+    origin ties with every list and a query within 1e-6 of it has all its
+    list distances inside the coarse error band: the band is the whole list
+    set.  Up to 256 band members are ordered in registers and LDS by the fast
+    instance; wider bands go whole to the LDS instance.  The probe sets must
+    still be the exact (D, list id) order, which the oracle's answer checks."""
+    import torch
+    from tests import gpu_cases as gc
+    from paper_2510_00566_amd.index import Index, Transform
+    d = 32
+    g = np.random.default_rng(nlist + nprobe)
+    cent = np.where(g.random((nlist, d)) < 0.5, -1.0, 1.0).astype(np.float32)
+    assign = (np.arange(3 * nlist) % nlist).astype(np.int32)
+    x = (cent[assign] + 0.05 * g.standard_normal((3 * nlist, d))).astype(np.float32)
+    q = np.zeros((6, d), np.float32)
+    q[3:] = (1e-6 * g.standard_normal((3, d))).astype(np.float32)
+    w = _workload(d=d, k=10, nlist=nlist, nprobe=nprobe, width=8, n=3 * nlist, nq=6)
+    _log(f"case coarse tie band nlist={nlist} nprobe={nprobe} n={3 * nlist} d={d}")
+    xd = torch.from_numpy(x).cuda()
+    cd, ad = torch.from_numpy(cent).cuda(), torch.from_numpy(assign).cuda()
+    tf = Transform.fit(x, seed=1)
+    idx = Index.build(gc.ctx(), tf, xd, cd, ad, w.level_cuts())
+    case = {"x": x, "cent": cent, "assign": assign, "idx": idx}
+    _run(torch_cuda, case, w, q)
+    idx.free()
+
+
+@gpu
 def test_out_of_distribution_queries_stay_exact(torch_cuda):
     """Queries whose spectrum is flat in the data's PCA basis (no energy
     compaction, Prop. 5.2's alpha_q -> 0) still get the exact answer."""
