@@ -118,17 +118,22 @@ __global__ void k_wl_fill(int64_t nq, int np_max, const int32_t *__restrict__ pr
 // at similar distance: the queries of the list's own cluster come first and
 // the far ones, whose candidates fail the level-1 bound, share groups of
 // their own.  A pure reordering of the work; the answer does not change.
-// One workgroup per list; lists of more than `cap` queries keep their order.
+// A list is ordered in chunks of WL_SORT_CHUNK queries, one workgroup per
+// chunk (blockIdx.y), so that long lists do not serialise on one workgroup:
+// each chunk spans the list's distance range in order, so its groups still
+// hold queries of similar distance.
+constexpr int WL_SORT_CHUNK = 1024;
 __global__ __launch_bounds__(NT) void k_wl_sort(int nlist, const int32_t *__restrict__ list_cnt,
                                                 const int64_t *__restrict__ list_qoff, int32_t *__restrict__ list_q,
                                                 const float *__restrict__ S, const float *__restrict__ qn2,
-                                                const float *__restrict__ cn2, int cap)
+                                                const float *__restrict__ cn2)
 {
-    extern __shared__ uint64_t Kq[];
+    __shared__ uint64_t Kq[WL_SORT_CHUNK];
     const int l = blockIdx.x;
-    const int cnt = list_cnt[l];
-    if (cnt < 2 || cnt > cap) return;
-    const int64_t off = list_qoff[l];
+    const int c0 = blockIdx.y * WL_SORT_CHUNK;
+    const int cnt = min(list_cnt[l] - c0, WL_SORT_CHUNK);
+    if (cnt < 2) return;
+    const int64_t off = list_qoff[l] + c0;
     const int P = next_pow2(cnt);
     const float c2 = cn2[l];
     for (int i = threadIdx.x; i < P; i += NT) {
@@ -2904,12 +2909,9 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
                                  : sizeof(uint64_t) * (4 * (size_t)next_pow2(c.kc + 64) + (size_t)c.G * c.kc);
     PANO_HIP(hipFuncSetAttribute((const void *)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merge_shm));
     // query groups ordered by distance to the list (reserved[4] = 1 keeps the
-    // arrival order); at most 16384 queries of a list are ordered
+    // arrival order), in chunks of WL_SORT_CHUNK queries
     const bool sort_groups = nlist > 1 && !(prm && prm->reserved[4] == 1) && nq > c.G;
-    const int sort_cap = (int)std::min<int64_t>(nq, 16384);
-    const size_t sort_shm = sizeof(uint64_t) * (size_t)next_pow2(sort_cap);
-    if (sort_groups)
-        PANO_HIP(hipFuncSetAttribute((const void *)k_wl_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_shm));
+    const int sort_chunks = (int)std::min<int64_t>((nq + WL_SORT_CHUNK - 1) / WL_SORT_CHUNK, 65535);
     // the per-wave scan instance of this search (and its counting twin)
     typedef void (*ScanKernel)(SearchConsts, IndexView, QueryView, WorkView);
     const ScanKernel wave_kern = brute ? (use_bf16 ? k_scan_wave_brute_bf16 : k_scan_wave_brute)
@@ -3025,8 +3027,8 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
                                list_fill, list_q);
         }
         if (sort_groups)
-            hipLaunchKernelGGL(k_wl_sort, dim3((unsigned)nlist), dim3(NT), sort_shm, st, nlist, list_cnt, list_qoff,
-                               list_q, Sco, qn2, ix->cent.as<float>() + (size_t)nlist * d, sort_cap);
+            hipLaunchKernelGGL(k_wl_sort, dim3((unsigned)nlist, (unsigned)sort_chunks), dim3(NT), 0, st, nlist,
+                               list_cnt, list_qoff, list_q, Sco, qn2, ix->cent.as<float>() + (size_t)nlist * d);
         if (fork) {
             PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
             PANO_HIP(hipStreamWaitEvent(st, ctx->ev_join2, 0));
