@@ -49,6 +49,8 @@ class Request:
     ids: np.ndarray | None = None
     dists: np.ndarray | None = None
     batch: int = -1           # id of the batch that served it
+    deferred: bool = False    # waited at the head of the queue for memory
+    rejected: bool = False    # refused at arrival: the queue was full
 
     @property
     def m(self) -> int:
@@ -81,14 +83,22 @@ class Scheduler:
     worker's charge to the resident size it reports (0 after a trim).  A
     single request that cannot fit even when no other batch is in flight is
     still admitted alone (it could never run otherwise); the budget is then
-    exceeded by that batch only."""
+    exceeded by that batch only.  max_queued (queries, None: no limit)
+    bounds the waiting queue: a request that would exceed it is rejected at
+    arrival (back-pressure instead of unbounded queueing).  A request that
+    reaches the head of the queue but must wait for memory held by other
+    batches is counted as deferred."""
 
     def __init__(self, cost: Callable[[str, int, int], int], budget: int, max_batch_queries: int = 4096,
-                 growth: float = 1.25):
+                 growth: float = 1.25, max_queued: int | None = None):
         self.cost = cost
         self.budget = int(budget)
         self.max_q = int(max_batch_queries)
         self.growth = float(growth)
+        self.max_queued = None if max_queued is None else int(max_queued)
+        self._queued = 0  # queries waiting
+        self.rejected = 0
+        self.deferred = 0
         self._lock = threading.Condition()
         self._queues: dict = collections.OrderedDict()  # (index, k) -> deque of Request
         self._charge: dict = {}  # worker id -> bytes charged for its context
@@ -100,11 +110,18 @@ class Scheduler:
         self._next_bid = 0
 
     # ---- producer side
-    def submit(self, req: Request):
+    def submit(self, req: Request) -> bool:
+        """Queue a request; False (and req.rejected) if the queue is full."""
         with self._lock:
+            if self.max_queued is not None and self._queued + req.m > self.max_queued:
+                req.rejected = True
+                self.rejected += 1
+                return False
+            self._queued += req.m
             key = (req.index, req.k)
             self._queues.setdefault(key, collections.deque()).append(req)
             self._lock.notify_all()
+            return True
 
     def close(self):
         """No more requests will be submitted; workers drain and stop."""
@@ -167,12 +184,16 @@ class Scheduler:
                 # the oldest class does not fit beside the memory the other
                 # workers hold: idle ones are asked to trim, busy ones may
                 # trim when they finish
+                if not q[0].deferred:
+                    q[0].deferred = True
+                    self.deferred += 1
                 if any(self._charge.get(w, 0) > 0 for w in self._idle if w != wid):
                     self._pressure = True
                 self._lock.notify_all()
                 self._lock.wait()
                 continue
             self._pressure = False
+            self._queued -= nq
             need = self.cost(index, nq, k)
             prev = self._charge.get(wid, 0)
             self._charge[wid] = max(prev, int(self.growth * need))
@@ -328,15 +349,16 @@ def latency_report(reqs: list) -> dict:
     the served requests."""
     lat = np.array([(r.done - r.arrival) * 1e3 for r in reqs if r.done >= 0])
     nq = sum(r.m for r in reqs if r.done >= 0)
+    counts = {"rejected": sum(1 for r in reqs if r.rejected), "deferred": sum(1 for r in reqs if r.deferred)}
     if lat.size == 0:
-        return {"requests": 0}
+        return {"requests": 0, **counts}
     t_first = min(r.arrival for r in reqs)
     t_last = max(r.done for r in reqs if r.done >= 0)
     span = max(t_last - t_first, 1e-9)
     return {"requests": int(lat.size), "queries": int(nq),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
-            "qps": float(nq / span), "rps": float(lat.size / span), "span_s": float(span)}
+            "qps": float(nq / span), "rps": float(lat.size / span), "span_s": float(span), **counts}
 
 
 # ---------------------------------------------------------------- GPU executor
@@ -405,10 +427,14 @@ def main(argv=None):
     from .index import Context, Index, Transform, ivf_assign
 
     ap = argparse.ArgumentParser(description="continuous-batching serving loop over two resident indexes")
-    ap.add_argument("--qps", type=float, nargs="+", default=[2000.0, 10000.0, 50000.0],
+    ap.add_argument("--qps", type=float, nargs="+", default=[2000.0, 5000.0, 10000.0, 20000.0, 50000.0],
                     help="offered loads in queries per second (Poisson request arrivals, mean request size "
                          "128.5 queries); one JSON line per load")
-    ap.add_argument("--duration", type=float, default=3.0, help="seconds of arrivals")
+    ap.add_argument("--duration", type=float, default=60.0, help="seconds of arrivals per load")
+    ap.add_argument("--max-queued", type=int, default=262144,
+                    help="queries waiting at most; requests beyond are rejected at arrival")
+    ap.add_argument("--c4-store", default="bf16", choices=["f32", "bf16"],
+                    help="level storage of the embedding-shaped index")
     ap.add_argument("--scale", type=float, default=0.1, help="fraction of each index's N")
     ap.add_argument("--workers", type=int, default=3)
     ap.add_argument("--budget-gib", type=float, default=8.0)
@@ -433,20 +459,21 @@ def main(argv=None):
         rows = np.random.Generator(np.random.PCG64(w.cfg_id)).choice(w.n, min(w.n, 65536), replace=False)
         c_np, a_np = cent.cpu().numpy(), assign.cpu().numpy()
         tf = Transform.fit(data["x"][rows] - c_np[a_np[rows]], fit_sample=0, seed=w.cfg_id)
-        indexes[name] = Index.build(ctx, tf, xd, cent, assign, w.level_cuts())
-        pools[name] = data["q"]
-        # the tuner's choice for the workload this index is shaped like (an
-        # entry for either storage type; the index here is FP32)
+        store = args.c4_store if name == "c4" else "f32"
+        # the tuner's choice (search knobs and level width) for the workload
+        # this index is shaped like and its storage type
         npv = w0.nprobe_range[1] if w0.nprobe_range else w0.nprobe
-        for store in ("f32", "bf16"):
-            p, _ = autotune.lookup(autotune.signature("gfx950", w.d, store, w.n, npv, w0.k))
-            if p is not None:
-                p.use_bf16 = 0
-                params[name] = p
-                break
+        p, width = autotune.lookup(autotune.signature("gfx950", w.d, store, w.n, npv, w0.k))
+        if p is not None:
+            p.use_bf16 = 1 if store == "bf16" else 0
+            params[name] = p
+        if width and w.tune_width:
+            w.level_width = int(width)
+        indexes[name] = Index.build(ctx, tf, xd, cent, assign, w.level_cuts(), store=store)
+        pools[name] = data["q"]
         del xd
         torch.cuda.synchronize()
-        log(f"[serve] index {name}: n={w.n} d={w.d} nlist={w.nlist} built in {time.time() - t:.1f}s")
+        log(f"[serve] index {name}: n={w.n} d={w.d} nlist={w.nlist} {store} built in {time.time() - t:.1f}s")
 
     log(f"[serve] search params {params}")
     ex = GpuExecutor(indexes, args.workers, params=params)
@@ -456,7 +483,7 @@ def main(argv=None):
     replay(srv, warm)
     for qps in args.qps:
         rate = qps / 128.5
-        sched = Scheduler(ex.cost, int(args.budget_gib * 2 ** 30), args.max_batch)
+        sched = Scheduler(ex.cost, int(args.budget_gib * 2 ** 30), args.max_batch, max_queued=args.max_queued)
         srv = Server(sched, ex, n_workers=args.workers)
         reqs = poisson_requests(pools, rate, args.duration, args.seed)
         log(f"[serve] offered {qps:.0f} q/s: {len(reqs)} requests, {sum(r.m for r in reqs)} queries "
@@ -466,6 +493,9 @@ def main(argv=None):
         rep.update({"offered_qps": qps, "workers": args.workers, "rate_rps": rate, "batches": len(srv.batches),
                     "mean_batch_queries": float(np.mean([b[4] for b in srv.batches])) if srv.batches else 0.0,
                     "peak_inflight_gib": sched.peak_inflight / 2 ** 30, "errors": len(srv.errors),
+                    "duration_s": args.duration, "max_queued": args.max_queued,
+                    "stores": {n: ("bf16" if (n == "c4" and args.c4_store == "bf16") else "f32") for n in indexes},
+                    "params": {n: vars(p) for n, p in params.items()},
                     "scale": args.scale, "indexes": {n: {"n": int(ix.info()["n"]), "d": ix.d}
                                                      for n, ix in indexes.items()}})
         print(json.dumps(rep), flush=True)

@@ -209,3 +209,37 @@ def test_resident_scratch_stays_within_budget():
     assert sched.inflight == sum(ex.res)
     # a worker above its share (budget / 3) trims after its batch
     assert all(r <= budget // 3 for r in ex.res)
+
+
+def test_full_queue_rejects_at_arrival():
+    """max_queued bounds the waiting queries: a request that would exceed it
+    is refused at arrival and counted; served requests leave room again."""
+    sched = Scheduler(lambda i, nq, k: nq, budget=1 << 30, max_batch_queries=64, max_queued=10)
+    a, b, c = _req(0, m=6), _req(1, m=4), _req(2, m=1)
+    assert sched.submit(a) and sched.submit(b)
+    assert not sched.submit(c) and c.rejected and sched.rejected == 1
+    bt = sched.next_batch(0)
+    assert [r.rid for r in bt.requests] == [0, 1]
+    d = _req(3, m=10)
+    assert sched.submit(d) and not d.rejected
+    rep = latency_report([a, b, c, d])
+    assert rep["rejected"] == 1
+
+
+def test_request_waiting_for_memory_is_counted_deferred():
+    """The head request does not fit beside a batch in flight: it waits (is
+    deferred) and runs once that batch finishes and releases its memory."""
+    sched = Scheduler(lambda i, nq, k: 100 * nq, budget=1000, max_batch_queries=64, growth=1.0)
+    sched.submit(_req(0, m=6))
+    first = sched.next_batch(0)
+    late = _req(1, m=6)
+    sched.submit(late)
+    got = []
+    t = threading.Thread(target=lambda: got.append(sched.next_batch(1)))
+    t.start()
+    time.sleep(0.2)
+    assert not got and late.deferred and sched.deferred == 1
+    sched.finish(first, resident=0)
+    t.join(timeout=5)
+    assert got and [r.rid for r in got[0].requests] == [1]
+    assert latency_report([late])["deferred"] == 1
