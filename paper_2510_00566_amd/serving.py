@@ -490,6 +490,8 @@ def main(argv=None):
             f"over {args.duration}s")
         replay(srv, reqs)
         rep = latency_report(reqs)
+        rep["by_index"] = {n: {k_: v_ for k_, v_ in latency_report([r for r in reqs if r.index == n]).items()
+                               if k_ in ("requests", "p50_ms", "p99_ms", "qps")} for n in indexes}
         rep.update({"offered_qps": qps, "workers": args.workers, "rate_rps": rate, "batches": len(srv.batches),
                     "mean_batch_queries": float(np.mean([b[4] for b in srv.batches])) if srv.batches else 0.0,
                     "peak_inflight_gib": sched.peak_inflight / 2 ** 30, "errors": len(srv.errors),
