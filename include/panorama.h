@@ -281,6 +281,32 @@ pano_status pano_refine(pano_index *idx, const float *q_dev, int64_t nq, int32_t
                         int32_t kprime, float eps, int64_t *ids_dev, float *dists_dev, void *stream);
 
 /*
+ * audit_bounds: the certified per-level bounds of sampled (query, row) pairs
+ * as the GPU computes them from the index, for checking the pruning's
+ * soundness (the bounds of Section 5: Eq. 3, Cauchy-Schwarz on the tails,
+ * with the margins of the floating-point analysis) against an exact
+ * distance.  Pair i is query pair_q_dev[i] (int32, a row of q_dev [nq][d]
+ * float32) and row pair_row_dev[i] (int64, a row id of build_levels' x).
+ * For level l = 0..L-1, bounds_dev[i][l][0..3] (float32) receives lower and
+ * upper bounds on the stored-frame distance ||y_q - y_x||^2 after levels
+ * 0..l, where y_q is the transformed query and y_x the stored FP32 row:
+ * [0], [1] with the head distance summed from coordinate differences (the
+ * form of the per-pair passes), [2], [3] in the dot-product form of the
+ * matrix-core levels (level energies from the tails minus twice the product).
+ * Bounds are those of eps = 1 and use the same bound functions and margins
+ * as the scans.  bf16 != 0 (an index built with PANO_BF16): heads are read
+ * from the bfloat16 tiles with the bfloat16 margins; the distance bounded is
+ * still the one to the FP32 row.  rows_dev (may be NULL) [npairs][2][d_pad]
+ * float32 receives y_q and y_x (padding columns zero).  Device pointers,
+ * caller-owned; runs on the index's context after the work queued on
+ * `stream` and returns when done.  Errors: EINVAL for a query or row index
+ * out of range, or bf16 on an index without bfloat16 tiles.
+ */
+pano_status pano_audit_bounds(pano_index *idx, const float *q_dev, int64_t nq, const int32_t *pair_q_dev,
+                              const int64_t *pair_row_dev, int64_t npairs, int32_t bf16, float *bounds_dev,
+                              float *rows_dev, void *stream);
+
+/*
  * search_noalloc: pano_search for callers that cannot allocate memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, semantics and results as pano_search without

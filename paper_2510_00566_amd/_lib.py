@@ -81,6 +81,7 @@ def lib():
         "pano_search_scratch_bytes": (C.c_int, [P, i64, i32, i32, i32, P, P]),
         "pano_search_noalloc": (C.c_int, [P, P, i64, i32, P, i32, f32, P, P, P, P]),
         "pano_refine": (C.c_int, [P, P, i64, i32, P, i32, f32, P, P, P]),
+        "pano_audit_bounds": (C.c_int, [P, P, i64, P, P, i64, i32, P, P, P]),
         "pano_search_bruteforce": (C.c_int, [P, P, i64, i32, P, i32, P, P, P, u32, P]),
         "pano_index_info": (C.c_int, [P, P]),
         "pano_index_layout": (C.c_int, [P, P, P]),
@@ -113,6 +114,6 @@ def exported_symbols():
             "pano_ctx_scratch_bytes", "pano_ctx_trim", "pano_ctx_status",
             "pano_build_transform", "pano_transform_identity", "pano_transform_from",
             "pano_transform_get", "pano_transform_free", "pano_ivf_assign", "pano_build_levels",
-            "pano_search", "pano_search_ctx", "pano_search_scratch_bytes", "pano_search_noalloc", "pano_refine", "pano_search_bruteforce", "pano_index_info", "pano_index_layout",
+            "pano_search", "pano_search_ctx", "pano_search_scratch_bytes", "pano_search_noalloc", "pano_refine", "pano_audit_bounds", "pano_search_bruteforce", "pano_index_info", "pano_index_layout",
             "pano_stats_get", "pano_index_free", "pano_shape_plan", "pano_transform_shape", "pano_pq_build",
             "pano_pq_search", "pano_pq_stats", "pano_pq_export", "pano_pq_free"]

@@ -599,6 +599,18 @@ pano_status pano_refine(pano_index *idx, const float *q_dev, int64_t nq, int32_t
     });
 }
 
+pano_status pano_audit_bounds(pano_index *idx, const float *q_dev, int64_t nq, const int32_t *pair_q_dev,
+                              const int64_t *pair_row_dev, int64_t npairs, int32_t bf16, float *bounds_dev,
+                              float *rows_dev, void *stream)
+{
+    return guarded([&] {
+        PANO_REQUIRE(idx && (npairs == 0 || (q_dev && pair_q_dev && pair_row_dev && bounds_dev)), "null argument");
+        PANO_REQUIRE(nq >= 1 && npairs >= 0, "need nq >= 1 and npairs >= 0");
+        run_audit_bounds(idx->ctx, idx, q_dev, nq, pair_q_dev, pair_row_dev, npairs, bf16 != 0, bounds_dev, rows_dev,
+                         (hipStream_t)stream);
+    });
+}
+
 pano_status pano_search_scratch_bytes(const pano_index *idx, int64_t nq, int32_t k, int32_t per_query_nprobe,
                                       int32_t nprobe_all, const pano_search_params *params, int64_t *bytes)
 {

@@ -385,6 +385,8 @@ void run_search(pano_ctx *ctx, pano_index *idx, const float *q, int64_t nq, int 
                 int nprobe_all, float eps, int64_t *ids, float *dists, const pano_search_params *prm,
                 uint32_t flags, bool brute, hipStream_t s, void *fixed = nullptr, size_t fixed_bytes = 0);
 // The point-centric refine of given candidate ids (synchronous).
+void run_audit_bounds(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, const int32_t *pair_q,
+                      const int64_t *pair_row, int64_t npairs, bool bf, float *out, float *rows, hipStream_t s);
 void run_refine(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k, const int64_t *cand, int kprime,
                 float eps, int64_t *ids, float *dists, hipStream_t s);
 // Bytes of fixed scratch a search needs (the allocation-free entry point).

@@ -726,11 +726,11 @@ __device__ __forceinline__ bool walk_pair(const SearchConsts &c, const float *__
         const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
         const float ct = c.mg.c_tail * (a + b) * (a + b);
         const float delta = BF ? c.ub * head_norm_upper(b0row, b) + 1e-37f : 0.f;
-        const bool pruned = BF ? bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct > th
-                               : (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
+        const bool pruned = BF ? pair_lower_bf(sh, a, b, err, ct, c.one_m_eps2, delta) > th
+                               : pair_lower(sh, a, b, err, ct, c.one_m_eps2) > th;
         if (pruned) return 1;
-        const float ubh = BF ? bf_head_upper(sh + err, delta) : sh + err;
-        if (!last && ubh + (a + b) * (a + b) + ct <= th) return 2;
+        const float ub = BF ? pair_upper_bf(sh, a, b, err, ct, delta) : pair_upper(sh, a, b, err, ct);
+        if (!last && ub <= th) return 2;
         return 0;
     };
     int lv = lv_start;
@@ -993,9 +993,8 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         const bool on = valid && gq < ng;
                         const float a1 = on && g.L > 1 ? qtl_s[gq][1] : 0.f;
                         const float sh = (on ? rqh_s[gq] : 0.f) + ex[nt] - 2.f * acc[nt][v];
-                        const float dt = a1 - b1;
-                        const float hl = bf_head_lower(sh - (on ? A_s[gq] : 0.f), delta);
-                        const float lb = hl + dt * dt + c.one_m_eps2 * a1 * b1 - c.mg.c_tail * (a1 + b1) * (a1 + b1);
+                        const float lb = pair_lower_bf(sh, a1, b1, on ? A_s[gq] : 0.f,
+                                                       c.mg.c_tail * (a1 + b1) * (a1 + b1), c.one_m_eps2, delta);
                         const bool sv = on && (lb <= thr_s[on ? gq : 0]);
                         mask |= (uint32_t)sv << (nt * 4 + v);
                         sval[nt * 4 + v] = sh;
@@ -1020,10 +1019,9 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                         const bool on = valid && gq < ng;
                         const float a1 = on && g.L > 1 ? qtl_s[gq][1] : 0.f;
                         const float sh = (on ? rqh_s[gq] : 0.f) + rxh - 2.f * acc[nt][v];
-                        const float dt = a1 - b1;
-                        const float lb = sh + dt * dt + c.one_m_eps2 * a1 * b1;
-                        const float eta = (on ? A_s[gq] : 0.f) + c.mg.c_tail * (a1 + b1) * (a1 + b1);
-                        const bool sv = on && (lb - eta <= thr_s[on ? gq : 0]);
+                        const float lb = pair_lower(sh, a1, b1, on ? A_s[gq] : 0.f,
+                                                    c.mg.c_tail * (a1 + b1) * (a1 + b1), c.one_m_eps2);
+                        const bool sv = on && (lb <= thr_s[on ? gq : 0]);
                         mask |= (uint32_t)sv << (nt * 4 + v);
                         sval[nt * 4 + v] = sh;
                     }
@@ -1091,19 +1089,11 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                             const float al = qtl_s[gq][lv], an = last ? 0.f : qtl_s[gq][lv + 1];
                             const float sh = sval[b] + (al * al - an * an) + rxl - 2.f * acc2[nt][v];
                             sval[b] = sh;
-                            const float dt = an - bn;
-                            if (BF) {
-                                const float hl =
-                                    bf_head_lower(sh - c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) - A_s[gq], delta);
-                                const float lb =
-                                    hl + dt * dt + c.one_m_eps2 * an * bn - c.mg.c_tail * (an + bn) * (an + bn);
-                                if (lb > thr_s[gq]) mask &= ~(1u << b);
-                            } else {
-                                const float lb = sh + dt * dt + c.one_m_eps2 * an * bn;
-                                const float eta = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + A_s[gq] +
-                                                  c.mg.c_tail * (an + bn) * (an + bn);
-                                if (lb - eta > thr_s[gq]) mask &= ~(1u << b);
-                            }
+                            const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + A_s[gq];
+                            const float ct = c.mg.c_tail * (an + bn) * (an + bn);
+                            const float lb = BF ? pair_lower_bf(sh, an, bn, err, ct, c.one_m_eps2, delta)
+                                                : pair_lower(sh, an, bn, err, ct, c.one_m_eps2);
+                            if (lb > thr_s[gq]) mask &= ~(1u << b);
                         }
                     }
                     if (STATS && tid == 0) {
@@ -1712,18 +1702,10 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             const bool on = valid && gq < ng;
                             const float a1 = a1q[v];
                             const float sh = rqh[v] + (BF ? ex[nt] : rxh) - 2.f * acc[nt][v];
-                            const float dt = a1 - b1;
-                            bool sv;
-                            if (BF) {
-                                const float hl = bf_head_lower(sh - Aq[v], delta);
-                                sv = on && (hl + dt * dt + c.one_m_eps2 * a1 * b1 -
-                                                c.mg.c_tail * (a1 + b1) * (a1 + b1) <=
-                                            th[v]);
-                            } else {
-                                const float lb = sh + dt * dt + c.one_m_eps2 * a1 * b1;
-                                const float eta = Aq[v] + c.mg.c_tail * (a1 + b1) * (a1 + b1);
-                                sv = on && (lb - eta <= th[v]);
-                            }
+                            const float ct = c.mg.c_tail * (a1 + b1) * (a1 + b1);
+                            const float lb = BF ? pair_lower_bf(sh, a1, b1, Aq[v], ct, c.one_m_eps2, delta)
+                                                : pair_lower(sh, a1, b1, Aq[v], ct, c.one_m_eps2);
+                            const bool sv = on && lb <= th[v];
                             mask |= (uint32_t)sv << (nt * 4 + v);
                             sval[nt * 4 + v] = sh;
                         }
@@ -1841,19 +1823,12 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                                 const float al = live ? qtl[gq * L + lv] : 0.f;
                                 const float an = (live && !last) ? qtl[gq * L + lv + 1] : 0.f;
                                 const float sh = sval[b] + (al * al - an * an) + rxl - 2.f * acc2[nt][v];
-                                const float dt = an - bn;
                                 const float Ag = live ? A_w[gq] : 0.f;
                                 const float th = live ? thr_w[gq] : 0.f;
-                                bool pruned;
-                                if (BF) {
-                                    const float hl = bf_head_lower(sh - c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) - Ag, delta);
-                                    pruned = hl + dt * dt + c.one_m_eps2 * an * bn - c.mg.c_tail * (an + bn) * (an + bn) > th;
-                                } else {
-                                    const float lb = sh + dt * dt + c.one_m_eps2 * an * bn;
-                                    const float eta = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Ag +
-                                                      c.mg.c_tail * (an + bn) * (an + bn);
-                                    pruned = lb - eta > th;
-                                }
+                                const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Ag;
+                                const float ct = c.mg.c_tail * (an + bn) * (an + bn);
+                                const bool pruned = (BF ? pair_lower_bf(sh, an, bn, err, ct, c.one_m_eps2, delta)
+                                                        : pair_lower(sh, an, bn, err, ct, c.one_m_eps2)) > th;
                                 sval[b] = sh;
                                 if (live && pruned) mask &= ~(1u << b);
                             }
@@ -1952,17 +1927,13 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             // the bound after this level (Eq. 3 / Eq. 4 with the
                             // certified margin)
                             const float a = last ? 0.f : qtl[gq * L + lv + 1];
-                            const float dt = a - b;
                             const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + A_w[gq];
                             const float ct = c.mg.c_tail * (a + b) * (a + b);
                             const float th = thr_w[gq];
-                            bool pruned;
-                            if (BF) {
-                                const float delta = c.ub * head_norm_upper(tl[ss], b) + 1e-37f;
-                                pruned = bf_head_lower(sh - err, delta) + dt * dt + c.one_m_eps2 * a * b - ct > th;
-                            } else {
-                                pruned = (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
-                            }
+                            const bool pruned =
+                                (BF ? pair_lower_bf(sh, a, b, err, ct, c.one_m_eps2,
+                                                    c.ub * head_norm_upper(tl[ss], b) + 1e-37f)
+                                    : pair_lower(sh, a, b, err, ct, c.one_m_eps2)) > th;
                             const bool keep = act && !pruned && sub == 0;
                             const uint64_t bal = __ballot(keep);
                             if (keep) {
@@ -2500,10 +2471,9 @@ __global__ __launch_bounds__(NT) void k_refine(SearchConsts c, IndexView ix, Que
             }
             sh += part;
             const float a = last ? 0.f : qt[lv + 1];
-            const float dt = a - b;
             const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Aq;
             const float ct = c.mg.c_tail * (a + b) * (a + b);
-            const bool pruned = (sh + dt * dt + c.one_m_eps2 * a * b) - (err + ct) > th;
+            const bool pruned = pair_lower(sh, a, b, err, ct, c.one_m_eps2) > th;
             act = act && !pruned;
         }
         // commit the group's survivors: append those that can reach the final
@@ -3211,6 +3181,167 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
 // Refine (the point-centric scan of given candidate ids): query transform
 // and constants, k_refine, and the merge's canonical rescoring, on the
 // context's stream; the caller's stream is ordered before by an event.
+// ================================================================ bound audit
+// The certified bounds of sampled (query, row) pairs after every level, from
+// the index's own tiles and tails and the query constants of a search, with
+// the bound functions the scans use (eps = 1).  One thread per pair; the head
+// sums are sequential fused multiply-adds over the level's coordinates (an
+// order the margins cover, as they cover the matrix cores' chunked sums).
+// out [npairs][L][4]: lower, upper bound with the head from coordinate
+// differences; lower, upper bound in the dot-product form.  rows (optional)
+// [npairs][2][d_pad]: the transformed query and the FP32 stored row.
+__global__ void k_audit_bounds(SearchConsts c, IndexView ix, QueryView qv, const uint16_t *__restrict__ lv16,
+                               int64_t nq, int64_t n, const int32_t *__restrict__ pair_q,
+                               const int64_t *__restrict__ pair_row, const int64_t *__restrict__ idpos,
+                               int64_t npairs, int bf, float *__restrict__ out, float *__restrict__ rows,
+                               int32_t *__restrict__ bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npairs) return;
+    const LevelGeom &g = c.g;
+    const int L = g.L;
+    const int32_t qi = pair_q[i];
+    const int64_t r = pair_row[i];
+    if (qi < 0 || qi >= nq || r < 0 || r >= n) {
+        atomicOr(bad, 1);
+        for (int e = 0; e < 4 * L; ++e) out[i * 4 * L + e] = NAN;
+        return;
+    }
+    const int64_t pos = idpos[r];
+    const int64_t blk = pos / g.B;
+    const int ss = (int)(pos % g.B);
+    const float *X = ix.levels + blk * (int64_t)g.B * g.d_pad;
+    const uint16_t *X16 = bf ? lv16 + blk * (int64_t)g.B * g.d_pad : nullptr;
+    const float *tl = ix.tails + blk * (int64_t)L * g.B;
+    const float *qr = qv.qy + (int64_t)qi * g.d_pad;
+    const float *qt = qv.qtail + (int64_t)qi * L;
+    const float A = qv.qA[qi];
+    const float b0 = tl[ss];
+    float shd = 0.f, shp = 0.f;
+    for (int lv = 0; lv < L; ++lv) {
+        const bool last = lv + 1 == L;
+        const float al = qt[lv], an = last ? 0.f : qt[lv + 1];
+        const float bl = tl[(int64_t)lv * g.B + ss], bn = last ? 0.f : tl[(int64_t)(lv + 1) * g.B + ss];
+        float part = 0.f, dot = 0.f, ex = 0.f;
+        for (int j = 0; j < g.wp[lv]; ++j) {
+            // level 1: groups of four coordinates stored for all B slots; later
+            // levels: each slot's slice contiguous
+            const int64_t o = lv == 0 ? (int64_t)(j >> 2) * 4 * g.B + (int64_t)ss * 4 + (j & 3)
+                                      : (int64_t)g.B * g.mp[lv] + (int64_t)ss * g.wp[lv] + j;
+            const float x = bf ? __uint_as_float((uint32_t)X16[o] << 16) : X[o];
+            const float y = qr[g.mp[lv] + j];
+            const float t = y - x;
+            part = __builtin_fmaf(t, t, part);
+            dot = __builtin_fmaf(y, x, dot);
+            ex = __builtin_fmaf(x, x, ex);
+            if (rows) {
+                rows[(i * 2) * g.d_pad + g.mp[lv] + j] = y;
+                rows[(i * 2 + 1) * g.d_pad + g.mp[lv] + j] = X[o];
+            }
+        }
+        shd += part;
+        const float rxl = bf ? ex : bl * bl - bn * bn;
+        shp = (lv == 0 ? (al * al - an * an) : shp + (al * al - an * an)) + rxl - 2.f * dot;
+        const float ct = c.mg.c_tail * (an + bn) * (an + bn);
+        const float errd = c.mg.c_level[lv + 1] * fmaxf(shd, 0.f) + A;
+        const float errp = lv == 0 ? A : c.mg.c_level[lv + 1] * fmaxf(shp, 0.f) + A;
+        float *o4 = out + (i * L + lv) * 4;
+        if (bf) {
+            const float delta = c.ub * head_norm_upper(b0, bn) + 1e-37f;
+            o4[0] = pair_lower_bf(shd, an, bn, errd, ct, 0.f, delta);
+            o4[1] = pair_upper_bf(shd, an, bn, errd, ct, delta);
+            o4[2] = pair_lower_bf(shp, an, bn, errp, ct, 0.f, delta);
+            o4[3] = pair_upper_bf(shp, an, bn, errp, ct, delta);
+        } else {
+            o4[0] = pair_lower(shd, an, bn, errd, ct, 0.f);
+            o4[1] = pair_upper(shd, an, bn, errd, ct);
+            o4[2] = pair_lower(shp, an, bn, errp, ct, 0.f);
+            o4[3] = pair_upper(shp, an, bn, errp, ct);
+        }
+    }
+}
+
+void run_audit_bounds(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, const int32_t *pair_q,
+                      const int64_t *pair_row, int64_t npairs, bool bf, float *out, float *rows, hipStream_t s)
+{
+    PANO_HIP(hipSetDevice(ctx->device));
+    PANO_REQUIRE(!bf || ix->has_bf16, "the index has no bfloat16 tiles");
+    const int d = ix->d, L = ix->L;
+    SearchConsts c{};
+    c.k = 1;
+    c.nlist = ix->nlist;
+    c.eps = 1.f;
+    c.one_m_eps2 = 0.f;
+    c.bf16 = bf ? 1 : 0;
+    c.ub = (float)(std::ldexp(1.0, -8) * (1.0 + 1e-6));
+    c.mg = ix->mg;
+    c.g = LevelGeom{};
+    c.g.L = L;
+    c.g.d = d;
+    c.g.d_pad = ix->d_pad;
+    c.g.B = ix->B;
+    for (int l = 0; l <= L; ++l) c.g.mp[l] = ix->mp[l];
+    for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
+    // the query constants of a search that reads these tiles
+    Margins mq = ix->mg;
+    if (bf) {
+        mq.c_abs = ix->c_abs_bf;
+        mq.b0max2 = (float)((double)ix->mg.b0max2 * (1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -8)) *
+                            (1.0 + 1e-6));
+    }
+    if (!ix->idpos.p) {
+        ix->idpos.alloc(sizeof(int64_t) * (size_t)ix->n);
+        const int64_t slots = ix->nblocks * ix->B;
+        hipLaunchKernelGGL(k_build_idpos, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, ctx->work_stream(),
+                           ix->ids.as<int32_t>(), ix->blk_cnt.as<int32_t>(), ix->nblocks, ix->B,
+                           ix->idpos.as<int64_t>());
+        PANO_HIP(hipGetLastError());
+    }
+    const size_t need0 = align_up(sizeof(float) * nq * ix->d_pad) + align_up(sizeof(float) * nq * L) +
+                         3 * align_up(sizeof(float) * nq) + align_up(sizeof(double) * nq);
+    const size_t need3 = align_up(sizeof(int32_t) * nq) + align_up(sizeof(int32_t));
+    ctx->quiesce();
+    ctx->scratch[0].ensure(need0);
+    ctx->scratch[3].ensure(need3);
+    Carver c0(ctx->scratch[0].p), c3(ctx->scratch[3].p);
+    float *qy = c0.take<float>(nq * ix->d_pad);
+    float *qtail = c0.take<float>(nq * L);
+    float *qE = c0.take<float>(nq);
+    float *qA = c0.take<float>(nq);
+    double *vnorm = c0.take<double>(nq);
+    int32_t *qbad = c3.take<int32_t>(nq);
+    int32_t *bad = c3.take<int32_t>(1);
+    hipStream_t ws = ctx->work_stream();
+    PANO_HIP(hipEventRecord(ctx->ev_in, s));
+    PANO_HIP(hipStreamWaitEvent(ws, ctx->ev_in, 0));
+    FillList fl{};
+    fl.add(bad, 1, 0u);
+    if (rows) fl.add(rows, npairs * 2 * (int64_t)ix->d_pad, 0u);
+    if (ix->d_pad != ix->d) fl.add(qy, nq * (int64_t)ix->d_pad, 0u);
+    hipLaunchKernelGGL(k_fill_multi, dim3(256), dim3(256), 0, ws, fl);
+    const GemmJob jt = transform_job(q, nq, d, ix->T32.as<float>(), ix->mu32.as<float>(), ix->meta.as<int32_t>(), qy,
+                                     ix->d_pad);
+    launch_gemm_jobs(jt, nullptr, ws, nullptr);
+    QueryConstsOut qc;
+    qc.mg = mq;
+    qc.qE = qE;
+    qc.qA = qA;
+    qc.badq = qbad;
+    launch_row_norms(qy, nq, c.g, q, ix->mu32.as<float>(), qtail, vnorm, ws, &qc);
+    IndexView iv{ix->levels.as<float>(), nullptr, ix->tails.as<float>(), ix->ids.as<int32_t>(),
+                 ix->blk_cnt.as<int32_t>(), ix->list_blk_d.as<int64_t>(), ix->raw.as<float>()};
+    QueryView qv{qy, qtail, qE, qA, q};
+    if (npairs > 0)
+        hipLaunchKernelGGL(k_audit_bounds, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, ws, c, iv, qv,
+                           bf ? ix->levels_bf16.as<uint16_t>() : nullptr, nq, ix->n, pair_q, pair_row,
+                           ix->idpos.as<int64_t>(), npairs, bf ? 1 : 0, out, rows, bad);
+    PANO_HIP(hipGetLastError());
+    int32_t hbad = 0;
+    PANO_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, ws));
+    PANO_HIP(hipStreamSynchronize(ws));
+    PANO_REQUIRE(hbad == 0, "a pair's query or row index is out of range");
+}
+
 void run_refine(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k, const int64_t *cand, int kprime,
                 float eps, int64_t *ids, float *dists, hipStream_t s)
 {

@@ -235,6 +235,36 @@ __device__ inline float bf_head_upper(float s_hi, float delta)
     return r * r * (1.f + 1e-6f);
 }
 
+// The certified bounds of one (query, row) pair after a level, in the
+// stored frame (Eq. 3 at eps = 1, Eq. 4 below it, with the margins of the
+// soundness analysis): sh = the computed head distance over the levels read,
+// a, b = the query's and the row's tail norms after the level, err = the
+// head's absolute error bound, ct = the tail term's (c_tail (a + b)^2),
+// ome2 = 2 (1 - eps).  The lower bound is what the scans compare with the
+// pruning threshold; the upper bound (the Cauchy-Schwarz bound with the sum
+// of the tails) holds after every level and for every eps.
+__device__ __forceinline__ float pair_lower(float sh, float a, float b, float err, float ct, float ome2)
+{
+    const float dt = a - b;
+    return (sh + dt * dt + ome2 * a * b) - (err + ct);
+}
+__device__ __forceinline__ float pair_upper(float sh, float a, float b, float err, float ct)
+{
+    return sh + err + (a + b) * (a + b) + ct;
+}
+// bfloat16 rows: sh is the head distance to the rounded row, and delta
+// (u_b times a bound on the head's norm) widens its square root.
+__device__ __forceinline__ float pair_lower_bf(float sh, float a, float b, float err, float ct, float ome2,
+                                               float delta)
+{
+    const float dt = a - b;
+    return bf_head_lower(sh - err, delta) + dt * dt + ome2 * a * b - ct;
+}
+__device__ __forceinline__ float pair_upper_bf(float sh, float a, float b, float err, float ct, float delta)
+{
+    return bf_head_upper(sh + err, delta) + (a + b) * (a + b) + ct;
+}
+
 // Error model of a computed stored-frame distance Dt of a query with absolute
 // margin A (dot-product form): the exact value lies in
 // [(Dt - A)(1 - c_final), (Dt + A)(1 + c_final)].  A distance computed from

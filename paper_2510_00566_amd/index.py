@@ -299,6 +299,23 @@ class Index:
                                     float(eps), _ptr(ids), _ptr(dists), _stream_handle(stream)))
         return ids, dists
 
+    def audit_bounds(self, q_dev, pair_q, pair_row, bf16: bool = False, rows: bool = True, stream=None):
+        """Per-level certified bounds of (query, row) pairs as the GPU computes
+        them: a tensor [npairs][L][4] (lower, upper with the head from
+        coordinate differences; lower, upper in the dot-product form), and,
+        with rows, the transformed query and stored row of each pair
+        [npairs][2][d_pad]."""
+        import torch
+        pq = torch.as_tensor(pair_q, dtype=torch.int32, device=q_dev.device).contiguous()
+        pr = torch.as_tensor(pair_row, dtype=torch.int64, device=q_dev.device).contiguous()
+        inf = self.info()
+        out = torch.empty((pq.shape[0], inf["L"], 4), dtype=torch.float32, device=q_dev.device)
+        rw = torch.empty((pq.shape[0], 2, inf["d_pad"]), dtype=torch.float32, device=q_dev.device) if rows else None
+        L.check(L.lib().pano_audit_bounds(self.h, _ptr(q_dev), q_dev.shape[0], _ptr(pq), _ptr(pr), pq.shape[0],
+                                          1 if bf16 else 0, _ptr(out), _ptr(rw) if rows else None,
+                                          _stream_handle(stream)))
+        return out, rw
+
     def search_noalloc(self, q_dev, k: int, nprobe=1, eps: float = 1.0, params: Params | None = None,
                        stream=None, out=None, nprobe_max: int = 0):
         """The same search with no allocation inside the library: its scratch
