@@ -1457,7 +1457,9 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
     __shared__ unsigned long long st_lv[64];
     __shared__ unsigned long long st_misc[2];  // items, bytes
     const LevelGeom &g = c.g;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // (the wave index through readfirstlane: the compiler then keeps it and
+    // every per-wave LDS address in scalar registers)
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n_ioff = 8 * c.ceil8 + 1;
     const bool ioff_in_lds = n_ioff <= IOFF_LDS;
     if (ioff_in_lds)
@@ -1481,6 +1483,7 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
     float *sb = reinterpret_cast<float *>(wb + lay.sb);
     uint16_t *pcode = reinterpret_cast<uint16_t *>(wb + lay.code);
     float *pS = reinterpret_cast<float *>(wb + lay.pS);
+    float4 *q1s = reinterpret_cast<float4 *>(wb + lay.q1);  // [16][kg0]
     const int r16 = lane & 15, kq = lane >> 4;
     const int L = g.L;
     const int kg0 = g.wp[0] >> 2;  // four-dimension chunks of level 1 (at most 16)
@@ -1543,10 +1546,14 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
             const int gq = e / L, lv = e - gq * L;
             qtl[e] = gq < ng ? qv.qtail[(int64_t)qid_w[gq] * L + lv] : 0.f;
         }
+        // the group's level-1 query slices, read at every step of the item
+        // from LDS (one address register instead of a global pointer per
+        // chunk)
+        for (int e = lane; e < ng * kg0; e += 64) {
+            const int gq = e / kg0, kg = e - gq * kg0;
+            q1s[e] = *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_w[gq] * g.d_pad + kg * 4);
+        }
         wave_sync();
-        // the level-1 query slices of this lane's row (query r16), read at
-        // every step beside the tile (they stay in the cache for the item)
-        const float *q1row = qv.qy + (int64_t)(r16 < ng ? qid_w[r16] : 0) * g.d_pad;
         if (STATS && lane == 0) atomicAdd(&st_misc[0], 1ull);
 
         for (int bb = bstart; bb < bend; ++bb) {
@@ -1582,8 +1589,7 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const int kg = 4 * t + kq;
-                        qa[t] = (t < T0 && r16 < ng && kg < kg0) ? *reinterpret_cast<const float4 *>(q1row + kg * 4)
-                                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+                        qa[t] = (t < T0 && r16 < ng && kg < kg0) ? q1s[r16 * kg0 + kg] : make_float4(0.f, 0.f, 0.f, 0.f);
                     }
                     // level 1 of the 64 slots against the group, on the matrix cores
                     if (BF) {
@@ -2626,7 +2632,7 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     const int mode_req = prm ? prm->reserved[1] : 0;
     // the brute-force scan of bfloat16 tiles is an instance of the per-wave scan
     pl.wave = mode_req == 4 || (brute && bf16_req);
-    c.wl = wave_lds_layout(L, k);
+    c.wl = wave_lds_layout(L, k, ix->wp[0]);
     // a query group meets at most 32 work items per list
     c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1;
     c.item_cap = 32;
@@ -3365,7 +3371,7 @@ void run_refine(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     c.g.B = ix->B;
     for (int l = 0; l <= L; ++l) c.g.mp[l] = ix->mp[l];
     for (int l = 0; l < L; ++l) c.g.wp[l] = ix->wp[l];
-    c.wl = wave_lds_layout(L, k);
+    c.wl = wave_lds_layout(L, k, ix->wp[0]);
     if (!ix->idpos.p) {
         ix->idpos.alloc(sizeof(int64_t) * (size_t)ix->n);
         const int64_t slots = ix->nblocks * ix->B;

@@ -44,6 +44,7 @@ struct WaveLds {
     int kb;                  // [16][k] the k best committed distances per query
     int sb;                  // [next_pow2(k + 64)] sort buffer
     int code, pS;            // [WAVE_PAIRS] pair codes (query << 8 | slot), partial distances
+    int q1;                  // [16][w_1] the group's level-1 query slices
     int bytes;
 };
 __host__ __device__ inline int wl_take(int &o, int b)
@@ -52,7 +53,7 @@ __host__ __device__ inline int wl_take(int &o, int b)
     o += (b + 15) & ~15;
     return r;
 }
-__host__ __device__ inline WaveLds wave_lds_layout(int L, int k)
+__host__ __device__ inline WaveLds wave_lds_layout(int L, int k, int w1)
 {
     WaveLds w{};
     int o = 0;
@@ -68,6 +69,7 @@ __host__ __device__ inline WaveLds wave_lds_layout(int L, int k)
     w.sb = wl_take(o, p * 4);
     w.code = wl_take(o, WAVE_PAIRS * 2);
     w.pS = wl_take(o, WAVE_PAIRS * 4);
+    w.q1 = wl_take(o, 16 * w1 * 4);
     w.bytes = o;
     return w;
 }
