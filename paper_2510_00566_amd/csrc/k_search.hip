@@ -1563,6 +1563,13 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
             const uint16_t *blk16 = BF ? ix.levels16 + gb * (int64_t)g.B * g.d_pad : nullptr;
             const float *tl = ix.tails + gb * (int64_t)g.B * L;
             for (int slot0 = 0; slot0 < cnt; slot0 += 64) {
+                // the lane index, opaque to the compiler at every step: values
+                // derived from it are recomputed here (a few instructions)
+                // instead of being computed once and spilled to memory
+                int lane_o = lane;
+                asm volatile("" : "+v"(lane_o));
+                const int lane = lane_o, r16 = lane_o & 15, kq = lane_o >> 4;
+                const uint64_t below = (1ull << lane_o) - 1ull;
                 // ---- thresholds: the queries' current d_k, requested now and
                 // published to the wave's copy once the step's level-1 products
                 // are done (the load overlaps the tile loads)
