@@ -832,7 +832,7 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
     __shared__ int32_t ioff_s[IOFF_LDS];
 
     const LevelGeom &g = c.g;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n_ioff = 8 * c.ceil8 + 1;
     const bool ioff_in_lds = n_ioff <= IOFF_LDS;
     if (ioff_in_lds)
@@ -928,6 +928,14 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
         __syncthreads();
 
         for (int bb = bstart; bb < bend; ++bb) {
+            // the thread index, opaque to the compiler at every block: values
+            // derived from it are recomputed here instead of being computed
+            // once and spilled to memory
+            int tid_o = threadIdx.x;
+            asm volatile("" : "+v"(tid_o));
+            const int tid = tid_o, lane = tid_o & 63, r16 = lane & 15, kq = lane >> 4;
+            const int wv = __builtin_amdgcn_readfirstlane(tid_o >> 6);
+            auto q_lds = [&](int kg) -> float4 { return qrow_s[r16][kg]; };
             const int64_t gb = lb0 + bb;
             const int cnt = ix.blk_cnt[gb];
             const float *blk = ix.levels + gb * (int64_t)g.B * g.d_pad;
