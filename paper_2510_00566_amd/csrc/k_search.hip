@@ -1492,6 +1492,8 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
     uint16_t *pcode = reinterpret_cast<uint16_t *>(wb + lay.code);
     float *pS = reinterpret_cast<float *>(wb + lay.pS);
     float4 *q1s = reinterpret_cast<float4 *>(wb + lay.q1);  // [16][kg0]
+    float *rq_w = reinterpret_cast<float *>(wb + lay.rq);
+    float *a1_w = reinterpret_cast<float *>(wb + lay.a1);
     const int r16 = lane & 15, kq = lane >> 4;
     const int L = g.L;
     const int kg0 = g.wp[0] >> 2;  // four-dimension chunks of level 1 (at most 16)
@@ -1560,6 +1562,15 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
         for (int e = lane; e < ng * kg0; e += 64) {
             const int gq = e / kg0, kg = e - gq * kg0;
             q1s[e] = *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_w[gq] * g.d_pad + kg * 4);
+        }
+        // per query: head energy of level 1, ||q_h||^2 = a_0^2 - a_1^2, and
+        // the tail a_1 (zero past the group)
+        if (lane < 16) {
+            const bool on = lane < ng;
+            const float a0 = on ? qtl[lane * L] : 0.f;
+            const float a1 = (on && L > 1) ? qtl[lane * L + 1] : 0.f;
+            rq_w[lane] = a0 * a0 - a1 * a1;
+            a1_w[lane] = a1;
         }
         wave_sync();
         if (STATS && lane == 0) atomicAdd(&st_misc[0], 1ull);
@@ -1697,18 +1708,16 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                     wave_sync();
                     // this lane's queries 4 kq + v: threshold, level-1 head
                     // energy, tail after level 1, margin
-                    float th[4], rqh[4], a1q[4], Aq[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int gq = 4 * kq + v;
-                        const bool on = gq < ng;
-                        const float a0 = on ? qtl[gq * L] : 0.f;
-                        const float a1 = (on && L > 1) ? qtl[gq * L + 1] : 0.f;
-                        th[v] = thr_w[gq];
-                        rqh[v] = a0 * a0 - a1 * a1;
-                        a1q[v] = a1;
-                        Aq[v] = on ? A_w[gq] : 0.f;
-                    }
+                    // (four consecutive queries: one LDS read per array; the
+                    // entries past the group are zero, and masked below)
+                    const float4 th4 = *reinterpret_cast<const float4 *>(thr_w + 4 * kq);
+                    const float4 rq4 = *reinterpret_cast<const float4 *>(rq_w + 4 * kq);
+                    const float4 a14 = *reinterpret_cast<const float4 *>(a1_w + 4 * kq);
+                    const float4 A4 = *reinterpret_cast<const float4 *>(A_w + 4 * kq);
+                    const float th[4] = {th4.x, th4.y, th4.z, th4.w};
+                    const float rqh[4] = {rq4.x, rq4.y, rq4.z, rq4.w};
+                    const float a1q[4] = {a14.x, a14.y, a14.z, a14.w};
+                    const float Aq[4] = {A4.x, A4.y, A4.z, A4.w};
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) {
                         const int s = slot0 + nt * 16 + r16;

@@ -45,6 +45,7 @@ struct WaveLds {
     int sb;                  // [next_pow2(k + 64)] sort buffer
     int code, pS;            // [WAVE_PAIRS] pair codes (query << 8 | slot), partial distances
     int q1;                  // [16][w_1] the group's level-1 query slices
+    int rq, a1;              // [16] level-1 head energy a_0^2 - a_1^2 and tail a_1 per query
     int bytes;
 };
 __host__ __device__ inline int wl_take(int &o, int b)
@@ -70,6 +71,8 @@ __host__ __device__ inline WaveLds wave_lds_layout(int L, int k, int w1)
     w.code = wl_take(o, WAVE_PAIRS * 2);
     w.pS = wl_take(o, WAVE_PAIRS * 4);
     w.q1 = wl_take(o, 16 * w1 * 4);
+    w.rq = wl_take(o, 64);
+    w.a1 = wl_take(o, 64);
     w.bytes = o;
     return w;
 }
