@@ -1837,6 +1837,22 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                                             g.wp[lv]);
                         else
                             level_dots<true>(blk + (int64_t)g.B * g.mp[lv], g.B, kgc, qload, slot0, lane, acc2, g.wp[lv]);
+                        // this lane's four queries at this level: head energy
+                        // a_l^2 - a_(l+1)^2, tail a_(l+1), margin, threshold
+                        // (for pairs that are not alive the values do not matter)
+                        float rql[4], anq[4];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int gq = 4 * kq + v;
+                            const float al = qtl[gq * L + lv];
+                            const float an = last ? 0.f : qtl[gq * L + lv + 1];
+                            rql[v] = al * al - an * an;
+                            anq[v] = an;
+                        }
+                        const float4 A4 = *reinterpret_cast<const float4 *>(A_w + 4 * kq);
+                        const float4 th4 = *reinterpret_cast<const float4 *>(thr_w + 4 * kq);
+                        const float Agq[4] = {A4.x, A4.y, A4.z, A4.w};
+                        const float thq[4] = {th4.x, th4.y, th4.z, th4.w};
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) {
                             const int sidx = slot0 + nt * 16 + r16;
@@ -1848,13 +1864,11 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 const int b = nt * 4 + v;
-                                const int gq = 4 * kq + v;
                                 const bool live = (mask >> b) & 1u;
-                                const float al = live ? qtl[gq * L + lv] : 0.f;
-                                const float an = (live && !last) ? qtl[gq * L + lv + 1] : 0.f;
-                                const float sh = sval[b] + (al * al - an * an) + rxl - 2.f * acc2[nt][v];
-                                const float Ag = live ? A_w[gq] : 0.f;
-                                const float th = live ? thr_w[gq] : 0.f;
+                                const float an = anq[v];
+                                const float sh = sval[b] + rql[v] + rxl - 2.f * acc2[nt][v];
+                                const float Ag = Agq[v];
+                                const float th = thq[v];
                                 const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Ag;
                                 const float ct = c.mg.c_tail * (an + bn) * (an + bn);
                                 const bool pruned = (BF ? pair_lower_bf(sh, an, bn, err, ct, c.one_m_eps2, delta)
