@@ -1811,9 +1811,7 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                 // with the margins of level 1)
                 int lv_first = 1;  // first level left to the sparse passes
                 if (PRUNE) {
-                    int alive = __popc(mask);
-#pragma unroll
-                    for (int o = 1; o < 64; o <<= 1) alive += __shfl_xor(alive, o, 64);
+                    int alive = wave_count16(mask);
                     while (lv_first < L && alive >= c.dense_min && g.wp[lv_first] <= 64) {
                         const int lv = lv_first;
                         const bool last = lv + 1 == L;
@@ -1883,33 +1881,18 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             atomicAdd(&st_misc[1], (unsigned long long)cs * (g.wp[lv] * (BF ? 2 : 4) + 8));
                         }
                         ++lv_first;
-                        alive = __popc(mask);
-#pragma unroll
-                        for (int o = 1; o < 64; o <<= 1) alive += __shfl_xor(alive, o, 64);
+                        alive = wave_count16(mask);
                     }
                 }
                 // ---- consolidate into the pair list, refine the later levels,
                 // commit; in two halves (slots 0-31, 32-63) when more pairs
                 // survive than the list holds
-                int na = __popc(mask);
-                int tot = na;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int t = __shfl_xor(tot, o, 64);
-                    tot += t;
-                }
+                const int tot = wave_count16(mask);
                 const int halves = tot > WAVE_PAIRS ? 2 : 1;
                 for (int hf = 0; hf < halves; ++hf) {
                     const uint32_t m = halves == 1 ? mask : (mask & (hf == 0 ? 0x00ffu : 0xff00u));
-                    const int nm = __popc(m);
-                    int incl = nm;
-#pragma unroll
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const int t = __shfl_up(incl, o, 64);
-                        if (lane >= o) incl += t;
-                    }
-                    int off = incl - nm;
-                    int n = __shfl(incl, 63, 64);
+                    int n = 0;
+                    int off = wave_prefix16(m, n);
                     if (n == 0) continue;
 #pragma unroll
                     for (int b = 0; b < 16; ++b) {
@@ -1999,8 +1982,7 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                         const int i = base + lane;
                         if (i < n) qm |= 1u << (pcode[i] >> 8);
                     }
-#pragma unroll
-                    for (int o = 1; o < 64; o <<= 1) qm |= (uint32_t)__shfl_xor((int)qm, o, 64);
+                    qm = wave_or16(qm);
                     while (qm) {
                         const int gq = __builtin_ctz(qm);
                         qm &= qm - 1u;
@@ -2020,7 +2002,7 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             if (nk == 0) continue;
                             int bpos = 0;
                             if (lane == 0) bpos = atomicAdd(&wk.buf_cnt[qq], nk);
-                            bpos = __shfl(bpos, 0, 64);
+                            bpos = __builtin_amdgcn_readfirstlane(bpos);  // every lane is active here
                             const int rk = __popcll(bal & below);
                             if (keep) {
                                 const int dst = bpos + rk;

@@ -240,6 +240,39 @@ __device__ inline float bf_head_upper(float s_hi, float delta)
     return r * r * (1.f + 1e-6f);
 }
 
+// Cross-lane sums of 16-bit masks by one ballot per bit: scalar popcounts
+// and lane-prefix counts, with no shuffle through LDS.
+// The set bits of every lane's m, summed over the wavefront.
+__device__ inline int wave_count16(uint32_t m)
+{
+    int n = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) n += __popcll(__ballot((m >> b) & 1u));
+    return n;
+}
+// The same sum over the lanes below this one (an exclusive prefix); total
+// receives the sum over all lanes.
+__device__ inline int wave_prefix16(uint32_t m, int &total)
+{
+    int off = 0, n = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        const uint64_t bb = __ballot((m >> b) & 1u);
+        off += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u));
+        n += __popcll(bb);
+    }
+    total = n;
+    return off;
+}
+// The OR of every lane's m.
+__device__ inline uint32_t wave_or16(uint32_t m)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) r |= (__ballot((m >> b) & 1u) != 0ull ? 1u : 0u) << b;
+    return r;
+}
+
 // The certified bounds of one (query, row) pair after a level, in the
 // stored frame (Eq. 3 at eps = 1, Eq. 4 below it, with the margins of the
 // soundness analysis): sh = the computed head distance over the levels read,
