@@ -1974,45 +1974,48 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                         wave_sync();
                     }
                     if (n == 0) continue;
-                    // ---- commit the survivors: append those that can reach the
-                    // final band to their query's result buffer, keep the k
-                    // best distances, publish the threshold
-                    uint32_t qm = 0;
+                    // ---- commit the survivors, 64 pairs at a time: those that
+                    // can reach the final band go to their query's result buffer
+                    // (one atomic per query of the chunk, all issued together),
+                    // then each query's k best distances and threshold are
+                    // updated
                     for (int base = 0; base < n; base += 64) {
                         const int i = base + lane;
-                        if (i < n) qm |= 1u << (pcode[i] >> 8);
-                    }
-                    qm = wave_or16(qm);
-                    while (qm) {
-                        const int gq = __builtin_ctz(qm);
-                        qm &= qm - 1u;
-                        const int qq = qid_w[gq];
-                        float th = thr_w[gq];
-                        const float Aqq = A_w[gq];
-                        int cntk = kc_w[gq];
-                        bool ovf = false;
-                        for (int base = 0; base < n; base += 64) {
-                            const int i = base + lane;
-                            const uint32_t pc = i < n ? pcode[i] : 0xffffu;
-                            const bool f = i < n && (int)(pc >> 8) == gq;
-                            const float D = f ? fmaxf(pS[i], 0.f) : 0.f;
-                            const bool keep = f && dist_lower(D, Aqq, c.mg, c.bfdelta) <= th;
-                            const uint64_t bal = __ballot(keep);
-                            const int nk = __popcll(bal);
-                            if (nk == 0) continue;
-                            int bpos = 0;
-                            if (lane == 0) bpos = atomicAdd(&wk.buf_cnt[qq], nk);
-                            bpos = __builtin_amdgcn_readfirstlane(bpos);  // every lane is active here
-                            const int rk = __popcll(bal & below);
-                            if (keep) {
-                                const int dst = bpos + rk;
-                                const int32_t id = ix.ids[gb * g.B + (pc & 255u)];
-                                if (dst < c.capq) wk.buf[(int64_t)qq * c.capq + dst] = make_key(D, id);
-                                else ovf = true;
-                            }
-                            // the k best distances so far
-                            for (int j = lane; j < cntk; j += 64) sb[j] = kb[gq * c.k + j];
-                            if (keep) sb[cntk + rk] = D;
+                        const bool act = i < n;
+                        const uint32_t pc = act ? pcode[i] : 0u;
+                        const int gq = act ? (int)(pc >> 8) : 0;
+                        const float D = act ? fmaxf(pS[i], 0.f) : 0.f;
+                        const bool keep = act && dist_lower(D, A_w[gq], c.mg, c.bfdelta) <= thr_w[gq];
+                        uint32_t qm = wave_or16(keep ? 1u << gq : 0u);
+                        // per query of the chunk: its count (to lane gq) and each
+                        // kept pair's rank among the query's kept pairs
+                        int cnt_l = 0, rk = 0;
+                        for (uint32_t m2 = qm; m2; m2 &= m2 - 1u) {
+                            const int g2 = __builtin_ctz(m2);
+                            const uint64_t bal = __ballot(keep && gq == g2);
+                            if (lane == g2) cnt_l = __popcll(bal);
+                            if (keep && gq == g2) rk = __popcll(bal & below);
+                        }
+                        int bpos = 0;
+                        if (cnt_l > 0) bpos = atomicAdd(&wk.buf_cnt[qid_w[lane]], cnt_l);
+                        bpos = __shfl(bpos, gq, 64);
+                        if (keep) {
+                            const int dst = bpos + rk;
+                            const int qq = qid_w[gq];
+                            const int32_t id = ix.ids[gb * g.B + (pc & 255u)];
+                            if (dst < c.capq) wk.buf[(int64_t)qq * c.capq + dst] = make_key(D, id);
+                            else atomicOr(&wk.flags[qq], FLAG_OVERFLOW);
+                        }
+                        // the k best distances so far and the threshold, one
+                        // query at a time
+                        while (qm) {
+                            const int g2 = __builtin_ctz(qm);
+                            qm &= qm - 1u;
+                            const bool mine = keep && gq == g2;
+                            const int nk = __popcll(__ballot(mine));
+                            int cntk = kc_w[g2];
+                            for (int j = lane; j < cntk; j += 64) sb[j] = kb[g2 * c.k + j];
+                            if (mine) sb[cntk + rk] = D;
                             const int tn = cntk + nk;
                             const int P2 = next_pow2(tn);
                             for (int j = tn + lane; j < P2; j += 64) sb[j] = INFINITY;
@@ -2020,18 +2023,18 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             wave_bitonic_sort_f(sb, P2, lane);
                             wave_sync();
                             cntk = min(c.k, tn);
-                            for (int j = lane; j < cntk; j += 64) kb[gq * c.k + j] = sb[j];
-                            if (cntk == c.k) th = fminf(th, prune_threshold(sb[c.k - 1], E_w[gq], Aqq, c.mg, c.bfdelta));
+                            for (int j = lane; j < cntk; j += 64) kb[g2 * c.k + j] = sb[j];
+                            if (lane == 0) {
+                                kc_w[g2] = cntk;
+                                if (cntk == c.k) {
+                                    const float th = fminf(thr_w[g2], prune_threshold(sb[c.k - 1], E_w[g2], A_w[g2],
+                                                                                      c.mg, c.bfdelta));
+                                    thr_w[g2] = th;
+                                    atomic_min_nonneg(&wk.thr[qid_w[g2]], th);
+                                }
+                            }
                             wave_sync();
                         }
-                        const bool anyovf = __ballot(ovf) != 0ull;
-                        if (lane == 0) {
-                            kc_w[gq] = cntk;
-                            thr_w[gq] = th;
-                            if (th < INFINITY) atomic_min_nonneg(&wk.thr[qq], th);
-                            if (anyovf) atomicOr(&wk.flags[qq], FLAG_OVERFLOW);
-                        }
-                        wave_sync();
                     }
                 }
             }
