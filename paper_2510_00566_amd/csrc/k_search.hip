@@ -1427,9 +1427,9 @@ __global__ __launch_bounds__(NT) void k_scan_brute_stats(SearchConsts c, IndexVi
 // workgroup.  One step is Algorithm 1 for a batch of 16 x 64 (query, slot)
 // pairs:
 //  * Compute / Update for level 1 on the matrix cores (the dot-product form of
-//    the Eq. 3 bound with its certified margin), the query slices held in
-//    registers for the whole item;
-//  * Consolidate: the surviving pairs are compacted by ballot and prefix sum
+//    the Eq. 3 bound with its certified margin), the query slices staged in
+//    LDS for the whole item;
+//  * Consolidate: the surviving pairs are compacted by ballots (per-bit lane counts)
 //    into the wave's pair list in LDS;
 //  * the later levels level-synchronously over that list: each pass reads one
 //    level of every live pair (one, two or four lanes per pair by the level
@@ -2012,18 +2012,47 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             const int g2 = __builtin_ctz(qm);
                             qm &= qm - 1u;
                             const bool mine = keep && gq == g2;
-                            const int nk = __popcll(__ballot(mine));
+                            const uint64_t mbal = __ballot(mine);
+                            const int nk = __popcll(mbal);
                             int cntk = kc_w[g2];
-                            for (int j = lane; j < cntk; j += 64) sb[j] = kb[g2 * c.k + j];
-                            if (mine) sb[cntk + rk] = D;
                             const int tn = cntk + nk;
-                            const int P2 = next_pow2(tn);
-                            for (int j = tn + lane; j < P2; j += 64) sb[j] = INFINITY;
-                            wave_sync();
-                            wave_bitonic_sort_f(sb, P2, lane);
-                            wave_sync();
-                            cntk = min(c.k, tn);
-                            for (int j = lane; j < cntk; j += 64) kb[g2 * c.k + j] = sb[j];
+                            if (c.k <= 64) {
+                                // merge by ranks: lane j < cntk holds the j-th best
+                                // so far; each value's place in the union is its
+                                // rank (kept values before new equal ones, new
+                                // ones in lane order), found with one broadcast
+                                // per value, with no sort
+                                // (a lane may hold both a kept value and a new one)
+                                const float kv = lane < cntk ? kb[g2 * c.k + lane] : INFINITY;
+                                int posk = lane, posn = 0;
+                                for (uint64_t mb = mbal; mb; mb &= mb - 1ull) {
+                                    const int src = __builtin_ctzll(mb);
+                                    const float v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__float_as_int(D), src));
+                                    const int r = __popcll(mbal & ((1ull << src) - 1ull));
+                                    posk += v < kv;
+                                    posn += v < D || (v == D && r < rk);
+                                }
+                                for (int j = 0; j < cntk; ++j) {
+                                    const float v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__float_as_int(kv), j));
+                                    posn += v <= D;
+                                }
+                                wave_sync();
+                                if (lane < cntk && posk < c.k) kb[g2 * c.k + posk] = kv;
+                                if (mine && posn < c.k) kb[g2 * c.k + posn] = D;
+                                wave_sync();
+                                cntk = min(c.k, tn);
+                                if (lane == 0 && cntk == c.k) sb[c.k - 1] = kb[g2 * c.k + c.k - 1];
+                            } else {
+                                for (int j = lane; j < cntk; j += 64) sb[j] = kb[g2 * c.k + j];
+                                if (mine) sb[cntk + rk] = D;
+                                const int P2 = next_pow2(tn);
+                                for (int j = tn + lane; j < P2; j += 64) sb[j] = INFINITY;
+                                wave_sync();
+                                wave_bitonic_sort_f(sb, P2, lane);
+                                wave_sync();
+                                cntk = min(c.k, tn);
+                                for (int j = lane; j < cntk; j += 64) kb[g2 * c.k + j] = sb[j];
+                            }
                             if (lane == 0) {
                                 kc_w[g2] = cntk;
                                 if (cntk == c.k) {
