@@ -1735,7 +1735,8 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             const float ct = c.mg.c_tail * (a1 + b1) * (a1 + b1);
                             const float lb = BF ? pair_lower_bf(sh, a1, b1, Aq[v], ct, c.one_m_eps2, delta)
                                                 : pair_lower(sh, a1, b1, Aq[v], ct, c.one_m_eps2);
-                            const bool sv = on && lb <= th[v];
+                            // (both sides evaluated: no branch per pair)
+                            const bool sv = on & (lb <= th[v]);
                             mask |= (uint32_t)sv << (nt * 4 + v);
                             sval[nt * 4 + v] = sh;
                         }
@@ -1792,9 +1793,9 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                         for (int v = 0; v < 4; ++v) {
                             const int gq = 4 * kq + v;
                             const bool on = valid && gq < ng;
-                            const float a0 = on ? qtl[gq * L] : 0.f;
+                            const float a0 = qtl[gq * L];  // zero past the group
                             const float dd = a0 * a0 + (BF ? ex[nt] : b0 * b0) - 2.f * acc[nt][v];
-                            const bool sv = on && dist_lower(dd, A_w[gq], c.mg, c.bfdelta) <= thr_w[gq];
+                            const bool sv = on & (dist_lower(dd, A_w[gq], c.mg, c.bfdelta) <= thr_w[gq]);
                             mask |= (uint32_t)sv << (nt * 4 + v);
                             sval[nt * 4 + v] = dd;
                         }
@@ -1862,7 +1863,6 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 const int b = nt * 4 + v;
-                                const bool live = (mask >> b) & 1u;
                                 const float an = anq[v];
                                 const float sh = sval[b] + rql[v] + rxl - 2.f * acc2[nt][v];
                                 const float Ag = Agq[v];
@@ -1872,7 +1872,8 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                                 const bool pruned = (BF ? pair_lower_bf(sh, an, bn, err, ct, c.one_m_eps2, delta)
                                                         : pair_lower(sh, an, bn, err, ct, c.one_m_eps2)) > th;
                                 sval[b] = sh;
-                                if (live && pruned) mask &= ~(1u << b);
+                                // (a pair that is not alive has its bit clear already)
+                                mask &= pruned ? ~(1u << b) : ~0u;
                             }
                         }
                         if (STATS && lane == 0) {
