@@ -1456,7 +1456,7 @@ __device__ __forceinline__ float4 wave_ld4(const float *__restrict__ blk, const 
     return *reinterpret_cast<const float4 *>(blk + o);
 }
 
-template <bool PRUNE, bool BF, bool STATS>
+template <bool PRUNE, bool BF, bool STATS, bool RELAX = true>
 __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const IndexView &ix, const QueryView &qv,
                                                const WorkView &wk)
 {
@@ -1733,8 +1733,8 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             const float a1 = a1q[v];
                             const float sh = rqh[v] + (BF ? ex[nt] : rxh) - 2.f * acc[nt][v];
                             const float ct = c.mg.c_tail * (a1 + b1) * (a1 + b1);
-                            const float lb = BF ? pair_lower_bf(sh, a1, b1, Aq[v], ct, c.one_m_eps2, delta)
-                                                : pair_lower(sh, a1, b1, Aq[v], ct, c.one_m_eps2);
+                            const float lb = BF ? pair_lower_bf<RELAX>(sh, a1, b1, Aq[v], ct, c.one_m_eps2, delta)
+                                                : pair_lower<RELAX>(sh, a1, b1, Aq[v], ct, c.one_m_eps2);
                             // (both sides evaluated: no branch per pair)
                             const bool sv = on & (lb <= th[v]);
                             mask |= (uint32_t)sv << (nt * 4 + v);
@@ -1869,8 +1869,8 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                                 const float th = thq[v];
                                 const float err = c.mg.c_level[lv + 1] * fmaxf(sh, 0.f) + Ag;
                                 const float ct = c.mg.c_tail * (an + bn) * (an + bn);
-                                const bool pruned = (BF ? pair_lower_bf(sh, an, bn, err, ct, c.one_m_eps2, delta)
-                                                        : pair_lower(sh, an, bn, err, ct, c.one_m_eps2)) > th;
+                                const bool pruned = (BF ? pair_lower_bf<RELAX>(sh, an, bn, err, ct, c.one_m_eps2, delta)
+                                                        : pair_lower<RELAX>(sh, an, bn, err, ct, c.one_m_eps2)) > th;
                                 sval[b] = sh;
                                 // (a pair that is not alive has its bit clear already)
                                 mask &= pruned ? ~(1u << b) : ~0u;
@@ -1959,9 +1959,9 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                             const float ct = c.mg.c_tail * (a + b) * (a + b);
                             const float th = thr_w[gq];
                             const bool pruned =
-                                (BF ? pair_lower_bf(sh, a, b, err, ct, c.one_m_eps2,
+                                (BF ? pair_lower_bf<RELAX>(sh, a, b, err, ct, c.one_m_eps2,
                                                     c.ub * head_norm_upper(tl[ss], b) + 1e-37f)
-                                    : pair_lower(sh, a, b, err, ct, c.one_m_eps2)) > th;
+                                    : pair_lower<RELAX>(sh, a, b, err, ct, c.one_m_eps2)) > th;
                             const bool keep = act && !pruned && sub == 0;
                             const uint64_t bal = __ballot(keep);
                             if (keep) {
@@ -2084,26 +2084,44 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave(SearchConsts c, IndexView ix,
                                                                                             QueryView qv, WorkView wk)
 {
-    wave_scan_body<true, false, false>(c, ix, qv, wk);
+    wave_scan_body<true, false, false, false>(c, ix, qv, wk);
 }
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_stats(SearchConsts c,
                                                                                                   IndexView ix,
                                                                                                   QueryView qv,
                                                                                                   WorkView wk)
 {
-    wave_scan_body<true, false, true>(c, ix, qv, wk);
+    wave_scan_body<true, false, true, false>(c, ix, qv, wk);
 }
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_bf16(SearchConsts c,
                                                                                                  IndexView ix,
                                                                                                  QueryView qv,
                                                                                                  WorkView wk)
 {
-    wave_scan_body<true, true, false>(c, ix, qv, wk);
+    wave_scan_body<true, true, false, false>(c, ix, qv, wk);
 }
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_bf16_stats(
     SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
 {
-    wave_scan_body<true, true, true>(c, ix, qv, wk);
+    wave_scan_body<true, true, true, false>(c, ix, qv, wk);
+}
+// The same pruned scans for eps < 1 (the relaxed bound of Eq. 4); the
+// instances above are those of eps = 1, which drop its 2 (1 - eps) a b term.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_relaxed(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    wave_scan_body<true, false, false, true>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_relaxed_stats(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    wave_scan_body<true, false, true, true>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_bf16_relaxed(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    wave_scan_body<true, true, false, true>(c, ix, qv, wk);
+}
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_bf16_relaxed_stats(SearchConsts c, IndexView ix, QueryView qv, WorkView wk)
+{
+    wave_scan_body<true, true, true, true>(c, ix, qv, wk);
 }
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAVE_SCAN_WPE, WAVE_SCAN_WPE))) void k_scan_wave_brute(SearchConsts c,
                                                                                                   IndexView ix,
@@ -2943,10 +2961,15 @@ void run_search(pano_ctx *ctx, pano_index *ix, const float *q, int64_t nq, int k
     const int sort_chunks = (int)std::min<int64_t>((nq + WL_SORT_CHUNK - 1) / WL_SORT_CHUNK, 65535);
     // the per-wave scan instance of this search (and its counting twin)
     typedef void (*ScanKernel)(SearchConsts, IndexView, QueryView, WorkView);
-    const ScanKernel wave_kern = brute ? (use_bf16 ? k_scan_wave_brute_bf16 : k_scan_wave_brute)
-                                       : (use_bf16 ? k_scan_wave_bf16 : k_scan_wave);
-    const ScanKernel wave_kern_stats = brute ? (use_bf16 ? k_scan_wave_brute_bf16_stats : k_scan_wave_brute_stats)
-                                             : (use_bf16 ? k_scan_wave_bf16_stats : k_scan_wave_stats);
+    const bool relaxed = eps < 1.f;
+    const ScanKernel wave_kern =
+        brute ? (use_bf16 ? k_scan_wave_brute_bf16 : k_scan_wave_brute)
+              : (use_bf16 ? (relaxed ? k_scan_wave_bf16_relaxed : k_scan_wave_bf16)
+                          : (relaxed ? k_scan_wave_relaxed : k_scan_wave));
+    const ScanKernel wave_kern_stats =
+        brute ? (use_bf16 ? k_scan_wave_brute_bf16_stats : k_scan_wave_brute_stats)
+              : (use_bf16 ? (relaxed ? k_scan_wave_bf16_relaxed_stats : k_scan_wave_bf16_stats)
+                          : (relaxed ? k_scan_wave_relaxed_stats : k_scan_wave_stats));
     if (wave) {
         PANO_REQUIRE(scan_shm <= 160 * 1024, "k and L too large for the per-wave scan's LDS");
         PANO_HIP(hipFuncSetAttribute((const void *)wave_kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)scan_shm));
@@ -3307,14 +3330,14 @@ __global__ void k_audit_bounds(SearchConsts c, IndexView ix, QueryView qv, const
         float *o4 = out + (i * L + lv) * 4;
         if (bf) {
             const float delta = c.ub * head_norm_upper(b0, bn) + 1e-37f;
-            o4[0] = pair_lower_bf(shd, an, bn, errd, ct, 0.f, delta);
+            o4[0] = pair_lower_bf<false>(shd, an, bn, errd, ct, 0.f, delta);
             o4[1] = pair_upper_bf(shd, an, bn, errd, ct, delta);
-            o4[2] = pair_lower_bf(shp, an, bn, errp, ct, 0.f, delta);
+            o4[2] = pair_lower_bf<false>(shp, an, bn, errp, ct, 0.f, delta);
             o4[3] = pair_upper_bf(shp, an, bn, errp, ct, delta);
         } else {
-            o4[0] = pair_lower(shd, an, bn, errd, ct, 0.f);
+            o4[0] = pair_lower<false>(shd, an, bn, errd, ct, 0.f);
             o4[1] = pair_upper(shd, an, bn, errd, ct);
-            o4[2] = pair_lower(shp, an, bn, errp, ct, 0.f);
+            o4[2] = pair_lower<false>(shp, an, bn, errp, ct, 0.f);
             o4[3] = pair_upper(shp, an, bn, errp, ct);
         }
     }

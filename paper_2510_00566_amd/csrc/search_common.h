@@ -281,10 +281,13 @@ __device__ inline uint32_t wave_or16(uint32_t m)
 // ome2 = 2 (1 - eps).  The lower bound is what the scans compare with the
 // pruning threshold; the upper bound (the Cauchy-Schwarz bound with the sum
 // of the tails) holds after every level and for every eps.
+// RELAX = false: eps = 1 known at compile time, the 2 (1 - eps) a b term is
+// dropped (it is an exact +0 there, so the value is the same).
+template <bool RELAX = true>
 __device__ __forceinline__ float pair_lower(float sh, float a, float b, float err, float ct, float ome2)
 {
     const float dt = a - b;
-    return (sh + dt * dt + ome2 * a * b) - (err + ct);
+    return RELAX ? (sh + dt * dt + ome2 * a * b) - (err + ct) : (sh + dt * dt) - (err + ct);
 }
 __device__ __forceinline__ float pair_upper(float sh, float a, float b, float err, float ct)
 {
@@ -292,11 +295,13 @@ __device__ __forceinline__ float pair_upper(float sh, float a, float b, float er
 }
 // bfloat16 rows: sh is the head distance to the rounded row, and delta
 // (u_b times a bound on the head's norm) widens its square root.
+template <bool RELAX = true>
 __device__ __forceinline__ float pair_lower_bf(float sh, float a, float b, float err, float ct, float ome2,
                                                float delta)
 {
     const float dt = a - b;
-    return bf_head_lower(sh - err, delta) + dt * dt + ome2 * a * b - ct;
+    return RELAX ? bf_head_lower(sh - err, delta) + dt * dt + ome2 * a * b - ct
+                 : bf_head_lower(sh - err, delta) + dt * dt - ct;
 }
 __device__ __forceinline__ float pair_upper_bf(float sh, float a, float b, float err, float ct, float delta)
 {
