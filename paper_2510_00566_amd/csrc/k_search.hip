@@ -982,6 +982,18 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                 tb0[nt] = tl[sc];
                 tb1[nt] = g.L > 1 ? tl[g.B + sc] : 0.f;
             }
+            // this lane's four queries (4 kq + v): tail after level 1, head
+            // energy of level 1, margin and threshold (the entries past the
+            // group are never used)
+            float qa1[4], qrq[4], qAq[4], qth[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gq = 4 * kq + v;
+                qa1[v] = g.L > 1 ? qtl_s[gq][1] : 0.f;
+                qrq[v] = rqh_s[gq];
+                qAq[v] = A_s[gq];
+                qth[v] = thr_s[gq];
+            }
             if (PRUNE && BF) {
                 // level 1 from the bfloat16 tile: the dot-product form gives
                 // ||q_h - x~_h||^2 within A; the triangle inequality moves the
@@ -997,13 +1009,12 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     const float delta = c.ub * head_norm_upper(b0, b1) + 1e-37f;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int gq = 4 * kq + v;
-                        const bool on = valid && gq < ng;
-                        const float a1 = on && g.L > 1 ? qtl_s[gq][1] : 0.f;
-                        const float sh = (on ? rqh_s[gq] : 0.f) + ex[nt] - 2.f * acc[nt][v];
-                        const float lb = pair_lower_bf(sh, a1, b1, on ? A_s[gq] : 0.f,
-                                                       c.mg.c_tail * (a1 + b1) * (a1 + b1), c.one_m_eps2, delta);
-                        const bool sv = on && (lb <= thr_s[on ? gq : 0]);
+                        const bool on = valid && 4 * kq + v < ng;
+                        const float a1 = qa1[v];
+                        const float sh = qrq[v] + ex[nt] - 2.f * acc[nt][v];
+                        const float lb = pair_lower_bf(sh, a1, b1, qAq[v], c.mg.c_tail * (a1 + b1) * (a1 + b1),
+                                                       c.one_m_eps2, delta);
+                        const bool sv = on & (lb <= qth[v]);  // both sides evaluated: no branch per pair
                         mask |= (uint32_t)sv << (nt * 4 + v);
                         sval[nt * 4 + v] = sh;
                     }
@@ -1023,13 +1034,12 @@ __device__ __forceinline__ void scan_body(const SearchConsts &c, const IndexView
                     const float rxh = b0 * b0 - b1 * b1;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int gq = 4 * kq + v;
-                        const bool on = valid && gq < ng;
-                        const float a1 = on && g.L > 1 ? qtl_s[gq][1] : 0.f;
-                        const float sh = (on ? rqh_s[gq] : 0.f) + rxh - 2.f * acc[nt][v];
-                        const float lb = pair_lower(sh, a1, b1, on ? A_s[gq] : 0.f,
-                                                    c.mg.c_tail * (a1 + b1) * (a1 + b1), c.one_m_eps2);
-                        const bool sv = on && (lb <= thr_s[on ? gq : 0]);
+                        const bool on = valid && 4 * kq + v < ng;
+                        const float a1 = qa1[v];
+                        const float sh = qrq[v] + rxh - 2.f * acc[nt][v];
+                        const float lb = pair_lower(sh, a1, b1, qAq[v], c.mg.c_tail * (a1 + b1) * (a1 + b1),
+                                                    c.one_m_eps2);
+                        const bool sv = on & (lb <= qth[v]);  // both sides evaluated: no branch per pair
                         mask |= (uint32_t)sv << (nt * 4 + v);
                         sval[nt * 4 + v] = sh;
                     }
