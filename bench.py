@@ -36,9 +36,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def scan_source_hash() -> str:
+def scan_source_hash(kernel: str = "k_scan") -> str:
+    """Hash of the sources a scan kernel is built from (the product
+    quantization scan's file for k_pq_*, the search kernels' file otherwise)."""
     h = hashlib.sha256()
-    for f in ("k_search.hip", "k_pq.hip", "search_common.h"):
+    main = "k_pq.hip" if kernel.startswith("k_pq") else "k_search.hip"
+    for f in (main, "search_common.h"):
         with open(os.path.join(ROOT, "paper_2510_00566_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -64,7 +67,7 @@ def traffic_from_profiles(kernel: str, workload: str):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_hash") != scan_source_hash():
+    if rec.get("source_hash") != scan_source_hash(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 
