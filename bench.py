@@ -224,8 +224,22 @@ class Run:
             self.idx.search_bruteforce(self.qd, w.k, nprobe=self.npd, params=bprm, out=(bi, bd), stats=True,
                                        nprobe_max=self.np_max)
             sb = self.idx.stats()
-            rec["scan_ms"] = None
             rec["scan_bytes"] = float(sb["scan_bytes"])
+            # its scan kernel's duration from the library's HIP events, and the
+            # roofline of that kernel (algorithmic bytes, and counter bytes
+            # when a profile of the current source is committed)
+            ms = []
+            for _ in range(bsteps):
+                self.idx.search_bruteforce(self.qd, w.k, nprobe=self.npd, params=bprm, out=(bi, bd),
+                                           nprobe_max=self.np_max, timing=True)
+                ms.append(self.idx.stats()["ms_scan"])
+            rec["scan_ms"] = float(np.mean(ms))
+            bkern = ("k_scan_wave_brute_bf16" if self.use_bf16 else "k_scan_wave_brute") \
+                if (bprm.scan_mode == 4 or self.use_bf16) else "k_scan_brute"
+            ach = rec["scan_bytes"] / 1e9 / (rec["scan_ms"] / 1e3)
+            rec["roofline"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                               "frac": ach / PEAK_HBM_GBS, "kernel": bkern,
+                               "traffic": traffic_from_profiles(bkern, w.name)}
             log(f"[bench] brute force {rec}")
             if best is None or rec["qps"] > best["qps"]:
                 best = rec

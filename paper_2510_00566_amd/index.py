@@ -341,14 +341,17 @@ class Index:
         return out.value
 
     def search_bruteforce(self, q_dev, k: int, nprobe=1, params: Params | None = None, stats: bool = False,
-                          stream=None, out=None, eager: bool = False, nprobe_max: int = 0):
+                          stream=None, out=None, eager: bool = False, nprobe_max: int = 0, timing: bool = False):
+        """The same probe lists scanned without bounds (every level of every
+        candidate).  timing: phase durations in stats(), as for search."""
         ids, dists = out if out is not None else self._outs(q_dev, k)
         np_dev, np_all = _probe_args(nprobe, nprobe_max)
         prm = params.c() if params is not None else None
+        flags = (L.PANO_SEARCH_STATS if stats else 0) | (L.PANO_SEARCH_EAGER if eager else 0)
+        flags |= L.PANO_SEARCH_TIMING if timing else 0
         L.check(L.lib().pano_search_bruteforce(self.h, _ptr(q_dev), q_dev.shape[0], k, _ptr(np_dev), np_all,
                                                _ptr(ids), _ptr(dists), C.byref(prm) if prm is not None else None,
-                                               (L.PANO_SEARCH_STATS if stats else 0) | (L.PANO_SEARCH_EAGER if eager else 0),
-                                               _stream_handle(stream)))
+                                               flags, _stream_handle(stream)))
         return ids, dists
 
     def info(self) -> dict:
