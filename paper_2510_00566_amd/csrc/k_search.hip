@@ -1569,10 +1569,12 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
         // the group's level-1 query slices, read at every step of the item
         // from LDS (one address register instead of a global pointer per
         // chunk)
-        for (int e = lane; e < ng * kg0; e += 64) {
-            const int gq = e / kg0, kg = e - gq * kg0;
-            q1s[e] = *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_w[gq] * g.d_pad + kg * 4);
-        }
+        // (the brute-force instances have no room for them and do not use them)
+        if (PRUNE)
+            for (int e = lane; e < ng * kg0; e += 64) {
+                const int gq = e / kg0, kg = e - gq * kg0;
+                q1s[e] = *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_w[gq] * g.d_pad + kg * 4);
+            }
         // per query: head energy of level 1, ||q_h||^2 = a_0^2 - a_1^2, and
         // the tail a_1 (zero past the group)
         if (lane < 16) {
@@ -1595,8 +1597,10 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                 // the lane index, opaque to the compiler at every step: values
                 // derived from it are recomputed here (a few instructions)
                 // instead of being computed once and spilled to memory
+                // (the brute-force instances keep their hoisted values: they
+                // have the registers for them)
                 int lane_o = lane;
-                asm volatile("" : "+v"(lane_o));
+                if (PRUNE) asm volatile("" : "+v"(lane_o));
                 const int lane = lane_o, r16 = lane_o & 15, kq = lane_o >> 4;
                 const uint64_t below = (1ull << lane_o) - 1ull;
                 // ---- thresholds: the queries' current d_k, requested now and
@@ -2713,7 +2717,9 @@ static void plan_search(const pano_index *ix, int64_t nq, int k, bool per_query_
     const int mode_req = prm ? prm->reserved[1] : 0;
     // the brute-force scan of bfloat16 tiles is an instance of the per-wave scan
     pl.wave = mode_req == 4 || (brute && bf16_req);
-    c.wl = wave_lds_layout(L, k, ix->wp[0]);
+    // (the level-1 query slices are staged only by the pruned scan: the
+    // brute-force instances keep the smaller layout and their occupancy)
+    c.wl = wave_lds_layout(L, k, brute ? 0 : ix->wp[0]);
     // a query group meets at most 32 work items per list
     c.bpi = (prm && prm->blocks_per_item > 0) ? prm->blocks_per_item : 1;
     c.item_cap = 32;
