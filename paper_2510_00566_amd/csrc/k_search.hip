@@ -1576,8 +1576,8 @@ __device__ __forceinline__ void wave_scan_body(const SearchConsts &c, const Inde
                 q1s[e] = *reinterpret_cast<const float4 *>(qv.qy + (int64_t)qid_w[gq] * g.d_pad + kg * 4);
             }
         // per query: head energy of level 1, ||q_h||^2 = a_0^2 - a_1^2, and
-        // the tail a_1 (zero past the group)
-        if (lane < 16) {
+        // the tail a_1 (zero past the group; pruned scan only)
+        if (PRUNE && lane < 16) {
             const bool on = lane < ng;
             const float a0 = on ? qtl[lane * L] : 0.f;
             const float a1 = (on && L > 1) ? qtl[lane * L + 1] : 0.f;

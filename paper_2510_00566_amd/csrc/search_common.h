@@ -70,9 +70,11 @@ __host__ __device__ inline WaveLds wave_lds_layout(int L, int k, int w1)
     w.sb = wl_take(o, p * 4);
     w.code = wl_take(o, WAVE_PAIRS * 2);
     w.pS = wl_take(o, WAVE_PAIRS * 4);
+    // (the pruned scan's per-item staging; none for the brute-force scan, whose
+    // occupancy the extra bytes could cost a workgroup per compute unit)
     w.q1 = wl_take(o, 16 * w1 * 4);
-    w.rq = wl_take(o, 64);
-    w.a1 = wl_take(o, 64);
+    w.rq = wl_take(o, w1 > 0 ? 64 : 0);
+    w.a1 = wl_take(o, w1 > 0 ? 64 : 0);
     w.bytes = o;
     return w;
 }
