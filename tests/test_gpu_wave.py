@@ -143,3 +143,23 @@ def test_wave_single_level_and_eps(torch_cuda):
             canon = brute.canonical_dist(q[i], c2["x"][ids[i]])
             assert np.array_equal(canon.astype(np.float32), dd[i])
             assert (dd[i] >= ref_d[i]).all()
+
+
+@gpu
+def test_wave_long_lists_ordered_in_chunks(torch_cuda):
+    """2,500 queries probing every one of 4 lists: each list holds 2,500
+    queries, which are ordered by their distance to the list in chunks of
+    1,024 per workgroup (three chunks per list, the last one ragged); the
+    answers of the per-wave scan, the workgroup scan and the brute force stay
+    those of the oracle."""
+    from tests import gpu_cases as gc
+    w = synth.scaled(synth.WORKLOADS["ivf_zipf_batched"], n=3000, nq=2500, nlist=4, n_clusters=4)
+    w = dataclasses.replace(w, d=32, level_width=8, nprobe_range=None, nprobe=4)
+    data = synth.generate(w)
+    _log("case wave long lists n=3000 d=32 nlist=4 nq=2500")
+    case = gc.build_case(w, data=data)
+    _check(torch_cuda, case, w, data["q"], 4)
+    qd = torch_cuda.from_numpy(data["q"]).cuda()
+    ids, dd = case["idx"].search(qd, w.k, nprobe=4, params=Params(scan_mode=0))
+    ref_i, ref_d = gc.oracle_answer(case, data["q"], 4, w.k)
+    gc.compare(ids.cpu().numpy(), dd.cpu().numpy(), ref_i, ref_d)
