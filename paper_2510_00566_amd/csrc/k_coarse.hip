@@ -1,6 +1,7 @@
 // Coarse probing: the nprobe nearest lists of every query, in the exact
 // (D, list) order of the canonical distance (the IVF stage ahead of
-// Algorithm 1; Section 6.2 runs it per query before the list scans).
+// Algorithm 1: Section 6.1's index scans the nprobe nearest clusters of a
+// query).
 //
 // One wavefront per query.  Approximate distances to every centroid come from
 // the dense product S = q . c (chunked FP32 on the matrix cores), with a
