@@ -105,6 +105,7 @@ class Scheduler:
         self._busy = 0  # batches in flight
         self._idle: set = set()  # workers waiting in next_batch
         self._pressure = False  # idle workers holding memory should trim
+        self._trimmed: set = set()  # workers that trimmed for the current shortage
         self._peak = 0
         self._closed = False
         self._next_bid = 0
@@ -158,8 +159,10 @@ class Scheduler:
 
     def _next_locked(self, wid: int) -> Batch | None:
         while True:
-            if self._pressure and self._charge.get(wid, 0) > 0:
-                # asked to make room: release this context's memory
+            if self._pressure and self._charge.get(wid, 0) > 0 and wid not in self._trimmed:
+                # asked to make room: release this context's memory (once
+                # per shortage: what a trim leaves, a second one leaves too)
+                self._trimmed.add(wid)
                 b = Batch(-1, "", 0, [], 0, worker=wid, prev_charge=self._charge[wid], trim=True)
                 self._busy += 1
                 return b
@@ -187,12 +190,13 @@ class Scheduler:
                 if not q[0].deferred:
                     q[0].deferred = True
                     self.deferred += 1
-                if any(self._charge.get(w, 0) > 0 for w in self._idle if w != wid):
+                if any(self._charge.get(w, 0) > 0 for w in self._idle if w != wid and w not in self._trimmed):
                     self._pressure = True
                 self._lock.notify_all()
                 self._lock.wait()
                 continue
             self._pressure = False
+            self._trimmed.clear()
             self._queued -= nq
             need = self.cost(index, nq, k)
             prev = self._charge.get(wid, 0)

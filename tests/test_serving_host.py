@@ -243,3 +243,50 @@ def test_request_waiting_for_memory_is_counted_deferred():
     t.join(timeout=5)
     assert got and [r.rid for r in got[0].requests] == [1]
     assert latency_report([late])["deferred"] == 1
+
+
+def test_trim_that_leaves_memory_is_asked_once():
+    """A context whose trim cannot release everything (worker 0 keeps 3000
+    bytes): when worker 1's batch does not fit beside it, worker 0 is asked to
+    trim once, then runs the batch itself (it fits there), instead of being
+    asked to trim again and again."""
+    sched = Scheduler(lambda i, nq, k: 1000 * nq, budget=10_000, max_batch_queries=64, growth=1.0)
+    sched.submit(_req(0, m=3))
+    sched.finish(sched.next_batch(0), resident=3000)
+    log, got1 = [], []
+
+    def worker0():
+        while True:
+            b = sched.next_batch(0)
+            if b is None:
+                return
+            if b.trim:
+                log.append("trim")
+                sched.finish(b, resident=3000)
+                if log.count("trim") > 3:
+                    sched.close()
+                    return
+                continue
+            log.append(("batch", [r.rid for r in b.requests]))
+            sched.finish(b, resident=3000)
+            sched.close()
+            return
+
+    def worker1():
+        # the request arrives and worker 1 looks at it before worker 0 wakes
+        with sched._lock:
+            sched.submit(_req(1, m=8))
+            got1.append(sched.next_batch(1))
+
+    a = threading.Thread(target=worker0, daemon=True)
+    a.start()
+    for _ in range(500):
+        if 0 in sched._idle:
+            break
+        time.sleep(0.01)
+    b = threading.Thread(target=worker1, daemon=True)
+    b.start()
+    a.join(timeout=10)
+    b.join(timeout=10)
+    assert log == ["trim", ("batch", [1])]
+    assert got1 == [None] and sched.deferred == 1
