@@ -230,12 +230,13 @@ typedef struct {
  * NULL to use nprobe_all for every query; probe counts are clamped to
  * [1, nlist].  With nprobe_dev, a positive nprobe_all is an upper bound on
  * the per-query counts (larger ones are clamped to it) and sizes the probe
- * tables as nq x nprobe_all; 0 sizes them for nlist probes per query.  The probe set of a query is its nprobe nearest lists by
- * (D(q, centroid), list id).  eps in [0, 1] (Eq. 4; 1 = exact).  Outputs
+ * tables as nq x nprobe_all; 0 sizes them for nlist probes per query.  The
+ * probe set of a query is its nprobe nearest lists by (D(q, centroid),
+ * list id).  k in [1, 128].  eps in [0, 1] (Eq. 4; 1 = exact).  Outputs
  * ids_dev [nq][k] int64 (row index of the vector in build_levels' x) and
  * dists_dev [nq][k] float32 (canonical D), ascending by (D, id).  `params`
- * may be NULL.  Errors: EINVAL if k < 1, nq < 0, eps outside [0, 1] or a
- * query is non-finite; ENOMEM if scratch cannot be allocated.  An ordinary
+ * may be NULL.  Errors: EINVAL if k < 1 or k > 128, nq < 0, eps outside
+ * [0, 1] or a query is non-finite; ENOMEM if scratch cannot be allocated.  An ordinary
  * search launches a graph (captured once per launch configuration on the
  * context's own stream) on `stream`; eager, counting and timing searches run
  * on the context's streams after the work already queued on `stream`.
@@ -273,8 +274,8 @@ pano_status pano_search_ctx(pano_ctx *ctx, pano_index *idx, const float *q_dev, 
  * (canonical D, ascending (D, id); -1 / +inf padding).  At eps = 1 the
  * result is the exact k-NN over the candidate set.  Runs on the index's
  * context, after the work queued on `stream`; returns when done.  Errors:
- * EINVAL if k < 1, kprime < 1, eps outside [0, 1], a query is non-finite or
- * a candidate id is outside [-1, n).  The first call on an index builds a
+ * EINVAL if k < 1 or k > 128, kprime < 1, eps outside [0, 1], a query is
+ * non-finite or a candidate id is outside [-1, n).  The first call on an index builds a
  * map from row id to block position (8 bytes per row, kept by the index).
  */
 pano_status pano_refine(pano_index *idx, const float *q_dev, int64_t nq, int32_t k, const int64_t *cand_dev,
