@@ -82,8 +82,9 @@ class Scheduler:
     budget caps the sum of the charges of all workers.  finish() sets the
     worker's charge to the resident size it reports (0 after a trim).  A
     single request that cannot fit even when no other batch is in flight is
-    still admitted alone (it could never run otherwise); the budget is then
-    exceeded by that batch only.  max_queued (queries, None: no limit)
+    still admitted alone (it could never run otherwise), and so is a batch
+    that does not fit beside memory the other workers keep after a trim; the
+    budget is then exceeded by that batch only.  max_queued (queries, None: no limit)
     bounds the waiting queue: a request that would exceed it is rejected at
     arrival (back-pressure instead of unbounded queueing).  A request that
     reaches the head of the queue but must wait for memory held by other
@@ -174,7 +175,9 @@ class Scheduler:
                 continue
             q = self._queues[key]
             index, k = key
-            others_hold = any(v > 0 for w, v in self._charge.items() if w != wid)
+            # memory other workers could still release (what is left after a
+            # trim stays: waiting for it would wait for ever)
+            others_hold = any(v > 0 for w, v in self._charge.items() if w != wid and w not in self._trimmed)
             take, nq = [], 0
             while q and (not take or nq + q[0].m <= self.max_q):
                 cand = nq + q[0].m

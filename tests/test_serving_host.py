@@ -290,3 +290,43 @@ def test_trim_that_leaves_memory_is_asked_once():
     b.join(timeout=10)
     assert log == ["trim", ("batch", [1])]
     assert got1 == [None] and sched.deferred == 1
+
+
+def test_batch_runs_beside_memory_left_after_trims():
+    """Both workers keep 3000 bytes that no trim releases; a 9000-byte batch
+    does not fit beside the other's 3000 under a 10000 budget.  Once each
+    worker has trimmed, nothing more can be released, so the batch runs
+    (over the budget by that memory only) instead of both workers waiting
+    for ever."""
+    sched = Scheduler(lambda i, nq, k: 1000 * nq, budget=10_000, max_batch_queries=64, growth=1.0)
+    for wid in (0, 1):
+        sched.submit(_req(wid, m=3))
+        sched.finish(sched.next_batch(wid), resident=3000)
+    log = []
+
+    def worker(wid):
+        while True:
+            b = sched.next_batch(wid)
+            if b is None:
+                return
+            if b.trim:
+                log.append(("trim", wid))
+                sched.finish(b, resident=3000)
+                continue
+            log.append(("batch", [r.rid for r in b.requests]))
+            sched.finish(b, resident=3000)
+            sched.close()
+
+    ts = [threading.Thread(target=worker, args=(w,), daemon=True) for w in (0, 1)]
+    for t in ts:
+        t.start()
+    for _ in range(500):
+        if sched._idle == {0, 1}:
+            break
+        time.sleep(0.01)
+    sched.submit(_req(2, m=9))
+    for t in ts:
+        t.join(timeout=10)
+    assert not any(t.is_alive() for t in ts), f"workers still waiting: {log}"
+    assert [e for e in log if e[0] == "batch"] == [("batch", [2])]
+    assert len([e for e in log if e[0] == "trim"]) <= 2
