@@ -1,8 +1,10 @@
 """GPU parity at the full sizes of the batched Zipf configuration (10M x 128,
-4096 Zipf(1.1) lists, nprobe ~ U[8, 128], 10,000 queries, k = 10) and the
-GIST-like one (1M x 960, 1024 lists, nprobe 32, 1,000 queries), in the
-launch configuration the benchmark times: its stored level width and search
-knobs, the residual PCA, the whole query batch in one call.
+4096 Zipf(1.1) lists, nprobe ~ U[8, 128], 10,000 queries, k = 10), the
+GIST-like one (1M x 960, 1024 lists, nprobe 32, 1,000 queries) and the
+unit-norm embedding one (5M x 768 stored in bfloat16, 4096 lists, nprobe 64,
+10,000 queries, k = 100), in the launch configuration the benchmark times:
+its stored level width and search knobs, the residual PCA, the whole query
+batch in one call.
 
 The oracle recomputes a sample of queries one by one (ids bit-exact,
 distances to 1e-5 relative): a seeded random sample plus the queries with
@@ -33,13 +35,13 @@ def torch_cuda():
     return torch
 
 
-def _full_size_case(torch, name):
+def _full_size_case(torch, name, store):
     from tests import gpu_cases as gc
     from paper_2510_00566_amd import autotune
     from paper_2510_00566_amd.index import Index, Transform, ivf_assign
     w = dataclasses.replace(synth.WORKLOADS[name])
     npv = w.nprobe_range[1] if w.nprobe_range else w.nprobe
-    prm, width = autotune.lookup(autotune.signature("gfx950", w.d, "f32", w.n, npv, w.k))
+    prm, width = autotune.lookup(autotune.signature("gfx950", w.d, store, w.n, npv, w.k))
     assert prm is not None, f"no stored search knobs for {name}"
     if width and w.tune_width:
         w.level_width = int(width)
@@ -53,16 +55,16 @@ def _full_size_case(torch, name):
     rows = np.random.Generator(np.random.PCG64(w.cfg_id)).choice(w.n, min(w.n, 131072), replace=False)
     tf = Transform.fit(x[rows] - c_np[a_np[rows]], fit_sample=0, seed=w.cfg_id)
     cuts = np.asarray(list(range(0, w.d, w.level_width)) + [w.d], dtype=np.int32)
-    idx = Index.build(gc.ctx(), tf, xd, cent, assign, cuts, store="f32")
+    idx = Index.build(gc.ctx(), tf, xd, cent, assign, cuts, store=store)
     del xd
     torch.cuda.synchronize()
     return w, prm, data, c_np, a_np, idx
 
 
-def _check_full_size(torch, name, sample_n, widest_n):
+def _check_full_size(torch, name, sample_n, widest_n, store="f32"):
     from tests import gpu_cases as gc
     from oracle import brute
-    w, prm, data, c_np, a_np, idx = _full_size_case(torch, name)
+    w, prm, data, c_np, a_np, idx = _full_size_case(torch, name, store)
     try:
         q = data["q"]
         qd = torch.from_numpy(q).cuda()
@@ -102,3 +104,9 @@ def test_full_size_zipf_batched(torch_cuda):
 @gpu
 def test_full_size_gist_like(torch_cuda):
     _check_full_size(torch_cuda, "ivf_gist_like", 12, 4)
+
+
+@gpu
+def test_full_size_embed_bf16(torch_cuda):
+    # bfloat16 level tiles, FP32 rescoring: the answer is still the exact one
+    _check_full_size(torch_cuda, "ivf_embed_bf16", 10, 0, store="bf16")
